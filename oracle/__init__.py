@@ -1,0 +1,90 @@
+"""CPU oracle for Eqn. 1 (out-of-place tensor transposition with scaling and
+update, column-major, per-index leading dimensions).
+
+TEST INFRASTRUCTURE ONLY.  Two independent CPU references live here:
+
+* ``transpose`` -- the plain C nested loop in ``ttx_ref.c`` (loaded with
+  ctypes from ``libttxref.so``, built by ``oracle/build.py``);
+* ``ref_np.transpose_np`` -- the same definition written with numpy views
+  (``np.transpose``'s ``axes`` argument is exactly the gather reading of the
+  permutation used throughout).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It imports nothing from the library
+under test, and the library imports nothing from it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .ref_np import transpose_np  # noqa: F401  (re-exported)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttxref.so")
+
+OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED = 0, 1, 2, 3, 4
+DTYPES = {np.dtype(np.float32): 0, np.dtype(np.float64): 1}
+
+_lib = None
+
+
+def lib():
+    """Loads (building first if absent) the C oracle."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build
+            build.build()
+        _lib = _load(LIB_PATH)
+    return _lib
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.ttx_ref_transpose.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_void_p]
+    L.ttx_ref_transpose.restype = ctypes.c_int
+    L.ttx_ref_check.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
+                                ctypes.c_void_p, ctypes.c_void_p]
+    L.ttx_ref_check.restype = ctypes.c_int
+    return L
+
+
+def _arr(vals, ctype):
+    if vals is None:
+        return None
+    vals = [int(v) for v in vals]
+    return (ctype * max(1, len(vals)))(*vals)
+
+
+def transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, library=None):
+    """B <- alpha * Pi(A) + beta * B in place on host numpy arrays (Eqn. 1).
+
+    ``A`` and ``B`` are flat numpy arrays of one dtype (float32 or float64)
+    holding the column-major outer tensors; ``perm`` is the gather
+    permutation (B position k holds A index ``perm[k]``).  Returns the C
+    status code.
+    """
+    L = library or lib()
+    assert A.dtype == B.dtype and A.dtype in DTYPES
+    assert A.flags.c_contiguous and B.flags.c_contiguous and B.flags.writeable
+    n = len(perm)
+    return L.ttx_ref_transpose(DTYPES[A.dtype], n, _arr(perm, ctypes.c_int),
+                               _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
+                               _arr(outer_b, ctypes.c_int64), float(alpha),
+                               A.ctypes.data, float(beta), B.ctypes.data)
+
+
+def check(dtype_code, perm, size, outer_a=None, outer_b=None, a_addr=1 << 20, b_addr=1 << 40,
+          n=None, library=None):
+    """Status code of the oracle's argument validation (touches no memory)."""
+    L = library or lib()
+    n = len(perm) if n is None else n
+    return L.ttx_ref_check(dtype_code, n, _arr(perm, ctypes.c_int) if perm is not None else None,
+                           _arr(size, ctypes.c_int64) if size is not None else None,
+                           _arr(outer_a, ctypes.c_int64), _arr(outer_b, ctypes.c_int64),
+                           a_addr, b_addr)

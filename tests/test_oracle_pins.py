@@ -1,0 +1,381 @@
+"""Pins the CPU oracle to facts other than itself (CPU only).
+
+Each ``pin_*`` function takes a loaded oracle library and raises
+AssertionError when the oracle disagrees with what the paper or the
+mathematics fixes:
+
+* the Sec. 2.1 example, written out by hand (tests/golden);
+* a closed form: with A's values encoding their own multi-index, every B
+  element must encode the A index the gather reading sends to it;
+* numpy's ``transpose`` (a library routine) on every permutation of up to 5
+  indices with tiny extents, contiguous and inside larger outer tensors;
+* the 2D case against a textbook matrix transpose (numpy ``.T``);
+* round trip through the inverse permutation, and composition of two
+  permutations (which separates the gather from the scatter reading);
+* the update against a separate elementwise axpby, beta = 0 never reading B,
+  the non-fused operation order (contraction detector), special values.
+
+``test_pins_catch_planted_mistakes`` compiles deliberately broken copies of
+the oracle and checks that some pin fails for each of them.
+"""
+import itertools
+import json
+import os
+import shutil
+import tempfile
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import build as oracle_build
+from oracle.ref_np import transpose_np
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _elems(dims):
+    return int(np.prod([int(d) for d in dims], dtype=np.int64))
+
+
+def _rand(n, dtype, rng):
+    if np.dtype(dtype) == F32:
+        return rng.random(n, dtype=np.float32) * 2 - 1
+    return rng.random(n) * 2 - 1
+
+
+def _run(L, perm, size, alpha, A, beta, B, outer_a=None, outer_b=None):
+    st = oracle.transpose(perm, size, alpha, A, beta, B, outer_a, outer_b, library=L)
+    assert st == oracle.OK, st
+    return B
+
+
+def _bits(x):
+    return x.view(np.uint32 if x.dtype == F32 else np.uint64)
+
+
+def _same_bits(x, y):
+    return np.array_equal(_bits(x), _bits(y))
+
+
+def _inverse(perm):
+    inv = [0] * len(perm)
+    for k, p in enumerate(perm):
+        inv[p] = k
+    return tuple(inv)
+
+
+# ---------------------------------------------------------------------------------------
+def pin_sec21_example(L):
+    g = _golden("sec21_merge_example.json")
+    size = g["size"]
+    i0, i1, i2 = np.meshgrid(*[np.arange(s) for s in size], indexing="ij")
+    A = (i0 + 10 * i1 + 100 * i2).astype(np.float64).flatten(order="F")
+    B = np.full(_elems(size), -1.0)
+    _run(L, g["perm"], size, 1.0, A, 0.0, B)
+    assert B.tolist() == [float(v) for v in g["B_flat_column_major"]]
+
+
+def pin_index_encoding(L):
+    """Closed form: A_i = sum_m i_m 8^m  =>  B_j = sum_k j_k 8^perm[k] (gather reading)."""
+    for perm, size in [((2, 0, 3, 1), (2, 3, 4, 5)), ((1, 2, 0), (3, 4, 5)),
+                       ((4, 0, 3, 1, 2), (2, 3, 2, 4, 3)), ((0, 5, 1, 4, 2, 3), (2, 2, 3, 2, 3, 2))]:
+        n = len(size)
+        grids = np.meshgrid(*[np.arange(s) for s in size], indexing="ij")
+        A = sum(g * 8 ** m for m, g in enumerate(grids)).astype(np.float64).flatten(order="F")
+        size_b = [size[p] for p in perm]
+        B = np.zeros(_elems(size))
+        _run(L, perm, size, 1.0, A, 0.0, B)
+        jg = np.meshgrid(*[np.arange(s) for s in size_b], indexing="ij")
+        expect = sum(jg[k] * 8 ** perm[k] for k in range(n)).astype(np.float64).flatten(order="F")
+        assert np.array_equal(B, expect), (perm, size)
+
+
+def _outer(rng, dims, pad):
+    return tuple(int(d) + int(rng.integers(0, pad + 1)) for d in dims)
+
+
+def pin_brute_force_vs_numpy(L, max_n=5, extents=(1, 2, 3, 5), sample_per_perm=2):
+    """Every permutation of 1..max_n indices, tiny extents, contiguous and embedded."""
+    rng = np.random.default_rng(11)
+    for n in range(1, max_n + 1):
+        for perm in itertools.permutations(range(n)):
+            for _ in range(sample_per_perm):
+                size = tuple(int(rng.choice(extents)) for _ in range(n))
+                size_b = [size[p] for p in perm]
+                for embedded in (False, True):
+                    oa = _outer(rng, size, 2) if embedded else None
+                    ob = _outer(rng, size_b, 2) if embedded else None
+                    for dtype in (F32, F64):
+                        for alpha, beta in ((1.0, 0.0), (1.3, 0.7), (-0.75, -2.0), (-1.5, 0.0)):
+                            A = _rand(_elems(oa or size), dtype, rng)
+                            B0 = _rand(_elems(ob or size_b), dtype, rng)
+                            B1, B2 = B0.copy(), B0.copy()
+                            _run(L, perm, size, alpha, A, beta, B1, oa, ob)
+                            transpose_np(perm, size, alpha, A, beta, B2, oa, ob)
+                            assert _same_bits(B1, B2), (perm, size, oa, ob, dtype, alpha, beta)
+
+
+def pin_textbook_2d(L):
+    rng = np.random.default_rng(12)
+    for dtype in (F32, F64):
+        m, n = 37, 53
+        A = _rand(m * n, dtype, rng)
+        B = _rand(n * m, dtype, rng)
+        t = np.dtype(dtype).type
+        Am = A.reshape((m, n), order="F")
+        Bm = B.reshape((n, m), order="F")
+        expect = (t(1.5) * Am.T + t(-0.25) * Bm).flatten(order="F")
+        _run(L, (1, 0), (m, n), 1.5, A, -0.25, B)
+        assert _same_bits(B, expect)
+        # leading dimensions: the matrix is the top-left block of larger arrays
+        lda, ldb = 41, 60
+        A2 = _rand(lda * n, dtype, rng)
+        B2 = _rand(ldb * m, dtype, rng)
+        ref = B2.copy().reshape((ldb, m), order="F")
+        ref[:n, :m] = A2.reshape((lda, n), order="F")[:m, :].T
+        _run(L, (1, 0), (m, n), 1.0, A2, 0.0, B2, (lda, n), (ldb, m))
+        assert _same_bits(B2, ref.flatten(order="F"))
+
+
+def pin_round_trip(L):
+    rng = np.random.default_rng(13)
+    for perm, size in [((2, 0, 3, 1), (3, 4, 5, 6)), ((0, 5, 1, 4, 2, 3), (2, 3, 2, 4, 3, 2)),
+                       ((1, 2, 0), (7, 1, 9)), ((4, 3, 2, 1, 0), (2, 3, 4, 3, 2))]:
+        for dtype in (F32, F64):
+            A = _rand(_elems(size), dtype, rng)
+            T = np.zeros_like(A)
+            _run(L, perm, size, 1.0, A, 0.0, T)
+            size_b = [size[p] for p in perm]
+            back = np.zeros_like(A)
+            _run(L, _inverse(perm), size_b, 1.0, T, 0.0, back)
+            assert _same_bits(back, A), (perm, size)
+
+
+def pin_composition(L):
+    """T_{p2}(T_{p1}(A)) == T_{r}(A) with r[k] = p1[p2[k]] (gather composition)."""
+    rng = np.random.default_rng(14)
+    for p1, p2, size in [((2, 0, 3, 1), (1, 3, 0, 2), (2, 3, 4, 5)),
+                         ((1, 2, 0), (1, 2, 0), (3, 4, 5)),
+                         ((0, 5, 1, 4, 2, 3), (3, 1, 4, 0, 5, 2), (2, 3, 2, 4, 3, 2))]:
+        A = _rand(_elems(size), F64, rng)
+        T1 = np.zeros_like(A)
+        _run(L, p1, size, 1.0, A, 0.0, T1)
+        s1 = [size[p] for p in p1]
+        T2 = np.zeros_like(A)
+        _run(L, p2, s1, 1.0, T1, 0.0, T2)
+        r = tuple(p1[p2[k]] for k in range(len(p1)))
+        direct = np.zeros_like(A)
+        _run(L, r, size, 1.0, A, 0.0, direct)
+        assert _same_bits(T2, direct), (p1, p2)
+        # the other composition order describes a different tensor for these
+        # non-commuting pairs, so this pin separates the two readings
+        wrong = tuple(p2[p1[k]] for k in range(len(p1)))
+        if wrong != r:
+            other = np.zeros_like(A)
+            _run(L, wrong, size, 1.0, A, 0.0, other)
+            assert not _same_bits(T2, other)
+
+
+def _axpby(alpha, x, beta, y):
+    """Separate elementwise y <- alpha*x + beta*y in x's dtype, non-fused."""
+    t = x.dtype.type
+    out = np.empty_like(y)
+    np.multiply(t(alpha), x, out=out)
+    tmp = np.empty_like(y)
+    np.multiply(t(beta), y, out=tmp)
+    np.add(out, tmp, out=out)
+    return out
+
+
+def pin_update_vs_axpby(L):
+    rng = np.random.default_rng(15)
+    for dtype in (F32, F64):
+        for perm, size in [((3, 2, 1, 0), (5, 6, 7, 8)), ((0, 2, 1, 3), (9, 5, 4, 3))]:
+            A = _rand(_elems(size), dtype, rng)
+            B = _rand(_elems(size), dtype, rng)
+            plain = np.zeros_like(A)
+            _run(L, perm, size, 1.0, A, 0.0, plain)
+            for alpha, beta in ((1.3, 0.7), (-2.0, 0.5), (0.0, 1.0)):
+                got = B.copy()
+                _run(L, perm, size, alpha, A, beta, got)
+                assert _same_bits(got, _axpby(alpha, plain, beta, B)), (dtype, perm, alpha, beta)
+
+
+def pin_identity_is_axpby(L):
+    rng = np.random.default_rng(16)
+    for dtype in (F32, F64):
+        size = (4, 5, 6)
+        A = _rand(120, dtype, rng)
+        B = _rand(120, dtype, rng)
+        got = B.copy()
+        _run(L, (0, 1, 2), size, 0.5, A, -1.5, got)
+        assert _same_bits(got, _axpby(0.5, A, -1.5, B))
+
+
+def pin_beta_zero_does_not_read_b(L):
+    rng = np.random.default_rng(17)
+    for dtype in (F32, F64):
+        A = _rand(60, dtype, rng)
+        B = np.full(60, np.nan, dtype=dtype)
+        _run(L, (2, 0, 1), (3, 4, 5), 1.0, A, 0.0, B)
+        assert not np.isnan(B).any()
+        B = np.full(60, np.inf, dtype=dtype)
+        _run(L, (2, 0, 1), (3, 4, 5), -2.0, A, -0.0, B)
+        assert np.isfinite(B).all()
+
+
+def pin_contraction_detector(L):
+    g = _golden("contraction.json")
+    assert g["f32"]["unfused"] == 0.0
+    for dtype, p in ((F32, 12), (F64, 27)):
+        t = dtype.type
+        alpha = 1.0 + 2.0 ** -p
+        A = np.array([alpha, alpha], dtype=dtype)
+        B = np.array([1.0 + 2.0 ** -(p - 1)] * 2, dtype=dtype)
+        assert A[0] == t(alpha) and float(A[0]) == alpha  # exactly representable
+        _run(L, (1, 0), (1, 2), alpha, A, -1.0, B)
+        assert B.tolist() == [0.0, 0.0], (dtype, B)
+        # the exact value (what a fused multiply-add would round), for contrast
+        exact = Fraction(alpha) * Fraction(alpha) - Fraction(1.0 + 2.0 ** -(p - 1))
+        assert exact == Fraction(1, 2 ** (2 * p))
+
+
+def pin_special_values(L):
+    for dtype in (F32, F64):
+        fi = np.finfo(dtype)
+        vals = np.array([0.0, -0.0, np.inf, -np.inf, fi.max, -fi.max, fi.tiny, fi.smallest_subnormal,
+                         -fi.smallest_subnormal, 1.0, -1.0, np.nan], dtype=dtype)
+        A = np.concatenate([vals, vals[::-1]])
+        B = np.zeros_like(A)
+        _run(L, (1, 0), (len(vals), 2), 1.0, A, 0.0, B)
+        expect = A.reshape((len(vals), 2), order="F").T.flatten(order="F")
+        fin = ~np.isnan(expect)
+        assert _same_bits(B[fin], expect[fin])
+        assert np.isnan(B[~fin]).all()
+
+
+def pin_embedded_canaries(L):
+    """A sub-tensor written into a canary-filled outer tensor equals the
+    contiguous result, and no element outside the sub-tensor changes."""
+    rng = np.random.default_rng(18)
+    size, perm = (6, 5, 4, 3), (1, 0, 2, 3)
+    oa, ob = (8, 6, 4, 5), (7, 9, 6, 3)
+    size_b = [size[p] for p in perm]
+    for dtype in (F32, F64):
+        A_full = _rand(_elems(oa), dtype, rng)
+        A_sub = A_full.reshape(oa, order="F")[tuple(slice(0, s) for s in size)].flatten(order="F")
+        ref = np.zeros(_elems(size_b), dtype=dtype)
+        _run(L, perm, size, 2.0, A_sub, 0.0, ref)
+        canary = dtype.type(-12345.0)
+        B = np.full(_elems(ob), canary, dtype=dtype)
+        _run(L, perm, size, 2.0, A_full, 0.0, B, oa, ob)
+        Bv = B.reshape(ob, order="F")
+        inner = Bv[tuple(slice(0, s) for s in size_b)]
+        assert _same_bits(inner.flatten(order="F"), ref)
+        mask = np.ones(ob, dtype=bool)
+        mask[tuple(slice(0, s) for s in size_b)] = False
+        assert (Bv[mask] == canary).all()
+
+
+def pin_validation(L):
+    big = 1 << 40
+    c = lambda *a, **k: oracle.check(*a, library=L, **k)
+    assert c(0, (0, 1), (2, 3)) == oracle.OK
+    assert c(2, (0, 1), (2, 3)) == oracle.EINVAL            # unknown dtype
+    assert c(0, (0, 0), (2, 3)) == oracle.EPERM             # repeated index
+    assert c(0, (0, 2), (2, 3)) == oracle.EPERM             # out of range
+    assert c(0, (1, 0), (2, -1)) == oracle.EINVAL           # negative extent
+    assert c(0, (1, 0), (2, 3), outer_a=(1, 3)) == oracle.EINVAL
+    assert c(0, (1, 0), (2, 3), outer_b=(3, 1)) == oracle.EINVAL   # outer_b is in B order
+    assert c(0, (1, 0), (2, 3), outer_b=(3, 2)) == oracle.OK
+    assert c(0, (), (), n=0) == oracle.EINVAL
+    assert c(0, tuple(range(17)), (1,) * 17) == oracle.EINVAL
+    assert c(0, (1, 0), (2, 3), a_addr=big, b_addr=big + 20) == oracle.EOVERLAP
+    assert c(0, (1, 0), (2, 3), a_addr=big, b_addr=big + 24) == oracle.OK
+    assert c(1, (1, 0), (2, 3), a_addr=big, b_addr=big + 24) == oracle.EOVERLAP
+    assert c(0, (1, 0), (0, 3), a_addr=big, b_addr=big) == oracle.OK   # empty: nothing to do
+
+
+PINS = [pin_sec21_example, pin_index_encoding, pin_brute_force_vs_numpy, pin_textbook_2d,
+        pin_round_trip, pin_composition, pin_update_vs_axpby, pin_identity_is_axpby,
+        pin_beta_zero_does_not_read_b, pin_contraction_detector, pin_special_values,
+        pin_embedded_canaries, pin_validation]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
+def test_oracle_pin(pin):
+    pin(oracle.lib())
+
+
+def test_numpy_mirror_matches_sec21_example():
+    g = _golden("sec21_merge_example.json")
+    size = g["size"]
+    i0, i1, i2 = np.meshgrid(*[np.arange(s) for s in size], indexing="ij")
+    A = (i0 + 10 * i1 + 100 * i2).astype(np.float64).flatten(order="F")
+    B = np.zeros(_elems(size))
+    transpose_np(g["perm"], size, 1.0, A, 0.0, B)
+    assert B.tolist() == [float(v) for v in g["B_flat_column_major"]]
+
+
+# ---------------------------------------------------------------------------------------
+# Planted mistakes: each line below is one plausible error in the oracle's source.
+MUTANTS = {
+    "scatter_reading": [("size_b[k] = size[perm[k]];", "size_b[perm[k]] = size[k];"),
+                        ("a_stride_in_b_order[k] = stride_a[perm[k]];",
+                         "a_stride_in_b_order[perm[k]] = stride_a[k];")],
+    "dropped_beta_term": [("B[off_b] = scaled_a + scaled_b;", "B[off_b] = scaled_a;")],
+    "wrong_sign": [("B[off_b] = scaled_a + scaled_b;", "B[off_b] = scaled_a - scaled_b;")],
+    "fused_update": [("float scaled_b = beta * B[off_b];\n        B[off_b] = scaled_a + scaled_b;",
+                      "B[off_b] = __builtin_fmaf(alpha, A[off_a], beta * B[off_b]);"),
+                     ("double scaled_b = beta * B[off_b];\n        B[off_b] = scaled_a + scaled_b;",
+                      "B[off_b] = __builtin_fma(alpha, A[off_a], beta * B[off_b]);")],
+    "ldb_from_lda": [("int64_t o = outer_b ? outer_b[k] : size_b[k];",
+                      "int64_t o = outer_a ? outer_a[k] : size_b[k];")],
+    "reads_b_when_beta_zero": [("B[off_b] = alpha * A[off_a];\n",
+                                "B[off_b] = alpha * A[off_a] + beta * B[off_b];\n")],
+    "unpermuted_read": [("off_a += j[k] * a_stride_in_b_order[k];", "off_a += j[k] * stride_a[k];")],
+    "alpha_dropped": [("B[off_b] = alpha * A[off_a];\n", "B[off_b] = A[off_a];\n")],
+    "lda_reversed": [("int64_t o = outer_a ? outer_a[m] : size[m];",
+                      "int64_t o = outer_a ? outer_a[n - 1 - m] : size[m];")],
+}
+
+
+def _build_mutant(tmp, name, edits):
+    with open(oracle_build.SRC) as f:
+        src = f.read()
+    for old, new in edits:
+        assert old in src, (name, old)
+        src = src.replace(old, new)
+    if name == "transposed_strides":   # stride over the other tensor's outer sizes
+        src = src.replace("int64_t o = outer_a ? outer_a[m] : size[m];",
+                          "int64_t o = outer_a ? outer_a[n - 1 - m] : size[n - 1 - m];"
+                          " if (o < size[m]) o = size[m];")
+    path = os.path.join(tmp, name + ".c")
+    with open(path, "w") as f:
+        f.write(src)
+    return oracle_build.build(out=os.path.join(tmp, "lib" + name + ".so"), src=path, extra=("-w",))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_pins_catch_planted_mistakes():
+    tmp = tempfile.mkdtemp(prefix="ttx_mutants_")
+    try:
+        for name, edits in MUTANTS.items():
+            L = oracle._load(_build_mutant(tmp, name, edits))
+            caught = []
+            for pin in PINS:
+                try:
+                    pin(L)
+                except AssertionError:
+                    caught.append(pin.__name__)
+            assert caught, "no pin catches the planted mistake %r" % name
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)

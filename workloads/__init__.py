@@ -1,0 +1,133 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module describes workloads only: shapes, permutations, scalars and
+uniformly distributed element values drawn from numpy's PCG64 generator.
+It holds none of the transposition's arithmetic; both the CPU oracle and the
+HIP library receive exactly the bits produced here.
+
+The paper's own benchmark (57 transpositions, 2D to 6D, about 200 MB per
+tensor, Sec. 3) is not available; the shapes below stand in for it with the
+same class of sizes.
+"""
+import math
+
+import numpy as np
+
+F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+
+
+def uniform(n, dtype, seed):
+    """n values uniform in [-1, 1) of the given dtype (exact on the dtype's grid)."""
+    rng = np.random.default_rng(seed)
+    dtype = np.dtype(dtype)
+    if dtype == F32:
+        return rng.random(int(n), dtype=np.float32) * 2 - 1
+    return rng.random(int(n)) * 2 - 1
+
+
+def elements(size):
+    return int(np.prod([int(s) for s in size], dtype=np.int64))
+
+
+# -- plain single transposition (correctness case) ------------------------------------
+PLAIN = dict(name="plain_3d_f32", dtype=F32, size=(96, 128, 80), perm=(2, 1, 0),
+             alpha=1.0, beta=0.0, seed_a=0)
+
+# -- paper-shaped large transpositions, about 200 MiB per tensor ----------------------
+LARGE_SHAPES = {
+    ("4d", F32): (160, 160, 64, 32),
+    ("4d", F64): (160, 160, 32, 32),
+    ("5d", F32): (40, 32, 40, 32, 32),
+    ("5d", F64): (44, 32, 24, 32, 24),
+    ("6d", F32): (24, 21, 20, 18, 17, 17),
+    ("6d", F64): (20, 16, 16, 20, 16, 16),
+}
+LARGE_PERMS = {
+    "4d": [(1, 0, 3, 2), (3, 2, 1, 0), (0, 2, 1, 3), (2, 0, 3, 1)],
+    "5d": [(4, 3, 2, 1, 0), (1, 3, 0, 4, 2), (0, 3, 2, 4, 1)],
+    "6d": [(5, 4, 3, 2, 1, 0), (0, 5, 1, 4, 2, 3)],
+}
+# the literal "(160,160,160,160)" shape: 2.44 GiB (FP32) / 4.88 GiB (FP64) per tensor
+LITERAL_4D = (160, 160, 160, 160)
+
+
+def large_cases(betas=(0.7, 0.0)):
+    """All paper-shaped large cases: dicts with name, dtype, size, perm, alpha, beta, seeds."""
+    out = []
+    case = 0
+    for rank in ("4d", "5d", "6d"):
+        for dtype in (F32, F64):
+            size = LARGE_SHAPES[(rank, dtype)]
+            for perm in LARGE_PERMS[rank]:
+                for beta in betas:
+                    out.append(dict(
+                        name="%s_%s_p%s_b%s" % (rank, "f32" if dtype == F32 else "f64",
+                                                "".join(map(str, perm)), beta),
+                        dtype=dtype, size=size, perm=perm, alpha=1.3, beta=beta,
+                        seed_a=1000 + case, seed_b=2000 + case))
+                    case += 1
+    return out
+
+
+# -- multiple leading dimensions (BLAS-3 packing shapes) ------------------------------
+LD_CASES = [
+    dict(name="ld_f64_packing", dtype=F64, size=(384, 96, 48, 32), perm=(1, 0, 2, 3),
+         outer_a=(400, 100, 48, 32), outer_b=(100, 400, 50, 32)),
+    dict(name="awkward_f32", dtype=F32, size=(7, 1023, 33, 65), perm=(1, 2, 3, 0),
+         outer_a=None, outer_b=None),
+    dict(name="awkward_f64", dtype=F64, size=(7, 1023, 33, 65), perm=(1, 2, 3, 0),
+         outer_a=None, outer_b=None),
+]
+LD_SCALARS = [(1.0, 0.0), (-0.5, 1.0)]
+
+
+# -- batched: 512 uneven transpositions ----------------------------------------------
+def batched_problems(count=512, seed=4, min_elems=4096, max_elems=4194304):
+    """Random problems: N uniform in 2..6, random perm, element count log-uniform in
+    [min_elems, max_elems] split across dims by a flat Dirichlet draw, 70% FP32,
+    alpha uniform in [-2, 2], beta zero with probability 1/4 else uniform in [-2, 2].
+    Degenerate draws (size-1 dims, identity after merging) are kept."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for _ in range(count):
+        n = int(rng.integers(2, 7))
+        perm = tuple(int(p) for p in rng.permutation(n))
+        e = math.exp(rng.uniform(math.log(min_elems), math.log(max_elems)))
+        w = rng.dirichlet(np.ones(n))
+        size = tuple(max(1, int(round(e ** float(wk)))) for wk in w)
+        dtype = F32 if rng.random() < 0.7 else F64
+        alpha = float(rng.uniform(-2, 2))
+        beta = 0.0 if rng.random() < 0.25 else float(rng.uniform(-2, 2))
+        probs.append(dict(dtype=dtype, size=size, perm=perm, alpha=alpha, beta=beta))
+    return probs
+
+
+# -- served: Poisson arrivals ---------------------------------------------------------
+def served_trace(rate=20000.0, duration=10.0, seed_arrivals=5, seed_shapes=6,
+                 large_frac=0.05, large_bytes=(64 << 20, 256 << 20)):
+    """Open-loop request trace: arrival times (seconds, exponential gaps at ``rate``)
+    and request shapes drawn as for the batched workload, with ``large_frac`` of
+    requests large (bytes log-uniform in ``large_bytes``, N in 3..6)."""
+    rng = np.random.default_rng(seed_arrivals)
+    gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 1.2) + 16)
+    times = np.cumsum(gaps)
+    times = times[times < duration]
+    shapes = np.random.default_rng(seed_shapes)
+    reqs = []
+    for _ in range(len(times)):
+        large = shapes.random() < large_frac
+        n = int(shapes.integers(3, 7)) if large else int(shapes.integers(2, 7))
+        perm = tuple(int(p) for p in shapes.permutation(n))
+        dtype = F32 if shapes.random() < 0.7 else F64
+        if large:
+            nbytes = math.exp(shapes.uniform(math.log(large_bytes[0]), math.log(large_bytes[1])))
+            e = nbytes / dtype.itemsize
+        else:
+            e = math.exp(shapes.uniform(math.log(4096), math.log(4194304)))
+        w = shapes.dirichlet(np.ones(n))
+        size = tuple(max(1, int(round(e ** float(wk)))) for wk in w)
+        alpha = float(shapes.uniform(-2, 2))
+        beta = 0.0 if shapes.random() < 0.25 else float(shapes.uniform(-2, 2))
+        reqs.append(dict(dtype=dtype, size=size, perm=perm, alpha=alpha, beta=beta,
+                         large=bool(large)))
+    return times, reqs
