@@ -51,6 +51,12 @@ def _load(path):
     L.ttx_ref_check.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
                                 ctypes.c_void_p, ctypes.c_void_p]
     L.ttx_ref_check.restype = ctypes.c_int
+    L.ttx_ref_sample.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p, ctypes.c_double,
+                                 ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                 i64p, ctypes.c_void_p]
+    L.ttx_ref_sample.restype = ctypes.c_int
+    L.ttx_ref_b_offsets.argtypes = [ctypes.c_int, ip, i64p, i64p, ctypes.c_int64, i64p, i64p]
+    L.ttx_ref_b_offsets.restype = ctypes.c_int
     return L
 
 
@@ -88,3 +94,24 @@ def check(dtype_code, perm, size, outer_a=None, outer_b=None, a_addr=1 << 20, b_
                            _arr(size, ctypes.c_int64) if size is not None else None,
                            _arr(outer_a, ctypes.c_int64), _arr(outer_b, ctypes.c_int64),
                            a_addr, b_addr)
+
+
+def sample(perm, size, alpha, A, beta, B_in, b_index, outer_a=None, outer_b=None, library=None):
+    """Eqn. 1 at the B-linear sub-tensor positions ``b_index`` (int64 array);
+    returns (expected values, their offsets inside B's outer tensor)."""
+    L = library or lib()
+    b_index = np.ascontiguousarray(b_index, dtype=np.int64)
+    out = np.empty(len(b_index), dtype=A.dtype)
+    off = np.empty(len(b_index), dtype=np.int64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    st = L.ttx_ref_sample(DTYPES[A.dtype], len(perm), _arr(perm, ctypes.c_int),
+                          _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
+                          _arr(outer_b, ctypes.c_int64), float(alpha), A.ctypes.data, float(beta),
+                          B_in.ctypes.data if B_in is not None else None, len(b_index),
+                          b_index.ctypes.data_as(i64p), out.ctypes.data)
+    assert st == OK, st
+    st = L.ttx_ref_b_offsets(len(perm), _arr(perm, ctypes.c_int), _arr(size, ctypes.c_int64),
+                             _arr(outer_b, ctypes.c_int64), len(b_index),
+                             b_index.ctypes.data_as(i64p), off.ctypes.data_as(i64p))
+    assert st == OK, st
+    return out, off

@@ -200,3 +200,74 @@ int ttx_ref_transpose(int dtype, int n, const int *perm, const int64_t *size,
     }
     return REF_OK;
 }
+
+/* Eqn. 1 at chosen elements only: for each q < count, B_index[q] is the
+ * position of an element of B's sub-tensor in B-linear order (B index 0
+ * fastest); out[q] receives alpha*A + beta*B_in at that position, where A is
+ * the element the permutation sends there.  B_in is read only when the
+ * rounded beta is non-zero.  Lets large problems be checked on samples. */
+int ttx_ref_sample(int dtype, int n, const int *perm, const int64_t *size,
+                   const int64_t *outer_a, const int64_t *outer_b,
+                   double alpha, const void *A, double beta, const void *B_in,
+                   int64_t count, const int64_t *B_index, void *out)
+{
+    int64_t size_b[REF_MAX_DIMS], stride_a[REF_MAX_DIMS], stride_b[REF_MAX_DIMS];
+    int empty, st;
+    const float alpha_f = (float)alpha, beta_f = (float)beta;
+
+    st = ref_prepare(dtype, n, perm, size, outer_a, outer_b, size_b, stride_a, stride_b, &empty);
+    if (st != REF_OK)
+        return st;
+    if (empty)
+        return count == 0 ? REF_OK : REF_EINVAL;
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t rest = B_index[q], off_a = 0, off_b = 0;
+        for (int k = 0; k < n; ++k) {
+            int64_t j = rest % size_b[k];
+            rest /= size_b[k];
+            off_a += j * stride_a[perm[k]];
+            off_b += j * stride_b[k];
+        }
+        if (B_index[q] < 0 || rest != 0)
+            return REF_EINVAL;
+        if (dtype == REF_F32) {
+            float b = beta_f == 0.0f ? 0.0f : ((const float *)B_in)[off_b];
+            float r = alpha_f * ((const float *)A)[off_a];
+            if (beta_f != 0.0f) {
+                float scaled_b = beta_f * b;
+                r = r + scaled_b;
+            }
+            ((float *)out)[q] = r;
+        } else {
+            double b = beta == 0.0 ? 0.0 : ((const double *)B_in)[off_b];
+            double r = alpha * ((const double *)A)[off_a];
+            if (beta != 0.0) {
+                double scaled_b = beta * b;
+                r = r + scaled_b;
+            }
+            ((double *)out)[q] = r;
+        }
+    }
+    return REF_OK;
+}
+
+/* Offset (in elements) of each B-linear sub-tensor position inside B's outer
+ * tensor, so that samples can be compared against a full B buffer. */
+int ttx_ref_b_offsets(int n, const int *perm, const int64_t *size, const int64_t *outer_b,
+                      int64_t count, const int64_t *B_index, int64_t *off)
+{
+    int64_t size_b[REF_MAX_DIMS], stride_a[REF_MAX_DIMS], stride_b[REF_MAX_DIMS];
+    int empty;
+    int st = ref_prepare(REF_F32, n, perm, size, NULL, outer_b, size_b, stride_a, stride_b, &empty);
+    if (st != REF_OK)
+        return st;
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t rest = B_index[q], o = 0;
+        for (int k = 0; k < n; ++k) {
+            o += (rest % size_b[k]) * stride_b[k];
+            rest /= size_b[k];
+        }
+        off[q] = o;
+    }
+    return REF_OK;
+}

@@ -1,0 +1,232 @@
+// C ABI: errors, plans, the per-call entry point and the ceiling kernels.
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "ttx_internal.h"
+
+struct ttx_plan {
+    ttx::Problem prob;
+    ttx_config cfg[2];       // [beta_is_zero]
+    int from_table[2];
+    bool user_set[2];
+    uint64_t table_gen;
+};
+
+namespace ttx {
+
+static thread_local std::string g_last_error;
+
+ttx_status fail(ttx_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static void resolve_configs(ttx_plan* plan) {
+    plan->table_gen = table_generation();
+    for (int z = 0; z < 2; ++z) {
+        if (plan->user_set[z]) continue;
+        ttx_config c;
+        if (table_lookup(plan->prob, z == 1, &c)) {
+            plan->cfg[z] = c;
+            plan->from_table[z] = 1;
+        } else {
+            plan->cfg[z] = default_config(plan->prob);
+            plan->from_table[z] = 0;
+        }
+    }
+}
+
+static ttx_status new_plan(ttx_plan** out, int dtype, int n, const int* perm, const int64_t* size,
+                           const int64_t* outer_a, const int64_t* outer_b) {
+    Problem p;
+    ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    if (st != TTX_OK) return st;
+    ttx_plan* plan = new (std::nothrow) ttx_plan;
+    if (!plan) return fail(TTX_ENOMEM, "out of host memory");
+    std::memset(plan, 0, sizeof(*plan));
+    plan->prob = p;
+    resolve_configs(plan);
+    *out = plan;
+    return TTX_OK;
+}
+
+static bool ranges_overlap(const void* x, int64_t xlen, const void* y, int64_t ylen) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
+    return a < b + uint64_t(ylen) && b < a + uint64_t(xlen);
+}
+
+static ttx_status execute(const ttx_plan* plan, double alpha, const void* A, double beta,
+                          const void* Bin, void* Bout, hipStream_t stream) {
+    const Problem& p = plan->prob;
+    if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
+    const bool beta0 = p.dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
+    if (!A || !Bout || (!beta0 && !Bin)) return fail(TTX_EINVAL, "NULL tensor pointer");
+    const uintptr_t esz = p.dtype == TTX_F32 ? 4 : 8;
+    if (reinterpret_cast<uintptr_t>(A) % esz || reinterpret_cast<uintptr_t>(Bout) % esz ||
+        (!beta0 && reinterpret_cast<uintptr_t>(Bin) % esz))
+        return fail(TTX_EINVAL, "tensor pointer not aligned to the element size");
+    if (ranges_overlap(A, p.extent_a, Bout, p.extent_b))
+        return fail(TTX_EOVERLAP, "A and B overlap (the operation is out-of-place)");
+    if (!beta0 && Bin != Bout && ranges_overlap(Bin, p.extent_b, Bout, p.extent_b))
+        return fail(TTX_EOVERLAP, "B_in and B_out overlap without being equal");
+    hipError_t e = launch_tiles(p, plan->cfg[beta0 ? 1 : 0], beta0, A, beta0 ? nullptr : Bin, Bout,
+                                alpha, beta, stream);
+    if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return TTX_OK;
+}
+
+// Plan cache for ttx_transpose, keyed by the raw arguments.
+static std::mutex g_cache_mu;
+static std::unordered_map<std::string, std::shared_ptr<ttx_plan>> g_cache;
+static constexpr size_t kCacheCap = 4096;
+
+static std::string cache_key(int dtype, int n, const int* perm, const int64_t* size,
+                             const int64_t* outer_a, const int64_t* outer_b) {
+    std::string k;
+    k.reserve(16 + n * 28);
+    auto put = [&](const void* src, size_t len) { k.append(static_cast<const char*>(src), len); };
+    put(&dtype, sizeof(dtype));
+    put(&n, sizeof(n));
+    put(perm, sizeof(int) * n);
+    put(size, sizeof(int64_t) * n);
+    const char na = outer_a ? 1 : 0, nb = outer_b ? 1 : 0;
+    put(&na, 1);
+    if (outer_a) put(outer_a, sizeof(int64_t) * n);
+    put(&nb, 1);
+    if (outer_b) put(outer_b, sizeof(int64_t) * n);
+    return k;
+}
+
+}  // namespace ttx
+
+using namespace ttx;
+
+extern "C" {
+
+const char* ttx_status_string(ttx_status s) {
+    switch (s) {
+        case TTX_OK: return "ok";
+        case TTX_EINVAL: return "invalid argument";
+        case TTX_EPERM: return "perm is not a permutation";
+        case TTX_EOVERLAP: return "A and B overlap";
+        case TTX_EUNSUPPORTED: return "unsupported";
+        case TTX_ENOMEM: return "out of memory";
+        case TTX_EHIP: return "HIP error";
+        case TTX_EBUSY: return "busy: request not admitted";
+        case TTX_ENOTFOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+const char* ttx_last_error(void) { return g_last_error.c_str(); }
+
+const char* ttx_version(void) { return "ttx 0.1 gfx950"; }
+
+ttx_status ttx_plan_create(ttx_plan** plan, ttx_dtype dtype, int n, const int* perm,
+                           const int64_t* size, const int64_t* outer_a, const int64_t* outer_b) {
+    if (!plan) return fail(TTX_EINVAL, "plan must not be NULL");
+    return new_plan(plan, dtype, n, perm, size, outer_a, outer_b);
+}
+
+ttx_status ttx_plan_execute(const ttx_plan* plan, double alpha, const void* A, double beta, void* B,
+                            hipStream_t stream) {
+    if (!plan) return fail(TTX_EINVAL, "plan must not be NULL");
+    return execute(plan, alpha, A, beta, B, B, stream);
+}
+
+ttx_status ttx_plan_execute_split(const ttx_plan* plan, double alpha, const void* A, double beta,
+                                  const void* B_in, void* B_out, hipStream_t stream) {
+    if (!plan) return fail(TTX_EINVAL, "plan must not be NULL");
+    return execute(plan, alpha, A, beta, B_in, B_out, stream);
+}
+
+ttx_status ttx_plan_describe(const ttx_plan* plan, ttx_plan_info* info) {
+    if (!plan || !info) return fail(TTX_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    const Problem& p = plan->prob;
+    info->dtype = p.dtype;
+    info->family = p.family;
+    info->n = p.n;
+    for (int d = 0; d < p.n; ++d) {
+        info->perm[d] = p.perm[d];
+        info->size[d] = p.dim[d].size;
+        info->stride_a[d] = p.dim[d].sa;
+        info->stride_b[d] = p.dim[d].sb;
+    }
+    info->elements = p.elements;
+    info->extent_a_bytes = p.extent_a;
+    info->extent_b_bytes = p.extent_b;
+    for (int z = 0; z < 2; ++z) {
+        info->config[z] = plan->cfg[z];
+        info->config_from_table[z] = plan->from_table[z];
+    }
+    return TTX_OK;
+}
+
+ttx_status ttx_plan_set_config(ttx_plan* plan, int beta_is_zero, const ttx_config* config) {
+    if (!plan || !config) return fail(TTX_EINVAL, "NULL argument");
+    std::string why;
+    if (!config_valid(plan->prob, *config, &why)) return fail(TTX_EINVAL, why);
+    const int z = beta_is_zero ? 1 : 0;
+    plan->cfg[z] = *config;
+    plan->user_set[z] = true;
+    plan->from_table[z] = 0;
+    return TTX_OK;
+}
+
+ttx_status ttx_plan_destroy(ttx_plan* plan) {
+    delete plan;
+    return TTX_OK;
+}
+
+ttx_status ttx_transpose(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                         const int64_t* outer_a, const int64_t* outer_b, double alpha,
+                         const void* A, double beta, void* B, hipStream_t stream) {
+    if (n < 1 || n > kMaxDims || !perm || !size) {
+        Problem p;
+        return make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    }
+    const std::string key = cache_key(dtype, n, perm, size, outer_a, outer_b);
+    std::shared_ptr<ttx_plan> plan;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) plan = it->second;
+    }
+    if (!plan || plan->table_gen != table_generation()) {
+        ttx_plan* raw = nullptr;
+        ttx_status st = new_plan(&raw, dtype, n, perm, size, outer_a, outer_b);
+        if (st != TTX_OK) return st;
+        plan.reset(raw);
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (g_cache.size() >= kCacheCap) g_cache.clear();
+        g_cache[key] = plan;
+    }
+    return execute(plan.get(), alpha, A, beta, B, B, stream);
+}
+
+ttx_status ttx_copy_kernel(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
+    if (!src || !dst || bytes < 0 || bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||
+        reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(TTX_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    if (bytes == 0) return TTX_OK;
+    hipError_t e = launch_copy16(src, dst, bytes, stream);
+    return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, hipGetErrorString(e));
+}
+
+ttx_status ttx_axpby_kernel(ttx_dtype dtype, int64_t n, double alpha, const void* x, double beta,
+                            void* y, hipStream_t stream) {
+    if ((dtype != TTX_F32 && dtype != TTX_F64) || n < 0 || !x || !y ||
+        reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
+        return fail(TTX_EINVAL, "axpby needs a valid dtype and 16-byte aligned pointers");
+    if (n == 0) return TTX_OK;
+    hipError_t e = launch_axpby(dtype, n, alpha, x, beta, y, stream);
+    return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Host-side launch of one planned transposition, the flat kernel, and the
+// bandwidth-ceiling kernels used for measurement.
+#include <mutex>
+
+#include "registry.h"
+#include "tile_kernels.h"
+
+namespace ttx {
+
+static constexpr uint32_t kMaxGrid = 1u << 20;
+
+static int device_cus() {
+    static std::mutex mu;
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+template <typename T>
+static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                              const void* Bsrc, void* Bdst, double alpha, double beta,
+                              hipStream_t stream) {
+    FlatArgs<T> a;
+    a.A = static_cast<const T*>(A);
+    a.Bsrc = static_cast<const T*>(Bsrc);
+    a.Bdst = static_cast<T*>(Bdst);
+    a.alpha = T(alpha);
+    a.beta = T(beta);
+    a.n = p.dim[0].size;
+    a.sa = p.dim[0].sa;
+    a.sb = p.dim[0].sb;
+    a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    const int64_t per_block = int64_t(kThreads) * ((a.flags & KF_VEC_A) ? kVec<T> * 4 : 1);
+    int64_t blocks = (a.n + per_block - 1) / per_block;
+    const int64_t cap = int64_t(device_cus()) * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    if (beta0)
+        hipLaunchKernelGGL((k_flat<T, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_flat<T, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                               const void* Bsrc, void* Bdst, double alpha, double beta,
+                               hipStream_t stream) {
+    TileArgs<T> a;
+    int64_t s[4];
+    build_grid(p, c, &a.g, s);
+    a.A = static_cast<const T*>(A);
+    a.Bsrc = static_cast<const T*>(Bsrc);
+    a.Bdst = static_cast<T*>(Bdst);
+    a.alpha = T(alpha);
+    a.beta = T(beta);
+    a.sAa = s[0];
+    a.sAb = s[1];
+    a.sBa = s[2];
+    a.sBb = s[3];
+    a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    const LauncherRow* table;
+    int n;
+    if (p.family == TTX_FAMILY_MOVED) {
+        if (p.dtype == TTX_F32)
+            n = beta0 ? moved_rows_f32_beta0(&table) : moved_rows_f32_beta(&table);
+        else
+            n = beta0 ? moved_rows_f64_beta0(&table) : moved_rows_f64_beta(&table);
+    } else {
+        n = preserved_rows(p.dtype, beta0, &table);
+    }
+    const int variant = a.flags & (KF_VEC_A | KF_VEC_B);
+    for (int i = 0; i < n; ++i) {
+        if (table[i].ta == c.tile_a && table[i].tb == c.tile_b) {
+            uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
+            return table[i].fn[variant](&a, grid, stream);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                        const void* Bsrc, void* Bdst, double alpha, double beta,
+                        hipStream_t stream) {
+    if (p.family == TTX_FAMILY_EMPTY) return hipSuccess;
+    if (p.family == TTX_FAMILY_FLAT) {
+        return p.dtype == TTX_F32 ? launch_flat<float>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream)
+                                  : launch_flat<double>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+    }
+    return p.dtype == TTX_F32 ? launch_tiled<float>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream)
+                              : launch_tiled<double>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Ceiling kernels: a 16-byte-vector copy and an unfused axpby (the SAXPY
+// peak of Sec. 3).  Grid-stride loops with 4 vectors in flight per thread.
+__global__ __launch_bounds__(kThreads) void k_copy16(const uint4* __restrict__ src,
+                                                     uint4* __restrict__ dst, int64_t nvec) {
+    constexpr int U = 4;
+    const int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t G = int64_t(gridDim.x) * kThreads;
+    for (int64_t base = gid; base < nvec; base += G * U) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * G < nvec) v[u] = src[base + u * G];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * G < nvec) dst[base + u * G] = v[u];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_axpby(const T* __restrict__ x, T* __restrict__ y,
+                                                    int64_t n, T alpha, T beta) {
+    constexpr int V = kVec<T>;
+    constexpr int U = 4;
+    const int64_t nv = n / V;
+    const int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t G = int64_t(gridDim.x) * kThreads;
+    for (int64_t base = gid; base < nv; base += G * U) {
+        vec_t<T, V> a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * G < nv) {
+                a[u] = ld<T, V>(x + (base + u * G) * V);
+                b[u] = ld<T, V>(y + (base + u * G) * V);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * G < nv)
+                st<T, V>(y + (base + u * G) * V, epilogue<T, V, false>(a[u], b[u], alpha, beta), false);
+    }
+    const int64_t i = nv * V + gid;
+    if (i < n) y[i] = epilogue<T, 1, false>(x[i], y[i], alpha, beta);
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
+    const int64_t nvec = bytes / 16;
+    int64_t blocks = (nvec + kThreads * 4 - 1) / (kThreads * 4);
+    const int64_t cap = int64_t(device_cus()) * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy16, dim3(uint32_t(blocks)), dim3(kThreads), 0, stream,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), nvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, double beta, void* y,
+                        hipStream_t stream) {
+    const int V = dtype == TTX_F32 ? 4 : 2;
+    int64_t blocks = (n / V + kThreads * 4 - 1) / (kThreads * 4);
+    const int64_t cap = int64_t(device_cus()) * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    if (dtype == TTX_F32)
+        hipLaunchKernelGGL((k_axpby<float>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream,
+                           static_cast<const float*>(x), static_cast<float*>(y), n, float(alpha), float(beta));
+    else
+        hipLaunchKernelGGL((k_axpby<double>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream,
+                           static_cast<const double*>(x), static_cast<double*>(y), n, alpha, beta);
+    return hipGetLastError();
+}
+
+}  // namespace ttx

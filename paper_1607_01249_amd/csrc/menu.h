@@ -1,0 +1,30 @@
+// Tile shapes the library instantiates, per dtype and kernel family.
+//
+// Sec. 2.2 blocks each tile edge by b in {w, 2w, 3w, 4w}.  Here w = 16
+// elements for both data types (64 B of FP32, one 128-B line of FP64), so the
+// regular moved-family tiles are {16,32,48,64} x {16,32,48,64}.  For indices
+// shorter than w the remainder rule of Sec. 2.3 would waste most of a tile,
+// so skinny shapes pair a short edge with a long one.  Preserved-family
+// tiles copy rows that are contiguous in both tensors; they are sized by
+// the number of elements a workgroup moves (1K to 4K).
+#pragma once
+
+// X(tile_a, tile_b)
+#define TTX_MOVED_MENU_F32(X)                                                             \
+    X(16, 16) X(16, 32) X(16, 48) X(16, 64) X(32, 16) X(32, 32) X(32, 48) X(32, 64)       \
+    X(48, 16) X(48, 32) X(48, 48) X(48, 64) X(64, 16) X(64, 32) X(64, 48) X(64, 64)       \
+    X(4, 256) X(8, 128) X(256, 4) X(128, 8)
+
+#define TTX_MOVED_MENU_F64(X)                                                             \
+    X(16, 16) X(16, 32) X(16, 48) X(16, 64) X(32, 16) X(32, 32) X(32, 48) X(32, 64)       \
+    X(48, 16) X(48, 32) X(48, 48) X(48, 64) X(64, 16) X(64, 32) X(64, 48) X(64, 64)       \
+    X(2, 256) X(4, 128) X(256, 2) X(128, 4)
+
+// X(tile_a, rows)
+#define TTX_PRESERVED_MENU_F32(X)                                                         \
+    X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
+    X(256, 4) X(256, 16) X(4, 256) X(8, 256)
+
+#define TTX_PRESERVED_MENU_F64(X)                                                         \
+    X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
+    X(256, 4) X(256, 16) X(2, 512) X(4, 256)

@@ -1,0 +1,25 @@
+// Kernel launcher tables: one row per instantiated tile shape.
+#pragma once
+
+#include "ttx_internal.h"
+
+namespace ttx {
+
+using TileLaunchFn = hipError_t (*)(const void* args, uint32_t grid, hipStream_t stream);
+
+// fn[v]: v = vector variant, bit 0 = 16-byte accesses along A's tile index,
+// bit 1 = along B's tile index (the preserved family uses 0 and 3 only).
+// A variant a shape cannot use (its tile edge is not a multiple of the
+// vector width) is instantiated with scalar accesses on that side.
+struct LauncherRow {
+    int ta, tb;
+    TileLaunchFn fn[4];
+};
+
+int moved_rows_f32_beta(const LauncherRow** out);
+int moved_rows_f32_beta0(const LauncherRow** out);
+int moved_rows_f64_beta(const LauncherRow** out);
+int moved_rows_f64_beta0(const LauncherRow** out);
+int preserved_rows(int dtype, bool beta0, const LauncherRow** out);
+
+}  // namespace ttx

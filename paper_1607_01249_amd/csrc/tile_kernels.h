@@ -1,0 +1,296 @@
+// Device code for the transposition kernels (gfx950, wave64).
+//
+// Sec. 2.2 splits an N-D transposition into independent 2D transpositions
+// ("macro-tiles") that run in parallel, one per thread block on GPUs, each
+// staged through on-chip memory.  Here one 256-thread workgroup handles one
+// tile at a time:
+//   - moved family (A's stride-1 index moves): the tile is TA elements along
+//     A's stride-1 index times TB elements along B's stride-1 index.  A is
+//     read along its stride-1 index with 16-byte vector loads, the tile is
+//     transposed through LDS (rows padded by one element so that the
+//     column-wise reads of the store phase fall in distinct banks), and B
+//     is written along its stride-1 index with 16-byte vector stores;
+//   - preserved family (the stride-1 index stays in place, Sec. 3.2): rows
+//     are contiguous in both tensors, so they are copied directly with
+//     vector loads and stores, no LDS;
+//   - flat: one merged index, a strided axpby.
+// Edge tiles are predicated (the remainder of Sec. 2.3).  The epilogue is
+// Eqn. 1: alpha*a when beta == 0 (B is never read), otherwise
+// alpha*a + beta*b with both products and the sum rounded separately.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ttx_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace ttx {
+
+template <typename T, int N>
+struct VecOf {
+    using type = T __attribute__((ext_vector_type(N)));
+};
+template <typename T>
+struct VecOf<T, 1> {
+    using type = T;
+};
+template <typename T, int N>
+using vec_t = typename VecOf<T, N>::type;
+
+template <typename T>
+constexpr int kVec = 16 / int(sizeof(T));
+
+template <typename T, int N>
+__device__ __forceinline__ T lane(const vec_t<T, N>& v, int j) {
+    if constexpr (N == 1)
+        return v;
+    else
+        return v[j];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void set_lane(vec_t<T, N>& v, int j, T x) {
+    if constexpr (N == 1)
+        v = x;
+    else
+        v[j] = x;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ vec_t<T, N> ld(const T* p) {
+    return *reinterpret_cast<const vec_t<T, N>*>(p);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void st(T* p, const vec_t<T, N>& v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, reinterpret_cast<vec_t<T, N>*>(p));
+    else
+        *reinterpret_cast<vec_t<T, N>*>(p) = v;
+}
+
+// Eqn. 1 on one vector: alpha*a, or alpha*a + beta*b (unfused).
+template <typename T, int N, bool BETA0>
+__device__ __forceinline__ vec_t<T, N> epilogue(const vec_t<T, N>& a, const vec_t<T, N>& b,
+                                                T alpha, T beta) {
+    if constexpr (BETA0) {
+        return alpha * a;
+    } else {
+        vec_t<T, N> pa = alpha * a;
+        vec_t<T, N> pb = beta * b;
+        return pa + pb;
+    }
+}
+
+// XCD-aware tile mapping.  Workgroups are dispatched round-robin over the
+// 8 XCDs of an MI355X, each with its own L2.  This bijection on [0, G) gives
+// XCD x the consecutive ids [start(x), start(x) + count(x)), so that tiles
+// that share cache lines or DRAM pages run under one L2.
+__device__ __forceinline__ uint32_t swizzle_id(uint32_t bid, uint32_t G) {
+    const uint32_t per = G >> 3, rem = G & 7;
+    const uint32_t x = bid & 7, local = bid >> 3;
+    const uint32_t start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return start + local;
+}
+
+struct TileCoord {
+    int64_t oa, ob;
+    int ea, eb;
+};
+
+// Tile id -> origin offsets in A and B and the extents of this (maybe edge) tile.
+__device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, int TA, int TB) {
+    TileCoord c{0, 0, TA, TB};
+    uint32_t rem = t;
+    for (int q = 0; q < g.nd; ++q) {
+        const uint32_t next = g.div[q].div(rem);
+        const uint32_t r = rem - next * g.count[q];
+        rem = next;
+        c.oa += int64_t(r) * g.stepA[q];
+        c.ob += int64_t(r) * g.stepB[q];
+        if (q == g.pa) c.ea = int(min(int64_t(TA), g.ext_a - int64_t(r) * TA));
+        if (q == g.pb) c.eb = int(min(int64_t(TB), g.ext_b - int64_t(r) * TB));
+    }
+    return c;
+}
+
+constexpr int pow2_ceil(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Thread layout used for both sides of a tile: a run of TA elements is
+// covered by P = pow2_ceil(TA / V) threads (the last P - TA/V idle when
+// TA / V is not a power of two), so NT / P runs are handled per pass and a
+// thread's address advances by a fixed stride from one pass to the next.
+
+// One moved-family tile: A[oa + x*sAa + y*sAb] -> B[ob + y*sBb + x*sBa] for
+// x < ea (A's stride-1 index), y < eb (B's stride-1 index).  VA / VB are the
+// vector widths along x in A and along y in B (VA > 1 implies sAa == 1,
+// VB > 1 implies sBb == 1).  `lds` holds TB rows of TA + 1 elements.
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
+__device__ __forceinline__ void moved_tile(T* __restrict__ lds, const TileArgs<T>& a,
+                                           const TileCoord& c) {
+    constexpr int NT = kThreads;
+    constexpr int LDR = TA + 1;
+    const int tid = threadIdx.x;
+    const bool nt = a.flags & KF_NT_STORE;
+
+    // A side: columns (fixed y) of TA elements along x.
+    constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
+    static_assert(PA <= NT, "tile edge too long for the workgroup");
+    const int xa = (tid % PA) * VA, ya = tid / PA;
+    const bool lane_a = (tid % PA) < LA;
+    const bool live_a = lane_a && xa < c.ea;
+    const T* pa = a.A + c.oa + int64_t(xa) * a.sAa + int64_t(ya) * a.sAb;
+    const int64_t step_a = int64_t(RA) * a.sAb;
+
+    // B side: rows (fixed x) of TB elements along y.
+    constexpr int LB = TB / VB, PB = pow2_ceil(LB), RB = NT / PB, NB = (TA + RB - 1) / RB;
+    static_assert(PB <= NT, "tile edge too long for the workgroup");
+    const int yb = (tid % PB) * VB, xb = tid / PB;
+    const bool live_b = (tid % PB) < LB && yb < c.eb;
+    const int64_t off_b = c.ob + int64_t(yb) * a.sBb + int64_t(xb) * a.sBa;
+    const int64_t step_b = int64_t(RB) * a.sBa;
+
+    vec_t<T, VA> ra[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + i * step_a);
+    vec_t<T, VB> rb[NB];
+    if constexpr (!BETA0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (live_b && xb + i * RB < c.ea) rb[i] = ld<T, VB>(a.Bsrc + off_b + i * step_b);
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int y = ya + i * RA;
+        if (lane_a && y < TB) {
+#pragma unroll
+            for (int j = 0; j < VA; ++j) lds[y * LDR + xa + j] = lane<T, VA>(ra[i], j);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int x = xb + i * RB;
+        if (live_b && x < c.ea) {
+            vec_t<T, VB> v;
+#pragma unroll
+            for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
+            vec_t<T, VB> o = epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta);
+            st<T, VB>(a.Bdst + off_b + i * step_b, o, nt);
+        }
+    }
+    __syncthreads();  // the next tile reuses the LDS buffer
+}
+
+// One preserved-family tile: rows of ea elements contiguous in A and B.
+// Row y < eb starts at A[oa + y*sAb] and B[ob + y*sBb]; element x of a row is
+// at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).
+template <typename T, bool BETA0, int TA, int TR, int V>
+__device__ __forceinline__ void preserved_tile(const TileArgs<T>& a, const TileCoord& c) {
+    constexpr int NT = kThreads;
+    constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
+    static_assert(P <= NT, "row too long for the workgroup");
+    const int tid = threadIdx.x;
+    const bool nt = a.flags & KF_NT_STORE;
+    const int x = (tid % P) * V, y0 = tid / P;
+    const bool live = (tid % P) < L && x < c.ea;
+    const int64_t off_a = c.oa + int64_t(x) * a.sAa + int64_t(y0) * a.sAb;
+    const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
+    const int64_t step_a = int64_t(R) * a.sAb, step_b = int64_t(R) * a.sBb;
+    vec_t<T, V> ra[N];
+    vec_t<T, V> rb[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (live && y0 + i * R < c.eb) {
+            ra[i] = ld<T, V>(a.A + off_a + i * step_a);
+            if constexpr (!BETA0) rb[i] = ld<T, V>(a.Bsrc + off_b + i * step_b);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (live && y0 + i * R < c.eb) {
+            vec_t<T, V> o = epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta);
+            st<T, V>(a.Bdst + off_b + i * step_b, o, nt);
+        }
+    }
+}
+
+// Vector widths are template parameters so that each variant gets its own
+// register allocation: the scalar fallbacks need many more address
+// registers than the 16-byte paths and would otherwise lower the occupancy
+// of every variant.  Scalar variants ask for at least 4 waves per SIMD.
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
+void k_moved(TileArgs<T> a) {
+    __shared__ T lds[TB * (TA + 1)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    for (uint32_t t = first; t < a.g.ntiles; t += G) {
+        const TileCoord c = decode_tile(a.g, t, TA, TB);
+        moved_tile<T, BETA0, TA, TB, VA, VB>(lds, a, c);
+    }
+}
+
+template <typename T, bool BETA0, int TA, int TR, int V>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
+void k_preserved(TileArgs<T> a) {
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    for (uint32_t t = first; t < a.g.ntiles; t += G) {
+        const TileCoord c = decode_tile(a.g, t, TA, TR);
+        preserved_tile<T, BETA0, TA, TR, V>(a, c);
+    }
+}
+
+// Flat: one index of n elements with strides sa, sb.  The vector path
+// (contiguous, aligned) moves 4 vectors per thread per iteration; the
+// remaining n % V elements are handled one per thread.
+template <typename T, bool BETA0>
+__global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
+    constexpr int V = kVec<T>;
+    constexpr int U = 4;
+    const bool nt = a.flags & KF_NT_STORE;
+    const int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t G = int64_t(gridDim.x) * kThreads;
+    if (a.flags & KF_VEC_A) {
+        const int64_t nv = a.n / V;
+        for (int64_t base = gid; base < nv; base += G * U) {
+            vec_t<T, V> va[U], vb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = base + u * G;
+                if (i < nv) {
+                    va[u] = ld<T, V>(a.A + i * V);
+                    if constexpr (!BETA0) vb[u] = ld<T, V>(a.Bsrc + i * V);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = base + u * G;
+                if (i < nv) st<T, V>(a.Bdst + i * V, epilogue<T, V, BETA0>(va[u], vb[u], a.alpha, a.beta), nt);
+            }
+        }
+        const int64_t i = nv * V + gid;
+        if (i < a.n) {
+            T b = T(0);
+            if constexpr (!BETA0) b = a.Bsrc[i];
+            a.Bdst[i] = epilogue<T, 1, BETA0>(a.A[i], b, a.alpha, a.beta);
+        }
+        return;
+    }
+    for (int64_t i = gid; i < a.n; i += G) {
+        T b = T(0);
+        if constexpr (!BETA0) b = a.Bsrc[i * a.sb];
+        a.Bdst[i * a.sb] = epilogue<T, 1, BETA0>(a.A[i * a.sa], b, a.alpha, a.beta);
+    }
+}
+
+}  // namespace ttx

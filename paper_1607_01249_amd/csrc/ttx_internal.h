@@ -1,0 +1,147 @@
+// Internal types shared by the planner, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ttx.h"
+
+namespace ttx {
+
+constexpr int kMaxDims = TTX_MAX_DIMS;
+
+// Division by a run-time invariant 32-bit divisor with a multiply and a
+// shift (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994): for d >= 1, l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1 give n / d = (mulhi(n, m) + n) >> l for
+// every 32-bit n (the sum is formed in 64 bits).
+struct FastDiv {
+    uint32_t d;
+    uint32_t m;
+    uint32_t l;
+
+    FastDiv() : d(1), m(1), l(0) {}
+    explicit FastDiv(uint32_t divisor) { init(divisor); }
+
+    void init(uint32_t divisor) {
+        d = divisor ? divisor : 1;
+        l = 0;
+        while ((uint64_t(1) << l) < d) ++l;
+        m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    }
+
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        uint64_t hi = (uint64_t(n) * m) >> 32;
+        return uint32_t((hi + n) >> l);
+    }
+};
+
+// Description of the tiled iteration space shared by the tile kernels.
+// Tile ids enumerate the merged indices in `order` (fastest first); position
+// p has count[p] steps, and one step moves the tile origin by stepA[p] /
+// stepB[p] elements.  Positions pa and pb hold the two tile indices; their
+// full extents bound the edge tiles.
+struct TileGrid {
+    int nd;
+    int pa, pb;
+    uint32_t ntiles;
+    int64_t ext_a, ext_b;          // extents along the two tile indices
+    uint32_t count[kMaxDims];
+    FastDiv div[kMaxDims];
+    int64_t stepA[kMaxDims];
+    int64_t stepB[kMaxDims];
+};
+
+// Kernel-side flags (separate from TTX_CFG_*, which describe a config).
+enum : int {
+    KF_VEC_A = 1,      // 16-byte vector accesses along the tile index of A
+    KF_VEC_B = 2,      // 16-byte vector accesses along the tile index of B
+    KF_NT_STORE = 4,   // non-temporal stores to B
+    KF_SWIZZLE = 8,    // XCD-aware tile id mapping
+};
+
+template <typename T>
+struct TileArgs {
+    const T* A;
+    const T* Bsrc;      // read when beta != 0
+    T* Bdst;
+    T alpha, beta;
+    int64_t sAa, sAb;   // A strides of the two tile indices
+    int64_t sBa, sBb;   // B strides of the two tile indices
+    int flags;
+    TileGrid g;
+};
+
+template <typename T>
+struct FlatArgs {
+    const T* A;
+    const T* Bsrc;
+    T* Bdst;
+    T alpha, beta;
+    int64_t n;          // element count
+    int64_t sa, sb;     // strides of the single index
+    int flags;
+};
+
+// A merged problem (planner output), A order.
+struct Dim {
+    int64_t size;
+    int64_t sa;   // stride in A
+    int64_t sb;   // stride in B
+};
+
+struct Problem {
+    int dtype = 0;
+    int n = 0;                  // merged rank
+    Dim dim[kMaxDims];
+    int perm[kMaxDims];         // merged gather perm: B position k holds merged dim perm[k]
+    int family = TTX_FAMILY_EMPTY;
+    int64_t elements = 0;
+    int64_t extent_a = 0;       // bytes
+    int64_t extent_b = 0;
+    // original (unmerged) problem, kept for keys and descriptions
+    int n_orig = 0;
+};
+
+// Status with a thread-local message.
+ttx_status fail(ttx_status s, const std::string& msg);
+void clear_error();
+
+// Planner (host only).
+ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
+                        const int64_t* outer_a, const int64_t* outer_b, Problem* out);
+// Validates a config against a problem; fills *why on rejection.
+bool config_valid(const Problem& p, const ttx_config& c, std::string* why);
+// The heuristic default config (best-ranked candidate).
+ttx_config default_config(const Problem& p);
+// Candidate enumeration with estimated costs (sorted ascending).
+int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost, int cap);
+// Builds the kernel-side grid for a config.
+void build_grid(const Problem& p, const ttx_config& c, TileGrid* g, int64_t s[4]);
+// Flags for the vector paths given the pointers in use.
+int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const void* Bsrc,
+                 const void* Bdst);
+
+// Kernel menu (tile shapes the library instantiates), per dtype and family.
+struct TileShape { int ta, tb; };
+int tile_menu(int dtype, int family, const TileShape** shapes);
+bool tile_in_menu(int dtype, int family, int ta, int tb);
+constexpr int kThreads = 256;
+
+// Launchers (kernels.hip).  They return hipSuccess or the launch error.
+hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                        const void* Bsrc, void* Bdst, double alpha, double beta,
+                        hipStream_t stream);
+
+// Ceiling kernels (dispatch.hip).
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t stream);
+hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, double beta, void* y,
+                        hipStream_t stream);
+
+// Tune table (tune.cpp).
+bool table_lookup(const Problem& p, bool beta0, ttx_config* out);
+void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec);
+uint64_t table_generation();
+
+}  // namespace ttx

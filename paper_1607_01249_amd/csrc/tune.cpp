@@ -1,0 +1,228 @@
+// Autotuner and tune table (Sec. 2.1 stages 2-6; Sec. 2.3).
+//
+// The paper's TTC generates C++/CUDA source for each ranked candidate,
+// compiles it and times it, then stores the fastest ("solution") in an SQL
+// database consulted before any new search.  Here the candidates are
+// run-time configurations of pre-instantiated kernels (tile shape from the
+// menu, loop order, XCD swizzle, streaming stores), so stage 4 (compile)
+// disappears and stage 5 times each candidate directly on the GPU.  The
+// database is an in-process table keyed by the merged problem, with a
+// one-line-per-entry text format for saving and loading.
+#include <atomic>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <vector>
+
+#include "ttx_internal.h"
+
+namespace ttx {
+
+struct TableEntry {
+    ttx_config cfg;
+    double usec;
+};
+
+static std::mutex g_table_mu;
+static std::map<std::string, TableEntry> g_table;
+static std::atomic<uint64_t> g_table_gen{1};
+
+uint64_t table_generation() { return g_table_gen.load(); }
+
+// Key: dtype, beta == 0, and the merged problem (extents, permutation and
+// both stride vectors), so that every call that plans to the same merged
+// problem shares a solution (Sec. 2.1: lookup happens after merging).
+static std::string table_key(const Problem& p, bool beta0) {
+    std::ostringstream os;
+    os << "d" << p.dtype << ":b" << (beta0 ? 1 : 0) << ":n" << p.n << ":s";
+    for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.dim[i].size;
+    os << ":p";
+    for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.perm[i];
+    os << ":a";
+    for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.dim[i].sa;
+    os << ":o";
+    for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.dim[i].sb;
+    return os.str();
+}
+
+bool table_lookup(const Problem& p, bool beta0, ttx_config* out) {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    auto it = g_table.find(table_key(p, beta0));
+    if (it == g_table.end() || !config_valid(p, it->second.cfg, nullptr)) return false;
+    *out = it->second.cfg;
+    return true;
+}
+
+void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec) {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    g_table[table_key(p, beta0)] = TableEntry{c, usec};
+    g_table_gen.fetch_add(1);
+}
+
+static std::string config_text(const ttx_config& c) {
+    std::ostringstream os;
+    os << c.family << " " << c.tile_a << " " << c.tile_b << " " << c.threads << " " << c.flags << " "
+       << c.n_order;
+    for (int i = 0; i < c.n_order; ++i) os << " " << c.order[i];
+    return os.str();
+}
+
+static bool parse_config(std::istringstream& is, ttx_config* c) {
+    std::memset(c, 0, sizeof(*c));
+    if (!(is >> c->family >> c->tile_a >> c->tile_b >> c->threads >> c->flags >> c->n_order)) return false;
+    if (c->n_order < 0 || c->n_order > kMaxDims) return false;
+    for (int i = 0; i < c->n_order; ++i)
+        if (!(is >> c->order[i])) return false;
+    return true;
+}
+
+// A scratch area that evicts L2 and the 256 MiB Infinity Cache between timed
+// runs ("the caches are cleared before each run", Sec. 3).
+static constexpr size_t kFlushBytes = size_t(1) << 30;
+
+struct TuneScratch {
+    void* A = nullptr;
+    void* B = nullptr;
+    void* flush = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch() {
+        if (A) (void)hipFree(A);
+        if (B) (void)hipFree(B);
+        if (flush) (void)hipFree(flush);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+}  // namespace ttx
+
+using namespace ttx;
+
+extern "C" {
+
+ttx_status ttx_tune_candidates(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                               const int64_t* outer_a, const int64_t* outer_b, int max_candidates,
+                               ttx_config* out, double* cost, int cap, int* count) {
+    if (!out || !count || cap < 0) return fail(TTX_EINVAL, "NULL output or negative cap");
+    Problem p;
+    ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    if (st != TTX_OK) return st;
+    *count = rank_candidates(p, max_candidates, out, cost, cap);
+    return TTX_OK;
+}
+
+ttx_status ttx_tune(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                    const int64_t* outer_a, const int64_t* outer_b, int beta_is_zero,
+                    int max_candidates, int reps, ttx_config* best, int* n_timed) {
+    if (!best) return fail(TTX_EINVAL, "best must not be NULL");
+    if (reps <= 0) reps = 3;
+    Problem p;
+    ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    if (st != TTX_OK) return st;
+    if (n_timed) *n_timed = 0;
+    if (p.family == TTX_FAMILY_EMPTY) {
+        *best = default_config(p);
+        return TTX_OK;
+    }
+    const int keep = max_candidates == 0 ? 200 : max_candidates;
+    std::vector<ttx_config> cands(keep < 0 ? 1 << 17 : keep);
+    int nc = rank_candidates(p, max_candidates, cands.data(), nullptr, int(cands.size()));
+    if (nc <= 0) return fail(TTX_EUNSUPPORTED, "no candidate for this problem");
+
+    TuneScratch s;
+    if (hipMalloc(&s.A, size_t(p.extent_a) + 16) != hipSuccess ||
+        hipMalloc(&s.B, size_t(p.extent_b) + 16) != hipSuccess ||
+        hipMalloc(&s.flush, kFlushBytes) != hipSuccess)
+        return fail(TTX_ENOMEM, "tuner scratch allocation failed");
+    if (hipStreamCreate(&s.stream) != hipSuccess || hipEventCreate(&s.e0) != hipSuccess ||
+        hipEventCreate(&s.e1) != hipSuccess)
+        return fail(TTX_EHIP, "tuner stream/event creation failed");
+    if (hipMemsetAsync(s.A, 0, size_t(p.extent_a), s.stream) != hipSuccess ||
+        hipMemsetAsync(s.B, 0, size_t(p.extent_b), s.stream) != hipSuccess)
+        return fail(TTX_EHIP, "tuner scratch initialisation failed");
+
+    const bool beta0 = beta_is_zero != 0;
+    const double alpha = 1.0, beta = beta0 ? 0.0 : 1.0;
+    double best_us = 1e300;
+    int best_i = -1;
+    for (int i = 0; i < nc; ++i) {
+        hipError_t e = launch_tiles(p, cands[i], beta0, s.A, s.B, s.B, alpha, beta, s.stream);
+        if (e != hipSuccess) return fail(TTX_EHIP, std::string("tuner launch: ") + hipGetErrorString(e));
+        double t_min = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            if (hipMemsetAsync(s.flush, r & 0xff, kFlushBytes, s.stream) != hipSuccess ||
+                hipEventRecord(s.e0, s.stream) != hipSuccess)
+                return fail(TTX_EHIP, "tuner timing failed");
+            e = launch_tiles(p, cands[i], beta0, s.A, s.B, s.B, alpha, beta, s.stream);
+            if (e != hipSuccess || hipEventRecord(s.e1, s.stream) != hipSuccess ||
+                hipEventSynchronize(s.e1) != hipSuccess)
+                return fail(TTX_EHIP, "tuner timing failed");
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, s.e0, s.e1);
+            if (ms * 1e3 < t_min) t_min = ms * 1e3;
+        }
+        // ties keep the earlier (better-ranked) candidate
+        if (t_min < best_us) {
+            best_us = t_min;
+            best_i = i;
+        }
+    }
+    if (hipStreamSynchronize(s.stream) != hipSuccess) return fail(TTX_EHIP, "tuner sync failed");
+    *best = cands[best_i];
+    if (n_timed) *n_timed = nc;
+    table_store(p, beta0, *best, best_us);
+    return TTX_OK;
+}
+
+ttx_status ttx_tune_table_save(const char* path) {
+    if (!path) return fail(TTX_EINVAL, "NULL path");
+    std::ofstream f(path);
+    if (!f) return fail(TTX_EINVAL, "cannot open tune table for writing");
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    f << "# ttx tune table v1: key | family tile_a tile_b threads flags n_order order... | usec\n";
+    for (const auto& kv : g_table)
+        f << kv.first << " | " << config_text(kv.second.cfg) << " | " << kv.second.usec << "\n";
+    return f ? TTX_OK : fail(TTX_EINVAL, "write failed");
+}
+
+ttx_status ttx_tune_table_load(const char* path) {
+    if (!path) return fail(TTX_EINVAL, "NULL path");
+    std::ifstream f(path);
+    if (!f) return fail(TTX_ENOTFOUND, "cannot open tune table");
+    std::map<std::string, TableEntry> loaded;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        size_t a = line.find(" | "), b = line.rfind(" | ");
+        if (a == std::string::npos || b == a) return fail(TTX_EINVAL, "malformed tune table line");
+        TableEntry e;
+        std::istringstream cs(line.substr(a + 3, b - a - 3));
+        if (!parse_config(cs, &e.cfg)) return fail(TTX_EINVAL, "malformed config in tune table");
+        e.usec = std::atof(line.substr(b + 3).c_str());
+        loaded[line.substr(0, a)] = e;
+    }
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    for (auto& kv : loaded) g_table[kv.first] = kv.second;
+    g_table_gen.fetch_add(1);
+    return TTX_OK;
+}
+
+ttx_status ttx_tune_table_clear(void) {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    g_table.clear();
+    g_table_gen.fetch_add(1);
+    return TTX_OK;
+}
+
+int ttx_tune_table_size(void) {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    return int(g_table.size());
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+"""Helpers for the GPU parity tests: run the HIP library through its C ABI on
+device copies of host arrays, and compare results with the oracle's."""
+import numpy as np
+
+import paper_1607_01249_amd as ttx
+
+F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+
+
+def dtype_code(dtype):
+    return ttx.F32 if np.dtype(dtype) == F32 else ttx.F64
+
+
+def to_device(x, pad_elems=0):
+    """Device copy of a host array; with pad_elems > 0 the data starts that
+    many elements into the allocation (for misaligned-pointer cases).
+    Returns (tensor, address of the first element)."""
+    import torch
+    t = torch.empty(len(x) + pad_elems, dtype=torch.float32 if x.dtype == F32 else torch.float64,
+                    device="cuda")
+    t[pad_elems:].copy_(torch.from_numpy(x))
+    return t, t.data_ptr() + pad_elems * x.dtype.itemsize
+
+
+def from_device(t, pad_elems=0):
+    import torch
+    torch.cuda.synchronize()
+    return t[pad_elems:].cpu().numpy()
+
+
+def gpu_transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, pad_a=0, pad_b=0,
+                  plan_config=None):
+    """Runs Eqn. 1 on the GPU through ttx_transpose (or a plan with a forced
+    config) and returns B as a host array."""
+    dA, pa = to_device(A, pad_a)
+    dB, pb = to_device(B, pad_b)
+    stream = ttx.current_stream()
+    if plan_config is None:
+        ttx.ttx_transpose(dtype_code(A.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa,
+                          beta, pb, stream)
+    else:
+        plan = ttx.ttx_plan_create(dtype_code(A.dtype), perm, size, outer_a, outer_b)
+        try:
+            beta0 = A.dtype.type(beta) == 0
+            ttx.ttx_plan_set_config(plan, beta0, plan_config)
+            ttx.ttx_plan_execute(plan, alpha, pa, beta, pb, stream)
+        finally:
+            ttx.ttx_plan_destroy(plan)
+    out = from_device(dB, pad_b)
+    del dA, dB
+    return out
+
+
+def ordered_bits(x):
+    """Maps floats to integers whose order and differences count ulps."""
+    if x.dtype == F32:
+        i = x.view(np.int32).astype(np.int64)
+        return np.where(i < 0, np.int64(-2 ** 31) - i, i)
+    i = x.view(np.int64)
+    return np.where(i < 0, np.int64(-2 ** 63) - i, i)
+
+
+def max_ulp(got, ref):
+    nan_g, nan_r = np.isnan(got), np.isnan(ref)
+    assert np.array_equal(nan_g, nan_r), "NaN positions differ"
+    g = ordered_bits(got[~nan_g])
+    r = ordered_bits(ref[~nan_r])
+    diff = np.nonzero(g != r)[0]
+    if diff.size == 0:
+        return 0
+    # exact integer arithmetic on the (few) differing elements
+    return max(abs(int(g[k]) - int(r[k])) for k in diff)
+
+
+def assert_parity(got, ref, exact, what=""):
+    """exact: every element bit-identical (NaNs compared by class);
+    otherwise at most 1 ulp apart (the same unfused operation order makes
+    bit-identity the expectation; the count of differing elements is
+    reported)."""
+    assert got.shape == ref.shape and got.dtype == ref.dtype
+    nan_g, nan_r = np.isnan(got), np.isnan(ref)
+    assert np.array_equal(nan_g, nan_r), "NaN positions differ %s" % what
+    ib = np.uint32 if got.dtype == F32 else np.uint64
+    differ = int(np.count_nonzero(got[~nan_g].view(ib) != ref[~nan_r].view(ib)))
+    if exact:
+        assert differ == 0, "%d elements differ %s" % (differ, what)
+    else:
+        ulp = max_ulp(got, ref)
+        assert ulp <= 1, "max %s ulp (%d elements differ) %s" % (ulp, differ, what)
+    return differ

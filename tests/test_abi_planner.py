@@ -1,0 +1,324 @@
+"""Host-side checks of the C ABI (no GPU): exported symbols, argument
+validation against the oracle's, the planner's index merging and family
+choice on the paper's examples, merge invariance through the oracle, and
+the candidate ranking of the tuner."""
+import itertools
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1607_01249_amd as ttx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ttx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ttx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert "ttx_transpose" in names and len(names) >= 15
+    L = ttx.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", ttx._ttx.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ttx_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+
+
+def test_binding_wraps_every_declared_symbol():
+    for n in _declared_symbols():
+        if n in ("ttx_status_string", "ttx_last_error", "ttx_version"):
+            continue
+        assert hasattr(ttx._ttx, n), n
+
+
+def test_status_strings():
+    L = ttx.lib()
+    for s in range(9):
+        assert L.ttx_status_string(s)
+    assert b"ttx" in L.ttx_version()
+
+
+# -- validation: the library's synchronous checks agree with the oracle's -------------
+INVALID = [
+    dict(dtype=2, perm=(0, 1), size=(2, 3)),
+    dict(dtype=0, perm=(0, 0), size=(2, 3)),
+    dict(dtype=0, perm=(0, 2), size=(2, 3)),
+    dict(dtype=0, perm=(1, 0), size=(2, -1)),
+    dict(dtype=0, perm=(1, 0), size=(2, 3), outer_a=(1, 3)),
+    dict(dtype=0, perm=(1, 0), size=(2, 3), outer_b=(3, 1)),
+    dict(dtype=1, perm=(2, 1, 0), size=(4, 5, 6), outer_a=(4, 5, 5)),
+    dict(dtype=0, perm=tuple(range(17)), size=(1,) * 17),
+]
+
+
+@pytest.mark.parametrize("case", INVALID)
+def test_plan_validation_matches_oracle(case):
+    expect = oracle.check(case["dtype"], case["perm"], case["size"], case.get("outer_a"),
+                          case.get("outer_b"))
+    assert expect != oracle.OK
+    with pytest.raises(ttx.TTXError) as err:
+        ttx.ttx_plan_create(case["dtype"], case["perm"], case["size"], case.get("outer_a"),
+                            case.get("outer_b"))
+    assert err.value.status == expect
+
+
+def test_transpose_rejects_overlap_and_null_without_gpu():
+    # validation happens before any HIP call, so these work without a GPU
+    base = 1 << 40
+    with pytest.raises(ttx.TTXError) as err:
+        ttx.ttx_transpose(0, 2, (1, 0), (2, 3), None, None, 1.0, base, 0.0, base + 20)
+    assert err.value.status == ttx.EOVERLAP
+    with pytest.raises(ttx.TTXError) as err:
+        ttx.ttx_transpose(0, 2, (1, 0), (2, 3), None, None, 1.0, None, 0.0, base)
+    assert err.value.status == ttx.EINVAL
+    with pytest.raises(ttx.TTXError) as err:   # misaligned for FP64
+        ttx.ttx_transpose(1, 2, (1, 0), (2, 3), None, None, 1.0, base + 4, 0.0, base + 4096)
+    assert err.value.status == ttx.EINVAL
+    # an empty tensor is a no-op even with dangling pointers
+    ttx.ttx_transpose(0, 2, (1, 0), (0, 3), None, None, 1.0, None, 0.0, None)
+
+
+# -- planner on the paper's examples ------------------------------------------------------
+def _describe(dtype, perm, size, outer_a=None, outer_b=None):
+    p = ttx.ttx_plan_create(dtype, perm, size, outer_a, outer_b)
+    try:
+        return ttx.ttx_plan_describe(p)
+    finally:
+        ttx.ttx_plan_destroy(p)
+
+
+def test_sec21_merge_example():
+    g = _golden("sec21_merge_example.json")
+    d = _describe(0, g["perm"], g["size"])
+    assert d["perm"] == g["merged_perm"] and d["size"] == g["merged_size"]
+    assert d["family"] == "moved"
+
+
+def test_fig2_packing_no_merge():
+    g = _golden("fig2_packing.json")
+    d = _describe(0, g["perm"], g["size"], g["outer_a"], g["outer_b"])
+    assert d["perm"] == g["merged_perm"] and d["size"] == g["merged_size"]
+    assert d["family"] == g["family"]
+    assert d["stride_a"] == g["stride_a"]
+    # stride_b is reported per A index: A index m sits at B position perm^-1(m)
+    inv = [g["perm"].index(m) for m in range(3)]
+    assert d["stride_b"] == [g["stride_b"][inv[m]] for m in range(3)]
+
+
+def test_stride1_kept_examples_are_preserved():
+    for case in _golden("stride1_kept_examples.json")["cases"]:
+        d = _describe(1, case["perm"], case["size"])
+        assert d["family"] == case["family"], case
+        assert d["perm"] == case["merged_perm"] and d["size"] == case["merged_size"]
+
+
+def test_ld_blocks_merge_and_contiguous_merges():
+    # outer_b[2] = 50 != 48 keeps i2 and i3 apart; contiguous B merges them
+    d = _describe(1, (1, 0, 2, 3), (384, 96, 48, 32), (400, 100, 48, 32), (100, 400, 50, 32))
+    assert d["n"] == 4 and d["family"] == "moved"
+    d = _describe(1, (1, 0, 2, 3), (384, 96, 48, 32), (400, 100, 48, 32), None)
+    assert d["perm"] == [1, 0, 2] and d["size"] == [384, 96, 48 * 32]
+    d = _describe(1, (1, 0, 2, 3), (384, 96, 48, 32))
+    assert d["perm"] == [1, 0, 2] and d["size"] == [384, 96, 48 * 32]
+
+
+def test_awkward_and_size1():
+    d = _describe(0, (1, 2, 3, 0), (7, 1023, 33, 65))
+    assert d["perm"] == [1, 0] and d["size"] == [7, 1023 * 33 * 65]
+    d = _describe(0, (2, 0, 1, 3), (5, 1, 6, 1))
+    assert d["perm"] == [1, 0] and d["size"] == [5, 6]
+    d = _describe(0, (1, 0), (1, 1))
+    assert d["family"] == "flat" and d["elements"] == 1
+    d = _describe(0, (0, 1, 2), (3, 4, 5))
+    assert d["family"] == "flat" and d["size"] == [60]
+    d = _describe(0, (0, 1), (3, 4), (5, 4))
+    assert d["family"] == "preserved" and d["size"] == [3, 4]
+    d = _describe(0, (1, 0), (3, 0))
+    assert d["family"] == "empty"
+    # a dropped leading index with a leading dimension leaves a strided index 0
+    d = _describe(0, (1, 0, 2), (1, 7, 5), (3, 7, 5))
+    assert d["stride_a"][0] == 3
+
+
+def _canonical_outer(d):
+    """The planner's merged problem as (perm, size, outer_a, outer_b).  A
+    leading extent-1 index carries the strides of merged index 0 when they
+    are not 1 (extent-1 indices with leading dimensions were dropped)."""
+    n, perm, size, sa, sb = d["n"], d["perm"], d["size"], d["stride_a"], d["stride_b"]
+    outer_a = [sa[0]] + [sa[m + 1] // sa[m] for m in range(n - 1)] + [size[-1]]
+    outer_b = [sb[perm[0]]] + [sb[perm[k + 1]] // sb[perm[k]] for k in range(n - 1)] + [size[perm[-1]]]
+    return [0] + [p + 1 for p in perm], [1] + list(size), outer_a, outer_b
+
+
+def test_merge_invariance_through_oracle():
+    """The oracle on the original problem equals the oracle on the planner's
+    merged, size-1-free problem, on the same buffers (A and B unchanged)."""
+    rng = np.random.default_rng(5)
+    cases = [((1, 2, 0), (3, 4, 5), None, None),
+             ((0, 5, 1, 4, 2, 3), (3, 2, 4, 2, 3, 2), None, None),
+             ((1, 2, 3, 0), (7, 3, 2, 5), None, None),
+             ((2, 3, 0, 1), (2, 3, 4, 5), None, None),
+             ((1, 0, 2, 3), (5, 4, 3, 2), (6, 4, 3, 2), (4, 7, 3, 2)),
+             ((2, 0, 1, 3), (3, 1, 4, 1), (3, 1, 4, 1), None),
+             ((0, 1, 2), (3, 4, 5), (3, 6, 5), None)]
+    for perm, size, oa, ob in cases:
+        d = _describe(1, perm, size, oa, ob)
+        cperm, csize, coa, cob = _canonical_outer(d)
+        size_b = [size[p] for p in perm]
+        na = int(np.prod(oa or size))
+        nb = int(np.prod(ob or size_b))
+        A = rng.random(na)
+        B0 = rng.random(nb)
+        B1, B2 = B0.copy(), B0.copy()
+        assert oracle.transpose(perm, size, 1.25, A, -0.5, B1, oa, ob) == 0
+        assert oracle.transpose(cperm, csize, 1.25, A, -0.5, B2, coa, cob) == 0
+        assert np.array_equal(B1, B2), (perm, size, d)
+
+
+def test_merge_random_against_oracle():
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        n = int(rng.integers(1, 7))
+        perm = tuple(int(p) for p in rng.permutation(n))
+        size = tuple(int(rng.choice([1, 2, 3, 4])) for _ in range(n))
+        size_b = [size[p] for p in perm]
+        oa = tuple(s + int(rng.integers(0, 2)) for s in size) if rng.random() < 0.5 else None
+        ob = tuple(s + int(rng.integers(0, 2)) for s in size_b) if rng.random() < 0.5 else None
+        d = _describe(0, perm, size, oa, ob)
+        cperm, csize, coa, cob = _canonical_outer(d)
+        A = rng.random(int(np.prod(oa or size)), dtype=np.float32)
+        B0 = rng.random(int(np.prod(ob or size_b)), dtype=np.float32)
+        B1, B2 = B0.copy(), B0.copy()
+        oracle.transpose(perm, size, 2.0, A, 0.0, B1, oa, ob)
+        oracle.transpose(cperm, csize, 2.0, A, 0.0, B2, coa, cob)
+        assert np.array_equal(B1, B2), (perm, size, oa, ob, d)
+        # families follow the merged permutation
+        fam = "flat" if d["n"] == 1 else ("preserved" if d["perm"][0] == 0 else "moved")
+        assert d["family"] == fam
+
+
+# -- candidate ranking (Sec. 2.1 stages 2-3, Sec. 2.3) ------------------------------------
+def test_candidate_list_is_bounded_and_sorted():
+    cands, cost = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), cap=4096)
+    assert len(cands) == 200  # default capacity
+    assert cost == sorted(cost)
+    few, few_cost = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=10)
+    assert len(few) == 10 and few_cost == cost[:10]
+    allc, _ = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=-1, cap=100000)
+    # every menu shape x 4! loop orders x 4 flag sets
+    assert len(allc) == 20 * 24 * 4
+    for c in cands:
+        assert sorted(c.order[:c.n_order]) == [0, 1, 2, 3]
+
+
+def test_blocking_heuristic_prefers_exact_tiles_and_skinny_for_short_index():
+    c, _ = ttx.ttx_tune_candidates(0, (1, 0), (7, 100000), max_candidates=1)
+    assert c[0].tile_a in (4, 8)     # the skinny shapes for a 7-long stride-1 index
+    # the remainder rule: the chosen shape leaves at most 20% of its lanes idle
+    c, _ = ttx.ttx_tune_candidates(0, (1, 0), (96, 80), max_candidates=1)
+    ta, tb = c[0].tile_a, c[0].tile_b
+    util = (96 / (-(-96 // ta) * ta)) * (80 / (-(-80 // tb) * tb))
+    assert util >= 0.8, (ta, tb)
+    c, _ = ttx.ttx_tune_candidates(0, (1, 0), (4096, 4096), max_candidates=1)
+    assert (c[0].tile_a, c[0].tile_b) == (64, 64)
+
+
+def test_loop_heuristic_prefers_small_strides_fastest():
+    # (2,1,0) on (1024, 64, 1024): the middle index has stride 1024 in both
+    # tensors while a step of either tile index jumps 64*65536 elements in
+    # one of them
+    c, cost = ttx.ttx_tune_candidates(0, (2, 1, 0), (1024, 64, 1024), max_candidates=-1, cap=100000)
+    # orders that enumerate the middle index among the resident tiles tie; the
+    # ones that leave it last (after both tile indices) cost more
+    orders = {tuple(x.order[:3]): cc for x, cc in zip(c, cost)
+              if (x.tile_a, x.tile_b, x.flags) == (c[0].tile_a, c[0].tile_b, 0)}
+    assert orders[(1, 0, 2)] < orders[(0, 2, 1)]
+
+
+def test_plan_set_config_validation():
+    p = ttx.ttx_plan_create(0, (2, 1, 0), (96, 128, 80))
+    try:
+        d = ttx.ttx_plan_describe(p)
+        cfg = d["config_raw"][1]
+        ttx.ttx_plan_set_config(p, 1, cfg)
+        bad = ttx.Config.from_buffer_copy(cfg)
+        bad.tile_a = 17
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, bad)
+        bad = ttx.Config.from_buffer_copy(cfg)
+        bad.order[0] = bad.order[1]
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, bad)
+        bad = ttx.Config.from_buffer_copy(cfg)
+        bad.family = ttx.FAMILY_PRESERVED
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, bad)
+    finally:
+        ttx.ttx_plan_destroy(p)
+
+
+def test_tune_table_roundtrip(tmp_path):
+    ttx.ttx_tune_table_clear()
+    path = str(tmp_path / "table.txt")
+    with open(path, "w") as f:
+        f.write("# comment\n")
+        f.write("d0:b1:n3:s96,128,80:p2,1,0:a1,96,12288:o10240,80,1 | 3 32 16 256 1 3 0 2 1 | 12.5\n")
+    ttx.ttx_tune_table_load(path)
+    assert ttx.ttx_tune_table_size() == 1
+    d = _describe(0, (2, 1, 0), (96, 128, 80))
+    assert d["config_from_table"] == [0, 1]
+    assert d["config"][1]["tile_a"] == 32 and d["config"][1]["order"] == [0, 2, 1]
+    out = str(tmp_path / "saved.txt")
+    ttx.ttx_tune_table_save(out)
+    assert "s96,128,80" in open(out).read()
+    ttx.ttx_tune_table_clear()
+    d = _describe(0, (2, 1, 0), (96, 128, 80))
+    assert d["config_from_table"] == [0, 0]
+
+
+def test_fastdiv_host_exhaustive_sample(tmp_path):
+    src = tmp_path / "fd.cpp"
+    src.write_text(r'''
+#include "ttx_internal.h"
+#include <cstdio>
+#include <random>
+int main() {
+    std::mt19937_64 rng(7);
+    const uint32_t ds[] = {1, 2, 3, 5, 7, 10, 24, 48, 641, 65535, 65536, 1u << 31, 0xffffffffu};
+    for (uint32_t d : ds) {
+        ttx::FastDiv f(d);
+        for (int i = 0; i < 200000; ++i) {
+            uint32_t n = i < 1000 ? uint32_t(i) : (i < 2000 ? 0xffffffffu - uint32_t(i) : uint32_t(rng()));
+            if (f.div(n) != n / d) { std::printf("bad %u %u\n", n, d); return 1; }
+        }
+    }
+    for (int i = 0; i < 200000; ++i) {
+        uint32_t d = uint32_t(rng()) % 100000 + 1, n = uint32_t(rng());
+        ttx::FastDiv f(d);
+        if (f.div(n) != n / d) { std::printf("bad %u %u\n", n, d); return 1; }
+    }
+    return 0;
+}
+''')
+    exe = tmp_path / "fd"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-I" + os.path.join(ROOT, "paper_1607_01249_amd", "csrc"), str(src), "-o", str(exe)],
+                   check=True)
+    subprocess.run([str(exe)], check=True)

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bit-exact for alpha = 1, beta = 0; at most 1 ulp otherwise (both sides
+evaluate fl(fl(alpha*a) + fl(beta*b)) with no fused multiply-add, so
+bit-identity is the expectation there too and the number of differing
+elements is reported).
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1607_01249_amd as ttx
+import workloads
+from gpu_util import F32, F64, assert_parity, gpu_transpose
+
+pytestmark = pytest.mark.gpu
+
+
+def _elems(d):
+    return workloads.elements(d)
+
+
+def _case(perm, size, dtype, alpha, beta, outer_a=None, outer_b=None, seed=0, pad_a=0, pad_b=0,
+          plan_config=None, B_fill=None):
+    size_b = [size[p] for p in perm]
+    A = workloads.uniform(_elems(outer_a or size), dtype, seed=1000 + seed)
+    if B_fill is None:
+        B = workloads.uniform(_elems(outer_b or size_b), dtype, seed=2000 + seed)
+    else:
+        B = np.full(_elems(outer_b or size_b), B_fill, dtype=dtype)
+    ref = B.copy()
+    assert oracle.transpose(perm, size, alpha, A, beta, ref, outer_a, outer_b) == 0
+    got = gpu_transpose(perm, size, alpha, A, beta, B, outer_a, outer_b, pad_a, pad_b, plan_config)
+    exact = alpha == 1.0 and beta == 0.0
+    return got, ref, exact
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# -- configuration 1: the plain correctness case ----------------------------------------
+def test_plain_3d_f32_bit_exact():
+    c = workloads.PLAIN
+    n = _elems(c["size"])
+    A = workloads.uniform(n, c["dtype"], c["seed_a"])
+    B = np.zeros(n, dtype=c["dtype"])
+    ref = B.copy()
+    assert oracle.transpose(c["perm"], c["size"], 1.0, A, 0.0, ref) == 0
+    got = gpu_transpose(c["perm"], c["size"], 1.0, A, 0.0, B)
+    assert_parity(got, ref, exact=True)
+
+
+# -- paper-shaped permutations at reduced sizes (several tiles, ragged edges) -----------
+REDUCED = {"4d": (37, 70, 19, 23), "5d": (13, 17, 11, 9, 7), "6d": (5, 7, 6, 4, 3, 5)}
+REDUCED_CASES = [(rank, perm, dt, beta) for rank in ("4d", "5d", "6d")
+                 for perm in workloads.LARGE_PERMS[rank] for dt in (F32, F64) for beta in (0.7, 0.0)]
+
+
+@pytest.mark.parametrize("rank,perm,dtype,beta", REDUCED_CASES)
+def test_reduced_large_perms(rank, perm, dtype, beta):
+    got, ref, exact = _case(perm, REDUCED[rank], dtype, 1.3, beta, seed=3)
+    assert_parity(got, ref, exact, (rank, perm, dtype, beta))
+
+
+@pytest.mark.parametrize("rank,perm,dtype", [(r, p, d) for r in ("4d", "5d", "6d")
+                                             for p in workloads.LARGE_PERMS[r] for d in (F32, F64)])
+def test_reduced_large_perms_plain_copy_exact(rank, perm, dtype):
+    got, ref, exact = _case(perm, REDUCED[rank], dtype, 1.0, 0.0, seed=4)
+    assert exact
+    assert_parity(got, ref, True)
+
+
+# -- paper-shaped permutations at full size (about 200 MiB per tensor) -------------------
+@pytest.mark.parametrize("case", workloads.large_cases(), ids=lambda c: c["name"])
+def test_full_size_large_perms(case):
+    _say("full-size case %s" % case["name"])
+    perm, size, dtype = case["perm"], case["size"], case["dtype"]
+    n = _elems(size)
+    A = workloads.uniform(n, dtype, case["seed_a"])
+    B = workloads.uniform(n, dtype, case["seed_b"])
+    ref = B.copy()
+    assert oracle.transpose(perm, size, case["alpha"], A, case["beta"], ref) == 0
+    got = gpu_transpose(perm, size, case["alpha"], A, case["beta"], B)
+    assert_parity(got, ref, exact=False, what=case["name"])
+
+
+@pytest.mark.parametrize("dtype,perm", [(F32, (3, 2, 1, 0)), (F32, (2, 0, 3, 1)),
+                                        (F64, (1, 0, 3, 2)), (F64, (0, 2, 1, 3))])
+def test_literal_160_4d_sampled(dtype, perm):
+    """(160,160,160,160): 2.4 GiB (FP32) / 4.9 GiB (FP64) per tensor, checked on
+    200K sampled elements computed one by one by the oracle."""
+    import torch
+    size = workloads.LITERAL_4D
+    _say("literal 160^4 %s %s" % (dtype, perm))
+    n = _elems(size)
+    A = workloads.uniform(n, dtype, 77)
+    B = workloads.uniform(n, dtype, 78)
+    idx = np.random.default_rng(79).integers(0, n, size=200000)
+    idx = np.concatenate([idx, [0, n - 1]])
+    expect, off = oracle.sample(perm, size, 1.3, A, 0.7, B, idx)
+    got = gpu_transpose(perm, size, 1.3, A, 0.7, B)
+    del A, B
+    assert_parity(got[off], expect, exact=False)
+    torch.cuda.empty_cache()
+
+
+# -- multiple leading dimensions (BLAS-3 packing) and awkward extents --------------------
+@pytest.mark.parametrize("case", workloads.LD_CASES, ids=lambda c: c["name"])
+@pytest.mark.parametrize("alpha,beta", workloads.LD_SCALARS)
+def test_leading_dimension_cases(case, alpha, beta):
+    _say("ld case %s %s %s" % (case["name"], alpha, beta))
+    got, ref, exact = _case(case["perm"], case["size"], case["dtype"], alpha, beta,
+                            case["outer_a"], case["outer_b"], seed=5)
+    # the whole outer B buffer is compared: elements outside the sub-tensor
+    # must keep their (random) initial values
+    assert_parity(got, ref, exact, case["name"])
+
+
+def test_fig2_packing_into_contiguous_b():
+    got, ref, exact = _case((2, 1, 0), (8, 16, 16), F32, 1.0, 0.0, outer_a=(32, 32, 32), seed=6)
+    assert_parity(got, ref, True)
+
+
+# -- degenerate and edge cases ------------------------------------------------------------
+EDGE = [
+    ((0,), (1,), None, None),
+    ((0,), (1000,), None, None),
+    ((0,), (37,), (50,), None),
+    ((1, 0), (1, 1), None, None),
+    ((0, 1, 2), (3, 4, 5), None, None),                     # identity: flat
+    ((0, 1, 2), (3, 4, 5), (4, 4, 5), (3, 6, 5)),           # identity with gaps: preserved
+    ((1, 0), (7, 1), None, None),
+    ((2, 0, 1, 3), (5, 1, 6, 1), None, None),
+    ((1, 0, 2), (1, 7, 5), (3, 7, 5), (7, 2, 5)),           # dropped leading index with ld
+    ((1, 0), (1, 1000), None, None),
+    ((1, 0), (3, 1000), None, None),
+    ((1, 0), (1000, 3), None, None),
+    ((1, 0), (65, 63), None, None),
+    ((1, 0), (4096, 5), None, None),
+    ((2, 1, 0), (129, 3, 130), None, None),
+    ((0, 2, 1), (2, 300, 301), None, None),
+    ((0, 2, 1), (1000, 3, 4), None, None),
+    (tuple(reversed(range(16))), (2, 3, 1, 2, 2, 1, 3, 2, 1, 2, 2, 1, 2, 3, 1, 2), None, None),
+    (tuple(range(1, 16)) + (0,), (3,) + (2,) * 15, None, None),
+]
+
+
+@pytest.mark.parametrize("perm,size,oa,ob", EDGE)
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (-0.5, 1.0)])
+def test_edge_shapes(perm, size, oa, ob, dtype, alpha, beta):
+    got, ref, exact = _case(perm, size, dtype, alpha, beta, oa, ob, seed=7)
+    assert_parity(got, ref, exact, (perm, size))
+
+
+@pytest.mark.parametrize("pad_a,pad_b", [(1, 0), (0, 1), (1, 3)])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_misaligned_pointers_take_scalar_paths(pad_a, pad_b, dtype):
+    for perm, size in [((2, 1, 0), (64, 9, 48)), ((0, 2, 1), (64, 9, 48)), ((0, 1), (64, 9))]:
+        got, ref, exact = _case(perm, size, dtype, 1.25, 0.5, seed=8, pad_a=pad_a, pad_b=pad_b)
+        assert_parity(got, ref, exact, (perm, size, pad_a, pad_b))
+
+
+def test_empty_is_noop():
+    B = np.arange(10, dtype=np.float32)
+    got = gpu_transpose((1, 0), (0, 10), 1.0, np.zeros(1, dtype=np.float32), 0.0, B)
+    assert np.array_equal(got, np.arange(10, dtype=np.float32))
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_beta_zero_does_not_read_b(dtype):
+    for perm, size in [((2, 1, 0), (33, 5, 70)), ((0, 2, 1), (40, 5, 7)), ((0,), (999,))]:
+        got, ref, _ = _case(perm, size, dtype, 2.0, 0.0, seed=9, B_fill=np.nan)
+        assert not np.isnan(got).any()
+        assert_parity(got, ref, exact=False)
+        got, ref, _ = _case(perm, size, dtype, 2.0, -0.0, seed=9, B_fill=np.inf)
+        assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("dtype,p", [(F32, 12), (F64, 27)])
+def test_contraction_detector(dtype, p):
+    """alpha = a = 1 + 2^-p, beta = -1, b = 1 + 2^-(p-1): the unfused result is 0
+    exactly; a fused multiply-add would leave 2^-2p."""
+    alpha = 1.0 + 2.0 ** -p
+    for perm, size in [((1, 0), (64, 64)), ((0, 2, 1), (64, 4, 4)), ((0,), (4096,))]:
+        n = _elems(size)
+        A = np.full(n, alpha, dtype=dtype)
+        B = np.full(n, 1.0 + 2.0 ** -(p - 1), dtype=dtype)
+        got = gpu_transpose(perm, size, alpha, A, -1.0, B)
+        assert (got == 0).all(), (perm, np.unique(got))
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_special_values_pass_through(dtype):
+    fi = np.finfo(dtype)
+    vals = np.array([0.0, -0.0, np.inf, -np.inf, fi.max, -fi.max, fi.tiny, fi.smallest_subnormal,
+                     -fi.smallest_subnormal, 1.0, -1.0, np.nan, 3 * fi.smallest_subnormal],
+                    dtype=dtype)
+    A = np.resize(vals, 64 * 48).astype(dtype)
+    for perm, size in [((1, 0), (64, 48)), ((0, 1), (64, 48)), ((0, 2, 1), (16, 4, 48))]:
+        B = np.zeros_like(A)
+        ref = B.copy()
+        oracle.transpose(perm, size, 1.0, A, 0.0, ref)
+        got = gpu_transpose(perm, size, 1.0, A, 0.0, B)
+        assert_parity(got, ref, True)   # includes subnormals and signed zeros
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_round_trip_on_gpu(dtype):
+    perm, size = (2, 0, 3, 1), (37, 70, 19, 23)
+    inv = [0] * 4
+    for k, p in enumerate(perm):
+        inv[p] = k
+    A = workloads.uniform(_elems(size), dtype, 10)
+    T = gpu_transpose(perm, size, 1.0, A, 0.0, np.zeros_like(A))
+    back = gpu_transpose(inv, [size[p] for p in perm], 1.0, T, 0.0, np.zeros_like(A))
+    assert_parity(back, A, True)
+
+
+def test_split_b_in_b_out():
+    import torch
+    perm, size = (1, 2, 0), (40, 30, 20)
+    n = _elems(size)
+    A = workloads.uniform(n, F64, 11)
+    Bin = workloads.uniform(n, F64, 12)
+    ref = Bin.copy()
+    oracle.transpose(perm, size, 0.75, A, -1.25, ref)
+    dA = torch.from_numpy(A).cuda()
+    dBin = torch.from_numpy(Bin).cuda()
+    dBout = torch.zeros(n, dtype=torch.float64, device="cuda")
+    plan = ttx.ttx_plan_create(ttx.F64, perm, size)
+    try:
+        ttx.ttx_plan_execute_split(plan, 0.75, dA.data_ptr(), -1.25, dBin.data_ptr(),
+                                   dBout.data_ptr(), ttx.current_stream())
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    torch.cuda.synchronize()
+    assert_parity(dBout.cpu().numpy(), ref, False)
+    assert np.array_equal(dBin.cpu().numpy(), Bin)
+
+
+# -- every tuner candidate computes the same bits ----------------------------------------
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("perm,size", [((2, 0, 3, 1), (37, 70, 19, 23)), ((0, 2, 1, 3), (40, 9, 11, 13)),
+                                       ((1, 0), (7, 3000)), ((1, 0), (300, 5))])
+def test_every_candidate_bit_identical(perm, size, dtype):
+    cands, _ = ttx.ttx_tune_candidates(ttx.F32 if dtype == F32 else ttx.F64, perm, size,
+                                       max_candidates=-1, cap=200000)
+    rng = np.random.default_rng(13)
+    pick = list(range(min(40, len(cands))))
+    pick += list(rng.choice(len(cands), size=min(60, len(cands)), replace=False))
+    shapes_seen = set()
+    for i in sorted(set(int(k) for k in pick)):
+        shapes_seen.add((cands[i].tile_a, cands[i].tile_b))
+    # make sure every tile shape of the menu appears at least once
+    for c in cands:
+        if (c.tile_a, c.tile_b) not in shapes_seen:
+            shapes_seen.add((c.tile_a, c.tile_b))
+            pick.append(cands.index(c))
+    n = _elems(size)
+    A = workloads.uniform(n, dtype, 14)
+    B = workloads.uniform(n, dtype, 15)
+    for beta in (0.7, 0.0):
+        ref = B.copy()
+        oracle.transpose(perm, size, 1.3, A, beta, ref)
+        for i in sorted(set(int(k) for k in pick)):
+            got = gpu_transpose(perm, size, 1.3, A, beta, B, plan_config=cands[i])
+            assert_parity(got, ref, exact=True, what=str(cands[i].as_dict()))

@@ -379,3 +379,20 @@ def test_pins_catch_planted_mistakes():
             assert caught, "no pin catches the planted mistake %r" % name
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_sampled_oracle_matches_full_oracle():
+    """The one-element-at-a-time entry point agrees with the full nested loop."""
+    rng = np.random.default_rng(19)
+    for perm, size, oa, ob in [((2, 0, 3, 1), (5, 6, 7, 3), None, None),
+                               ((1, 0, 2, 3), (6, 5, 4, 3), (8, 5, 4, 3), (7, 9, 5, 3)),
+                               ((0, 2, 1), (4, 3, 5), None, (6, 5, 3))]:
+        size_b = [size[p] for p in perm]
+        for dtype, (alpha, beta) in itertools.product((F32, F64), ((1.3, 0.7), (1.0, 0.0))):
+            A = _rand(_elems(oa or size), dtype, rng)
+            B0 = _rand(_elems(ob or size_b), dtype, rng)
+            full = B0.copy()
+            _run(oracle.lib(), perm, size, alpha, A, beta, full, oa, ob)
+            idx = rng.integers(0, _elems(size), size=50)
+            vals, off = oracle.sample(perm, size, alpha, A, beta, B0, idx, oa, ob)
+            assert _same_bits(vals, full[off])
