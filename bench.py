@@ -1,0 +1,435 @@
+#!/usr/bin/env python3
+"""Benchmark of the ttx hot path on one MI355X.
+
+Workload (one "step"): the 36 paper-shaped transpositions of about 200 MiB
+per tensor -- 4D, 5D and 6D, FP32 and FP64, beta = 0.7 and beta = 0 with
+alpha = 1.3 -- each through the per-call entry point ``ttx_transpose`` on
+its own device buffers (14 GiB in all, so no tensor is still cached in the
+256 MiB Infinity Cache when its turn comes).  The reported value is the
+whole step's algorithmic traffic (2S bytes for beta = 0, 3S otherwise, S the
+bytes of the transposed tensor; Sec. 3, Eqn. 2) divided by its wall time.
+
+Also reported: every case's bandwidth as a fraction of a measured
+hipMemcpy device-to-device ceiling, the dominant kernel against the HBM
+roofline (8 TB/s), and the CPU oracle timed on the host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E, published
+TABLE = os.path.join(ROOT, "paper_1607_01249_amd", "tune", "gfx950.txt")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCES = ["tile_kernels.h", "menu.h", "registry.h", "kernels_moved_f32_beta.hip",
+                  "kernels_moved_f32_beta0.hip", "kernels_moved_f64_beta.hip",
+                  "kernels_moved_f64_beta0.hip", "kernels_preserved.hip", "dispatch.hip"]
+METRIC = "achieved HBM GB/s (% of D2D-copy peak) per perm; batched p50/p99 latency vs per-call"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1607_01249_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tune-candidates", type=int, default=100,
+                    help="candidates timed per shape missing from the tune table")
+    ap.add_argument("--retune", action="store_true", help="ignore the shipped tune table")
+    ap.add_argument("--save-table", default=None, help="write the tune table here")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--literal", action="store_true",
+                    help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for rocprofv3: no tuning, 1 warm-up, 2 steps, no CPU leg")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "script into profiles/traffic_counters.json and exit")
+    ap.add_argument("--summarize-trace", metavar="DB",
+                    help="print the kernel statistics of a rocprofv3 --kernel-trace --stats run")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------------------
+def make_cases(literal):
+    import workloads
+    cases = workloads.large_cases()
+    if literal:
+        for dtype in (workloads.F32, workloads.F64):
+            for perm in [(3, 2, 1, 0), (2, 0, 3, 1)]:
+                cases.append(dict(name="literal160_%s_p%s_b0.7" % ("f32" if dtype == workloads.F32 else "f64",
+                                                                    "".join(map(str, perm))),
+                                  dtype=dtype, size=workloads.LITERAL_4D, perm=perm, alpha=1.3,
+                                  beta=0.7, seed_a=3000, seed_b=3001))
+    for c in cases:
+        c["elements"] = workloads.elements(c["size"])
+        S = c["elements"] * c["dtype"].itemsize
+        c["bytes"] = (2 if c["beta"] == 0 else 3) * S
+    return cases
+
+
+def fill_uniform(torch, t, seed):
+    """Seeded uniform [-1, 1) values generated on the device."""
+    g = torch.Generator(device=t.device)
+    g.manual_seed(int(seed))
+    t.uniform_(-1.0, 1.0, generator=g)
+
+
+def time_events(torch, fn, reps, flush=None):
+    """Minimum and median of `reps` runs of fn() bracketed by events (flush before each)."""
+    times = []
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    return min(times), float(np.median(times))
+
+
+def hip_runtime():
+    """The HIP runtime torch loaded (so that streams are shared)."""
+    import ctypes
+    maps = open("/proc/self/maps").read().splitlines()
+    paths = sorted({l.split()[-1] for l in maps if "libamdhip64" in l})
+    L = ctypes.CDLL(paths[0] if paths else "libamdhip64.so")
+    L.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                 ctypes.c_void_p]
+    L.hipMemcpyAsync.restype = ctypes.c_int
+    return L
+
+
+def measure_ceilings(torch, ttx):
+    """hipMemcpy D2D (the metric's denominator), a 16-byte copy kernel and an
+    unfused axpby (the SAXPY peak of Sec. 3) on 1 GiB buffers.  Four buffer
+    pairs are used in rotation, so that each run streams data the previous
+    runs have pushed out of the 256 MiB Infinity Cache (no flush kernel runs
+    in between whose dirty lines would be written back during the run)."""
+    nbytes = 1 << 30
+    pairs = []
+    for i in range(4):
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        fill_uniform(torch, src, 1 + i)
+        fill_uniform(torch, dst, 11 + i)
+        pairs.append((src, dst))
+    torch.cuda.synchronize()
+    hip = hip_runtime()
+    stream = torch.cuda.current_stream().cuda_stream
+    state = {"i": 0}
+
+    def nxt():
+        state["i"] = (state["i"] + 1) % len(pairs)
+        return pairs[state["i"]]
+
+    def d2d():
+        src, dst = nxt()
+        rc = hip.hipMemcpyAsync(dst.data_ptr(), src.data_ptr(), nbytes, 3, stream)
+        assert rc == 0, rc
+
+    def copyk():
+        src, dst = nxt()
+        ttx.ttx_copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+
+    def axpby():
+        src, dst = nxt()
+        ttx.ttx_axpby_kernel(ttx.F32, nbytes // 4, 1.3, src.data_ptr(), 0.7, dst.data_ptr(), stream)
+
+    out = {}
+    for name, fn, moved in [("hipMemcpy_d2d", d2d, 2 * nbytes), ("copy_kernel", copyk, 2 * nbytes),
+                            ("axpby_f32", axpby, 3 * nbytes)]:
+        for _ in range(4):
+            fn()
+        tmin, tmed = time_events(torch, fn, 12)
+        out[name] = dict(GBps=round(moved / tmin / 1e9, 1), GBps_median=round(moved / tmed / 1e9, 1),
+                         bytes=moved)
+    del pairs
+    return out
+
+
+def cpu_baseline(cases, budget_s):
+    """The oracle (plain C loop nest, OpenMP over the outermost B index) on the
+    host cores, timed on a bounded sample of the step's cases."""
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    os.environ.setdefault("OMP_PLACES", "cores")
+    import oracle
+    import workloads
+    # every third case, so that each rank, dtype and both betas appear
+    pick = cases[::3]
+    total_bytes, total_t, runs, names = 0, 0.0, 0, []
+    t_start = time.time()
+    for c in pick:
+        if time.time() - t_start > budget_s and names:
+            break
+        A = workloads.uniform(c["elements"], c["dtype"], c["seed_a"])
+        B = workloads.uniform(c["elements"], c["dtype"], c["seed_b"])
+        best = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            st = oracle.transpose(c["perm"], c["size"], c["alpha"], A, c["beta"], B)
+            dt = time.perf_counter() - t0
+            assert st == 0
+            best = dt if best is None else min(best, dt)
+            runs += 1
+            if time.time() - t_start > budget_s:
+                break
+        total_bytes += c["bytes"]
+        total_t += best
+        names.append(c["name"])
+        del A, B
+    return dict(value=round(total_bytes / total_t / 1e9, 3), unit="GB/s", cores=oracle.threads(),
+                kind="oracle",
+                sample="%d of the step's cases (%s), min of up to 3 runs each, %d runs in %.1f s" %
+                       (len(names), ", ".join(names), runs, time.time() - t_start))
+
+
+def _rocpd(path):
+    import sqlite3
+    files = [path] if path.endswith(".db") else glob.glob(os.path.join(path, "**", "*.db"), recursive=True)
+    assert files, "no rocpd database under %s" % path
+    return [sqlite3.connect(f) for f in files]
+
+
+def _short_kernel(name):
+    """'void ttx::k_moved<float, false, 64, 64, 4, 4>(ttx::TileArgs<float>)' -> 'k_moved<...>'."""
+    name = name.replace("void ", "").replace("ttx::", "")
+    depth, out = 0, ""
+    for ch in name:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out += ch
+    return out
+
+
+def traffic_from(fetch_path, write_path):
+    """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of every ttx kernel from two
+    rocprofv3 --pmc runs of bench.py, each scaled by what the same counter
+    reads for the 1 GiB copy kernel (1 GiB read, 1 GiB written)."""
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
+        per = {}
+        for db in _rocpd(path):
+            for name, cname, val in db.execute("select name, counter_name, counter_value from pmc_events"):
+                if cname == counter:
+                    per.setdefault(_short_kernel(name), []).append(float(val))
+        copy = per.get("k_copy16")
+        assert copy, "copy kernel missing from the %s run" % counter
+        scale = (1 << 30) / (float(np.median(copy)) * 1024.0)
+        res[counter] = dict(scale=scale, copy_kib=float(np.median(copy)),
+                            kernels={k: dict(kib=float(np.mean(v)), dispatches=len(v))
+                                     for k, v in per.items() if k.startswith("k_")})
+    table = {}
+    for k, f in res["FETCH_SIZE"]["kernels"].items():
+        w = res["WRITE_SIZE"]["kernels"].get(k)
+        if w is None:
+            continue
+        fb = f["kib"] * 1024 * res["FETCH_SIZE"]["scale"]
+        wb = w["kib"] * 1024 * res["WRITE_SIZE"]["scale"]
+        table[k] = dict(fetch_bytes=round(fb), write_bytes=round(wb), traffic_bytes=round(fb + wb),
+                        dispatches=f["dispatches"])
+    out = dict(source_hash=kernel_source_hash(),
+               scale=dict(FETCH_SIZE=res["FETCH_SIZE"]["scale"], WRITE_SIZE=res["WRITE_SIZE"]["scale"]),
+               copy_kernel_kib=dict(FETCH_SIZE=res["FETCH_SIZE"]["copy_kib"],
+                                    WRITE_SIZE=res["WRITE_SIZE"]["copy_kib"]),
+               kernels=table)
+    with open(TRAFFIC, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, sort_keys=True))
+
+
+def summarize_trace(path, top=25):
+    """Markdown table of the kernel statistics in a rocprofv3 --kernel-trace --stats database."""
+    rows = {}
+    for db in _rocpd(path):
+        for name, calls, total, avg in db.execute(
+                "select name, total_calls, total_duration, average from top_kernels"):
+            k = _short_kernel(name) if "ttx::" in name else name[:60]
+            r = rows.setdefault(k, [0, 0.0])
+            r[0] += calls
+            r[1] += total
+    total_all = sum(r[1] for r in rows.values())
+    lines = ["| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for k, (calls, total) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append("| %s | %d | %.1f | %.2f | %.1f |" % (k, calls, total, total / calls,
+                                                          100 * total / total_all))
+    print("\n".join(lines))
+
+
+# ---------------------------------------------------------------------------------------
+def main():
+    args = parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return 0
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return 0
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+    if args.profile_run:
+        args.steps, args.warmup, args.no_cpu_baseline = 2, 1, True
+
+    import torch
+    import paper_1607_01249_amd as ttx
+
+    ttx.lib()   # raises when the HIP library is not built
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    cases = make_cases(args.literal)
+    log("allocating %d cases (%.1f GiB)" % (len(cases), sum(2 * c["elements"] * c["dtype"].itemsize for c in cases) / 2 ** 30))
+    for i, c in enumerate(cases):
+        tdt = torch.float32 if c["dtype"].itemsize == 4 else torch.float64
+        c["A"] = torch.empty(c["elements"], dtype=tdt, device="cuda")
+        c["B"] = torch.empty(c["elements"], dtype=tdt, device="cuda")
+        fill_uniform(torch, c["A"], c["seed_a"])
+        fill_uniform(torch, c["B"], c["seed_b"])
+        c["code"] = ttx.F32 if tdt == torch.float32 else ttx.F64
+    torch.cuda.synchronize()
+
+    # Solution lookup before search (Sec. 2.1): shipped table first, tune the rest.
+    if os.path.exists(TABLE) and not args.retune:
+        ttx.ttx_tune_table_load(TABLE)
+    tune_t0 = time.time()
+    tuned = 0
+    for c in cases:
+        plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
+        info = ttx.ttx_plan_describe(plan)
+        ttx.ttx_plan_destroy(plan)
+        z = 1 if c["beta"] == 0 else 0
+        if not info["config_from_table"][z]:
+            if args.profile_run:
+                raise SystemExit("--profile-run needs every case in the tune table (%s)" % c["name"])
+            log("tuning %s" % c["name"])
+            ttx.ttx_tune(c["code"], c["perm"], c["size"], beta_is_zero=bool(z),
+                         max_candidates=args.tune_candidates, reps=3)
+            tuned += 1
+    tune_s = time.time() - tune_t0
+    if args.save_table:
+        ttx.ttx_tune_table_save(args.save_table)
+    for c in cases:
+        plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
+        c["kernel"] = ttx.ttx_plan_kernel_name(plan, c["beta"], c["A"].data_ptr(), c["B"].data_ptr())
+        c["config"] = ttx.ttx_plan_describe(plan)["config"][1 if c["beta"] == 0 else 0]
+        ttx.ttx_plan_destroy(plan)
+
+    log("measuring ceilings")
+    ceil = measure_ceilings(torch, ttx)
+    d2d = ceil["hipMemcpy_d2d"]["GBps"]
+
+    def step(events=None):
+        for i, c in enumerate(cases):
+            if events is not None:
+                events[i].record()
+            ttx.ttx_transpose(c["code"], len(c["perm"]), c["perm"], c["size"], None, None,
+                              c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
+        if events is not None:
+            events[len(cases)].record()
+
+    log("warm-up")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(cases) + 1)]
+              for _ in range(args.steps)]
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    step_bytes = sum(c["bytes"] for c in cases)
+    value = step_bytes * args.steps / wall / 1e9
+    per_case, by_kernel = [], {}
+    for i, c in enumerate(cases):
+        durs = [events[k][i].elapsed_time(events[k][i + 1]) * 1e-3 for k in range(args.steps)]
+        med = float(np.median(durs))
+        gbps = c["bytes"] / med / 1e9
+        per_case.append(dict(case=c["name"], perm=list(c["perm"]), size=list(c["size"]),
+                             dtype="f32" if c["dtype"].itemsize == 4 else "f64", beta=c["beta"],
+                             GBps=round(gbps, 1), pct_of_d2d=round(100 * gbps / d2d, 1),
+                             us=round(med * 1e6, 1), kernel=c["kernel"]))
+        k = by_kernel.setdefault(c["kernel"], dict(time=0.0, bytes=0, launches=0))
+        k["time"] += sum(durs)
+        k["bytes"] += c["bytes"] * args.steps
+        k["launches"] += args.steps
+    dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["time"])
+    achieved = dom["bytes"] / dom["time"] / 1e9
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    traffic = None   # counter bytes per launch, only while the kernel sources are unchanged
+    if os.path.exists(TRAFFIC):
+        with open(TRAFFIC) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash() and dom_name in tr.get("kernels", {}):
+            traffic = tr["kernels"][dom_name]["traffic_bytes"]
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBPS, 4), traffic=traffic,
+                    kernel=dom_name, launches=dom["launches"],
+                    avg_launch_us=round(dom["time"] / dom["launches"] * 1e6, 2),
+                    algorithmic_bytes_per_launch=int(bytes_per_launch))
+    dom_path = os.path.join(ROOT, "gpurun_out", "dominant_kernel.json")
+    if os.path.isdir(os.path.dirname(dom_path)) and not args.profile_run:
+        with open(dom_path, "w") as f:
+            json.dump(dict(kernel=dom_name, bytes_per_launch=bytes_per_launch,
+                           avg_launch_us=roofline["avg_launch_us"]), f)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        cpu = cpu_baseline(cases, args.cpu_seconds)
+
+    gbps_cases = [p["GBps"] for p in per_case]
+    out = dict(
+        metric=METRIC, value=round(value, 1), unit="GB/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(wall / args.steps * 1e3, 3), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+        config=dict(workload="paper-shaped transpositions, ~200 MiB per tensor: 4D/5D/6D x FP32/FP64 x "
+                             "(beta=0.7, beta=0), alpha=1.3, %d cases per step%s" %
+                             (len(cases), " + literal 160^4" if args.literal else ""),
+                    cases=len(cases), bytes_per_step=step_bytes, layout="column-major",
+                    entry_point="ttx_transpose (per call)", parallelism="single GPU"),
+        pct_of_d2d=round(100 * value / d2d, 1),
+        ceilings=ceil,
+        per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
+        roofline=roofline, cpu_baseline=cpu,
+        tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
+                    shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
+        per_perm=per_case,
+    )
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

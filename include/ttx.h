@@ -155,6 +155,12 @@ ttx_status ttx_plan_describe(const ttx_plan *plan, ttx_plan_info *info);
  * otherwise TTX_EINVAL.  Every accepted config computes the same bits. */
 ttx_status ttx_plan_set_config(ttx_plan *plan, int beta_is_zero, const ttx_config *config);
 ttx_status ttx_plan_destroy(ttx_plan *plan);
+/* Name of the kernel ttx_plan_execute would launch for these pointers (the
+ * vector variant depends on their alignment), e.g.
+ * "k_moved<float, false, 64, 64, 4, 4>", as profilers print it; written
+ * NUL-terminated into buf (len bytes).  Host only. */
+ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A, const void *B,
+                                char *buf, int len);
 
 /* -- autotuner (Sec. 2.1 stages 2-6, Sec. 2.3) --------------------------------
  * Enumerates every candidate (tile shape from the kernel menu x loop order

@@ -57,6 +57,8 @@ def _load(path):
     L.ttx_ref_sample.restype = ctypes.c_int
     L.ttx_ref_b_offsets.argtypes = [ctypes.c_int, ip, i64p, i64p, ctypes.c_int64, i64p, i64p]
     L.ttx_ref_b_offsets.restype = ctypes.c_int
+    L.ttx_ref_threads.argtypes = []
+    L.ttx_ref_threads.restype = ctypes.c_int
     return L
 
 
@@ -115,3 +117,8 @@ def sample(perm, size, alpha, A, beta, B_in, b_index, outer_a=None, outer_b=None
                              b_index.ctypes.data_as(i64p), off.ctypes.data_as(i64p))
     assert st == OK, st
     return out, off
+
+
+def threads(library=None):
+    """OpenMP threads the oracle's loop nest runs on."""
+    return (library or lib()).ttx_ref_threads()

@@ -38,6 +38,7 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <omp.h>
 
 enum { REF_OK = 0, REF_EINVAL = 1, REF_EPERM = 2, REF_EOVERLAP = 3, REF_EUNSUPPORTED = 4 };
 enum { REF_F32 = 0, REF_F64 = 1 };
@@ -270,4 +271,10 @@ int ttx_ref_b_offsets(int n, const int *perm, const int64_t *size, const int64_t
         off[q] = o;
     }
     return REF_OK;
+}
+
+/* Threads the parallel loop of ttx_ref_transpose uses. */
+int ttx_ref_threads(void)
+{
+    return omp_get_max_threads();
 }

@@ -61,6 +61,10 @@ def lib():
     """The loaded libttx.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        try:   # share the HIP runtime torch loads (one runtime per process)
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libttx.so is not built (run paper_1607_01249_amd/build.py); "
                                "there is no fallback implementation")
@@ -83,6 +87,7 @@ def _declare(L):
         "ttx_plan_describe": ([vp, ctypes.POINTER(PlanInfo)], S),
         "ttx_plan_set_config": ([vp, S, ctypes.POINTER(Config)], S),
         "ttx_plan_destroy": ([vp], S),
+        "ttx_plan_kernel_name": ([vp, ctypes.c_double, vp, vp, ctypes.c_char_p, S], S),
         "ttx_tune": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_candidates": ([S, S, ip, i64p, i64p, i64p, S, ctypes.POINTER(Config),
                                  ctypes.POINTER(ctypes.c_double), S, ip], S),
@@ -154,6 +159,12 @@ def ttx_plan_describe(plan):
 
 def ttx_plan_set_config(plan, beta_is_zero, config):
     return _check(lib().ttx_plan_set_config(plan, int(beta_is_zero), ctypes.byref(config)))
+
+
+def ttx_plan_kernel_name(plan, beta, A, B):
+    buf = ctypes.create_string_buffer(256)
+    _check(lib().ttx_plan_kernel_name(plan, float(beta), A, B, buf, 256))
+    return buf.value.decode()
 
 
 def ttx_plan_destroy(plan):

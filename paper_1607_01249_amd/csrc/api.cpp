@@ -179,6 +179,17 @@ ttx_status ttx_plan_set_config(ttx_plan* plan, int beta_is_zero, const ttx_confi
     return TTX_OK;
 }
 
+ttx_status ttx_plan_kernel_name(const ttx_plan* plan, double beta, const void* A, const void* B,
+                                char* buf, int len) {
+    if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
+    const Problem& p = plan->prob;
+    const bool beta0 = p.dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
+    const std::string name = kernel_name(p, plan->cfg[beta0 ? 1 : 0], beta0, A, B, B);
+    if (int(name.size()) >= len) return fail(TTX_EINVAL, "buffer too small");
+    std::memcpy(buf, name.c_str(), name.size() + 1);
+    return TTX_OK;
+}
+
 ttx_status ttx_plan_destroy(ttx_plan* plan) {
     delete plan;
     return TTX_OK;

@@ -1,5 +1,6 @@
 // Host-side launch of one planned transposition, the flat kernel, and the
 // bandwidth-ceiling kernels used for measurement.
+#include <cstdio>
 #include <mutex>
 
 #include "registry.h"
@@ -97,6 +98,27 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
     }
     return p.dtype == TTX_F32 ? launch_tiled<float>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream)
                               : launch_tiled<double>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+}
+
+std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                        const void* Bsrc, const void* Bdst) {
+    if (p.family == TTX_FAMILY_EMPTY) return "";
+    const char* t = p.dtype == TTX_F32 ? "float" : "double";
+    const char* z = beta0 ? "true" : "false";
+    const int V = p.dtype == TTX_F32 ? 4 : 2;
+    const int f = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    char buf[128];
+    if (p.family == TTX_FAMILY_FLAT) {
+        std::snprintf(buf, sizeof(buf), "k_flat<%s, %s>", t, z);
+    } else if (p.family == TTX_FAMILY_MOVED) {
+        const int va = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
+        const int vb = (f & KF_VEC_B) && c.tile_b % V == 0 ? V : 1;
+        std::snprintf(buf, sizeof(buf), "k_moved<%s, %s, %d, %d, %d, %d>", t, z, c.tile_a, c.tile_b, va, vb);
+    } else {
+        const int v = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
+        std::snprintf(buf, sizeof(buf), "k_preserved<%s, %s, %d, %d, %d>", t, z, c.tile_a, c.tile_b, v);
+    }
+    return buf;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -134,6 +134,10 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
                         const void* Bsrc, void* Bdst, double alpha, double beta,
                         hipStream_t stream);
 
+// The kernel launch_tiles would use, spelled as profilers print it.
+std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
+                        const void* Bsrc, const void* Bdst);
+
 // Ceiling kernels (dispatch.hip).
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t stream);
 hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, double beta, void* y,
