@@ -62,6 +62,10 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--literal", action="store_true",
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="Poisson arrival rate (req/s)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: no tuning, 1 warm-up, 2 steps, no CPU leg")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -122,6 +126,8 @@ def hip_runtime():
     L.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                  ctypes.c_void_p]
     L.hipMemcpyAsync.restype = ctypes.c_int
+    L.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    L.hipMemcpy.restype = ctypes.c_int
     return L
 
 
@@ -283,6 +289,167 @@ def summarize_trace(path, top=25):
     print("\n".join(lines))
 
 
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_batched(torch, ttx, reps=20):
+    """The 512 uneven transpositions: per-call loop vs one graph-captured
+    persistent launch (after per-shape tuning)."""
+    import workloads
+    probs = workloads.batched_problems()
+    stream = torch.cuda.current_stream().cuda_stream
+    tens, qs, nbytes = [], [], 0
+    for i, p in enumerate(probs):
+        n = workloads.elements(p["size"])
+        tdt = torch.float32 if p["dtype"].itemsize == 4 else torch.float64
+        A = torch.empty(n, dtype=tdt, device="cuda")
+        B = torch.empty(n, dtype=tdt, device="cuda")
+        fill_uniform(torch, A, 5000 + 2 * i)
+        fill_uniform(torch, B, 5001 + 2 * i)
+        tens.append((A, B))
+        qs.append(ttx.make_problem(ttx.F32 if tdt == torch.float32 else ttx.F64, p["perm"], p["size"],
+                                   p["alpha"], A.data_ptr(), p["beta"], B.data_ptr()))
+        nbytes += n * p["dtype"].itemsize * (2 if p["beta"] == 0 else 3)
+    torch.cuda.synchronize()
+
+    def per_call():
+        for q in qs:
+            ttx.ttx_transpose(q.dtype, q.n, list(q.perm[:q.n]), list(q.size[:q.n]), None, None, q.alpha,
+                              q.A, q.beta, q.B, stream)
+
+    per_call()
+    per_call()
+    pc_min, pc_med = time_events(torch, per_call, reps)
+    lat_pc = []
+    for q in qs:   # one call at a time, synchronised: the per-call latency
+        t0 = time.perf_counter()
+        ttx.ttx_transpose(q.dtype, q.n, list(q.perm[:q.n]), list(q.size[:q.n]), None, None, q.alpha,
+                          q.A, q.beta, q.B, stream)
+        torch.cuda.current_stream().synchronize()
+        lat_pc.append((time.perf_counter() - t0) * 1e6)
+    h = ttx.ttx_batch_create(qs)
+    t0 = time.time()
+    ttx.ttx_batch_tune(h, 8, 2)
+    tune_s = time.time() - t0
+    info = ttx.ttx_batch_get_info(h)
+    run = lambda: ttx.ttx_batch_execute(h, stream)
+    run()
+    run()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    ttx.ttx_batch_destroy(h)
+    del tens
+    b_min, b_med = min(times), float(np.median(times))
+    return dict(problems=len(qs), algorithmic_bytes=nbytes,
+                per_call=dict(GBps=round(nbytes / pc_med / 1e9, 1), ms=round(pc_med * 1e3, 3),
+                              launches=len(qs), call_latency_p50_us=round(_pct(lat_pc, 50), 1),
+                              call_latency_p99_us=round(_pct(lat_pc, 99), 1)),
+                batched=dict(GBps=round(nbytes / b_med / 1e9, 1), ms=round(b_med * 1e3, 3),
+                             makespan_p50_ms=round(_pct(times, 50) * 1e3, 3),
+                             makespan_p99_ms=round(_pct(times, 99) * 1e3, 3),
+                             grid=info["grid"], tiles=info["total_tiles"],
+                             variants=info["variants_used"], tuned=info["tuned"],
+                             tune_seconds=round(tune_s, 1), launch="1 persistent kernel per hipGraph replay"),
+                speedup=round(pc_med / b_med, 2))
+
+
+def bench_served(torch, ttx, seconds, rate):
+    """Open-loop Poisson trace through the server vs the same trace run one
+    synchronised per-call request at a time; a sample of requests is re-run
+    alone and compared bitwise with its in-mix result."""
+    import workloads
+    times, shapes = workloads.served_trace(rate=rate, duration=seconds)
+    n = len(times)
+    pool_bytes = 2 << 30
+    half = pool_bytes // 2
+    pool = torch.empty(pool_bytes // 4, dtype=torch.float32, device="cuda")
+    fill_uniform(torch, pool, 777)
+    base = pool.data_ptr()
+    rng = np.random.default_rng(8)
+    reqs = ttx._ttx.request_array(n)
+    nbytes_total = 0
+    max_out = 0
+    large_seen = 0
+    meta = []
+    for i, r in enumerate(shapes):
+        es = r["dtype"].itemsize
+        ne = workloads.elements(r["size"])
+        nb = ne * es
+        off_a = int(rng.integers(0, (half - nb) // 256 + 1)) * 256
+        off_b = half + int(rng.integers(0, (half - nb) // 256 + 1)) * 256
+        k = len(r["perm"])
+        row = reqs[i]
+        row["dtype"] = ttx.F32 if es == 4 else ttx.F64
+        row["n"] = k
+        row["perm"][:k] = r["perm"]
+        row["size"][:k] = r["size"]
+        row["alpha"] = r["alpha"]
+        row["beta"] = r["beta"]
+        row["A"] = base + off_a
+        row["B_in"] = base + off_b
+        keep = i % 997 == 0 or (r["large"] and large_seen < 64)
+        large_seen += 1 if r["large"] else 0
+        row["keep_result"] = 1 if keep else 0
+        nbytes_total += nb * (2 if r["beta"] == 0 else 3)
+        max_out = max(max_out, nb)
+        meta.append((r, off_a, off_b, nb))
+    offsets = (np.asarray(times) * 1e9).astype(np.int64)
+    torch.cuda.synchronize()
+    log("serving %d requests over %.1f s" % (n, seconds))
+    s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
+    try:
+        tickets = ttx.ttx_server_replay(s, reqs, offsets)
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        # the mix check: each kept result against the same request alone
+        hip = hip_runtime()
+        scratch = torch.empty(max_out + 256, dtype=torch.uint8, device="cuda")
+        served = torch.empty_like(scratch)
+        stream = torch.cuda.current_stream().cuda_stream
+        checked = mismatched = 0
+        for i in range(n):
+            if not reqs[i]["keep_result"] or tickets[i] == 0:
+                continue
+            r, off_a, off_b, nb = meta[i]
+            ptr, _ = ttx.ttx_server_result(s, int(tickets[i]))
+            torch.cuda.synchronize()
+            assert hip.hipMemcpy(served.data_ptr(), ptr, nb, 3) == 0
+            plan = ttx.ttx_plan_create(ttx.F32 if r["dtype"].itemsize == 4 else ttx.F64, r["perm"], r["size"])
+            ttx.ttx_plan_execute_split(plan, r["alpha"], base + off_a, r["beta"], base + off_b,
+                                       scratch.data_ptr(), stream)
+            ttx.ttx_plan_destroy(plan)
+            torch.cuda.synchronize()
+            checked += 1
+            mismatched += 0 if torch.equal(scratch[:nb], served[:nb]) else 1
+            ttx.ttx_server_release(s, int(tickets[i]))
+    finally:
+        ttx.ttx_server_destroy(s)
+    log("sequential per-call baseline")
+    scratch = torch.empty(max_out + 256, dtype=torch.uint8, device="cuda")
+    lat = ttx.ttx_replay_sequential(reqs, offsets, scratch.data_ptr(), scratch.numel(),
+                                    torch.cuda.current_stream().cuda_stream)
+    span = float(np.max(times + lat * 1e-6) - times[0])
+    del pool, scratch
+    return dict(requests=n, rate_per_s=rate, seconds=seconds, algorithmic_bytes=nbytes_total,
+                served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
+                            p99_us=round(st["p99_us"], 1), max_us=round(st["max_us"], 1),
+                            batches=st["batches"], mean_batch=round(st["mean_batch"], 2),
+                            rejected=st["rejected"], budget_GB=round(st["budget_bytes"] / 1e9, 1),
+                            peak_in_use_GB=round(st["peak_in_use_bytes"] / 1e9, 3), slots=4),
+                sequential=dict(GBps=round(nbytes_total / span / 1e9, 1), p50_us=round(_pct(lat, 50), 1),
+                                p99_us=round(_pct(lat, 99), 1), max_us=round(float(np.max(lat)), 1)),
+                throughput_ratio=round(st["throughput_gbps"] / (nbytes_total / span / 1e9), 2),
+                mix_check=dict(compared=checked, bitwise_mismatches=mismatched))
+
+
 # ---------------------------------------------------------------------------------------
 def main():
     args = parse_args()
@@ -298,6 +465,7 @@ def main():
         return 2
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu_baseline = 2, 1, True
+        args.no_batched = args.no_served = True
 
     import torch
     import paper_1607_01249_amd as ttx
@@ -404,6 +572,18 @@ def main():
             json.dump(dict(kernel=dom_name, bytes_per_launch=bytes_per_launch,
                            avg_launch_us=roofline["avg_launch_us"]), f)
 
+    for c in cases:   # the large cases' buffers are not needed any more
+        c.pop("A", None)
+        c.pop("B", None)
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        log("batched: 512 problems")
+        batched = bench_batched(torch, ttx)
+    served = None
+    if not args.no_served:
+        served = bench_served(torch, ttx, args.serve_seconds, args.serve_rate)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
@@ -422,7 +602,7 @@ def main():
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
-        roofline=roofline, cpu_baseline=cpu,
+        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,

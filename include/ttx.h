@@ -187,6 +187,145 @@ ttx_status ttx_tune_table_load(const char *path);
 ttx_status ttx_tune_table_clear(void);
 int ttx_tune_table_size(void);
 
+/* -- batched execution ----------------------------------------------------------
+ * Many independent transpositions, each Eqn. 1 with its own dtype, shape,
+ * permutation, leading dimensions, scalars and tensors, run by ONE
+ * persistent kernel launch: the planner splits every problem into tiles
+ * (Sec. 2.2 macro-tiles), the kernel's workgroups walk the combined tile
+ * space through a device-resident descriptor table, and the launch is
+ * captured once into a HIP graph and replayed by ttx_batch_execute.  Each
+ * problem's tile variant comes from a small menu compiled into that kernel:
+ * the per-shape tune table when ttx_batch_tune has timed it, otherwise the
+ * heuristics of Sec. 2.3.  Results are bitwise the same as per-call
+ * execution (the same tile code and operation order). */
+typedef struct ttx_problem {
+    ttx_dtype dtype;
+    int n;
+    int perm[TTX_MAX_DIMS];
+    int64_t size[TTX_MAX_DIMS];
+    int64_t outer_a[TTX_MAX_DIMS];   /* read when has_outer_a != 0 */
+    int64_t outer_b[TTX_MAX_DIMS];   /* read when has_outer_b != 0 */
+    int has_outer_a;
+    int has_outer_b;
+    double alpha;
+    double beta;
+    const void *A;
+    const void *B_in;                /* beta*B is read from here; NULL means B */
+    void *B;                         /* result */
+} ttx_problem;
+
+typedef struct ttx_batch_info {
+    int count;
+    int grid;                        /* workgroups of the persistent launch */
+    int variants_used;               /* distinct tile variants among the problems */
+    int tuned;                       /* problems whose config came from tuning */
+    int64_t total_tiles;
+    int64_t algorithmic_bytes;       /* sum of 2S (beta == 0) or 3S bytes */
+} ttx_batch_info;
+
+typedef struct ttx_batch ttx_batch;
+
+/* Plans all problems and uploads the descriptor table (the batch owns that
+ * device memory; the caller owns every A and B).  Every problem is checked
+ * as ttx_transpose would check it; the first failure is returned. */
+ttx_status ttx_batch_create(ttx_batch **batch, int count, const ttx_problem *problems);
+/* Times up to max_candidates batched-menu configs per distinct shape (0:
+ * 16) inside the persistent kernel on scratch buffers, keeps the fastest in
+ * a process-wide per-shape table and rebuilds the descriptors.  Blocks. */
+ttx_status ttx_batch_tune(ttx_batch *batch, int max_candidates, int reps);
+/* One graph launch of the persistent kernel on `stream` (captured on first use). */
+ttx_status ttx_batch_execute(ttx_batch *batch, hipStream_t stream);
+/* The same persistent kernel launched directly (no graph). */
+ttx_status ttx_batch_execute_direct(ttx_batch *batch, hipStream_t stream);
+/* New pointers and scalars for problems of unchanged shape; the copy to the
+ * descriptor table is ordered on `stream` and completes before returning. */
+ttx_status ttx_batch_update(ttx_batch *batch, int count, const ttx_problem *problems,
+                            hipStream_t stream);
+ttx_status ttx_batch_get_info(const ttx_batch *batch, ttx_batch_info *info);
+/* The config problem `index` runs with. */
+ttx_status ttx_batch_config(const ttx_batch *batch, int index, ttx_config *config);
+ttx_status ttx_batch_destroy(ttx_batch *batch);
+/* Host-only planning of `count` problems as ttx_batch_create would plan them
+ * (no HIP call, no device memory): the config and tile count of each. */
+ttx_status ttx_batch_plan(int count, const ttx_problem *problems, ttx_config *configs,
+                          int64_t *tiles);
+
+/* -- serving ----------------------------------------------------------------------
+ * A request loop with continuous batching.  Requests (one Eqn. 1 each) are
+ * admitted in arrival order while the sum of the HBM footprints of admitted,
+ * unreleased requests stays within the budget (hbm_fraction of the device
+ * memory free at creation; footprint = bytes of the A and B_in sub-tensor
+ * extents plus the output).  An admitted request whose problem.B is NULL gets
+ * its output in a server-owned arena.  A dispatcher thread launches whatever
+ * is admitted as one persistent batched-kernel launch whenever one of
+ * `slots` device slots (each a stream plus a descriptor ring entry in device
+ * memory) is free, so work that arrives while earlier micro-batches run
+ * overlaps with them on the device.  Results are bitwise those of
+ * ttx_transpose on the same inputs.  Latency = completion (observed by the
+ * dispatcher) minus arrival. */
+typedef struct ttx_server_opts {
+    double hbm_fraction;      /* admission budget as a fraction of free device memory (0: 0.8) */
+    int64_t arena_bytes;      /* output arena; 0: the whole budget */
+    int slots;                /* micro-batches in flight at once (0: 4) */
+    int max_batch;            /* requests per micro-batch (0: 256) */
+    int64_t max_batch_bytes;  /* algorithmic bytes per micro-batch (0: 256 MiB); one request always fits */
+    int max_queue;            /* waiting requests before submit refuses with TTX_EBUSY (0: 65536) */
+    int fake_device;          /* test hook: no HIP call and no memory access; requests "finish"
+                                 after the time their bytes would take at 4 TB/s, computing nothing */
+    int64_t fake_free_bytes;  /* free memory assumed by fake_device (0: 2^34 / 0.8) */
+} ttx_server_opts;
+
+typedef struct ttx_request {
+    ttx_problem problem;      /* problem.B == NULL: output in the server arena (then a beta != 0
+                                 request reads beta*B from problem.B_in, which must be set) */
+    int64_t arrival_ns;       /* steady-clock arrival time for latency; 0: time of submission */
+    int keep_result;          /* keep the output until ttx_server_release (else freed at completion) */
+} ttx_request;
+
+typedef struct ttx_server_stats {
+    int64_t submitted, rejected, completed, queued, running, batches;
+    double mean_batch;                 /* requests per micro-batch */
+    int64_t algorithmic_bytes;         /* of completed requests */
+    int64_t budget_bytes, in_use_bytes, peak_in_use_bytes;
+    double span_s;                     /* first arrival to last completion */
+    double throughput_gbps;            /* algorithmic bytes / span */
+    double p50_us, p99_us, max_us;     /* latency of completed requests */
+} ttx_server_stats;
+
+typedef struct ttx_server ttx_server;
+
+/* Allocates the arena and slots and starts the dispatcher thread. */
+ttx_status ttx_server_create(ttx_server **server, const ttx_server_opts *opts);
+/* Queues a request; TTX_EBUSY when its footprint can never fit the budget or
+ * the queue is full.  *ticket identifies it (tickets start at 1). */
+ttx_status ttx_server_submit(ttx_server *server, const ttx_request *request, uint64_t *ticket);
+ttx_status ttx_server_poll(ttx_server *server, uint64_t ticket, int *done);
+ttx_status ttx_server_wait(ttx_server *server, uint64_t ticket);
+/* Output pointer and latency of a finished request kept with keep_result. */
+ttx_status ttx_server_result(ttx_server *server, uint64_t ticket, void **B, double *latency_us);
+/* Frees a kept result's arena region and budget. */
+ttx_status ttx_server_release(ttx_server *server, uint64_t ticket);
+/* Waits until nothing is queued or running; TTX_EBUSY if admission is blocked
+ * by results the caller still holds. */
+ttx_status ttx_server_drain(ttx_server *server);
+/* Open-loop replay from the calling thread: request i is submitted at
+ * (start + offsets_ns[i]), which is also its arrival time; a full queue is
+ * retried, a request that can never fit gets ticket 0. */
+ttx_status ttx_server_replay(ttx_server *server, int64_t count, const ttx_request *requests,
+                             const int64_t *offsets_ns, uint64_t *tickets);
+ttx_status ttx_server_get_stats(ttx_server *server, ttx_server_stats *stats);
+/* The serving baseline: the same open-loop trace run one request at a time
+ * through the per-call path, each launched at its arrival time (or as soon
+ * as the previous one finished) and synchronised before the next;
+ * latencies_us[i] = completion - arrival.  A request with problem.B == NULL
+ * writes to `scratch` (scratch_bytes long). */
+ttx_status ttx_replay_sequential(int64_t count, const ttx_request *requests,
+                                 const int64_t *offsets_ns, void *scratch, int64_t scratch_bytes,
+                                 hipStream_t stream, double *latencies_us);
+/* Stops the dispatcher (requests not yet launched are dropped), waits for
+ * the device and frees everything. */
+ttx_status ttx_server_destroy(ttx_server *server);
+
 /* -- measurement kernels --------------------------------------------------------
  * Bandwidth ceilings the transposition is compared with (Sec. 3: the peak is
  * the bandwidth of an optimised SAXPY).  Both are plain streaming kernels. */

@@ -54,6 +54,82 @@ class PlanInfo(ctypes.Structure):
                 ("config", Config * 2), ("config_from_table", ctypes.c_int * 2)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("n", ctypes.c_int), ("perm", ctypes.c_int * MAX_DIMS),
+                ("size", i64 * MAX_DIMS), ("outer_a", i64 * MAX_DIMS), ("outer_b", i64 * MAX_DIMS),
+                ("has_outer_a", ctypes.c_int), ("has_outer_b", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("A", vp), ("B_in", vp), ("B", vp)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("grid", ctypes.c_int), ("variants_used", ctypes.c_int),
+                ("tuned", ctypes.c_int), ("total_tiles", i64), ("algorithmic_bytes", i64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("problem", Problem), ("arrival_ns", i64), ("keep_result", ctypes.c_int)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_fraction", ctypes.c_double), ("arena_bytes", i64), ("slots", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("max_batch_bytes", i64), ("max_queue", ctypes.c_int),
+                ("fake_device", ctypes.c_int), ("fake_free_bytes", i64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", i64), ("rejected", i64), ("completed", i64), ("queued", i64),
+                ("running", i64), ("batches", i64), ("mean_batch", ctypes.c_double),
+                ("algorithmic_bytes", i64), ("budget_bytes", i64), ("in_use_bytes", i64),
+                ("peak_in_use_bytes", i64), ("span_s", ctypes.c_double),
+                ("throughput_gbps", ctypes.c_double), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("max_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def request_array(count):
+    """A zeroed numpy array laid out exactly as `count` ttx_request structs, with
+    fields problem_dtype, n, perm, size, alpha, beta, A, B_in, B, arrival_ns,
+    keep_result (outer sizes unused: contiguous tensors)."""
+    import numpy as np
+    P = Problem
+    off = lambda f: getattr(P, f).offset
+    dt = np.dtype({"names": ["dtype", "n", "perm", "size", "alpha", "beta", "A", "B_in", "B",
+                             "arrival_ns", "keep_result"],
+                   "formats": [np.int32, np.int32, (np.int32, MAX_DIMS), (np.int64, MAX_DIMS),
+                               np.float64, np.float64, np.uint64, np.uint64, np.uint64, np.int64,
+                               np.int32],
+                   "offsets": [off("dtype"), off("n"), off("perm"), off("size"), off("alpha"),
+                               off("beta"), off("A"), off("B_in"), off("B"),
+                               Request.arrival_ns.offset, Request.keep_result.offset],
+                   "itemsize": ctypes.sizeof(Request)})
+    return np.zeros(count, dtype=dt)
+
+
+def make_problem(dtype, perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, B_in=None):
+    """A ttx_problem (A, B, B_in are device addresses)."""
+    q = Problem()
+    q.dtype = dtype
+    q.n = len(perm)
+    for k, v in enumerate(perm):
+        q.perm[k] = int(v)
+    for k, v in enumerate(size):
+        q.size[k] = int(v)
+    if outer_a is not None:
+        q.has_outer_a = 1
+        for k, v in enumerate(outer_a):
+            q.outer_a[k] = int(v)
+    if outer_b is not None:
+        q.has_outer_b = 1
+        for k, v in enumerate(outer_b):
+            q.outer_b[k] = int(v)
+    q.alpha, q.beta = float(alpha), float(beta)
+    q.A, q.B, q.B_in = A, B, B_in
+    return q
+
+
 _lib = None
 
 
@@ -95,6 +171,26 @@ def _declare(L):
         "ttx_tune_table_load": ([ctypes.c_char_p], S),
         "ttx_tune_table_clear": ([], S),
         "ttx_tune_table_size": ([], S),
+        "ttx_batch_create": ([ctypes.POINTER(vp), S, ctypes.POINTER(Problem)], S),
+        "ttx_batch_tune": ([vp, S, S], S),
+        "ttx_batch_execute": ([vp, vp], S),
+        "ttx_batch_execute_direct": ([vp, vp], S),
+        "ttx_batch_update": ([vp, S, ctypes.POINTER(Problem), vp], S),
+        "ttx_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], S),
+        "ttx_batch_config": ([vp, S, ctypes.POINTER(Config)], S),
+        "ttx_batch_destroy": ([vp], S),
+        "ttx_batch_plan": ([S, ctypes.POINTER(Problem), ctypes.POINTER(Config), i64p], S),
+        "ttx_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(ServerOpts)], S),
+        "ttx_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], S),
+        "ttx_server_poll": ([vp, ctypes.c_uint64, ip], S),
+        "ttx_server_wait": ([vp, ctypes.c_uint64], S),
+        "ttx_server_result": ([vp, ctypes.c_uint64, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double)], S),
+        "ttx_server_release": ([vp, ctypes.c_uint64], S),
+        "ttx_server_drain": ([vp], S),
+        "ttx_server_replay": ([vp, i64, vp, i64p, ctypes.POINTER(ctypes.c_uint64)], S),
+        "ttx_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], S),
+        "ttx_server_destroy": ([vp], S),
+        "ttx_replay_sequential": ([i64, vp, i64p, vp, i64, vp, ctypes.POINTER(ctypes.c_double)], S),
         "ttx_copy_kernel": ([vp, vp, i64, vp], S),
         "ttx_axpby_kernel": ([S, i64, ctypes.c_double, vp, ctypes.c_double, vp, vp], S),
     }
@@ -205,6 +301,138 @@ def ttx_tune_table_clear():
 
 def ttx_tune_table_size():
     return lib().ttx_tune_table_size()
+
+
+def _problem_array(problems):
+    arr = (Problem * max(1, len(problems)))()
+    for i, q in enumerate(problems):
+        arr[i] = q
+    return arr
+
+
+def ttx_batch_create(problems):
+    h = vp()
+    _check(lib().ttx_batch_create(ctypes.byref(h), len(problems), _problem_array(problems)))
+    return h
+
+
+def ttx_batch_tune(batch, max_candidates=0, reps=3):
+    return _check(lib().ttx_batch_tune(batch, int(max_candidates), int(reps)))
+
+
+def ttx_batch_execute(batch, stream=0):
+    return _check(lib().ttx_batch_execute(batch, stream))
+
+
+def ttx_batch_execute_direct(batch, stream=0):
+    return _check(lib().ttx_batch_execute_direct(batch, stream))
+
+
+def ttx_batch_update(batch, problems, stream=0):
+    return _check(lib().ttx_batch_update(batch, len(problems), _problem_array(problems), stream))
+
+
+def ttx_batch_get_info(batch):
+    info = BatchInfo()
+    _check(lib().ttx_batch_get_info(batch, ctypes.byref(info)))
+    return dict(count=info.count, grid=info.grid, variants_used=info.variants_used,
+                tuned=info.tuned, total_tiles=info.total_tiles,
+                algorithmic_bytes=info.algorithmic_bytes)
+
+
+def ttx_batch_config(batch, index):
+    c = Config()
+    _check(lib().ttx_batch_config(batch, int(index), ctypes.byref(c)))
+    return c
+
+
+def ttx_batch_destroy(batch):
+    return _check(lib().ttx_batch_destroy(batch))
+
+
+def ttx_batch_plan(problems):
+    """Host-only planning of a batch: (configs, tiles) per problem."""
+    n = len(problems)
+    cfg = (Config * max(1, n))()
+    tiles = (i64 * max(1, n))()
+    _check(lib().ttx_batch_plan(n, _problem_array(problems), cfg, tiles))
+    return [cfg[i] for i in range(n)], [tiles[i] for i in range(n)]
+
+
+def ttx_server_create(hbm_fraction=0.8, arena_bytes=0, slots=0, max_batch=0, max_batch_bytes=0,
+                      max_queue=0, fake_device=False, fake_free_bytes=0):
+    o = ServerOpts(hbm_fraction, arena_bytes, slots, max_batch, max_batch_bytes, max_queue,
+                   int(fake_device), fake_free_bytes)
+    h = vp()
+    _check(lib().ttx_server_create(ctypes.byref(h), ctypes.byref(o)))
+    return h
+
+
+def make_request(problem, arrival_ns=0, keep_result=False):
+    return Request(problem, int(arrival_ns), int(keep_result))
+
+
+def ttx_server_submit(server, request):
+    t = ctypes.c_uint64(0)
+    _check(lib().ttx_server_submit(server, ctypes.byref(request), ctypes.byref(t)))
+    return t.value
+
+
+def ttx_server_poll(server, ticket):
+    d = ctypes.c_int(0)
+    _check(lib().ttx_server_poll(server, ticket, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def ttx_server_wait(server, ticket):
+    return _check(lib().ttx_server_wait(server, ticket))
+
+
+def ttx_server_result(server, ticket):
+    b = vp()
+    lat = ctypes.c_double(0)
+    _check(lib().ttx_server_result(server, ticket, ctypes.byref(b), ctypes.byref(lat)))
+    return b.value, lat.value
+
+
+def ttx_server_release(server, ticket):
+    return _check(lib().ttx_server_release(server, ticket))
+
+
+def ttx_server_drain(server):
+    return _check(lib().ttx_server_drain(server))
+
+
+def ttx_server_replay(server, requests, offsets_ns):
+    """requests: a request_array(); offsets_ns: int64 numpy array.  Returns tickets."""
+    import numpy as np
+    offsets_ns = np.ascontiguousarray(offsets_ns, dtype=np.int64)
+    tickets = np.zeros(len(requests), dtype=np.uint64)
+    _check(lib().ttx_server_replay(server, len(requests), requests.ctypes.data,
+                                   offsets_ns.ctypes.data_as(i64p),
+                                   tickets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return tickets
+
+
+def ttx_server_get_stats(server):
+    st = ServerStats()
+    _check(lib().ttx_server_get_stats(server, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def ttx_replay_sequential(requests, offsets_ns, scratch, scratch_bytes, stream=0):
+    """Per-call baseline of a trace; returns the latencies in microseconds."""
+    import numpy as np
+    offsets_ns = np.ascontiguousarray(offsets_ns, dtype=np.int64)
+    lat = np.zeros(len(requests), dtype=np.float64)
+    _check(lib().ttx_replay_sequential(len(requests), requests.ctypes.data,
+                                       offsets_ns.ctypes.data_as(i64p), scratch, int(scratch_bytes),
+                                       stream, lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return lat
+
+
+def ttx_server_destroy(server):
+    return _check(lib().ttx_server_destroy(server))
 
 
 def ttx_copy_kernel(src, dst, nbytes, stream=0):

@@ -27,8 +27,8 @@ def _compile(src):
     cmd = ["hipcc", *COMMON]
     if src.endswith(".hip"):
         cmd += DEVICE + ["-x", "hip"]
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+    else:   # host-only translation units
+        cmd += ["--offload-arch=" + ARCH, "-D__HIP_PLATFORM_AMD__"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -60,11 +60,13 @@ static bool ranges_overlap(const void* x, int64_t xlen, const void* y, int64_t y
     return a < b + uint64_t(ylen) && b < a + uint64_t(xlen);
 }
 
-static ttx_status execute(const ttx_plan* plan, double alpha, const void* A, double beta,
-                          const void* Bin, void* Bout, hipStream_t stream) {
-    const Problem& p = plan->prob;
+bool beta_is_zero(int dtype, double beta) {
+    return dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
+}
+
+ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, const void* Bout,
+                          bool beta0) {
     if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
-    const bool beta0 = p.dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
     if (!A || !Bout || (!beta0 && !Bin)) return fail(TTX_EINVAL, "NULL tensor pointer");
     const uintptr_t esz = p.dtype == TTX_F32 ? 4 : 8;
     if (reinterpret_cast<uintptr_t>(A) % esz || reinterpret_cast<uintptr_t>(Bout) % esz ||
@@ -74,6 +76,16 @@ static ttx_status execute(const ttx_plan* plan, double alpha, const void* A, dou
         return fail(TTX_EOVERLAP, "A and B overlap (the operation is out-of-place)");
     if (!beta0 && Bin != Bout && ranges_overlap(Bin, p.extent_b, Bout, p.extent_b))
         return fail(TTX_EOVERLAP, "B_in and B_out overlap without being equal");
+    return TTX_OK;
+}
+
+static ttx_status execute(const ttx_plan* plan, double alpha, const void* A, double beta,
+                          const void* Bin, void* Bout, hipStream_t stream) {
+    const Problem& p = plan->prob;
+    if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
+    const bool beta0 = beta_is_zero(p.dtype, beta);
+    ttx_status st = check_pointers(p, A, Bin, Bout, beta0);
+    if (st != TTX_OK) return st;
     hipError_t e = launch_tiles(p, plan->cfg[beta0 ? 1 : 0], beta0, A, beta0 ? nullptr : Bin, Bout,
                                 alpha, beta, stream);
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -100,6 +112,33 @@ static std::string cache_key(int dtype, int n, const int* perm, const int64_t* s
     put(&nb, 1);
     if (outer_b) put(outer_b, sizeof(int64_t) * n);
     return k;
+}
+
+ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
+                            const int64_t* outer_a, const int64_t* outer_b, double alpha,
+                            const void* A, double beta, const void* Bin, void* Bout,
+                            hipStream_t stream) {
+    if (n < 1 || n > kMaxDims || !perm || !size) {
+        Problem p;
+        return make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    }
+    const std::string key = cache_key(dtype, n, perm, size, outer_a, outer_b);
+    std::shared_ptr<ttx_plan> plan;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) plan = it->second;
+    }
+    if (!plan || plan->table_gen != table_generation()) {
+        ttx_plan* raw = nullptr;
+        ttx_status st = new_plan(&raw, dtype, n, perm, size, outer_a, outer_b);
+        if (st != TTX_OK) return st;
+        plan.reset(raw);
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (g_cache.size() >= kCacheCap) g_cache.clear();
+        g_cache[key] = plan;
+    }
+    return execute(plan.get(), alpha, A, beta, Bin, Bout, stream);
 }
 
 }  // namespace ttx
@@ -183,7 +222,7 @@ ttx_status ttx_plan_kernel_name(const ttx_plan* plan, double beta, const void* A
                                 char* buf, int len) {
     if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
     const Problem& p = plan->prob;
-    const bool beta0 = p.dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
+    const bool beta0 = beta_is_zero(p.dtype, beta);
     const std::string name = kernel_name(p, plan->cfg[beta0 ? 1 : 0], beta0, A, B, B);
     if (int(name.size()) >= len) return fail(TTX_EINVAL, "buffer too small");
     std::memcpy(buf, name.c_str(), name.size() + 1);
@@ -198,27 +237,7 @@ ttx_status ttx_plan_destroy(ttx_plan* plan) {
 ttx_status ttx_transpose(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
                          const int64_t* outer_a, const int64_t* outer_b, double alpha,
                          const void* A, double beta, void* B, hipStream_t stream) {
-    if (n < 1 || n > kMaxDims || !perm || !size) {
-        Problem p;
-        return make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
-    }
-    const std::string key = cache_key(dtype, n, perm, size, outer_a, outer_b);
-    std::shared_ptr<ttx_plan> plan;
-    {
-        std::lock_guard<std::mutex> lock(g_cache_mu);
-        auto it = g_cache.find(key);
-        if (it != g_cache.end()) plan = it->second;
-    }
-    if (!plan || plan->table_gen != table_generation()) {
-        ttx_plan* raw = nullptr;
-        ttx_status st = new_plan(&raw, dtype, n, perm, size, outer_a, outer_b);
-        if (st != TTX_OK) return st;
-        plan.reset(raw);
-        std::lock_guard<std::mutex> lock(g_cache_mu);
-        if (g_cache.size() >= kCacheCap) g_cache.clear();
-        g_cache[key] = plan;
-    }
-    return execute(plan.get(), alpha, A, beta, B, B, stream);
+    return transpose_cached(dtype, n, perm, size, outer_a, outer_b, alpha, A, beta, B, B, stream);
 }
 
 ttx_status ttx_copy_kernel(const void* src, void* dst, int64_t bytes, hipStream_t stream) {

@@ -28,3 +28,25 @@
 #define TTX_PRESERVED_MENU_F64(X)                                                         \
     X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
     X(256, 4) X(256, 16) X(2, 512) X(4, 256)
+
+// Tile variants compiled into the persistent batched kernel, per dtype:
+// X(index, family, tile_a, tile_b, vector) where vector = 1 means 16-byte
+// accesses on both sides.  Kept small: every variant adds code to the one
+// kernel and its register and LDS needs set the kernel's occupancy.
+#define TTX_BATCH_MENU_F32(X)                                                             \
+    X(0, TTX_FAMILY_MOVED, 64, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
+    X(2, TTX_FAMILY_MOVED, 64, 64, 0) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
+    X(4, TTX_FAMILY_MOVED, 8, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 8, 0)                   \
+    X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
+    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 1024, 1, 1)               \
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0)
+
+#define TTX_BATCH_MENU_F64(X)                                                             \
+    X(0, TTX_FAMILY_MOVED, 32, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
+    X(2, TTX_FAMILY_MOVED, 64, 32, 0) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
+    X(4, TTX_FAMILY_MOVED, 4, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 4, 0)                   \
+    X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
+    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 512, 1, 1)                \
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0)
+
+#define TTX_BATCH_MENU_SIZE 11

@@ -455,7 +455,7 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
     return n;
 }
 
-ttx_config default_config(const Problem& p) {
+ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns) {
     ttx_config best;
     std::memset(&best, 0, sizeof(best));
     best.family = p.family;
@@ -468,8 +468,6 @@ ttx_config default_config(const Problem& p) {
     }
     // Greedy use of both heuristics: the cheapest tile shape, then the
     // indices sorted by the span one step covers (smallest first).
-    const TileShape* shapes;
-    int ns = tile_menu(p.dtype, p.family, &shapes);
     int a, b;
     tile_dims(p, &a, &b);
     double bestc = 1e300;
@@ -483,7 +481,8 @@ ttx_config default_config(const Problem& p) {
         };
         std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
         ttx_config c = make_config(p, ta, tb, o, 0);
-        if (!config_valid(p, c, nullptr)) continue;
+        // shapes outside the per-call menu (batched-kernel variants) are checked by their caller
+        if (tile_in_menu(p.dtype, p.family, ta, tb) && !config_valid(p, c, nullptr)) continue;
         double cost = blocking_cost(p, ta, tb) * (1.0 + order_cost(p, ta, tb, o.data()));
         if (cost < bestc) {
             bestc = cost;
@@ -491,6 +490,12 @@ ttx_config default_config(const Problem& p) {
         }
     }
     return best;
+}
+
+ttx_config default_config(const Problem& p) {
+    const TileShape* shapes;
+    int ns = tile_menu(p.dtype, p.family, &shapes);
+    return default_config_from(p, shapes, ns);
 }
 
 }  // namespace ttx

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <functional>
 #include <string>
 
 #include "../../include/ttx.h"
@@ -104,9 +105,24 @@ struct Problem {
     int n_orig = 0;
 };
 
+struct TileShape { int ta, tb; };
+
 // Status with a thread-local message.
 ttx_status fail(ttx_status s, const std::string& msg);
 void clear_error();
+
+// beta == 0 after rounding to the element type (then B is not read).
+bool beta_is_zero(int dtype, double beta);
+// Pointer checks shared by every entry point: NULL, element alignment, and
+// overlap of A with B_out and of B_in with B_out (unless they are equal).
+ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, const void* Bout,
+                          bool beta0);
+
+// The per-call path with the plan cache; B_in may differ from B_out.
+ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
+                            const int64_t* outer_a, const int64_t* outer_b, double alpha,
+                            const void* A, double beta, const void* Bin, void* Bout,
+                            hipStream_t stream);
 
 // Planner (host only).
 ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
@@ -115,6 +131,8 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why);
 // The heuristic default config (best-ranked candidate).
 ttx_config default_config(const Problem& p);
+// The same greedy choice restricted to the given tile shapes.
+ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns);
 // Candidate enumeration with estimated costs (sorted ascending).
 int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost, int cap);
 // Builds the kernel-side grid for a config.
@@ -124,7 +142,6 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
                  const void* Bdst);
 
 // Kernel menu (tile shapes the library instantiates), per dtype and family.
-struct TileShape { int ta, tb; };
 int tile_menu(int dtype, int family, const TileShape** shapes);
 bool tile_in_menu(int dtype, int family, int ta, int tb);
 constexpr int kThreads = 256;
@@ -147,5 +164,38 @@ hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, doubl
 bool table_lookup(const Problem& p, bool beta0, ttx_config* out);
 void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec);
 uint64_t table_generation();
+// Times `count` candidates on tuner-owned scratch buffers sized for p (minimum
+// of `reps` runs, the 1 GiB flush area cleared before each) and returns the
+// fastest; launch(i, A, B, stream) runs candidate i.
+ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
+                           const std::function<hipError_t(int, const void*, void*, hipStream_t)>& launch,
+                           int* best_i, double* best_us);
+
+// -- batched execution (batch.hip) ------------------------------------------
+// One entry of the device descriptor table read by the persistent kernel:
+// the tile variant (an index into the batched menu for the dtype and beta
+// class, or -1 when there is nothing to do), the tile count, and the
+// arguments of the tile body (a TileArgs<float> or TileArgs<double>).
+struct alignas(16) BatchDesc {
+    int variant;
+    int dtype;
+    uint32_t tiles;
+    uint32_t pad;
+    alignas(16) unsigned char args[sizeof(TileArgs<double>)];
+};
+
+// Fills *d for one problem: a tuned config when `forced` is non-NULL (it
+// must name a batched-menu shape), else the heuristic choice among the
+// batched-menu shapes.  *used receives the config.  Host only.
+ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0, const void* A,
+                          const void* Bsrc, void* Bdst, double alpha, double beta, BatchDesc* d,
+                          ttx_config* used);
+// Batched-menu configs for a problem, best heuristic first (for tuning).
+int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int cap);
+// Workgroups of the persistent launch for `total` tiles.
+int batch_grid(uint32_t total);
+// The persistent kernel over count descriptors (prefix[count] == total).
+hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_prefix, int count,
+                        uint32_t total, int grid, hipStream_t stream);
 
 }  // namespace ttx

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -84,6 +85,18 @@ static bool parse_config(std::istringstream& is, ttx_config* c) {
 // runs ("the caches are cleared before each run", Sec. 3).
 static constexpr size_t kFlushBytes = size_t(1) << 30;
 
+// One flush area per device, allocated on first use and kept for the life of
+// the process (tuning many small shapes would otherwise allocate 1 GiB each).
+static void* flush_area() {
+    static std::mutex mu;
+    static void* area[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!area[dev] && hipMalloc(&area[dev], kFlushBytes) != hipSuccess) area[dev] = nullptr;
+    return area[dev];
+}
+
 struct TuneScratch {
     void* A = nullptr;
     void* B = nullptr;
@@ -93,12 +106,54 @@ struct TuneScratch {
     ~TuneScratch() {
         if (A) (void)hipFree(A);
         if (B) (void)hipFree(B);
-        if (flush) (void)hipFree(flush);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
+
+ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
+                           const std::function<hipError_t(int, const void*, void*, hipStream_t)>& launch,
+                           int* best_i, double* best_us) {
+    if (reps <= 0) reps = 3;
+    TuneScratch s;
+    s.flush = flush_area();
+    if (!s.flush || hipMalloc(&s.A, size_t(p.extent_a) + 16) != hipSuccess ||
+        hipMalloc(&s.B, size_t(p.extent_b) + 16) != hipSuccess)
+        return fail(TTX_ENOMEM, "tuner scratch allocation failed");
+    if (hipStreamCreate(&s.stream) != hipSuccess || hipEventCreate(&s.e0) != hipSuccess ||
+        hipEventCreate(&s.e1) != hipSuccess)
+        return fail(TTX_EHIP, "tuner stream/event creation failed");
+    if (hipMemsetAsync(s.A, 0, size_t(p.extent_a), s.stream) != hipSuccess ||
+        hipMemsetAsync(s.B, 0, size_t(p.extent_b), s.stream) != hipSuccess)
+        return fail(TTX_EHIP, "tuner scratch initialisation failed");
+    (void)beta0;
+    *best_i = -1;
+    *best_us = 1e300;
+    for (int i = 0; i < count; ++i) {
+        hipError_t e = launch(i, s.A, s.B, s.stream);
+        if (e != hipSuccess) return fail(TTX_EHIP, std::string("tuner launch: ") + hipGetErrorString(e));
+        double t_min = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            if (hipMemsetAsync(s.flush, r & 0xff, kFlushBytes, s.stream) != hipSuccess ||
+                hipEventRecord(s.e0, s.stream) != hipSuccess)
+                return fail(TTX_EHIP, "tuner timing failed");
+            e = launch(i, s.A, s.B, s.stream);
+            if (e != hipSuccess || hipEventRecord(s.e1, s.stream) != hipSuccess ||
+                hipEventSynchronize(s.e1) != hipSuccess)
+                return fail(TTX_EHIP, "tuner timing failed");
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, s.e0, s.e1);
+            if (ms * 1e3 < t_min) t_min = ms * 1e3;
+        }
+        if (t_min < *best_us) {   // ties keep the earlier (better-ranked) candidate
+            *best_us = t_min;
+            *best_i = i;
+        }
+    }
+    if (hipStreamSynchronize(s.stream) != hipSuccess) return fail(TTX_EHIP, "tuner sync failed");
+    return TTX_OK;
+}
 
 }  // namespace ttx
 
@@ -121,7 +176,6 @@ ttx_status ttx_tune(ttx_dtype dtype, int n, const int* perm, const int64_t* size
                     const int64_t* outer_a, const int64_t* outer_b, int beta_is_zero,
                     int max_candidates, int reps, ttx_config* best, int* n_timed) {
     if (!best) return fail(TTX_EINVAL, "best must not be NULL");
-    if (reps <= 0) reps = 3;
     Problem p;
     ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
     if (st != TTX_OK) return st;
@@ -134,46 +188,16 @@ ttx_status ttx_tune(ttx_dtype dtype, int n, const int* perm, const int64_t* size
     std::vector<ttx_config> cands(keep < 0 ? 1 << 17 : keep);
     int nc = rank_candidates(p, max_candidates, cands.data(), nullptr, int(cands.size()));
     if (nc <= 0) return fail(TTX_EUNSUPPORTED, "no candidate for this problem");
-
-    TuneScratch s;
-    if (hipMalloc(&s.A, size_t(p.extent_a) + 16) != hipSuccess ||
-        hipMalloc(&s.B, size_t(p.extent_b) + 16) != hipSuccess ||
-        hipMalloc(&s.flush, kFlushBytes) != hipSuccess)
-        return fail(TTX_ENOMEM, "tuner scratch allocation failed");
-    if (hipStreamCreate(&s.stream) != hipSuccess || hipEventCreate(&s.e0) != hipSuccess ||
-        hipEventCreate(&s.e1) != hipSuccess)
-        return fail(TTX_EHIP, "tuner stream/event creation failed");
-    if (hipMemsetAsync(s.A, 0, size_t(p.extent_a), s.stream) != hipSuccess ||
-        hipMemsetAsync(s.B, 0, size_t(p.extent_b), s.stream) != hipSuccess)
-        return fail(TTX_EHIP, "tuner scratch initialisation failed");
-
+    cands.resize(nc);
     const bool beta0 = beta_is_zero != 0;
-    const double alpha = 1.0, beta = beta0 ? 0.0 : 1.0;
-    double best_us = 1e300;
     int best_i = -1;
-    for (int i = 0; i < nc; ++i) {
-        hipError_t e = launch_tiles(p, cands[i], beta0, s.A, s.B, s.B, alpha, beta, s.stream);
-        if (e != hipSuccess) return fail(TTX_EHIP, std::string("tuner launch: ") + hipGetErrorString(e));
-        double t_min = 1e300;
-        for (int r = 0; r < reps; ++r) {
-            if (hipMemsetAsync(s.flush, r & 0xff, kFlushBytes, s.stream) != hipSuccess ||
-                hipEventRecord(s.e0, s.stream) != hipSuccess)
-                return fail(TTX_EHIP, "tuner timing failed");
-            e = launch_tiles(p, cands[i], beta0, s.A, s.B, s.B, alpha, beta, s.stream);
-            if (e != hipSuccess || hipEventRecord(s.e1, s.stream) != hipSuccess ||
-                hipEventSynchronize(s.e1) != hipSuccess)
-                return fail(TTX_EHIP, "tuner timing failed");
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, s.e0, s.e1);
-            if (ms * 1e3 < t_min) t_min = ms * 1e3;
-        }
-        // ties keep the earlier (better-ranked) candidate
-        if (t_min < best_us) {
-            best_us = t_min;
-            best_i = i;
-        }
-    }
-    if (hipStreamSynchronize(s.stream) != hipSuccess) return fail(TTX_EHIP, "tuner sync failed");
+    double best_us = 0;
+    st = time_candidates(p, beta0, int(cands.size()), reps,
+                         [&](int i, const void* A, void* B, hipStream_t s) {
+                             return launch_tiles(p, cands[i], beta0, A, B, B, 1.0, beta0 ? 0.0 : 1.0, s);
+                         },
+                         &best_i, &best_us);
+    if (st != TTX_OK) return st;
     *best = cands[best_i];
     if (n_timed) *n_timed = nc;
     table_store(p, beta0, *best, best_us);

@@ -88,3 +88,22 @@ def assert_parity(got, ref, exact, what=""):
         ulp = max_ulp(got, ref)
         assert ulp <= 1, "max %s ulp (%d elements differ) %s" % (ulp, differ, what)
     return differ
+
+
+_hip = None
+
+
+def dev_copy(dst, src, nbytes):
+    """Device-to-device copy through the HIP runtime (hipMemcpy), synchronous."""
+    global _hip
+    import ctypes
+    import torch
+    if _hip is None:
+        maps = open("/proc/self/maps").read().splitlines()
+        paths = sorted({l.split()[-1] for l in maps if "libamdhip64" in l})
+        _hip = ctypes.CDLL(paths[0])
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    torch.cuda.synchronize()
+    rc = _hip.hipMemcpy(dst, src, nbytes, 3)
+    assert rc == 0, rc

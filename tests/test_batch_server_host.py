@@ -1,0 +1,187 @@
+"""Host-side logic of batched execution and serving (no GPU): batch planning,
+and the server's admission, back-pressure, result holding, draining and
+latency accounting, driven by its fake executor (which computes nothing and
+touches no memory; requests finish after the time their bytes would take)."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_1607_01249_amd as ttx
+import workloads
+
+FAKE_BASE = 1 << 40
+
+
+def _fake_problems(probs, gap=256):
+    """ttx_problems for workload dicts at made-up, non-overlapping addresses."""
+    base = FAKE_BASE
+    out = []
+    for p in probs:
+        nbytes = workloads.elements(p["size"]) * p["dtype"].itemsize
+        A = base
+        base += nbytes + gap
+        B = base
+        base += nbytes + gap
+        out.append(ttx.make_problem(ttx.F32 if p["dtype"].itemsize == 4 else ttx.F64, p["perm"],
+                                    p["size"], p["alpha"], A, p["beta"], B))
+    return out
+
+
+BATCH_SHAPES = {
+    (ttx.F32, ttx.FAMILY_MOVED): {(64, 64), (32, 32), (8, 128), (128, 8)},
+    (ttx.F64, ttx.FAMILY_MOVED): {(32, 64), (32, 32), (64, 32), (4, 128), (128, 4)},
+    (ttx.F32, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64)},
+    (ttx.F64, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64)},
+    (ttx.F32, ttx.FAMILY_FLAT): {(1024, 1), (256, 1)},
+    (ttx.F64, ttx.FAMILY_FLAT): {(512, 1), (256, 1)},
+}
+
+
+def test_batch_plan_uses_the_batched_menu():
+    probs = workloads.batched_problems()
+    qs = _fake_problems(probs)
+    cfgs, tiles = ttx.ttx_batch_plan(qs)
+    assert len(cfgs) == 512
+    for q, c, t in zip(qs, cfgs, tiles):
+        assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(q.dtype, c.family)], c.as_dict()
+        assert c.flags & ttx.CFG_XCD_SWIZZLE == 0
+        # every element is covered: tiles * tile area >= elements
+        n = int(np.prod(list(q.size[:q.n])))
+        assert t >= 1 and t * c.tile_a * max(1, c.tile_b) >= n
+    fams = {c.family for c in cfgs}
+    assert fams >= {ttx.FAMILY_MOVED, ttx.FAMILY_PRESERVED, ttx.FAMILY_FLAT}
+
+
+def test_batch_plan_misaligned_pointers_use_scalar_variants():
+    q = ttx.make_problem(ttx.F32, (1, 0), (64, 64), 1.0, FAKE_BASE + 4, 0.0, FAKE_BASE + (1 << 20))
+    (c,), _ = ttx.ttx_batch_plan([q])
+    assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(ttx.F32, ttx.FAMILY_MOVED)]
+    q = ttx.make_problem(ttx.F32, (0,), (1001,), 1.0, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
+    (c,), _ = ttx.ttx_batch_plan([q])
+    assert c.family == ttx.FAMILY_FLAT and c.tile_a == 256     # 1001 % 4 != 0: scalar
+    q = ttx.make_problem(ttx.F32, (0,), (1000,), 1.0, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
+    (c,), _ = ttx.ttx_batch_plan([q])
+    assert c.tile_a == 1024
+
+
+def test_batch_plan_rejects_bad_problems():
+    good = ttx.make_problem(ttx.F32, (1, 0), (8, 8), 1.0, FAKE_BASE, 0.0, FAKE_BASE + 4096)
+    bad = ttx.make_problem(ttx.F32, (0, 0), (8, 8), 1.0, FAKE_BASE, 0.0, FAKE_BASE + 4096)
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_batch_plan([good, bad])
+    assert e.value.status == ttx.EPERM
+    overlap = ttx.make_problem(ttx.F32, (1, 0), (8, 8), 1.0, FAKE_BASE, 0.0, FAKE_BASE + 16)
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_batch_plan([overlap])
+    assert e.value.status == ttx.EOVERLAP
+
+
+# -- server with the fake executor -------------------------------------------------------
+def _req(size=(64, 64), perm=(1, 0), dtype=ttx.F32, beta=0.0, A=FAKE_BASE, B=None, B_in=None,
+         keep=False):
+    q = ttx.make_problem(dtype, perm, size, 1.5, A, beta, B, B_in=B_in)
+    return ttx.make_request(q, 0, keep)
+
+
+def test_server_budget_rejects_oversized_request():
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=1 << 20)   # budget 0.8 MiB
+    try:
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_server_submit(s, _req(size=(512, 512)))   # 1 MiB in + 1 MiB out
+        assert e.value.status == ttx.EBUSY
+        t = ttx.ttx_server_submit(s, _req(size=(64, 64)))
+        ttx.ttx_server_wait(s, t)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["rejected"] == 1 and st["completed"] == 1 and st["in_use_bytes"] == 0
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
+def test_server_holds_results_until_release_and_blocks_admission():
+    # each request: 64 KiB in + 64 KiB out; budget 0.8 * 512 KiB -> 3 fit
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=512 << 10, max_queue=4)
+    try:
+        held = [ttx.ttx_server_submit(s, _req(size=(128, 128), keep=True)) for _ in range(3)]
+        for t in held:
+            ttx.ttx_server_wait(s, t)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["in_use_bytes"] == 3 * 2 * 65536
+        blocked = [ttx.ttx_server_submit(s, _req(size=(128, 128))) for _ in range(4)]
+        time.sleep(0.05)
+        assert not any(ttx.ttx_server_poll(s, t) for t in blocked)
+        with pytest.raises(ttx.TTXError) as e:      # queue of 4 is full
+            ttx.ttx_server_submit(s, _req(size=(128, 128)))
+        assert e.value.status == ttx.EBUSY
+        with pytest.raises(ttx.TTXError) as e:      # nothing running, head cannot be admitted
+            ttx.ttx_server_drain(s)
+        assert e.value.status == ttx.EBUSY
+        ptr, lat = ttx.ttx_server_result(s, held[0])
+        assert ptr >= 1 << 44 and lat >= 0
+        for t in held:
+            ttx.ttx_server_release(s, t)
+        ttx.ttx_server_drain(s)
+        assert all(ttx.ttx_server_poll(s, t) for t in blocked)
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_server_release(s, held[0])
+        assert e.value.status == ttx.ENOTFOUND
+        st = ttx.ttx_server_get_stats(s)
+        assert st["completed"] == 7 and st["in_use_bytes"] == 0
+        assert st["peak_in_use_bytes"] <= st["budget_bytes"]
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
+def test_server_validation():
+    s = ttx.ttx_server_create(fake_device=True)
+    try:
+        with pytest.raises(ttx.TTXError) as e:     # beta != 0 with an arena output needs B_in
+            ttx.ttx_server_submit(s, _req(beta=0.5))
+        assert e.value.status == ttx.EINVAL
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_server_submit(s, _req(perm=(0, 0)))
+        assert e.value.status == ttx.EPERM
+        t = ttx.ttx_server_submit(s, _req(beta=0.5, B_in=FAKE_BASE + (1 << 20)))
+        ttx.ttx_server_wait(s, t)
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_server_poll(s, 12345)
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
+def test_server_replay_batches_and_accounts_latency():
+    n = 3000
+    reqs = ttx._ttx.request_array(n)
+    rng = np.random.default_rng(3)
+    for i in range(n):
+        k = int(rng.integers(2, 5))
+        reqs[i]["dtype"] = ttx.F32 if rng.random() < 0.7 else ttx.F64
+        reqs[i]["n"] = k
+        reqs[i]["perm"][:k] = rng.permutation(k)
+        reqs[i]["size"][:k] = rng.integers(2, 40, size=k)
+        reqs[i]["alpha"] = 1.0
+        reqs[i]["beta"] = 0.0
+        reqs[i]["A"] = FAKE_BASE
+    offsets = np.cumsum(np.random.default_rng(4).exponential(1e9 / 100000.0, size=n)).astype(np.int64)
+    s = ttx.ttx_server_create(fake_device=True, slots=2, max_batch=64)
+    try:
+        tickets = ttx.ttx_server_replay(s, reqs, offsets)
+        assert (tickets > 0).all() and len(set(tickets.tolist())) == n
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["submitted"] == n and st["completed"] == n and st["rejected"] == 0
+        assert 0 <= st["p50_us"] <= st["p99_us"] <= st["max_us"]
+        assert st["batches"] <= n and st["mean_batch"] >= 1.0
+        assert st["span_s"] >= offsets[-1] * 1e-9 * 0.99
+        assert st["in_use_bytes"] == 0
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
+def test_server_destroy_with_queued_work():
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=256 << 10)
+    t = ttx.ttx_server_submit(s, _req(size=(128, 128), keep=True))
+    ttx.ttx_server_wait(s, t)
+    for _ in range(5):
+        ttx.ttx_server_submit(s, _req(size=(128, 128)))
+    ttx.ttx_server_destroy(s)   # must return although the queue is blocked
