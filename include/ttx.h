@@ -90,7 +90,9 @@ typedef enum ttx_family {
  *   threads : threads per workgroup;
  *   order   : the merged indices in the order tile ids enumerate them,
  *             fastest first (the "loop order" of Sec. 2.2); n_order entries;
- *   flags   : TTX_CFG_* bits. */
+ *   flags   : TTX_CFG_* bits;
+ *   group_a/b: moved family only -- index groups that extend the 2D tile
+ *             when stride-1 extents are short (1 = the single index). */
 typedef struct ttx_config {
     int family;
     int tile_a;
@@ -99,6 +101,8 @@ typedef struct ttx_config {
     int n_order;
     int order[TTX_MAX_DIMS];
     int flags;
+    int group_a;   /* MOVED: A's first group_a merged indices, contiguous in A, form the tile's A edge */
+    int group_b;   /* MOVED: B's first group_b merged indices, contiguous in B, form its B edge; else 1 */
 } ttx_config;
 
 /* What the planner made of a problem (Sec. 2.1 stage 1 and the family split

@@ -40,9 +40,9 @@ struct ttx_batch {
 namespace ttx {
 
 struct BatchEntry {
-    int index, family, ta, tb, vec;
+    int index, kind, p1, p2, p3;
 };
-#define TTX_BATCH_ENTRY(i, fam, ta, tb, vec) {i, fam, ta, tb, vec},
+#define TTX_BATCH_ENTRY(i, kind, p1, p2, p3) {i, kind, p1, p2, p3},
 static const BatchEntry kBatchF32[] = {TTX_BATCH_MENU_F32(TTX_BATCH_ENTRY)};
 static const BatchEntry kBatchF64[] = {TTX_BATCH_MENU_F64(TTX_BATCH_ENTRY)};
 #undef TTX_BATCH_ENTRY
@@ -52,16 +52,24 @@ static const BatchEntry* batch_menu(int dtype) { return dtype == TTX_F32 ? kBatc
 static int batch_index(int dtype, int family, int ta, int tb, int vec) {
     const BatchEntry* m = batch_menu(dtype);
     for (int i = 0; i < TTX_BATCH_MENU_SIZE; ++i)
-        if (m[i].family == family && m[i].ta == ta && m[i].tb == tb && m[i].vec == vec) return i;
+        if (m[i].kind == family && m[i].p1 == ta && m[i].p2 == tb && m[i].p3 == vec) return i;
     return -1;
 }
 
-// LDS of the largest moved-family variant of either dtype.
-constexpr int lds_need(int family, int ta, int tb, int esize) {
-    return family == TTX_FAMILY_MOVED ? tb * (ta + 1) * esize : 0;
+static int staged_index(int dtype, int lanes, int tx, int ty) {
+    const BatchEntry* m = batch_menu(dtype);
+    for (int i = 0; i < TTX_BATCH_MENU_SIZE; ++i)
+        if (m[i].kind == TTX_BATCH_STAGED && m[i].p1 == lanes && m[i].p2 == tx && m[i].p3 == ty) return i;
+    return -1;
 }
-#define TTX_LDS_F32(i, fam, ta, tb, vec) lds_need(fam, ta, tb, 4),
-#define TTX_LDS_F64(i, fam, ta, tb, vec) lds_need(fam, ta, tb, 8),
+
+// LDS of the largest LDS-staged variant of either dtype.
+constexpr int lds_need(int kind, int p1, int p2, int p3, int esize) {
+    return kind == TTX_FAMILY_MOVED ? p2 * (p1 + 1) * esize
+                                    : kind == TTX_BATCH_STAGED ? p3 * (p2 * p1 + 1) * esize : 0;
+}
+#define TTX_LDS_F32(i, kind, p1, p2, p3) lds_need(kind, p1, p2, p3, 4),
+#define TTX_LDS_F64(i, kind, p1, p2, p3) lds_need(kind, p1, p2, p3, 8),
 constexpr int batch_lds_bytes() {
     constexpr int list[] = {TTX_BATCH_MENU_F32(TTX_LDS_F32) TTX_BATCH_MENU_F64(TTX_LDS_F64) 0};
     int m = 0;
@@ -72,14 +80,19 @@ constexpr int batch_lds_bytes() {
 #undef TTX_LDS_F64
 constexpr int kBatchLds = batch_lds_bytes();
 
-template <typename T, bool B0, int FAM, int TA, int TB, int VEC>
-__device__ __forceinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a, uint32_t local) {
-    constexpr int V = VEC ? kVec<T> : 1;
-    const TileCoord c = decode_tile(a.g, local, TA, TB);
-    if constexpr (FAM == TTX_FAMILY_MOVED)
-        moved_tile<T, B0, TA, TB, V, V>(reinterpret_cast<T*>(lds), a, c);
-    else
-        preserved_tile<T, B0, TA, TB, V>(a, c);
+template <typename T, bool B0, int KIND, int P1, int P2, int P3>
+__device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a, uint32_t local) {
+    if constexpr (KIND == TTX_BATCH_STAGED) {
+        const TileCoord c = decode_tile(a.g, local, P2, P3);
+        staged_tile<T, B0, P1, P2, P3>(reinterpret_cast<T*>(lds), a, c);
+    } else {
+        constexpr int V = P3 ? kVec<T> : 1;
+        const TileCoord c = decode_tile(a.g, local, P1, P2);
+        if constexpr (KIND == TTX_FAMILY_MOVED)
+            moved_tile<T, B0, P1, P2, V, V>(reinterpret_cast<T*>(lds), a, c);
+        else
+            preserved_tile<T, B0, P1, P2, V>(a, c);
+    }
 }
 
 template <bool B0>
@@ -87,8 +100,8 @@ __device__ __forceinline__ void batch_dispatch_f32(int idx, unsigned char* lds, 
                                                    uint32_t local) {
     const TileArgs<float>& a = *reinterpret_cast<const TileArgs<float>*>(d.args);
     switch (idx) {
-#define TTX_CASE(i, fam, ta, tb, vec) \
-    case i: batch_body<float, B0, fam, ta, tb, vec>(lds, a, local); break;
+#define TTX_CASE(i, kind, p1, p2, p3) \
+    case i: batch_body<float, B0, kind, p1, p2, p3>(lds, a, local); break;
         TTX_BATCH_MENU_F32(TTX_CASE)
 #undef TTX_CASE
         default: break;
@@ -100,8 +113,8 @@ __device__ __forceinline__ void batch_dispatch_f64(int idx, unsigned char* lds, 
                                                    uint32_t local) {
     const TileArgs<double>& a = *reinterpret_cast<const TileArgs<double>*>(d.args);
     switch (idx) {
-#define TTX_CASE(i, fam, ta, tb, vec) \
-    case i: batch_body<double, B0, fam, ta, tb, vec>(lds, a, local); break;
+#define TTX_CASE(i, kind, p1, p2, p3) \
+    case i: batch_body<double, B0, kind, p1, p2, p3>(lds, a, local); break;
         TTX_BATCH_MENU_F64(TTX_CASE)
 #undef TTX_CASE
         default: break;
@@ -118,6 +131,9 @@ void k_batch(const BatchDesc* __restrict__ desc,
     int p = 0;
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         while (p + 1 < count && t >= prefix[p + 1]) ++p;
+        // p is the same in every lane: say so, so that the descriptor is read
+        // through the scalar cache into scalar registers
+        p = __builtin_amdgcn_readfirstlane(p);
         const BatchDesc& d = desc[p];
         const int v = d.variant;
         if (v < 0) continue;
@@ -188,15 +204,19 @@ static ttx_config batch_default(const Problem& p, bool vec) {
         ttx_config c = default_config(p);
         return c;
     }
-    std::vector<TileShape> shapes;
+    std::vector<TileShape> shapes, staged;
     const BatchEntry* m = batch_menu(p.dtype);
     for (int i = 0; i < TTX_BATCH_MENU_SIZE; ++i) {
-        if (m[i].family != p.family || (m[i].vec && !vec)) continue;
+        if (m[i].kind == TTX_BATCH_STAGED) {
+            if (p.family == TTX_FAMILY_PRESERVED) staged.push_back(TileShape{m[i].p1 * 65536 + m[i].p2, m[i].p3});
+            continue;
+        }
+        if (m[i].kind != p.family || (m[i].p3 && !vec)) continue;
         bool dup = false;
-        for (const auto& s : shapes) dup |= s.ta == m[i].ta && s.tb == m[i].tb;
-        if (!dup) shapes.push_back(TileShape{m[i].ta, m[i].tb});
+        for (const auto& s : shapes) dup |= s.ta == m[i].p1 && s.tb == m[i].p2;
+        if (!dup) shapes.push_back(TileShape{m[i].p1, m[i].p2});
     }
-    return default_config_from(p, shapes.data(), int(shapes.size()));
+    return default_config_from(p, shapes.data(), int(shapes.size()), staged.data(), int(staged.size()));
 }
 
 ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0, const void* A,
@@ -219,6 +239,13 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
         c.tile_a = use_vec ? (p.dtype == TTX_F32 ? 1024 : 512) : 256;
         c.tile_b = 1;
         idx = batch_index(p.dtype, p.family, c.tile_a, 1, use_vec ? 1 : 0);
+    } else if (config_is_staged(c)) {
+        idx = staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b);
+        if (idx < 0 && forced) {
+            c = batch_default(p, false);
+            idx = config_is_staged(c) ? staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b)
+                                      : batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0);
+        }
     } else {
         if (c.n_order != p.n) return fail(TTX_EINVAL, "order must list every merged index");
         idx = use_vec ? batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) : -1;
@@ -234,29 +261,26 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
         }
     }
     if (idx < 0) return fail(TTX_EINVAL, "tile shape not in the batched menu");
-    int64_t s[4];
     const int vclass = (p.dtype == TTX_F32 ? 0 : 2) + (beta0 ? 1 : 0);
     if (p.dtype == TTX_F32) {
         TileArgs<float> a;
-        build_grid(p, c, &a.g, s);
+        build_grid(p, c, &a);
         a.A = static_cast<const float*>(A);
         a.Bsrc = static_cast<const float*>(beta0 ? nullptr : Bsrc);
         a.Bdst = static_cast<float*>(Bdst);
         a.alpha = float(alpha);
         a.beta = float(beta);
-        a.sAa = s[0]; a.sAb = s[1]; a.sBa = s[2]; a.sBb = s[3];
         a.flags = (c.flags & TTX_CFG_NT_STORE) ? KF_NT_STORE : 0;
         d->tiles = a.g.ntiles;
         std::memcpy(d->args, &a, sizeof(a));
     } else {
         TileArgs<double> a;
-        build_grid(p, c, &a.g, s);
+        build_grid(p, c, &a);
         a.A = static_cast<const double*>(A);
         a.Bsrc = static_cast<const double*>(beta0 ? nullptr : Bsrc);
         a.Bdst = static_cast<double*>(Bdst);
         a.alpha = alpha;
         a.beta = beta;
-        a.sAa = s[0]; a.sAb = s[1]; a.sBa = s[2]; a.sBb = s[3];
         a.flags = (c.flags & TTX_CFG_NT_STORE) ? KF_NT_STORE : 0;
         d->tiles = a.g.ntiles;
         std::memcpy(d->args, &a, sizeof(a));
@@ -285,9 +309,12 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     for (int i = 0; i < na && n < limit; ++i) {
         const ttx_config& c = all[i];
         if (c.flags & TTX_CFG_XCD_SWIZZLE) continue;
-        if (batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0) < 0 &&
-            batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) < 0)
+        if (config_is_staged(c)) {
+            if (staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b) < 0) continue;
+        } else if (batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0) < 0 &&
+                   batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) < 0) {
             continue;
+        }
         out[n++] = c;
     }
     return n;

@@ -56,18 +56,25 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
                                const void* Bsrc, void* Bdst, double alpha, double beta,
                                hipStream_t stream) {
     TileArgs<T> a;
-    int64_t s[4];
-    build_grid(p, c, &a.g, s);
+    build_grid(p, c, &a);
     a.A = static_cast<const T*>(A);
     a.Bsrc = static_cast<const T*>(Bsrc);
     a.Bdst = static_cast<T*>(Bdst);
     a.alpha = T(alpha);
     a.beta = T(beta);
-    a.sAa = s[0];
-    a.sAb = s[1];
-    a.sBa = s[2];
-    a.sBb = s[3];
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    if (config_is_staged(c)) {
+        const StagedRow* rows;
+        const int nr = staged_rows(p.dtype, beta0, &rows);
+        const int lanes = staged_lanes(p.dim[0].size);
+        for (int i = 0; i < nr; ++i) {
+            if (rows[i].n0_max == lanes && rows[i].tx == c.tile_a && rows[i].ty == c.tile_b) {
+                uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
+                return rows[i].fn(&a, grid, stream);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     const LauncherRow* table;
     int n;
     if (p.family == TTX_FAMILY_MOVED) {
@@ -114,6 +121,9 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
         const int va = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
         const int vb = (f & KF_VEC_B) && c.tile_b % V == 0 ? V : 1;
         std::snprintf(buf, sizeof(buf), "k_moved<%s, %s, %d, %d, %d, %d>", t, z, c.tile_a, c.tile_b, va, vb);
+    } else if (config_is_staged(c)) {
+        std::snprintf(buf, sizeof(buf), "k_staged<%s, %s, %d, %d, %d>", t, z, staged_lanes(p.dim[0].size),
+                      c.tile_a, c.tile_b);
     } else {
         const int v = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
         std::snprintf(buf, sizeof(buf), "k_preserved<%s, %s, %d, %d, %d>", t, z, c.tile_a, c.tile_b, v);

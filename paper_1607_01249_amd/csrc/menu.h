@@ -29,17 +29,33 @@
     X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
     X(256, 4) X(256, 16) X(2, 512) X(4, 256)
 
+// Staged preserved-family tiles, for short stride-1 rows: X(n0_max, tile_x,
+// tile_y) with n0_max lanes per row (rows of n0 <= n0_max elements), tile_x
+// rows along A's next indices and tile_y along B's next indices.
+#define TTX_STAGED_MENU_F32(X)                                                            \
+    X(16, 16, 16) X(16, 8, 32) X(16, 32, 8) X(32, 8, 16) X(32, 16, 8) X(32, 4, 32)        \
+    X(32, 32, 4) X(32, 8, 8) X(64, 8, 8) X(64, 4, 16) X(64, 16, 4) X(64, 4, 4)
+
+#define TTX_STAGED_MENU_F64(X)                                                            \
+    X(16, 16, 8) X(16, 8, 16) X(16, 4, 32) X(16, 32, 4) X(32, 8, 8) X(32, 4, 16)          \
+    X(32, 16, 4) X(32, 2, 32) X(32, 32, 2) X(64, 4, 8) X(64, 8, 4) X(64, 4, 4)
+
 // Tile variants compiled into the persistent batched kernel, per dtype:
-// X(index, family, tile_a, tile_b, vector) where vector = 1 means 16-byte
-// accesses on both sides.  Kept small: every variant adds code to the one
-// kernel and its register and LDS needs set the kernel's occupancy.
+// X(index, kind, p1, p2, p3).  For the moved, preserved and flat kinds
+// (TTX_FAMILY_*) p1 x p2 is the tile and p3 = 1 selects 16-byte accesses on
+// both sides; for TTX_BATCH_STAGED p1 is the row-lane count and p2 x p3 the
+// staged tile.  Kept small: every variant adds code to the one kernel and
+// its register and LDS needs set the kernel's occupancy.
+#define TTX_BATCH_STAGED 4
+
 #define TTX_BATCH_MENU_F32(X)                                                             \
     X(0, TTX_FAMILY_MOVED, 64, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
     X(2, TTX_FAMILY_MOVED, 64, 64, 0) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
     X(4, TTX_FAMILY_MOVED, 8, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 8, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 1024, 1, 1)               \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0)
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 16, 16)                 \
+    X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)
 
 #define TTX_BATCH_MENU_F64(X)                                                             \
     X(0, TTX_FAMILY_MOVED, 32, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
@@ -47,6 +63,7 @@
     X(4, TTX_FAMILY_MOVED, 4, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 4, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 512, 1, 1)                \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0)
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 16, 8)                  \
+    X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)
 
-#define TTX_BATCH_MENU_SIZE 11
+#define TTX_BATCH_MENU_SIZE 14

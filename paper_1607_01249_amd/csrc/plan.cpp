@@ -40,6 +40,33 @@ int tile_menu(int dtype, int family, const TileShape** shapes) {
     return 0;
 }
 
+#define TTX_STAGED(n0, tx, ty) {n0, tx, ty},
+struct StagedShape { int n0, tx, ty; };
+static const StagedShape kStagedF32[] = {TTX_STAGED_MENU_F32(TTX_STAGED)};
+static const StagedShape kStagedF64[] = {TTX_STAGED_MENU_F64(TTX_STAGED)};
+#undef TTX_STAGED
+
+int staged_lanes(int64_t n0) {
+    if (n0 <= 16) return 16;
+    if (n0 <= 32) return 32;
+    if (n0 <= 64) return 64;
+    return 0;
+}
+
+static int staged_menu(int dtype, const StagedShape** out) {
+    *out = dtype == TTX_F32 ? kStagedF32 : kStagedF64;
+    return dtype == TTX_F32 ? int(sizeof(kStagedF32) / sizeof(StagedShape))
+                            : int(sizeof(kStagedF64) / sizeof(StagedShape));
+}
+
+bool staged_in_menu(int dtype, int n0_max, int tx, int ty) {
+    const StagedShape* m;
+    const int n = staged_menu(dtype, &m);
+    for (int i = 0; i < n; ++i)
+        if (m[i].n0 == n0_max && m[i].tx == tx && m[i].ty == ty) return true;
+    return false;
+}
+
 bool tile_in_menu(int dtype, int family, int ta, int tb) {
     const TileShape* s;
     int n = tile_menu(dtype, family, &s);
@@ -164,11 +191,142 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
     return TTX_OK;
 }
 
-// The two merged indices that span a tile: A's stride-1 index and, for the
-// moved family, B's stride-1 index; for the preserved family, B's second index.
-static void tile_dims(const Problem& p, int* a, int* b) {
-    *a = 0;
-    *b = p.family == TTX_FAMILY_MOVED ? p.perm[0] : (p.n > 1 ? p.perm[1] : 0);
+// ---------------------------------------------------------------------------------------
+// Tile layout.  A moved-family tile spans two "super indices": the A side is
+// the first ga merged indices (consecutive in A and contiguous there, so the
+// tile reads runs of TA elements across all of them), the B side the first
+// gb indices in B's order (contiguous in B).  With ga = gb = 1 this is the
+// 2D macro-tile of Sec. 2.2; larger groups keep tiles full when the stride-1
+// extents are short (e.g. 24 x 17 for a 6D reversal).  The preserved family
+// tiles A's stride-1 index against B's second index; flat has one index.
+struct Layout {
+    int a = 0, b = 0;                 // leaders (merged index numbers)
+    int ga = 1, gb = 1;
+    bool staged = false;              // preserved family with short rows: staged tiles
+    int memA[kMaxGroup] = {}, memB[kMaxGroup] = {};
+    int64_t SA = 1, SB = 1;           // super extents
+    bool member[kMaxDims] = {};       // non-leader group members: not grid indices
+};
+
+static bool make_layout(const Problem& p, int ga, int gb, Layout* L) {
+    L->ga = ga < 1 ? 1 : ga;
+    L->gb = gb < 1 ? 1 : gb;
+    L->a = 0;
+    if (p.family == TTX_FAMILY_FLAT) {
+        L->b = 0;
+        L->SA = L->SB = p.dim[0].size;
+        return L->ga == 1 && L->gb == 1;
+    }
+    if (p.family == TTX_FAMILY_PRESERVED && L->ga == 1 && L->gb == 1) {
+        L->b = p.perm[1];
+        L->SA = p.dim[0].size;
+        L->SB = p.dim[L->b].size;
+        return true;
+    }
+    if (p.family == TTX_FAMILY_PRESERVED) {
+        // staged: A's indices 1..ga-1 (contiguous in A after the row index) and
+        // B's indices perm[1..gb-1] (contiguous in B after it) span the tile;
+        // the row index 0 lies wholly inside every tile
+        if (L->ga < 2 || L->gb < 2 || L->ga > kMaxGroup + 1 || L->gb > kMaxGroup + 1) return false;
+        if (L->ga > p.n || L->gb > p.n || staged_lanes(p.dim[0].size) == 0) return false;
+        bool inA[kMaxDims] = {};
+        L->SA = 1;
+        for (int k = 1; k < L->ga; ++k) {
+            if (p.dim[k].sa != p.dim[k - 1].sa * p.dim[k - 1].size) return false;
+            L->memA[k - 1] = k;
+            inA[k] = true;
+            L->SA *= p.dim[k].size;
+        }
+        L->SB = 1;
+        for (int k = 1; k < L->gb; ++k) {
+            const int d = p.perm[k], prev = p.perm[k - 1];
+            if (inA[d] || p.dim[d].sb != p.dim[prev].sb * p.dim[prev].size) return false;
+            L->memB[k - 1] = d;
+            L->SB *= p.dim[d].size;
+        }
+        if (L->SA >= (int64_t(1) << 31) || L->SB >= (int64_t(1) << 31)) return false;
+        L->staged = true;
+        L->a = 1;
+        L->b = p.perm[1];
+        L->member[0] = true;
+        for (int k = 1; k < L->ga - 1; ++k) L->member[L->memA[k]] = true;
+        for (int k = 1; k < L->gb - 1; ++k) L->member[L->memB[k]] = true;
+        return true;
+    }
+    if (L->ga > kMaxGroup || L->gb > kMaxGroup || L->ga > p.n || L->gb > p.n) return false;
+    bool inA[kMaxDims] = {};
+    L->SA = 1;
+    for (int k = 0; k < L->ga; ++k) {
+        const int d = k;   // A's first ga indices
+        if (k > 0 && p.dim[d].sa != p.dim[d - 1].sa * p.dim[d - 1].size) return false;
+        L->memA[k] = d;
+        inA[d] = true;
+        L->SA *= p.dim[d].size;
+    }
+    L->SB = 1;
+    for (int k = 0; k < L->gb; ++k) {
+        const int d = p.perm[k];   // B's first gb indices
+        if (inA[d]) return false;
+        if (k > 0) {
+            const int prev = p.perm[k - 1];
+            if (p.dim[d].sb != p.dim[prev].sb * p.dim[prev].size) return false;
+        }
+        L->memB[k] = d;
+        L->SB *= p.dim[d].size;
+    }
+    // digits are extracted with 32-bit divisions when a group has several members
+    if ((L->ga > 1 && L->SA >= (int64_t(1) << 31)) || (L->gb > 1 && L->SB >= (int64_t(1) << 31)))
+        return false;
+    L->b = p.perm[0];
+    for (int k = 1; k < L->ga; ++k) L->member[L->memA[k]] = true;
+    for (int k = 1; k < L->gb; ++k) L->member[L->memB[k]] = true;
+    return true;
+}
+
+// Group sizes worth considering: a group grows only while its super extent
+// is still short of a full tile edge (< 64 elements).
+static std::vector<std::pair<int, int>> group_options(const Problem& p) {
+    std::vector<std::pair<int, int>> out;
+    if (p.family == TTX_FAMILY_PRESERVED) {
+        out.push_back({1, 1});
+        // staged tiles for rows shorter than a 256-byte run; each side grows
+        // while its run (row length times the rows fused so far) is short
+        const int64_t n0 = p.dim[0].size;
+        if (n0 * elem_bytes(p.dtype) >= 256 || staged_lanes(n0) == 0) return out;
+        for (int ga = 2; ga <= kMaxGroup + 1; ++ga)
+            for (int gb = 2; gb <= kMaxGroup + 1; ++gb) {
+                Layout L;
+                if (!make_layout(p, ga, gb, &L)) continue;
+                if (ga > 2 && n0 * (L.SA / p.dim[L.memA[ga - 2]].size) >= 256) continue;
+                if (gb > 2 && n0 * (L.SB / p.dim[L.memB[gb - 2]].size) >= 256) continue;
+                out.push_back({ga, gb});
+            }
+        return out;
+    }
+    if (p.family != TTX_FAMILY_MOVED) {
+        out.push_back({1, 1});
+        return out;
+    }
+    for (int ga = 1; ga <= kMaxGroup; ++ga)
+        for (int gb = 1; gb <= kMaxGroup; ++gb) {
+            Layout L;
+            if (!make_layout(p, ga, gb, &L)) continue;
+            if (ga > 1 && L.SA / p.dim[L.memA[ga - 1]].size >= 64) continue;
+            if (gb > 1 && L.SB / p.dim[L.memB[gb - 1]].size >= 64) continue;
+            out.push_back({ga, gb});
+        }
+    return out;
+}
+
+static Group make_group(const Problem& p, const int* members, int ng, bool strides_of_a) {
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.ng = ng;
+    for (int k = 0; k < ng; ++k) {
+        if (k + 1 < ng) g.div[k].init(uint32_t(p.dim[members[k]].size));
+        g.stride[k] = strides_of_a ? p.dim[members[k]].sa : p.dim[members[k]].sb;
+    }
+    return g;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -189,46 +347,80 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
             return bad("order is not a permutation of the merged indices");
         seen[c.order[i]] = true;
     }
+    Layout L;
+    if (!make_layout(p, c.group_a, c.group_b, &L)) return bad("invalid index groups for this problem");
     if (p.family == TTX_FAMILY_FLAT) return true;
-    if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b)) return bad("tile shape not in menu");
+    if (L.staged) {
+        if (!staged_in_menu(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b))
+            return bad("staged tile shape not in menu");
+    } else if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b)) {
+        return bad("tile shape not in menu");
+    }
     // the tile id space must fit 32 bits
-    int a, b;
-    tile_dims(p, &a, &b);
-    uint64_t tiles = 1;
+    uint64_t tiles = uint64_t((L.SA + c.tile_a - 1) / c.tile_a) * uint64_t((L.SB + c.tile_b - 1) / c.tile_b);
     for (int d = 0; d < p.n; ++d) {
-        int64_t ext = d == a ? c.tile_a : d == b ? c.tile_b : 1;
-        tiles *= uint64_t((p.dim[d].size + ext - 1) / ext);
+        if (d == L.a || d == L.b || L.member[d]) continue;
+        tiles *= uint64_t(p.dim[d].size);
         if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
     }
+    if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
     return true;
 }
 
-void build_grid(const Problem& p, const ttx_config& c, TileGrid* g, int64_t s[4]) {
-    int a, b;
-    tile_dims(p, &a, &b);
+void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
+    Layout L;
+    make_layout(p, c.group_a, c.group_b, &L);
+    TileGrid* g = &h->g;
     std::memset(g, 0, sizeof(*g));
-    g->nd = p.n;
     g->pa = g->pb = -1;
+    const bool moved = p.family == TTX_FAMILY_MOVED || L.staged;
     uint64_t tiles = 1;
-    for (int q = 0; q < p.n; ++q) {
-        int d = c.order[q];
-        int64_t ext = d == a ? c.tile_a : d == b ? c.tile_b : 1;
-        uint32_t cnt = uint32_t((p.dim[d].size + ext - 1) / ext);
+    int q = 0;
+    for (int i = 0; i < p.n; ++i) {
+        const int d = c.order[i];
+        if (L.member[d]) continue;
+        int64_t ext = 1, extent = p.dim[d].size;
+        int64_t stepA, stepB;
+        if (d == L.a) {
+            ext = c.tile_a;
+            extent = L.SA;
+        } else if (d == L.b) {
+            ext = c.tile_b;
+            extent = L.SB;
+        }
+        stepA = ext * p.dim[d].sa;
+        stepB = ext * p.dim[d].sb;
+        // moved tiles add the group offsets of their absolute coordinates in
+        // the body, so the cross terms are left out of the origin here
+        if (moved && d == L.a) stepB = 0;
+        if (moved && d == L.b) stepA = 0;
+        const uint32_t cnt = uint32_t((extent + ext - 1) / ext);
         g->count[q] = cnt;
         g->div[q].init(cnt);
-        g->stepA[q] = ext * p.dim[d].sa;
-        g->stepB[q] = ext * p.dim[d].sb;
-        if (d == a) g->pa = q;
-        if (d == b) g->pb = q;
+        g->stepA[q] = stepA;
+        g->stepB[q] = stepB;
+        if (d == L.a) g->pa = q;
+        if (d == L.b) g->pb = q;
         tiles *= cnt;
+        ++q;
     }
+    g->nd = q;
     g->ntiles = uint32_t(tiles);
-    g->ext_a = p.dim[a].size;
-    g->ext_b = p.dim[b].size;
-    s[0] = p.dim[a].sa;
-    s[1] = p.dim[b].sa;
-    s[2] = p.dim[a].sb;
-    s[3] = p.dim[b].sb;
+    g->ext_a = L.SA;
+    g->ext_b = L.SB;
+    h->sAa = p.dim[L.a].sa;
+    h->sAb = p.dim[L.b].sa;
+    h->sBa = p.dim[L.a].sb;
+    h->sBb = p.dim[L.b].sb;
+    h->gA = make_group(p, L.memA, L.staged ? L.ga - 1 : (moved ? L.ga : 1), false);   // B offsets of the A side
+    h->gB = make_group(p, L.memB, L.staged ? L.gb - 1 : (moved ? L.gb : 1), true);    // A offsets of the B side
+    if (!moved) {
+        h->gA.stride[0] = p.dim[L.a].sb;
+        h->gB.stride[0] = p.dim[L.b].sa;
+    }
+    h->s0A = p.dim[0].sa;
+    h->s0B = p.dim[0].sb;
+    h->n0 = int(p.dim[0].size);
 }
 
 static bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
@@ -244,28 +436,30 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
         if (p.dim[0].sa == 1 && p.dim[0].sb == 1 && aligned16(A) && bptrs) f |= KF_VEC_A;
         return f;
     }
-    int a, b;
-    tile_dims(p, &a, &b);
-    auto multiples = [&](bool use_a, int skip) {
-        for (int d = 0; d < p.n; ++d) {
-            if (d == skip) continue;
-            int64_t s = use_a ? p.dim[d].sa : p.dim[d].sb;
-            if (s % V) return false;
-        }
-        return true;
-    };
-    if (p.family == TTX_FAMILY_MOVED) {
-        if (p.dim[a].sa == 1 && c.tile_a % V == 0 && p.dim[a].size % V == 0 && aligned16(A) &&
-            multiples(true, a))
-            f |= KF_VEC_A;
-        if (p.dim[b].sb == 1 && c.tile_b % V == 0 && p.dim[b].size % V == 0 && bptrs &&
-            multiples(false, b))
-            f |= KF_VEC_B;
-    } else {  // preserved: rows contiguous in both tensors
-        if (p.dim[a].sa == 1 && p.dim[a].sb == 1 && c.tile_a % V == 0 && p.dim[a].size % V == 0 &&
-            aligned16(A) && bptrs && multiples(true, a) && multiples(false, a))
-            f |= KF_VEC_A | KF_VEC_B;
+    Layout L;
+    if (!make_layout(p, c.group_a, c.group_b, &L)) return f;
+    bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
+    for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
+    for (int k = 0; k < L.gb; ++k) inB[L.memB[k]] = true;
+    if (L.staged) return f;   // staged tiles move single elements
+    if (p.family == TTX_FAMILY_PRESERVED) {
+        inA[0] = inB[0] = true;
+        bool ok = p.dim[0].sa == 1 && p.dim[0].sb == 1 && c.tile_a % V == 0 && p.dim[0].size % V == 0 &&
+                  aligned16(A) && bptrs;
+        for (int d = 1; d < p.n && ok; ++d) ok = p.dim[d].sa % V == 0 && p.dim[d].sb % V == 0;
+        if (ok) f |= KF_VEC_A | KF_VEC_B;
+        return f;
     }
+    // A side: runs along the A-side super index, every other A stride a
+    // multiple of the vector width; B side likewise
+    bool okA = p.dim[L.a].sa == 1 && c.tile_a % V == 0 && L.SA % V == 0 && aligned16(A);
+    for (int d = 0; d < p.n && okA; ++d)
+        if (!inA[d]) okA = p.dim[d].sa % V == 0;
+    bool okB = p.dim[L.b].sb == 1 && c.tile_b % V == 0 && L.SB % V == 0 && bptrs;
+    for (int d = 0; d < p.n && okB; ++d)
+        if (!inB[d]) okB = p.dim[d].sb % V == 0;
+    if (okA) f |= KF_VEC_A;
+    if (okB) f |= KF_VEC_B;
     return f;
 }
 
@@ -292,11 +486,31 @@ static constexpr double kResident = 2048.0;
 
 static double lines(double bytes) { return std::ceil(bytes / kLine) * kLine; }
 
-static double blocking_cost(const Problem& p, int ta, int tb) {
-    int a, b;
-    tile_dims(p, &a, &b);
+// Staged tiles: A runs of n0*x rows, B runs of n0*y rows, n0_max lanes per row.
+static double staged_cost(const Problem& p, const Layout& L, int tx, int ty) {
     const double e = elem_bytes(p.dtype);
-    const int64_t Sa = p.dim[a].size, Sb = p.dim[b].size;
+    const double n0 = double(p.dim[0].size), lanes_row = staged_lanes(p.dim[0].size);
+    double traffic = 0, useful = 0, lanes = 0, work = 0;
+    for (int ix = 0; ix < 2; ++ix)
+        for (int iy = 0; iy < 2; ++iy) {
+            const double cx = ix ? (L.SA % tx ? 1 : 0) : double(L.SA / tx);
+            const double cy = iy ? (L.SB % ty ? 1 : 0) : double(L.SB / ty);
+            const double ex = ix ? double(L.SA % tx) : tx, ey = iy ? double(L.SB % ty) : ty;
+            const double cnt = cx * cy;
+            if (cnt == 0) continue;
+            traffic += cnt * (ey * lines(n0 * ex * e) + ex * lines(n0 * ey * e) + kTileOverhead);
+            useful += cnt * 2.0 * n0 * ex * ey * e;
+            lanes += cnt * lanes_row * tx * ty;
+            work += cnt * n0 * ex * ey;
+        }
+    if (useful == 0) return 1e30;
+    return traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
+}
+
+static double blocking_cost(const Problem& p, const Layout& L, int ta, int tb) {
+    if (L.staged) return staged_cost(p, L, ta, tb);
+    const double e = elem_bytes(p.dtype);
+    const int64_t Sa = L.SA, Sb = L.SB;
     struct Edge { double ext, count; };
     auto edges = [](int64_t S, int t, Edge out[2]) {
         int64_t full = S / t, rem = S % t;
@@ -308,9 +522,9 @@ static double blocking_cost(const Problem& p, int ta, int tb) {
     edges(Sb, tb, eb);
     // other indices multiply every tile count equally; they cancel in the ratio
     const bool moved = p.family == TTX_FAMILY_MOVED;
-    const bool a_cols_adjacent = p.dim[b].sa == Sa * p.dim[a].sa;   // A columns back to back
-    const bool b_rows_adjacent = moved ? p.dim[a].sb == Sb * p.dim[b].sb
-                                       : p.dim[b].sb == Sa * p.dim[a].sb;
+    const bool a_cols_adjacent = p.dim[L.b].sa == Sa * p.dim[L.a].sa;   // A columns back to back
+    const bool b_rows_adjacent = moved ? p.dim[L.a].sb == Sb * p.dim[L.b].sb
+                                       : p.dim[L.b].sb == Sa * p.dim[L.a].sb;
     double traffic = 0, useful = 0, lanes = 0, work = 0;
     for (const Edge& x : ea)
         for (const Edge& y : eb) {
@@ -332,18 +546,40 @@ static double blocking_cost(const Problem& p, int ta, int tb) {
     return traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
 }
 
-static double order_cost(const Problem& p, int ta, int tb, const int* order) {
-    int a, b;
-    tile_dims(p, &a, &b);
+// Grid indices of a layout (leaders and the indices outside both groups).
+static std::vector<int> grid_indices(const Problem& p, const Layout& L) {
+    std::vector<int> g;
+    for (int d = 0; d < p.n; ++d)
+        if (!L.member[d]) g.push_back(d);
+    return g;
+}
+
+static void grid_step(const Problem& p, const Layout& L, int d, int ta, int tb, double* cnt,
+                      double* sA, double* sB) {
+    double ext = 1, extent = double(p.dim[d].size);
+    if (d == L.a) {
+        ext = ta;
+        extent = double(L.SA);
+    } else if (d == L.b) {
+        ext = tb;
+        extent = double(L.SB);
+    }
+    *cnt = std::ceil(extent / ext);
+    *sA = ext * double(p.dim[d].sa);
+    *sB = ext * double(p.dim[d].sb);
+}
+
+static double order_cost(const Problem& p, const Layout& L, int ta, int tb, const int* order, int n) {
     const double e = elem_bytes(p.dtype);
     double resident = 1, spanA = 0, spanB = 0;
-    for (int q = 0; q < p.n && resident < kResident; ++q) {
-        int d = order[q];
-        int64_t ext = d == a ? ta : d == b ? tb : 1;
-        double cnt = double((p.dim[d].size + ext - 1) / ext);
+    for (int q = 0; q < n && resident < kResident; ++q) {
+        const int d = order[q];
+        if (L.member[d]) continue;
+        double cnt, sA, sB;
+        grid_step(p, L, d, ta, tb, &cnt, &sA, &sB);
         double take = std::min(cnt, std::ceil(kResident / resident));
-        spanA += (take - 1) * double(ext) * double(p.dim[d].sa);
-        spanB += (take - 1) * double(ext) * double(p.dim[d].sb);
+        spanA += (take - 1) * sA;
+        spanB += (take - 1) * sB;
         resident *= cnt;
     }
     double tiles = std::min(resident, kResident);
@@ -357,34 +593,40 @@ static double flag_cost(int flags) {
     return 0.001 * ((flags & TTX_CFG_XCD_SWIZZLE) ? 1 : 0) + 0.002 * ((flags & TTX_CFG_NT_STORE) ? 1 : 0);
 }
 
-// Loop orders considered for a problem of merged rank n: all n! when n <= 6
-// (as Sec. 2.2 explores all d! orders), otherwise a few structured ones.
-static std::vector<std::vector<int>> loop_orders(const Problem& p) {
+// Full orders (every merged index) from orders of the grid indices: group
+// members, which the grid skips, are appended in index order.
+static std::vector<std::vector<int>> loop_orders(const Problem& p, const Layout& L) {
     std::vector<std::vector<int>> out;
-    std::vector<int> o(p.n);
-    std::iota(o.begin(), o.end(), 0);
-    if (p.n <= 6) {
-        do out.push_back(o);
+    std::vector<int> g = grid_indices(p, L), tail;
+    for (int d = 0; d < p.n; ++d)
+        if (L.member[d]) tail.push_back(d);
+    auto full = [&](std::vector<int> o) {
+        o.insert(o.end(), tail.begin(), tail.end());
+        return o;
+    };
+    if (g.size() <= 6) {
+        std::vector<int> o = g;
+        do out.push_back(full(o));
         while (std::next_permutation(o.begin(), o.end()));
         return out;
     }
-    int a, b;
-    tile_dims(p, &a, &b);
-    std::vector<int> border(p.perm, p.perm + p.n);
-    out.push_back(o);        // A order
-    out.push_back(border);   // B order
-    for (const auto& base : {o, border}) {
-        std::vector<int> t = {a};
-        if (b != a) t.push_back(b);
+    std::vector<int> border;
+    for (int k = 0; k < p.n; ++k)
+        if (!L.member[p.perm[k]]) border.push_back(p.perm[k]);
+    out.push_back(full(g));
+    out.push_back(full(border));
+    for (const auto& base : {g, border}) {
+        std::vector<int> t = {L.a};
+        if (L.b != L.a) t.push_back(L.b);
         for (int d : base)
-            if (d != a && d != b) t.push_back(d);
-        out.push_back(t);
+            if (d != L.a && d != L.b) t.push_back(d);
+        out.push_back(full(t));
     }
     return out;
 }
 
 static ttx_config make_config(const Problem& p, int ta, int tb, const std::vector<int>& order,
-                              int flags) {
+                              int flags, int ga = 1, int gb = 1) {
     ttx_config c;
     std::memset(&c, 0, sizeof(c));
     c.family = p.family;
@@ -394,7 +636,20 @@ static ttx_config make_config(const Problem& p, int ta, int tb, const std::vecto
     c.n_order = int(order.size());
     for (size_t i = 0; i < order.size(); ++i) c.order[i] = order[i];
     c.flags = flags;
+    c.group_a = ga;
+    c.group_b = gb;
     return c;
+}
+
+// The staged menu's (tile_x, tile_y) shapes for this problem's row length.
+static std::vector<TileShape> staged_shape_list(const Problem& p) {
+    std::vector<TileShape> out;
+    const StagedShape* m;
+    const int n = staged_menu(p.dtype, &m);
+    const int lanes = staged_lanes(p.dim[0].size);
+    for (int i = 0; i < n; ++i)
+        if (m[i].n0 == lanes) out.push_back(TileShape{m[i].tx, m[i].ty});
+    return out;
 }
 
 int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost,
@@ -427,17 +682,30 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
     if (p.family == TTX_FAMILY_FLAT) {
         for (int f : {0, TTX_CFG_NT_STORE}) offer(1.0 + flag_cost(f), make_config(p, 0, 0, {0}, f));
     } else {
-        const TileShape* shapes;
-        int ns = tile_menu(p.dtype, p.family, &shapes);
-        auto orders = loop_orders(p);
-        for (int s = 0; s < ns; ++s) {
-            ttx_config probe = make_config(p, shapes[s].ta, shapes[s].tb, orders[0], 0);
-            if (!config_valid(p, probe, nullptr)) continue;
-            double bc = blocking_cost(p, shapes[s].ta, shapes[s].tb);
-            for (const auto& o : orders) {
-                double oc = order_cost(p, shapes[s].ta, shapes[s].tb, o.data());
-                for (int f : flag_sets)
-                    offer(bc * (1.0 + oc) + flag_cost(f), make_config(p, shapes[s].ta, shapes[s].tb, o, f));
+        const TileShape* menu;
+        const int nmenu = tile_menu(p.dtype, p.family, &menu);
+        for (auto [ga, gb] : group_options(p)) {
+            Layout L;
+            make_layout(p, ga, gb, &L);
+            std::vector<TileShape> staged_shapes;
+            const TileShape* shapes = menu;
+            int ns = nmenu;
+            if (L.staged) {
+                staged_shapes = staged_shape_list(p);
+                shapes = staged_shapes.data();
+                ns = int(staged_shapes.size());
+            }
+            auto orders = loop_orders(p, L);
+            for (int s = 0; s < ns; ++s) {
+                ttx_config probe = make_config(p, shapes[s].ta, shapes[s].tb, orders[0], 0, ga, gb);
+                if (!config_valid(p, probe, nullptr)) continue;
+                double bc = blocking_cost(p, L, shapes[s].ta, shapes[s].tb);
+                for (const auto& o : orders) {
+                    double oc = order_cost(p, L, shapes[s].ta, shapes[s].tb, o.data(), p.n);
+                    for (int f : flag_sets)
+                        offer(bc * (1.0 + oc) + flag_cost(f),
+                              make_config(p, shapes[s].ta, shapes[s].tb, o, f, ga, gb));
+                }
             }
         }
     }
@@ -455,38 +723,60 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
     return n;
 }
 
-ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns) {
+ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
+                               const TileShape* staged, int nstaged) {
     ttx_config best;
     std::memset(&best, 0, sizeof(best));
     best.family = p.family;
     best.threads = kThreads;
+    best.group_a = best.group_b = 1;
     if (p.family == TTX_FAMILY_EMPTY) return best;
     if (p.family == TTX_FAMILY_FLAT) {
         best.n_order = 1;
         best.order[0] = 0;
         return best;
     }
-    // Greedy use of both heuristics: the cheapest tile shape, then the
-    // indices sorted by the span one step covers (smallest first).
-    int a, b;
-    tile_dims(p, &a, &b);
+    // Greedy use of both heuristics: the cheapest groups and tile shape, then
+    // the grid indices sorted by the span one step covers (smallest first).
     double bestc = 1e300;
-    for (int s = 0; s < ns; ++s) {
-        std::vector<int> o(p.n);
-        std::iota(o.begin(), o.end(), 0);
-        const int ta = shapes[s].ta, tb = shapes[s].tb;
-        auto span = [&](int d) {
-            int64_t ext = d == a ? ta : d == b ? tb : 1;
-            return double(ext) * double(p.dim[d].sa + p.dim[d].sb);
-        };
-        std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
-        ttx_config c = make_config(p, ta, tb, o, 0);
-        // shapes outside the per-call menu (batched-kernel variants) are checked by their caller
-        if (tile_in_menu(p.dtype, p.family, ta, tb) && !config_valid(p, c, nullptr)) continue;
-        double cost = blocking_cost(p, ta, tb) * (1.0 + order_cost(p, ta, tb, o.data()));
-        if (cost < bestc) {
-            bestc = cost;
-            best = c;
+    for (auto [ga, gb] : group_options(p)) {
+        Layout L;
+        make_layout(p, ga, gb, &L);
+        std::vector<int> tail;
+        for (int d = 0; d < p.n; ++d)
+            if (L.member[d]) tail.push_back(d);
+        std::vector<TileShape> own;
+        const TileShape* sh = shapes;
+        int nsh = ns;
+        if (L.staged) {
+            if (nstaged < 0) {
+                own = staged_shape_list(p);
+            } else {
+                const int lanes = staged_lanes(p.dim[0].size);
+                for (int i = 0; i < nstaged; ++i)   // (lanes, tx, ty) packed as {lanes*65536 + tx, ty}
+                    if (staged[i].ta >> 16 == lanes) own.push_back(TileShape{staged[i].ta & 0xffff, staged[i].tb});
+            }
+            sh = own.data();
+            nsh = int(own.size());
+        }
+        for (int s = 0; s < nsh; ++s) {
+            const int ta = sh[s].ta, tb = sh[s].tb;
+            std::vector<int> o = grid_indices(p, L);
+            auto span = [&](int d) {
+                double cnt, sA, sB;
+                grid_step(p, L, d, ta, tb, &cnt, &sA, &sB);
+                return sA + sB;
+            };
+            std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
+            o.insert(o.end(), tail.begin(), tail.end());
+            ttx_config c = make_config(p, ta, tb, o, 0, ga, gb);
+            // shapes outside the per-call menu (batched-kernel variants) are checked by their caller
+            if ((L.staged || tile_in_menu(p.dtype, p.family, ta, tb)) && !config_valid(p, c, nullptr)) continue;
+            double cost = blocking_cost(p, L, ta, tb) * (1.0 + order_cost(p, L, ta, tb, o.data(), p.n));
+            if (cost < bestc) {
+                bestc = cost;
+                best = c;
+            }
         }
     }
     return best;
@@ -495,7 +785,7 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
 ttx_config default_config(const Problem& p) {
     const TileShape* shapes;
     int ns = tile_menu(p.dtype, p.family, &shapes);
-    return default_config_from(p, shapes, ns);
+    return default_config_from(p, shapes, ns, nullptr, -1);
 }
 
 }  // namespace ttx

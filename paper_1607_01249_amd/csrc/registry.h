@@ -22,4 +22,10 @@ int moved_rows_f64_beta(const LauncherRow** out);
 int moved_rows_f64_beta0(const LauncherRow** out);
 int preserved_rows(int dtype, bool beta0, const LauncherRow** out);
 
+struct StagedRow {
+    int n0_max, tx, ty;
+    TileLaunchFn fn;
+};
+int staged_rows(int dtype, bool beta0, const StagedRow** out);
+
 }  // namespace ttx

@@ -95,13 +95,14 @@ __device__ __forceinline__ uint32_t swizzle_id(uint32_t bid, uint32_t G) {
 }
 
 struct TileCoord {
-    int64_t oa, ob;
-    int ea, eb;
+    int64_t oa, ob;     // origin offsets (moved family: without the group cross terms)
+    int64_t x0, y0;     // origin along the two tile (super) indices
+    int ea, eb;         // extents of this (maybe edge) tile
 };
 
 // Tile id -> origin offsets in A and B and the extents of this (maybe edge) tile.
 __device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, int TA, int TB) {
-    TileCoord c{0, 0, TA, TB};
+    TileCoord c{0, 0, 0, 0, TA, TB};
     uint32_t rem = t;
     for (int q = 0; q < g.nd; ++q) {
         const uint32_t next = g.div[q].div(rem);
@@ -109,8 +110,14 @@ __device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, 
         rem = next;
         c.oa += int64_t(r) * g.stepA[q];
         c.ob += int64_t(r) * g.stepB[q];
-        if (q == g.pa) c.ea = int(min(int64_t(TA), g.ext_a - int64_t(r) * TA));
-        if (q == g.pb) c.eb = int(min(int64_t(TB), g.ext_b - int64_t(r) * TB));
+        if (q == g.pa) {
+            c.x0 = int64_t(r) * TA;
+            c.ea = int(min(int64_t(TA), g.ext_a - c.x0));
+        }
+        if (q == g.pb) {
+            c.y0 = int64_t(r) * TB;
+            c.eb = int(min(int64_t(TB), g.ext_b - c.y0));
+        }
     }
     return c;
 }
@@ -126,10 +133,13 @@ constexpr int pow2_ceil(int x) {
 // TA / V is not a power of two), so NT / P runs are handled per pass and a
 // thread's address advances by a fixed stride from one pass to the next.
 
-// One moved-family tile: A[oa + x*sAa + y*sAb] -> B[ob + y*sBb + x*sBa] for
-// x < ea (A's stride-1 index), y < eb (B's stride-1 index).  VA / VB are the
-// vector widths along x in A and along y in B (VA > 1 implies sAa == 1,
-// VB > 1 implies sBb == 1).  `lds` holds TB rows of TA + 1 elements.
+// One moved-family tile over the A-side super index x (A's first group_a
+// indices, contiguous in A) and the B-side super index y (B's first group_b
+// indices, contiguous in B): element (x0 + x, y0 + y) for x < ea, y < eb is
+// A[oa + x*sAa + gB.offset(y0 + y)] -> B[ob + y*sBb + gA.offset(x0 + x)].
+// VA / VB are the vector widths along x in A and along y in B (VA > 1
+// implies sAa == 1, VB > 1 implies sBb == 1).  `lds` holds TB rows of
+// TA + 1 elements.
 template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
 __device__ __forceinline__ void moved_tile(T* __restrict__ lds, const TileArgs<T>& a,
                                            const TileCoord& c) {
@@ -144,26 +154,25 @@ __device__ __forceinline__ void moved_tile(T* __restrict__ lds, const TileArgs<T
     const int xa = (tid % PA) * VA, ya = tid / PA;
     const bool lane_a = (tid % PA) < LA;
     const bool live_a = lane_a && xa < c.ea;
-    const T* pa = a.A + c.oa + int64_t(xa) * a.sAa + int64_t(ya) * a.sAb;
-    const int64_t step_a = int64_t(RA) * a.sAb;
+    const T* pa = a.A + c.oa + int64_t(xa) * a.sAa;
 
     // B side: rows (fixed x) of TB elements along y.
     constexpr int LB = TB / VB, PB = pow2_ceil(LB), RB = NT / PB, NB = (TA + RB - 1) / RB;
     static_assert(PB <= NT, "tile edge too long for the workgroup");
     const int yb = (tid % PB) * VB, xb = tid / PB;
     const bool live_b = (tid % PB) < LB && yb < c.eb;
-    const int64_t off_b = c.ob + int64_t(yb) * a.sBb + int64_t(xb) * a.sBa;
-    const int64_t step_b = int64_t(RB) * a.sBa;
+    const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
 
     vec_t<T, VA> ra[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i)
-        if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + i * step_a);
+        if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
     vec_t<T, VB> rb[NB];
     if constexpr (!BETA0) {
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (live_b && xb + i * RB < c.ea) rb[i] = ld<T, VB>(a.Bsrc + off_b + i * step_b);
+            if (live_b && xb + i * RB < c.ea)
+                rb[i] = ld<T, VB>(a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB));
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -182,7 +191,7 @@ __device__ __forceinline__ void moved_tile(T* __restrict__ lds, const TileArgs<T
 #pragma unroll
             for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
             vec_t<T, VB> o = epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta);
-            st<T, VB>(a.Bdst + off_b + i * step_b, o, nt);
+            st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), o, nt);
         }
     }
     __syncthreads();  // the next tile reuses the LDS buffer
@@ -218,6 +227,79 @@ __device__ __forceinline__ void preserved_tile(const TileArgs<T>& a, const TileC
             vec_t<T, V> o = epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta);
             st<T, V>(a.Bdst + off_b + i * step_b, o, nt);
         }
+    }
+}
+
+// One staged preserved-family tile, for short stride-1 rows: rows of n0
+// (<= N0) elements are contiguous in both tensors; the tile holds TX rows
+// along A's super index x (A's indices after the row index, contiguous in A)
+// for each of TY rows along B's super index y (B's indices after the row
+// index, contiguous in B).  Element (i, x0 + x, y0 + y) is
+//   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
+// A is read in runs of n0*TX elements and B written in runs of n0*TY; the
+// tile passes through LDS as [y][x][i] (row length TX*N0 + 1).
+template <typename T, bool BETA0, int N0, int TX, int TY>
+__device__ __forceinline__ void staged_tile(T* __restrict__ lds, const TileArgs<T>& a,
+                                            const TileCoord& c) {
+    constexpr int NT = kThreads;
+    constexpr int LDR = TX * N0 + 1;
+    // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
+    constexpr int PA = N0 * TX, PB = N0 * TY;
+    constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
+    static_assert((N0 & (N0 - 1)) == 0 && (PA & (PA - 1)) == 0 && (PB & (PB - 1)) == 0, "powers of two");
+    static_assert(PA * TY % NT == 0, "whole passes");
+    const int tid = threadIdx.x;
+    const int n0 = a.n0;
+    const bool nt = a.flags & KF_NT_STORE;
+    const T* A0 = a.A + c.oa;
+
+    T ra[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int e = tid + i * NT, r = e % PA, y = e / PA;
+        const int iv = r % N0, x = r / N0;
+        if (iv < n0 && x < c.ea && y < c.eb)
+            ra[i] = A0[int64_t(iv) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y)];
+    }
+    T rb[NB];
+    if constexpr (!BETA0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * NT, r = e % PB, x = e / PB;
+            const int iv = r % N0, y = r / N0;
+            if (iv < n0 && y < c.eb && x < c.ea)
+                rb[i] = a.Bsrc[c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x)];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int e = tid + i * NT, r = e % PA, y = e / PA;
+        const int iv = r % N0, x = r / N0;
+        if (iv < n0) lds[y * LDR + x * N0 + iv] = ra[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int e = tid + i * NT, r = e % PB, x = e / PB;
+        const int iv = r % N0, y = r / N0;
+        if (iv < n0 && y < c.eb && x < c.ea) {
+            const T v = lds[y * LDR + x * N0 + iv];
+            const T o = epilogue<T, 1, BETA0>(v, rb[i], a.alpha, a.beta);
+            st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x), o, nt);
+        }
+    }
+    __syncthreads();  // the next tile reuses the LDS buffer
+}
+
+template <typename T, bool BETA0, int N0, int TX, int TY>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_staged(TileArgs<T> a) {
+    __shared__ T lds[TY * (TX * N0 + 1)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    for (uint32_t t = first; t < a.g.ntiles; t += G) {
+        const TileCoord c = decode_tile(a.g, t, TX, TY);
+        staged_tile<T, BETA0, N0, TX, TY>(lds, a, c);
     }
 }
 

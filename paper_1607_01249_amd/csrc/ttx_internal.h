@@ -62,16 +62,47 @@ enum : int {
     KF_SWIZZLE = 8,    // XCD-aware tile id mapping
 };
 
+// A super index: ng consecutive merged indices tiled as one.  The offset of
+// position y in the other tensor is sum_k digit_k(y) * stride[k] with
+// digit_k = (y / prod_{j<k} size_j) % size_k (index 0 fastest).  With several
+// members the extent is below 2^31 and digits come from 32-bit divisions.
+constexpr int kMaxGroup = 4;
+struct Group {
+    int ng;
+    FastDiv div[kMaxGroup - 1];   // sizes of all members but the last
+    int64_t stride[kMaxGroup];
+
+    __host__ __device__ __forceinline__ int64_t offset(int64_t y) const {
+        if (ng == 1) return y * stride[0];
+        uint32_t rem = uint32_t(y);
+        int64_t off = 0;
+        for (int k = 0; k + 1 < ng; ++k) {
+            const uint32_t q = div[k].div(rem);
+            off += int64_t(rem - q * div[k].d) * stride[k];
+            rem = q;
+        }
+        return off + int64_t(rem) * stride[ng - 1];
+    }
+};
+
+// The dtype-independent part of a tile kernel's arguments (built by the planner).
+struct TileArgsHost {
+    TileGrid g;
+    int64_t sAa, sAb;   // A strides of the two tile (leader) indices
+    int64_t sBa, sBb;   // B strides of the two tile (leader) indices
+    Group gA;           // B offsets of the A-side super index (moved and staged tiles)
+    Group gB;           // A offsets of the B-side super index (moved and staged tiles)
+    int64_t s0A, s0B;   // staged tiles: strides of the shared row index in A and B
+    int n0;             // staged tiles: row length
+};
+
 template <typename T>
-struct TileArgs {
+struct TileArgs : TileArgsHost {
     const T* A;
     const T* Bsrc;      // read when beta != 0
     T* Bdst;
     T alpha, beta;
-    int64_t sAa, sAb;   // A strides of the two tile indices
-    int64_t sBa, sBb;   // B strides of the two tile indices
     int flags;
-    TileGrid g;
 };
 
 template <typename T>
@@ -131,12 +162,16 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why);
 // The heuristic default config (best-ranked candidate).
 ttx_config default_config(const Problem& p);
-// The same greedy choice restricted to the given tile shapes.
-ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns);
+// The same greedy choice restricted to the given tile shapes; staged tiles
+// (preserved family, short rows) come from `staged` entries packed as
+// {lanes * 65536 + tile_x, tile_y}, or from the whole staged menu when
+// nstaged < 0.
+ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
+                               const TileShape* staged, int nstaged);
 // Candidate enumeration with estimated costs (sorted ascending).
 int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost, int cap);
-// Builds the kernel-side grid for a config.
-void build_grid(const Problem& p, const ttx_config& c, TileGrid* g, int64_t s[4]);
+// Builds the kernel-side grid, strides and index groups for a config.
+void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h);
 // Flags for the vector paths given the pointers in use.
 int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const void* Bsrc,
                  const void* Bdst);
@@ -144,6 +179,14 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
 // Kernel menu (tile shapes the library instantiates), per dtype and family.
 int tile_menu(int dtype, int family, const TileShape** shapes);
 bool tile_in_menu(int dtype, int family, int ta, int tb);
+// Staged preserved tiles: row-lane count for a row length (16, 32 or 64; 0 if
+// the rows are too long to stage) and whether (n0_max, tx, ty) is instantiated.
+int staged_lanes(int64_t n0);
+bool staged_in_menu(int dtype, int n0_max, int tx, int ty);
+// A preserved-family config with index groups selects the staged tiles.
+inline bool config_is_staged(const ttx_config& c) {
+    return c.family == TTX_FAMILY_PRESERVED && (c.group_a > 1 || c.group_b > 1);
+}
 constexpr int kThreads = 256;
 
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.

@@ -67,14 +67,16 @@ void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec)
 static std::string config_text(const ttx_config& c) {
     std::ostringstream os;
     os << c.family << " " << c.tile_a << " " << c.tile_b << " " << c.threads << " " << c.flags << " "
-       << c.n_order;
+       << c.group_a << " " << c.group_b << " " << c.n_order;
     for (int i = 0; i < c.n_order; ++i) os << " " << c.order[i];
     return os.str();
 }
 
 static bool parse_config(std::istringstream& is, ttx_config* c) {
     std::memset(c, 0, sizeof(*c));
-    if (!(is >> c->family >> c->tile_a >> c->tile_b >> c->threads >> c->flags >> c->n_order)) return false;
+    if (!(is >> c->family >> c->tile_a >> c->tile_b >> c->threads >> c->flags >> c->group_a >> c->group_b >>
+          c->n_order))
+        return false;
     if (c->n_order < 0 || c->n_order > kMaxDims) return false;
     for (int i = 0; i < c->n_order; ++i)
         if (!(is >> c->order[i])) return false;
@@ -209,7 +211,7 @@ ttx_status ttx_tune_table_save(const char* path) {
     std::ofstream f(path);
     if (!f) return fail(TTX_EINVAL, "cannot open tune table for writing");
     std::lock_guard<std::mutex> lock(g_table_mu);
-    f << "# ttx tune table v1: key | family tile_a tile_b threads flags n_order order... | usec\n";
+    f << "# ttx tune table v2: key | family tile_a tile_b threads flags group_a group_b n_order order... | usec\n";
     for (const auto& kv : g_table)
         f << kv.first << " | " << config_text(kv.second.cfg) << " | " << kv.second.usec << "\n";
     return f ? TTX_OK : fail(TTX_EINVAL, "write failed");

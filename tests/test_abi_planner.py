@@ -222,8 +222,11 @@ def test_candidate_list_is_bounded_and_sorted():
     few, few_cost = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=10)
     assert len(few) == 10 and few_cost == cost[:10]
     allc, _ = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=-1, cap=100000)
-    # every menu shape x 4! loop orders x 4 flag sets
-    assert len(allc) == 20 * 24 * 4
+    # every menu shape x 4 flag sets x the loop orders of each index grouping:
+    # 4! orders with single indices, and 3! when B's short stride-1 index (32)
+    # is grouped with the next B index (the grid then has 3 indices)
+    assert len(allc) == 20 * 4 * (24 + 6)
+    assert {(c.group_a, c.group_b) for c in allc} == {(1, 1), (1, 2)}
     for c in cands:
         assert sorted(c.order[:c.n_order]) == [0, 1, 2, 3]
 
@@ -279,7 +282,7 @@ def test_tune_table_roundtrip(tmp_path):
     path = str(tmp_path / "table.txt")
     with open(path, "w") as f:
         f.write("# comment\n")
-        f.write("d0:b1:n3:s96,128,80:p2,1,0:a1,96,12288:o10240,80,1 | 3 32 16 256 1 3 0 2 1 | 12.5\n")
+        f.write("d0:b1:n3:s96,128,80:p2,1,0:a1,96,12288:o10240,80,1 | 3 32 16 256 1 1 1 3 0 2 1 | 12.5\n")
     ttx.ttx_tune_table_load(path)
     assert ttx.ttx_tune_table_size() == 1
     d = _describe(0, (2, 1, 0), (96, 128, 80))

@@ -146,6 +146,15 @@ EDGE = [
     ((0, 2, 1), (2, 300, 301), None, None),
     ((0, 2, 1), (1000, 3, 4), None, None),
     (tuple(reversed(range(16))), (2, 3, 1, 2, 2, 1, 3, 2, 1, 2, 2, 1, 2, 3, 1, 2), None, None),
+    # short stride-1 extents: index groups on the moved side, staged tiles on the kept side
+    ((3, 2, 1, 0), (5, 3, 7, 9), None, None),
+    ((5, 4, 3, 2, 1, 0), (7, 5, 3, 6, 5, 3), None, None),
+    ((2, 3, 0, 1), (3, 11, 7, 13), None, None),
+    ((0, 3, 2, 1), (6, 5, 7, 3), None, None),
+    ((0, 2, 1), (3, 50, 70), None, None),
+    ((0, 5, 1, 4, 2, 3), (24, 5, 4, 3, 17, 3), None, None),
+    ((3, 2, 1, 0), (5, 3, 7, 9), (6, 3, 8, 9), (10, 7, 3, 5)),   # gaps block the groups
+    ((0, 3, 2, 1), (6, 5, 7, 3), (6, 6, 7, 3), None),
     (tuple(range(1, 16)) + (0,), (3,) + (2,) * 15, None, None),
 ]
 
