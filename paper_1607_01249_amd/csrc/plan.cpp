@@ -203,6 +203,8 @@ struct Layout {
     int a = 0, b = 0;                 // leaders (merged index numbers)
     int ga = 1, gb = 1;
     bool staged = false;              // preserved family with short rows: staged tiles
+    // group members: moved layouts list all ga (gb) indices; staged layouts
+    // list the ga - 1 (gb - 1) indices after the shared row index
     int memA[kMaxGroup] = {}, memB[kMaxGroup] = {};
     int64_t SA = 1, SB = 1;           // super extents
     bool member[kMaxDims] = {};       // non-leader group members: not grid indices
@@ -438,10 +440,10 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
     }
     Layout L;
     if (!make_layout(p, c.group_a, c.group_b, &L)) return f;
+    if (L.staged) return f;   // staged tiles move single elements
     bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
     for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
     for (int k = 0; k < L.gb; ++k) inB[L.memB[k]] = true;
-    if (L.staged) return f;   // staged tiles move single elements
     if (p.family == TTX_FAMILY_PRESERVED) {
         inA[0] = inB[0] = true;
         bool ok = p.dim[0].sa == 1 && p.dim[0].sb == 1 && c.tile_a % V == 0 && p.dim[0].size % V == 0 &&

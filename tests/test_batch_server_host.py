@@ -47,9 +47,11 @@ def test_batch_plan_uses_the_batched_menu():
     for q, c, t in zip(qs, cfgs, tiles):
         assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(q.dtype, c.family)], c.as_dict()
         assert c.flags & ttx.CFG_XCD_SWIZZLE == 0
-        # every element is covered: tiles * tile area >= elements
+        # every element is covered: tiles * tile area >= elements (staged
+        # tiles of the kept family also hold whole stride-1 rows)
         n = int(np.prod(list(q.size[:q.n])))
-        assert t >= 1 and t * c.tile_a * max(1, c.tile_b) >= n
+        rows = max(q.size[:q.n]) if (c.family == ttx.FAMILY_PRESERVED and c.group_a > 1) else 1
+        assert t >= 1 and t * c.tile_a * max(1, c.tile_b) * rows >= n
     fams = {c.family for c in cfgs}
     assert fams >= {ttx.FAMILY_MOVED, ttx.FAMILY_PRESERVED, ttx.FAMILY_FLAT}
 
