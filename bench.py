@@ -355,7 +355,7 @@ def bench_batched(torch, ttx, reps=20):
                 batched=dict(GBps=round(nbytes / b_med / 1e9, 1), ms=round(b_med * 1e3, 3),
                              makespan_p50_ms=round(_pct(times, 50) * 1e3, 3),
                              makespan_p99_ms=round(_pct(times, 99) * 1e3, 3),
-                             grid=info["grid"], tiles=info["total_tiles"],
+                             grid=info["grid"], tiles=info["total_tiles"], chunks=info["chunks"],
                              variants=info["variants_used"], tuned=info["tuned"],
                              tune_seconds=round(tune_s, 1), launch="1 persistent kernel per hipGraph replay"),
                 speedup=round(pc_med / b_med, 2))
@@ -437,6 +437,7 @@ def bench_served(torch, ttx, seconds, rate):
     lat = ttx.ttx_replay_sequential(reqs, offsets, scratch.data_ptr(), scratch.numel(),
                                     torch.cuda.current_stream().cuda_stream)
     span = float(np.max(times + lat * 1e-6) - times[0])
+    saturated = bench_saturated(torch, ttx, reqs, meta, scratch)
     del pool, scratch
     return dict(requests=n, rate_per_s=rate, seconds=seconds, algorithmic_bytes=nbytes_total,
                 served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
@@ -447,7 +448,41 @@ def bench_served(torch, ttx, seconds, rate):
                 sequential=dict(GBps=round(nbytes_total / span / 1e9, 1), p50_us=round(_pct(lat, 50), 1),
                                 p99_us=round(_pct(lat, 99), 1), max_us=round(float(np.max(lat)), 1)),
                 throughput_ratio=round(st["throughput_gbps"] / (nbytes_total / span / 1e9), 2),
-                mix_check=dict(compared=checked, bitwise_mismatches=mismatched))
+                mix_check=dict(compared=checked, bitwise_mismatches=mismatched),
+                saturated=saturated)
+
+
+def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
+    """Capacity: the trace's first requests (up to ~8 GB of algorithmic
+    traffic) all arrive at once, through the server and through the
+    sequential per-call loop; throughput = bytes / (last completion - arrival)."""
+    nb = np.array([m[3] * (2 if m[0]["beta"] == 0 else 3) for m in meta], dtype=np.float64)
+    m = int(np.searchsorted(np.cumsum(nb), budget_bytes)) + 1
+    m = max(1, min(m, len(meta)))
+    sub = ttx._ttx.request_array(m)     # zeroed, so the unnamed outer-size fields stay zero
+    for f in reqs.dtype.names:
+        sub[f] = reqs[f][:m]
+    sub["keep_result"] = 0
+    zeros = np.zeros(m, dtype=np.int64)
+    total = float(nb[:m].sum())
+    log("saturated: %d requests at once (%.2f GB)" % (m, total / 1e9))
+    s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
+    try:
+        ttx.ttx_server_replay(s, sub, zeros)
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+    finally:
+        ttx.ttx_server_destroy(s)
+    lat = ttx.ttx_replay_sequential(sub, zeros, scratch.data_ptr(), scratch.numel(),
+                                    torch.cuda.current_stream().cuda_stream)
+    seq_span = float(np.max(lat)) * 1e-6
+    return dict(requests=m, algorithmic_bytes=int(total),
+                served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
+                            p99_us=round(st["p99_us"], 1), batches=st["batches"],
+                            mean_batch=round(st["mean_batch"], 2)),
+                sequential=dict(GBps=round(total / seq_span / 1e9, 1), p50_us=round(_pct(lat, 50), 1),
+                                p99_us=round(_pct(lat, 99), 1)),
+                throughput_ratio=round(st["throughput_gbps"] / (total / seq_span / 1e9), 2))
 
 
 # ---------------------------------------------------------------------------------------

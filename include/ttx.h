@@ -225,6 +225,8 @@ typedef struct ttx_batch_info {
     int tuned;                       /* problems whose config came from tuning */
     int64_t total_tiles;
     int64_t algorithmic_bytes;       /* sum of 2S (beta == 0) or 3S bytes */
+    int64_t chunks;                  /* units of work claimed by the workgroups: runs of up to
+                                        a fixed number of consecutive tiles of one problem */
 } ttx_batch_info;
 
 typedef struct ttx_batch ttx_batch;
@@ -237,7 +239,9 @@ ttx_status ttx_batch_create(ttx_batch **batch, int count, const ttx_problem *pro
  * 16) inside the persistent kernel on scratch buffers, keeps the fastest in
  * a process-wide per-shape table and rebuilds the descriptors.  Blocks. */
 ttx_status ttx_batch_tune(ttx_batch *batch, int max_candidates, int reps);
-/* One graph launch of the persistent kernel on `stream` (captured on first use). */
+/* One graph launch of the persistent kernel on `stream` (captured on first use).
+ * Launches of one batch must not overlap each other (they share the batch's
+ * work counter and outputs): order them on one stream or synchronise. */
 ttx_status ttx_batch_execute(ttx_batch *batch, hipStream_t stream);
 /* The same persistent kernel launched directly (no graph). */
 ttx_status ttx_batch_execute_direct(ttx_batch *batch, hipStream_t stream);

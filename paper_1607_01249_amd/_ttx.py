@@ -66,7 +66,7 @@ class Problem(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int), ("grid", ctypes.c_int), ("variants_used", ctypes.c_int),
-                ("tuned", ctypes.c_int), ("total_tiles", i64), ("algorithmic_bytes", i64)]
+                ("tuned", ctypes.c_int), ("total_tiles", i64), ("algorithmic_bytes", i64), ("chunks", i64)]
 
 
 class Request(ctypes.Structure):
@@ -339,7 +339,7 @@ def ttx_batch_get_info(batch):
     _check(lib().ttx_batch_get_info(batch, ctypes.byref(info)))
     return dict(count=info.count, grid=info.grid, variants_used=info.variants_used,
                 tuned=info.tuned, total_tiles=info.total_tiles,
-                algorithmic_bytes=info.algorithmic_bytes)
+                algorithmic_bytes=info.algorithmic_bytes, chunks=info.chunks)
 
 
 def ttx_batch_config(batch, index):

@@ -24,11 +24,13 @@ struct ttx_batch {
     std::vector<ttx_problem> src;
     std::vector<ttx_config> cfg;
     std::vector<int> forced;
-    std::vector<ttx::BatchDesc> desc;
-    std::vector<uint32_t> prefix;
-    ttx::BatchDesc* d_desc = nullptr;
-    uint32_t* d_prefix = nullptr;
-    uint32_t total = 0;
+    std::vector<ttx::BatchDesc> desc;    // in work order
+    std::vector<uint32_t> chunk_prefix;  // over the work order
+    std::vector<int> order;              // work position -> problem index
+    unsigned char* d_work = nullptr;     // descriptors, chunk prefix, claim counter
+    size_t work_bytes = 0;
+    uint64_t total = 0;                  // tiles
+    uint32_t chunks = 0;
     int grid = 0;
     int64_t bytes = 0;
     hipStream_t cap_stream = nullptr;
@@ -80,76 +82,130 @@ constexpr int batch_lds_bytes() {
 #undef TTX_LDS_F64
 constexpr int kBatchLds = batch_lds_bytes();
 
+// Tiles [t0, t1) of one problem with the variant's tile body, pipelined
+// across the tiles.  Thread 0 also claims the workgroup's next chunk: the
+// claim is issued first, so that its round trip overlaps the chunk, and its
+// result is left in *next (LDS) for the caller's barrier to publish.
+//
+// The body is a separate function so that each variant gets its own register
+// allocation (inlined into one kernel, the variants together need far more
+// registers than any one of them).  A callee cannot see that its arguments
+// are the same in every lane, so the descriptor address and the tile range
+// are made wave-uniform explicitly and the descriptor is read through the
+// constant address space: its fields then live in scalar registers, as the
+// kernel arguments of the per-call kernels do.
 template <typename T, bool B0, int KIND, int P1, int P2, int P3>
-__device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a, uint32_t local) {
+__device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& args, uint32_t t0, uint32_t t1,
+                                        uint32_t* counter, uint32_t* next) {
+    typedef __attribute__((address_space(4))) const TileArgs<T> ConstArgs;
+    const uint64_t bits = reinterpret_cast<uint64_t>(&args);
+    // (readfirstlane returns a signed int: widen through uint32_t so that the
+    // low word is not sign-extended into the high one)
+    const uint64_t ubits = uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(bits >> 32)))) << 32 |
+                           uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(bits))));
+    const TileArgs<T>& a = *(const TileArgs<T>*)((ConstArgs*)ubits);
+    t0 = uint32_t(__builtin_amdgcn_readfirstlane(t0));
+    t1 = uint32_t(__builtin_amdgcn_readfirstlane(t1));
+    uint32_t claim = 0;
+    if (threadIdx.x == 0) claim = atomicAdd(counter, 1u);
+    T* l = reinterpret_cast<T*>(lds);
     if constexpr (KIND == TTX_BATCH_STAGED) {
-        const TileCoord c = decode_tile(a.g, local, P2, P3);
-        staged_tile<T, B0, P1, P2, P3>(reinterpret_cast<T*>(lds), a, c);
+        tile_loop<StagedTile<T, B0, P1, P2, P3>, true>(l, a, t0, t1, 1);
     } else {
         constexpr int V = P3 ? kVec<T> : 1;
-        const TileCoord c = decode_tile(a.g, local, P1, P2);
         if constexpr (KIND == TTX_FAMILY_MOVED)
-            moved_tile<T, B0, P1, P2, V, V>(reinterpret_cast<T*>(lds), a, c);
+            tile_loop<MovedTile<T, B0, P1, P2, V, V>, true>(l, a, t0, t1, 1);
         else
-            preserved_tile<T, B0, P1, P2, V>(a, c);
+            tile_loop<PreservedTile<T, B0, P1, P2, V>, true>(l, a, t0, t1, 1);
     }
+    if (threadIdx.x == 0) *next = claim;
 }
 
 template <bool B0>
-__device__ __forceinline__ void batch_dispatch_f32(int idx, unsigned char* lds, const BatchDesc& d,
-                                                   uint32_t local) {
+__device__ __forceinline__ bool batch_dispatch_f32(int idx, unsigned char* lds, const BatchDesc& d, uint32_t t0,
+                                                   uint32_t t1, uint32_t* counter, uint32_t* next) {
     const TileArgs<float>& a = *reinterpret_cast<const TileArgs<float>*>(d.args);
     switch (idx) {
 #define TTX_CASE(i, kind, p1, p2, p3) \
-    case i: batch_body<float, B0, kind, p1, p2, p3>(lds, a, local); break;
+    case i: batch_body<float, B0, kind, p1, p2, p3>(lds, a, t0, t1, counter, next); return true;
         TTX_BATCH_MENU_F32(TTX_CASE)
 #undef TTX_CASE
-        default: break;
+        default: return false;
     }
 }
 
 template <bool B0>
-__device__ __forceinline__ void batch_dispatch_f64(int idx, unsigned char* lds, const BatchDesc& d,
-                                                   uint32_t local) {
+__device__ __forceinline__ bool batch_dispatch_f64(int idx, unsigned char* lds, const BatchDesc& d, uint32_t t0,
+                                                   uint32_t t1, uint32_t* counter, uint32_t* next) {
     const TileArgs<double>& a = *reinterpret_cast<const TileArgs<double>*>(d.args);
     switch (idx) {
 #define TTX_CASE(i, kind, p1, p2, p3) \
-    case i: batch_body<double, B0, kind, p1, p2, p3>(lds, a, local); break;
+    case i: batch_body<double, B0, kind, p1, p2, p3>(lds, a, t0, t1, counter, next); return true;
         TTX_BATCH_MENU_F64(TTX_CASE)
 #undef TTX_CASE
-        default: break;
+        default: return false;
     }
 }
 
-// prefix[0] = 0 and prefix[count] = total; problems without tiles have
-// equal consecutive prefix entries and are skipped by the cursor.
+// Persistent kernel: each workgroup claims chunks (runs of up to
+// desc.chunk consecutive tiles of one problem) from counter[0] until the
+// chunks run out.  The claimed chunk's problem is found by binary search
+// over chunk_prefix.  The last workgroup to finish (counted in counter[1])
+// resets both words, so the launch can be replayed from a graph without a
+// reset node.  Chunk ids are handed out in descriptor order, and the host
+// orders descriptors by decreasing size, so the last chunks are short.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_batch(const BatchDesc* __restrict__ desc,
-                                                    const uint32_t* __restrict__ prefix, int count,
-                                                    uint32_t total) {
+void k_batch(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ chunk_prefix, int count,
+             uint32_t chunks, uint32_t* counter) {
     __shared__ __align__(16) unsigned char lds[kBatchLds];
-    int p = 0;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        while (p + 1 < count && t >= prefix[p + 1]) ++p;
-        // p is the same in every lane: say so, so that the descriptor is read
-        // through the scalar cache into scalar registers
-        p = __builtin_amdgcn_readfirstlane(p);
+    __shared__ uint32_t claim[2];
+    if (threadIdx.x == 0) claim[0] = atomicAdd(&counter[0], 1u);
+    __syncthreads();
+    uint32_t c = claim[0];
+    int slot = 0;
+    while (c < chunks) {
+        // largest p with chunk_prefix[p] <= c (chunk_prefix[0] == 0)
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (chunk_prefix[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const int p = __builtin_amdgcn_readfirstlane(lo);
         const BatchDesc& d = desc[p];
         const int v = d.variant;
-        if (v < 0) continue;
-        const uint32_t local = t - prefix[p];
-        const int idx = v % TTX_BATCH_MENU_SIZE;
-        switch (v / TTX_BATCH_MENU_SIZE) {
-            case 0: batch_dispatch_f32<false>(idx, lds, d, local); break;
-            case 1: batch_dispatch_f32<true>(idx, lds, d, local); break;
-            case 2: batch_dispatch_f64<false>(idx, lds, d, local); break;
-            case 3: batch_dispatch_f64<true>(idx, lds, d, local); break;
-            default: break;
+        uint32_t* next = &claim[slot ^ 1];
+        bool ran = false;
+        if (v >= 0) {
+            const uint32_t t0 = (c - chunk_prefix[p]) * d.chunk;
+            const uint32_t t1 = min(t0 + d.chunk, d.tiles);
+            const int idx = v % TTX_BATCH_MENU_SIZE;
+            switch (v / TTX_BATCH_MENU_SIZE) {
+                case 0: ran = batch_dispatch_f32<false>(idx, lds, d, t0, t1, counter, next); break;
+                case 1: ran = batch_dispatch_f32<true>(idx, lds, d, t0, t1, counter, next); break;
+                case 2: ran = batch_dispatch_f64<false>(idx, lds, d, t0, t1, counter, next); break;
+                case 3: ran = batch_dispatch_f64<true>(idx, lds, d, t0, t1, counter, next); break;
+                default: break;
+            }
+        }
+        // a body claims the next chunk itself; without one, claim here
+        if (!ran && threadIdx.x == 0) *next = atomicAdd(counter, 1u);
+        // publishes *next; every thread read claim[slot] before this barrier
+        __syncthreads();
+        c = claim[slot ^ 1];
+        slot ^= 1;
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t done = atomicAdd(&counter[1], 1u);
+        if (done == gridDim.x - 1) {
+            // every other workgroup has made its last claim
+            atomicExch(&counter[0], 0u);
+            atomicExch(&counter[1], 0u);
         }
     }
 }
 
-int batch_grid(uint32_t total) {
+int batch_grid(uint32_t chunks) {
     static std::mutex mu;
     static int per_cu[64] = {};
     static int cus[64] = {};
@@ -168,13 +224,32 @@ int batch_grid(uint32_t total) {
         }
     }
     const uint64_t g = uint64_t(per_cu[dev]) * uint64_t(cus[dev]);
-    return int(total < g ? total : g);
+    return int(chunks < g ? chunks : g);
 }
 
-hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_prefix, int count,
-                        uint32_t total, int grid, hipStream_t stream) {
-    if (total == 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), 0, stream, d_desc, d_prefix, count, total);
+uint32_t batch_layout(BatchDesc* desc, int count, uint32_t* chunk_prefix, int* grid) {
+    uint64_t tiles = 0;
+    for (int i = 0; i < count; ++i) tiles += desc[i].tiles;
+    // about 8 chunks per workgroup of a full launch, at most 32 tiles each
+    const uint64_t g = uint64_t(batch_grid(0xffffffffu));
+    uint64_t k = tiles / (8 * g);
+    k = k < 1 ? 1 : (k > 32 ? 32 : k);
+    uint64_t chunks = 0;
+    for (int i = 0; i < count; ++i) {
+        chunk_prefix[i] = uint32_t(chunks);
+        desc[i].chunk = uint32_t(k);
+        chunks += (desc[i].tiles + k - 1) / k;
+    }
+    chunk_prefix[count] = uint32_t(chunks);
+    *grid = batch_grid(uint32_t(chunks));
+    return uint32_t(chunks);
+}
+
+hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_chunk_prefix, int count, uint32_t chunks,
+                        int grid, uint32_t* counter, hipStream_t stream) {
+    if (chunks == 0 || grid <= 0 || count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), 0, stream, d_desc, d_chunk_prefix, count, chunks,
+                       counter);
     return hipGetLastError();
 }
 
@@ -341,10 +416,23 @@ static ttx_status problem_from(const ttx_problem& q, Problem* p) {
                         q.has_outer_b ? q.outer_b : nullptr, p);
 }
 
+// Device work block of a batch: descriptors, chunk prefix, claim counter.
+static size_t desc_bytes(int count) { return size_t(count) * sizeof(BatchDesc); }
+static size_t prefix_offset(int count) { return desc_bytes(count); }
+static size_t counter_offset(int count) { return (prefix_offset(count) + sizeof(uint32_t) * (count + 1) + 15) & ~size_t(15); }
+static size_t work_bytes(int count) { return counter_offset(count) + 2 * sizeof(uint32_t); }
+
+static const BatchDesc* work_desc(const ttx_batch* b) { return reinterpret_cast<const BatchDesc*>(b->d_work); }
+static const uint32_t* work_prefix(const ttx_batch* b) {
+    return reinterpret_cast<const uint32_t*>(b->d_work + prefix_offset(int(b->prob.size())));
+}
+static uint32_t* work_counter(const ttx_batch* b) {
+    return reinterpret_cast<uint32_t*>(b->d_work + counter_offset(int(b->prob.size())));
+}
+
 static ttx_status describe_all(ttx_batch* b) {
     const int count = int(b->prob.size());
-    b->desc.assign(count, BatchDesc());
-    b->prefix.assign(count + 1, 0);
+    std::vector<BatchDesc> desc(count);
     uint64_t total = 0;
     b->bytes = 0;
     for (int i = 0; i < count; ++i) {
@@ -354,30 +442,44 @@ static ttx_status describe_all(ttx_batch* b) {
         const void* Bin = q.B_in ? q.B_in : q.B;
         ttx_config used;
         ttx_status st = batch_describe(p, b->forced[i] ? &b->cfg[i] : nullptr, beta0, q.A, Bin, q.B,
-                                       q.alpha, q.beta, &b->desc[i], &used);
+                                       q.alpha, q.beta, &desc[i], &used);
         if (st != TTX_OK) return st;
         b->cfg[i] = used;
-        b->prefix[i] = uint32_t(total);
-        total += b->desc[i].tiles;
+        total += desc[i].tiles;
         if (total >= (uint64_t(1) << 32)) return fail(TTX_EUNSUPPORTED, "batch has too many tiles");
         b->bytes += p.elements * (p.dtype == TTX_F32 ? 4 : 8) * (beta0 ? 2 : 3);
     }
-    b->prefix[count] = uint32_t(total);
-    b->total = uint32_t(total);
-    b->grid = batch_grid(b->total);
+    // largest problems first, so that the chunks claimed last are short ones
+    b->order.resize(count);
+    for (int i = 0; i < count; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return b->prob[x].elements * (b->prob[x].dtype == TTX_F32 ? 4 : 8) >
+               b->prob[y].elements * (b->prob[y].dtype == TTX_F32 ? 4 : 8);
+    });
+    b->desc.resize(count);
+    for (int i = 0; i < count; ++i) b->desc[i] = desc[b->order[i]];
+    b->chunk_prefix.assign(count + 1, 0);
+    b->total = total;
+    b->chunks = count ? batch_layout(b->desc.data(), count, b->chunk_prefix.data(), &b->grid) : 0;
+    if (!count) b->grid = 0;
     return TTX_OK;
 }
 
 static ttx_status upload(ttx_batch* b, hipStream_t stream) {
-    const size_t nd = b->desc.size() * sizeof(BatchDesc);
-    const size_t np = b->prefix.size() * sizeof(uint32_t);
-    if (!b->d_desc) {
-        if (hipMalloc(reinterpret_cast<void**>(&b->d_desc), nd ? nd : sizeof(BatchDesc)) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&b->d_prefix), np) != hipSuccess)
+    const int count = int(b->prob.size());
+    const size_t need = work_bytes(count);
+    if (!b->d_work) {
+        if (hipMalloc(reinterpret_cast<void**>(&b->d_work), need) != hipSuccess)
             return fail(TTX_ENOMEM, "batch descriptor allocation failed");
+        b->work_bytes = need;
+        // the claim counter starts at zero; every launch leaves it at zero
+        if (hipMemset(b->d_work + counter_offset(count), 0, 2 * sizeof(uint32_t)) != hipSuccess)
+            return fail(TTX_EHIP, "batch counter initialisation failed");
     }
-    if ((nd && hipMemcpyAsync(b->d_desc, b->desc.data(), nd, hipMemcpyHostToDevice, stream) != hipSuccess) ||
-        hipMemcpyAsync(b->d_prefix, b->prefix.data(), np, hipMemcpyHostToDevice, stream) != hipSuccess ||
+    if ((count && hipMemcpyAsync(b->d_work, b->desc.data(), desc_bytes(count), hipMemcpyHostToDevice, stream) !=
+                      hipSuccess) ||
+        hipMemcpyAsync(b->d_work + prefix_offset(count), b->chunk_prefix.data(), sizeof(uint32_t) * (count + 1),
+                       hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return fail(TTX_EHIP, "batch descriptor upload failed");
     return TTX_OK;
@@ -450,25 +552,31 @@ ttx_status ttx_batch_update(ttx_batch* b, int count, const ttx_problem* problems
         st = check_pointers(p, problems[i].A, Bin, problems[i].B, beta0);
         if (st != TTX_OK) return st;
     }
-    const uint32_t old_total = b->total;
+    const uint32_t old_chunks = b->chunks;
+    const int old_grid = b->grid;
     b->src.assign(problems, problems + count);
     for (int i = 0; i < count; ++i) b->forced[i] = b->prob[i].family != TTX_FAMILY_EMPTY;
     ttx_status st = describe_all(b);
     if (st != TTX_OK) return st;
-    if (b->total != old_total) drop_graph(b);
+    if (b->chunks != old_chunks || b->grid != old_grid) drop_graph(b);
     return upload(b, stream);
 }
 
 ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
     if (max_candidates == 0) max_candidates = 16;
-    BatchDesc* d_one = nullptr;
-    uint32_t* d_pre = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&d_one), sizeof(BatchDesc)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&d_pre), 2 * sizeof(uint32_t)) != hipSuccess) {
-        if (d_one) (void)hipFree(d_one);
+    // a one-problem work block: descriptor, chunk prefix, claim counter
+    const size_t need = work_bytes(1);
+    unsigned char* d_blk = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&d_blk), need) != hipSuccess)
         return fail(TTX_ENOMEM, "tuner descriptor allocation failed");
+    if (hipMemset(d_blk + counter_offset(1), 0, 2 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(d_blk);
+        return fail(TTX_EHIP, "tuner counter initialisation failed");
     }
+    BatchDesc* d_one = reinterpret_cast<BatchDesc*>(d_blk);
+    uint32_t* d_pre = reinterpret_cast<uint32_t*>(d_blk + prefix_offset(1));
+    uint32_t* d_cnt = reinterpret_cast<uint32_t*>(d_blk + counter_offset(1));
     ttx_status result = TTX_OK;
     std::vector<ttx_config> cands(4096);
     for (size_t i = 0; i < b->prob.size() && result == TTX_OK; ++i) {
@@ -503,12 +611,14 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
                 void* bb = static_cast<char*>(B) + offb;
                 if (batch_describe(p, &cands[c], beta0, a, bb, bb, 1.0, beta0 ? 0.0 : 1.0, &one, nullptr) != TTX_OK)
                     return hipErrorInvalidValue;
-                const uint32_t pre[2] = {0, one.tiles};
+                uint32_t pre[2];
+                int grid = 0;
+                const uint32_t chunks = batch_layout(&one, 1, pre, &grid);
                 hipError_t e = hipMemcpyAsync(d_one, &one, sizeof(one), hipMemcpyHostToDevice, s);
                 if (e == hipSuccess) e = hipMemcpyAsync(d_pre, pre, sizeof(pre), hipMemcpyHostToDevice, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e != hipSuccess) return e;
-                return launch_batch(d_one, d_pre, 1, one.tiles, batch_grid(one.tiles), s);
+                return launch_batch(d_one, d_pre, 1, chunks, grid, d_cnt, s);
             },
             &best_i, &best_us);
         if (result == TTX_OK && best_i >= 0) {
@@ -518,33 +628,34 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
             g_btab[key] = cands[best_i];
         }
     }
-    (void)hipFree(d_one);
-    (void)hipFree(d_pre);
+    (void)hipFree(d_blk);
     if (result != TTX_OK) return result;
-    const uint32_t old_total = b->total;
+    const uint32_t old_chunks = b->chunks;
+    const int old_grid = b->grid;
     ttx_status st = describe_all(b);
     if (st != TTX_OK) return st;
-    if (b->total != old_total) drop_graph(b);
+    if (b->chunks != old_chunks || b->grid != old_grid) drop_graph(b);
     return upload(b, nullptr);
 }
 
 ttx_status ttx_batch_execute_direct(ttx_batch* b, hipStream_t stream) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
-    hipError_t e = launch_batch(b->d_desc, b->d_prefix, int(b->prob.size()), b->total, b->grid, stream);
+    hipError_t e = launch_batch(work_desc(b), work_prefix(b), int(b->prob.size()), b->chunks, b->grid,
+                                work_counter(b), stream);
     return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
 }
 
 ttx_status ttx_batch_execute(ttx_batch* b, hipStream_t stream) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
-    if (b->total == 0) return TTX_OK;
+    if (b->chunks == 0) return TTX_OK;
     if (!b->captured) {
         drop_graph(b);
         if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(TTX_EHIP, "capture stream creation failed");
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(TTX_EHIP, "stream capture failed to start");
-        hipError_t e = launch_batch(b->d_desc, b->d_prefix, int(b->prob.size()), b->total, b->grid,
-                                    b->cap_stream);
+        hipError_t e = launch_batch(work_desc(b), work_prefix(b), int(b->prob.size()), b->chunks, b->grid,
+                                    work_counter(b), b->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -566,7 +677,8 @@ ttx_status ttx_batch_get_info(const ttx_batch* b, ttx_batch_info* info) {
     if (!b || !info) return fail(TTX_EINVAL, "NULL argument");
     std::memset(info, 0, sizeof(*info));
     info->count = int(b->prob.size());
-    info->total_tiles = b->total;
+    info->total_tiles = int64_t(b->total);
+    info->chunks = b->chunks;
     info->grid = b->grid;
     info->algorithmic_bytes = b->bytes;
     bool seen[4 * TTX_BATCH_MENU_SIZE] = {};
@@ -612,8 +724,7 @@ ttx_status ttx_batch_destroy(ttx_batch* b) {
     if (!b) return TTX_OK;
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    if (b->d_desc) (void)hipFree(b->d_desc);
-    if (b->d_prefix) (void)hipFree(b->d_prefix);
+    if (b->d_work) (void)hipFree(b->d_work);
     delete b;
     return TTX_OK;
 }

@@ -49,21 +49,21 @@
 #define TTX_BATCH_STAGED 4
 
 #define TTX_BATCH_MENU_F32(X)                                                             \
-    X(0, TTX_FAMILY_MOVED, 64, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
-    X(2, TTX_FAMILY_MOVED, 64, 64, 0) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
+    X(0, TTX_FAMILY_MOVED, 64, 32, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
+    X(2, TTX_FAMILY_MOVED, 32, 64, 1) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
     X(4, TTX_FAMILY_MOVED, 8, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 8, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 1024, 1, 1)               \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 16, 16)                 \
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
     X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)
 
 #define TTX_BATCH_MENU_F64(X)                                                             \
-    X(0, TTX_FAMILY_MOVED, 32, 64, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
-    X(2, TTX_FAMILY_MOVED, 64, 32, 0) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
+    X(0, TTX_FAMILY_MOVED, 32, 32, 1) X(1, TTX_FAMILY_MOVED, 32, 16, 1)                   \
+    X(2, TTX_FAMILY_MOVED, 16, 32, 1) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
     X(4, TTX_FAMILY_MOVED, 4, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 4, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 512, 1, 1)                \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 16, 8)                  \
-    X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)
+    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
+    X(12, TTX_BATCH_STAGED, 32, 4, 4) X(13, TTX_BATCH_STAGED, 64, 4, 4)
 
 #define TTX_BATCH_MENU_SIZE 14

@@ -102,10 +102,12 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    BatchDesc* d_desc = nullptr;
-    uint32_t* d_prefix = nullptr;
-    BatchDesc* h_desc = nullptr;     // pinned staging
-    uint32_t* h_prefix = nullptr;
+    // work block of one micro-batch: count descriptors followed directly by
+    // the count + 1 chunk prefix entries (one host-to-device copy), and the
+    // claim counter at a fixed offset after room for max_batch descriptors
+    unsigned char* d_blk = nullptr;
+    unsigned char* h_blk = nullptr;  // pinned staging (host memory with the fake executor)
+    uint32_t* d_counter = nullptr;
     std::vector<uint64_t> tickets;
     bool busy = false;
     int64_t fake_done_at = 0;
@@ -213,25 +215,25 @@ static bool launch_locked(ttx_server* s) {
     if (!slot) return false;
     int count = 0;
     int64_t bytes = 0;
-    uint64_t tiles = 0;
+    BatchDesc* h_desc = reinterpret_cast<BatchDesc*>(slot->h_blk);
     while (!s->ready.empty() && count < s->opts.max_batch) {
         Request& r = s->reqs[s->ready.front()];
         if (count > 0 && bytes + r.bytes > s->opts.max_batch_bytes) break;
-        BatchDesc& d = slot->h_desc[count];
+        BatchDesc& d = h_desc[count];
         if (batch_describe(r.p, &r.cfg, r.beta0, r.A, r.Bin, r.Bout, r.alpha, r.beta, &d, nullptr) != TTX_OK) {
             // cannot happen for a validated request; count it as done to keep the loop live
             d.variant = -1;
             d.tiles = 0;
         }
-        slot->h_prefix[count] = uint32_t(tiles);
-        tiles += d.tiles;
         bytes += r.bytes;
         r.state = RUNNING;
         slot->tickets.push_back(s->ready.front());
         s->ready.pop_front();
         ++count;
     }
-    slot->h_prefix[count] = uint32_t(tiles);
+    uint32_t* h_prefix = reinterpret_cast<uint32_t*>(slot->h_blk + sizeof(BatchDesc) * count);
+    int grid = 0;
+    const uint32_t chunks = s->opts.fake_device ? 0 : batch_layout(h_desc, count, h_prefix, &grid);
     slot->busy = true;
     s->running += count;
     ++s->batches;
@@ -241,14 +243,12 @@ static bool launch_locked(ttx_server* s) {
         slot->fake_done_at = now_ns() + int64_t(double(bytes) / 4e12 * 1e9) + 2000;
         return true;
     }
-    hipError_t e = hipMemcpyAsync(slot->d_desc, slot->h_desc, sizeof(BatchDesc) * count,
-                                  hipMemcpyHostToDevice, slot->stream);
+    const size_t nbytes = sizeof(BatchDesc) * count + sizeof(uint32_t) * (count + 1);
+    hipError_t e = hipMemcpyAsync(slot->d_blk, slot->h_blk, nbytes, hipMemcpyHostToDevice, slot->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(slot->d_prefix, slot->h_prefix, sizeof(uint32_t) * (count + 1),
-                           hipMemcpyHostToDevice, slot->stream);
-    if (e == hipSuccess)
-        e = launch_batch(slot->d_desc, slot->d_prefix, count, uint32_t(tiles), batch_grid(uint32_t(tiles)),
-                         slot->stream);
+        e = launch_batch(reinterpret_cast<const BatchDesc*>(slot->d_blk),
+                         reinterpret_cast<const uint32_t*>(slot->d_blk + sizeof(BatchDesc) * count), count, chunks,
+                         grid, slot->d_counter, slot->stream);
     if (e == hipSuccess) e = hipEventRecord(slot->done, slot->stream);
     if (e != hipSuccess) s->worker_error = std::string("server launch: ") + hipGetErrorString(e);
     return true;
@@ -281,14 +281,11 @@ static void free_slots(ttx_server* s) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.d_desc) (void)hipFree(sl.d_desc);
-        if (sl.d_prefix) (void)hipFree(sl.d_prefix);
+        if (sl.d_blk) (void)hipFree(sl.d_blk);
         if (!s->opts.fake_device) {
-            if (sl.h_desc) (void)hipHostFree(sl.h_desc);
-            if (sl.h_prefix) (void)hipHostFree(sl.h_prefix);
+            if (sl.h_blk) (void)hipHostFree(sl.h_blk);
         } else {
-            delete[] sl.h_desc;
-            delete[] sl.h_prefix;
+            delete[] sl.h_blk;
         }
     }
     s->slots.clear();
@@ -402,23 +399,24 @@ ttx_status ttx_server_create(ttx_server** out, const ttx_server_opts* opts) {
         return fail(TTX_ENOMEM, "arena allocation failed");
     }
     s->slots.resize(o.slots);
+    const size_t staged = sizeof(BatchDesc) * o.max_batch + sizeof(uint32_t) * (o.max_batch + 1);
+    const size_t counter_at = (staged + 255) & ~size_t(255);
     for (auto& sl : s->slots) {
         if (o.fake_device) {
-            sl.h_desc = new BatchDesc[o.max_batch];
-            sl.h_prefix = new uint32_t[o.max_batch + 1];
+            sl.h_blk = new unsigned char[staged];
             continue;
         }
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&sl.d_desc), sizeof(BatchDesc) * o.max_batch) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&sl.d_prefix), sizeof(uint32_t) * (o.max_batch + 1)) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), sizeof(BatchDesc) * o.max_batch, 0) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&sl.h_prefix), sizeof(uint32_t) * (o.max_batch + 1), 0) != hipSuccess) {
+            hipMalloc(reinterpret_cast<void**>(&sl.d_blk), counter_at + 2 * sizeof(uint32_t)) != hipSuccess ||
+            hipMemset(sl.d_blk + counter_at, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&sl.h_blk), staged, 0) != hipSuccess) {
             free_slots(s);
             if (s->arena_base) (void)hipFree(s->arena_base);
             delete s;
             return fail(TTX_ENOMEM, "server slot allocation failed");
         }
+        sl.d_counter = reinterpret_cast<uint32_t*>(sl.d_blk + counter_at);
     }
     s->worker = std::thread(worker_main, s);
     *out = s;

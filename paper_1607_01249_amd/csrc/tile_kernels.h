@@ -133,102 +133,144 @@ constexpr int pow2_ceil(int x) {
 // TA / V is not a power of two), so NT / P runs are handled per pass and a
 // thread's address advances by a fixed stride from one pass to the next.
 
+// The tile bodies are split into phases so that a workgroup working through
+// several tiles can overlap them: tile k+1's loads are issued before tile
+// k's stores, so waiting for those loads never waits for the stores (memory
+// operations retire in order), and the stores drain while the next tile is
+// transposed.  `tile_loop` runs tiles t, t + step, ... < end that way.
+
 // One moved-family tile over the A-side super index x (A's first group_a
 // indices, contiguous in A) and the B-side super index y (B's first group_b
 // indices, contiguous in B): element (x0 + x, y0 + y) for x < ea, y < eb is
 // A[oa + x*sAa + gB.offset(y0 + y)] -> B[ob + y*sBb + gA.offset(x0 + x)].
 // VA / VB are the vector widths along x in A and along y in B (VA > 1
-// implies sAa == 1, VB > 1 implies sBb == 1).  `lds` holds TB rows of
+// implies sAa == 1, VB > 1 implies sBb == 1).  The LDS tile has TB rows of
 // TA + 1 elements.
 template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
-__device__ __forceinline__ void moved_tile(T* __restrict__ lds, const TileArgs<T>& a,
-                                           const TileCoord& c) {
-    constexpr int NT = kThreads;
-    constexpr int LDR = TA + 1;
-    const int tid = threadIdx.x;
-    const bool nt = a.flags & KF_NT_STORE;
-
-    // A side: columns (fixed y) of TA elements along x.
-    constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
-    static_assert(PA <= NT, "tile edge too long for the workgroup");
-    const int xa = (tid % PA) * VA, ya = tid / PA;
-    const bool lane_a = (tid % PA) < LA;
-    const bool live_a = lane_a && xa < c.ea;
-    const T* pa = a.A + c.oa + int64_t(xa) * a.sAa;
-
-    // B side: rows (fixed x) of TB elements along y.
-    constexpr int LB = TB / VB, PB = pow2_ceil(LB), RB = NT / PB, NB = (TA + RB - 1) / RB;
-    static_assert(PB <= NT, "tile edge too long for the workgroup");
-    const int yb = (tid % PB) * VB, xb = tid / PB;
-    const bool live_b = (tid % PB) < LB && yb < c.eb;
-    const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
+struct MovedTile {
+    static constexpr bool kUsesLds = true;
+    static constexpr int kTA = TA, kTB = TB;
+    static constexpr int NT = kThreads, LDR = TA + 1;
+    // A side: columns (fixed y) of TA elements along x
+    static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
+    // B side: rows (fixed x) of TB elements along y
+    static constexpr int LB = TB / VB, PB = pow2_ceil(LB), RB = NT / PB, NB = (TA + RB - 1) / RB;
+    static_assert(PA <= NT && PB <= NT, "tile edge too long for the workgroup");
 
     vec_t<T, VA> ra[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-        if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
     vec_t<T, VB> rb[NB];
-    if constexpr (!BETA0) {
+    vec_t<T, VB> out[NB];
+
+    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int xa = (tid % PA) * VA, ya = tid / PA;
+        const bool live_a = (tid % PA) < LA && xa < c.ea;
+        const T* pa = a.A + c.oa + int64_t(xa) * a.sAa;
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
-            if (live_b && xb + i * RB < c.ea)
-                rb[i] = ld<T, VB>(a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB));
-    }
+        for (int i = 0; i < NA; ++i)
+            if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
+        if constexpr (!BETA0) {
+            const int yb = (tid % PB) * VB, xb = tid / PB;
+            const bool live_b = (tid % PB) < LB && yb < c.eb;
+            const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        const int y = ya + i * RA;
-        if (lane_a && y < TB) {
-#pragma unroll
-            for (int j = 0; j < VA; ++j) lds[y * LDR + xa + j] = lane<T, VA>(ra[i], j);
+            for (int i = 0; i < NB; ++i)
+                if (live_b && xb + i * RB < c.ea)
+                    rb[i] = ld<T, VB>(a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB));
         }
     }
-    __syncthreads();
+
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int xa = (tid % PA) * VA, ya = tid / PA;
+        if ((tid % PA) >= LA) return;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int x = xb + i * RB;
-        if (live_b && x < c.ea) {
-            vec_t<T, VB> v;
+        for (int i = 0; i < NA; ++i) {
+            const int y = ya + i * RA;
+            if (y < TB) {
 #pragma unroll
-            for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
-            vec_t<T, VB> o = epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta);
-            st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), o, nt);
+                for (int j = 0; j < VA; ++j) lds[y * LDR + xa + j] = lane<T, VA>(ra[i], j);
+            }
         }
     }
-    __syncthreads();  // the next tile reuses the LDS buffer
-}
+
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+                                             const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int yb = (tid % PB) * VB, xb = tid / PB;
+        const bool live_b = (tid % PB) < LB && yb < c.eb;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int x = xb + i * RB;
+            if (live_b && x < c.ea) {
+                vec_t<T, VB> v;
+#pragma unroll
+                for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
+                out[i] = epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int yb = (tid % PB) * VB, xb = tid / PB;
+        const bool live_b = (tid % PB) < LB && yb < c.eb;
+        const bool nt = a.flags & KF_NT_STORE;
+        const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int x = xb + i * RB;
+            if (live_b && x < c.ea) st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], nt);
+        }
+    }
+};
 
 // One preserved-family tile: rows of ea elements contiguous in A and B.
 // Row y < eb starts at A[oa + y*sAb] and B[ob + y*sBb]; element x of a row is
-// at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).
+// at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).  No LDS.
 template <typename T, bool BETA0, int TA, int TR, int V>
-__device__ __forceinline__ void preserved_tile(const TileArgs<T>& a, const TileCoord& c) {
-    constexpr int NT = kThreads;
-    constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
+struct PreservedTile {
+    static constexpr bool kUsesLds = false;
+    static constexpr int kTA = TA, kTB = TR;
+    static constexpr int NT = kThreads;
+    static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
-    const int tid = threadIdx.x;
-    const bool nt = a.flags & KF_NT_STORE;
-    const int x = (tid % P) * V, y0 = tid / P;
-    const bool live = (tid % P) < L && x < c.ea;
-    const int64_t off_a = c.oa + int64_t(x) * a.sAa + int64_t(y0) * a.sAb;
-    const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
-    const int64_t step_a = int64_t(R) * a.sAb, step_b = int64_t(R) * a.sBb;
+
     vec_t<T, V> ra[N];
     vec_t<T, V> rb[N];
+    vec_t<T, V> out[N];
+
+    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int x = (tid % P) * V, y0 = tid / P;
+        const bool live = (tid % P) < L && x < c.ea;
+        const int64_t off_a = c.oa + int64_t(x) * a.sAa + int64_t(y0) * a.sAb;
+        const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        if (live && y0 + i * R < c.eb) {
-            ra[i] = ld<T, V>(a.A + off_a + i * step_a);
-            if constexpr (!BETA0) rb[i] = ld<T, V>(a.Bsrc + off_b + i * step_b);
+        for (int i = 0; i < N; ++i) {
+            if (live && y0 + i * R < c.eb) {
+                ra[i] = ld<T, V>(a.A + off_a + i * int64_t(R) * a.sAb);
+                if constexpr (!BETA0) rb[i] = ld<T, V>(a.Bsrc + off_b + i * int64_t(R) * a.sBb);
+            }
         }
     }
+
+    __device__ __forceinline__ void finish(const TileArgs<T>& a, const TileCoord& c) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        if (live && y0 + i * R < c.eb) {
-            vec_t<T, V> o = epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta);
-            st<T, V>(a.Bdst + off_b + i * step_b, o, nt);
-        }
+        for (int i = 0; i < N; ++i) out[i] = epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta);
     }
-}
+
+    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int x = (tid % P) * V, y0 = tid / P;
+        const bool live = (tid % P) < L && x < c.ea;
+        const bool nt = a.flags & KF_NT_STORE;
+        const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (live && y0 + i * R < c.eb) st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], nt);
+    }
+};
 
 // One staged preserved-family tile, for short stride-1 rows: rows of n0
 // (<= N0) elements are contiguous in both tensors; the tile holds TX rows
@@ -239,67 +281,118 @@ __device__ __forceinline__ void preserved_tile(const TileArgs<T>& a, const TileC
 // A is read in runs of n0*TX elements and B written in runs of n0*TY; the
 // tile passes through LDS as [y][x][i] (row length TX*N0 + 1).
 template <typename T, bool BETA0, int N0, int TX, int TY>
-__device__ __forceinline__ void staged_tile(T* __restrict__ lds, const TileArgs<T>& a,
-                                            const TileCoord& c) {
-    constexpr int NT = kThreads;
-    constexpr int LDR = TX * N0 + 1;
+struct StagedTile {
+    static constexpr bool kUsesLds = true;
+    static constexpr int kTA = TX, kTB = TY;
+    static constexpr int NT = kThreads, LDR = TX * N0 + 1;
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
-    constexpr int PA = N0 * TX, PB = N0 * TY;
-    constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
+    static constexpr int PA = N0 * TX, PB = N0 * TY;
+    static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
     static_assert((N0 & (N0 - 1)) == 0 && (PA & (PA - 1)) == 0 && (PB & (PB - 1)) == 0, "powers of two");
     static_assert(PA * TY % NT == 0, "whole passes");
-    const int tid = threadIdx.x;
-    const int n0 = a.n0;
-    const bool nt = a.flags & KF_NT_STORE;
-    const T* A0 = a.A + c.oa;
 
     T ra[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        const int e = tid + i * NT, r = e % PA, y = e / PA;
-        const int iv = r % N0, x = r / N0;
-        if (iv < n0 && x < c.ea && y < c.eb)
-            ra[i] = A0[int64_t(iv) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y)];
-    }
     T rb[NB];
-    if constexpr (!BETA0) {
+    T out[NB];
+    int n0_ = 0;
+
+    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x, n0 = a.n0;
+        n0_ = n0;
+        const T* A0 = a.A + c.oa;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * NT, r = e % PA, y = e / PA;
+            const int iv = r % N0, x = r / N0;
+            if (iv < n0 && x < c.ea && y < c.eb)
+                ra[i] = A0[int64_t(iv) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y)];
+        }
+        if constexpr (!BETA0) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int e = tid + i * NT, r = e % PB, x = e / PB;
+                const int iv = r % N0, y = r / N0;
+                if (iv < n0 && y < c.eb && x < c.ea)
+                    rb[i] = a.Bsrc[c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x)];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileCoord& c) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * NT, r = e % PA, y = e / PA;
+            const int iv = r % N0, x = r / N0;
+            if (iv < n0_) lds[y * LDR + x * N0 + iv] = ra[i];
+        }
+    }
+
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+                                             const TileCoord& c) {
+        const int tid = threadIdx.x, n0 = a.n0;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * NT, r = e % PB, x = e / PB;
             const int iv = r % N0, y = r / N0;
             if (iv < n0 && y < c.eb && x < c.ea)
-                rb[i] = a.Bsrc[c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x)];
+                out[i] = epilogue<T, 1, BETA0>(lds[y * LDR + x * N0 + iv], rb[i], a.alpha, a.beta);
         }
     }
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        const int e = tid + i * NT, r = e % PA, y = e / PA;
-        const int iv = r % N0, x = r / N0;
-        if (iv < n0) lds[y * LDR + x * N0 + iv] = ra[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int e = tid + i * NT, r = e % PB, x = e / PB;
-        const int iv = r % N0, y = r / N0;
-        if (iv < n0 && y < c.eb && x < c.ea) {
-            const T v = lds[y * LDR + x * N0 + iv];
-            const T o = epilogue<T, 1, BETA0>(v, rb[i], a.alpha, a.beta);
-            st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x), o, nt);
-        }
-    }
-    __syncthreads();  // the next tile reuses the LDS buffer
-}
 
-template <typename T, bool BETA0, int N0, int TX, int TY>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_staged(TileArgs<T> a) {
-    __shared__ T lds[TY * (TX * N0 + 1)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    for (uint32_t t = first; t < a.g.ntiles; t += G) {
-        const TileCoord c = decode_tile(a.g, t, TX, TY);
-        staged_tile<T, BETA0, N0, TX, TY>(lds, a, c);
+    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x, n0 = a.n0;
+        const bool nt = a.flags & KF_NT_STORE;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * NT, r = e % PB, x = e / PB;
+            const int iv = r % N0, y = r / N0;
+            if (iv < n0 && y < c.eb && x < c.ea)
+                st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
+                         out[i], nt);
+        }
+    }
+};
+
+// Tiles t, t + step, ... < end of one problem.  With PIPE, tile k+1's loads
+// are issued between tile k's LDS read and its stores, as described above;
+// this holds two tiles' data in registers at once, so it is used where the
+// register budget allows.  Every thread of the workgroup runs the same trip
+// count (t, end, step are uniform), so the barriers are reached by all.
+template <class Tile, bool PIPE, typename T>
+__device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>& a, uint32_t t,
+                                          uint32_t end, uint32_t step) {
+    Tile tile;
+    TileCoord c = decode_tile(a.g, t, Tile::kTA, Tile::kTB);
+    tile.load(a, c);
+    while (true) {
+        if constexpr (Tile::kUsesLds) {
+            tile.to_lds(lds, c);
+            __syncthreads();
+            tile.from_lds(lds, a, c);
+        } else {
+            tile.finish(a, c);
+        }
+        const uint64_t tn = uint64_t(t) + step;
+        const bool more = tn < end;
+        if constexpr (PIPE) {
+            TileCoord cn = c;
+            if (more) {
+                cn = decode_tile(a.g, uint32_t(tn), Tile::kTA, Tile::kTB);
+                tile.load(a, cn);
+            }
+            tile.store(a, c);
+            if constexpr (Tile::kUsesLds) __syncthreads();   // the LDS tile is rewritten next
+            if (!more) break;
+            c = cn;
+        } else {
+            tile.store(a, c);
+            if (!more) break;
+            if constexpr (Tile::kUsesLds) __syncthreads();
+            c = decode_tile(a.g, uint32_t(tn), Tile::kTA, Tile::kTB);
+            tile.load(a, c);
+        }
+        t = uint32_t(tn);
     }
 }
 
@@ -314,10 +407,7 @@ void k_moved(TileArgs<T> a) {
     __shared__ T lds[TB * (TA + 1)];
     const uint32_t G = gridDim.x;
     const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    for (uint32_t t = first; t < a.g.ntiles; t += G) {
-        const TileCoord c = decode_tile(a.g, t, TA, TB);
-        moved_tile<T, BETA0, TA, TB, VA, VB>(lds, a, c);
-    }
+    if (first < a.g.ntiles) tile_loop<MovedTile<T, BETA0, TA, TB, VA, VB>, false>(lds, a, first, a.g.ntiles, G);
 }
 
 template <typename T, bool BETA0, int TA, int TR, int V>
@@ -326,10 +416,17 @@ __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
 void k_preserved(TileArgs<T> a) {
     const uint32_t G = gridDim.x;
     const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    for (uint32_t t = first; t < a.g.ntiles; t += G) {
-        const TileCoord c = decode_tile(a.g, t, TA, TR);
-        preserved_tile<T, BETA0, TA, TR, V>(a, c);
-    }
+    if (first < a.g.ntiles)
+        tile_loop<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
+}
+
+template <typename T, bool BETA0, int N0, int TX, int TY>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_staged(TileArgs<T> a) {
+    __shared__ T lds[TY * (TX * N0 + 1)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles) tile_loop<StagedTile<T, BETA0, N0, TX, TY>, false>(lds, a, first, a.g.ntiles, G);
 }
 
 // Flat: one index of n elements with strides sa, sb.  The vector path

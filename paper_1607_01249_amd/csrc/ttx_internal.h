@@ -223,7 +223,7 @@ struct alignas(16) BatchDesc {
     int variant;
     int dtype;
     uint32_t tiles;
-    uint32_t pad;
+    uint32_t chunk;     // tiles per claimed chunk (set by batch_layout)
     alignas(16) unsigned char args[sizeof(TileArgs<double>)];
 };
 
@@ -235,10 +235,18 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
                           ttx_config* used);
 // Batched-menu configs for a problem, best heuristic first (for tuning).
 int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int cap);
-// Workgroups of the persistent launch for `total` tiles.
-int batch_grid(uint32_t total);
-// The persistent kernel over count descriptors (prefix[count] == total).
-hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_prefix, int count,
-                        uint32_t total, int grid, hipStream_t stream);
+// Work layout of a persistent launch over `count` descriptors: sets each
+// descriptor's chunk size and fills chunk_prefix[0..count] (chunks of
+// problem i are chunk_prefix[i] .. chunk_prefix[i+1]-1).  Returns the total
+// chunk count and sets *grid to the workgroup count.  Host only.
+uint32_t batch_layout(BatchDesc* desc, int count, uint32_t* chunk_prefix, int* grid);
+// Workgroups of the persistent launch for `chunks` chunks.
+int batch_grid(uint32_t chunks);
+// The persistent kernel over count descriptors.  `counter` is two words of
+// device memory that are zero before the launch; the launch leaves them zero
+// again (the last workgroup to finish resets them), so launches that use
+// the same counter must not overlap.
+hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_chunk_prefix, int count,
+                        uint32_t chunks, int grid, uint32_t* counter, hipStream_t stream);
 
 }  // namespace ttx

@@ -29,11 +29,11 @@ def _fake_problems(probs, gap=256):
 
 
 BATCH_SHAPES = {
-    (ttx.F32, ttx.FAMILY_MOVED): {(64, 64), (32, 32), (8, 128), (128, 8)},
-    (ttx.F64, ttx.FAMILY_MOVED): {(32, 64), (32, 32), (64, 32), (4, 128), (128, 4)},
+    (ttx.F32, ttx.FAMILY_MOVED): {(64, 32), (32, 32), (32, 64), (8, 128), (128, 8)},
+    (ttx.F64, ttx.FAMILY_MOVED): {(32, 32), (32, 16), (16, 32), (4, 128), (128, 4)},
     # direct preserved tiles, and staged (tile_x, tile_y) for short rows
-    (ttx.F32, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (16, 16), (8, 8), (4, 4)},
-    (ttx.F64, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (16, 8), (8, 8), (4, 4)},
+    (ttx.F32, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
+    (ttx.F64, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
     (ttx.F32, ttx.FAMILY_FLAT): {(1024, 1), (256, 1)},
     (ttx.F64, ttx.FAMILY_FLAT): {(512, 1), (256, 1)},
 }
