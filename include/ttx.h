@@ -81,6 +81,10 @@ typedef enum ttx_family {
 /* Config flags. */
 #define TTX_CFG_XCD_SWIZZLE 1  /* map consecutive tile ids onto one XCD */
 #define TTX_CFG_NT_STORE 2     /* non-temporal (streaming) stores to B */
+#define TTX_CFG_DENSE 4        /* dense tiles (MOVED, or PRESERVED with index groups): tile_a x
+                                  tile_b are run-time extents, rows of the shared stride-1 index
+                                  (PRESERVED) are packed without padding, at most 1024 elements
+                                  per tile, element-wise accesses */
 
 /* One implementation candidate (Sec. 2.2: blocking and loop order).
  *   tile_a  : tile extent along A's stride-1 index (merged index 0);
@@ -91,8 +95,15 @@ typedef enum ttx_family {
  *   order   : the merged indices in the order tile ids enumerate them,
  *             fastest first (the "loop order" of Sec. 2.2); n_order entries;
  *   flags   : TTX_CFG_* bits;
- *   group_a/b: moved family only -- index groups that extend the 2D tile
- *             when stride-1 extents are short (1 = the single index). */
+ *   group_a/b: index groups that extend the 2D tile when stride-1 extents
+ *             are short (1 = the single index).  MOVED: A's first group_a
+ *             and B's first group_b merged indices.  PRESERVED with groups
+ *             (short rows): tiles hold whole rows of the shared stride-1
+ *             index times A's next group_a-1 and B's next group_b-1 indices;
+ *             tile_a and tile_b then count rows along those super indices.
+ *   With TTX_CFG_DENSE, tile_a and tile_b may be any positive extents with
+ *   rows x tile_a x tile_b within the dense capacity (rows = the row length
+ *   for PRESERVED, 1 for MOVED). */
 typedef struct ttx_config {
     int family;
     int tile_a;
@@ -101,8 +112,8 @@ typedef struct ttx_config {
     int n_order;
     int order[TTX_MAX_DIMS];
     int flags;
-    int group_a;   /* MOVED: A's first group_a merged indices, contiguous in A, form the tile's A edge */
-    int group_b;   /* MOVED: B's first group_b merged indices, contiguous in B, form its B edge; else 1 */
+    int group_a;   /* index groups, see above (1 = the single index) */
+    int group_b;
 } ttx_config;
 
 /* What the planner made of a problem (Sec. 2.1 stage 1 and the family split

@@ -22,7 +22,8 @@ F32, F64 = 0, 1
 OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = range(9)
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
-CFG_XCD_SWIZZLE, CFG_NT_STORE = 1, 2
+CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE = 1, 2, 4
+DENSE_CAP = {F32: 1024, F64: 1024}
 
 i64 = ctypes.c_int64
 i64p = ctypes.POINTER(ctypes.c_int64)

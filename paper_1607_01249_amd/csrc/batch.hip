@@ -58,6 +58,13 @@ static int batch_index(int dtype, int family, int ta, int tb, int vec) {
     return -1;
 }
 
+static int dense_index(int dtype) {
+    const BatchEntry* m = batch_menu(dtype);
+    for (int i = 0; i < TTX_BATCH_MENU_SIZE; ++i)
+        if (m[i].kind == TTX_BATCH_DENSE) return i;
+    return -1;
+}
+
 static int staged_index(int dtype, int lanes, int tx, int ty) {
     const BatchEntry* m = batch_menu(dtype);
     for (int i = 0; i < TTX_BATCH_MENU_SIZE; ++i)
@@ -67,8 +74,10 @@ static int staged_index(int dtype, int lanes, int tx, int ty) {
 
 // LDS of the largest LDS-staged variant of either dtype.
 constexpr int lds_need(int kind, int p1, int p2, int p3, int esize) {
-    return kind == TTX_FAMILY_MOVED ? p2 * (p1 + 1) * esize
-                                    : kind == TTX_BATCH_STAGED ? p3 * (p2 * p1 + 1) * esize : 0;
+    return kind == TTX_FAMILY_MOVED    ? p2 * (p1 + 1) * esize
+           : kind == TTX_BATCH_STAGED ? p3 * (p2 * p1 + 1) * esize
+           : kind == TTX_BATCH_DENSE  ? dense_lds_elems(p1) * esize
+                                      : 0;
 }
 #define TTX_LDS_F32(i, kind, p1, p2, p3) lds_need(kind, p1, p2, p3, 4),
 #define TTX_LDS_F64(i, kind, p1, p2, p3) lds_need(kind, p1, p2, p3, 8),
@@ -111,6 +120,8 @@ __device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a
     T* l = reinterpret_cast<T*>(lds);
     if constexpr (KIND == TTX_BATCH_STAGED) {
         tile_loop<StagedTile<T, B0, P1, P2, P3>, true>(l, a, t0, t1, 1);
+    } else if constexpr (KIND == TTX_BATCH_DENSE) {
+        tile_loop<DenseTile<T, B0, P1>, false>(l, a, t0, t1, 1);
     } else {
         constexpr int V = P3 ? kVec<T> : 1;
         if constexpr (KIND == TTX_FAMILY_MOVED)
@@ -286,12 +297,13 @@ static ttx_config batch_default(const Problem& p, bool vec) {
             if (p.family == TTX_FAMILY_PRESERVED) staged.push_back(TileShape{m[i].p1 * 65536 + m[i].p2, m[i].p3});
             continue;
         }
+        if (m[i].kind == TTX_BATCH_DENSE) continue;
         if (m[i].kind != p.family || (m[i].p3 && !vec)) continue;
         bool dup = false;
         for (const auto& s : shapes) dup |= s.ta == m[i].p1 && s.tb == m[i].p2;
         if (!dup) shapes.push_back(TileShape{m[i].p1, m[i].p2});
     }
-    return default_config_from(p, shapes.data(), int(shapes.size()), staged.data(), int(staged.size()));
+    return default_config_from(p, shapes.data(), int(shapes.size()), staged.data(), int(staged.size()), true);
 }
 
 ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0, const void* A,
@@ -308,32 +320,26 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     ttx_config c = forced ? *forced : batch_default(p, vec);
     if (c.family != p.family) return fail(TTX_EINVAL, "config family does not match the problem");
     c.flags &= ~TTX_CFG_XCD_SWIZZLE;  // tile ids are global in the persistent launch
-    int idx;
-    bool use_vec = vec;
-    if (p.family == TTX_FAMILY_FLAT) {
-        c.tile_a = use_vec ? (p.dtype == TTX_F32 ? 1024 : 512) : 256;
-        c.tile_b = 1;
-        idx = batch_index(p.dtype, p.family, c.tile_a, 1, use_vec ? 1 : 0);
-    } else if (config_is_staged(c)) {
-        idx = staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b);
-        if (idx < 0 && forced) {
-            c = batch_default(p, false);
-            idx = config_is_staged(c) ? staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b)
-                                      : batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0);
+    // the menu entry for a config (-1: none); flat configs get their tile here
+    auto resolve = [&](ttx_config& k) -> int {
+        if (p.family == TTX_FAMILY_FLAT) {
+            k.tile_a = vec ? (p.dtype == TTX_F32 ? 1024 : 512) : 256;
+            k.tile_b = 1;
+            return batch_index(p.dtype, p.family, k.tile_a, 1, vec ? 1 : 0);
         }
-    } else {
-        if (c.n_order != p.n) return fail(TTX_EINVAL, "order must list every merged index");
-        idx = use_vec ? batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) : -1;
-        if (idx < 0) {
-            use_vec = false;
-            idx = batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0);
-        }
-        if (idx < 0 && forced) {
-            // a tuned shape that only exists as a vector variant, now with
-            // pointers that rule vectors out: fall back to the heuristic choice
-            c = batch_default(p, false);
-            idx = batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0);
-        }
+        if (config_is_dense(k)) return dense_index(p.dtype);
+        if (config_is_staged(k)) return staged_index(p.dtype, staged_lanes(p.dim[0].size), k.tile_a, k.tile_b);
+        if (k.n_order != p.n) return -1;
+        const int v = vec ? batch_index(p.dtype, p.family, k.tile_a, k.tile_b, 1) : -1;
+        return v >= 0 ? v : batch_index(p.dtype, p.family, k.tile_a, k.tile_b, 0);
+    };
+    int idx = resolve(c);
+    if (idx < 0 && forced) {
+        // a tuned shape that only exists as a vector variant, now with
+        // pointers that rule vectors out: fall back to the heuristic choice
+        c = batch_default(p, false);
+        c.flags &= ~TTX_CFG_XCD_SWIZZLE;
+        idx = resolve(c);
     }
     if (idx < 0) return fail(TTX_EINVAL, "tile shape not in the batched menu");
     const int vclass = (p.dtype == TTX_F32 ? 0 : 2) + (beta0 ? 1 : 0);
@@ -384,7 +390,9 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     for (int i = 0; i < na && n < limit; ++i) {
         const ttx_config& c = all[i];
         if (c.flags & TTX_CFG_XCD_SWIZZLE) continue;
-        if (config_is_staged(c)) {
+        if (config_is_dense(c)) {
+            if (dense_index(p.dtype) < 0) continue;
+        } else if (config_is_staged(c)) {
             if (staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b) < 0) continue;
         } else if (batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0) < 0 &&
                    batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) < 0) {

@@ -63,6 +63,10 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
     a.alpha = T(alpha);
     a.beta = T(beta);
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    if (config_is_dense(c)) {
+        uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
+        return dense_launcher(p.dtype, beta0)(&a, grid, stream);
+    }
     if (config_is_staged(c)) {
         const StagedRow* rows;
         const int nr = staged_rows(p.dtype, beta0, &rows);
@@ -117,6 +121,8 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
     char buf[128];
     if (p.family == TTX_FAMILY_FLAT) {
         std::snprintf(buf, sizeof(buf), "k_flat<%s, %s>", t, z);
+    } else if (config_is_dense(c)) {
+        std::snprintf(buf, sizeof(buf), "k_dense<%s, %s, %d>", t, z, dense_cap(p.dtype));
     } else if (p.family == TTX_FAMILY_MOVED) {
         const int va = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
         const int vb = (f & KF_VEC_B) && c.tile_b % V == 0 ? V : 1;

@@ -40,13 +40,18 @@
     X(16, 16, 8) X(16, 8, 16) X(16, 4, 32) X(16, 32, 4) X(32, 8, 8) X(32, 4, 16)          \
     X(32, 16, 4) X(32, 2, 32) X(32, 32, 2) X(64, 4, 8) X(64, 8, 4) X(64, 4, 4)
 
+// Dense tiles: elements per tile, 4 per thread (4 KiB FP32, 8 KiB FP64).
+#define TTX_DENSE_CAP_F32 1024
+#define TTX_DENSE_CAP_F64 1024
+
 // Tile variants compiled into the persistent batched kernel, per dtype:
 // X(index, kind, p1, p2, p3).  For the moved, preserved and flat kinds
 // (TTX_FAMILY_*) p1 x p2 is the tile and p3 = 1 selects 16-byte accesses on
 // both sides; for TTX_BATCH_STAGED p1 is the row-lane count and p2 x p3 the
-// staged tile.  Kept small: every variant adds code to the one kernel and
+// staged tile; for TTX_BATCH_DENSE p1 is the dense capacity.  Kept small: every variant adds code to the one kernel and
 // its register and LDS needs set the kernel's occupancy.
 #define TTX_BATCH_STAGED 4
+#define TTX_BATCH_DENSE 5
 
 #define TTX_BATCH_MENU_F32(X)                                                             \
     X(0, TTX_FAMILY_MOVED, 64, 32, 1) X(1, TTX_FAMILY_MOVED, 32, 32, 1)                   \
@@ -55,7 +60,8 @@
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 1024, 1, 1)               \
     X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
-    X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)
+    X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
+    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F32, 0, 0)
 
 #define TTX_BATCH_MENU_F64(X)                                                             \
     X(0, TTX_FAMILY_MOVED, 32, 32, 1) X(1, TTX_FAMILY_MOVED, 32, 16, 1)                   \
@@ -64,6 +70,7 @@
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 512, 1, 1)                \
     X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
-    X(12, TTX_BATCH_STAGED, 32, 4, 4) X(13, TTX_BATCH_STAGED, 64, 4, 4)
+    X(12, TTX_BATCH_STAGED, 32, 4, 4) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
+    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F64, 0, 0)
 
-#define TTX_BATCH_MENU_SIZE 14
+#define TTX_BATCH_MENU_SIZE 15

@@ -226,15 +226,15 @@ static bool make_layout(const Problem& p, int ga, int gb, Layout* L) {
         return true;
     }
     if (p.family == TTX_FAMILY_PRESERVED) {
-        // staged: A's indices 1..ga-1 (contiguous in A after the row index) and
-        // B's indices perm[1..gb-1] (contiguous in B after it) span the tile;
-        // the row index 0 lies wholly inside every tile
+        // staged: A's indices 1..ga-1 (contiguous with each other in A) and
+        // B's indices perm[1..gb-1] (contiguous with each other in B) span the
+        // tile; the row index 0 lies wholly inside every tile
         if (L->ga < 2 || L->gb < 2 || L->ga > kMaxGroup + 1 || L->gb > kMaxGroup + 1) return false;
         if (L->ga > p.n || L->gb > p.n || staged_lanes(p.dim[0].size) == 0) return false;
         bool inA[kMaxDims] = {};
         L->SA = 1;
         for (int k = 1; k < L->ga; ++k) {
-            if (p.dim[k].sa != p.dim[k - 1].sa * p.dim[k - 1].size) return false;
+            if (k > 1 && p.dim[k].sa != p.dim[k - 1].sa * p.dim[k - 1].size) return false;
             L->memA[k - 1] = k;
             inA[k] = true;
             L->SA *= p.dim[k].size;
@@ -242,7 +242,7 @@ static bool make_layout(const Problem& p, int ga, int gb, Layout* L) {
         L->SB = 1;
         for (int k = 1; k < L->gb; ++k) {
             const int d = p.perm[k], prev = p.perm[k - 1];
-            if (inA[d] || p.dim[d].sb != p.dim[prev].sb * p.dim[prev].size) return false;
+            if (inA[d] || (k > 1 && p.dim[d].sb != p.dim[prev].sb * p.dim[prev].size)) return false;
             L->memB[k - 1] = d;
             L->SB *= p.dim[d].size;
         }
@@ -340,7 +340,7 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     };
     if (c.family != p.family) return bad("config family does not match the problem");
     if (c.threads != kThreads) return bad("threads must be 256");
-    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE)) return bad("unknown flag");
+    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE)) return bad("unknown flag");
     if (p.family == TTX_FAMILY_EMPTY) return true;
     if (c.n_order != p.n) return bad("order must list every merged index");
     bool seen[kMaxDims] = {};
@@ -351,8 +351,18 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     }
     Layout L;
     if (!make_layout(p, c.group_a, c.group_b, &L)) return bad("invalid index groups for this problem");
-    if (p.family == TTX_FAMILY_FLAT) return true;
-    if (L.staged) {
+    if (p.family == TTX_FAMILY_FLAT) {
+        if (config_is_dense(c)) return bad("dense tiles need a moved or preserved problem");
+        return true;
+    }
+    if (config_is_dense(c)) {
+        if (p.family == TTX_FAMILY_PRESERVED && !L.staged)
+            return bad("dense preserved tiles need index groups (short rows)");
+        const int64_t rows = L.staged ? p.dim[0].size : 1;
+        if (c.tile_a < 1 || c.tile_b < 1 || c.tile_a > dense_cap(p.dtype) || c.tile_b > dense_cap(p.dtype) ||
+            rows * c.tile_a * c.tile_b > dense_cap(p.dtype))
+            return bad("dense tile larger than the dense capacity");
+    } else if (L.staged) {
         if (!staged_in_menu(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b))
             return bad("staged tile shape not in menu");
     } else if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b)) {
@@ -423,6 +433,16 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
     h->s0A = p.dim[0].sa;
     h->s0B = p.dim[0].sb;
     h->n0 = int(p.dim[0].size);
+    // dense tiles (harmless values for the other kinds)
+    h->dn0 = L.staged ? int(p.dim[0].size) : 1;
+    h->tx = c.tile_a > 0 ? c.tile_a : 1;
+    h->ty = c.tile_b > 0 ? c.tile_b : 1;
+    h->runA = uint32_t(h->dn0) * uint32_t(h->tx);
+    h->runB = uint32_t(h->dn0) * uint32_t(h->ty);
+    h->ldr = int(h->runA % 2 == 0 ? h->runA + 1 : h->runA);   // odd rows spread the banks
+    h->dv0.init(uint32_t(h->dn0));
+    h->dvA.init(h->runA);
+    h->dvB.init(h->runB);
 }
 
 static bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
@@ -438,6 +458,7 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
         if (p.dim[0].sa == 1 && p.dim[0].sb == 1 && aligned16(A) && bptrs) f |= KF_VEC_A;
         return f;
     }
+    if (config_is_dense(c)) return f;   // dense tiles move single elements
     Layout L;
     if (!make_layout(p, c.group_a, c.group_b, &L)) return f;
     if (L.staged) return f;   // staged tiles move single elements
@@ -507,6 +528,65 @@ static double staged_cost(const Problem& p, const Layout& L, int tx, int ty) {
         }
     if (useful == 0) return 1e30;
     return traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
+}
+
+// Dense tiles: A runs of n0*tx elements, B runs of n0*ty, CAP slots per tile
+// (idle slots cost issue time, as idle lanes do).  Element-wise accesses are
+// charged a fixed 15% over the 16-byte vector tiles.
+static constexpr double kDensePenalty = 1.15;
+
+static double dense_cost(const Problem& p, const Layout& L, int tx, int ty) {
+    const double e = elem_bytes(p.dtype);
+    const double n0 = L.staged ? double(p.dim[0].size) : 1.0, cap = dense_cap(p.dtype);
+    double traffic = 0, useful = 0, slots = 0, work = 0;
+    for (int ix = 0; ix < 2; ++ix)
+        for (int iy = 0; iy < 2; ++iy) {
+            const double cx = ix ? (L.SA % tx ? 1 : 0) : double(L.SA / tx);
+            const double cy = iy ? (L.SB % ty ? 1 : 0) : double(L.SB / ty);
+            const double ex = ix ? double(L.SA % tx) : tx, ey = iy ? double(L.SB % ty) : ty;
+            const double cnt = cx * cy;
+            if (cnt == 0) continue;
+            traffic += cnt * (ey * lines(n0 * ex * e) + ex * lines(n0 * ey * e) + kTileOverhead);
+            useful += cnt * 2.0 * n0 * ex * ey * e;
+            slots += cnt * cap;
+            work += cnt * n0 * ex * ey;
+        }
+    if (useful == 0) return 1e30;
+    return kDensePenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
+}
+
+// Dense tile extents worth trying: tx from powers of two, the whole extent
+// and near-even splits of it; ty as large as the capacity allows, or an
+// even split of B's extent.
+static std::vector<TileShape> dense_shapes(const Problem& p, const Layout& L) {
+    std::vector<TileShape> out;
+    const int64_t n0 = L.staged ? p.dim[0].size : 1, cap = dense_cap(p.dtype);
+    const int64_t maxa = cap / n0;
+    if (maxa < 1) return out;
+    std::vector<int64_t> txs;
+    for (int64_t v = 1; v <= maxa; v *= 2) txs.push_back(std::min<int64_t>(v, L.SA));
+    for (int64_t k = 1; k <= 8; ++k) {
+        const int64_t v = (L.SA + k - 1) / k;
+        if (v <= maxa) txs.push_back(v);
+    }
+    std::sort(txs.begin(), txs.end());
+    txs.erase(std::unique(txs.begin(), txs.end()), txs.end());
+    for (int64_t tx : txs) {
+        const int64_t tymax = std::min<int64_t>(cap / (n0 * tx), L.SB);
+        if (tymax < 1) continue;
+        const int64_t even = (L.SB + ((L.SB + tymax - 1) / tymax) - 1) / ((L.SB + tymax - 1) / tymax);
+        for (int64_t ty : {tymax, even}) {
+            bool dup = false;
+            for (const auto& t : out) dup |= t.ta == tx && t.tb == ty;
+            if (!dup) out.push_back(TileShape{int(tx), int(ty)});
+        }
+    }
+    return out;
+}
+
+// Whether a layout can take dense tiles.
+static bool dense_layout(const Problem& p, const Layout& L) {
+    return p.family == TTX_FAMILY_MOVED || (p.family == TTX_FAMILY_PRESERVED && L.staged);
 }
 
 static double blocking_cost(const Problem& p, const Layout& L, int ta, int tb) {
@@ -709,6 +789,17 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
                               make_config(p, shapes[s].ta, shapes[s].tb, o, f, ga, gb));
                 }
             }
+            if (!dense_layout(p, L)) continue;
+            for (const TileShape& d : dense_shapes(p, L)) {
+                ttx_config probe = make_config(p, d.ta, d.tb, orders[0], TTX_CFG_DENSE, ga, gb);
+                if (!config_valid(p, probe, nullptr)) continue;
+                double bc = dense_cost(p, L, d.ta, d.tb);
+                for (const auto& o : orders) {
+                    double oc = order_cost(p, L, d.ta, d.tb, o.data(), p.n);
+                    for (int f : flag_sets)
+                        offer(bc * (1.0 + oc) + flag_cost(f), make_config(p, d.ta, d.tb, o, f | TTX_CFG_DENSE, ga, gb));
+                }
+            }
         }
     }
     std::vector<Cand> all;
@@ -726,7 +817,7 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
 }
 
 ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
-                               const TileShape* staged, int nstaged) {
+                               const TileShape* staged, int nstaged, bool dense) {
     ttx_config best;
     std::memset(&best, 0, sizeof(best));
     best.family = p.family;
@@ -780,6 +871,24 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
                 best = c;
             }
         }
+        if (!dense || !dense_layout(p, L)) continue;
+        for (const TileShape& d : dense_shapes(p, L)) {
+            std::vector<int> o = grid_indices(p, L);
+            auto span = [&](int q) {
+                double cnt, sA, sB;
+                grid_step(p, L, q, d.ta, d.tb, &cnt, &sA, &sB);
+                return sA + sB;
+            };
+            std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
+            o.insert(o.end(), tail.begin(), tail.end());
+            ttx_config c = make_config(p, d.ta, d.tb, o, TTX_CFG_DENSE, ga, gb);
+            if (!config_valid(p, c, nullptr)) continue;
+            double cost = dense_cost(p, L, d.ta, d.tb) * (1.0 + order_cost(p, L, d.ta, d.tb, o.data(), p.n));
+            if (cost < bestc) {
+                bestc = cost;
+                best = c;
+            }
+        }
     }
     return best;
 }
@@ -787,7 +896,7 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
 ttx_config default_config(const Problem& p) {
     const TileShape* shapes;
     int ns = tile_menu(p.dtype, p.family, &shapes);
-    return default_config_from(p, shapes, ns, nullptr, -1);
+    return default_config_from(p, shapes, ns, nullptr, -1, true);
 }
 
 }  // namespace ttx

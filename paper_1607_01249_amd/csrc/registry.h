@@ -28,4 +28,7 @@ struct StagedRow {
 };
 int staged_rows(int dtype, bool beta0, const StagedRow** out);
 
+// The dense-tile kernel for a dtype and beta class.
+TileLaunchFn dense_launcher(int dtype, bool beta0);
+
 }  // namespace ttx

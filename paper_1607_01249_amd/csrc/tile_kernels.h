@@ -151,6 +151,8 @@ struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
     static constexpr int NT = kThreads, LDR = TA + 1;
+    __device__ static int ext_a(const TileArgs<T>&) { return TA; }
+    __device__ static int ext_b(const TileArgs<T>&) { return TB; }
     // A side: columns (fixed y) of TA elements along x
     static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
     // B side: rows (fixed x) of TB elements along y
@@ -180,7 +182,7 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileCoord& c) {
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int xa = (tid % PA) * VA, ya = tid / PA;
         if ((tid % PA) >= LA) return;
@@ -223,6 +225,27 @@ struct MovedTile {
             if (live_b && x < c.ea) st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], nt);
         }
     }
+
+    // from_lds and store in one pass (no tile held in registers in between)
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+                                               const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int yb = (tid % PB) * VB, xb = tid / PB;
+        const bool live_b = (tid % PB) < LB && yb < c.eb;
+        const bool nt = a.flags & KF_NT_STORE;
+        const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int x = xb + i * RB;
+            if (live_b && x < c.ea) {
+                vec_t<T, VB> v;
+#pragma unroll
+                for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
+                st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
+                          nt);
+            }
+        }
+    }
 };
 
 // One preserved-family tile: rows of ea elements contiguous in A and B.
@@ -233,6 +256,8 @@ struct PreservedTile {
     static constexpr bool kUsesLds = false;
     static constexpr int kTA = TA, kTB = TR;
     static constexpr int NT = kThreads;
+    __device__ static int ext_a(const TileArgs<T>&) { return TA; }
+    __device__ static int ext_b(const TileArgs<T>&) { return TR; }
     static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
 
@@ -270,6 +295,20 @@ struct PreservedTile {
         for (int i = 0; i < N; ++i)
             if (live && y0 + i * R < c.eb) st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], nt);
     }
+
+    // finish and store in one pass
+    __device__ __forceinline__ void finish_store(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const int x = (tid % P) * V, y0 = tid / P;
+        const bool live = (tid % P) < L && x < c.ea;
+        const bool nt = a.flags & KF_NT_STORE;
+        const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (live && y0 + i * R < c.eb)
+                st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
+                         epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta), nt);
+    }
 };
 
 // One staged preserved-family tile, for short stride-1 rows: rows of n0
@@ -285,6 +324,8 @@ struct StagedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TX, kTB = TY;
     static constexpr int NT = kThreads, LDR = TX * N0 + 1;
+    __device__ static int ext_a(const TileArgs<T>&) { return TX; }
+    __device__ static int ext_b(const TileArgs<T>&) { return TY; }
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
     static constexpr int PA = N0 * TX, PB = N0 * TY;
     static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
@@ -318,7 +359,7 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileCoord& c) {
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
@@ -352,7 +393,141 @@ struct StagedTile {
                          out[i], nt);
         }
     }
+
+    // from_lds and store in one pass
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+                                               const TileCoord& c) {
+        const int tid = threadIdx.x, n0 = a.n0;
+        const bool nt = a.flags & KF_NT_STORE;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * NT, r = e % PB, x = e / PB;
+            const int iv = r % N0, y = r / N0;
+            if (iv < n0 && y < c.eb && x < c.ea) {
+                const T v = lds[y * LDR + x * N0 + iv];
+                st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
+                         epilogue<T, 1, BETA0>(v, rb[i], a.alpha, a.beta), nt);
+            }
+        }
+    }
 };
+
+// One dense tile: rows of n0 = dn0 elements (the shared stride-1 index of
+// the preserved family; n0 = 1 for the moved family), tx rows along A's super
+// index x and ty rows along B's super index y, with tx and ty run-time values
+// and n0 * tx * ty <= CAP.  Element (i, x0 + x, y0 + y) is
+//   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
+// Slot e of the tile (e = tid + s*NT) is read as A-run element
+// (y = e / runA, i + n0*x = e % runA) and written as B-run element
+// (x = e / runB, i + n0*y = e % runB), so that both sides run along their
+// contiguous index without padding lanes to a power of two.  The tile passes
+// through LDS as [y][x][i], rows of ldr >= runA elements (odd when possible).
+template <typename T, bool BETA0, int CAP>
+struct DenseTile {
+    static constexpr bool kUsesLds = true;
+    static constexpr int NT = kThreads, NS = CAP / NT;
+    static_assert(CAP % NT == 0, "whole passes");
+    __device__ static int ext_a(const TileArgs<T>& a) { return a.tx; }
+    __device__ static int ext_b(const TileArgs<T>& a) { return a.ty; }
+
+    T ra[NS];
+    T rb[NS];
+    T out[NS];
+
+    // A-side coordinates of slot e: row y, and r = i + n0*x within the row
+    __device__ __forceinline__ static void a_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
+                                                  uint32_t& i, uint32_t& r) {
+        y = a.dvA.div(e);
+        r = e - y * a.runA;
+        x = a.dv0.div(r);
+        i = r - x * uint32_t(a.dn0);
+    }
+    // B-side coordinates of slot e
+    __device__ __forceinline__ static void b_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
+                                                  uint32_t& i) {
+        x = a.dvB.div(e);
+        const uint32_t r = e - x * a.runB;
+        y = a.dv0.div(r);
+        i = r - y * uint32_t(a.dn0);
+    }
+    __device__ __forceinline__ static int64_t b_offset(const TileArgs<T>& a, const TileCoord& c, uint32_t x,
+                                                       uint32_t y, uint32_t i) {
+        return c.ob + int64_t(i) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x);
+    }
+
+    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+        const uint32_t tid = threadIdx.x;
+        const T* A0 = a.A + c.oa;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t x, y, i, r;
+            a_slot(a, tid + s * NT, x, y, i, r);
+            if (x < uint32_t(c.ea) && y < uint32_t(c.eb))
+                ra[s] = A0[int64_t(i) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y)];
+        }
+        if constexpr (!BETA0) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                uint32_t x, y, i;
+                b_slot(a, tid + s * NT, x, y, i);
+                if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) rb[s] = a.Bsrc[b_offset(a, c, x, y, i)];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>& a, const TileCoord& c) {
+        const uint32_t tid = threadIdx.x;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t x, y, i, r;
+            a_slot(a, tid + s * NT, x, y, i, r);
+            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) lds[y * uint32_t(a.ldr) + r] = ra[s];
+        }
+    }
+
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+                                             const TileCoord& c) {
+        const uint32_t tid = threadIdx.x;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t x, y, i;
+            b_slot(a, tid + s * NT, x, y, i);
+            if (x < uint32_t(c.ea) && y < uint32_t(c.eb))
+                out[s] = epilogue<T, 1, BETA0>(lds[y * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i], rb[s],
+                                               a.alpha, a.beta);
+        }
+    }
+
+    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+        const uint32_t tid = threadIdx.x;
+        const bool nt = a.flags & KF_NT_STORE;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t x, y, i;
+            b_slot(a, tid + s * NT, x, y, i);
+            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) st<T, 1>(a.Bdst + b_offset(a, c, x, y, i), out[s], nt);
+        }
+    }
+
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+                                               const TileCoord& c) {
+        const uint32_t tid = threadIdx.x;
+        const bool nt = a.flags & KF_NT_STORE;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t x, y, i;
+            b_slot(a, tid + s * NT, x, y, i);
+            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) {
+                const T v = lds[y * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i];
+                st<T, 1>(a.Bdst + b_offset(a, c, x, y, i), epilogue<T, 1, BETA0>(v, rb[s], a.alpha, a.beta), nt);
+            }
+        }
+    }
+};
+
+// LDS elements of a dense tile: ty rows of ldr <= runA + 1 elements, with
+// runA * ty <= CAP and ty <= CAP.
+constexpr int dense_lds_elems(int cap) { return 2 * cap; }
 
 // Tiles t, t + step, ... < end of one problem.  With PIPE, tile k+1's loads
 // are issued between tile k's LDS read and its stores, as described above;
@@ -363,36 +538,43 @@ template <class Tile, bool PIPE, typename T>
 __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>& a, uint32_t t,
                                           uint32_t end, uint32_t step) {
     Tile tile;
-    TileCoord c = decode_tile(a.g, t, Tile::kTA, Tile::kTB);
-    tile.load(a, c);
-    while (true) {
-        if constexpr (Tile::kUsesLds) {
-            tile.to_lds(lds, c);
-            __syncthreads();
-            tile.from_lds(lds, a, c);
-        } else {
-            tile.finish(a, c);
+    if constexpr (!PIPE) {
+        for (uint64_t u = t; u < end; u += step) {
+            const TileCoord c = decode_tile(a.g, uint32_t(u), Tile::ext_a(a), Tile::ext_b(a));
+            tile.load(a, c);
+            if constexpr (Tile::kUsesLds) {
+                tile.to_lds(lds, a, c);
+                __syncthreads();
+                tile.read_store(lds, a, c);
+                __syncthreads();   // the next tile rewrites the LDS tile
+            } else {
+                tile.finish_store(a, c);
+            }
         }
-        const uint64_t tn = uint64_t(t) + step;
-        const bool more = tn < end;
-        if constexpr (PIPE) {
+    } else {
+        TileCoord c = decode_tile(a.g, t, Tile::ext_a(a), Tile::ext_b(a));
+        tile.load(a, c);
+        while (true) {
+            if constexpr (Tile::kUsesLds) {
+                tile.to_lds(lds, a, c);
+                __syncthreads();
+                tile.from_lds(lds, a, c);
+            } else {
+                tile.finish(a, c);
+            }
+            const uint64_t tn = uint64_t(t) + step;
+            const bool more = tn < end;
             TileCoord cn = c;
             if (more) {
-                cn = decode_tile(a.g, uint32_t(tn), Tile::kTA, Tile::kTB);
+                cn = decode_tile(a.g, uint32_t(tn), Tile::ext_a(a), Tile::ext_b(a));
                 tile.load(a, cn);
             }
             tile.store(a, c);
             if constexpr (Tile::kUsesLds) __syncthreads();   // the LDS tile is rewritten next
             if (!more) break;
             c = cn;
-        } else {
-            tile.store(a, c);
-            if (!more) break;
-            if constexpr (Tile::kUsesLds) __syncthreads();
-            c = decode_tile(a.g, uint32_t(tn), Tile::kTA, Tile::kTB);
-            tile.load(a, c);
+            t = uint32_t(tn);
         }
-        t = uint32_t(tn);
     }
 }
 
@@ -418,6 +600,14 @@ void k_preserved(TileArgs<T> a) {
     const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
     if (first < a.g.ntiles)
         tile_loop<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
+}
+
+template <typename T, bool BETA0, int CAP>
+__global__ __launch_bounds__(kThreads) void k_dense(TileArgs<T> a) {
+    __shared__ T lds[dense_lds_elems(CAP)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP>, false>(lds, a, first, a.g.ntiles, G);
 }
 
 template <typename T, bool BETA0, int N0, int TX, int TY>

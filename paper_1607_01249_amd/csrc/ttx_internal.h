@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/ttx.h"
+#include "menu.h"
 
 namespace ttx {
 
@@ -94,6 +95,12 @@ struct TileArgsHost {
     Group gB;           // A offsets of the B-side super index (moved and staged tiles)
     int64_t s0A, s0B;   // staged tiles: strides of the shared row index in A and B
     int n0;             // staged tiles: row length
+    // dense tiles: rows of dn0 elements (1 for the moved family), tx x ty rows
+    // per tile; an A run holds runA = dn0*tx elements, a B run runB = dn0*ty;
+    // the LDS tile has ty rows of ldr >= runA elements
+    int dn0, tx, ty, ldr;
+    uint32_t runA, runB;
+    FastDiv dv0, dvA, dvB;
 };
 
 template <typename T>
@@ -165,9 +172,9 @@ ttx_config default_config(const Problem& p);
 // The same greedy choice restricted to the given tile shapes; staged tiles
 // (preserved family, short rows) come from `staged` entries packed as
 // {lanes * 65536 + tile_x, tile_y}, or from the whole staged menu when
-// nstaged < 0.
+// nstaged < 0; dense tiles are considered when `dense` is set.
 ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
-                               const TileShape* staged, int nstaged);
+                               const TileShape* staged, int nstaged, bool dense);
 // Candidate enumeration with estimated costs (sorted ascending).
 int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost, int cap);
 // Builds the kernel-side grid, strides and index groups for a config.
@@ -183,10 +190,14 @@ bool tile_in_menu(int dtype, int family, int ta, int tb);
 // the rows are too long to stage) and whether (n0_max, tx, ty) is instantiated.
 int staged_lanes(int64_t n0);
 bool staged_in_menu(int dtype, int n0_max, int tx, int ty);
-// A preserved-family config with index groups selects the staged tiles.
+// A preserved-family config with index groups selects the staged tiles
+// (the padded-lane kind unless dense).
+inline bool config_is_dense(const ttx_config& c) { return (c.flags & TTX_CFG_DENSE) != 0; }
 inline bool config_is_staged(const ttx_config& c) {
-    return c.family == TTX_FAMILY_PRESERVED && (c.group_a > 1 || c.group_b > 1);
+    return c.family == TTX_FAMILY_PRESERVED && (c.group_a > 1 || c.group_b > 1) && !config_is_dense(c);
 }
+// Elements per dense tile.
+inline int dense_cap(int dtype) { return dtype == TTX_F32 ? TTX_DENSE_CAP_F32 : TTX_DENSE_CAP_F64; }
 constexpr int kThreads = 256;
 
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.

@@ -225,10 +225,58 @@ def test_candidate_list_is_bounded_and_sorted():
     # every menu shape x 4 flag sets x the loop orders of each index grouping:
     # 4! orders with single indices, and 3! when B's short stride-1 index (32)
     # is grouped with the next B index (the grid then has 3 indices)
-    assert len(allc) == 20 * 4 * (24 + 6)
+    fixed = [c for c in allc if not c.flags & ttx.CFG_DENSE]
+    assert len(fixed) == 20 * 4 * (24 + 6)
     assert {(c.group_a, c.group_b) for c in allc} == {(1, 1), (1, 2)}
+    # dense tiles: run-time extents within the capacity, the same loop orders
+    dense = [c for c in allc if c.flags & ttx.CFG_DENSE]
+    assert dense and len(dense) % (4 * 6) == 0
+    for c in dense:
+        assert 1 <= c.tile_a and 1 <= c.tile_b and c.tile_a * c.tile_b <= ttx.DENSE_CAP[ttx.F32]
     for c in cands:
         assert sorted(c.order[:c.n_order]) == [0, 1, 2, 3]
+
+
+def test_dense_tiles_validation_and_choice():
+    F = ttx.CFG_DENSE
+    # short rows of the kept stride-1 index (n0 = 2): dense tiles hold whole
+    # rows, so n0 * tile_a * tile_b is bounded by the capacity
+    cands, _ = ttx.ttx_tune_candidates(0, (0, 2, 1), (2, 17835, 2), max_candidates=-1, cap=100000)
+    dense = [c for c in cands if c.flags & F]
+    assert dense and all(c.group_a >= 2 and c.group_b >= 2 for c in dense)
+    assert all(2 * c.tile_a * c.tile_b <= ttx.DENSE_CAP[ttx.F32] for c in dense)
+    # the heuristic default picks a dense tile here (padded rows would idle most lanes)
+    d = _describe(0, (0, 2, 1), (2, 17835, 2))
+    assert d["config"][1]["flags"] & F
+    p = ttx.ttx_plan_create(0, (0, 2, 1), (2, 17835, 2))
+    try:
+        good = ttx.Config.from_buffer_copy(dense[0])
+        ttx.ttx_plan_set_config(p, 1, good)
+        assert "k_dense<float" in ttx.ttx_plan_kernel_name(p, 1, 1 << 40, 1 << 41)
+        bad = ttx.Config.from_buffer_copy(dense[0])
+        bad.tile_a, bad.tile_b = 64, 16            # 2 * 64 * 16 > 1024
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, bad)
+        bad = ttx.Config.from_buffer_copy(dense[0])
+        bad.group_a = bad.group_b = 1              # dense preserved tiles need row groups
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, bad)
+    finally:
+        ttx.ttx_plan_destroy(p)
+    # moved problems take dense tiles of any extents within the capacity
+    cands, _ = ttx.ttx_tune_candidates(1, (1, 0), (7, 3000), max_candidates=-1, cap=100000)
+    dense = [c for c in cands if c.flags & F]
+    assert dense and {c.tile_a for c in dense} >= {7}
+    assert all(c.tile_a * c.tile_b <= ttx.DENSE_CAP[ttx.F64] for c in dense)
+    # flat problems have no dense form
+    p = ttx.ttx_plan_create(0, (0, 1), (10, 10))
+    try:
+        cfg = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(p)["config_raw"][1])
+        cfg.flags |= F
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(p, 1, cfg)
+    finally:
+        ttx.ttx_plan_destroy(p)
 
 
 def test_blocking_heuristic_prefers_exact_tiles_and_skinny_for_short_index():

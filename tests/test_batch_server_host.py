@@ -44,16 +44,27 @@ def test_batch_plan_uses_the_batched_menu():
     qs = _fake_problems(probs)
     cfgs, tiles = ttx.ttx_batch_plan(qs)
     assert len(cfgs) == 512
+    dense = 0
     for q, c, t in zip(qs, cfgs, tiles):
-        assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(q.dtype, c.family)], c.as_dict()
+        # the merged row length (kept stride-1 index) of the kept family
+        plan = ttx.ttx_plan_create(q.dtype, list(q.perm[:q.n]), list(q.size[:q.n]))
+        n0 = ttx.ttx_plan_describe(plan)["size"][0]
+        ttx.ttx_plan_destroy(plan)
+        if c.flags & ttx.CFG_DENSE:     # dense tiles: run-time extents within the capacity
+            dense += 1
+            rows = n0 if c.family == ttx.FAMILY_PRESERVED else 1
+            assert rows * c.tile_a * c.tile_b <= ttx.DENSE_CAP[q.dtype], c.as_dict()
+        else:
+            assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(q.dtype, c.family)], c.as_dict()
         assert c.flags & ttx.CFG_XCD_SWIZZLE == 0
         # every element is covered: tiles * tile area >= elements (staged
         # tiles of the kept family also hold whole stride-1 rows)
         n = int(np.prod(list(q.size[:q.n])))
-        rows = max(q.size[:q.n]) if (c.family == ttx.FAMILY_PRESERVED and c.group_a > 1) else 1
+        rows = n0 if (c.family == ttx.FAMILY_PRESERVED and c.group_a > 1) else 1
         assert t >= 1 and t * c.tile_a * max(1, c.tile_b) * rows >= n
     fams = {c.family for c in cfgs}
     assert fams >= {ttx.FAMILY_MOVED, ttx.FAMILY_PRESERVED, ttx.FAMILY_FLAT}
+    assert dense > 0
 
 
 def test_batch_plan_misaligned_pointers_use_scalar_variants():

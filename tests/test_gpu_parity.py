@@ -280,3 +280,43 @@ def test_every_candidate_bit_identical(perm, size, dtype):
         for i in sorted(set(int(k) for k in pick)):
             got = gpu_transpose(perm, size, 1.3, A, beta, B, plan_config=cands[i])
             assert_parity(got, ref, exact=True, what=str(cands[i].as_dict()))
+
+
+# -- dense tiles (run-time extents, rows packed without padding) ----------------------------
+DENSE_CASES = [
+    ((0, 2, 1), (2, 17835, 2), None, None),            # kept stride-1 index, rows of 2
+    ((0, 2, 1, 3), (5, 40, 30, 3), None, None),        # rows of 5
+    ((0, 3, 1, 2), (20, 16, 7, 9), None, None),        # rows of 20
+    ((1, 0), (7, 3000), None, None),                   # moved, short stride-1 index
+    ((2, 0, 1), (6, 7, 500), None, None),
+    ((5, 4, 3, 2, 1, 0), (5, 7, 6, 4, 3, 5), None, None),
+    ((0, 2, 1), (6, 50, 40), (8, 52, 41), (7, 41, 51)),   # outer sizes on both sides
+    ((2, 1, 0), (33, 17, 29), (35, 17, 30), None),
+]
+
+
+@pytest.mark.parametrize("perm,size,oa,ob", DENSE_CASES)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_dense_tiles(perm, size, oa, ob, dtype):
+    code = ttx.F32 if dtype == F32 else ttx.F64
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, outer_a=oa, outer_b=ob, max_candidates=-1,
+                                       cap=200000)
+    dense = [c for c in cands if c.flags & ttx.CFG_DENSE]
+    assert dense, "no dense candidate"
+    # every distinct dense shape (first loop order of each), plus a spread of the rest
+    seen, pick = set(), []
+    for c in dense:
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b)
+        if key not in seen:
+            seen.add(key)
+            pick.append(c)
+    pick += dense[::max(1, len(dense) // 8)]
+    # the padded-row staged tiles of the same layouts (kept stride-1 index)
+    staged = [c for c in cands if c.family == ttx.FAMILY_PRESERVED and c.group_a > 1
+              and not c.flags & ttx.CFG_DENSE]
+    pick += staged[::max(1, len(staged) // 6)]
+    _say("dense %s %s: %d configs" % (perm, size, len(pick)))
+    for alpha, beta in ((1.0, 0.0), (-0.5, 1.0)):
+        for i, c in enumerate(pick):
+            got, ref, exact = _case(perm, size, dtype, alpha, beta, oa, ob, seed=40 + i % 3, plan_config=c)
+            assert_parity(got, ref, exact=exact, what=str(c.as_dict()))
