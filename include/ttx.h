@@ -102,8 +102,11 @@ typedef enum ttx_family {
  *             index times A's next group_a-1 and B's next group_b-1 indices;
  *             tile_a and tile_b then count rows along those super indices.
  *   With TTX_CFG_DENSE, tile_a and tile_b may be any positive extents with
- *   rows x tile_a x tile_b within the dense capacity (rows = the row length
- *   for PRESERVED, 1 for MOVED). */
+ *   rows x tile_a x tile_b x tile_c within the dense capacity (rows = the row
+ *   length for PRESERVED, 1 for MOVED);
+ *   tile_c  : dense tiles only -- extent along a third index, the first index
+ *             of `order` that is neither a tile index nor a group member, so
+ *             that one tile holds several small planes (0 or 1: one plane). */
 typedef struct ttx_config {
     int family;
     int tile_a;
@@ -114,6 +117,7 @@ typedef struct ttx_config {
     int flags;
     int group_a;   /* index groups, see above (1 = the single index) */
     int group_b;
+    int tile_c;    /* dense tiles: planes per tile along the third index (0 or 1: one) */
 } ttx_config;
 
 /* What the planner made of a problem (Sec. 2.1 stage 1 and the family split

@@ -41,12 +41,12 @@ class Config(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("tile_a", ctypes.c_int), ("tile_b", ctypes.c_int),
                 ("threads", ctypes.c_int), ("n_order", ctypes.c_int),
                 ("order", ctypes.c_int * MAX_DIMS), ("flags", ctypes.c_int),
-                ("group_a", ctypes.c_int), ("group_b", ctypes.c_int)]
+                ("group_a", ctypes.c_int), ("group_b", ctypes.c_int), ("tile_c", ctypes.c_int)]
 
     def as_dict(self):
         return dict(family=FAMILY_NAMES[self.family], tile_a=self.tile_a, tile_b=self.tile_b,
                     threads=self.threads, order=list(self.order[:self.n_order]), flags=self.flags,
-                    group_a=self.group_a, group_b=self.group_b)
+                    group_a=self.group_a, group_b=self.group_b, tile_c=self.tile_c)
 
 
 class PlanInfo(ctypes.Structure):

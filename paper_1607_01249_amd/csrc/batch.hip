@@ -122,6 +122,9 @@ __device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a
         tile_loop<StagedTile<T, B0, P1, P2, P3>, true>(l, a, t0, t1, 1);
     } else if constexpr (KIND == TTX_BATCH_DENSE) {
         tile_loop<DenseTile<T, B0, P1>, false>(l, a, t0, t1, 1);
+    } else if constexpr (KIND == TTX_FAMILY_FLAT) {
+        constexpr int V = P3 ? kVec<T> : 1;
+        tile_loop<FlatTile<T, B0, V, P1 / (kThreads * V)>, true>(l, a, t0, t1, 1);
     } else {
         constexpr int V = P3 ? kVec<T> : 1;
         if constexpr (KIND == TTX_FAMILY_MOVED)
@@ -323,7 +326,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     // the menu entry for a config (-1: none); flat configs get their tile here
     auto resolve = [&](ttx_config& k) -> int {
         if (p.family == TTX_FAMILY_FLAT) {
-            k.tile_a = vec ? (p.dtype == TTX_F32 ? 1024 : 512) : 256;
+            k.tile_a = vec ? (p.dtype == TTX_F32 ? 4096 : 2048) : 1024;
             k.tile_b = 1;
             return batch_index(p.dtype, p.family, k.tile_a, 1, vec ? 1 : 0);
         }

@@ -47,7 +47,8 @@
 // Tile variants compiled into the persistent batched kernel, per dtype:
 // X(index, kind, p1, p2, p3).  For the moved, preserved and flat kinds
 // (TTX_FAMILY_*) p1 x p2 is the tile and p3 = 1 selects 16-byte accesses on
-// both sides; for TTX_BATCH_STAGED p1 is the row-lane count and p2 x p3 the
+// both sides (flat tiles: p1 consecutive elements, four per thread, in
+// vectors or single elements); for TTX_BATCH_STAGED p1 is the row-lane count and p2 x p3 the
 // staged tile; for TTX_BATCH_DENSE p1 is the dense capacity.  Kept small: every variant adds code to the one kernel and
 // its register and LDS needs set the kernel's occupancy.
 #define TTX_BATCH_STAGED 4
@@ -58,8 +59,8 @@
     X(2, TTX_FAMILY_MOVED, 32, 64, 1) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
     X(4, TTX_FAMILY_MOVED, 8, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 8, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
-    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 1024, 1, 1)               \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
+    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 4096, 1, 1)               \
+    X(10, TTX_FAMILY_FLAT, 1024, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                  \
     X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
     X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F32, 0, 0)
 
@@ -68,8 +69,8 @@
     X(2, TTX_FAMILY_MOVED, 16, 32, 1) X(3, TTX_FAMILY_MOVED, 32, 32, 0)                   \
     X(4, TTX_FAMILY_MOVED, 4, 128, 0) X(5, TTX_FAMILY_MOVED, 128, 4, 0)                   \
     X(6, TTX_FAMILY_PRESERVED, 64, 16, 1) X(7, TTX_FAMILY_PRESERVED, 64, 16, 0)           \
-    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 512, 1, 1)                \
-    X(10, TTX_FAMILY_FLAT, 256, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                   \
+    X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 2048, 1, 1)               \
+    X(10, TTX_FAMILY_FLAT, 1024, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                  \
     X(12, TTX_BATCH_STAGED, 32, 4, 4) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
     X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F64, 0, 0)
 

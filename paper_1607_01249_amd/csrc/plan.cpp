@@ -331,6 +331,16 @@ static Group make_group(const Problem& p, const int* members, int ng, bool strid
     return g;
 }
 
+// The third index of a dense tile: the first index of the loop order that is
+// neither a tile index nor a group member (-1 if there is none).
+static int dense_z(const Problem& p, const Layout& L, const int* order, int n) {
+    for (int k = 0; k < n; ++k) {
+        const int d = order[k];
+        if (d != L.a && d != L.b && !L.member[d]) return d;
+    }
+    return -1;
+}
+
 // ---------------------------------------------------------------------------------------
 // Config validation and the kernel-side grid
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
@@ -355,13 +365,21 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
         if (config_is_dense(c)) return bad("dense tiles need a moved or preserved problem");
         return true;
     }
+    const int64_t tc = c.tile_c > 1 ? c.tile_c : 1;
+    int z = -1;
     if (config_is_dense(c)) {
         if (p.family == TTX_FAMILY_PRESERVED && !L.staged)
             return bad("dense preserved tiles need index groups (short rows)");
         const int64_t rows = L.staged ? p.dim[0].size : 1;
         if (c.tile_a < 1 || c.tile_b < 1 || c.tile_a > dense_cap(p.dtype) || c.tile_b > dense_cap(p.dtype) ||
-            rows * c.tile_a * c.tile_b > dense_cap(p.dtype))
+            tc > dense_cap(p.dtype) || rows * c.tile_a * c.tile_b * tc > dense_cap(p.dtype))
             return bad("dense tile larger than the dense capacity");
+        if (tc > 1) {
+            z = dense_z(p, L, c.order, c.n_order);
+            if (z < 0) return bad("tile_c needs a third index outside the tile");
+        }
+    } else if (tc > 1) {
+        return bad("tile_c is for dense tiles only");
     } else if (L.staged) {
         if (!staged_in_menu(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b))
             return bad("staged tile shape not in menu");
@@ -372,7 +390,7 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     uint64_t tiles = uint64_t((L.SA + c.tile_a - 1) / c.tile_a) * uint64_t((L.SB + c.tile_b - 1) / c.tile_b);
     for (int d = 0; d < p.n; ++d) {
         if (d == L.a || d == L.b || L.member[d]) continue;
-        tiles *= uint64_t(p.dim[d].size);
+        tiles *= d == z ? uint64_t((p.dim[d].size + tc - 1) / tc) : uint64_t(p.dim[d].size);
         if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
     }
     if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
@@ -384,8 +402,10 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
     make_layout(p, c.group_a, c.group_b, &L);
     TileGrid* g = &h->g;
     std::memset(g, 0, sizeof(*g));
-    g->pa = g->pb = -1;
+    g->pa = g->pb = g->pz = -1;
     const bool moved = p.family == TTX_FAMILY_MOVED || L.staged;
+    const int tc = config_is_dense(c) && c.tile_c > 1 ? c.tile_c : 1;
+    const int z = tc > 1 ? dense_z(p, L, c.order, c.n_order) : -1;
     uint64_t tiles = 1;
     int q = 0;
     for (int i = 0; i < p.n; ++i) {
@@ -399,6 +419,8 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
         } else if (d == L.b) {
             ext = c.tile_b;
             extent = L.SB;
+        } else if (d == z) {
+            ext = tc;
         }
         stepA = ext * p.dim[d].sa;
         stepB = ext * p.dim[d].sb;
@@ -413,6 +435,7 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
         g->stepB[q] = stepB;
         if (d == L.a) g->pa = q;
         if (d == L.b) g->pb = q;
+        if (d == z) g->pz = q;
         tiles *= cnt;
         ++q;
     }
@@ -443,6 +466,14 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
     h->dv0.init(uint32_t(h->dn0));
     h->dvA.init(h->runA);
     h->dvB.init(h->runB);
+    g->ext_z = z >= 0 ? p.dim[z].size : 1;
+    h->tz = tc;
+    h->sAz = z >= 0 ? p.dim[z].sa : 0;
+    h->sBz = z >= 0 ? p.dim[z].sb : 0;
+    h->planeA = h->runA * uint32_t(h->ty);
+    h->planeB = h->runB * uint32_t(h->tx);
+    h->dvPA.init(h->planeA);
+    h->dvPB.init(h->planeB);
 }
 
 static bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
@@ -507,6 +538,10 @@ static constexpr double kLine = 128.0;
 static constexpr double kTileOverhead = 1536.0;  // bytes-equivalent per tile
 static constexpr double kResident = 2048.0;
 
+// Element-wise accesses (dense and staged tiles, and menu tiles whose runs
+// cannot take 16-byte vectors) are charged a fixed 15% over vector tiles.
+static constexpr double kScalarPenalty = 1.15;
+
 static double lines(double bytes) { return std::ceil(bytes / kLine) * kLine; }
 
 // Staged tiles: A runs of n0*x rows, B runs of n0*y rows, n0_max lanes per row.
@@ -527,32 +562,92 @@ static double staged_cost(const Problem& p, const Layout& L, int tx, int ty) {
             work += cnt * n0 * ex * ey;
         }
     if (useful == 0) return 1e30;
-    return traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
+    return kScalarPenalty * traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
 }
 
-// Dense tiles: A runs of n0*tx elements, B runs of n0*ty, CAP slots per tile
-// (idle slots cost issue time, as idle lanes do).  Element-wise accesses are
-// charged a fixed 15% over the 16-byte vector tiles.
-static constexpr double kDensePenalty = 1.15;
+// Whether a menu tile of this layout can use 16-byte accesses on both sides,
+// judged from extents and strides alone (pointer alignment aside).
+static bool vector_shape(const Problem& p, const Layout& L, int ta, int tb) {
+    const int V = 16 / elem_bytes(p.dtype);
+    if (L.staged) return false;
+    bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
+    for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
+    for (int k = 0; k < L.gb; ++k) inB[L.memB[k]] = true;
+    if (p.family == TTX_FAMILY_PRESERVED) {
+        bool ok = p.dim[0].sa == 1 && p.dim[0].sb == 1 && ta % V == 0 && p.dim[0].size % V == 0;
+        for (int d = 1; d < p.n && ok; ++d) ok = p.dim[d].sa % V == 0 && p.dim[d].sb % V == 0;
+        return ok;
+    }
+    bool ok = p.dim[L.a].sa == 1 && ta % V == 0 && L.SA % V == 0 && p.dim[L.b].sb == 1 && tb % V == 0 &&
+              L.SB % V == 0;
+    for (int d = 0; d < p.n && ok; ++d) {
+        if (!inA[d]) ok = p.dim[d].sa % V == 0;
+        if (ok && !inB[d]) ok = p.dim[d].sb % V == 0;
+    }
+    return ok;
+}
 
-static double dense_cost(const Problem& p, const Layout& L, int tx, int ty) {
+// Dense tiles: rows of n0, tx x ty rows per plane, tz planes (along index z,
+// -1 for none), CAP slots per tile (idle slots cost issue time, as idle
+// lanes do).  A is read in runs along (row, x), which continue across y and
+// then z where those are adjacent in A and the tile spans the whole extent
+// before them; B likewise along (row, y), then x, then z.
+static double dense_cost(const Problem& p, const Layout& L, int tx, int ty, int tz, int z) {
     const double e = elem_bytes(p.dtype);
-    const double n0 = L.staged ? double(p.dim[0].size) : 1.0, cap = dense_cap(p.dtype);
+    const int64_t n0 = L.staged ? p.dim[0].size : 1;
+    const double cap = dense_cap(p.dtype);
+    const int64_t zs = z >= 0 ? p.dim[z].size : 1;
+    // element strides of the tile's coordinates in A and B
+    const int64_t rowA = L.staged ? p.dim[0].size * p.dim[0].sa : 1;      // contiguous (row, x) runs
+    const bool xa_lin = L.staged ? p.dim[L.a].sa == rowA : true;
+    const int64_t rowB = L.staged ? p.dim[0].size * p.dim[0].sb : 1;
+    const bool yb_lin = L.staged ? p.dim[L.b].sb == rowB : true;
+    const bool y_single = L.staged ? L.gb == 2 : L.gb == 1;
+    const bool x_single = L.staged ? L.ga == 2 : L.ga == 1;
     double traffic = 0, useful = 0, slots = 0, work = 0;
     for (int ix = 0; ix < 2; ++ix)
-        for (int iy = 0; iy < 2; ++iy) {
-            const double cx = ix ? (L.SA % tx ? 1 : 0) : double(L.SA / tx);
-            const double cy = iy ? (L.SB % ty ? 1 : 0) : double(L.SB / ty);
-            const double ex = ix ? double(L.SA % tx) : tx, ey = iy ? double(L.SB % ty) : ty;
-            const double cnt = cx * cy;
-            if (cnt == 0) continue;
-            traffic += cnt * (ey * lines(n0 * ex * e) + ex * lines(n0 * ey * e) + kTileOverhead);
-            useful += cnt * 2.0 * n0 * ex * ey * e;
-            slots += cnt * cap;
-            work += cnt * n0 * ex * ey;
-        }
+        for (int iy = 0; iy < 2; ++iy)
+            for (int iz = 0; iz < 2; ++iz) {
+                const double cx = ix ? (L.SA % tx ? 1 : 0) : double(L.SA / tx);
+                const double cy = iy ? (L.SB % ty ? 1 : 0) : double(L.SB / ty);
+                const double cz = iz ? (zs % tz ? 1 : 0) : double(zs / tz);
+                const int64_t ex = ix ? L.SA % tx : tx, ey = iy ? L.SB % ty : ty, ez = iz ? zs % tz : tz;
+                const double cnt = cx * cy * cz;
+                if (cnt == 0) continue;
+                const double elems = double(n0 * ex * ey * ez);
+                // A runs
+                double ra = xa_lin ? double(n0 * ex) : double(n0);
+                if (xa_lin && ex == L.SA && y_single && p.dim[L.b].sa == L.SA * rowA) {
+                    ra *= double(ey);
+                    if (ey == L.SB && z >= 0 && p.dim[z].sa == L.SB * L.SA * rowA) ra *= double(ez);
+                }
+                // B runs
+                double rb = yb_lin ? double(n0 * ey) : double(n0);
+                if (yb_lin && ey == L.SB && x_single && p.dim[L.a].sb == L.SB * rowB) {
+                    rb *= double(ex);
+                    if (ex == L.SA && z >= 0 && p.dim[z].sb == L.SA * L.SB * rowB) rb *= double(ez);
+                }
+                traffic += cnt * (elems / ra * lines(ra * e) + elems / rb * lines(rb * e) + kTileOverhead);
+                useful += cnt * 2.0 * elems * e;
+                slots += cnt * cap;
+                work += cnt * elems;
+            }
     if (useful == 0) return 1e30;
-    return kDensePenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
+    return kScalarPenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
+}
+
+// Planes per dense tile worth trying along index z (1 = one plane).
+static std::vector<int> dense_planes(const Problem& p, const Layout& L, int tx, int ty, int z) {
+    std::vector<int> out = {1};
+    if (z < 0) return out;
+    const int64_t n0 = L.staged ? p.dim[0].size : 1;
+    const int64_t most = std::min<int64_t>(dense_cap(p.dtype) / (n0 * tx * ty), p.dim[z].size);
+    if (most < 2) return out;
+    const int64_t pieces = (p.dim[z].size + most - 1) / most;
+    out.push_back(int(most));
+    const int64_t even = (p.dim[z].size + pieces - 1) / pieces;
+    if (even != most && even > 1) out.push_back(int(even));
+    return out;
 }
 
 // Dense tile extents worth trying: tx from powers of two, the whole extent
@@ -625,7 +720,8 @@ static double blocking_cost(const Problem& p, const Layout& L, int ta, int tb) {
             work += cnt * ax * by;
         }
     if (useful == 0) return 1e30;
-    return traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
+    const double scalar = vector_shape(p, L, ta, tb) ? 1.0 : kScalarPenalty;
+    return scalar * traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
 }
 
 // Grid indices of a layout (leaders and the indices outside both groups).
@@ -793,11 +889,17 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
             for (const TileShape& d : dense_shapes(p, L)) {
                 ttx_config probe = make_config(p, d.ta, d.tb, orders[0], TTX_CFG_DENSE, ga, gb);
                 if (!config_valid(p, probe, nullptr)) continue;
-                double bc = dense_cost(p, L, d.ta, d.tb);
                 for (const auto& o : orders) {
+                    const int z = dense_z(p, L, o.data(), p.n);
                     double oc = order_cost(p, L, d.ta, d.tb, o.data(), p.n);
-                    for (int f : flag_sets)
-                        offer(bc * (1.0 + oc) + flag_cost(f), make_config(p, d.ta, d.tb, o, f | TTX_CFG_DENSE, ga, gb));
+                    for (int tz : dense_planes(p, L, d.ta, d.tb, z)) {
+                        const double bc = dense_cost(p, L, d.ta, d.tb, tz, z);
+                        for (int f : flag_sets) {
+                            ttx_config c = make_config(p, d.ta, d.tb, o, f | TTX_CFG_DENSE, ga, gb);
+                            c.tile_c = tz;
+                            offer(bc * (1.0 + oc) + flag_cost(f), c);
+                        }
+                    }
                 }
             }
         }
@@ -881,12 +983,17 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
             };
             std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
             o.insert(o.end(), tail.begin(), tail.end());
-            ttx_config c = make_config(p, d.ta, d.tb, o, TTX_CFG_DENSE, ga, gb);
-            if (!config_valid(p, c, nullptr)) continue;
-            double cost = dense_cost(p, L, d.ta, d.tb) * (1.0 + order_cost(p, L, d.ta, d.tb, o.data(), p.n));
-            if (cost < bestc) {
-                bestc = cost;
-                best = c;
+            const int z = dense_z(p, L, o.data(), p.n);
+            for (int tz : dense_planes(p, L, d.ta, d.tb, z)) {
+                ttx_config c = make_config(p, d.ta, d.tb, o, TTX_CFG_DENSE, ga, gb);
+                c.tile_c = tz;
+                if (!config_valid(p, c, nullptr)) continue;
+                double cost =
+                    dense_cost(p, L, d.ta, d.tb, tz, z) * (1.0 + order_cost(p, L, d.ta, d.tb, o.data(), p.n));
+                if (cost < bestc) {
+                    bestc = cost;
+                    best = c;
+                }
             }
         }
     }

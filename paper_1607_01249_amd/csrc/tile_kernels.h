@@ -98,11 +98,13 @@ struct TileCoord {
     int64_t oa, ob;     // origin offsets (moved family: without the group cross terms)
     int64_t x0, y0;     // origin along the two tile (super) indices
     int ea, eb;         // extents of this (maybe edge) tile
+    int ez;             // dense tiles: planes along the third index
 };
 
-// Tile id -> origin offsets in A and B and the extents of this (maybe edge) tile.
-__device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, int TA, int TB) {
-    TileCoord c{0, 0, 0, 0, TA, TB};
+// Tile id -> origin offsets in A and B and the extents of this (maybe edge)
+// tile; TC is the tile extent along the third index of dense tiles.
+__device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, int TA, int TB, int TC = 1) {
+    TileCoord c{0, 0, 0, 0, TA, TB, TC};
     uint32_t rem = t;
     for (int q = 0; q < g.nd; ++q) {
         const uint32_t next = g.div[q].div(rem);
@@ -118,6 +120,7 @@ __device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, 
             c.y0 = int64_t(r) * TB;
             c.eb = int(min(int64_t(TB), g.ext_b - c.y0));
         }
+        if (q == g.pz) c.ez = int(min(int64_t(TC), g.ext_z - int64_t(r) * TC));
     }
     return c;
 }
@@ -153,6 +156,7 @@ struct MovedTile {
     static constexpr int NT = kThreads, LDR = TA + 1;
     __device__ static int ext_a(const TileArgs<T>&) { return TA; }
     __device__ static int ext_b(const TileArgs<T>&) { return TB; }
+    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
     // A side: columns (fixed y) of TA elements along x
     static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
     // B side: rows (fixed x) of TB elements along y
@@ -258,6 +262,7 @@ struct PreservedTile {
     static constexpr int NT = kThreads;
     __device__ static int ext_a(const TileArgs<T>&) { return TA; }
     __device__ static int ext_b(const TileArgs<T>&) { return TR; }
+    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
     static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
 
@@ -326,6 +331,7 @@ struct StagedTile {
     static constexpr int NT = kThreads, LDR = TX * N0 + 1;
     __device__ static int ext_a(const TileArgs<T>&) { return TX; }
     __device__ static int ext_b(const TileArgs<T>&) { return TY; }
+    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
     static constexpr int PA = N0 * TX, PB = N0 * TY;
     static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
@@ -414,14 +420,16 @@ struct StagedTile {
 
 // One dense tile: rows of n0 = dn0 elements (the shared stride-1 index of
 // the preserved family; n0 = 1 for the moved family), tx rows along A's super
-// index x and ty rows along B's super index y, with tx and ty run-time values
-// and n0 * tx * ty <= CAP.  Element (i, x0 + x, y0 + y) is
-//   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
-// Slot e of the tile (e = tid + s*NT) is read as A-run element
-// (y = e / runA, i + n0*x = e % runA) and written as B-run element
-// (x = e / runB, i + n0*y = e % runB), so that both sides run along their
+// index x and ty rows along B's super index y, and tz planes along a third
+// index z, with tx, ty, tz run-time values and n0 * tx * ty * tz <= CAP.
+// Element (i, x0 + x, y0 + y, z) is
+//   A[oa + i*s0A + x*sAa + gB.offset(y0 + y) + z*sAz]
+//     -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x) + z*sBz].
+// Slot e of the tile (e = tid + s*NT) is read in A order (i, x, y, z: plane
+// z = e / planeA, then y and i + n0*x within runs of runA) and written in B
+// order (i, y, x, z: runs of runB), so that both sides run along their
 // contiguous index without padding lanes to a power of two.  The tile passes
-// through LDS as [y][x][i], rows of ldr >= runA elements (odd when possible).
+// through LDS as [z][y][x][i], rows of ldr >= runA elements (odd when possible).
 template <typename T, bool BETA0, int CAP>
 struct DenseTile {
     static constexpr bool kUsesLds = true;
@@ -429,30 +437,40 @@ struct DenseTile {
     static_assert(CAP % NT == 0, "whole passes");
     __device__ static int ext_a(const TileArgs<T>& a) { return a.tx; }
     __device__ static int ext_b(const TileArgs<T>& a) { return a.ty; }
+    __device__ static int ext_c(const TileArgs<T>& a) { return a.tz; }
 
     T ra[NS];
     T rb[NS];
     T out[NS];
 
-    // A-side coordinates of slot e: row y, and r = i + n0*x within the row
+    // A-order coordinates of slot e; r = i + n0*x, and l is its LDS index
     __device__ __forceinline__ static void a_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
-                                                  uint32_t& i, uint32_t& r) {
-        y = a.dvA.div(e);
-        r = e - y * a.runA;
+                                                  uint32_t& z, uint32_t& i, uint32_t& l) {
+        z = a.dvPA.div(e);
+        const uint32_t rem = e - z * a.planeA;
+        y = a.dvA.div(rem);
+        const uint32_t r = rem - y * a.runA;
         x = a.dv0.div(r);
         i = r - x * uint32_t(a.dn0);
+        l = (z * uint32_t(a.ty) + y) * uint32_t(a.ldr) + r;
     }
-    // B-side coordinates of slot e
+    // B-order coordinates of slot e, and the LDS index it reads
     __device__ __forceinline__ static void b_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
-                                                  uint32_t& i) {
-        x = a.dvB.div(e);
-        const uint32_t r = e - x * a.runB;
+                                                  uint32_t& z, uint32_t& i, uint32_t& l) {
+        z = a.dvPB.div(e);
+        const uint32_t rem = e - z * a.planeB;
+        x = a.dvB.div(rem);
+        const uint32_t r = rem - x * a.runB;
         y = a.dv0.div(r);
         i = r - y * uint32_t(a.dn0);
+        l = (z * uint32_t(a.ty) + y) * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i;
+    }
+    __device__ __forceinline__ static bool inside(const TileCoord& c, uint32_t x, uint32_t y, uint32_t z) {
+        return x < uint32_t(c.ea) && y < uint32_t(c.eb) && z < uint32_t(c.ez);
     }
     __device__ __forceinline__ static int64_t b_offset(const TileArgs<T>& a, const TileCoord& c, uint32_t x,
-                                                       uint32_t y, uint32_t i) {
-        return c.ob + int64_t(i) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x);
+                                                       uint32_t y, uint32_t z, uint32_t i) {
+        return c.ob + int64_t(i) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x) + int64_t(z) * a.sBz;
     }
 
     __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
@@ -460,17 +478,17 @@ struct DenseTile {
         const T* A0 = a.A + c.oa;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, i, r;
-            a_slot(a, tid + s * NT, x, y, i, r);
-            if (x < uint32_t(c.ea) && y < uint32_t(c.eb))
-                ra[s] = A0[int64_t(i) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y)];
+            uint32_t x, y, z, i, l;
+            a_slot(a, tid + s * NT, x, y, z, i, l);
+            if (inside(c, x, y, z))
+                ra[s] = A0[int64_t(i) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y) + int64_t(z) * a.sAz];
         }
         if constexpr (!BETA0) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                uint32_t x, y, i;
-                b_slot(a, tid + s * NT, x, y, i);
-                if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) rb[s] = a.Bsrc[b_offset(a, c, x, y, i)];
+                uint32_t x, y, z, i, l;
+                b_slot(a, tid + s * NT, x, y, z, i, l);
+                if (inside(c, x, y, z)) rb[s] = a.Bsrc[b_offset(a, c, x, y, z, i)];
             }
         }
     }
@@ -479,9 +497,9 @@ struct DenseTile {
         const uint32_t tid = threadIdx.x;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, i, r;
-            a_slot(a, tid + s * NT, x, y, i, r);
-            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) lds[y * uint32_t(a.ldr) + r] = ra[s];
+            uint32_t x, y, z, i, l;
+            a_slot(a, tid + s * NT, x, y, z, i, l);
+            if (inside(c, x, y, z)) lds[l] = ra[s];
         }
     }
 
@@ -490,11 +508,9 @@ struct DenseTile {
         const uint32_t tid = threadIdx.x;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, i;
-            b_slot(a, tid + s * NT, x, y, i);
-            if (x < uint32_t(c.ea) && y < uint32_t(c.eb))
-                out[s] = epilogue<T, 1, BETA0>(lds[y * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i], rb[s],
-                                               a.alpha, a.beta);
+            uint32_t x, y, z, i, l;
+            b_slot(a, tid + s * NT, x, y, z, i, l);
+            if (inside(c, x, y, z)) out[s] = epilogue<T, 1, BETA0>(lds[l], rb[s], a.alpha, a.beta);
         }
     }
 
@@ -503,9 +519,9 @@ struct DenseTile {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, i;
-            b_slot(a, tid + s * NT, x, y, i);
-            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) st<T, 1>(a.Bdst + b_offset(a, c, x, y, i), out[s], nt);
+            uint32_t x, y, z, i, l;
+            b_slot(a, tid + s * NT, x, y, z, i, l);
+            if (inside(c, x, y, z)) st<T, 1>(a.Bdst + b_offset(a, c, x, y, z, i), out[s], nt);
         }
     }
 
@@ -515,19 +531,63 @@ struct DenseTile {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, i;
-            b_slot(a, tid + s * NT, x, y, i);
-            if (x < uint32_t(c.ea) && y < uint32_t(c.eb)) {
-                const T v = lds[y * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i];
-                st<T, 1>(a.Bdst + b_offset(a, c, x, y, i), epilogue<T, 1, BETA0>(v, rb[s], a.alpha, a.beta), nt);
-            }
+            uint32_t x, y, z, i, l;
+            b_slot(a, tid + s * NT, x, y, z, i, l);
+            if (inside(c, x, y, z))
+                st<T, 1>(a.Bdst + b_offset(a, c, x, y, z, i), epilogue<T, 1, BETA0>(lds[l], rb[s], a.alpha, a.beta),
+                         nt);
         }
     }
 };
 
-// LDS elements of a dense tile: ty rows of ldr <= runA + 1 elements, with
-// runA * ty <= CAP and ty <= CAP.
+// LDS elements of a dense tile: tz*ty rows of ldr <= runA + 1 elements, with
+// runA * ty * tz <= CAP.
 constexpr int dense_lds_elems(int cap) { return 2 * cap; }
+
+// One flat tile (everything merged into one index): TF consecutive elements,
+// V-element vectors (V > 1 needs unit strides and an element count that is
+// a multiple of V), U vectors per thread.  No LDS.
+template <typename T, bool BETA0, int V, int U>
+struct FlatTile {
+    static constexpr bool kUsesLds = false;
+    static constexpr int NT = kThreads, TF = NT * V * U;
+    __device__ static int ext_a(const TileArgs<T>&) { return TF; }
+    __device__ static int ext_b(const TileArgs<T>&) { return 1; }
+    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
+
+    vec_t<T, V> ra[U];
+    vec_t<T, V> rb[U];
+    vec_t<T, V> out[U];
+
+    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = (tid + u * NT) * V;
+            if (k < c.ea) {
+                ra[u] = ld<T, V>(a.A + c.oa + int64_t(k) * a.sAa);
+                if constexpr (!BETA0) rb[u] = ld<T, V>(a.Bsrc + c.ob + int64_t(k) * a.sBa);
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(const TileArgs<T>& a, const TileCoord&) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) out[u] = epilogue<T, V, BETA0>(ra[u], rb[u], a.alpha, a.beta);
+    }
+    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+        const int tid = threadIdx.x;
+        const bool nt = a.flags & KF_NT_STORE;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = (tid + u * NT) * V;
+            if (k < c.ea) st<T, V>(a.Bdst + c.ob + int64_t(k) * a.sBa, out[u], nt);
+        }
+    }
+    __device__ __forceinline__ void finish_store(const TileArgs<T>& a, const TileCoord& c) {
+        finish(a, c);
+        store(a, c);
+    }
+};
 
 // Tiles t, t + step, ... < end of one problem.  With PIPE, tile k+1's loads
 // are issued between tile k's LDS read and its stores, as described above;
@@ -540,7 +600,7 @@ __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>
     Tile tile;
     if constexpr (!PIPE) {
         for (uint64_t u = t; u < end; u += step) {
-            const TileCoord c = decode_tile(a.g, uint32_t(u), Tile::ext_a(a), Tile::ext_b(a));
+            const TileCoord c = decode_tile(a.g, uint32_t(u), Tile::ext_a(a), Tile::ext_b(a), Tile::ext_c(a));
             tile.load(a, c);
             if constexpr (Tile::kUsesLds) {
                 tile.to_lds(lds, a, c);
@@ -552,7 +612,7 @@ __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>
             }
         }
     } else {
-        TileCoord c = decode_tile(a.g, t, Tile::ext_a(a), Tile::ext_b(a));
+        TileCoord c = decode_tile(a.g, t, Tile::ext_a(a), Tile::ext_b(a), Tile::ext_c(a));
         tile.load(a, c);
         while (true) {
             if constexpr (Tile::kUsesLds) {
@@ -566,7 +626,7 @@ __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>
             const bool more = tn < end;
             TileCoord cn = c;
             if (more) {
-                cn = decode_tile(a.g, uint32_t(tn), Tile::ext_a(a), Tile::ext_b(a));
+                cn = decode_tile(a.g, uint32_t(tn), Tile::ext_a(a), Tile::ext_b(a), Tile::ext_c(a));
                 tile.load(a, cn);
             }
             tile.store(a, c);

@@ -47,8 +47,10 @@ struct FastDiv {
 struct TileGrid {
     int nd;
     int pa, pb;
+    int pz;                        // dense tiles: position of the third tiled index (-1: none)
     uint32_t ntiles;
     int64_t ext_a, ext_b;          // extents along the two tile indices
+    int64_t ext_z;                 // and along the third (dense tiles)
     uint32_t count[kMaxDims];
     FastDiv div[kMaxDims];
     int64_t stepA[kMaxDims];
@@ -101,6 +103,12 @@ struct TileArgsHost {
     int dn0, tx, ty, ldr;
     uint32_t runA, runB;
     FastDiv dv0, dvA, dvB;
+    // and tz planes along a third index (strides sAz, sBz); a plane holds
+    // planeA = runA*ty (A order) or planeB = runB*tx (B order) elements
+    int tz;
+    int64_t sAz, sBz;
+    uint32_t planeA, planeB;
+    FastDiv dvPA, dvPB;
 };
 
 template <typename T>

@@ -69,6 +69,7 @@ static std::string config_text(const ttx_config& c) {
     os << c.family << " " << c.tile_a << " " << c.tile_b << " " << c.threads << " " << c.flags << " "
        << c.group_a << " " << c.group_b << " " << c.n_order;
     for (int i = 0; i < c.n_order; ++i) os << " " << c.order[i];
+    if (c.tile_c > 1) os << " c" << c.tile_c;
     return os.str();
 }
 
@@ -80,6 +81,12 @@ static bool parse_config(std::istringstream& is, ttx_config* c) {
     if (c->n_order < 0 || c->n_order > kMaxDims) return false;
     for (int i = 0; i < c->n_order; ++i)
         if (!(is >> c->order[i])) return false;
+    std::string extra;   // optional "c<planes>" (dense tiles)
+    if (is >> extra) {
+        if (extra.size() < 2 || extra[0] != 'c') return false;
+        c->tile_c = std::atoi(extra.c_str() + 1);
+        if (c->tile_c < 1) return false;
+    }
     return true;
 }
 
@@ -211,7 +218,7 @@ ttx_status ttx_tune_table_save(const char* path) {
     std::ofstream f(path);
     if (!f) return fail(TTX_EINVAL, "cannot open tune table for writing");
     std::lock_guard<std::mutex> lock(g_table_mu);
-    f << "# ttx tune table v2: key | family tile_a tile_b threads flags group_a group_b n_order order... | usec\n";
+    f << "# ttx tune table v3: key | family tile_a tile_b threads flags group_a group_b n_order order... [c<tile_c>] | usec\n";
     for (const auto& kv : g_table)
         f << kv.first << " | " << config_text(kv.second.cfg) << " | " << kv.second.usec << "\n";
     return f ? TTX_OK : fail(TTX_EINVAL, "write failed");

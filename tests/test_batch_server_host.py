@@ -34,8 +34,8 @@ BATCH_SHAPES = {
     # direct preserved tiles, and staged (tile_x, tile_y) for short rows
     (ttx.F32, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
     (ttx.F64, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
-    (ttx.F32, ttx.FAMILY_FLAT): {(1024, 1), (256, 1)},
-    (ttx.F64, ttx.FAMILY_FLAT): {(512, 1), (256, 1)},
+    (ttx.F32, ttx.FAMILY_FLAT): {(4096, 1), (1024, 1)},
+    (ttx.F64, ttx.FAMILY_FLAT): {(2048, 1), (1024, 1)},
 }
 
 
@@ -53,7 +53,7 @@ def test_batch_plan_uses_the_batched_menu():
         if c.flags & ttx.CFG_DENSE:     # dense tiles: run-time extents within the capacity
             dense += 1
             rows = n0 if c.family == ttx.FAMILY_PRESERVED else 1
-            assert rows * c.tile_a * c.tile_b <= ttx.DENSE_CAP[q.dtype], c.as_dict()
+            assert rows * c.tile_a * c.tile_b * max(1, c.tile_c) <= ttx.DENSE_CAP[q.dtype], c.as_dict()
         else:
             assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(q.dtype, c.family)], c.as_dict()
         assert c.flags & ttx.CFG_XCD_SWIZZLE == 0
@@ -61,7 +61,7 @@ def test_batch_plan_uses_the_batched_menu():
         # tiles of the kept family also hold whole stride-1 rows)
         n = int(np.prod(list(q.size[:q.n])))
         rows = n0 if (c.family == ttx.FAMILY_PRESERVED and c.group_a > 1) else 1
-        assert t >= 1 and t * c.tile_a * max(1, c.tile_b) * rows >= n
+        assert t >= 1 and t * c.tile_a * max(1, c.tile_b) * max(1, c.tile_c) * rows >= n
     fams = {c.family for c in cfgs}
     assert fams >= {ttx.FAMILY_MOVED, ttx.FAMILY_PRESERVED, ttx.FAMILY_FLAT}
     assert dense > 0
@@ -73,10 +73,10 @@ def test_batch_plan_misaligned_pointers_use_scalar_variants():
     assert (c.tile_a, c.tile_b) in BATCH_SHAPES[(ttx.F32, ttx.FAMILY_MOVED)]
     q = ttx.make_problem(ttx.F32, (0,), (1001,), 1.0, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
     (c,), _ = ttx.ttx_batch_plan([q])
-    assert c.family == ttx.FAMILY_FLAT and c.tile_a == 256     # 1001 % 4 != 0: scalar
+    assert c.family == ttx.FAMILY_FLAT and c.tile_a == 1024    # 1001 % 4 != 0: scalar
     q = ttx.make_problem(ttx.F32, (0,), (1000,), 1.0, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
     (c,), _ = ttx.ttx_batch_plan([q])
-    assert c.tile_a == 1024
+    assert c.tile_a == 4096
 
 
 def test_batch_plan_rejects_bad_problems():

@@ -292,6 +292,10 @@ DENSE_CASES = [
     ((5, 4, 3, 2, 1, 0), (5, 7, 6, 4, 3, 5), None, None),
     ((0, 2, 1), (6, 50, 40), (8, 52, 41), (7, 41, 51)),   # outer sizes on both sides
     ((2, 1, 0), (33, 17, 29), (35, 17, 30), None),
+    ((1, 0, 2), (3, 4, 5000), None, None),             # many tiny planes: several per tile
+    ((1, 0, 2, 3), (5, 3, 7, 40), None, None),
+    ((1, 0, 5, 2, 4, 3), (2, 6, 5, 9, 2, 4), None, None),
+    ((1, 0, 2), (3, 4, 700), (4, 5, 700), (5, 3, 701)),  # planes with gaps between them
 ]
 
 
@@ -306,7 +310,7 @@ def test_dense_tiles(perm, size, oa, ob, dtype):
     # every distinct dense shape (first loop order of each), plus a spread of the rest
     seen, pick = set(), []
     for c in dense:
-        key = (c.tile_a, c.tile_b, c.group_a, c.group_b)
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c)
         if key not in seen:
             seen.add(key)
             pick.append(c)
