@@ -378,6 +378,10 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
             z = dense_z(p, L, c.order, c.n_order);
             if (z < 0) return bad("tile_c needs a third index outside the tile");
         }
+        // offsets within a dense tile are 32-bit
+        const int64_t es = elem_bytes(p.dtype);
+        if (p.extent_a / es >= (int64_t(1) << 31) || p.extent_b / es >= (int64_t(1) << 31))
+            return bad("dense tiles need tensors below 2^31 elements");
     } else if (tc > 1) {
         return bad("tile_c is for dense tiles only");
     } else if (L.staged) {
@@ -933,13 +937,36 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
     }
     // Greedy use of both heuristics: the cheapest groups and tile shape, then
     // the grid indices sorted by the span one step covers (smallest first).
+    // A shape whose blocking cost alone is not below the best so far is
+    // skipped (the loop-order factor is at least 1).
     double bestc = 1e300;
     for (auto [ga, gb] : group_options(p)) {
         Layout L;
         make_layout(p, ga, gb, &L);
-        std::vector<int> tail;
-        for (int d = 0; d < p.n; ++d)
-            if (L.member[d]) tail.push_back(d);
+        int gi[kMaxDims], ng = 0, tail[kMaxDims], nt = 0;
+        double span[kMaxDims] = {};
+        for (int d = 0; d < p.n; ++d) {
+            if (L.member[d]) {
+                tail[nt++] = d;
+                continue;
+            }
+            gi[ng++] = d;
+            double cnt, sA, sB;
+            grid_step(p, L, d, 1, 1, &cnt, &sA, &sB);
+            span[d] = sA + sB;
+        }
+        // the order for tile extents (ta, tb): the tile indices' steps scale
+        auto make_order = [&](int ta, int tb, std::vector<int>& o) {
+            double sp[kMaxDims];
+            for (int k = 0; k < ng; ++k) {
+                const int d = gi[k];
+                sp[d] = span[d] * (d == L.a ? ta : d == L.b ? tb : 1);
+            }
+            o.assign(gi, gi + ng);
+            std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return sp[x] < sp[y]; });
+            o.insert(o.end(), tail, tail + nt);
+        };
+        std::vector<int> o;
         std::vector<TileShape> own;
         const TileShape* sh = shapes;
         int nsh = ns;
@@ -956,18 +983,13 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
         }
         for (int s = 0; s < nsh; ++s) {
             const int ta = sh[s].ta, tb = sh[s].tb;
-            std::vector<int> o = grid_indices(p, L);
-            auto span = [&](int d) {
-                double cnt, sA, sB;
-                grid_step(p, L, d, ta, tb, &cnt, &sA, &sB);
-                return sA + sB;
-            };
-            std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
-            o.insert(o.end(), tail.begin(), tail.end());
+            const double bc = blocking_cost(p, L, ta, tb);
+            if (bc >= bestc) continue;
+            make_order(ta, tb, o);
             ttx_config c = make_config(p, ta, tb, o, 0, ga, gb);
             // shapes outside the per-call menu (batched-kernel variants) are checked by their caller
             if ((L.staged || tile_in_menu(p.dtype, p.family, ta, tb)) && !config_valid(p, c, nullptr)) continue;
-            double cost = blocking_cost(p, L, ta, tb) * (1.0 + order_cost(p, L, ta, tb, o.data(), p.n));
+            const double cost = bc * (1.0 + order_cost(p, L, ta, tb, o.data(), p.n));
             if (cost < bestc) {
                 bestc = cost;
                 best = c;
@@ -975,21 +997,15 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
         }
         if (!dense || !dense_layout(p, L)) continue;
         for (const TileShape& d : dense_shapes(p, L)) {
-            std::vector<int> o = grid_indices(p, L);
-            auto span = [&](int q) {
-                double cnt, sA, sB;
-                grid_step(p, L, q, d.ta, d.tb, &cnt, &sA, &sB);
-                return sA + sB;
-            };
-            std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return span(x) < span(y); });
-            o.insert(o.end(), tail.begin(), tail.end());
+            make_order(d.ta, d.tb, o);
             const int z = dense_z(p, L, o.data(), p.n);
             for (int tz : dense_planes(p, L, d.ta, d.tb, z)) {
+                const double dc = dense_cost(p, L, d.ta, d.tb, tz, z);
+                if (dc >= bestc) continue;
                 ttx_config c = make_config(p, d.ta, d.tb, o, TTX_CFG_DENSE, ga, gb);
                 c.tile_c = tz;
                 if (!config_valid(p, c, nullptr)) continue;
-                double cost =
-                    dense_cost(p, L, d.ta, d.tb, tz, z) * (1.0 + order_cost(p, L, d.ta, d.tb, o.data(), p.n));
+                const double cost = dc * (1.0 + order_cost(p, L, d.ta, d.tb, o.data(), p.n));
                 if (cost < bestc) {
                     bestc = cost;
                     best = c;

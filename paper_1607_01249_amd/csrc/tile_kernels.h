@@ -157,6 +157,7 @@ struct MovedTile {
     __device__ static int ext_a(const TileArgs<T>&) { return TA; }
     __device__ static int ext_b(const TileArgs<T>&) { return TB; }
     __device__ static int ext_c(const TileArgs<T>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T>&) {}
     // A side: columns (fixed y) of TA elements along x
     static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
     // B side: rows (fixed x) of TB elements along y
@@ -263,6 +264,7 @@ struct PreservedTile {
     __device__ static int ext_a(const TileArgs<T>&) { return TA; }
     __device__ static int ext_b(const TileArgs<T>&) { return TR; }
     __device__ static int ext_c(const TileArgs<T>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T>&) {}
     static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
 
@@ -332,6 +334,7 @@ struct StagedTile {
     __device__ static int ext_a(const TileArgs<T>&) { return TX; }
     __device__ static int ext_b(const TileArgs<T>&) { return TY; }
     __device__ static int ext_c(const TileArgs<T>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T>&) {}
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
     static constexpr int PA = N0 * TX, PB = N0 * TY;
     static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
@@ -434,7 +437,7 @@ template <typename T, bool BETA0, int CAP>
 struct DenseTile {
     static constexpr bool kUsesLds = true;
     static constexpr int NT = kThreads, NS = CAP / NT;
-    static_assert(CAP % NT == 0, "whole passes");
+    static_assert(CAP % NT == 0 && CAP <= 1024, "whole passes; slot coordinates packed in 11+11+10 bits");
     __device__ static int ext_a(const TileArgs<T>& a) { return a.tx; }
     __device__ static int ext_b(const TileArgs<T>& a) { return a.ty; }
     __device__ static int ext_c(const TileArgs<T>& a) { return a.tz; }
@@ -442,101 +445,96 @@ struct DenseTile {
     T ra[NS];
     T rb[NS];
     T out[NS];
+    // Per-slot constants (the same for every tile of a problem): offsets
+    // within the tile in A and B (a group with one member is linear and is
+    // folded in), LDS indices, and the slot's (x, y, z) packed as
+    // x | y << 11 | z << 22 (all ones: beyond the tile).
+    int32_t relA[NS], relB[NS];
+    uint32_t la[NS], lb[NS];
+    uint32_t pa[NS], pb[NS];
 
-    // A-order coordinates of slot e; r = i + n0*x, and l is its LDS index
-    __device__ __forceinline__ static void a_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
-                                                  uint32_t& z, uint32_t& i, uint32_t& l) {
-        z = a.dvPA.div(e);
-        const uint32_t rem = e - z * a.planeA;
-        y = a.dvA.div(rem);
-        const uint32_t r = rem - y * a.runA;
-        x = a.dv0.div(r);
-        i = r - x * uint32_t(a.dn0);
-        l = (z * uint32_t(a.ty) + y) * uint32_t(a.ldr) + r;
+    __device__ __forceinline__ void init(const TileArgs<T>& a) {
+        const uint32_t tid = threadIdx.x;
+        const uint32_t count = a.planeA * uint32_t(a.tz);
+        const int64_t ya = a.gB.ng == 1 ? a.gB.stride[0] : 0;   // A stride of y when linear
+        const int64_t xb = a.gA.ng == 1 ? a.gA.stride[0] : 0;   // B stride of x when linear
+        const uint32_t n0 = uint32_t(a.dn0), ty = uint32_t(a.ty), ldr = uint32_t(a.ldr);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint32_t e = tid + s * NT;
+            // A order: i fastest, then x (runs of runA), y, z
+            uint32_t z = a.dvPA.div(e);
+            uint32_t rem = e - z * a.planeA;
+            uint32_t y = a.dvA.div(rem);
+            uint32_t r = rem - y * a.runA;
+            uint32_t x = a.dv0.div(r);
+            uint32_t i = r - x * n0;
+            la[s] = (z * ty + y) * ldr + r;
+            relA[s] = int32_t(int64_t(i) * a.s0A + int64_t(x) * a.sAa + int64_t(z) * a.sAz + int64_t(y) * ya);
+            pa[s] = e < count ? (x | y << 11 | z << 22) : 0xffffffffu;
+            // B order: i fastest, then y (runs of runB), x, z
+            z = a.dvPB.div(e);
+            rem = e - z * a.planeB;
+            x = a.dvB.div(rem);
+            r = rem - x * a.runB;
+            y = a.dv0.div(r);
+            i = r - y * n0;
+            lb[s] = (z * ty + y) * ldr + x * n0 + i;
+            relB[s] = int32_t(int64_t(i) * a.s0B + int64_t(y) * a.sBb + int64_t(z) * a.sBz + int64_t(x) * xb);
+            pb[s] = e < count ? (x | y << 11 | z << 22) : 0xffffffffu;
+        }
     }
-    // B-order coordinates of slot e, and the LDS index it reads
-    __device__ __forceinline__ static void b_slot(const TileArgs<T>& a, uint32_t e, uint32_t& x, uint32_t& y,
-                                                  uint32_t& z, uint32_t& i, uint32_t& l) {
-        z = a.dvPB.div(e);
-        const uint32_t rem = e - z * a.planeB;
-        x = a.dvB.div(rem);
-        const uint32_t r = rem - x * a.runB;
-        y = a.dv0.div(r);
-        i = r - y * uint32_t(a.dn0);
-        l = (z * uint32_t(a.ty) + y) * uint32_t(a.ldr) + x * uint32_t(a.dn0) + i;
+    __device__ __forceinline__ static bool inside(const TileCoord& c, uint32_t p) {
+        return (p & 2047u) < uint32_t(c.ea) && ((p >> 11) & 2047u) < uint32_t(c.eb) && (p >> 22) < uint32_t(c.ez);
     }
-    __device__ __forceinline__ static bool inside(const TileCoord& c, uint32_t x, uint32_t y, uint32_t z) {
-        return x < uint32_t(c.ea) && y < uint32_t(c.eb) && z < uint32_t(c.ez);
+    // A and B addresses of slot s in tile c
+    __device__ __forceinline__ const T* a_ptr(const TileArgs<T>& a, const TileCoord& c, int s) const {
+        if (a.gB.ng == 1) return a.A + (c.oa + c.y0 * a.gB.stride[0]) + relA[s];
+        return a.A + c.oa + relA[s] + a.gB.offset(c.y0 + ((pa[s] >> 11) & 2047u));
     }
-    __device__ __forceinline__ static int64_t b_offset(const TileArgs<T>& a, const TileCoord& c, uint32_t x,
-                                                       uint32_t y, uint32_t z, uint32_t i) {
-        return c.ob + int64_t(i) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x) + int64_t(z) * a.sBz;
+    __device__ __forceinline__ int64_t b_off(const TileArgs<T>& a, const TileCoord& c, int s) const {
+        if (a.gA.ng == 1) return c.ob + c.x0 * a.gA.stride[0] + relB[s];
+        return c.ob + relB[s] + a.gA.offset(c.x0 + (pb[s] & 2047u));
     }
 
     __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
-        const uint32_t tid = threadIdx.x;
-        const T* A0 = a.A + c.oa;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, z, i, l;
-            a_slot(a, tid + s * NT, x, y, z, i, l);
-            if (inside(c, x, y, z))
-                ra[s] = A0[int64_t(i) * a.s0A + int64_t(x) * a.sAa + a.gB.offset(c.y0 + y) + int64_t(z) * a.sAz];
-        }
+        for (int s = 0; s < NS; ++s)
+            if (inside(c, pa[s])) ra[s] = *a_ptr(a, c, s);
         if constexpr (!BETA0) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                uint32_t x, y, z, i, l;
-                b_slot(a, tid + s * NT, x, y, z, i, l);
-                if (inside(c, x, y, z)) rb[s] = a.Bsrc[b_offset(a, c, x, y, z, i)];
-            }
+            for (int s = 0; s < NS; ++s)
+                if (inside(c, pb[s])) rb[s] = a.Bsrc[b_off(a, c, s)];
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>& a, const TileCoord& c) {
-        const uint32_t tid = threadIdx.x;
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, z, i, l;
-            a_slot(a, tid + s * NT, x, y, z, i, l);
-            if (inside(c, x, y, z)) lds[l] = ra[s];
-        }
+        for (int s = 0; s < NS; ++s)
+            if (inside(c, pa[s])) lds[la[s]] = ra[s];
     }
 
     __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
                                              const TileCoord& c) {
-        const uint32_t tid = threadIdx.x;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, z, i, l;
-            b_slot(a, tid + s * NT, x, y, z, i, l);
-            if (inside(c, x, y, z)) out[s] = epilogue<T, 1, BETA0>(lds[l], rb[s], a.alpha, a.beta);
-        }
+        for (int s = 0; s < NS; ++s)
+            if (inside(c, pb[s])) out[s] = epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta);
     }
 
     __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
-        const uint32_t tid = threadIdx.x;
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, z, i, l;
-            b_slot(a, tid + s * NT, x, y, z, i, l);
-            if (inside(c, x, y, z)) st<T, 1>(a.Bdst + b_offset(a, c, x, y, z, i), out[s], nt);
-        }
+        for (int s = 0; s < NS; ++s)
+            if (inside(c, pb[s])) st<T, 1>(a.Bdst + b_off(a, c, s), out[s], nt);
     }
 
     __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
                                                const TileCoord& c) {
-        const uint32_t tid = threadIdx.x;
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t x, y, z, i, l;
-            b_slot(a, tid + s * NT, x, y, z, i, l);
-            if (inside(c, x, y, z))
-                st<T, 1>(a.Bdst + b_offset(a, c, x, y, z, i), epilogue<T, 1, BETA0>(lds[l], rb[s], a.alpha, a.beta),
-                         nt);
-        }
+        for (int s = 0; s < NS; ++s)
+            if (inside(c, pb[s]))
+                st<T, 1>(a.Bdst + b_off(a, c, s), epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta), nt);
     }
 };
 
@@ -554,6 +552,7 @@ struct FlatTile {
     __device__ static int ext_a(const TileArgs<T>&) { return TF; }
     __device__ static int ext_b(const TileArgs<T>&) { return 1; }
     __device__ static int ext_c(const TileArgs<T>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T>&) {}
 
     vec_t<T, V> ra[U];
     vec_t<T, V> rb[U];
@@ -598,6 +597,7 @@ template <class Tile, bool PIPE, typename T>
 __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>& a, uint32_t t,
                                           uint32_t end, uint32_t step) {
     Tile tile;
+    tile.init(a);
     if constexpr (!PIPE) {
         for (uint64_t u = t; u < end; u += step) {
             const TileCoord c = decode_tile(a.g, uint32_t(u), Tile::ext_a(a), Tile::ext_b(a), Tile::ext_c(a));
