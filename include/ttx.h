@@ -283,7 +283,9 @@ ttx_status ttx_batch_plan(int count, const ttx_problem *problems, ttx_config *co
  * is admitted as one persistent batched-kernel launch whenever one of
  * `slots` device slots (each a stream plus a descriptor ring entry in device
  * memory) is free, so work that arrives while earlier micro-batches run
- * overlaps with them on the device.  Results are bitwise those of
+ * overlaps with them on the device.  A request of at least 32 MiB of
+ * algorithmic traffic fills the device alone and takes a slot by itself,
+ * launched with the per-call kernels (whole tile menu, tune table).  Results are bitwise those of
  * ttx_transpose on the same inputs.  Latency = completion (observed by the
  * dispatcher) minus arrival. */
 typedef struct ttx_server_opts {

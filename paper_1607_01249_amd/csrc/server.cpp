@@ -81,9 +81,14 @@ class Arena {
 
 enum ReqState { WAITING = 0, READY = 1, RUNNING = 2, DONE = 3 };
 
+// Requests of at least this many algorithmic bytes run alone.
+static constexpr int64_t kDirectBytes = int64_t(32) << 20;
+
 struct Request {
     Problem p;
     ttx_config cfg;          // batched-menu config, chosen at submission
+    ttx_config direct;       // per-call config, for requests large enough to run alone
+    bool large = false;
     bool beta0;
     double alpha, beta;
     const void* A;
@@ -218,7 +223,25 @@ static bool launch_locked(ttx_server* s) {
     BatchDesc* h_desc = reinterpret_cast<BatchDesc*>(slot->h_blk);
     while (!s->ready.empty() && count < s->opts.max_batch) {
         Request& r = s->reqs[s->ready.front()];
-        if (count > 0 && bytes + r.bytes > s->opts.max_batch_bytes) break;
+        if (count > 0 && (r.large || bytes + r.bytes > s->opts.max_batch_bytes)) break;
+        if (r.large) {   // alone, with the per-call kernels
+            slot->tickets.push_back(s->ready.front());
+            s->ready.pop_front();
+            r.state = RUNNING;
+            slot->busy = true;
+            s->running += 1;
+            ++s->batches;
+            s->batched_requests += 1;
+            if (s->opts.fake_device) {
+                slot->fake_done_at = now_ns() + int64_t(double(r.bytes) / 4e12 * 1e9) + 2000;
+                return true;
+            }
+            hipError_t e = launch_tiles(r.p, r.direct, r.beta0, r.A, r.beta0 ? nullptr : r.Bin, r.Bout, r.alpha,
+                                        r.beta, slot->stream);
+            if (e == hipSuccess) e = hipEventRecord(slot->done, slot->stream);
+            if (e != hipSuccess) s->worker_error = std::string("server launch: ") + hipGetErrorString(e);
+            return true;
+        }
         BatchDesc& d = h_desc[count];
         if (batch_describe(r.p, &r.cfg, r.beta0, r.A, r.Bin, r.Bout, r.alpha, r.beta, &d, nullptr) != TTX_OK) {
             // cannot happen for a validated request; count it as done to keep the loop live
@@ -336,6 +359,10 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
         st = batch_describe(r.p, nullptr, r.beta0, r.A, r.Bin, const_cast<void*>(out_probe), r.alpha,
                             r.beta, &probe, &r.cfg);
         if (st != TTX_OK) return st;
+        // a large request fills the device by itself: it runs alone with the
+        // per-call kernels (whole tile menu, tuned configs)
+        r.large = r.bytes >= kDirectBytes;
+        if (r.large && !table_lookup(r.p, r.beta0, &r.direct)) r.direct = default_config(r.p);
     }
     r.t_arrival = rq->arrival_ns > 0 ? rq->arrival_ns : now_ns();
     std::lock_guard<std::mutex> lock(s->mu);

@@ -199,3 +199,19 @@ def test_server_destroy_with_queued_work():
     for _ in range(5):
         ttx.ttx_server_submit(s, _req(size=(128, 128)))
     ttx.ttx_server_destroy(s)   # must return although the queue is blocked
+
+
+def test_server_runs_large_requests_alone():
+    # 64 MiB in + 64 MiB out: at least 32 MiB of traffic, so it takes a slot by itself
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=1 << 34, slots=2)
+    try:
+        small = [ttx.ttx_server_submit(s, _req(size=(64, 64))) for _ in range(3)]
+        big = ttx.ttx_server_submit(s, _req(size=(4096, 4096)))
+        more = [ttx.ttx_server_submit(s, _req(size=(64, 64))) for _ in range(3)]
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["completed"] == 7 and st["in_use_bytes"] == 0
+        assert st["batches"] >= 2     # the large request never shares a micro-batch
+        assert all(ttx.ttx_server_poll(s, t) for t in small + [big] + more)
+    finally:
+        ttx.ttx_server_destroy(s)
