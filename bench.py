@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E, published
 TABLE = os.path.join(ROOT, "paper_1607_01249_amd", "tune", "gfx950.txt")
+# submitting threads of the served runs (clients sharing one server)
+CLIENTS = 4
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = ["tile_kernels.h", "menu.h", "registry.h", "kernels_moved_f32_beta.hip",
                   "kernels_moved_f32_beta0.hip", "kernels_moved_f64_beta.hip",
@@ -406,7 +408,7 @@ def bench_served(torch, ttx, seconds, rate):
     log("serving %d requests over %.1f s" % (n, seconds))
     s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
     try:
-        tickets = ttx.ttx_server_replay(s, reqs, offsets)
+        tickets = ttx.ttx_server_replay_clients(s, reqs, offsets, CLIENTS)
         ttx.ttx_server_drain(s)
         st = ttx.ttx_server_get_stats(s)
         # the mix check: each kept result against the same request alone
@@ -439,7 +441,7 @@ def bench_served(torch, ttx, seconds, rate):
     span = float(np.max(times + lat * 1e-6) - times[0])
     saturated = bench_saturated(torch, ttx, reqs, meta, scratch)
     del pool, scratch
-    return dict(requests=n, rate_per_s=rate, seconds=seconds, algorithmic_bytes=nbytes_total,
+    return dict(requests=n, rate_per_s=rate, seconds=seconds, algorithmic_bytes=nbytes_total, clients=CLIENTS,
                 served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
                             p99_us=round(st["p99_us"], 1), max_us=round(st["max_us"], 1),
                             batches=st["batches"], mean_batch=round(st["mean_batch"], 2),
@@ -468,7 +470,7 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
     log("saturated: %d requests at once (%.2f GB)" % (m, total / 1e9))
     s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
     try:
-        ttx.ttx_server_replay(s, sub, zeros)
+        ttx.ttx_server_replay_clients(s, sub, zeros, CLIENTS)
         ttx.ttx_server_drain(s)
         st = ttx.ttx_server_get_stats(s)
     finally:
@@ -476,7 +478,7 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
     lat = ttx.ttx_replay_sequential(sub, zeros, scratch.data_ptr(), scratch.numel(),
                                     torch.cuda.current_stream().cuda_stream)
     seq_span = float(np.max(lat)) * 1e-6
-    return dict(requests=m, algorithmic_bytes=int(total),
+    return dict(requests=m, algorithmic_bytes=int(total), clients=CLIENTS,
                 served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
                             p99_us=round(st["p99_us"], 1), batches=st["batches"],
                             mean_batch=round(st["mean_batch"], 2)),

@@ -338,6 +338,11 @@ ttx_status ttx_server_drain(ttx_server *server);
  * retried, a request that can never fit gets ticket 0. */
 ttx_status ttx_server_replay(ttx_server *server, int64_t count, const ttx_request *requests,
                              const int64_t *offsets_ns, uint64_t *tickets);
+/* The same from `clients` submitting threads (client c submits requests
+ * c, c + clients, ...), as when several clients share one server.  Planning
+ * a request runs on its client's thread. */
+ttx_status ttx_server_replay_clients(ttx_server *server, int64_t count, const ttx_request *requests,
+                                     const int64_t *offsets_ns, int clients, uint64_t *tickets);
 ttx_status ttx_server_get_stats(ttx_server *server, ttx_server_stats *stats);
 /* The serving baseline: the same open-loop trace run one request at a time
  * through the per-call path, each launched at its arrival time (or as soon

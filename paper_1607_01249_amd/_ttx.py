@@ -191,6 +191,7 @@ def _declare(L):
         "ttx_server_release": ([vp, ctypes.c_uint64], S),
         "ttx_server_drain": ([vp], S),
         "ttx_server_replay": ([vp, i64, vp, i64p, ctypes.POINTER(ctypes.c_uint64)], S),
+        "ttx_server_replay_clients": ([vp, i64, vp, i64p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)], S),
         "ttx_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], S),
         "ttx_server_destroy": ([vp], S),
         "ttx_replay_sequential": ([i64, vp, i64p, vp, i64, vp, ctypes.POINTER(ctypes.c_double)], S),
@@ -408,12 +409,21 @@ def ttx_server_drain(server):
 
 def ttx_server_replay(server, requests, offsets_ns):
     """requests: a request_array(); offsets_ns: int64 numpy array.  Returns tickets."""
+    return ttx_server_replay_clients(server, requests, offsets_ns, 1)
+
+
+def ttx_server_replay_clients(server, requests, offsets_ns, clients):
+    """The replay from `clients` submitting threads.  Returns tickets."""
     import numpy as np
     offsets_ns = np.ascontiguousarray(offsets_ns, dtype=np.int64)
     tickets = np.zeros(len(requests), dtype=np.uint64)
-    _check(lib().ttx_server_replay(server, len(requests), requests.ctypes.data,
-                                   offsets_ns.ctypes.data_as(i64p),
-                                   tickets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    tp = tickets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    if clients == 1:
+        _check(lib().ttx_server_replay(server, len(requests), requests.ctypes.data,
+                                       offsets_ns.ctypes.data_as(i64p), tp))
+    else:
+        _check(lib().ttx_server_replay_clients(server, len(requests), requests.ctypes.data,
+                                               offsets_ns.ctypes.data_as(i64p), int(clients), tp))
     return tickets
 
 

@@ -374,6 +374,14 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     return TTX_OK;
 }
 
+void batch_set_output(BatchDesc* d, void* Bdst) {
+    if (d->variant < 0) return;
+    if (d->dtype == TTX_F32)
+        reinterpret_cast<TileArgs<float>*>(d->args)->Bdst = static_cast<float*>(Bdst);
+    else
+        reinterpret_cast<TileArgs<double>*>(d->args)->Bdst = static_cast<double*>(Bdst);
+}
+
 int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int cap) {
     if (p.family == TTX_FAMILY_EMPTY) return 0;
     int n = 0;
@@ -390,19 +398,43 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     }
     std::vector<ttx_config> all(1 << 17);
     int na = rank_candidates(p, -1, all.data(), nullptr, int(all.size()));
-    for (int i = 0; i < na && n < limit; ++i) {
+    // batched-menu candidates in cost order, and a quarter of the list kept
+    // for each kind (menu, staged, dense tiles), as in rank_candidates
+    std::vector<int> eligible, kind;
+    for (int i = 0; i < na; ++i) {
         const ttx_config& c = all[i];
         if (c.flags & TTX_CFG_XCD_SWIZZLE) continue;
+        int k = 0;
         if (config_is_dense(c)) {
             if (dense_index(p.dtype) < 0) continue;
+            k = 2;
         } else if (config_is_staged(c)) {
             if (staged_index(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b) < 0) continue;
+            k = 1;
         } else if (batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 0) < 0 &&
                    batch_index(p.dtype, p.family, c.tile_a, c.tile_b, 1) < 0) {
             continue;
         }
-        out[n++] = c;
+        eligible.push_back(i);
+        kind.push_back(k);
     }
+    std::vector<char> taken(eligible.size(), 0);
+    int per_kind[3] = {};
+    const int quota = limit / 4;
+    for (size_t j = 0; j < eligible.size() && n < limit; ++j)
+        if (per_kind[kind[j]] < quota) {
+            ++per_kind[kind[j]];
+            taken[j] = 1;
+            ++n;
+        }
+    for (size_t j = 0; j < eligible.size() && n < limit; ++j)
+        if (!taken[j]) {
+            taken[j] = 1;
+            ++n;
+        }
+    n = 0;
+    for (size_t j = 0; j < eligible.size(); ++j)
+        if (taken[j]) out[n++] = all[eligible[j]];
     return n;
 }
 

@@ -64,7 +64,8 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
     a.beta = T(beta);
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
     if (config_is_dense(c)) {
-        uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
+        const uint32_t full = dense_grid(p.dtype, beta0);
+        const uint32_t grid = a.g.ntiles < full ? a.g.ntiles : full;
         return dense_launcher(p.dtype, beta0)(&a, grid, stream);
     }
     if (config_is_staged(c)) {

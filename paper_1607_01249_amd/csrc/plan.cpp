@@ -545,6 +545,8 @@ static constexpr double kResident = 2048.0;
 // Element-wise accesses (dense and staged tiles, and menu tiles whose runs
 // cannot take 16-byte vectors) are charged a fixed 15% over vector tiles.
 static constexpr double kScalarPenalty = 1.15;
+// Dense tiles also decode every element's coordinates at run time.
+static constexpr double kDensePenalty = 1.3;
 
 static double lines(double bytes) { return std::ceil(bytes / kLine) * kLine; }
 
@@ -637,7 +639,7 @@ static double dense_cost(const Problem& p, const Layout& L, int tx, int ty, int 
                 work += cnt * elems;
             }
     if (useful == 0) return 1e30;
-    return kScalarPenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
+    return kDensePenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
 }
 
 // Planes per dense tile worth trying along index z (1 = one plane).
@@ -847,11 +849,16 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
         return x.cost < y.cost || (x.cost == y.cost && x.index < y.index);
     };
     // Bounded list (Sec. 2.1 stage 3): a max-heap on cost; a candidate enters
-    // while the list has room, or replaces the worst when it is cheaper.
-    std::priority_queue<Cand, std::vector<Cand>, decltype(worse)> heap(worse);
+    // while the list has room, or replaces the worst when it is cheaper.  One
+    // list per kernel kind (menu, staged, dense tiles): the estimates compare
+    // shapes of one kind better than they compare kinds, so each kind keeps a
+    // quarter of the final list when it has that many candidates.
+    using Heap = std::priority_queue<Cand, std::vector<Cand>, decltype(worse)>;
+    Heap heaps[3] = {Heap(worse), Heap(worse), Heap(worse)};
     int index = 0;
     auto offer = [&](double c, const ttx_config& cfg) {
         Cand cand{c, index++, cfg};
+        Heap& heap = heaps[config_is_dense(cfg) ? 2 : config_is_staged(cfg) ? 1 : 0];
         if (max_candidates < 0 || int(heap.size()) < max_candidates) {
             heap.push(cand);
         } else if (worse(cand, heap.top())) {
@@ -908,10 +915,30 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
             }
         }
     }
-    std::vector<Cand> all;
-    while (!heap.empty()) {
-        all.push_back(heap.top());
-        heap.pop();
+    std::vector<Cand> kinds[3], all;
+    for (int k = 0; k < 3; ++k) {
+        while (!heaps[k].empty()) {
+            kinds[k].push_back(heaps[k].top());
+            heaps[k].pop();
+        }
+        std::sort(kinds[k].begin(), kinds[k].end(), [&](const Cand& x, const Cand& y) { return worse(x, y); });
+    }
+    if (max_candidates < 0) {
+        for (auto& v : kinds) all.insert(all.end(), v.begin(), v.end());
+    } else {
+        // each kind's quota first, then the cheapest of the rest
+        const size_t quota = size_t(max_candidates) / 4;
+        std::vector<Cand> rest;
+        for (auto& v : kinds) {
+            const size_t q = std::min(quota, v.size());
+            all.insert(all.end(), v.begin(), v.begin() + q);
+            rest.insert(rest.end(), v.begin() + q, v.end());
+        }
+        std::sort(rest.begin(), rest.end(), [&](const Cand& x, const Cand& y) { return worse(x, y); });
+        for (const Cand& c : rest) {
+            if (all.size() >= size_t(max_candidates)) break;
+            all.push_back(c);
+        }
     }
     std::sort(all.begin(), all.end(), [&](const Cand& x, const Cand& y) { return worse(x, y); });
     int n = std::min<int>(int(all.size()), cap);

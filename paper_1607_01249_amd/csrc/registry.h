@@ -28,7 +28,9 @@ struct StagedRow {
 };
 int staged_rows(int dtype, bool beta0, const StagedRow** out);
 
-// The dense-tile kernel for a dtype and beta class.
+// The dense-tile kernel for a dtype and beta class, and the workgroups that
+// fill the device with it (its launches loop over the tiles).
 TileLaunchFn dense_launcher(int dtype, bool beta0);
+uint32_t dense_grid(int dtype, bool beta0);
 
 }  // namespace ttx

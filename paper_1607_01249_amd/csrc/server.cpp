@@ -88,6 +88,7 @@ struct Request {
     Problem p;
     ttx_config cfg;          // batched-menu config, chosen at submission
     ttx_config direct;       // per-call config, for requests large enough to run alone
+    BatchDesc desc;          // described at submission; an arena output is filled in at launch
     bool large = false;
     bool beta0;
     double alpha, beta;
@@ -115,6 +116,7 @@ struct Slot {
     uint32_t* d_counter = nullptr;
     std::vector<uint64_t> tickets;
     bool busy = false;
+    bool finished = false;   // seen complete by the dispatcher's lock-free poll
     int64_t fake_done_at = 0;
 };
 
@@ -134,6 +136,7 @@ struct ttx_server {
 
     std::mutex mu;
     std::condition_variable cv_work;   // wakes the dispatcher
+    std::atomic<uint64_t> work_seq{0};  // bumped on submission, release and stop
     std::condition_variable cv_done;   // wakes waiters
     std::deque<uint64_t> waiting;      // submitted, not admitted yet
     std::deque<uint64_t> ready;        // admitted, not launched yet
@@ -156,15 +159,17 @@ static void release_locked(ttx_server* s, Request& r) {
 }
 
 // Completion: requests of finished slots become DONE.
+// Whether a busy slot's work is complete (dispatcher thread only; no lock).
+static bool slot_complete(const ttx_server* s, Slot& slot) {
+    if (!slot.finished)
+        slot.finished = s->opts.fake_device ? now_ns() >= slot.fake_done_at
+                                            : hipEventQuery(slot.done) == hipSuccess;
+    return slot.finished;
+}
+
 static void reap_locked(ttx_server* s) {
     for (auto& slot : s->slots) {
-        if (!slot.busy) continue;
-        bool finished;
-        if (s->opts.fake_device)
-            finished = now_ns() >= slot.fake_done_at;
-        else
-            finished = hipEventQuery(slot.done) == hipSuccess;
-        if (!finished) continue;
+        if (!slot.busy || !slot_complete(s, slot)) continue;
         const int64_t t = now_ns();
         for (uint64_t tk : slot.tickets) {
             auto it = s->reqs.find(tk);
@@ -184,6 +189,7 @@ static void reap_locked(ttx_server* s) {
         }
         slot.tickets.clear();
         slot.busy = false;
+        slot.finished = false;
         s->cv_done.notify_all();
     }
 }
@@ -243,11 +249,8 @@ static bool launch_locked(ttx_server* s) {
             return true;
         }
         BatchDesc& d = h_desc[count];
-        if (batch_describe(r.p, &r.cfg, r.beta0, r.A, r.Bin, r.Bout, r.alpha, r.beta, &d, nullptr) != TTX_OK) {
-            // cannot happen for a validated request; count it as done to keep the loop live
-            d.variant = -1;
-            d.tiles = 0;
-        }
+        d = r.desc;
+        if (r.arena_out) batch_set_output(&d, r.Bout);
         bytes += r.bytes;
         r.state = RUNNING;
         slot->tickets.push_back(s->ready.front());
@@ -288,10 +291,19 @@ static void worker_main(ttx_server* s) {
         const bool busy = s->running > 0;
         if (s->stop && !busy) break;   // requests never launched are dropped
         if (busy) {
-            // device work in flight: poll its completion without sleeping
-            // (a sleep would add the scheduler's timer slack to every latency)
+            // device work in flight: poll its completion without sleeping (a
+            // sleep would add the scheduler's timer slack to every latency)
+            // and without the lock, so that submissions are not held up;
+            // return to the locked part when a slot finishes or work arrives
+            const uint64_t seq = s->work_seq.load(std::memory_order_acquire);
             lock.unlock();
-            std::this_thread::yield();
+            while (true) {
+                bool done = false;
+                for (auto& slot : s->slots)
+                    if (slot.busy && slot_complete(s, slot)) done = true;
+                if (done || s->work_seq.load(std::memory_order_acquire) != seq) break;
+                std::this_thread::yield();
+            }
             lock.lock();
         } else {
             s->cv_work.wait_for(lock, std::chrono::milliseconds(2));
@@ -354,10 +366,9 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
     if (r.p.family != TTX_FAMILY_EMPTY) {
         // plan outside the lock; arena outputs are 256-byte aligned, like the
         // probe pointer used here for the vector decision
-        BatchDesc probe;
         const void* out_probe = r.arena_out ? reinterpret_cast<void*>(uintptr_t(1) << 44) : r.Bout;
         st = batch_describe(r.p, nullptr, r.beta0, r.A, r.Bin, const_cast<void*>(out_probe), r.alpha,
-                            r.beta, &probe, &r.cfg);
+                            r.beta, &r.desc, &r.cfg);
         if (st != TTX_OK) return st;
         // a large request fills the device by itself: it runs alone with the
         // per-call kernels (whole tile menu, tuned configs)
@@ -387,6 +398,7 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
     } else {
         s->reqs[tk] = r;
         s->waiting.push_back(tk);
+        s->work_seq.fetch_add(1, std::memory_order_release);
         s->cv_work.notify_one();
     }
     *ticket = tk;
@@ -499,6 +511,7 @@ ttx_status ttx_server_release(ttx_server* s, uint64_t ticket) {
     if (it->second.state != DONE) return fail(TTX_EBUSY, "request not finished");
     release_locked(s, it->second);
     s->reqs.erase(it);
+    s->work_seq.fetch_add(1, std::memory_order_release);
     s->cv_work.notify_one();
     return TTX_OK;
 }
@@ -522,33 +535,55 @@ ttx_status ttx_server_drain(ttx_server* s) {
     return s->worker_error.empty() ? TTX_OK : fail(TTX_EHIP, s->worker_error);
 }
 
-ttx_status ttx_server_replay(ttx_server* s, int64_t count, const ttx_request* requests,
-                             const int64_t* offsets_ns, uint64_t* tickets) {
-    if (!s || count < 0 || (count > 0 && (!requests || !offsets_ns || !tickets)))
+ttx_status ttx_server_replay_clients(ttx_server* s, int64_t count, const ttx_request* requests,
+                                     const int64_t* offsets_ns, int clients, uint64_t* tickets) {
+    if (!s || count < 0 || clients < 1 || clients > 64 || (count > 0 && (!requests || !offsets_ns || !tickets)))
         return fail(TTX_EINVAL, "bad replay arguments");
     const int64_t t0 = now_ns();
-    for (int64_t i = 0; i < count; ++i) {
-        const int64_t due = t0 + offsets_ns[i];
-        while (now_ns() < due) {
-            const int64_t wait = due - now_ns();
-            if (wait > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 100000));
-        }
-        ttx_request r = requests[i];
-        r.arrival_ns = due;
-        ttx_status st;
-        // a full queue is back-pressure: retry; a request too large for the
-        // budget can never be admitted and is reported as ticket 0
-        while ((st = submit_one(s, &r, &tickets[i])) == TTX_EBUSY) {
-            std::string why = ttx_last_error();
-            if (why.find("queue full") == std::string::npos) {
-                tickets[i] = 0;
-                break;
+    std::vector<ttx_status> status(clients, TTX_OK);
+    std::vector<std::string> errors(clients);
+    auto client = [&](int c) {
+        for (int64_t i = c; i < count; i += clients) {
+            const int64_t due = t0 + offsets_ns[i];
+            while (now_ns() < due) {
+                const int64_t wait = due - now_ns();
+                if (wait > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 100000));
             }
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            ttx_request r = requests[i];
+            r.arrival_ns = due;
+            ttx_status st;
+            // a full queue is back-pressure: retry; a request too large for the
+            // budget can never be admitted and is reported as ticket 0
+            while ((st = submit_one(s, &r, &tickets[i])) == TTX_EBUSY) {
+                std::string why = ttx_last_error();
+                if (why.find("queue full") == std::string::npos) {
+                    tickets[i] = 0;
+                    break;
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+            if (st != TTX_OK && st != TTX_EBUSY) {
+                status[c] = st;
+                errors[c] = ttx_last_error();
+                return;
+            }
         }
-        if (st != TTX_OK && st != TTX_EBUSY) return st;
+    };
+    if (clients == 1) {
+        client(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int c = 0; c < clients; ++c) pool.emplace_back(client, c);
+        for (auto& t : pool) t.join();
     }
+    for (int c = 0; c < clients; ++c)
+        if (status[c] != TTX_OK) return fail(status[c], errors[c]);
     return TTX_OK;
+}
+
+ttx_status ttx_server_replay(ttx_server* s, int64_t count, const ttx_request* requests,
+                             const int64_t* offsets_ns, uint64_t* tickets) {
+    return ttx_server_replay_clients(s, count, requests, offsets_ns, 1, tickets);
 }
 
 ttx_status ttx_server_get_stats(ttx_server* s, ttx_server_stats* out) {
@@ -610,6 +645,7 @@ ttx_status ttx_server_destroy(ttx_server* s) {
     {
         std::lock_guard<std::mutex> lock(s->mu);
         s->stop = true;
+        s->work_seq.fetch_add(1, std::memory_order_release);
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();

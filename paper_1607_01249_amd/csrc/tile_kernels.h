@@ -662,12 +662,14 @@ void k_preserved(TileArgs<T> a) {
         tile_loop<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
 }
 
+// Launched with about one wave of workgroups, each looping over tiles
+// (pipelined): the per-slot offsets are computed once per workgroup.
 template <typename T, bool BETA0, int CAP>
 __global__ __launch_bounds__(kThreads) void k_dense(TileArgs<T> a) {
     __shared__ T lds[dense_lds_elems(CAP)];
     const uint32_t G = gridDim.x;
     const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP>, false>(lds, a, first, a.g.ntiles, G);
+    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP>, true>(lds, a, first, a.g.ntiles, G);
 }
 
 template <typename T, bool BETA0, int N0, int TX, int TY>

@@ -252,6 +252,8 @@ struct alignas(16) BatchDesc {
 ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0, const void* A,
                           const void* Bsrc, void* Bdst, double alpha, double beta, BatchDesc* d,
                           ttx_config* used);
+// Points a described problem at another output tensor (same alignment class).
+void batch_set_output(BatchDesc* d, void* Bdst);
 // Batched-menu configs for a problem, best heuristic first (for tuning).
 int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int cap);
 // Work layout of a persistent launch over `count` descriptors: sets each

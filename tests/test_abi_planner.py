@@ -220,7 +220,11 @@ def test_candidate_list_is_bounded_and_sorted():
     assert len(cands) == 200  # default capacity
     assert cost == sorted(cost)
     few, few_cost = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=10)
-    assert len(few) == 10 and few_cost == cost[:10]
+    assert len(few) == 10 and few_cost == sorted(few_cost)
+    # each kernel kind keeps a quarter of a bounded list; the rest are the cheapest
+    dense = [c for c in cands if c.flags & ttx.CFG_DENSE]
+    assert len(dense) >= 50 and len([c for c in few if c.flags & ttx.CFG_DENSE]) >= 2
+    assert few_cost[0] == cost[0]
     allc, _ = ttx.ttx_tune_candidates(0, (3, 2, 1, 0), (160, 160, 64, 32), max_candidates=-1, cap=100000)
     # every menu shape x 4 flag sets x the loop orders of each index grouping:
     # 4! orders with single indices, and 3! when B's short stride-1 index (32)

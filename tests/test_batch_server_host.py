@@ -215,3 +215,32 @@ def test_server_runs_large_requests_alone():
         assert all(ttx.ttx_server_poll(s, t) for t in small + [big] + more)
     finally:
         ttx.ttx_server_destroy(s)
+
+
+def test_server_replay_from_several_clients():
+    n = 2000
+    reqs = ttx._ttx.request_array(n)
+    rng = np.random.default_rng(5)
+    for i in range(n):
+        k = int(rng.integers(2, 5))
+        reqs[i]["dtype"] = ttx.F32
+        reqs[i]["n"] = k
+        reqs[i]["perm"][:k] = rng.permutation(k)
+        reqs[i]["size"][:k] = rng.integers(2, 30, size=k)
+        reqs[i]["alpha"] = 1.0
+        reqs[i]["A"] = FAKE_BASE
+    s = ttx.ttx_server_create(fake_device=True, slots=4)
+    try:
+        tickets = ttx.ttx_server_replay_clients(s, reqs, np.zeros(n, dtype=np.int64), 4)
+        assert (tickets > 0).all() and len(set(tickets.tolist())) == n
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["submitted"] == n and st["completed"] == n and st["in_use_bytes"] == 0
+    finally:
+        ttx.ttx_server_destroy(s)
+    with pytest.raises(ttx.TTXError):
+        s = ttx.ttx_server_create(fake_device=True)
+        try:
+            ttx.ttx_server_replay_clients(s, reqs[:4], np.zeros(4, dtype=np.int64), 0)
+        finally:
+            ttx.ttx_server_destroy(s)
