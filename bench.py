@@ -35,7 +35,8 @@ CLIENTS = 4
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = ["tile_kernels.h", "menu.h", "registry.h", "kernels_moved_f32_beta.hip",
                   "kernels_moved_f32_beta0.hip", "kernels_moved_f64_beta.hip",
-                  "kernels_moved_f64_beta0.hip", "kernels_preserved.hip", "dispatch.hip"]
+                  "kernels_moved_f64_beta0.hip", "kernels_preserved.hip", "kernels_staged.hip",
+                  "kernels_dense.hip", "dispatch.hip"]
 METRIC = "achieved HBM GB/s (% of D2D-copy peak) per perm; batched p50/p99 latency vs per-call"
 
 
