@@ -2,13 +2,13 @@
 // own shape, permutation, scalars and tensors, run by ONE persistent kernel.
 //
 // The host plans every problem, picks a tile variant from the small batched
-// menu (tuned per shape or chosen by the heuristics of Sec. 2.3), and writes
-// a descriptor table plus the prefix sums of the per-problem tile counts to
-// device memory.  The kernel is launched with about one wave of resident
-// workgroups; workgroup w takes tiles w, w + G, w + 2G, ... of the combined
-// tile space, finds the owning problem by advancing a cursor over the prefix
-// sums (tile ids only grow, so the cursor only moves forward), and runs that
-// problem's tile body -- the same device code as the per-call kernels.  The
+// menu (tuned per shape or chosen by the heuristics of Sec. 2.3), splits its
+// tiles into chunks of consecutive tiles, and writes the descriptor table and
+// the prefix sums of the per-problem chunk counts to device memory.  The
+// kernel is launched with about one wave of resident workgroups; each claims
+// chunks from a counter, finds the owning problem by binary search over the
+// prefix sums, and runs that problem's tile body over the chunk -- the same
+// tile code as the per-call kernels, pipelined across the chunk's tiles.  The
 // launch is captured once into a HIP graph and replayed.
 #include <cstring>
 #include <map>

@@ -12,7 +12,10 @@
 //     is written along its stride-1 index with 16-byte vector stores;
 //   - preserved family (the stride-1 index stays in place, Sec. 3.2): rows
 //     are contiguous in both tensors, so they are copied directly with
-//     vector loads and stores, no LDS;
+//     vector loads and stores, no LDS; short rows are staged through LDS
+//     with whole rows inside the tile (StagedTile);
+//   - dense tiles (either family): run-time tile extents, rows packed
+//     without padding, several small planes per tile (DenseTile);
 //   - flat: one merged index, a strided axpby.
 // Edge tiles are predicated (the remainder of Sec. 2.3).  The epilogue is
 // Eqn. 1: alpha*a when beta == 0 (B is never read), otherwise
