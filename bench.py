@@ -45,10 +45,15 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines left out (a
+    comment edit does not invalidate measured counters)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1607_01249_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1607_01249_amd", "csrc", name)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
