@@ -32,6 +32,8 @@ PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E, published
 TABLE = os.path.join(ROOT, "paper_1607_01249_amd", "tune", "gfx950.txt")
 # submitting threads of the served runs (clients sharing one server)
 CLIENTS = 4
+# device slots (micro-batches in flight) of the served runs
+SLOTS = 8
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = ["tile_kernels.h", "menu.h", "registry.h", "kernels_moved_f32_beta.hip",
                   "kernels_moved_f32_beta0.hip", "kernels_moved_f64_beta.hip",
@@ -412,7 +414,7 @@ def bench_served(torch, ttx, seconds, rate):
     offsets = (np.asarray(times) * 1e9).astype(np.int64)
     torch.cuda.synchronize()
     log("serving %d requests over %.1f s" % (n, seconds))
-    s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
+    s = ttx.ttx_server_create(slots=SLOTS, arena_bytes=16 << 30)
     try:
         tickets = ttx.ttx_server_replay_clients(s, reqs, offsets, CLIENTS)
         ttx.ttx_server_drain(s)
@@ -452,7 +454,7 @@ def bench_served(torch, ttx, seconds, rate):
                             p99_us=round(st["p99_us"], 1), max_us=round(st["max_us"], 1),
                             batches=st["batches"], mean_batch=round(st["mean_batch"], 2),
                             rejected=st["rejected"], budget_GB=round(st["budget_bytes"] / 1e9, 1),
-                            peak_in_use_GB=round(st["peak_in_use_bytes"] / 1e9, 3), slots=4),
+                            peak_in_use_GB=round(st["peak_in_use_bytes"] / 1e9, 3), slots=SLOTS),
                 sequential=dict(GBps=round(nbytes_total / span / 1e9, 1), p50_us=round(_pct(lat, 50), 1),
                                 p99_us=round(_pct(lat, 99), 1), max_us=round(float(np.max(lat)), 1)),
                 throughput_ratio=round(st["throughput_gbps"] / (nbytes_total / span / 1e9), 2),
@@ -474,7 +476,7 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
     zeros = np.zeros(m, dtype=np.int64)
     total = float(nb[:m].sum())
     log("saturated: %d requests at once (%.2f GB)" % (m, total / 1e9))
-    s = ttx.ttx_server_create(slots=4, arena_bytes=16 << 30)
+    s = ttx.ttx_server_create(slots=SLOTS, arena_bytes=16 << 30)
     try:
         ttx.ttx_server_replay_clients(s, sub, zeros, CLIENTS)
         ttx.ttx_server_drain(s)
@@ -484,7 +486,7 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
     lat = ttx.ttx_replay_sequential(sub, zeros, scratch.data_ptr(), scratch.numel(),
                                     torch.cuda.current_stream().cuda_stream)
     seq_span = float(np.max(lat)) * 1e-6
-    return dict(requests=m, algorithmic_bytes=int(total), clients=CLIENTS,
+    return dict(requests=m, algorithmic_bytes=int(total), clients=CLIENTS, slots=SLOTS,
                 served=dict(GBps=round(st["throughput_gbps"], 1), p50_us=round(st["p50_us"], 1),
                             p99_us=round(st["p99_us"], 1), batches=st["batches"],
                             mean_batch=round(st["mean_batch"], 2)),
