@@ -78,9 +78,13 @@ def parse_args():
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="Poisson arrival rate (req/s)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: no tuning, 1 warm-up, 2 steps, no CPU leg")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="for rocprofv3: only the 512-problem batched comparison, untuned, 5 replays")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "script into profiles/traffic_counters.json and exit")
+    ap.add_argument("--traffic-out", default=None,
+                    help="where --traffic-from writes (default profiles/traffic_counters.json)")
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="print the kernel statistics of a rocprofv3 --kernel-trace --stats run")
     return ap.parse_args()
@@ -245,7 +249,7 @@ def _short_kernel(name):
     return out
 
 
-def traffic_from(fetch_path, write_path):
+def traffic_from(fetch_path, write_path, out_path=None):
     """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of every ttx kernel from two
     rocprofv3 --pmc runs of bench.py, each scaled by what the same counter
     reads for the 1 GiB copy kernel (1 GiB read, 1 GiB written)."""
@@ -276,7 +280,7 @@ def traffic_from(fetch_path, write_path):
                copy_kernel_kib=dict(FETCH_SIZE=res["FETCH_SIZE"]["copy_kib"],
                                     WRITE_SIZE=res["WRITE_SIZE"]["copy_kib"]),
                kernels=table)
-    with open(TRAFFIC, "w") as f:
+    with open(out_path or TRAFFIC, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     print(json.dumps(out, sort_keys=True))
 
@@ -303,7 +307,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
-def bench_batched(torch, ttx, reps=20):
+def bench_batched(torch, ttx, reps=20, tune=True):
     """The 512 uneven transpositions: per-call loop vs one graph-captured
     persistent launch (after per-shape tuning)."""
     import workloads
@@ -340,7 +344,8 @@ def bench_batched(torch, ttx, reps=20):
         lat_pc.append((time.perf_counter() - t0) * 1e6)
     h = ttx.ttx_batch_create(qs)
     t0 = time.time()
-    ttx.ttx_batch_tune(h, 8, 2)
+    if tune:
+        ttx.ttx_batch_tune(h, 8, 2)
     tune_s = time.time() - t0
     info = ttx.ttx_batch_get_info(h)
     run = lambda: ttx.ttx_batch_execute(h, stream)
@@ -499,7 +504,7 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
 def main():
     args = parse_args()
     if args.traffic_from:
-        traffic_from(*args.traffic_from)
+        traffic_from(*args.traffic_from, out_path=args.traffic_out)
         return 0
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
@@ -518,6 +523,17 @@ def main():
     ttx.lib()   # raises when the HIP library is not built
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.profile_batched:
+        # the 1 GiB copy kernel first: the counter runs calibrate against it
+        src = torch.empty((1 << 30) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        fill_uniform(torch, src, 1)
+        for _ in range(3):
+            ttx.ttx_copy_kernel(src.data_ptr(), dst.data_ptr(), 1 << 30, stream)
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps(bench_batched(torch, ttx, reps=5, tune=False)))
+        return 0
     cases = make_cases(args.literal)
     log("allocating %d cases (%.1f GiB)" % (len(cases), sum(2 * c["elements"] * c["dtype"].itemsize for c in cases) / 2 ** 30))
     for i, c in enumerate(cases):
