@@ -4,7 +4,9 @@
 // elements for both data types (64 B of FP32, one 128-B line of FP64), so the
 // regular moved-family tiles are {16,32,48,64} x {16,32,48,64}.  For indices
 // shorter than w the remainder rule of Sec. 2.3 would waste most of a tile,
-// so skinny shapes pair a short edge with a long one.  Preserved-family
+// so skinny shapes pair a short edge with a long one; long-run shapes (512-B
+// FP32 and 1-KiB FP64 runs along one side) trade the other edge for fewer
+// DRAM pages per tile.  Preserved-family
 // tiles copy rows that are contiguous in both tensors; they are sized by
 // the number of elements a workgroup moves (1K to 4K).
 #pragma once
@@ -13,12 +15,12 @@
 #define TTX_MOVED_MENU_F32(X)                                                             \
     X(16, 16) X(16, 32) X(16, 48) X(16, 64) X(32, 16) X(32, 32) X(32, 48) X(32, 64)       \
     X(48, 16) X(48, 32) X(48, 48) X(48, 64) X(64, 16) X(64, 32) X(64, 48) X(64, 64)       \
-    X(4, 256) X(8, 128) X(256, 4) X(128, 8)
+    X(4, 256) X(8, 128) X(256, 4) X(128, 8) X(128, 32) X(32, 128)
 
 #define TTX_MOVED_MENU_F64(X)                                                             \
     X(16, 16) X(16, 32) X(16, 48) X(16, 64) X(32, 16) X(32, 32) X(32, 48) X(32, 64)       \
     X(48, 16) X(48, 32) X(48, 48) X(48, 64) X(64, 16) X(64, 32) X(64, 48) X(64, 64)       \
-    X(2, 256) X(4, 128) X(256, 2) X(128, 4)
+    X(2, 256) X(4, 128) X(256, 2) X(128, 4) X(128, 16) X(16, 128)
 
 // X(tile_a, rows)
 #define TTX_PRESERVED_MENU_F32(X)                                                         \
