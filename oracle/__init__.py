@@ -24,7 +24,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttxref.so")
 
 OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED = 0, 1, 2, 3, 4
-DTYPES = {np.dtype(np.float32): 0, np.dtype(np.float64): 1}
+DTYPES = {np.dtype(np.float32): 0, np.dtype(np.float64): 1,
+          np.dtype(np.complex64): 2, np.dtype(np.complex128): 3}
 
 _lib = None
 
@@ -48,6 +49,14 @@ def _load(path):
                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
                                     ctypes.c_void_p]
     L.ttx_ref_transpose.restype = ctypes.c_int
+    d2 = ctypes.POINTER(ctypes.c_double)
+    L.ttx_ref_transpose_c.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p, d2,
+                                      ctypes.c_void_p, d2, ctypes.c_void_p]
+    L.ttx_ref_transpose_c.restype = ctypes.c_int
+    L.ttx_ref_sample_c.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p, d2,
+                                   ctypes.c_void_p, d2, ctypes.c_void_p, ctypes.c_int64, i64p,
+                                   ctypes.c_void_p]
+    L.ttx_ref_sample_c.restype = ctypes.c_int
     L.ttx_ref_check.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
                                 ctypes.c_void_p, ctypes.c_void_p]
     L.ttx_ref_check.restype = ctypes.c_int
@@ -69,22 +78,28 @@ def _arr(vals, ctype):
     return (ctype * max(1, len(vals)))(*vals)
 
 
+def _scalar2(v):
+    v = complex(v)
+    return (ctypes.c_double * 2)(v.real, v.imag)
+
+
 def transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, library=None):
     """B <- alpha * Pi(A) + beta * B in place on host numpy arrays (Eqn. 1).
 
-    ``A`` and ``B`` are flat numpy arrays of one dtype (float32 or float64)
-    holding the column-major outer tensors; ``perm`` is the gather
-    permutation (B position k holds A index ``perm[k]``).  Returns the C
-    status code.
+    ``A`` and ``B`` are flat numpy arrays of one dtype (float32, float64,
+    complex64 or complex128) holding the column-major outer tensors;
+    ``perm`` is the gather permutation (B position k holds A index
+    ``perm[k]``).  ``alpha`` and ``beta`` may be complex for the complex
+    dtypes.  Returns the C status code.
     """
     L = library or lib()
     assert A.dtype == B.dtype and A.dtype in DTYPES
     assert A.flags.c_contiguous and B.flags.c_contiguous and B.flags.writeable
     n = len(perm)
-    return L.ttx_ref_transpose(DTYPES[A.dtype], n, _arr(perm, ctypes.c_int),
-                               _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
-                               _arr(outer_b, ctypes.c_int64), float(alpha),
-                               A.ctypes.data, float(beta), B.ctypes.data)
+    return L.ttx_ref_transpose_c(DTYPES[A.dtype], n, _arr(perm, ctypes.c_int),
+                                 _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
+                                 _arr(outer_b, ctypes.c_int64), _scalar2(alpha),
+                                 A.ctypes.data, _scalar2(beta), B.ctypes.data)
 
 
 def check(dtype_code, perm, size, outer_a=None, outer_b=None, a_addr=1 << 20, b_addr=1 << 40,
@@ -106,11 +121,11 @@ def sample(perm, size, alpha, A, beta, B_in, b_index, outer_a=None, outer_b=None
     out = np.empty(len(b_index), dtype=A.dtype)
     off = np.empty(len(b_index), dtype=np.int64)
     i64p = ctypes.POINTER(ctypes.c_int64)
-    st = L.ttx_ref_sample(DTYPES[A.dtype], len(perm), _arr(perm, ctypes.c_int),
-                          _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
-                          _arr(outer_b, ctypes.c_int64), float(alpha), A.ctypes.data, float(beta),
-                          B_in.ctypes.data if B_in is not None else None, len(b_index),
-                          b_index.ctypes.data_as(i64p), out.ctypes.data)
+    st = L.ttx_ref_sample_c(DTYPES[A.dtype], len(perm), _arr(perm, ctypes.c_int),
+                            _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
+                            _arr(outer_b, ctypes.c_int64), _scalar2(alpha), A.ctypes.data,
+                            _scalar2(beta), B_in.ctypes.data if B_in is not None else None,
+                            len(b_index), b_index.ctypes.data_as(i64p), out.ctypes.data)
     assert st == OK, st
     st = L.ttx_ref_b_offsets(len(perm), _arr(perm, ctypes.c_int), _arr(size, ctypes.c_int64),
                              _arr(outer_b, ctypes.c_int64), len(b_index),

@@ -6,6 +6,10 @@ reshaped column-major, the addressed sub-tensor is sliced out, and
 ``np.transpose(sub, perm)`` produces the tensor laid out in B's index order
 (gather reading: B position k holds A index ``perm[k]``, Sec. 2.1).  numpy
 rounds each elementwise product and sum separately in the array's dtype.
+For the complex dtypes numpy's own complex product is used, whose internal
+rounding order (and use of fused multiply-add) numpy does not fix: complex
+results agree with the C oracle to within a few units in the last place,
+not bit for bit.
 """
 import numpy as np
 
@@ -30,7 +34,10 @@ def transpose_np(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None):
     a_sub = _sub(A, outer_a, size)
     b_sub = _sub(B, outer_b, size_b)
     moved = np.transpose(a_sub, perm)
-    alpha_t, beta_t = t(alpha), t(beta)
+    if np.iscomplexobj(A):
+        alpha_t, beta_t = t(complex(alpha)), t(complex(beta))
+    else:
+        alpha_t, beta_t = t(alpha), t(beta)
     if beta_t == 0:
         b_sub[...] = alpha_t * moved
     else:

@@ -24,7 +24,12 @@
  *     rounded beta is zero, B is only written, never read (Sec. 1: beta = 0
  *     overwrites B);
  *   - each product and the sum are rounded separately in the element type
- *     (no fused multiply-add).  Build with -ffp-contract=off.
+ *     (no fused multiply-add).  Build with -ffp-contract=off;
+ *   - data types (the four of the paper's type list, Sec. 3): 0 = float,
+ *     1 = double, 2 = single complex, 3 = double complex.  Complex elements
+ *     are interleaved (re, im) pairs and alpha, beta may be complex (the
+ *     _c entry points); the order of the complex arithmetic is stated at
+ *     ref_update_c32 below.
  *
  * The loop nest walks B linearly (B index 0 fastest), the loop order of the
  * reference implementation of Sec. 3.2, with the outermost B index shared
@@ -41,7 +46,7 @@
 #include <omp.h>
 
 enum { REF_OK = 0, REF_EINVAL = 1, REF_EPERM = 2, REF_EOVERLAP = 3, REF_EUNSUPPORTED = 4 };
-enum { REF_F32 = 0, REF_F64 = 1 };
+enum { REF_F32 = 0, REF_F64 = 1, REF_C32 = 2, REF_C64 = 3 };
 #define REF_MAX_DIMS 16
 
 /* Checks the arguments and fills in sizeB and the two stride vectors.
@@ -54,7 +59,7 @@ static int ref_prepare(int dtype, int n, const int *perm, const int64_t *size,
     int seen[REF_MAX_DIMS] = {0};
     int64_t prod;
 
-    if (dtype != REF_F32 && dtype != REF_F64)
+    if (dtype != REF_F32 && dtype != REF_F64 && dtype != REF_C32 && dtype != REF_C64)
         return REF_EINVAL;
     if (n < 1 || n > REF_MAX_DIMS || perm == NULL || size == NULL)
         return REF_EINVAL;
@@ -127,6 +132,51 @@ static void ref_update_f64(const double *A, double *B, int64_t off_a, int64_t of
     }
 }
 
+/* Complex elements (the c and z data types of the paper's type list) are
+ * interleaved (re, im) pairs.  The product of scalar s = (sr, si) and
+ * element x = (xr, xi) is written out as
+ *     re = fl( fl(sr*xr) - fl(si*xi) ),   im = fl( fl(sr*xi) + fl(si*xr) ),
+ * every product and sum rounded separately in the element type (the paper
+ * fixes no order for complex arithmetic; this one is the textbook formula,
+ * evaluated left to right).  The update adds the two products part by part:
+ * B = fl(alpha*a + beta*b) componentwise, and B is not read when both parts
+ * of the rounded beta are zero. */
+static void ref_update_c32(const float *A, float *B, int64_t off_a, int64_t off_b,
+                           float ar, float ai, float br, float bi)
+{
+    const float xr = A[2 * off_a], xi = A[2 * off_a + 1];
+    float t1 = ar * xr, t2 = ai * xi, t3 = ar * xi, t4 = ai * xr;
+    float pr = t1 - t2, pi = t3 + t4;
+    if (br == 0.0f && bi == 0.0f) {
+        B[2 * off_b] = pr;
+        B[2 * off_b + 1] = pi;
+    } else {
+        const float yr = B[2 * off_b], yi = B[2 * off_b + 1];
+        float u1 = br * yr, u2 = bi * yi, u3 = br * yi, u4 = bi * yr;
+        float qr = u1 - u2, qi = u3 + u4;
+        B[2 * off_b] = pr + qr;
+        B[2 * off_b + 1] = pi + qi;
+    }
+}
+
+static void ref_update_c64(const double *A, double *B, int64_t off_a, int64_t off_b,
+                           double ar, double ai, double br, double bi)
+{
+    const double xr = A[2 * off_a], xi = A[2 * off_a + 1];
+    double t1 = ar * xr, t2 = ai * xi, t3 = ar * xi, t4 = ai * xr;
+    double pr = t1 - t2, pi = t3 + t4;
+    if (br == 0.0 && bi == 0.0) {
+        B[2 * off_b] = pr;
+        B[2 * off_b + 1] = pi;
+    } else {
+        const double yr = B[2 * off_b], yi = B[2 * off_b + 1];
+        double u1 = br * yr, u2 = bi * yi, u3 = br * yi, u4 = bi * yr;
+        double qr = u1 - u2, qi = u3 + u4;
+        B[2 * off_b] = pr + qr;
+        B[2 * off_b + 1] = pi + qi;
+    }
+}
+
 /* Validation only: the status ttx_ref_transpose would return, without
  * touching A or B (A and B are compared as addresses only). */
 int ttx_ref_check(int dtype, int n, const int *perm, const int64_t *size,
@@ -142,7 +192,7 @@ int ttx_ref_check(int dtype, int n, const int *perm, const int64_t *size,
         return st;
     if (A == NULL || B == NULL)
         return REF_EINVAL;
-    elem = dtype == REF_F32 ? 4 : 8;
+    elem = dtype == REF_F32 ? 4 : dtype == REF_C64 ? 16 : 8;
     a_lo = (int64_t)(uintptr_t)A;
     a_hi = a_lo + ref_extent_bytes(n, size, stride_a, elem);
     b_lo = (int64_t)(uintptr_t)B;
@@ -152,15 +202,21 @@ int ttx_ref_check(int dtype, int n, const int *perm, const int64_t *size,
     return REF_OK;
 }
 
-/* B_{Pi(i)} <- alpha*A_i + beta*B_{Pi(i)} over host arrays (Eqn. 1). */
-int ttx_ref_transpose(int dtype, int n, const int *perm, const int64_t *size,
-                      const int64_t *outer_a, const int64_t *outer_b,
-                      double alpha, const void *A, double beta, void *B)
+/* B_{Pi(i)} <- alpha*A_i + beta*B_{Pi(i)} over host arrays (Eqn. 1), with
+ * complex scalars alpha = (alpha[0], alpha[1]) and beta likewise; for the
+ * real data types the imaginary parts must be zero. */
+int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
+                        const int64_t *outer_a, const int64_t *outer_b,
+                        const double *alpha, const void *A, const double *beta, void *B)
 {
     int64_t size_b[REF_MAX_DIMS], stride_a[REF_MAX_DIMS], stride_b[REF_MAX_DIMS];
     int64_t a_stride_in_b_order[REF_MAX_DIMS];
     int empty, st;
-    const float alpha_f = (float)alpha, beta_f = (float)beta;
+    const float alpha_f = (float)alpha[0], beta_f = (float)beta[0];
+    const float alpha_fi = (float)alpha[1], beta_fi = (float)beta[1];
+
+    if ((dtype == REF_F32 || dtype == REF_F64) && (alpha[1] != 0.0 || beta[1] != 0.0))
+        return REF_EINVAL;
 
     st = ttx_ref_check(dtype, n, perm, size, outer_a, outer_b, A, B);
     if (st != REF_OK)
@@ -190,8 +246,13 @@ int ttx_ref_transpose(int dtype, int n, const int *perm, const int64_t *size,
             }
             if (dtype == REF_F32)
                 ref_update_f32((const float *)A, (float *)B, off_a, off_b, alpha_f, beta_f);
+            else if (dtype == REF_F64)
+                ref_update_f64((const double *)A, (double *)B, off_a, off_b, alpha[0], beta[0]);
+            else if (dtype == REF_C32)
+                ref_update_c32((const float *)A, (float *)B, off_a, off_b, alpha_f, alpha_fi, beta_f, beta_fi);
             else
-                ref_update_f64((const double *)A, (double *)B, off_a, off_b, alpha, beta);
+                ref_update_c64((const double *)A, (double *)B, off_a, off_b, alpha[0], alpha[1], beta[0],
+                               beta[1]);
             for (int k = 0; k < n - 1; ++k) {   /* advance the odometer */
                 if (++j[k] < size_b[k])
                     break;
@@ -202,25 +263,43 @@ int ttx_ref_transpose(int dtype, int n, const int *perm, const int64_t *size,
     return REF_OK;
 }
 
+/* The real-scalar form of ttx_ref_transpose_c (any data type). */
+int ttx_ref_transpose(int dtype, int n, const int *perm, const int64_t *size,
+                      const int64_t *outer_a, const int64_t *outer_b,
+                      double alpha, const void *A, double beta, void *B)
+{
+    const double a2[2] = {alpha, 0.0}, b2[2] = {beta, 0.0};
+    return ttx_ref_transpose_c(dtype, n, perm, size, outer_a, outer_b, a2, A, b2, B);
+}
+
 /* Eqn. 1 at chosen elements only: for each q < count, B_index[q] is the
- * position of an element of B's sub-tensor in B-linear order (B index 0
- * fastest); out[q] receives alpha*A + beta*B_in at that position, where A is
- * the element the permutation sends there.  B_in is read only when the
- * rounded beta is non-zero.  Lets large problems be checked on samples. */
-int ttx_ref_sample(int dtype, int n, const int *perm, const int64_t *size,
-                   const int64_t *outer_a, const int64_t *outer_b,
-                   double alpha, const void *A, double beta, const void *B_in,
-                   int64_t count, const int64_t *B_index, void *out)
+ * B-linear position inside the sub-tensor (first B index fastest); out[q]
+ * receives the value the transposition leaves there, given B's prior
+ * contents B_in (not read when beta rounds to zero).  Complex scalars as in
+ * ttx_ref_transpose_c; each element takes the same operations, in the same
+ * order, as in the full loop nest. */
+int ttx_ref_sample_c(int dtype, int n, const int *perm, const int64_t *size,
+                     const int64_t *outer_a, const int64_t *outer_b,
+                     const double *alpha, const void *A, const double *beta, const void *B_in,
+                     int64_t count, const int64_t *B_index, void *out)
 {
     int64_t size_b[REF_MAX_DIMS], stride_a[REF_MAX_DIMS], stride_b[REF_MAX_DIMS];
     int empty, st;
-    const float alpha_f = (float)alpha, beta_f = (float)beta;
+    const float alpha_f = (float)alpha[0], beta_f = (float)beta[0];
+    const float alpha_fi = (float)alpha[1], beta_fi = (float)beta[1];
+    int reads_b;
 
+    if ((dtype == REF_F32 || dtype == REF_F64) && (alpha[1] != 0.0 || beta[1] != 0.0))
+        return REF_EINVAL;
     st = ref_prepare(dtype, n, perm, size, outer_a, outer_b, size_b, stride_a, stride_b, &empty);
     if (st != REF_OK)
         return st;
     if (empty)
         return count == 0 ? REF_OK : REF_EINVAL;
+    if (dtype == REF_F32 || dtype == REF_C32)
+        reads_b = beta_f != 0.0f || beta_fi != 0.0f;
+    else
+        reads_b = beta[0] != 0.0 || beta[1] != 0.0;
     for (int64_t q = 0; q < count; ++q) {
         int64_t rest = B_index[q], off_a = 0, off_b = 0;
         for (int k = 0; k < n; ++k) {
@@ -231,25 +310,41 @@ int ttx_ref_sample(int dtype, int n, const int *perm, const int64_t *size,
         }
         if (B_index[q] < 0 || rest != 0)
             return REF_EINVAL;
-        if (dtype == REF_F32) {
-            float b = beta_f == 0.0f ? 0.0f : ((const float *)B_in)[off_b];
-            float r = alpha_f * ((const float *)A)[off_a];
-            if (beta_f != 0.0f) {
-                float scaled_b = beta_f * b;
-                r = r + scaled_b;
-            }
-            ((float *)out)[q] = r;
-        } else {
-            double b = beta == 0.0 ? 0.0 : ((const double *)B_in)[off_b];
-            double r = alpha * ((const double *)A)[off_a];
-            if (beta != 0.0) {
-                double scaled_b = beta * b;
-                r = r + scaled_b;
-            }
-            ((double *)out)[q] = r;
+        /* out[q] stands in for B's element: load B's prior value, update. */
+        switch (dtype) {
+        case REF_F32:
+            ((float *)out)[q] = reads_b ? ((const float *)B_in)[off_b] : 0.0f;
+            ref_update_f32((const float *)A, (float *)out, off_a, q, alpha_f, beta_f);
+            break;
+        case REF_F64:
+            ((double *)out)[q] = reads_b ? ((const double *)B_in)[off_b] : 0.0;
+            ref_update_f64((const double *)A, (double *)out, off_a, q, alpha[0], beta[0]);
+            break;
+        case REF_C32:
+            ((float *)out)[2 * q] = reads_b ? ((const float *)B_in)[2 * off_b] : 0.0f;
+            ((float *)out)[2 * q + 1] = reads_b ? ((const float *)B_in)[2 * off_b + 1] : 0.0f;
+            ref_update_c32((const float *)A, (float *)out, off_a, q, alpha_f, alpha_fi, beta_f, beta_fi);
+            break;
+        default:
+            ((double *)out)[2 * q] = reads_b ? ((const double *)B_in)[2 * off_b] : 0.0;
+            ((double *)out)[2 * q + 1] = reads_b ? ((const double *)B_in)[2 * off_b + 1] : 0.0;
+            ref_update_c64((const double *)A, (double *)out, off_a, q, alpha[0], alpha[1], beta[0],
+                           beta[1]);
+            break;
         }
     }
     return REF_OK;
+}
+
+/* The real-scalar form of ttx_ref_sample_c. */
+int ttx_ref_sample(int dtype, int n, const int *perm, const int64_t *size,
+                   const int64_t *outer_a, const int64_t *outer_b,
+                   double alpha, const void *A, double beta, const void *B_in,
+                   int64_t count, const int64_t *B_index, void *out)
+{
+    const double a2[2] = {alpha, 0.0}, b2[2] = {beta, 0.0};
+    return ttx_ref_sample_c(dtype, n, perm, size, outer_a, outer_b, a2, A, b2, B_in, count, B_index,
+                            out);
 }
 
 /* Offset (in elements) of each B-linear sub-tensor position inside B's outer

@@ -57,7 +57,7 @@ def test_status_strings():
 
 # -- validation: the library's synchronous checks agree with the oracle's -------------
 INVALID = [
-    dict(dtype=2, perm=(0, 1), size=(2, 3)),
+    dict(dtype=4, perm=(0, 1), size=(2, 3)),
     dict(dtype=0, perm=(0, 0), size=(2, 3)),
     dict(dtype=0, perm=(0, 2), size=(2, 3)),
     dict(dtype=0, perm=(1, 0), size=(2, -1)),

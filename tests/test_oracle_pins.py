@@ -13,7 +13,12 @@ mathematics fixes:
 * round trip through the inverse permutation, and composition of two
   permutations (which separates the gather from the scatter reading);
 * the update against a separate elementwise axpby, beta = 0 never reading B,
-  the non-fused operation order (contraction detector), special values.
+  the non-fused operation order (contraction detector), special values;
+* complex elements (the c and z types): with real scalars the result equals
+  the real transposition of the interleaved (re, im) planes, multiplying by
+  i swaps and negates parts exactly, numpy's complex arithmetic agrees to a
+  few units in the last place, and exact rational arithmetic stays within
+  the rounding-error bound of the stated operation order.
 
 ``test_pins_catch_planted_mistakes`` compiles deliberately broken copies of
 the oracle and checks that some pin fails for each of them.
@@ -34,6 +39,8 @@ from oracle.ref_np import transpose_np
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+C32, C64 = np.dtype(np.complex64), np.dtype(np.complex128)
+REAL_OF = {C32: F32, C64: F64}
 
 
 def _golden(name):
@@ -46,7 +53,11 @@ def _elems(dims):
 
 
 def _rand(n, dtype, rng):
-    if np.dtype(dtype) == F32:
+    dtype = np.dtype(dtype)
+    if dtype in REAL_OF:
+        parts = _rand(2 * n, REAL_OF[dtype], rng)
+        return parts.view(dtype)
+    if dtype == F32:
         return rng.random(n, dtype=np.float32) * 2 - 1
     return rng.random(n) * 2 - 1
 
@@ -58,6 +69,8 @@ def _run(L, perm, size, alpha, A, beta, B, outer_a=None, outer_b=None):
 
 
 def _bits(x):
+    if x.dtype in REAL_OF:
+        x = x.view(REAL_OF[x.dtype])
     return x.view(np.uint32 if x.dtype == F32 else np.uint64)
 
 
@@ -289,7 +302,9 @@ def pin_validation(L):
     big = 1 << 40
     c = lambda *a, **k: oracle.check(*a, library=L, **k)
     assert c(0, (0, 1), (2, 3)) == oracle.OK
-    assert c(2, (0, 1), (2, 3)) == oracle.EINVAL            # unknown dtype
+    assert c(2, (0, 1), (2, 3)) == oracle.OK                # single complex
+    assert c(4, (0, 1), (2, 3)) == oracle.EINVAL            # unknown dtype
+    assert c(-1, (0, 1), (2, 3)) == oracle.EINVAL
     assert c(0, (0, 0), (2, 3)) == oracle.EPERM             # repeated index
     assert c(0, (0, 2), (2, 3)) == oracle.EPERM             # out of range
     assert c(0, (1, 0), (2, -1)) == oracle.EINVAL           # negative extent
@@ -301,13 +316,152 @@ def pin_validation(L):
     assert c(0, (1, 0), (2, 3), a_addr=big, b_addr=big + 20) == oracle.EOVERLAP
     assert c(0, (1, 0), (2, 3), a_addr=big, b_addr=big + 24) == oracle.OK
     assert c(1, (1, 0), (2, 3), a_addr=big, b_addr=big + 24) == oracle.EOVERLAP
+    assert c(2, (1, 0), (2, 3), a_addr=big, b_addr=big + 48) == oracle.OK        # 8-byte elements
+    assert c(3, (1, 0), (2, 3), a_addr=big, b_addr=big + 88) == oracle.EOVERLAP  # 16-byte elements
+    assert c(3, (1, 0), (2, 3), a_addr=big, b_addr=big + 96) == oracle.OK
     assert c(0, (1, 0), (0, 3), a_addr=big, b_addr=big) == oracle.OK   # empty: nothing to do
+
+
+# ---------------------------------------------------------------------------------------
+# Complex elements.
+
+def _complex_cases():
+    return [((2, 0, 3, 1), (3, 4, 2, 5), None, None),
+            ((1, 0), (7, 6), (9, 6), (8, 7)),
+            ((0, 2, 1), (5, 3, 4), None, None)]
+
+
+def _inner_mask(outer, extent):
+    mask = np.zeros(tuple(int(o) for o in outer), dtype=bool)
+    mask[tuple(slice(0, int(e)) for e in extent)] = True
+    return mask.flatten(order="F")
+
+
+def pin_complex_real_scalars_are_planewise(L):
+    """Real alpha, beta: the complex transposition is the real one applied to
+    the (re, im) planes, i.e. a real transposition with one more, kept,
+    leading index of extent 2."""
+    rng = np.random.default_rng(31)
+    for dtype in (C32, C64):
+        real = REAL_OF[dtype]
+        for perm, size, oa, ob in _complex_cases():
+            size_b = [size[p] for p in perm]
+            A = _rand(_elems(oa or size), dtype, rng)
+            B0 = _rand(_elems(ob or size_b), dtype, rng)
+            perm2 = (0,) + tuple(p + 1 for p in perm)
+            size2 = (2,) + tuple(size)
+            oa2 = None if oa is None else (2,) + tuple(oa)
+            ob2 = None if ob is None else (2,) + tuple(ob)
+            for alpha, beta in ((1.0, 0.0), (-1.75, 0.0), (1.3, 0.7), (0.5, -2.25)):
+                got = B0.copy()
+                _run(L, perm, size, alpha, A, beta, got, oa, ob)
+                want = B0.view(real).copy()
+                _run(L, perm2, size2, alpha, A.view(real), beta, want, oa2, ob2)
+                assert _same_bits(got.view(real), want), (dtype, perm, alpha, beta)
+
+
+def pin_complex_times_i(L):
+    """alpha = i rotates: (re, im) -> (-im, re) exactly; beta = i adds
+    i*B, i.e. re -= B.im and im += B.re, one rounding each."""
+    rng = np.random.default_rng(32)
+    for dtype in (C32, C64):
+        for perm, size, oa, ob in _complex_cases():
+            size_b = [size[p] for p in perm]
+            A = _rand(_elems(oa or size), dtype, rng)
+            B0 = _rand(_elems(ob or size_b), dtype, rng)
+            inner = _inner_mask(ob or size_b, size_b)
+            plain = B0.copy()
+            _run(L, perm, size, 1.0, A, 0.0, plain, oa, ob)
+            got = B0.copy()
+            _run(L, perm, size, 1j, A, 0.0, got, oa, ob)
+            assert np.array_equal(got.real[inner], -plain.imag[inner])
+            assert np.array_equal(got.imag[inner], plain.real[inner])
+            got = B0.copy()
+            _run(L, perm, size, 1.0, A, 1j, got, oa, ob)
+            assert np.array_equal(got.real[inner], (plain.real - B0.imag)[inner])
+            assert np.array_equal(got.imag[inner], (plain.imag + B0.real)[inner])
+            assert _same_bits(got[~inner], B0[~inner])
+
+
+def pin_complex_vs_numpy(L):
+    """numpy's complex arithmetic (whose rounding order numpy leaves open)
+    agrees to within a few units in the last place, on every permutation of
+    up to 4 indices."""
+    rng = np.random.default_rng(33)
+    for dtype in (C32, C64):
+        eps = np.finfo(REAL_OF[dtype]).eps
+        for n in range(1, 5):
+            for perm in itertools.permutations(range(n)):
+                size = tuple(int(v) for v in rng.integers(1, 5, size=n))
+                size_b = [size[p] for p in perm]
+                A = _rand(_elems(size), dtype, rng)
+                B0 = _rand(_elems(size_b), dtype, rng)
+                alpha, beta = complex(*rng.uniform(-2, 2, 2)), complex(*rng.uniform(-2, 2, 2))
+                got = B0.copy()
+                _run(L, perm, size, alpha, A, beta, got)
+                want = B0.copy()
+                transpose_np(perm, size, alpha, A, beta, want)
+                tol = 16.0 * (abs(alpha) + abs(beta)) * eps
+                assert np.abs(got - want).max() <= tol, (dtype, perm)
+
+
+def _exact(v):
+    return Fraction(float(v))
+
+
+def pin_complex_error_bound(L):
+    """Each part lies within the rounding-error bound of the stated order
+    (two products and their difference or sum; for the update one more sum)
+    around the exact complex value alpha*a + beta*b, in rationals."""
+    rng = np.random.default_rng(34)
+    perm, size = (2, 0, 1), (3, 2, 4)
+    size_b = [size[p] for p in perm]
+    for dtype in (C32, C64):
+        real = REAL_OF[dtype]
+        u = Fraction(1, 2 ** (np.finfo(real).nmant + 1))
+        A = _rand(_elems(size), dtype, rng)
+        B0 = _rand(_elems(size_b), dtype, rng)
+        a_t = A.reshape(size, order="F").transpose(perm).flatten(order="F")
+        for alpha, beta in ((complex(0.75, -1.25), 0j), (complex(-0.3, 0.9), complex(1.1, 0.4)),
+                            (complex(0.0, 2.0), complex(-0.5, 0.0))):
+            got = B0.copy()
+            _run(L, perm, size, alpha, A, beta, got)
+            ar, ai = _exact(real.type(alpha.real)), _exact(real.type(alpha.imag))
+            br, bi = _exact(real.type(beta.real)), _exact(real.type(beta.imag))
+            upd = br != 0 or bi != 0
+            k = 3 if upd else 2
+            bound = k * u + 3 * u * u
+            for q in range(len(got)):
+                xr, xi = _exact(a_t[q].real), _exact(a_t[q].imag)
+                yr, yi = (_exact(B0[q].real), _exact(B0[q].imag)) if upd else (0, 0)
+                re = ar * xr - ai * xi + br * yr - bi * yi
+                im = ar * xi + ai * xr + br * yi + bi * yr
+                s_re = abs(ar * xr) + abs(ai * xi) + abs(br * yr) + abs(bi * yi)
+                s_im = abs(ar * xi) + abs(ai * xr) + abs(br * yi) + abs(bi * yr)
+                assert abs(_exact(got[q].real) - re) <= bound * s_re, (dtype, alpha, beta, q)
+                assert abs(_exact(got[q].imag) - im) <= bound * s_im, (dtype, alpha, beta, q)
+
+
+def pin_complex_beta_zero_does_not_read_b(L):
+    rng = np.random.default_rng(35)
+    for dtype in (C32, C64):
+        nan = np.array([complex(np.nan, np.nan)], dtype=dtype)[0]
+        A = _rand(60, dtype, rng)
+        B = np.full(60, nan, dtype=dtype)
+        _run(L, (2, 0, 1), (3, 4, 5), complex(0.5, -1.0), A, 0.0, B)
+        assert not np.isnan(B.view(REAL_OF[dtype])).any()
+        if dtype == C32:   # beta = 1e-300 i rounds to zero in single precision
+            B = np.full(60, nan, dtype=dtype)
+            _run(L, (2, 0, 1), (3, 4, 5), 1.0, A, 1e-300j, B)
+            assert not np.isnan(B.view(F32)).any()
 
 
 PINS = [pin_sec21_example, pin_index_encoding, pin_brute_force_vs_numpy, pin_textbook_2d,
         pin_round_trip, pin_composition, pin_update_vs_axpby, pin_identity_is_axpby,
         pin_beta_zero_does_not_read_b, pin_contraction_detector, pin_special_values,
-        pin_embedded_canaries, pin_validation]
+        pin_embedded_canaries, pin_validation, pin_complex_real_scalars_are_planewise,
+        pin_complex_times_i, pin_complex_vs_numpy, pin_complex_error_bound,
+        pin_complex_beta_zero_does_not_read_b]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -345,6 +499,18 @@ MUTANTS = {
     "alpha_dropped": [("B[off_b] = alpha * A[off_a];\n", "B[off_b] = A[off_a];\n")],
     "lda_reversed": [("int64_t o = outer_a ? outer_a[m] : size[m];",
                       "int64_t o = outer_a ? outer_a[n - 1 - m] : size[m];")],
+    "complex_cross_sign": [("pr = t1 - t2, pi = t3 + t4;", "pr = t1 + t2, pi = t3 + t4;")],
+    "complex_imag_sign": [("pr = t1 - t2, pi = t3 + t4;", "pr = t1 - t2, pi = t3 - t4;")],
+    "complex_parts_swapped": [("const float xr = A[2 * off_a], xi = A[2 * off_a + 1];",
+                               "const float xi = A[2 * off_a], xr = A[2 * off_a + 1];"),
+                              ("const double xr = A[2 * off_a], xi = A[2 * off_a + 1];",
+                               "const double xi = A[2 * off_a], xr = A[2 * off_a + 1];")],
+    "complex_beta_imag_dropped": [("qr = u1 - u2, qi = u3 + u4;", "qr = u1, qi = u3;")],
+    "complex_beta_real_only_test": [("if (br == 0.0f && bi == 0.0f) {", "if (br == 0.0f) {"),
+                                    ("if (br == 0.0 && bi == 0.0) {", "if (br == 0.0) {")],
+    "complex_unscaled_offsets": [("A[2 * off_a]", "A[off_a]"), ("A[2 * off_a + 1]", "A[off_a + 1]")],
+    "complex_alpha_imag_in_f32": [("const float alpha_fi = (float)alpha[1], beta_fi = (float)beta[1];",
+                                   "const float alpha_fi = 0.0f, beta_fi = (float)beta[1];")],
 }
 
 
@@ -388,7 +554,17 @@ def test_sampled_oracle_matches_full_oracle():
                                ((1, 0, 2, 3), (6, 5, 4, 3), (8, 5, 4, 3), (7, 9, 5, 3)),
                                ((0, 2, 1), (4, 3, 5), None, (6, 5, 3))]:
         size_b = [size[p] for p in perm]
-        for dtype, (alpha, beta) in itertools.product((F32, F64), ((1.3, 0.7), (1.0, 0.0))):
+        for dtype, (alpha, beta) in itertools.product((F32, F64, C32, C64),
+                                                      ((1.3, 0.7), (1.0, 0.0))):
+            A = _rand(_elems(oa or size), dtype, rng)
+            B0 = _rand(_elems(ob or size_b), dtype, rng)
+            full = B0.copy()
+            _run(oracle.lib(), perm, size, alpha, A, beta, full, oa, ob)
+            idx = rng.integers(0, _elems(size), size=50)
+            vals, off = oracle.sample(perm, size, alpha, A, beta, B0, idx, oa, ob)
+            assert _same_bits(vals, full[off])
+        for dtype, (alpha, beta) in itertools.product((C32, C64), ((0.3 - 1.2j, 0.7 + 0.25j),
+                                                                   (1j, 0.0))):
             A = _rand(_elems(oa or size), dtype, rng)
             B0 = _rand(_elems(ob or size_b), dtype, rng)
             full = B0.copy()
