@@ -24,16 +24,27 @@
  *    and strideB[k] = prod_{j<k} outer_b[j].  NULL means the tensor is stored
  *    contiguously (outer = size).  outer < size is TTX_EINVAL.  Elements of
  *    the outer tensor of B outside the sub-tensor are never touched.
- *  - dtype selects FP32 or FP64 for both A and B (Sec. 2.1, Table 1 "s", "d").
- *  - alpha and beta are rounded once to the element type (round to nearest).
- *    When the rounded beta is zero (+0 or -0) B is written without being
+ *  - dtype selects the element type of both A and B among the four of the
+ *    paper's type list (Sec. 2.1, Table 1 "s", "d"; Sec. 3 "c", "z"): FP32,
+ *    FP64, and single and double complex stored as interleaved (re, im)
+ *    pairs (8 and 16 bytes).
+ *  - alpha and beta are rounded once to the element type (round to nearest;
+ *    for complex types each part to the real part type).  When the rounded
+ *    beta is zero (+0 or -0; complex: both parts) B is written without being
  *    read (Sec. 1: with beta = 0 the output is overwritten), so NaN or Inf
  *    in B do not propagate.  Otherwise each element is computed as
  *    fl(fl(alpha*a) + fl(beta*b)): two rounded products and a rounded sum,
- *    never a fused multiply-add.
- *  - A and B (device pointers) must be aligned to the element size and the
- *    byte ranges they address must not overlap (the operation is
- *    out-of-place, Sec. 1): overlap is TTX_EOVERLAP.
+ *    never a fused multiply-add.  A complex product s*x is formed as
+ *    re = fl(fl(s.re*x.re) - fl(s.im*x.im)), im = fl(fl(s.re*x.im) +
+ *    fl(s.im*x.re)), every product and sum rounded on its own, and the
+ *    update adds the two products part by part.  The entry points that
+ *    take double alpha, beta pass complex scalars with zero imaginary parts
+ *    (the arithmetic above still applies); the *_c entry points take
+ *    complex scalars as two doubles (re, im).
+ *  - A and B (device pointers) must be aligned to the element size (8 bytes
+ *    for single complex, 16 for double complex) and the byte ranges they
+ *    address must not overlap (the operation is out-of-place, Sec. 1):
+ *    overlap is TTX_EOVERLAP.
  *  - 1 <= n <= TTX_MAX_DIMS.  Index arithmetic is 64-bit.
  *
  * Ownership: the caller owns A and B; the per-call and plan paths never
@@ -56,7 +67,7 @@ extern "C" {
 
 #define TTX_MAX_DIMS 16
 
-typedef enum ttx_dtype { TTX_F32 = 0, TTX_F64 = 1 } ttx_dtype;
+typedef enum ttx_dtype { TTX_F32 = 0, TTX_F64 = 1, TTX_C32 = 2, TTX_C64 = 3 } ttx_dtype;
 
 typedef enum ttx_status {
     TTX_OK = 0,
@@ -151,6 +162,14 @@ ttx_status ttx_transpose(ttx_dtype dtype, int n, const int *perm, const int64_t 
                          const int64_t *outer_a, const int64_t *outer_b,
                          double alpha, const void *A, double beta, void *B,
                          hipStream_t stream);
+/* The same with complex alpha and beta (Eqn. 1 over the c and z types of
+ * Sec. 3): alpha[0..1] and beta[0..1] are (re, im), host pointers read
+ * before the call returns.  For TTX_F32 and TTX_F64 the imaginary parts
+ * must be zero (else TTX_EINVAL). */
+ttx_status ttx_transpose_c(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
+                           const int64_t *outer_a, const int64_t *outer_b,
+                           const double *alpha, const void *A, const double *beta, void *B,
+                           hipStream_t stream);
 
 /* -- plans ------------------------------------------------------------------
  * A plan fixes dtype, perm, size and outer sizes (host work only: no HIP
@@ -167,6 +186,11 @@ ttx_status ttx_plan_execute(const ttx_plan *plan, double alpha, const void *A, d
  * equal B_out).  The arithmetic is identical to ttx_plan_execute. */
 ttx_status ttx_plan_execute_split(const ttx_plan *plan, double alpha, const void *A, double beta,
                                   const void *B_in, void *B_out, hipStream_t stream);
+/* ttx_plan_execute_split with complex alpha and beta, (re, im) pairs as in
+ * ttx_transpose_c. */
+ttx_status ttx_plan_execute_c(const ttx_plan *plan, const double *alpha, const void *A,
+                              const double *beta, const void *B_in, void *B_out,
+                              hipStream_t stream);
 ttx_status ttx_plan_describe(const ttx_plan *plan, ttx_plan_info *info);
 /* Overrides the config used for beta == 0 (beta_is_zero = 1) or beta != 0.
  * The config must be one the planner accepts for this problem (its family,

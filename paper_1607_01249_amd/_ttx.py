@@ -18,12 +18,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttx.so")
 MAX_DIMS = 16
 
-F32, F64 = 0, 1
+F32, F64, C32, C64 = 0, 1, 2, 3
+ELEM_BYTES = {F32: 4, F64: 8, C32: 8, C64: 16}
 OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = range(9)
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
 CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE = 1, 2, 4
-DENSE_CAP = {F32: 1024, F64: 1024}
+DENSE_CAP = {F32: 1024, F64: 1024, C32: 1024, C64: 512}
 
 i64 = ctypes.c_int64
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -155,14 +156,17 @@ def lib():
 
 def _declare(L):
     S = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "ttx_status_string": ([S], ctypes.c_char_p),
         "ttx_last_error": ([], ctypes.c_char_p),
         "ttx_version": ([], ctypes.c_char_p),
         "ttx_transpose": ([S, S, ip, i64p, i64p, i64p, ctypes.c_double, vp, ctypes.c_double, vp, vp], S),
+        "ttx_transpose_c": ([S, S, ip, i64p, i64p, i64p, dp, vp, dp, vp, vp], S),
         "ttx_plan_create": ([ctypes.POINTER(vp), S, S, ip, i64p, i64p, i64p], S),
         "ttx_plan_execute": ([vp, ctypes.c_double, vp, ctypes.c_double, vp, vp], S),
         "ttx_plan_execute_split": ([vp, ctypes.c_double, vp, ctypes.c_double, vp, vp, vp], S),
+        "ttx_plan_execute_c": ([vp, dp, vp, dp, vp, vp, vp], S),
         "ttx_plan_describe": ([vp, ctypes.POINTER(PlanInfo)], S),
         "ttx_plan_set_config": ([vp, S, ctypes.POINTER(Config)], S),
         "ttx_plan_destroy": ([vp], S),
@@ -228,6 +232,17 @@ def ttx_transpose(dtype, n, perm, size, outer_a, outer_b, alpha, A, beta, B, str
                                       _i64s(outer_b), float(alpha), A, float(beta), B, stream))
 
 
+def _complex2(v):
+    v = complex(v)
+    return (ctypes.c_double * 2)(v.real, v.imag)
+
+
+def ttx_transpose_c(dtype, n, perm, size, outer_a, outer_b, alpha, A, beta, B, stream=0):
+    return _check(lib().ttx_transpose_c(dtype, n, _ints(perm), _i64s(size), _i64s(outer_a),
+                                        _i64s(outer_b), _complex2(alpha), A, _complex2(beta), B,
+                                        stream))
+
+
 def ttx_plan_create(dtype, perm, size, outer_a=None, outer_b=None):
     h = vp()
     _check(lib().ttx_plan_create(ctypes.byref(h), dtype, len(perm), _ints(perm), _i64s(size),
@@ -241,6 +256,11 @@ def ttx_plan_execute(plan, alpha, A, beta, B, stream=0):
 
 def ttx_plan_execute_split(plan, alpha, A, beta, B_in, B_out, stream=0):
     return _check(lib().ttx_plan_execute_split(plan, float(alpha), A, float(beta), B_in, B_out, stream))
+
+
+def ttx_plan_execute_c(plan, alpha, A, beta, B_in, B_out, stream=0):
+    return _check(lib().ttx_plan_execute_c(plan, _complex2(alpha), A, _complex2(beta), B_in, B_out,
+                                           stream))
 
 
 def ttx_plan_describe(plan):
@@ -463,7 +483,12 @@ def dtype_code(t):
         return F32
     if t.dtype == torch.float64:
         return F64
-    raise TypeError("ttx supports float32 and float64 tensors, got %s" % t.dtype)
+    if t.dtype == torch.complex64:
+        return C32
+    if t.dtype == torch.complex128:
+        return C64
+    raise TypeError("ttx supports float32, float64, complex64 and complex128 tensors, got %s"
+                    % t.dtype)
 
 
 def current_stream():
@@ -482,5 +507,8 @@ def transpose(A, B, perm, size, alpha=1.0, beta=0.0, outer_a=None, outer_b=None,
         raise ValueError("A and B must be device tensors")
     if stream is None:
         stream = current_stream()
+    if isinstance(alpha, complex) or isinstance(beta, complex):
+        return ttx_transpose_c(code, len(perm), perm, size, outer_a, outer_b, alpha, A.data_ptr(),
+                               beta, B.data_ptr(), stream)
     return ttx_transpose(code, len(perm), perm, size, outer_a, outer_b, alpha, A.data_ptr(), beta,
                          B.data_ptr(), stream)

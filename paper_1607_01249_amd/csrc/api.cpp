@@ -60,15 +60,16 @@ static bool ranges_overlap(const void* x, int64_t xlen, const void* y, int64_t y
     return a < b + uint64_t(ylen) && b < a + uint64_t(xlen);
 }
 
-bool beta_is_zero(int dtype, double beta) {
-    return dtype == TTX_F32 ? float(beta) == 0.0f : beta == 0.0;
+bool beta_is_zero(int dtype, const Scalar& beta) {
+    if (dtype == TTX_F32 || dtype == TTX_C32) return float(beta.re) == 0.0f && float(beta.im) == 0.0f;
+    return beta.re == 0.0 && beta.im == 0.0;
 }
 
 ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, const void* Bout,
                           bool beta0) {
     if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
     if (!A || !Bout || (!beta0 && !Bin)) return fail(TTX_EINVAL, "NULL tensor pointer");
-    const uintptr_t esz = p.dtype == TTX_F32 ? 4 : 8;
+    const uintptr_t esz = uintptr_t(elem_bytes(p.dtype));
     if (reinterpret_cast<uintptr_t>(A) % esz || reinterpret_cast<uintptr_t>(Bout) % esz ||
         (!beta0 && reinterpret_cast<uintptr_t>(Bin) % esz))
         return fail(TTX_EINVAL, "tensor pointer not aligned to the element size");
@@ -79,9 +80,11 @@ ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, cons
     return TTX_OK;
 }
 
-static ttx_status execute(const ttx_plan* plan, double alpha, const void* A, double beta,
+static ttx_status execute(const ttx_plan* plan, const Scalar& alpha, const void* A, const Scalar& beta,
                           const void* Bin, void* Bout, hipStream_t stream) {
     const Problem& p = plan->prob;
+    if (!dtype_complex(p.dtype) && (alpha.im != 0.0 || beta.im != 0.0))
+        return fail(TTX_EINVAL, "complex alpha or beta for a real element type");
     if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
     const bool beta0 = beta_is_zero(p.dtype, beta);
     ttx_status st = check_pointers(p, A, Bin, Bout, beta0);
@@ -115,8 +118,8 @@ static std::string cache_key(int dtype, int n, const int* perm, const int64_t* s
 }
 
 ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
-                            const int64_t* outer_a, const int64_t* outer_b, double alpha,
-                            const void* A, double beta, const void* Bin, void* Bout,
+                            const int64_t* outer_a, const int64_t* outer_b, const Scalar& alpha,
+                            const void* A, const Scalar& beta, const void* Bin, void* Bout,
                             hipStream_t stream) {
     if (n < 1 || n > kMaxDims || !perm || !size) {
         Problem p;
@@ -184,6 +187,12 @@ ttx_status ttx_plan_execute_split(const ttx_plan* plan, double alpha, const void
     return execute(plan, alpha, A, beta, B_in, B_out, stream);
 }
 
+ttx_status ttx_plan_execute_c(const ttx_plan* plan, const double* alpha, const void* A,
+                              const double* beta, const void* B_in, void* B_out, hipStream_t stream) {
+    if (!plan || !alpha || !beta) return fail(TTX_EINVAL, "NULL argument");
+    return execute(plan, Scalar(alpha[0], alpha[1]), A, Scalar(beta[0], beta[1]), B_in, B_out, stream);
+}
+
 ttx_status ttx_plan_describe(const ttx_plan* plan, ttx_plan_info* info) {
     if (!plan || !info) return fail(TTX_EINVAL, "NULL argument");
     std::memset(info, 0, sizeof(*info));
@@ -238,6 +247,14 @@ ttx_status ttx_transpose(ttx_dtype dtype, int n, const int* perm, const int64_t*
                          const int64_t* outer_a, const int64_t* outer_b, double alpha,
                          const void* A, double beta, void* B, hipStream_t stream) {
     return transpose_cached(dtype, n, perm, size, outer_a, outer_b, alpha, A, beta, B, B, stream);
+}
+
+ttx_status ttx_transpose_c(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                           const int64_t* outer_a, const int64_t* outer_b, const double* alpha,
+                           const void* A, const double* beta, void* B, hipStream_t stream) {
+    if (!alpha || !beta) return fail(TTX_EINVAL, "alpha and beta must not be NULL");
+    return transpose_cached(dtype, n, perm, size, outer_a, outer_b, Scalar(alpha[0], alpha[1]), A,
+                            Scalar(beta[0], beta[1]), B, B, stream);
 }
 
 ttx_status ttx_copy_kernel(const void* src, void* dst, int64_t bytes, hipStream_t stream) {

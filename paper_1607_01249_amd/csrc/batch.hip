@@ -268,7 +268,7 @@ hipError_t launch_batch(const BatchDesc* d_desc, const uint32_t* d_chunk_prefix,
 }
 
 // -- host side --------------------------------------------------------------------------
-static int elem_size(int dtype) { return dtype == TTX_F32 ? 4 : 8; }
+static int elem_size(int dtype) { return elem_bytes(dtype); }
 
 // Whether 16-byte accesses are possible on both sides for this problem and
 // these pointers (the batched tile shapes are all multiples of the vector
@@ -315,6 +315,8 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     std::memset(d, 0, sizeof(*d));
     d->dtype = p.dtype;
     d->variant = -1;
+    if (dtype_complex(p.dtype))
+        return fail(TTX_EUNSUPPORTED, "batched execution takes FP32 and FP64 problems only");
     if (p.family == TTX_FAMILY_EMPTY) {
         if (used) *used = default_config(p);
         return TTX_OK;
@@ -490,14 +492,14 @@ static ttx_status describe_all(ttx_batch* b) {
         b->cfg[i] = used;
         total += desc[i].tiles;
         if (total >= (uint64_t(1) << 32)) return fail(TTX_EUNSUPPORTED, "batch has too many tiles");
-        b->bytes += p.elements * (p.dtype == TTX_F32 ? 4 : 8) * (beta0 ? 2 : 3);
+        b->bytes += p.elements * elem_bytes(p.dtype) * (beta0 ? 2 : 3);
     }
     // largest problems first, so that the chunks claimed last are short ones
     b->order.resize(count);
     for (int i = 0; i < count; ++i) b->order[i] = i;
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
-        return b->prob[x].elements * (b->prob[x].dtype == TTX_F32 ? 4 : 8) >
-               b->prob[y].elements * (b->prob[y].dtype == TTX_F32 ? 4 : 8);
+        return b->prob[x].elements * elem_bytes(b->prob[x].dtype) >
+               b->prob[y].elements * elem_bytes(b->prob[y].dtype);
     });
     b->desc.resize(count);
     for (int i = 0; i < count; ++i) b->desc[i] = desc[b->order[i]];

@@ -25,16 +25,27 @@ static int device_cus() {
     return cached[dev];
 }
 
+// Calls f with a value of the element type of dtype.
+template <typename F>
+static hipError_t with_type(int dtype, F&& f) {
+    switch (dtype) {
+        case TTX_F32: return f(float{});
+        case TTX_F64: return f(double{});
+        case TTX_C32: return f(cf32{});
+        default: return f(cf64{});
+    }
+}
+
 template <typename T>
 static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0, const void* A,
-                              const void* Bsrc, void* Bdst, double alpha, double beta,
+                              const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                               hipStream_t stream) {
     FlatArgs<T> a;
     a.A = static_cast<const T*>(A);
     a.Bsrc = static_cast<const T*>(Bsrc);
     a.Bdst = static_cast<T*>(Bdst);
-    a.alpha = T(alpha);
-    a.beta = T(beta);
+    a.alpha = scalar_as<T>(alpha);
+    a.beta = scalar_as<T>(beta);
     a.n = p.dim[0].size;
     a.sa = p.dim[0].sa;
     a.sb = p.dim[0].sb;
@@ -53,15 +64,15 @@ static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0,
 
 template <typename T>
 static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A,
-                               const void* Bsrc, void* Bdst, double alpha, double beta,
+                               const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                                hipStream_t stream) {
     TileArgs<T> a;
     build_grid(p, c, &a);
     a.A = static_cast<const T*>(A);
     a.Bsrc = static_cast<const T*>(Bsrc);
     a.Bdst = static_cast<T*>(Bdst);
-    a.alpha = T(alpha);
-    a.beta = T(beta);
+    a.alpha = scalar_as<T>(alpha);
+    a.beta = scalar_as<T>(beta);
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
     if (config_is_dense(c)) {
         const uint32_t full = dense_grid(p.dtype, beta0);
@@ -83,10 +94,7 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
     const LauncherRow* table;
     int n;
     if (p.family == TTX_FAMILY_MOVED) {
-        if (p.dtype == TTX_F32)
-            n = beta0 ? moved_rows_f32_beta0(&table) : moved_rows_f32_beta(&table);
-        else
-            n = beta0 ? moved_rows_f64_beta0(&table) : moved_rows_f64_beta(&table);
+        n = moved_rows(p.dtype, beta0, &table);
     } else {
         n = preserved_rows(p.dtype, beta0, &table);
     }
@@ -101,23 +109,23 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
 }
 
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
-                        const void* Bsrc, void* Bdst, double alpha, double beta,
+                        const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream) {
     if (p.family == TTX_FAMILY_EMPTY) return hipSuccess;
-    if (p.family == TTX_FAMILY_FLAT) {
-        return p.dtype == TTX_F32 ? launch_flat<float>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream)
-                                  : launch_flat<double>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-    }
-    return p.dtype == TTX_F32 ? launch_tiled<float>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream)
-                              : launch_tiled<double>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+    return with_type(p.dtype, [&](auto tag) {
+        using T = decltype(tag);
+        if (p.family == TTX_FAMILY_FLAT) return launch_flat<T>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+        return launch_tiled<T>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+    });
 }
 
 std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, const void* Bdst) {
     if (p.family == TTX_FAMILY_EMPTY) return "";
-    const char* t = p.dtype == TTX_F32 ? "float" : "double";
+    static const char* const kTypeName[] = {"float", "double", "ttx::cf32", "ttx::cf64"};
+    const char* t = kTypeName[p.dtype];
     const char* z = beta0 ? "true" : "false";
-    const int V = p.dtype == TTX_F32 ? 4 : 2;
+    const int V = 16 / elem_bytes(p.dtype);
     const int f = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
     char buf[128];
     if (p.family == TTX_FAMILY_FLAT) {
@@ -125,14 +133,14 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
     } else if (config_is_dense(c)) {
         std::snprintf(buf, sizeof(buf), "k_dense<%s, %s, %d>", t, z, dense_cap(p.dtype));
     } else if (p.family == TTX_FAMILY_MOVED) {
-        const int va = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
-        const int vb = (f & KF_VEC_B) && c.tile_b % V == 0 ? V : 1;
+        const int va = (f & KF_VEC_A) && V > 1 && c.tile_a % V == 0 ? V : 1;
+        const int vb = (f & KF_VEC_B) && V > 1 && c.tile_b % V == 0 ? V : 1;
         std::snprintf(buf, sizeof(buf), "k_moved<%s, %s, %d, %d, %d, %d>", t, z, c.tile_a, c.tile_b, va, vb);
     } else if (config_is_staged(c)) {
         std::snprintf(buf, sizeof(buf), "k_staged<%s, %s, %d, %d, %d>", t, z, staged_lanes(p.dim[0].size),
                       c.tile_a, c.tile_b);
     } else {
-        const int v = (f & KF_VEC_A) && c.tile_a % V == 0 ? V : 1;
+        const int v = (f & KF_VEC_A) && V > 1 && c.tile_a % V == 0 ? V : 1;
         std::snprintf(buf, sizeof(buf), "k_preserved<%s, %s, %d, %d, %d>", t, z, c.tile_a, c.tile_b, v);
     }
     return buf;

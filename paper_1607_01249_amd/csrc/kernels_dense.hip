@@ -1,4 +1,4 @@
-// Dense-tile kernel instantiations (one capacity per dtype).
+// Dense-tile kernel instantiations (one capacity per element type).
 #include <mutex>
 
 #include "menu.h"
@@ -38,15 +38,29 @@ static uint32_t resident(int dev) {
 uint32_t dense_grid(int dtype, bool beta0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    if (dtype == TTX_F32)
-        return beta0 ? resident<float, true, TTX_DENSE_CAP_F32>(dev) : resident<float, false, TTX_DENSE_CAP_F32>(dev);
-    return beta0 ? resident<double, true, TTX_DENSE_CAP_F64>(dev) : resident<double, false, TTX_DENSE_CAP_F64>(dev);
+    switch (dtype) {
+        case TTX_F32:
+            return beta0 ? resident<float, true, TTX_DENSE_CAP_F32>(dev) : resident<float, false, TTX_DENSE_CAP_F32>(dev);
+        case TTX_F64:
+            return beta0 ? resident<double, true, TTX_DENSE_CAP_F64>(dev) : resident<double, false, TTX_DENSE_CAP_F64>(dev);
+        case TTX_C32:
+            return beta0 ? resident<cf32, true, TTX_DENSE_CAP_C32>(dev) : resident<cf32, false, TTX_DENSE_CAP_C32>(dev);
+        default:
+            return beta0 ? resident<cf64, true, TTX_DENSE_CAP_C64>(dev) : resident<cf64, false, TTX_DENSE_CAP_C64>(dev);
+    }
 }
 
 TileLaunchFn dense_launcher(int dtype, bool beta0) {
-    if (dtype == TTX_F32)
-        return beta0 ? launch_dense<float, true, TTX_DENSE_CAP_F32> : launch_dense<float, false, TTX_DENSE_CAP_F32>;
-    return beta0 ? launch_dense<double, true, TTX_DENSE_CAP_F64> : launch_dense<double, false, TTX_DENSE_CAP_F64>;
+    switch (dtype) {
+        case TTX_F32:
+            return beta0 ? launch_dense<float, true, TTX_DENSE_CAP_F32> : launch_dense<float, false, TTX_DENSE_CAP_F32>;
+        case TTX_F64:
+            return beta0 ? launch_dense<double, true, TTX_DENSE_CAP_F64> : launch_dense<double, false, TTX_DENSE_CAP_F64>;
+        case TTX_C32:
+            return beta0 ? launch_dense<cf32, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, false, TTX_DENSE_CAP_C32>;
+        default:
+            return beta0 ? launch_dense<cf64, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, false, TTX_DENSE_CAP_C64>;
+    }
 }
 
 }  // namespace ttx

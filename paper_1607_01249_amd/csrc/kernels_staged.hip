@@ -16,18 +16,27 @@ static hipError_t launch(const void* args, uint32_t grid, hipStream_t stream) {
 #define TTX_F32_Z(n0, tx, ty) {n0, tx, ty, launch<float, true, n0, tx, ty>},
 #define TTX_F64_B(n0, tx, ty) {n0, tx, ty, launch<double, false, n0, tx, ty>},
 #define TTX_F64_Z(n0, tx, ty) {n0, tx, ty, launch<double, true, n0, tx, ty>},
+#define TTX_C32_B(n0, tx, ty) {n0, tx, ty, launch<cf32, false, n0, tx, ty>},
+#define TTX_C32_Z(n0, tx, ty) {n0, tx, ty, launch<cf32, true, n0, tx, ty>},
+#define TTX_C64_B(n0, tx, ty) {n0, tx, ty, launch<cf64, false, n0, tx, ty>},
+#define TTX_C64_Z(n0, tx, ty) {n0, tx, ty, launch<cf64, true, n0, tx, ty>},
 static const StagedRow kF32B[] = {TTX_STAGED_MENU_F32(TTX_F32_B)};
 static const StagedRow kF32Z[] = {TTX_STAGED_MENU_F32(TTX_F32_Z)};
 static const StagedRow kF64B[] = {TTX_STAGED_MENU_F64(TTX_F64_B)};
 static const StagedRow kF64Z[] = {TTX_STAGED_MENU_F64(TTX_F64_Z)};
+static const StagedRow kC32B[] = {TTX_STAGED_MENU_F64(TTX_C32_B)};
+static const StagedRow kC32Z[] = {TTX_STAGED_MENU_F64(TTX_C32_Z)};
+static const StagedRow kC64B[] = {TTX_STAGED_MENU_C64(TTX_C64_B)};
+static const StagedRow kC64Z[] = {TTX_STAGED_MENU_C64(TTX_C64_Z)};
 
+#define TTX_PICK(B, Z) return *out = beta0 ? Z : B, int(sizeof(B) / sizeof(B[0]))
 int staged_rows(int dtype, bool beta0, const StagedRow** out) {
-    if (dtype == TTX_F32) {
-        *out = beta0 ? kF32Z : kF32B;
-        return int(sizeof(kF32B) / sizeof(kF32B[0]));
+    switch (dtype) {
+        case TTX_F32: TTX_PICK(kF32B, kF32Z);
+        case TTX_F64: TTX_PICK(kF64B, kF64Z);
+        case TTX_C32: TTX_PICK(kC32B, kC32Z);
+        default: TTX_PICK(kC64B, kC64Z);
     }
-    *out = beta0 ? kF64Z : kF64B;
-    return int(sizeof(kF64B) / sizeof(kF64B[0]));
 }
 
 }  // namespace ttx

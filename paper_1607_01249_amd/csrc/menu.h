@@ -11,6 +11,11 @@
 // the number of elements a workgroup moves (1K to 4K).
 #pragma once
 
+// Single complex elements (8 bytes) use the FP64 menus.  Double complex
+// elements are 16 bytes, one vector each: w = 8 elements (one 128-B line),
+// regular tiles {8,16,24,32} x {8,16,24,32}, skinny shapes for 2- and
+// 4-element edges and 1-KiB long-run shapes.
+//
 // X(tile_a, tile_b)
 #define TTX_MOVED_MENU_F32(X)                                                             \
     X(16, 16) X(16, 32) X(16, 48) X(16, 64) X(32, 16) X(32, 32) X(32, 48) X(32, 64)       \
@@ -22,6 +27,11 @@
     X(48, 16) X(48, 32) X(48, 48) X(48, 64) X(64, 16) X(64, 32) X(64, 48) X(64, 64)       \
     X(2, 256) X(4, 128) X(256, 2) X(128, 4) X(128, 16) X(16, 128)
 
+#define TTX_MOVED_MENU_C64(X)                                                             \
+    X(8, 8) X(8, 16) X(8, 24) X(8, 32) X(16, 8) X(16, 16) X(16, 24) X(16, 32)              \
+    X(24, 8) X(24, 16) X(24, 24) X(24, 32) X(32, 8) X(32, 16) X(32, 24) X(32, 32)          \
+    X(2, 128) X(4, 64) X(128, 2) X(64, 4) X(64, 16) X(16, 64)
+
 // X(tile_a, rows)
 #define TTX_PRESERVED_MENU_F32(X)                                                         \
     X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
@@ -30,6 +40,10 @@
 #define TTX_PRESERVED_MENU_F64(X)                                                         \
     X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \
     X(256, 4) X(256, 16) X(2, 512) X(4, 256)
+
+#define TTX_PRESERVED_MENU_C64(X)                                                         \
+    X(8, 64) X(8, 256) X(16, 32) X(16, 128) X(32, 16) X(32, 64) X(64, 8) X(64, 32)        \
+    X(128, 4) X(128, 16) X(2, 256) X(4, 128)
 
 // Staged preserved-family tiles, for short stride-1 rows: X(n0_max, tile_x,
 // tile_y) with n0_max lanes per row (rows of n0 <= n0_max elements), tile_x
@@ -42,9 +56,17 @@
     X(16, 16, 8) X(16, 8, 16) X(16, 4, 32) X(16, 32, 4) X(32, 8, 8) X(32, 4, 16)          \
     X(32, 16, 4) X(32, 2, 32) X(32, 32, 2) X(64, 4, 8) X(64, 8, 4) X(64, 4, 4)
 
-// Dense tiles: elements per tile, 4 per thread (4 KiB FP32, 8 KiB FP64).
+// Double complex rows are staged only when shorter than 16 elements (256 B).
+#define TTX_STAGED_MENU_C64(X)                                                            \
+    X(16, 8, 8) X(16, 4, 16) X(16, 16, 4) X(16, 2, 32) X(16, 32, 2) X(16, 4, 8)           \
+    X(16, 8, 4) X(16, 4, 4) X(16, 2, 16) X(16, 16, 2)
+
+// Dense tiles: elements per tile (4 KiB FP32, 8 KiB FP64 and single complex,
+// 8 KiB double complex).
 #define TTX_DENSE_CAP_F32 1024
 #define TTX_DENSE_CAP_F64 1024
+#define TTX_DENSE_CAP_C32 1024
+#define TTX_DENSE_CAP_C64 512
 
 // Tile variants compiled into the persistent batched kernel, per dtype:
 // X(index, kind, p1, p2, p3).  For the moved, preserved and flat kinds

@@ -14,27 +14,30 @@
 
 namespace ttx {
 
-static int elem_bytes(int dtype) { return dtype == TTX_F32 ? 4 : 8; }
-
 // ---------------------------------------------------------------------------------------
 // Menus
 #define TTX_SHAPE(a, b) {a, b},
 static const TileShape kMovedF32[] = {TTX_MOVED_MENU_F32(TTX_SHAPE)};
 static const TileShape kMovedF64[] = {TTX_MOVED_MENU_F64(TTX_SHAPE)};
+static const TileShape kMovedC64[] = {TTX_MOVED_MENU_C64(TTX_SHAPE)};
 static const TileShape kPresF32[] = {TTX_PRESERVED_MENU_F32(TTX_SHAPE)};
 static const TileShape kPresF64[] = {TTX_PRESERVED_MENU_F64(TTX_SHAPE)};
+static const TileShape kPresC64[] = {TTX_PRESERVED_MENU_C64(TTX_SHAPE)};
 #undef TTX_SHAPE
 
+#define TTX_COUNT(arr) int(sizeof(arr) / sizeof(arr[0]))
+
+// Single complex elements have the byte size of FP64 ones and use the FP64 menus.
 int tile_menu(int dtype, int family, const TileShape** shapes) {
     if (family == TTX_FAMILY_MOVED) {
-        *shapes = dtype == TTX_F32 ? kMovedF32 : kMovedF64;
-        return dtype == TTX_F32 ? int(sizeof(kMovedF32) / sizeof(TileShape))
-                                : int(sizeof(kMovedF64) / sizeof(TileShape));
+        if (dtype == TTX_F32) return *shapes = kMovedF32, TTX_COUNT(kMovedF32);
+        if (dtype == TTX_C64) return *shapes = kMovedC64, TTX_COUNT(kMovedC64);
+        return *shapes = kMovedF64, TTX_COUNT(kMovedF64);
     }
     if (family == TTX_FAMILY_PRESERVED) {
-        *shapes = dtype == TTX_F32 ? kPresF32 : kPresF64;
-        return dtype == TTX_F32 ? int(sizeof(kPresF32) / sizeof(TileShape))
-                                : int(sizeof(kPresF64) / sizeof(TileShape));
+        if (dtype == TTX_F32) return *shapes = kPresF32, TTX_COUNT(kPresF32);
+        if (dtype == TTX_C64) return *shapes = kPresC64, TTX_COUNT(kPresC64);
+        return *shapes = kPresF64, TTX_COUNT(kPresF64);
     }
     *shapes = nullptr;
     return 0;
@@ -44,6 +47,7 @@ int tile_menu(int dtype, int family, const TileShape** shapes) {
 struct StagedShape { int n0, tx, ty; };
 static const StagedShape kStagedF32[] = {TTX_STAGED_MENU_F32(TTX_STAGED)};
 static const StagedShape kStagedF64[] = {TTX_STAGED_MENU_F64(TTX_STAGED)};
+static const StagedShape kStagedC64[] = {TTX_STAGED_MENU_C64(TTX_STAGED)};
 #undef TTX_STAGED
 
 int staged_lanes(int64_t n0) {
@@ -54,9 +58,9 @@ int staged_lanes(int64_t n0) {
 }
 
 static int staged_menu(int dtype, const StagedShape** out) {
-    *out = dtype == TTX_F32 ? kStagedF32 : kStagedF64;
-    return dtype == TTX_F32 ? int(sizeof(kStagedF32) / sizeof(StagedShape))
-                            : int(sizeof(kStagedF64) / sizeof(StagedShape));
+    if (dtype == TTX_F32) return *out = kStagedF32, TTX_COUNT(kStagedF32);
+    if (dtype == TTX_C64) return *out = kStagedC64, TTX_COUNT(kStagedC64);
+    return *out = kStagedF64, TTX_COUNT(kStagedF64);
 }
 
 bool staged_in_menu(int dtype, int n0_max, int tx, int ty) {
@@ -79,7 +83,7 @@ bool tile_in_menu(int dtype, int family, int ta, int tb) {
 // Problem construction
 ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
                         const int64_t* outer_a, const int64_t* outer_b, Problem* out) {
-    if (dtype != TTX_F32 && dtype != TTX_F64) return fail(TTX_EINVAL, "unknown dtype");
+    if (!dtype_valid(dtype)) return fail(TTX_EINVAL, "unknown dtype");
     if (n < 1 || n > kMaxDims) return fail(TTX_EINVAL, "n must be in 1..16");
     if (!perm || !size) return fail(TTX_EINVAL, "perm and size must not be NULL");
     bool seen[kMaxDims] = {};
@@ -543,8 +547,10 @@ static constexpr double kTileOverhead = 1536.0;  // bytes-equivalent per tile
 static constexpr double kResident = 2048.0;
 
 // Element-wise accesses (dense and staged tiles, and menu tiles whose runs
-// cannot take 16-byte vectors) are charged a fixed 15% over vector tiles.
+// cannot take 16-byte vectors) are charged a fixed 15% over vector tiles,
+// except for 16-byte elements (double complex), which are whole vectors.
 static constexpr double kScalarPenalty = 1.15;
+static double scalar_penalty(const Problem& p) { return elem_bytes(p.dtype) >= 16 ? 1.0 : kScalarPenalty; }
 // Dense tiles also decode every element's coordinates at run time.
 static constexpr double kDensePenalty = 1.3;
 
@@ -568,7 +574,7 @@ static double staged_cost(const Problem& p, const Layout& L, int tx, int ty) {
             work += cnt * n0 * ex * ey;
         }
     if (useful == 0) return 1e30;
-    return kScalarPenalty * traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
+    return scalar_penalty(p) * traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
 }
 
 // Whether a menu tile of this layout can use 16-byte accesses on both sides,
@@ -726,7 +732,7 @@ static double blocking_cost(const Problem& p, const Layout& L, int ta, int tb) {
             work += cnt * ax * by;
         }
     if (useful == 0) return 1e30;
-    const double scalar = vector_shape(p, L, ta, tb) ? 1.0 : kScalarPenalty;
+    const double scalar = vector_shape(p, L, ta, tb) ? 1.0 : scalar_penalty(p);
     return scalar * traffic / useful * (1.0 + 0.25 * (lanes / work - 1.0));
 }
 

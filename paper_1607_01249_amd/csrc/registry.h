@@ -20,6 +20,18 @@ int moved_rows_f32_beta(const LauncherRow** out);
 int moved_rows_f32_beta0(const LauncherRow** out);
 int moved_rows_f64_beta(const LauncherRow** out);
 int moved_rows_f64_beta0(const LauncherRow** out);
+int moved_rows_c32_beta(const LauncherRow** out);
+int moved_rows_c32_beta0(const LauncherRow** out);
+int moved_rows_c64_beta(const LauncherRow** out);
+int moved_rows_c64_beta0(const LauncherRow** out);
+inline int moved_rows(int dtype, bool beta0, const LauncherRow** out) {
+    switch (dtype) {
+        case TTX_F32: return beta0 ? moved_rows_f32_beta0(out) : moved_rows_f32_beta(out);
+        case TTX_F64: return beta0 ? moved_rows_f64_beta0(out) : moved_rows_f64_beta(out);
+        case TTX_C32: return beta0 ? moved_rows_c32_beta0(out) : moved_rows_c32_beta(out);
+        default: return beta0 ? moved_rows_c64_beta0(out) : moved_rows_c64_beta(out);
+    }
+}
 int preserved_rows(int dtype, bool beta0, const LauncherRow** out);
 
 struct StagedRow {

@@ -24,11 +24,27 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ttx_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace ttx {
+
+template <typename T>
+struct IsComplex : std::false_type {};
+template <>
+struct IsComplex<cf32> : std::true_type {};
+template <>
+struct IsComplex<cf64> : std::true_type {};
+
+// Two single complex elements: one 16-byte vector.
+struct alignas(16) cf32x2 {
+    cf32 e[2];
+    __device__ __forceinline__ cf32& operator[](int j) { return e[j]; }
+    __device__ __forceinline__ const cf32& operator[](int j) const { return e[j]; }
+};
 
 template <typename T, int N>
 struct VecOf {
@@ -38,8 +54,30 @@ template <typename T>
 struct VecOf<T, 1> {
     using type = T;
 };
+template <>
+struct VecOf<cf32, 2> {
+    using type = cf32x2;
+};
 template <typename T, int N>
 using vec_t = typename VecOf<T, N>::type;
+
+// The same bytes as a vector of a built-in type, for loads and stores.
+template <typename T, int N>
+struct RawOf {
+    using type = vec_t<T, N>;
+};
+template <>
+struct RawOf<cf32, 1> {
+    using type = float __attribute__((ext_vector_type(2)));
+};
+template <>
+struct RawOf<cf32, 2> {
+    using type = float __attribute__((ext_vector_type(4)));
+};
+template <>
+struct RawOf<cf64, 1> {
+    using type = double __attribute__((ext_vector_type(2)));
+};
 
 template <typename T>
 constexpr int kVec = 16 / int(sizeof(T));
@@ -62,22 +100,48 @@ __device__ __forceinline__ void set_lane(vec_t<T, N>& v, int j, T x) {
 
 template <typename T, int N>
 __device__ __forceinline__ vec_t<T, N> ld(const T* p) {
-    return *reinterpret_cast<const vec_t<T, N>*>(p);
+    using R = typename RawOf<T, N>::type;
+    return __builtin_bit_cast(vec_t<T, N>, *reinterpret_cast<const R*>(p));
 }
 
 template <typename T, int N>
 __device__ __forceinline__ void st(T* p, const vec_t<T, N>& v, bool nt) {
+    using R = typename RawOf<T, N>::type;
+    const R r = __builtin_bit_cast(R, v);
     if (nt)
-        __builtin_nontemporal_store(v, reinterpret_cast<vec_t<T, N>*>(p));
+        __builtin_nontemporal_store(r, reinterpret_cast<R*>(p));
     else
-        *reinterpret_cast<vec_t<T, N>*>(p) = v;
+        *reinterpret_cast<R*>(p) = r;
 }
 
-// Eqn. 1 on one vector: alpha*a, or alpha*a + beta*b (unfused).
+// Complex product s*x: re = s.re*x.re - s.im*x.im, im = s.re*x.im + s.im*x.re,
+// every product and sum rounded on its own (contraction is off in this file).
+template <typename C>
+__device__ __forceinline__ C cmul(const C& s, const C& x) {
+    const auto t1 = s.re * x.re, t2 = s.im * x.im, t3 = s.re * x.im, t4 = s.im * x.re;
+    return C{t1 - t2, t3 + t4};
+}
+
+// Eqn. 1 on one vector: alpha*a, or alpha*a + beta*b (unfused; complex
+// elements add the two complex products part by part).
 template <typename T, int N, bool BETA0>
 __device__ __forceinline__ vec_t<T, N> epilogue(const vec_t<T, N>& a, const vec_t<T, N>& b,
                                                 T alpha, T beta) {
-    if constexpr (BETA0) {
+    if constexpr (IsComplex<T>::value) {
+        vec_t<T, N> r;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const T x = lane<T, N>(a, j);
+            const T pa = cmul(alpha, x);
+            if constexpr (BETA0) {
+                set_lane<T, N>(r, j, pa);
+            } else {
+                const T pb = cmul(beta, lane<T, N>(b, j));
+                set_lane<T, N>(r, j, T{pa.re + pb.re, pa.im + pb.im});
+            }
+        }
+        return r;
+    } else if constexpr (BETA0) {
         return alpha * a;
     } else {
         vec_t<T, N> pa = alpha * a;
@@ -714,14 +778,14 @@ __global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
         }
         const int64_t i = nv * V + gid;
         if (i < a.n) {
-            T b = T(0);
+            T b{};
             if constexpr (!BETA0) b = a.Bsrc[i];
             a.Bdst[i] = epilogue<T, 1, BETA0>(a.A[i], b, a.alpha, a.beta);
         }
         return;
     }
     for (int64_t i = gid; i < a.n; i += G) {
-        T b = T(0);
+        T b{};
         if constexpr (!BETA0) b = a.Bsrc[i * a.sb];
         a.Bdst[i * a.sb] = epilogue<T, 1, BETA0>(a.A[i * a.sa], b, a.alpha, a.beta);
     }

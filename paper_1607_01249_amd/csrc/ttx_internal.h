@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <functional>
 #include <string>
+#include <type_traits>
 
 #include "../../include/ttx.h"
 #include "menu.h"
@@ -12,6 +13,44 @@
 namespace ttx {
 
 constexpr int kMaxDims = TTX_MAX_DIMS;
+
+// Complex elements: interleaved (re, im) pairs, aligned to their size so
+// that one element is one 8- or 16-byte access.
+struct alignas(8) cf32 {
+    float re, im;
+};
+struct alignas(16) cf64 {
+    double re, im;
+};
+
+inline bool dtype_valid(int dtype) { return dtype >= TTX_F32 && dtype <= TTX_C64; }
+inline bool dtype_complex(int dtype) { return dtype == TTX_C32 || dtype == TTX_C64; }
+inline int elem_bytes(int dtype) {
+    return dtype == TTX_F32 ? 4 : dtype == TTX_F64 ? 8 : dtype == TTX_C32 ? 8 : 16;
+}
+inline const char* dtype_name(int dtype) {
+    return dtype == TTX_F32 ? "f32" : dtype == TTX_F64 ? "f64" : dtype == TTX_C32 ? "c32" : "c64";
+}
+
+// A scalar alpha or beta as the caller passed it (the imaginary part is zero
+// for the real element types).
+struct Scalar {
+    double re = 0.0, im = 0.0;
+    Scalar() = default;
+    Scalar(double r) : re(r) {}
+    Scalar(double r, double i) : re(r), im(i) {}
+};
+
+// The scalar rounded to the element type's scalar.
+template <typename T>
+inline T scalar_as(const Scalar& s) {
+    if constexpr (std::is_same<T, cf32>::value)
+        return T{float(s.re), float(s.im)};
+    else if constexpr (std::is_same<T, cf64>::value)
+        return T{s.re, s.im};
+    else
+        return T(s.re);
+}
 
 // Division by a run-time invariant 32-bit divisor with a multiply and a
 // shift (Granlund and Montgomery, "Division by invariant integers using
@@ -157,8 +196,8 @@ struct TileShape { int ta, tb; };
 ttx_status fail(ttx_status s, const std::string& msg);
 void clear_error();
 
-// beta == 0 after rounding to the element type (then B is not read).
-bool beta_is_zero(int dtype, double beta);
+// beta == 0 after rounding to the element type (complex: both parts); then B is not read.
+bool beta_is_zero(int dtype, const Scalar& beta);
 // Pointer checks shared by every entry point: NULL, element alignment, and
 // overlap of A with B_out and of B_in with B_out (unless they are equal).
 ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, const void* Bout,
@@ -166,8 +205,8 @@ ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, cons
 
 // The per-call path with the plan cache; B_in may differ from B_out.
 ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
-                            const int64_t* outer_a, const int64_t* outer_b, double alpha,
-                            const void* A, double beta, const void* Bin, void* Bout,
+                            const int64_t* outer_a, const int64_t* outer_b, const Scalar& alpha,
+                            const void* A, const Scalar& beta, const void* Bin, void* Bout,
                             hipStream_t stream);
 
 // Planner (host only).
@@ -205,12 +244,15 @@ inline bool config_is_staged(const ttx_config& c) {
     return c.family == TTX_FAMILY_PRESERVED && (c.group_a > 1 || c.group_b > 1) && !config_is_dense(c);
 }
 // Elements per dense tile.
-inline int dense_cap(int dtype) { return dtype == TTX_F32 ? TTX_DENSE_CAP_F32 : TTX_DENSE_CAP_F64; }
+inline int dense_cap(int dtype) {
+    return dtype == TTX_F32 ? TTX_DENSE_CAP_F32 : dtype == TTX_F64 ? TTX_DENSE_CAP_F64
+           : dtype == TTX_C32 ? TTX_DENSE_CAP_C32 : TTX_DENSE_CAP_C64;
+}
 constexpr int kThreads = 256;
 
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
-                        const void* Bsrc, void* Bdst, double alpha, double beta,
+                        const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream);
 
 // The kernel launch_tiles would use, spelled as profilers print it.

@@ -5,10 +5,19 @@ import numpy as np
 import paper_1607_01249_amd as ttx
 
 F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+C32, C64 = np.dtype(np.complex64), np.dtype(np.complex128)
+REAL_OF = {C32: F32, C64: F64}
+_CODES = {F32: ttx.F32, F64: ttx.F64, C32: ttx.C32, C64: ttx.C64}
 
 
 def dtype_code(dtype):
-    return ttx.F32 if np.dtype(dtype) == F32 else ttx.F64
+    return _CODES[np.dtype(dtype)]
+
+
+def _torch_dtype(dtype):
+    import torch
+    return {F32: torch.float32, F64: torch.float64, C32: torch.complex64,
+            C64: torch.complex128}[np.dtype(dtype)]
 
 
 def to_device(x, pad_elems=0):
@@ -16,8 +25,7 @@ def to_device(x, pad_elems=0):
     many elements into the allocation (for misaligned-pointer cases).
     Returns (tensor, address of the first element)."""
     import torch
-    t = torch.empty(len(x) + pad_elems, dtype=torch.float32 if x.dtype == F32 else torch.float64,
-                    device="cuda")
+    t = torch.empty(len(x) + pad_elems, dtype=_torch_dtype(x.dtype), device="cuda")
     t[pad_elems:].copy_(torch.from_numpy(x))
     return t, t.data_ptr() + pad_elems * x.dtype.itemsize
 
@@ -35,15 +43,19 @@ def gpu_transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, pad
     dA, pa = to_device(A, pad_a)
     dB, pb = to_device(B, pad_b)
     stream = ttx.current_stream()
+    cx = isinstance(alpha, complex) or isinstance(beta, complex)
     if plan_config is None:
-        ttx.ttx_transpose(dtype_code(A.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa,
-                          beta, pb, stream)
+        run = ttx.ttx_transpose_c if cx else ttx.ttx_transpose
+        run(dtype_code(A.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa, beta, pb, stream)
     else:
         plan = ttx.ttx_plan_create(dtype_code(A.dtype), perm, size, outer_a, outer_b)
         try:
             beta0 = A.dtype.type(beta) == 0
             ttx.ttx_plan_set_config(plan, beta0, plan_config)
-            ttx.ttx_plan_execute(plan, alpha, pa, beta, pb, stream)
+            if cx:
+                ttx.ttx_plan_execute_c(plan, alpha, pa, beta, pb, pb, stream)
+            else:
+                ttx.ttx_plan_execute(plan, alpha, pa, beta, pb, stream)
         finally:
             ttx.ttx_plan_destroy(plan)
     out = from_device(dB, pad_b)
@@ -78,6 +90,8 @@ def assert_parity(got, ref, exact, what=""):
     bit-identity the expectation; the count of differing elements is
     reported)."""
     assert got.shape == ref.shape and got.dtype == ref.dtype
+    if got.dtype in REAL_OF:   # complex: both parts, compared as real numbers
+        got, ref = got.view(REAL_OF[got.dtype]), ref.view(REAL_OF[ref.dtype])
     nan_g, nan_r = np.isnan(got), np.isnan(ref)
     assert np.array_equal(nan_g, nan_r), "NaN positions differ %s" % what
     ib = np.uint32 if got.dtype == F32 else np.uint64

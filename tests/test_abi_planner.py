@@ -378,3 +378,68 @@ int main() {
                     "-I" + os.path.join(ROOT, "paper_1607_01249_amd", "csrc"), str(src), "-o", str(exe)],
                    check=True)
     subprocess.run([str(exe)], check=True)
+
+
+# -- complex element types (c and z) ------------------------------------------------------
+COMPLEX_SHAPES = [((2, 0, 3, 1), (37, 70, 19, 23)), ((0, 2, 1), (5, 40, 33)), ((1, 0), (7, 3000)),
+                  ((1, 0, 2), (3, 4, 700)), ((0,), (100,)), ((0, 2, 1), (64, 9, 48))]
+
+
+@pytest.mark.parametrize("code", [ttx.C32, ttx.C64])
+@pytest.mark.parametrize("perm,size", COMPLEX_SHAPES)
+def test_complex_plans_and_candidates(code, perm, size):
+    tname = "ttx::cf32" if code == ttx.C32 else "ttx::cf64"
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        info = ttx.ttx_plan_describe(plan)
+        assert info["dtype"] == code
+        name = ttx.ttx_plan_kernel_name(plan, 1, 1 << 40, 1 << 41)
+        assert tname in name, name
+        if code == ttx.C64:   # one element is a whole 16-byte access: no vector variants
+            assert not any(v in name for v in (", 2>", ", 2, 2>", ", 2, 1>", ", 1, 2>")), name
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    cands, cost = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    assert cands and cost == sorted(cost)
+    n0 = size[0] if perm[0] == 0 else 1
+    for c in cands:
+        if c.flags & ttx.CFG_DENSE:
+            rows = n0 if c.family == ttx.FAMILY_PRESERVED else 1
+            assert rows * c.tile_a * c.tile_b * max(1, c.tile_c) <= ttx.DENSE_CAP[code]
+
+
+def test_complex_c32_uses_the_fp64_menu_shapes():
+    """Single complex elements have the FP64 byte size: same tile menu."""
+    perm, size = (2, 0, 3, 1), (37, 70, 19, 23)
+    shapes = {}
+    for code in (ttx.F64, ttx.C32, ttx.C64):
+        cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+        shapes[code] = {(c.tile_a, c.tile_b) for c in cands if not c.flags & ttx.CFG_DENSE}
+    assert shapes[ttx.C32] == shapes[ttx.F64]
+    assert shapes[ttx.C64] != shapes[ttx.F64] and (32, 32) in shapes[ttx.C64]
+
+
+def test_complex_argument_errors_need_no_gpu():
+    perm, size = (1, 0), (4, 5)
+    # complex scalars for a real element type
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_transpose_c(ttx.F32, 2, perm, size, None, None, 1 + 1j, 1 << 40, 0.0, 1 << 41)
+    assert e.value.status == ttx.EINVAL
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_transpose_c(ttx.F64, 2, perm, size, None, None, 1.0, 1 << 40, 2j, 1 << 41)
+    assert e.value.status == ttx.EINVAL
+    # element alignment: 8 bytes for single complex, 16 for double complex
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_transpose_c(ttx.C32, 2, perm, size, None, None, 1j, (1 << 40) + 4, 0.0, 1 << 41)
+    assert e.value.status == ttx.EINVAL
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_transpose_c(ttx.C64, 2, perm, size, None, None, 1j, (1 << 40) + 8, 0.0, 1 << 41)
+    assert e.value.status == ttx.EINVAL
+    # overlap uses the complex element size (20 elements of 16 bytes)
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_transpose_c(ttx.C64, 2, perm, size, None, None, 1j, 1 << 40, 0.0, (1 << 40) + 304)
+    assert e.value.status == ttx.EOVERLAP
+    # oracle and library agree on the dtype codes
+    for code in (ttx.C32, ttx.C64):
+        assert oracle.check(code, perm, size) == oracle.OK
+    assert oracle.check(4, perm, size) != oracle.OK

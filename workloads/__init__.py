@@ -14,12 +14,17 @@ import math
 import numpy as np
 
 F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
+C32, C64 = np.dtype(np.complex64), np.dtype(np.complex128)
 
 
 def uniform(n, dtype, seed):
-    """n values uniform in [-1, 1) of the given dtype (exact on the dtype's grid)."""
-    rng = np.random.default_rng(seed)
+    """n values uniform in [-1, 1) of the given dtype (exact on the dtype's grid);
+    complex values have both parts drawn that way (real, imaginary, real, ...)."""
     dtype = np.dtype(dtype)
+    if dtype in (C32, C64):
+        parts = uniform(2 * int(n), F32 if dtype == C32 else F64, seed)
+        return parts.view(dtype)
+    rng = np.random.default_rng(seed)
     if dtype == F32:
         return rng.random(int(n), dtype=np.float32) * 2 - 1
     return rng.random(int(n)) * 2 - 1
