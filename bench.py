@@ -74,6 +74,7 @@ def parse_args():
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-complex", action="store_true", help="skip the complex (c, z) cases")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="Poisson arrival rate (req/s)")
     ap.add_argument("--profile-run", action="store_true",
@@ -376,6 +377,61 @@ def bench_batched(torch, ttx, reps=20, tune=True):
                 speedup=round(pc_med / b_med, 2))
 
 
+def bench_complex(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False):
+    """Per-call complex transpositions (c and z types, complex alpha and beta,
+    beta != 0), about 200 MiB per tensor, one case resident at a time: the
+    median time of `reps` launches per case (3S bytes each).  Launches rotate
+    over three (A, B) pairs so that each one starts with the data of the two
+    before it in the 256 MiB Infinity Cache, not its own."""
+    import workloads
+    out = []
+    tdt = {workloads.C32: torch.complex64, workloads.C64: torch.complex128}
+    codes = {workloads.C32: ttx.C32, workloads.C64: ttx.C64}
+    tuned = 0
+    for c in workloads.complex_cases():
+        n = workloads.elements(c["size"])
+        code = codes[c["dtype"]]
+        plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
+        if not ttx.ttx_plan_describe(plan)["config_from_table"][0]:
+            if profile:
+                raise SystemExit("--profile-run needs every case in the tune table (%s)" % c["name"])
+            log("tuning %s" % c["name"])
+            ttx.ttx_tune(code, c["perm"], c["size"], beta_is_zero=False,
+                         max_candidates=tune_candidates, reps=3)
+            ttx.ttx_plan_destroy(plan)
+            plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
+            tuned += 1
+        pairs = []
+        for k in range(3):
+            A = torch.empty(n, dtype=tdt[c["dtype"]], device="cuda")
+            B = torch.empty_like(A)
+            fill_uniform(torch, torch.view_as_real(A), c["seed_a"] + 100 * k)
+            fill_uniform(torch, torch.view_as_real(B), c["seed_b"] + 100 * k)
+            pairs.append((A, B))
+        kernel = ttx.ttx_plan_kernel_name(plan, 1.0, pairs[0][0].data_ptr(), pairs[0][1].data_ptr())
+        state = {"i": 0}
+
+        def run():
+            state["i"] = (state["i"] + 1) % len(pairs)
+            A, B = pairs[state["i"]]
+            ttx.ttx_plan_execute_c(plan, c["alpha"], A.data_ptr(), c["beta"], B.data_ptr(),
+                                   B.data_ptr(), stream)
+
+        for _ in range(3):
+            run()
+        _, tmed = time_events(torch, run, reps)
+        ttx.ttx_plan_destroy(plan)
+        nbytes = 3 * n * c["dtype"].itemsize
+        gbps = nbytes / tmed / 1e9
+        out.append(dict(case=c["name"], GBps=round(gbps, 1), pct_of_d2d=round(100 * gbps / d2d, 1),
+                        us=round(tmed * 1e6, 1), kernel=kernel))
+        del pairs
+        torch.cuda.empty_cache()
+    g = [o["GBps"] for o in out]
+    return dict(cases=out, shapes_tuned_now=tuned, GBps_median=float(np.median(g)), GBps_min=min(g),
+                pct_of_d2d_median=round(100 * float(np.median(g)) / d2d, 1))
+
+
 def bench_served(torch, ttx, seconds, rate):
     """Open-loop Poisson trace through the server vs the same trace run one
     synchronised per-call request at a time; a sample of requests is re-run
@@ -645,6 +701,13 @@ def main():
     if not args.no_served:
         served = bench_served(torch, ttx, args.serve_seconds, args.serve_rate)
 
+    cplx = None
+    if not args.no_complex and not args.profile_run:
+        log("complex cases")
+        cplx = bench_complex(torch, ttx, d2d, stream, args.tune_candidates)
+        if args.save_table:
+            ttx.ttx_tune_table_save(args.save_table)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
@@ -663,7 +726,7 @@ def main():
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
-        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served,
+        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served, complex=cplx,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,

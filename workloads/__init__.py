@@ -74,6 +74,40 @@ def large_cases(betas=(0.7, 0.0)):
     return out
 
 
+# -- complex elements (the c and z types), about 200 MiB per tensor --------------------
+# Single complex elements have the FP64 byte size and take the FP64 shapes;
+# double complex halves the last extent.
+COMPLEX_PERMS = {
+    "4d": [(3, 2, 1, 0), (2, 0, 3, 1), (0, 2, 1, 3)],
+    "5d": [(1, 3, 0, 4, 2), (0, 3, 2, 4, 1)],
+    "6d": [(5, 4, 3, 2, 1, 0), (0, 5, 1, 4, 2, 3)],
+}
+COMPLEX_ALPHA, COMPLEX_BETA = complex(0.75, -1.25), complex(-0.5, 0.375)
+
+
+def complex_shape(rank, dtype):
+    size = list(LARGE_SHAPES[(rank, F64)])
+    if np.dtype(dtype) == C64:
+        size[-1] //= 2
+    return tuple(size)
+
+
+def complex_cases():
+    """Large complex cases (complex alpha and beta, beta != 0)."""
+    out = []
+    case = 0
+    for rank in ("4d", "5d", "6d"):
+        for dtype in (C32, C64):
+            for perm in COMPLEX_PERMS[rank]:
+                out.append(dict(name="%s_%s_p%s" % (rank, "c32" if dtype == C32 else "c64",
+                                                   "".join(map(str, perm))),
+                                dtype=dtype, size=complex_shape(rank, dtype), perm=perm,
+                                alpha=COMPLEX_ALPHA, beta=COMPLEX_BETA,
+                                seed_a=5000 + case, seed_b=6000 + case))
+                case += 1
+    return out
+
+
 # -- multiple leading dimensions (BLAS-3 packing shapes) ------------------------------
 LD_CASES = [
     dict(name="ld_f64_packing", dtype=F64, size=(384, 96, 48, 32), perm=(1, 0, 2, 3),
