@@ -53,6 +53,12 @@ def _load(path):
     L.ttx_ref_transpose_c.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p, d2,
                                       ctypes.c_void_p, d2, ctypes.c_void_p]
     L.ttx_ref_transpose_c.restype = ctypes.c_int
+    L.ttx_ref_transpose_x.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
+                                      d2, ctypes.c_void_p, d2, ctypes.c_void_p]
+    L.ttx_ref_transpose_x.restype = ctypes.c_int
+    L.ttx_ref_check_x.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p,
+                                  ctypes.c_void_p, ctypes.c_void_p]
+    L.ttx_ref_check_x.restype = ctypes.c_int
     L.ttx_ref_sample_c.argtypes = [ctypes.c_int, ctypes.c_int, ip, i64p, i64p, i64p, d2,
                                    ctypes.c_void_p, d2, ctypes.c_void_p, ctypes.c_int64, i64p,
                                    ctypes.c_void_p]
@@ -86,37 +92,42 @@ def _scalar2(v):
 def transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, library=None):
     """B <- alpha * Pi(A) + beta * B in place on host numpy arrays (Eqn. 1).
 
-    ``A`` and ``B`` are flat numpy arrays of one dtype (float32, float64,
-    complex64 or complex128) holding the column-major outer tensors;
-    ``perm`` is the gather permutation (B position k holds A index
-    ``perm[k]``).  ``alpha`` and ``beta`` may be complex for the complex
-    dtypes.  Returns the C status code.
+    ``A`` and ``B`` are flat numpy arrays (float32, float64, complex64 or
+    complex128) holding the column-major outer tensors; ``perm`` is the
+    gather permutation (B position k holds A index ``perm[k]``).  ``alpha``
+    and ``beta`` may be complex for the complex dtypes.  A and B may differ
+    in precision (float32 with float64, complex64 with complex128: mixed
+    precision, computed in B's precision after converting A).  Returns the
+    C status code.
     """
     L = library or lib()
-    assert A.dtype == B.dtype and A.dtype in DTYPES
+    assert A.dtype in DTYPES and B.dtype in DTYPES
     assert A.flags.c_contiguous and B.flags.c_contiguous and B.flags.writeable
     n = len(perm)
-    return L.ttx_ref_transpose_c(DTYPES[A.dtype], n, _arr(perm, ctypes.c_int),
+    return L.ttx_ref_transpose_x(DTYPES[A.dtype], DTYPES[B.dtype], n, _arr(perm, ctypes.c_int),
                                  _arr(size, ctypes.c_int64), _arr(outer_a, ctypes.c_int64),
                                  _arr(outer_b, ctypes.c_int64), _scalar2(alpha),
                                  A.ctypes.data, _scalar2(beta), B.ctypes.data)
 
 
 def check(dtype_code, perm, size, outer_a=None, outer_b=None, a_addr=1 << 20, b_addr=1 << 40,
-          n=None, library=None):
-    """Status code of the oracle's argument validation (touches no memory)."""
+          n=None, library=None, dtype_a=None):
+    """Status code of the oracle's argument validation (touches no memory);
+    ``dtype_a`` (default: ``dtype_code``) is A's type for mixed precision."""
     L = library or lib()
     n = len(perm) if n is None else n
-    return L.ttx_ref_check(dtype_code, n, _arr(perm, ctypes.c_int) if perm is not None else None,
-                           _arr(size, ctypes.c_int64) if size is not None else None,
-                           _arr(outer_a, ctypes.c_int64), _arr(outer_b, ctypes.c_int64),
-                           a_addr, b_addr)
+    return L.ttx_ref_check_x(dtype_code if dtype_a is None else dtype_a, dtype_code, n,
+                             _arr(perm, ctypes.c_int) if perm is not None else None,
+                             _arr(size, ctypes.c_int64) if size is not None else None,
+                             _arr(outer_a, ctypes.c_int64), _arr(outer_b, ctypes.c_int64),
+                             a_addr, b_addr)
 
 
 def sample(perm, size, alpha, A, beta, B_in, b_index, outer_a=None, outer_b=None, library=None):
     """Eqn. 1 at the B-linear sub-tensor positions ``b_index`` (int64 array);
     returns (expected values, their offsets inside B's outer tensor)."""
     L = library or lib()
+    assert B_in is None or B_in.dtype == A.dtype, "sampling takes one element type"
     b_index = np.ascontiguousarray(b_index, dtype=np.int64)
     out = np.empty(len(b_index), dtype=A.dtype)
     off = np.empty(len(b_index), dtype=np.int64)

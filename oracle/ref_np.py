@@ -30,11 +30,11 @@ def transpose_np(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None):
     size_b = [size[p] for p in perm]
     outer_a = list(size) if outer_a is None else [int(o) for o in outer_a]
     outer_b = list(size_b) if outer_b is None else [int(o) for o in outer_b]
-    t = A.dtype.type
+    t = B.dtype.type
     a_sub = _sub(A, outer_a, size)
     b_sub = _sub(B, outer_b, size_b)
-    moved = np.transpose(a_sub, perm)
-    if np.iscomplexobj(A):
+    moved = np.transpose(a_sub, perm).astype(B.dtype)   # mixed precision: to B's type first
+    if np.iscomplexobj(B):
         alpha_t, beta_t = t(complex(alpha)), t(complex(beta))
     else:
         alpha_t, beta_t = t(alpha), t(beta)

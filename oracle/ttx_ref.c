@@ -29,7 +29,9 @@
  *     1 = double, 2 = single complex, 3 = double complex.  Complex elements
  *     are interleaved (re, im) pairs and alpha, beta may be complex (the
  *     _c entry points); the order of the complex arithmetic is stated at
- *     ref_update_c32 below.
+ *     ref_update_c32 below.  The _x entry points take A and B in different
+ *     precisions of one kind (mixed precision, Table 1), see
+ *     ttx_ref_transpose_x.
  *
  * The loop nest walks B linearly (B index 0 fastest), the loop order of the
  * reference implementation of Sec. 3.2, with the outermost B index shared
@@ -179,33 +181,64 @@ static void ref_update_c64(const double *A, double *B, int64_t off_a, int64_t of
 
 /* Validation only: the status ttx_ref_transpose would return, without
  * touching A or B (A and B are compared as addresses only). */
-int ttx_ref_check(int dtype, int n, const int *perm, const int64_t *size,
-                  const int64_t *outer_a, const int64_t *outer_b,
-                  const void *A, const void *B)
+static int64_t ref_elem_bytes(int dtype)
+{
+    return dtype == REF_F32 ? 4 : dtype == REF_C64 ? 16 : 8;
+}
+
+/* The pairs of data types a transposition may take (Table 1): A and B of
+ * one type, or mixed precision with A and B of the same kind (real or
+ * complex) in different precisions: sd, ds, cz, zc. */
+static int ref_pair_valid(int dtype_a, int dtype_b)
+{
+    if (dtype_a == dtype_b)
+        return 1;
+    return (dtype_a == REF_F32 && dtype_b == REF_F64) || (dtype_a == REF_F64 && dtype_b == REF_F32) ||
+           (dtype_a == REF_C32 && dtype_b == REF_C64) || (dtype_a == REF_C64 && dtype_b == REF_C32);
+}
+
+/* ttx_ref_check with A of type dtype_a and B of type dtype_b. */
+int ttx_ref_check_x(int dtype_a, int dtype_b, int n, const int *perm, const int64_t *size,
+                    const int64_t *outer_a, const int64_t *outer_b,
+                    const void *A, const void *B)
 {
     int64_t size_b[REF_MAX_DIMS], stride_a[REF_MAX_DIMS], stride_b[REF_MAX_DIMS];
     int empty, st;
-    int64_t elem, a_lo, a_hi, b_lo, b_hi;
+    int64_t a_lo, a_hi, b_lo, b_hi;
 
-    st = ref_prepare(dtype, n, perm, size, outer_a, outer_b, size_b, stride_a, stride_b, &empty);
-    if (st != REF_OK || empty)
+    st = ref_prepare(dtype_b, n, perm, size, outer_a, outer_b, size_b, stride_a, stride_b, &empty);
+    if (st != REF_OK)
         return st;
+    if (!ref_pair_valid(dtype_a, dtype_b))
+        return REF_EINVAL;
+    if (empty)
+        return REF_OK;
     if (A == NULL || B == NULL)
         return REF_EINVAL;
-    elem = dtype == REF_F32 ? 4 : dtype == REF_C64 ? 16 : 8;
     a_lo = (int64_t)(uintptr_t)A;
-    a_hi = a_lo + ref_extent_bytes(n, size, stride_a, elem);
+    a_hi = a_lo + ref_extent_bytes(n, size, stride_a, ref_elem_bytes(dtype_a));
     b_lo = (int64_t)(uintptr_t)B;
-    b_hi = b_lo + ref_extent_bytes(n, size_b, stride_b, elem);
+    b_hi = b_lo + ref_extent_bytes(n, size_b, stride_b, ref_elem_bytes(dtype_b));
     if (a_lo < b_hi && b_lo < a_hi)
         return REF_EOVERLAP;
     return REF_OK;
 }
 
+int ttx_ref_check(int dtype, int n, const int *perm, const int64_t *size,
+                  const int64_t *outer_a, const int64_t *outer_b,
+                  const void *A, const void *B)
+{
+    return ttx_ref_check_x(dtype, dtype, n, perm, size, outer_a, outer_b, A, B);
+}
+
 /* B_{Pi(i)} <- alpha*A_i + beta*B_{Pi(i)} over host arrays (Eqn. 1), with
  * complex scalars alpha = (alpha[0], alpha[1]) and beta likewise; for the
- * real data types the imaginary parts must be zero. */
-int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
+ * real data types the imaginary parts must be zero.  A holds elements of
+ * type dtype_a and B of type dtype (mixed precision, Table 1 "sd", "ds",
+ * "cz", "zc"): each A element is first converted to B's type (widening is
+ * exact; narrowing rounds to nearest, part by part for complex), and the
+ * update is then computed in B's type exactly as when both types agree. */
+int ttx_ref_transpose_x(int dtype_a, int dtype, int n, const int *perm, const int64_t *size,
                         const int64_t *outer_a, const int64_t *outer_b,
                         const double *alpha, const void *A, const double *beta, void *B)
 {
@@ -218,7 +251,7 @@ int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
     if ((dtype == REF_F32 || dtype == REF_F64) && (alpha[1] != 0.0 || beta[1] != 0.0))
         return REF_EINVAL;
 
-    st = ttx_ref_check(dtype, n, perm, size, outer_a, outer_b, A, B);
+    st = ttx_ref_check_x(dtype_a, dtype, n, perm, size, outer_a, outer_b, A, B);
     if (st != REF_OK)
         return st;
     st = ref_prepare(dtype, n, perm, size, outer_a, outer_b, size_b, stride_a, stride_b, &empty);
@@ -244,7 +277,24 @@ int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
                 off_a += j[k] * a_stride_in_b_order[k];
                 off_b += j[k] * stride_b[k];
             }
-            if (dtype == REF_F32)
+            if (dtype_a != dtype) {
+                /* mixed precision: convert the A element to B's type first */
+                if (dtype == REF_F64) {
+                    const double a = (double)((const float *)A)[off_a];
+                    ref_update_f64(&a, (double *)B, 0, off_b, alpha[0], beta[0]);
+                } else if (dtype == REF_F32) {
+                    const float a = (float)((const double *)A)[off_a];
+                    ref_update_f32(&a, (float *)B, 0, off_b, alpha_f, beta_f);
+                } else if (dtype == REF_C64) {
+                    const float *x = (const float *)A + 2 * off_a;
+                    const double a[2] = {(double)x[0], (double)x[1]};
+                    ref_update_c64(a, (double *)B, 0, off_b, alpha[0], alpha[1], beta[0], beta[1]);
+                } else {
+                    const double *x = (const double *)A + 2 * off_a;
+                    const float a[2] = {(float)x[0], (float)x[1]};
+                    ref_update_c32(a, (float *)B, 0, off_b, alpha_f, alpha_fi, beta_f, beta_fi);
+                }
+            } else if (dtype == REF_F32)
                 ref_update_f32((const float *)A, (float *)B, off_a, off_b, alpha_f, beta_f);
             else if (dtype == REF_F64)
                 ref_update_f64((const double *)A, (double *)B, off_a, off_b, alpha[0], beta[0]);
@@ -261,6 +311,14 @@ int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
         }
     }
     return REF_OK;
+}
+
+/* A and B of one type. */
+int ttx_ref_transpose_c(int dtype, int n, const int *perm, const int64_t *size,
+                        const int64_t *outer_a, const int64_t *outer_b,
+                        const double *alpha, const void *A, const double *beta, void *B)
+{
+    return ttx_ref_transpose_x(dtype, dtype, n, perm, size, outer_a, outer_b, alpha, A, beta, B);
 }
 
 /* The real-scalar form of ttx_ref_transpose_c (any data type). */

@@ -14,6 +14,9 @@ mathematics fixes:
   permutations (which separates the gather from the scatter reading);
 * the update against a separate elementwise axpby, beta = 0 never reading B,
   the non-fused operation order (contraction detector), special values;
+* mixed precision (sd, ds, cz, zc): widening is exact, narrowing rounds to
+  nearest on float midpoints, and any update equals numpy's conversion
+  followed by the one-type transposition;
 * complex elements (the c and z types): with real scalars the result equals
   the real transposition of the interleaved (re, im) planes, multiplying by
   i swaps and negates parts exactly, numpy's complex arithmetic agrees to a
@@ -456,12 +459,93 @@ def pin_complex_beta_zero_does_not_read_b(L):
             assert not np.isnan(B.view(F32)).any()
 
 
+# ---------------------------------------------------------------------------------------
+# Mixed precision (A and B of one kind, different precisions: sd, ds, cz, zc).
+
+MIXED_PAIRS = [(F32, F64), (F64, F32), (C32, C64), (C64, C32)]
+
+
+def _rand_kind(n, dtype, rng):
+    return _rand(n, dtype, rng)
+
+
+def pin_mixed_widening_is_exact(L):
+    """A single, B double (sd, cz), alpha = 1, beta = 0: B is A transposed and
+    widened, exactly (numpy's transpose and astype)."""
+    rng = np.random.default_rng(41)
+    for da, db in ((F32, F64), (C32, C64)):
+        for perm, size in [((2, 0, 1), (5, 6, 7)), ((1, 0), (9, 4)), ((0, 2, 1, 3), (3, 4, 5, 2))]:
+            A = _rand_kind(_elems(size), da, rng)
+            B = np.full(_elems(size), np.nan, dtype=db)
+            _run(L, perm, size, 1.0, A, 0.0, B)
+            want = A.reshape(size, order="F").transpose(perm).astype(db).flatten(order="F")
+            assert _same_bits(B, want), (da, db, perm)
+
+
+def pin_mixed_narrowing_rounds_to_nearest(L):
+    """A double, B single (ds, zc), alpha = 1, beta = 0: each part rounds to
+    the nearest float, ties to even (values on and beside float midpoints)."""
+    u = 2.0 ** -24   # half an ulp of 1.0f
+    src = [1.0 + u, 1.0 + 3 * u, 1.0 + u * (1 + 2.0 ** -20), -(1.0 + 3 * u), 2.0 ** -150,
+           3.0 * 2.0 ** -150, 1e300, -1e300, 0.1]
+    want = [1.0, 1.0 + 4 * u, 1.0 + 2 * u, -(1.0 + 4 * u), 0.0, 2.0 ** -148, np.inf, -np.inf,
+            float.fromhex("0x1.99999ap-4")]
+    A = np.array(src, dtype=F64)
+    B = np.zeros(len(src), dtype=F32)
+    _run(L, (0, 1), (len(src), 1), 1.0, A, 0.0, B)
+    assert B.tolist() == [float(np.float32(w)) for w in want], B
+    assert np.signbit(B[4]) == False   # noqa: E712
+    # complex: finite values only (alpha = 1 multiplies as (1, 0), and 0 * inf is NaN)
+    fin = [k for k in range(len(src)) if abs(src[k]) < 1e300]
+    re, im = [src[k] for k in fin], [src[k] for k in fin[::-1]]
+    Az = np.array([complex(a, b) for a, b in zip(re, im)], dtype=C64)
+    Bz = np.zeros(len(fin), dtype=C32)
+    _run(L, (0, 1), (len(fin), 1), 1.0, Az, 0.0, Bz)
+    assert Bz.real.tolist() == B[fin].tolist() and Bz.imag.tolist() == B[fin[::-1]].tolist()
+
+
+def pin_mixed_is_conversion_then_update(L):
+    """Any alpha, beta: the mixed result equals A converted to B's type (numpy
+    astype, round to nearest) followed by the one-type transposition."""
+    rng = np.random.default_rng(42)
+    for da, db in MIXED_PAIRS:
+        for perm, size, oa, ob in [((2, 0, 3, 1), (3, 4, 2, 5), None, None),
+                                   ((1, 0), (7, 6), (9, 6), (8, 7))]:
+            size_b = [size[p] for p in perm]
+            A = _rand_kind(_elems(oa or size), da, rng) * 3.7
+            B0 = _rand_kind(_elems(ob or size_b), db, rng)
+            cx = db in (C32, C64)
+            for alpha, beta in ((1.3, 0.7), (-2.0, 0.0)) + (((0.5 - 1j), (0.25 + 2j)),) * cx:
+                got = B0.copy()
+                _run(L, perm, size, alpha, A, beta, got, oa, ob)
+                want = B0.copy()
+                _run(L, perm, size, alpha, A.astype(db), beta, want, oa, ob)
+                assert _same_bits(got, want), (da, db, perm, alpha, beta)
+
+
+def pin_mixed_validation(L):
+    big = 1 << 40
+    c = lambda *a, **k: oracle.check(*a, library=L, **k)
+    for da, db in ((0, 1), (1, 0), (2, 3), (3, 2)):
+        assert c(db, (1, 0), (2, 3), dtype_a=da) == oracle.OK
+    for da, db in ((0, 2), (2, 0), (1, 3), (3, 1), (0, 3), (4, 0)):
+        assert c(db, (1, 0), (2, 3), dtype_a=da) == oracle.EINVAL, (da, db)
+    # overlap with A in 4-byte and B in 8-byte elements (6 elements each)
+    assert c(1, (1, 0), (2, 3), a_addr=big, b_addr=big + 20, dtype_a=0) == oracle.EOVERLAP
+    assert c(1, (1, 0), (2, 3), a_addr=big, b_addr=big + 24, dtype_a=0) == oracle.OK
+    # A in 8-byte elements after B in 4-byte ones: [40, 88) meets [20, 44); [44, 92) does not
+    assert c(0, (1, 0), (2, 3), a_addr=big + 40, b_addr=big + 20, dtype_a=1) == oracle.EOVERLAP
+    assert c(0, (1, 0), (2, 3), a_addr=big + 44, b_addr=big + 20, dtype_a=1) == oracle.OK
+
+
 PINS = [pin_sec21_example, pin_index_encoding, pin_brute_force_vs_numpy, pin_textbook_2d,
         pin_round_trip, pin_composition, pin_update_vs_axpby, pin_identity_is_axpby,
         pin_beta_zero_does_not_read_b, pin_contraction_detector, pin_special_values,
         pin_embedded_canaries, pin_validation, pin_complex_real_scalars_are_planewise,
         pin_complex_times_i, pin_complex_vs_numpy, pin_complex_error_bound,
-        pin_complex_beta_zero_does_not_read_b]
+        pin_complex_beta_zero_does_not_read_b, pin_mixed_widening_is_exact,
+        pin_mixed_narrowing_rounds_to_nearest, pin_mixed_is_conversion_then_update,
+        pin_mixed_validation]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -509,6 +593,12 @@ MUTANTS = {
     "complex_beta_real_only_test": [("if (br == 0.0f && bi == 0.0f) {", "if (br == 0.0f) {"),
                                     ("if (br == 0.0 && bi == 0.0) {", "if (br == 0.0) {")],
     "complex_unscaled_offsets": [("A[2 * off_a]", "A[off_a]"), ("A[2 * off_a + 1]", "A[off_a + 1]")],
+    "mixed_not_converted": [("            if (dtype_a != dtype) {", "            if (0) {")],
+    "mixed_imag_dropped": [("const double a[2] = {(double)x[0], (double)x[1]};",
+                            "const double a[2] = {(double)x[0], 0.0};")],
+    "mixed_offset_not_doubled": [("const float *x = (const float *)A + 2 * off_a;",
+                                  "const float *x = (const float *)A + off_a;")],
+    "mixed_pair_unchecked": [("    if (!ref_pair_valid(dtype_a, dtype_b))\n        return REF_EINVAL;\n", "")],
     "complex_alpha_imag_in_f32": [("const float alpha_fi = (float)alpha[1], beta_fi = (float)beta[1];",
                                    "const float alpha_fi = 0.0f, beta_fi = (float)beta[1];")],
 }
@@ -530,18 +620,36 @@ def _build_mutant(tmp, name, edits):
     return oracle_build.build(out=os.path.join(tmp, "lib" + name + ".so"), src=path, extra=("-w",))
 
 
+def _caught_by(lib_path):
+    """Names of the pins that fail against the library at lib_path."""
+    L = oracle._load(lib_path)
+    caught = []
+    for pin in PINS:
+        try:
+            pin(L)
+        except AssertionError:
+            caught.append(pin.__name__)
+    return caught
+
+
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
 def test_pins_catch_planted_mistakes():
+    """Each mutant runs in a child process: some mistakes (a B stride taken
+    from A's outer sizes) write outside B, which must not corrupt the test
+    process.  A child that dies instead of reporting also counts as caught."""
+    import subprocess
+    import sys
     tmp = tempfile.mkdtemp(prefix="ttx_mutants_")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
     try:
         for name, edits in MUTANTS.items():
-            L = oracle._load(_build_mutant(tmp, name, edits))
-            caught = []
-            for pin in PINS:
-                try:
-                    pin(L)
-                except AssertionError:
-                    caught.append(pin.__name__)
+            path = _build_mutant(tmp, name, edits)
+            code = ("import json, sys; sys.path[:0] = [%r, %r]; import test_oracle_pins as t; "
+                    "print(json.dumps(t._caught_by(%r)))" % (here, root, path))
+            r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                               timeout=300)
+            caught = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else ["crash"]
             assert caught, "no pin catches the planted mistake %r" % name
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
