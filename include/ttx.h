@@ -24,10 +24,10 @@
  *    and strideB[k] = prod_{j<k} outer_b[j].  NULL means the tensor is stored
  *    contiguously (outer = size).  outer < size is TTX_EINVAL.  Elements of
  *    the outer tensor of B outside the sub-tensor are never touched.
- *  - dtype selects the element type of both A and B among the four of the
- *    paper's type list (Sec. 2.1, Table 1 "s", "d"; Sec. 3 "c", "z"): FP32,
- *    FP64, and single and double complex stored as interleaved (re, im)
- *    pairs (8 and 16 bytes).
+ *  - dtype selects the element types of A and B among those of the paper's
+ *    type list (Sec. 2.1, Table 1): FP32, FP64, single and double complex
+ *    stored as interleaved (re, im) pairs (8 and 16 bytes), or a
+ *    mixed-precision pair (see ttx_dtype).
  *  - alpha and beta are rounded once to the element type (round to nearest;
  *    for complex types each part to the real part type).  When the rounded
  *    beta is zero (+0 or -0; complex: both parts) B is written without being
@@ -41,8 +41,8 @@
  *    take double alpha, beta pass complex scalars with zero imaginary parts
  *    (the arithmetic above still applies); the *_c entry points take
  *    complex scalars as two doubles (re, im).
- *  - A and B (device pointers) must be aligned to the element size (8 bytes
- *    for single complex, 16 for double complex) and the byte ranges they
+ *  - A and B (device pointers) must be aligned to their element sizes (8
+ *    bytes for single complex, 16 for double complex) and the byte ranges they
  *    address must not overlap (the operation is out-of-place, Sec. 1):
  *    overlap is TTX_EOVERLAP.
  *  - 1 <= n <= TTX_MAX_DIMS.  Index arithmetic is 64-bit.
@@ -67,7 +67,19 @@ extern "C" {
 
 #define TTX_MAX_DIMS 16
 
-typedef enum ttx_dtype { TTX_F32 = 0, TTX_F64 = 1, TTX_C32 = 2, TTX_C64 = 3 } ttx_dtype;
+/* Element types of A and B (Table 1 --dataType): s, d, c, z, and the
+ * mixed-precision pairs sd, ds, cz, zc (A's type first).  With mixed
+ * precision each A element is converted to B's type as it is loaded
+ * (widening is exact; narrowing rounds to nearest, part by part for complex
+ * elements), and the update is computed in B's type; alpha and beta are
+ * rounded to B's type. */
+typedef enum ttx_dtype {
+    TTX_F32 = 0, TTX_F64 = 1, TTX_C32 = 2, TTX_C64 = 3,
+    TTX_F32_F64 = 4,   /* sd: A FP32, B FP64 */
+    TTX_F64_F32 = 5,   /* ds: A FP64, B FP32 */
+    TTX_C32_C64 = 6,   /* cz: A single complex, B double complex */
+    TTX_C64_C32 = 7    /* zc: A double complex, B single complex */
+} ttx_dtype;
 
 typedef enum ttx_status {
     TTX_OK = 0,

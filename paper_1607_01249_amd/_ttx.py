@@ -19,12 +19,19 @@ LIB_PATH = os.path.join(HERE, "libttx.so")
 MAX_DIMS = 16
 
 F32, F64, C32, C64 = 0, 1, 2, 3
+# mixed precision (A's type first): sd, ds, cz, zc
+F32_F64, F64_F32, C32_C64, C64_C32 = 4, 5, 6, 7
 ELEM_BYTES = {F32: 4, F64: 8, C32: 8, C64: 16}
+# (A's element type, B's element type) of every data-type code
+TYPES_OF = {F32: (F32, F32), F64: (F64, F64), C32: (C32, C32), C64: (C64, C64),
+            F32_F64: (F32, F64), F64_F32: (F64, F32), C32_C64: (C32, C64), C64_C32: (C64, C32)}
+CODE_OF = {v: k for k, v in TYPES_OF.items()}
 OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = range(9)
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
 CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE = 1, 2, 4
 DENSE_CAP = {F32: 1024, F64: 1024, C32: 1024, C64: 512}
+DENSE_CAP.update({code: DENSE_CAP[b] for code, (a, b) in TYPES_OF.items() if a != b})
 
 i64 = ctypes.c_int64
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -500,9 +507,10 @@ def transpose(A, B, perm, size, alpha=1.0, beta=0.0, outer_a=None, outer_b=None,
     """B_{Pi(i)} <- alpha*A_i + beta*B_{Pi(i)} on device tensors used as flat
     column-major storage (Eqn. 1); asynchronous on ``stream`` (default: the
     current torch stream)."""
-    code = dtype_code(A)
-    if dtype_code(B) != code:
-        raise TypeError("A and B must have the same dtype")
+    pair = (dtype_code(A), dtype_code(B))
+    if pair not in CODE_OF:
+        raise TypeError("A and B must have the same dtype or differ only in precision")
+    code = CODE_OF[pair]
     if not (A.is_cuda and B.is_cuda):
         raise ValueError("A and B must be device tensors")
     if stream is None:

@@ -69,8 +69,8 @@ ttx_status check_pointers(const Problem& p, const void* A, const void* Bin, cons
                           bool beta0) {
     if (p.family == TTX_FAMILY_EMPTY) return TTX_OK;
     if (!A || !Bout || (!beta0 && !Bin)) return fail(TTX_EINVAL, "NULL tensor pointer");
-    const uintptr_t esz = uintptr_t(elem_bytes(p.dtype));
-    if (reinterpret_cast<uintptr_t>(A) % esz || reinterpret_cast<uintptr_t>(Bout) % esz ||
+    const uintptr_t esa = uintptr_t(elem_bytes(p.dtype_a)), esz = uintptr_t(elem_bytes(p.dtype));
+    if (reinterpret_cast<uintptr_t>(A) % esa || reinterpret_cast<uintptr_t>(Bout) % esz ||
         (!beta0 && reinterpret_cast<uintptr_t>(Bin) % esz))
         return fail(TTX_EINVAL, "tensor pointer not aligned to the element size");
     if (ranges_overlap(A, p.extent_a, Bout, p.extent_b))
@@ -197,7 +197,7 @@ ttx_status ttx_plan_describe(const ttx_plan* plan, ttx_plan_info* info) {
     if (!plan || !info) return fail(TTX_EINVAL, "NULL argument");
     std::memset(info, 0, sizeof(*info));
     const Problem& p = plan->prob;
-    info->dtype = p.dtype;
+    info->dtype = p.code;
     info->family = p.family;
     info->n = p.n;
     for (int d = 0; d < p.n; ++d) {

@@ -315,7 +315,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     std::memset(d, 0, sizeof(*d));
     d->dtype = p.dtype;
     d->variant = -1;
-    if (dtype_complex(p.dtype))
+    if (dtype_complex(p.dtype) || p.dtype_a != p.dtype)
         return fail(TTX_EUNSUPPORTED, "batched execution takes FP32 and FP64 problems only");
     if (p.family == TTX_FAMILY_EMPTY) {
         if (used) *used = default_config(p);

@@ -2,6 +2,7 @@
 // bandwidth-ceiling kernels used for measurement.
 #include <cstdio>
 #include <mutex>
+#include <type_traits>
 
 #include "registry.h"
 #include "tile_kernels.h"
@@ -25,23 +26,28 @@ static int device_cus() {
     return cached[dev];
 }
 
-// Calls f with a value of the element type of dtype.
+// Calls f with values of B's and A's element types for a data-type code.
 template <typename F>
-static hipError_t with_type(int dtype, F&& f) {
-    switch (dtype) {
-        case TTX_F32: return f(float{});
-        case TTX_F64: return f(double{});
-        case TTX_C32: return f(cf32{});
-        default: return f(cf64{});
+static hipError_t with_types(int code, F&& f) {
+    switch (code) {
+        case TTX_F32: return f(float{}, float{});
+        case TTX_F64: return f(double{}, double{});
+        case TTX_C32: return f(cf32{}, cf32{});
+        case TTX_C64: return f(cf64{}, cf64{});
+        case TTX_F32_F64: return f(double{}, float{});
+        case TTX_F64_F32: return f(float{}, double{});
+        case TTX_C32_C64: return f(cf64{}, cf32{});
+        case TTX_C64_C32: return f(cf32{}, cf64{});
+        default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, typename S>
 static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                               const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                               hipStream_t stream) {
-    FlatArgs<T> a;
-    a.A = static_cast<const T*>(A);
+    FlatArgs<T, S> a;
+    a.A = static_cast<const S*>(A);
     a.Bsrc = static_cast<const T*>(Bsrc);
     a.Bdst = static_cast<T*>(Bdst);
     a.alpha = scalar_as<T>(alpha);
@@ -50,38 +56,46 @@ static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0,
     a.sa = p.dim[0].sa;
     a.sb = p.dim[0].sb;
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
-    const int64_t per_block = int64_t(kThreads) * ((a.flags & KF_VEC_A) ? kVec<T> * 4 : 1);
+    constexpr int V = kVec<T> < kVec<S> ? kVec<T> : kVec<S>;
+    const int64_t per_block = int64_t(kThreads) * ((a.flags & KF_VEC_A) ? V * 4 : 1);
     int64_t blocks = (a.n + per_block - 1) / per_block;
     const int64_t cap = int64_t(device_cus()) * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    if (beta0)
-        hipLaunchKernelGGL((k_flat<T, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
-    else
-        hipLaunchKernelGGL((k_flat<T, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+    if constexpr (std::is_same<T, S>::value) {
+        if (beta0)
+            hipLaunchKernelGGL((k_flat<T, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_flat<T, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+    } else {
+        if (beta0)
+            hipLaunchKernelGGL((k_flat_x<T, S, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_flat_x<T, S, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename S>
 static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                                const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                                hipStream_t stream) {
-    TileArgs<T> a;
+    TileArgs<T, S> a;
     build_grid(p, c, &a);
-    a.A = static_cast<const T*>(A);
+    a.A = static_cast<const S*>(A);
     a.Bsrc = static_cast<const T*>(Bsrc);
     a.Bdst = static_cast<T*>(Bdst);
     a.alpha = scalar_as<T>(alpha);
     a.beta = scalar_as<T>(beta);
     a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
     if (config_is_dense(c)) {
-        const uint32_t full = dense_grid(p.dtype, beta0);
+        const uint32_t full = dense_grid(p.code, beta0);
         const uint32_t grid = a.g.ntiles < full ? a.g.ntiles : full;
-        return dense_launcher(p.dtype, beta0)(&a, grid, stream);
+        return dense_launcher(p.code, beta0)(&a, grid, stream);
     }
     if (config_is_staged(c)) {
         const StagedRow* rows;
-        const int nr = staged_rows(p.dtype, beta0, &rows);
+        const int nr = staged_rows(p.code, beta0, &rows);
         const int lanes = staged_lanes(p.dim[0].size);
         for (int i = 0; i < nr; ++i) {
             if (rows[i].n0_max == lanes && rows[i].tx == c.tile_a && rows[i].ty == c.tile_b) {
@@ -94,9 +108,9 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
     const LauncherRow* table;
     int n;
     if (p.family == TTX_FAMILY_MOVED) {
-        n = moved_rows(p.dtype, beta0, &table);
+        n = moved_rows(p.code, beta0, &table);
     } else {
-        n = preserved_rows(p.dtype, beta0, &table);
+        n = preserved_rows(p.code, beta0, &table);
     }
     const int variant = a.flags & (KF_VEC_A | KF_VEC_B);
     for (int i = 0; i < n; ++i) {
@@ -112,10 +126,11 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
                         const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream) {
     if (p.family == TTX_FAMILY_EMPTY) return hipSuccess;
-    return with_type(p.dtype, [&](auto tag) {
-        using T = decltype(tag);
-        if (p.family == TTX_FAMILY_FLAT) return launch_flat<T>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-        return launch_tiled<T>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+    return with_types(p.code, [&](auto t, auto s) {
+        using T = decltype(t);
+        using S = decltype(s);
+        if (p.family == TTX_FAMILY_FLAT) return launch_flat<T, S>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+        return launch_tiled<T, S>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
     });
 }
 
@@ -123,25 +138,32 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
                         const void* Bsrc, const void* Bdst) {
     if (p.family == TTX_FAMILY_EMPTY) return "";
     static const char* const kTypeName[] = {"float", "double", "ttx::cf32", "ttx::cf64"};
-    const char* t = kTypeName[p.dtype];
+    // the same-type kernels are k_<kind><T, ...>; mixed ones k_<kind>_x<T, S, ...>
+    char ts[64];
+    const bool mixed = p.dtype_a != p.dtype;
+    if (mixed)
+        std::snprintf(ts, sizeof(ts), "_x<%s, %s", kTypeName[p.dtype], kTypeName[p.dtype_a]);
+    else
+        std::snprintf(ts, sizeof(ts), "<%s", kTypeName[p.dtype]);
     const char* z = beta0 ? "true" : "false";
-    const int V = 16 / elem_bytes(p.dtype);
+    const int VA = 16 / elem_bytes(p.dtype_a), VB = 16 / elem_bytes(p.dtype);
+    const int V = VA < VB ? VA : VB;
     const int f = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
-    char buf[128];
+    char buf[160];
     if (p.family == TTX_FAMILY_FLAT) {
-        std::snprintf(buf, sizeof(buf), "k_flat<%s, %s>", t, z);
+        std::snprintf(buf, sizeof(buf), "k_flat%s, %s>", ts, z);
     } else if (config_is_dense(c)) {
-        std::snprintf(buf, sizeof(buf), "k_dense<%s, %s, %d>", t, z, dense_cap(p.dtype));
+        std::snprintf(buf, sizeof(buf), "k_dense%s, %s, %d>", ts, z, dense_cap(p.dtype));
     } else if (p.family == TTX_FAMILY_MOVED) {
-        const int va = (f & KF_VEC_A) && V > 1 && c.tile_a % V == 0 ? V : 1;
-        const int vb = (f & KF_VEC_B) && V > 1 && c.tile_b % V == 0 ? V : 1;
-        std::snprintf(buf, sizeof(buf), "k_moved<%s, %s, %d, %d, %d, %d>", t, z, c.tile_a, c.tile_b, va, vb);
+        const int va = (f & KF_VEC_A) && VA > 1 && c.tile_a % VA == 0 ? VA : 1;
+        const int vb = (f & KF_VEC_B) && VB > 1 && c.tile_b % VB == 0 ? VB : 1;
+        std::snprintf(buf, sizeof(buf), "k_moved%s, %s, %d, %d, %d, %d>", ts, z, c.tile_a, c.tile_b, va, vb);
     } else if (config_is_staged(c)) {
-        std::snprintf(buf, sizeof(buf), "k_staged<%s, %s, %d, %d, %d>", t, z, staged_lanes(p.dim[0].size),
+        std::snprintf(buf, sizeof(buf), "k_staged%s, %s, %d, %d, %d>", ts, z, staged_lanes(p.dim[0].size),
                       c.tile_a, c.tile_b);
     } else {
         const int v = (f & KF_VEC_A) && V > 1 && c.tile_a % V == 0 ? V : 1;
-        std::snprintf(buf, sizeof(buf), "k_preserved<%s, %s, %d, %d, %d>", t, z, c.tile_a, c.tile_b, v);
+        std::snprintf(buf, sizeof(buf), "k_preserved%s, %s, %d, %d, %d>", ts, z, c.tile_a, c.tile_b, v);
     }
     return buf;
 }

@@ -1,5 +1,7 @@
-// Dense-tile kernel instantiations (one capacity per element type).
+// Dense-tile kernel instantiations (the dense capacity of B's element type,
+// for every data-type code).
 #include <mutex>
+#include <type_traits>
 
 #include "menu.h"
 #include "registry.h"
@@ -7,17 +9,28 @@
 
 namespace ttx {
 
-template <typename T, bool B0, int CAP>
+template <typename T, typename S, bool B0, int CAP>
 static hipError_t launch_dense(const void* args, uint32_t grid, hipStream_t stream) {
-    const TileArgs<T>& a = *static_cast<const TileArgs<T>*>(args);
-    hipLaunchKernelGGL((k_dense<T, B0, CAP>), dim3(grid), dim3(kThreads), 0, stream, a);
+    const TileArgs<T, S>& a = *static_cast<const TileArgs<T, S>*>(args);
+    if constexpr (std::is_same<T, S>::value)
+        hipLaunchKernelGGL((k_dense<T, B0, CAP>), dim3(grid), dim3(kThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_dense_x<T, S, B0, CAP>), dim3(grid), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
+}
+
+template <typename T, typename S, bool B0, int CAP>
+static hipError_t dense_occupancy(int* nb) {
+    if constexpr (std::is_same<T, S>::value)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense<T, B0, CAP>, kThreads, 0);
+    else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense_x<T, S, B0, CAP>, kThreads, 0);
 }
 
 // Workgroups of a full wave of the dense kernel on the current device: the
 // kernel loops over tiles (pipelined), so that each workgroup computes its
 // per-slot offsets once and streams many tiles.
-template <typename T, bool B0, int CAP>
+template <typename T, typename S, bool B0, int CAP>
 static uint32_t resident(int dev) {
     static std::mutex mu;
     static uint32_t cache[64] = {};
@@ -25,8 +38,7 @@ static uint32_t resident(int dev) {
     if (dev < 0 || dev >= 64) dev = 0;
     if (!cache[dev]) {
         int nb = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dense<T, B0, CAP>, kThreads, 0) != hipSuccess ||
-            nb <= 0)
+        if (dense_occupancy<T, S, B0, CAP>(&nb) != hipSuccess || nb <= 0)
             nb = 4;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
@@ -35,31 +47,49 @@ static uint32_t resident(int dev) {
     return cache[dev];
 }
 
-uint32_t dense_grid(int dtype, bool beta0) {
+uint32_t dense_grid(int code, bool beta0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    switch (dtype) {
+    switch (code) {
         case TTX_F32:
-            return beta0 ? resident<float, true, TTX_DENSE_CAP_F32>(dev) : resident<float, false, TTX_DENSE_CAP_F32>(dev);
+            return beta0 ? resident<float, float, true, TTX_DENSE_CAP_F32>(dev) : resident<float, float, false, TTX_DENSE_CAP_F32>(dev);
         case TTX_F64:
-            return beta0 ? resident<double, true, TTX_DENSE_CAP_F64>(dev) : resident<double, false, TTX_DENSE_CAP_F64>(dev);
+            return beta0 ? resident<double, double, true, TTX_DENSE_CAP_F64>(dev) : resident<double, double, false, TTX_DENSE_CAP_F64>(dev);
         case TTX_C32:
-            return beta0 ? resident<cf32, true, TTX_DENSE_CAP_C32>(dev) : resident<cf32, false, TTX_DENSE_CAP_C32>(dev);
-        default:
-            return beta0 ? resident<cf64, true, TTX_DENSE_CAP_C64>(dev) : resident<cf64, false, TTX_DENSE_CAP_C64>(dev);
+            return beta0 ? resident<cf32, cf32, true, TTX_DENSE_CAP_C32>(dev) : resident<cf32, cf32, false, TTX_DENSE_CAP_C32>(dev);
+        case TTX_C64:
+            return beta0 ? resident<cf64, cf64, true, TTX_DENSE_CAP_C64>(dev) : resident<cf64, cf64, false, TTX_DENSE_CAP_C64>(dev);
+        case TTX_F32_F64:
+            return beta0 ? resident<double, float, true, TTX_DENSE_CAP_F64>(dev) : resident<double, float, false, TTX_DENSE_CAP_F64>(dev);
+        case TTX_F64_F32:
+            return beta0 ? resident<float, double, true, TTX_DENSE_CAP_F32>(dev) : resident<float, double, false, TTX_DENSE_CAP_F32>(dev);
+        case TTX_C32_C64:
+            return beta0 ? resident<cf64, cf32, true, TTX_DENSE_CAP_C64>(dev) : resident<cf64, cf32, false, TTX_DENSE_CAP_C64>(dev);
+        case TTX_C64_C32:
+            return beta0 ? resident<cf32, cf64, true, TTX_DENSE_CAP_C32>(dev) : resident<cf32, cf64, false, TTX_DENSE_CAP_C32>(dev);
+        default: return 0;
     }
 }
 
-TileLaunchFn dense_launcher(int dtype, bool beta0) {
-    switch (dtype) {
+TileLaunchFn dense_launcher(int code, bool beta0) {
+    switch (code) {
         case TTX_F32:
-            return beta0 ? launch_dense<float, true, TTX_DENSE_CAP_F32> : launch_dense<float, false, TTX_DENSE_CAP_F32>;
+            return beta0 ? launch_dense<float, float, true, TTX_DENSE_CAP_F32> : launch_dense<float, float, false, TTX_DENSE_CAP_F32>;
         case TTX_F64:
-            return beta0 ? launch_dense<double, true, TTX_DENSE_CAP_F64> : launch_dense<double, false, TTX_DENSE_CAP_F64>;
+            return beta0 ? launch_dense<double, double, true, TTX_DENSE_CAP_F64> : launch_dense<double, double, false, TTX_DENSE_CAP_F64>;
         case TTX_C32:
-            return beta0 ? launch_dense<cf32, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, false, TTX_DENSE_CAP_C32>;
-        default:
-            return beta0 ? launch_dense<cf64, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, false, TTX_DENSE_CAP_C64>;
+            return beta0 ? launch_dense<cf32, cf32, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, cf32, false, TTX_DENSE_CAP_C32>;
+        case TTX_C64:
+            return beta0 ? launch_dense<cf64, cf64, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, cf64, false, TTX_DENSE_CAP_C64>;
+        case TTX_F32_F64:
+            return beta0 ? launch_dense<double, float, true, TTX_DENSE_CAP_F64> : launch_dense<double, float, false, TTX_DENSE_CAP_F64>;
+        case TTX_F64_F32:
+            return beta0 ? launch_dense<float, double, true, TTX_DENSE_CAP_F32> : launch_dense<float, double, false, TTX_DENSE_CAP_F32>;
+        case TTX_C32_C64:
+            return beta0 ? launch_dense<cf64, cf32, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, cf32, false, TTX_DENSE_CAP_C64>;
+        case TTX_C64_C32:
+            return beta0 ? launch_dense<cf32, cf64, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, cf64, false, TTX_DENSE_CAP_C32>;
+        default: return nullptr;
     }
 }
 

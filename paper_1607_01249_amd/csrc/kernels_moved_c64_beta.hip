@@ -1,5 +1,5 @@
 // Moved-family kernel instantiations: double complex, beta != 0.
 #include "moved_launch.h"
 
-#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(cf64, false, ta, tb)
+#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(cf64, cf64, false, ta, tb)
 TTX_MOVED_TABLE(moved_rows_c64_beta, TTX_MOVED_MENU_C64)

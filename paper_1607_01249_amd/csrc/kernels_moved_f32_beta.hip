@@ -1,5 +1,5 @@
 // Moved-family kernel instantiations: FP32, beta != 0.
 #include "moved_launch.h"
 
-#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(float, false, ta, tb)
+#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(float, float, false, ta, tb)
 TTX_MOVED_TABLE(moved_rows_f32_beta, TTX_MOVED_MENU_F32)

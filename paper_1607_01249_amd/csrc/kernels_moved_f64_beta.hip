@@ -1,5 +1,5 @@
 // Moved-family kernel instantiations: FP64, beta != 0.
 #include "moved_launch.h"
 
-#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(double, false, ta, tb)
+#define TTX_ENTRY(ta, tb) TTX_MOVED_ENTRY(double, double, false, ta, tb)
 TTX_MOVED_TABLE(moved_rows_f64_beta, TTX_MOVED_MENU_F64)

@@ -115,9 +115,11 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
     for (int k = 0; k < n; ++k) sb[perm[k]] = sbpos[k];
 
     Problem p;
-    p.dtype = dtype;
+    p.code = dtype;
+    p.dtype = dtype_b_of(dtype);
+    p.dtype_a = dtype_a_of(dtype);
     p.n_orig = n;
-    const int eb = elem_bytes(dtype);
+    const int ea = elem_bytes(p.dtype_a), eb = elem_bytes(p.dtype);
     bool empty = false;
     int64_t last_a = 0, last_b = 0, elems = 1;
     for (int m = 0; m < n; ++m) {
@@ -134,7 +136,7 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
         return TTX_OK;
     }
     p.elements = elems;
-    p.extent_a = (last_a + 1) * eb;
+    p.extent_a = (last_a + 1) * ea;
     p.extent_b = (last_b + 1) * eb;
 
     // Drop extent-1 indices; their leading dimensions already sit in the
@@ -383,8 +385,8 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
             if (z < 0) return bad("tile_c needs a third index outside the tile");
         }
         // offsets within a dense tile are 32-bit
-        const int64_t es = elem_bytes(p.dtype);
-        if (p.extent_a / es >= (int64_t(1) << 31) || p.extent_b / es >= (int64_t(1) << 31))
+        if (p.extent_a / elem_bytes(p.dtype_a) >= (int64_t(1) << 31) ||
+            p.extent_b / elem_bytes(p.dtype) >= (int64_t(1) << 31))
             return bad("dense tiles need tensors below 2^31 elements");
     } else if (tc > 1) {
         return bad("tile_c is for dense tiles only");
@@ -491,7 +493,10 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
     int f = 0;
     if (c.flags & TTX_CFG_NT_STORE) f |= KF_NT_STORE;
     if (c.flags & TTX_CFG_XCD_SWIZZLE) f |= KF_SWIZZLE;
-    const int V = 16 / elem_bytes(p.dtype);
+    // elements per 16-byte vector of A and of B; kept-row tiles (and flat)
+    // use one width for both sides
+    const int VA = 16 / elem_bytes(p.dtype_a), VB = 16 / elem_bytes(p.dtype);
+    const int V = VA < VB ? VA : VB;
     const bool bptrs = aligned16(Bdst) && (Bsrc == nullptr || aligned16(Bsrc));
     if (p.family == TTX_FAMILY_FLAT) {
         if (p.dim[0].sa == 1 && p.dim[0].sb == 1 && aligned16(A) && bptrs) f |= KF_VEC_A;
@@ -514,12 +519,12 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
     }
     // A side: runs along the A-side super index, every other A stride a
     // multiple of the vector width; B side likewise
-    bool okA = p.dim[L.a].sa == 1 && c.tile_a % V == 0 && L.SA % V == 0 && aligned16(A);
+    bool okA = p.dim[L.a].sa == 1 && c.tile_a % VA == 0 && L.SA % VA == 0 && aligned16(A);
     for (int d = 0; d < p.n && okA; ++d)
-        if (!inA[d]) okA = p.dim[d].sa % V == 0;
-    bool okB = p.dim[L.b].sb == 1 && c.tile_b % V == 0 && L.SB % V == 0 && bptrs;
+        if (!inA[d]) okA = p.dim[d].sa % VA == 0;
+    bool okB = p.dim[L.b].sb == 1 && c.tile_b % VB == 0 && L.SB % VB == 0 && bptrs;
     for (int d = 0; d < p.n && okB; ++d)
-        if (!inB[d]) okB = p.dim[d].sb % V == 0;
+        if (!inB[d]) okB = p.dim[d].sb % VB == 0;
     if (okA) f |= KF_VEC_A;
     if (okB) f |= KF_VEC_B;
     return f;
@@ -580,7 +585,8 @@ static double staged_cost(const Problem& p, const Layout& L, int tx, int ty) {
 // Whether a menu tile of this layout can use 16-byte accesses on both sides,
 // judged from extents and strides alone (pointer alignment aside).
 static bool vector_shape(const Problem& p, const Layout& L, int ta, int tb) {
-    const int V = 16 / elem_bytes(p.dtype);
+    const int VA = 16 / elem_bytes(p.dtype_a), VB = 16 / elem_bytes(p.dtype);
+    const int V = VA < VB ? VA : VB;
     if (L.staged) return false;
     bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
     for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
@@ -590,11 +596,11 @@ static bool vector_shape(const Problem& p, const Layout& L, int ta, int tb) {
         for (int d = 1; d < p.n && ok; ++d) ok = p.dim[d].sa % V == 0 && p.dim[d].sb % V == 0;
         return ok;
     }
-    bool ok = p.dim[L.a].sa == 1 && ta % V == 0 && L.SA % V == 0 && p.dim[L.b].sb == 1 && tb % V == 0 &&
-              L.SB % V == 0;
+    bool ok = p.dim[L.a].sa == 1 && ta % VA == 0 && L.SA % VA == 0 && p.dim[L.b].sb == 1 && tb % VB == 0 &&
+              L.SB % VB == 0;
     for (int d = 0; d < p.n && ok; ++d) {
-        if (!inA[d]) ok = p.dim[d].sa % V == 0;
-        if (ok && !inB[d]) ok = p.dim[d].sb % V == 0;
+        if (!inA[d]) ok = p.dim[d].sa % VA == 0;
+        if (ok && !inB[d]) ok = p.dim[d].sb % VB == 0;
     }
     return ok;
 }

@@ -24,25 +24,39 @@ int moved_rows_c32_beta(const LauncherRow** out);
 int moved_rows_c32_beta0(const LauncherRow** out);
 int moved_rows_c64_beta(const LauncherRow** out);
 int moved_rows_c64_beta0(const LauncherRow** out);
-inline int moved_rows(int dtype, bool beta0, const LauncherRow** out) {
-    switch (dtype) {
+int moved_rows_sd_beta(const LauncherRow** out);
+int moved_rows_sd_beta0(const LauncherRow** out);
+int moved_rows_ds_beta(const LauncherRow** out);
+int moved_rows_ds_beta0(const LauncherRow** out);
+int moved_rows_cz_beta(const LauncherRow** out);
+int moved_rows_cz_beta0(const LauncherRow** out);
+int moved_rows_zc_beta(const LauncherRow** out);
+int moved_rows_zc_beta0(const LauncherRow** out);
+// Rows for a data-type code (ttx_dtype: the element types of A and B).
+inline int moved_rows(int code, bool beta0, const LauncherRow** out) {
+    switch (code) {
         case TTX_F32: return beta0 ? moved_rows_f32_beta0(out) : moved_rows_f32_beta(out);
         case TTX_F64: return beta0 ? moved_rows_f64_beta0(out) : moved_rows_f64_beta(out);
         case TTX_C32: return beta0 ? moved_rows_c32_beta0(out) : moved_rows_c32_beta(out);
-        default: return beta0 ? moved_rows_c64_beta0(out) : moved_rows_c64_beta(out);
+        case TTX_C64: return beta0 ? moved_rows_c64_beta0(out) : moved_rows_c64_beta(out);
+        case TTX_F32_F64: return beta0 ? moved_rows_sd_beta0(out) : moved_rows_sd_beta(out);
+        case TTX_F64_F32: return beta0 ? moved_rows_ds_beta0(out) : moved_rows_ds_beta(out);
+        case TTX_C32_C64: return beta0 ? moved_rows_cz_beta0(out) : moved_rows_cz_beta(out);
+        case TTX_C64_C32: return beta0 ? moved_rows_zc_beta0(out) : moved_rows_zc_beta(out);
+        default: return 0;
     }
 }
-int preserved_rows(int dtype, bool beta0, const LauncherRow** out);
+int preserved_rows(int code, bool beta0, const LauncherRow** out);
 
 struct StagedRow {
     int n0_max, tx, ty;
     TileLaunchFn fn;
 };
-int staged_rows(int dtype, bool beta0, const StagedRow** out);
+int staged_rows(int code, bool beta0, const StagedRow** out);
 
-// The dense-tile kernel for a dtype and beta class, and the workgroups that
-// fill the device with it (its launches loop over the tiles).
-TileLaunchFn dense_launcher(int dtype, bool beta0);
-uint32_t dense_grid(int dtype, bool beta0);
+// The dense-tile kernel for a data-type code and beta class, and the
+// workgroups that fill the device with it (its launches loop over the tiles).
+TileLaunchFn dense_launcher(int code, bool beta0);
+uint32_t dense_grid(int code, bool beta0);
 
 }  // namespace ttx

@@ -352,12 +352,11 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
     if (!r.arena_out) {
         st = check_pointers(r.p, r.A, r.Bin, r.Bout, r.beta0);
         if (st != TTX_OK) return st;
-    } else if (r.p.family != TTX_FAMILY_EMPTY && (!r.A || reinterpret_cast<uintptr_t>(r.A) % elem_bytes(r.p.dtype))) {
+    } else if (r.p.family != TTX_FAMILY_EMPTY && (!r.A || reinterpret_cast<uintptr_t>(r.A) % elem_bytes(r.p.dtype_a))) {
         return fail(TTX_EINVAL, "A must be a non-NULL, element-aligned device pointer");
     }
-    const int64_t es = elem_bytes(r.p.dtype);
     r.out_bytes = r.p.family == TTX_FAMILY_EMPTY ? 0 : r.p.extent_b;
-    r.bytes = r.p.elements * es * (r.beta0 ? 2 : 3);
+    r.bytes = r.p.elements * (elem_bytes(r.p.dtype_a) + elem_bytes(r.p.dtype) * (r.beta0 ? 1 : 2));
     // HBM the request occupies while admitted: its output region plus the
     // tensors it reads (inputs may be shared with other requests; counting
     // them keeps the bound conservative)

@@ -150,6 +150,28 @@ __device__ __forceinline__ vec_t<T, N> epilogue(const vec_t<T, N>& a, const vec_
     }
 }
 
+// Mixed precision: an A element (type S) converted to B's type T (widening
+// exact, narrowing to nearest, part by part for complex elements).
+template <typename T, typename S>
+__device__ __forceinline__ T conv(const S& x) {
+    if constexpr (std::is_same<T, S>::value)
+        return x;
+    else if constexpr (IsComplex<T>::value)
+        return T{decltype(T::re)(x.re), decltype(T::im)(x.im)};
+    else
+        return T(x);
+}
+
+template <typename T, typename S, int V>
+__device__ __forceinline__ vec_t<T, V> conv_vec(const vec_t<S, V>& v) {
+    if constexpr (std::is_same<T, S>::value)
+        return v;
+    else if constexpr (V == 1)
+        return conv<T, S>(v);
+    else
+        return __builtin_convertvector(v, vec_t<T, V>);
+}
+
 // XCD-aware tile mapping.  Workgroups are dispatched round-robin over the
 // 8 XCDs of an MI355X, each with its own L2.  This bijection on [0, G) gives
 // XCD x the consecutive ids [start(x), start(x) + count(x)), so that tiles
@@ -216,33 +238,33 @@ constexpr int pow2_ceil(int x) {
 // VA / VB are the vector widths along x in A and along y in B (VA > 1
 // implies sAa == 1, VB > 1 implies sBb == 1).  The LDS tile has TB rows of
 // TA + 1 elements.
-template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T>
 struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
     static constexpr int NT = kThreads, LDR = TA + 1;
-    __device__ static int ext_a(const TileArgs<T>&) { return TA; }
-    __device__ static int ext_b(const TileArgs<T>&) { return TB; }
-    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T>&) {}
+    __device__ static int ext_a(const TileArgs<T, S>&) { return TA; }
+    __device__ static int ext_b(const TileArgs<T, S>&) { return TB; }
+    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
     // A side: columns (fixed y) of TA elements along x
     static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
     // B side: rows (fixed x) of TB elements along y
     static constexpr int LB = TB / VB, PB = pow2_ceil(LB), RB = NT / PB, NB = (TA + RB - 1) / RB;
     static_assert(PA <= NT && PB <= NT, "tile edge too long for the workgroup");
 
-    vec_t<T, VA> ra[NA];
+    vec_t<S, VA> ra[NA];
     vec_t<T, VB> rb[NB];
     vec_t<T, VB> out[NB];
 
-    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int xa = (tid % PA) * VA, ya = tid / PA;
         const bool live_a = (tid % PA) < LA && xa < c.ea;
-        const T* pa = a.A + c.oa + int64_t(xa) * a.sAa;
+        const S* pa = a.A + c.oa + int64_t(xa) * a.sAa;
 #pragma unroll
         for (int i = 0; i < NA; ++i)
-            if (live_a && ya + i * RA < c.eb) ra[i] = ld<T, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
+            if (live_a && ya + i * RA < c.eb) ra[i] = ld<S, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
         if constexpr (!BETA0) {
             const int yb = (tid % PB) * VB, xb = tid / PB;
             const bool live_b = (tid % PB) < LB && yb < c.eb;
@@ -254,7 +276,7 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int xa = (tid % PA) * VA, ya = tid / PA;
         if ((tid % PA) >= LA) return;
@@ -263,12 +285,12 @@ struct MovedTile {
             const int y = ya + i * RA;
             if (y < TB) {
 #pragma unroll
-                for (int j = 0; j < VA; ++j) lds[y * LDR + xa + j] = lane<T, VA>(ra[i], j);
+                for (int j = 0; j < VA; ++j) lds[y * LDR + xa + j] = conv<T, S>(lane<S, VA>(ra[i], j));
             }
         }
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                              const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
@@ -285,7 +307,7 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
@@ -299,7 +321,7 @@ struct MovedTile {
     }
 
     // from_lds and store in one pass (no tile held in registers in between)
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
@@ -323,23 +345,23 @@ struct MovedTile {
 // One preserved-family tile: rows of ea elements contiguous in A and B.
 // Row y < eb starts at A[oa + y*sAb] and B[ob + y*sBb]; element x of a row is
 // at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).  No LDS.
-template <typename T, bool BETA0, int TA, int TR, int V>
+template <typename T, bool BETA0, int TA, int TR, int V, typename S = T>
 struct PreservedTile {
     static constexpr bool kUsesLds = false;
     static constexpr int kTA = TA, kTB = TR;
     static constexpr int NT = kThreads;
-    __device__ static int ext_a(const TileArgs<T>&) { return TA; }
-    __device__ static int ext_b(const TileArgs<T>&) { return TR; }
-    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T>&) {}
+    __device__ static int ext_a(const TileArgs<T, S>&) { return TA; }
+    __device__ static int ext_b(const TileArgs<T, S>&) { return TR; }
+    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
     static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
 
-    vec_t<T, V> ra[N];
+    vec_t<S, V> ra[N];
     vec_t<T, V> rb[N];
     vec_t<T, V> out[N];
 
-    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -348,18 +370,18 @@ struct PreservedTile {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             if (live && y0 + i * R < c.eb) {
-                ra[i] = ld<T, V>(a.A + off_a + i * int64_t(R) * a.sAb);
+                ra[i] = ld<S, V>(a.A + off_a + i * int64_t(R) * a.sAb);
                 if constexpr (!BETA0) rb[i] = ld<T, V>(a.Bsrc + off_b + i * int64_t(R) * a.sBb);
             }
         }
     }
 
-    __device__ __forceinline__ void finish(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void finish(const TileArgs<T, S>& a, const TileCoord& c) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) out[i] = epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta);
+        for (int i = 0; i < N; ++i) out[i] = epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta);
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -371,7 +393,7 @@ struct PreservedTile {
     }
 
     // finish and store in one pass
-    __device__ __forceinline__ void finish_store(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void finish_store(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -381,7 +403,7 @@ struct PreservedTile {
         for (int i = 0; i < N; ++i)
             if (live && y0 + i * R < c.eb)
                 st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
-                         epilogue<T, V, BETA0>(ra[i], rb[i], a.alpha, a.beta), nt);
+                         epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta), nt);
     }
 };
 
@@ -393,30 +415,30 @@ struct PreservedTile {
 //   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
 // A is read in runs of n0*TX elements and B written in runs of n0*TY; the
 // tile passes through LDS as [y][x][i] (row length TX*N0 + 1).
-template <typename T, bool BETA0, int N0, int TX, int TY>
+template <typename T, bool BETA0, int N0, int TX, int TY, typename S = T>
 struct StagedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TX, kTB = TY;
     static constexpr int NT = kThreads, LDR = TX * N0 + 1;
-    __device__ static int ext_a(const TileArgs<T>&) { return TX; }
-    __device__ static int ext_b(const TileArgs<T>&) { return TY; }
-    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T>&) {}
+    __device__ static int ext_a(const TileArgs<T, S>&) { return TX; }
+    __device__ static int ext_b(const TileArgs<T, S>&) { return TY; }
+    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
+    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
     static constexpr int PA = N0 * TX, PB = N0 * TY;
     static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
     static_assert((N0 & (N0 - 1)) == 0 && (PA & (PA - 1)) == 0 && (PB & (PB - 1)) == 0, "powers of two");
     static_assert(PA * TY % NT == 0, "whole passes");
 
-    T ra[NA];
+    S ra[NA];
     T rb[NB];
     T out[NB];
     int n0_ = 0;
 
-    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         n0_ = n0;
-        const T* A0 = a.A + c.oa;
+        const S* A0 = a.A + c.oa;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * NT, r = e % PA, y = e / PA;
@@ -435,17 +457,17 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * NT, r = e % PA, y = e / PA;
             const int iv = r % N0, x = r / N0;
-            if (iv < n0_) lds[y * LDR + x * N0 + iv] = ra[i];
+            if (iv < n0_) lds[y * LDR + x * N0 + iv] = conv<T, S>(ra[i]);
         }
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                              const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
 #pragma unroll
@@ -457,7 +479,7 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
@@ -471,7 +493,7 @@ struct StagedTile {
     }
 
     // from_lds and store in one pass
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         const bool nt = a.flags & KF_NT_STORE;
@@ -500,16 +522,16 @@ struct StagedTile {
 // order (i, y, x, z: runs of runB), so that both sides run along their
 // contiguous index without padding lanes to a power of two.  The tile passes
 // through LDS as [z][y][x][i], rows of ldr >= runA elements (odd when possible).
-template <typename T, bool BETA0, int CAP>
+template <typename T, bool BETA0, int CAP, typename S = T>
 struct DenseTile {
     static constexpr bool kUsesLds = true;
     static constexpr int NT = kThreads, NS = CAP / NT;
     static_assert(CAP % NT == 0 && CAP <= 1024, "whole passes; slot coordinates packed in 11+11+10 bits");
-    __device__ static int ext_a(const TileArgs<T>& a) { return a.tx; }
-    __device__ static int ext_b(const TileArgs<T>& a) { return a.ty; }
-    __device__ static int ext_c(const TileArgs<T>& a) { return a.tz; }
+    __device__ static int ext_a(const TileArgs<T, S>& a) { return a.tx; }
+    __device__ static int ext_b(const TileArgs<T, S>& a) { return a.ty; }
+    __device__ static int ext_c(const TileArgs<T, S>& a) { return a.tz; }
 
-    T ra[NS];
+    S ra[NS];
     T rb[NS];
     T out[NS];
     // Per-slot constants (the same for every tile of a problem): offsets
@@ -520,7 +542,7 @@ struct DenseTile {
     uint32_t la[NS], lb[NS];
     uint32_t pa[NS], pb[NS];
 
-    __device__ __forceinline__ void init(const TileArgs<T>& a) {
+    __device__ __forceinline__ void init(const TileArgs<T, S>& a) {
         const uint32_t tid = threadIdx.x;
         const uint32_t count = a.planeA * uint32_t(a.tz);
         const int64_t ya = a.gB.ng == 1 ? a.gB.stride[0] : 0;   // A stride of y when linear
@@ -555,16 +577,16 @@ struct DenseTile {
         return (p & 2047u) < uint32_t(c.ea) && ((p >> 11) & 2047u) < uint32_t(c.eb) && (p >> 22) < uint32_t(c.ez);
     }
     // A and B addresses of slot s in tile c
-    __device__ __forceinline__ const T* a_ptr(const TileArgs<T>& a, const TileCoord& c, int s) const {
+    __device__ __forceinline__ const S* a_ptr(const TileArgs<T, S>& a, const TileCoord& c, int s) const {
         if (a.gB.ng == 1) return a.A + (c.oa + c.y0 * a.gB.stride[0]) + relA[s];
         return a.A + c.oa + relA[s] + a.gB.offset(c.y0 + ((pa[s] >> 11) & 2047u));
     }
-    __device__ __forceinline__ int64_t b_off(const TileArgs<T>& a, const TileCoord& c, int s) const {
+    __device__ __forceinline__ int64_t b_off(const TileArgs<T, S>& a, const TileCoord& c, int s) const {
         if (a.gA.ng == 1) return c.ob + c.x0 * a.gA.stride[0] + relB[s];
         return c.ob + relB[s] + a.gA.offset(c.x0 + (pb[s] & 2047u));
     }
 
-    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pa[s])) ra[s] = *a_ptr(a, c, s);
@@ -575,27 +597,27 @@ struct DenseTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T>&, const TileCoord& c) {
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (inside(c, pa[s])) lds[la[s]] = ra[s];
+            if (inside(c, pa[s])) lds[la[s]] = conv<T, S>(ra[s]);
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                              const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pb[s])) out[s] = epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta);
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pb[s])) st<T, 1>(a.Bdst + b_off(a, c, s), out[s], nt);
     }
 
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T>& a,
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
                                                const TileCoord& c) {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
@@ -660,8 +682,8 @@ struct FlatTile {
 // this holds two tiles' data in registers at once, so it is used where the
 // register budget allows.  Every thread of the workgroup runs the same trip
 // count (t, end, step are uniform), so the barriers are reached by all.
-template <class Tile, bool PIPE, typename T>
-__device__ __forceinline__ void tile_loop(T* __restrict__ lds, const TileArgs<T>& a, uint32_t t,
+template <class Tile, bool PIPE, typename T, typename Args>
+__device__ __forceinline__ void tile_loop(T* __restrict__ lds, const Args& a, uint32_t t,
                                           uint32_t end, uint32_t step) {
     Tile tile;
     tile.init(a);
@@ -748,12 +770,53 @@ void k_staged(TileArgs<T> a) {
     if (first < a.g.ntiles) tile_loop<StagedTile<T, BETA0, N0, TX, TY>, false>(lds, a, first, a.g.ntiles, G);
 }
 
+// Mixed precision (A of type S, B of type T): the same tiles, converting
+// A's elements to T as they are loaded.
+template <typename T, typename S, bool BETA0, int TA, int TB, int VA, int VB>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
+void k_moved_x(TileArgs<T, S> a) {
+    __shared__ T lds[TB * (TA + 1)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles)
+        tile_loop<MovedTile<T, BETA0, TA, TB, VA, VB, S>, false>(lds, a, first, a.g.ntiles, G);
+}
+
+template <typename T, typename S, bool BETA0, int TA, int TR, int V>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
+void k_preserved_x(TileArgs<T, S> a) {
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles)
+        tile_loop<PreservedTile<T, BETA0, TA, TR, V, S>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
+}
+
+template <typename T, typename S, bool BETA0, int CAP>
+__global__ __launch_bounds__(kThreads) void k_dense_x(TileArgs<T, S> a) {
+    __shared__ T lds[dense_lds_elems(CAP)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP, S>, true>(lds, a, first, a.g.ntiles, G);
+}
+
+template <typename T, typename S, bool BETA0, int N0, int TX, int TY>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_staged_x(TileArgs<T, S> a) {
+    __shared__ T lds[TY * (TX * N0 + 1)];
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles) tile_loop<StagedTile<T, BETA0, N0, TX, TY, S>, false>(lds, a, first, a.g.ntiles, G);
+}
+
 // Flat: one index of n elements with strides sa, sb.  The vector path
 // (contiguous, aligned) moves 4 vectors per thread per iteration; the
-// remaining n % V elements are handled one per thread.
-template <typename T, bool BETA0>
-__global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
-    constexpr int V = kVec<T>;
+// remaining n % V elements are handled one per thread.  V counts elements
+// of both A and B (the smaller of their 16-byte widths).
+template <typename T, typename S, bool BETA0>
+__device__ __forceinline__ void flat_body(const FlatArgs<T, S>& a) {
+    constexpr int V = kVec<T> < kVec<S> ? kVec<T> : kVec<S>;
     constexpr int U = 4;
     const bool nt = a.flags & KF_NT_STORE;
     const int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x;
@@ -761,34 +824,47 @@ __global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
     if (a.flags & KF_VEC_A) {
         const int64_t nv = a.n / V;
         for (int64_t base = gid; base < nv; base += G * U) {
-            vec_t<T, V> va[U], vb[U];
+            vec_t<S, V> va[U];
+            vec_t<T, V> vb[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t i = base + u * G;
                 if (i < nv) {
-                    va[u] = ld<T, V>(a.A + i * V);
+                    va[u] = ld<S, V>(a.A + i * V);
                     if constexpr (!BETA0) vb[u] = ld<T, V>(a.Bsrc + i * V);
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t i = base + u * G;
-                if (i < nv) st<T, V>(a.Bdst + i * V, epilogue<T, V, BETA0>(va[u], vb[u], a.alpha, a.beta), nt);
+                if (i < nv)
+                    st<T, V>(a.Bdst + i * V, epilogue<T, V, BETA0>(conv_vec<T, S, V>(va[u]), vb[u], a.alpha, a.beta),
+                             nt);
             }
         }
         const int64_t i = nv * V + gid;
         if (i < a.n) {
             T b{};
             if constexpr (!BETA0) b = a.Bsrc[i];
-            a.Bdst[i] = epilogue<T, 1, BETA0>(a.A[i], b, a.alpha, a.beta);
+            a.Bdst[i] = epilogue<T, 1, BETA0>(conv<T, S>(a.A[i]), b, a.alpha, a.beta);
         }
         return;
     }
     for (int64_t i = gid; i < a.n; i += G) {
         T b{};
         if constexpr (!BETA0) b = a.Bsrc[i * a.sb];
-        a.Bdst[i * a.sb] = epilogue<T, 1, BETA0>(a.A[i * a.sa], b, a.alpha, a.beta);
+        a.Bdst[i * a.sb] = epilogue<T, 1, BETA0>(conv<T, S>(a.A[i * a.sa]), b, a.alpha, a.beta);
     }
+}
+
+template <typename T, bool BETA0>
+__global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
+    flat_body<T, T, BETA0>(a);
+}
+
+template <typename T, typename S, bool BETA0>
+__global__ __launch_bounds__(kThreads) void k_flat_x(FlatArgs<T, S> a) {
+    flat_body<T, S, BETA0>(a);
 }
 
 }  // namespace ttx

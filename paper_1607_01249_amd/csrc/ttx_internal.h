@@ -23,7 +23,17 @@ struct alignas(16) cf64 {
     double re, im;
 };
 
-inline bool dtype_valid(int dtype) { return dtype >= TTX_F32 && dtype <= TTX_C64; }
+// A data-type code (ttx_dtype) names the element types of A and B; they
+// differ for the mixed-precision codes.
+inline bool dtype_valid(int code) { return code >= TTX_F32 && code <= TTX_C64_C32; }
+inline int dtype_b_of(int code) {
+    static const int b[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F64, TTX_F32, TTX_C64, TTX_C32};
+    return b[code];
+}
+inline int dtype_a_of(int code) {
+    static const int a[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F32, TTX_F64, TTX_C32, TTX_C64};
+    return a[code];
+}
 inline bool dtype_complex(int dtype) { return dtype == TTX_C32 || dtype == TTX_C64; }
 inline int elem_bytes(int dtype) {
     return dtype == TTX_F32 ? 4 : dtype == TTX_F64 ? 8 : dtype == TTX_C32 ? 8 : 16;
@@ -150,18 +160,20 @@ struct TileArgsHost {
     FastDiv dvPA, dvPB;
 };
 
-template <typename T>
+// T: B's element type (the arithmetic and LDS type); S: A's (converted to T
+// on load when the precisions differ).
+template <typename T, typename S = T>
 struct TileArgs : TileArgsHost {
-    const T* A;
+    const S* A;
     const T* Bsrc;      // read when beta != 0
     T* Bdst;
     T alpha, beta;
     int flags;
 };
 
-template <typename T>
+template <typename T, typename S = T>
 struct FlatArgs {
-    const T* A;
+    const S* A;
     const T* Bsrc;
     T* Bdst;
     T alpha, beta;
@@ -178,7 +190,9 @@ struct Dim {
 };
 
 struct Problem {
-    int dtype = 0;
+    int dtype = 0;              // B's element type (TTX_F32 .. TTX_C64)
+    int dtype_a = 0;            // A's element type
+    int code = 0;               // the ttx_dtype code the problem was made with
     int n = 0;                  // merged rank
     Dim dim[kMaxDims];
     int perm[kMaxDims];         // merged gather perm: B position k holds merged dim perm[k]

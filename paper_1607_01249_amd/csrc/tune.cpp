@@ -39,7 +39,7 @@ uint64_t table_generation() { return g_table_gen.load(); }
 // problem shares a solution (Sec. 2.1: lookup happens after merging).
 static std::string table_key(const Problem& p, bool beta0) {
     std::ostringstream os;
-    os << "d" << p.dtype << ":b" << (beta0 ? 1 : 0) << ":n" << p.n << ":s";
+    os << "d" << p.code << ":b" << (beta0 ? 1 : 0) << ":n" << p.n << ":s";
     for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.dim[i].size;
     os << ":p";
     for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.perm[i];

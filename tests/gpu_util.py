@@ -10,8 +10,11 @@ REAL_OF = {C32: F32, C64: F64}
 _CODES = {F32: ttx.F32, F64: ttx.F64, C32: ttx.C32, C64: ttx.C64}
 
 
-def dtype_code(dtype):
-    return _CODES[np.dtype(dtype)]
+def dtype_code(dtype, dtype_b=None):
+    """The ttx data-type code for A's dtype (and B's, when it differs)."""
+    a = _CODES[np.dtype(dtype)]
+    b = a if dtype_b is None else _CODES[np.dtype(dtype_b)]
+    return ttx.CODE_OF[(a, b)]
 
 
 def _torch_dtype(dtype):
@@ -46,11 +49,12 @@ def gpu_transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, pad
     cx = isinstance(alpha, complex) or isinstance(beta, complex)
     if plan_config is None:
         run = ttx.ttx_transpose_c if cx else ttx.ttx_transpose
-        run(dtype_code(A.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa, beta, pb, stream)
+        run(dtype_code(A.dtype, B.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa, beta, pb,
+            stream)
     else:
-        plan = ttx.ttx_plan_create(dtype_code(A.dtype), perm, size, outer_a, outer_b)
+        plan = ttx.ttx_plan_create(dtype_code(A.dtype, B.dtype), perm, size, outer_a, outer_b)
         try:
-            beta0 = A.dtype.type(beta) == 0
+            beta0 = B.dtype.type(beta) == 0
             ttx.ttx_plan_set_config(plan, beta0, plan_config)
             if cx:
                 ttx.ttx_plan_execute_c(plan, alpha, pa, beta, pb, pb, stream)

@@ -57,7 +57,7 @@ def test_status_strings():
 
 # -- validation: the library's synchronous checks agree with the oracle's -------------
 INVALID = [
-    dict(dtype=4, perm=(0, 1), size=(2, 3)),
+    dict(dtype=8, perm=(0, 1), size=(2, 3)),
     dict(dtype=0, perm=(0, 0), size=(2, 3)),
     dict(dtype=0, perm=(0, 2), size=(2, 3)),
     dict(dtype=0, perm=(1, 0), size=(2, -1)),
@@ -442,4 +442,53 @@ def test_complex_argument_errors_need_no_gpu():
     # oracle and library agree on the dtype codes
     for code in (ttx.C32, ttx.C64):
         assert oracle.check(code, perm, size) == oracle.OK
-    assert oracle.check(4, perm, size) != oracle.OK
+    assert oracle.check(8, perm, size) != oracle.OK
+
+
+# -- mixed precision (sd, ds, cz, zc) ---------------------------------------------------------
+MIXED = [(ttx.F32_F64, ttx.F64, "double, float"), (ttx.F64_F32, ttx.F32, "float, double"),
+         (ttx.C32_C64, ttx.C64, "ttx::cf64, ttx::cf32"), (ttx.C64_C32, ttx.C32, "ttx::cf32, ttx::cf64")]
+
+
+@pytest.mark.parametrize("code,b_type,names", MIXED)
+@pytest.mark.parametrize("perm,size", COMPLEX_SHAPES)
+def test_mixed_plans_use_b_type_menus(code, b_type, names, perm, size):
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        info = ttx.ttx_plan_describe(plan)
+        assert info["dtype"] == code
+        name = ttx.ttx_plan_kernel_name(plan, 1, 1 << 40, 1 << 41)
+        assert "_x<" + names + "," in name, name
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    got, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    same, _ = ttx.ttx_tune_candidates(b_type, perm, size, max_candidates=-1, cap=200000)
+    shape = lambda c: (c.family, c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c, c.flags & ttx.CFG_DENSE)
+    assert {shape(c) for c in got} == {shape(c) for c in same}
+
+
+def test_mixed_argument_errors_need_no_gpu():
+    perm, size = (1, 0), (4, 5)   # 20 elements
+    big = 1 << 40
+    cases = [(ttx.F32_F64, big, big + 4096 + 4, ttx.EINVAL),    # B (FP64) not 8-byte aligned
+             (ttx.F64_F32, big + 4, big + 4096, ttx.EINVAL),    # A (FP64) not 8-byte aligned
+             (ttx.C32_C64, big + 8, big + 4096 + 8, ttx.EINVAL),  # B (double complex) needs 16
+             (ttx.F32_F64, big, big + 72, ttx.EOVERLAP),        # A spans 80 bytes (FP32)
+             (ttx.F64_F32, big, big + 80, ttx.EOVERLAP)]        # A spans 160 bytes (FP64)
+    for code, a, b, status in cases:
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_transpose(code, 2, perm, size, None, None, 1.0, a, 0.0, b)
+        assert e.value.status == status, (code, a, b)
+    with pytest.raises(ttx.TTXError) as e:   # complex scalars for a real pair
+        ttx.ttx_transpose_c(ttx.F32_F64, 2, perm, size, None, None, 1j, big, 0.0, big + 4096)
+    assert e.value.status == ttx.EINVAL
+    for a, b in ((0, 1), (1, 0), (2, 3), (3, 2)):
+        assert oracle.check(b, perm, size, dtype_a=a) == oracle.OK
+
+
+@pytest.mark.parametrize("code", [ttx.C32, ttx.C64, ttx.F32_F64, ttx.C64_C32])
+def test_batch_takes_real_one_type_problems_only(code):
+    q = ttx.make_problem(code, (1, 0), (4, 5), 1.0, 1 << 40, 0.0, 1 << 41)
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_batch_plan([q])
+    assert e.value.status == ttx.EUNSUPPORTED
