@@ -74,7 +74,8 @@ def parse_args():
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
-    ap.add_argument("--no-complex", action="store_true", help="skip the complex (c, z) cases")
+    ap.add_argument("--no-types", action="store_true",
+                    help="skip the complex (c, z) and mixed-precision (sd, ds, cz, zc) cases")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="Poisson arrival rate (req/s)")
     ap.add_argument("--profile-run", action="store_true",
@@ -377,20 +378,23 @@ def bench_batched(torch, ttx, reps=20, tune=True):
                 speedup=round(pc_med / b_med, 2))
 
 
-def bench_complex(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False):
-    """Per-call complex transpositions (c and z types, complex alpha and beta,
-    beta != 0), about 200 MiB per tensor, one case resident at a time: the
-    median time of `reps` launches per case (3S bytes each).  Launches rotate
-    over three (A, B) pairs so that each one starts with the data of the two
-    before it in the 256 MiB Infinity Cache, not its own."""
+def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False):
+    """Per-call transpositions of the other element types: complex (c and z,
+    complex alpha and beta) about 200 MiB per tensor, and mixed precision
+    (sd, ds, cz, zc), beta != 0, one case resident at a time: the median
+    time of `reps` launches per case (bytes: read A, read and write B).
+    Launches rotate over three (A, B) pairs so that each one starts with the
+    data of the two before it in the 256 MiB Infinity Cache, not its own."""
     import workloads
     out = []
-    tdt = {workloads.C32: torch.complex64, workloads.C64: torch.complex128}
-    codes = {workloads.C32: ttx.C32, workloads.C64: ttx.C64}
+    tdt = {workloads.F32: torch.float32, workloads.F64: torch.float64,
+           workloads.C32: torch.complex64, workloads.C64: torch.complex128}
+    tcode = {workloads.F32: ttx.F32, workloads.F64: ttx.F64, workloads.C32: ttx.C32,
+             workloads.C64: ttx.C64}
     tuned = 0
-    for c in workloads.complex_cases():
+    for c in workloads.complex_cases() + workloads.mixed_cases():
         n = workloads.elements(c["size"])
-        code = codes[c["dtype"]]
+        code = ttx.CODE_OF[(tcode[c["dtype_a"]], tcode[c["dtype"]])]
         plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
         if not ttx.ttx_plan_describe(plan)["config_from_table"][0]:
             if profile:
@@ -402,11 +406,12 @@ def bench_complex(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=Fal
             plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
             tuned += 1
         pairs = []
+        real = lambda t: torch.view_as_real(t) if t.is_complex() else t
         for k in range(3):
-            A = torch.empty(n, dtype=tdt[c["dtype"]], device="cuda")
-            B = torch.empty_like(A)
-            fill_uniform(torch, torch.view_as_real(A), c["seed_a"] + 100 * k)
-            fill_uniform(torch, torch.view_as_real(B), c["seed_b"] + 100 * k)
+            A = torch.empty(n, dtype=tdt[c["dtype_a"]], device="cuda")
+            B = torch.empty(n, dtype=tdt[c["dtype"]], device="cuda")
+            fill_uniform(torch, real(A), c["seed_a"] + 100 * k)
+            fill_uniform(torch, real(B), c["seed_b"] + 100 * k)
             pairs.append((A, B))
         kernel = ttx.ttx_plan_kernel_name(plan, 1.0, pairs[0][0].data_ptr(), pairs[0][1].data_ptr())
         state = {"i": 0}
@@ -421,7 +426,7 @@ def bench_complex(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=Fal
             run()
         _, tmed = time_events(torch, run, reps)
         ttx.ttx_plan_destroy(plan)
-        nbytes = 3 * n * c["dtype"].itemsize
+        nbytes = n * (c["dtype_a"].itemsize + 2 * c["dtype"].itemsize)
         gbps = nbytes / tmed / 1e9
         out.append(dict(case=c["name"], GBps=round(gbps, 1), pct_of_d2d=round(100 * gbps / d2d, 1),
                         us=round(tmed * 1e6, 1), kernel=kernel))
@@ -702,9 +707,9 @@ def main():
         served = bench_served(torch, ttx, args.serve_seconds, args.serve_rate)
 
     cplx = None
-    if not args.no_complex and not args.profile_run:
-        log("complex cases")
-        cplx = bench_complex(torch, ttx, d2d, stream, args.tune_candidates)
+    if not args.no_types and not args.profile_run:
+        log("complex and mixed-precision cases")
+        cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates)
         if args.save_table:
             ttx.ttx_tune_table_save(args.save_table)
 
@@ -726,7 +731,7 @@ def main():
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
-        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served, complex=cplx,
+        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served, other_types=cplx,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,

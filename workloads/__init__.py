@@ -93,7 +93,7 @@ def complex_shape(rank, dtype):
 
 
 def complex_cases():
-    """Large complex cases (complex alpha and beta, beta != 0)."""
+    """Large complex cases (complex alpha and beta, beta != 0); A and B of one type."""
     out = []
     case = 0
     for rank in ("4d", "5d", "6d"):
@@ -101,10 +101,30 @@ def complex_cases():
             for perm in COMPLEX_PERMS[rank]:
                 out.append(dict(name="%s_%s_p%s" % (rank, "c32" if dtype == C32 else "c64",
                                                    "".join(map(str, perm))),
-                                dtype=dtype, size=complex_shape(rank, dtype), perm=perm,
+                                dtype_a=dtype, dtype=dtype, size=complex_shape(rank, dtype), perm=perm,
                                 alpha=COMPLEX_ALPHA, beta=COMPLEX_BETA,
                                 seed_a=5000 + case, seed_b=6000 + case))
                 case += 1
+    return out
+
+
+# -- mixed precision (Table 1 "sd", "ds", "cz", "zc"): A's type, then B's -------------
+MIXED_PAIRS = {"sd": (F32, F64), "ds": (F64, F32), "cz": (C32, C64), "zc": (C64, C32)}
+MIXED_PERMS = [(3, 2, 1, 0), (2, 0, 3, 1), (0, 2, 1, 3)]
+
+
+def mixed_cases():
+    """Large 4D mixed-precision cases: the double (complex) side about 200 MiB."""
+    out = []
+    case = 0
+    for name, (da, db) in MIXED_PAIRS.items():
+        size = (160, 160, 32, 32) if da in (F32, F64) else (160, 160, 32, 16)
+        cx = db in (C32, C64)
+        for perm in MIXED_PERMS:
+            out.append(dict(name="4d_%s_p%s" % (name, "".join(map(str, perm))), dtype_a=da, dtype=db,
+                            size=size, perm=perm, alpha=COMPLEX_ALPHA if cx else 1.3,
+                            beta=COMPLEX_BETA if cx else 0.7, seed_a=9000 + case, seed_b=9500 + case))
+            case += 1
     return out
 
 
