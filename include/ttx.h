@@ -108,6 +108,14 @@ typedef enum ttx_family {
                                   tile_b are run-time extents, rows of the shared stride-1 index
                                   (PRESERVED) are packed without padding, at most 1024 elements
                                   per tile, element-wise accesses */
+#define TTX_CFG_WIDE 8         /* with TTX_CFG_DENSE, PRESERVED, FP32 or FP64 only: the kept
+                                  stride-1 rows are moved in whole 16-byte units (8-byte units
+                                  for FP32 rows that are not a multiple of 4 elements long):
+                                  the row length and every other stride must be multiples of
+                                  the unit, the row at least two units long; tile_a, tile_b,
+                                  tile_c and the capacity count rows of units (512 units of 16
+                                  bytes, 1024 of 8).  Pointers not aligned to the unit run an
+                                  element-wise configuration instead. */
 
 /* One implementation candidate (Sec. 2.2: blocking and loop order).
  *   tile_a  : tile extent along A's stride-1 index (merged index 0);

@@ -324,6 +324,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     const bool vec = vector_ok(p, A, beta0 ? nullptr : Bsrc, Bdst);
     ttx_config c = forced ? *forced : batch_default(p, vec);
     if (c.family != p.family) return fail(TTX_EINVAL, "config family does not match the problem");
+    if (config_is_wide(c)) return fail(TTX_EINVAL, "whole-unit rows are for per-call launches only");
     c.flags &= ~TTX_CFG_XCD_SWIZZLE;  // tile ids are global in the persistent launch
     // the menu entry for a config (-1: none); flat configs get their tile here
     auto resolve = [&](ttx_config& k) -> int {
@@ -405,7 +406,7 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     std::vector<int> eligible, kind;
     for (int i = 0; i < na; ++i) {
         const ttx_config& c = all[i];
-        if (c.flags & TTX_CFG_XCD_SWIZZLE) continue;
+        if (c.flags & (TTX_CFG_XCD_SWIZZLE | TTX_CFG_WIDE)) continue;
         int k = 0;
         if (config_is_dense(c)) {
             if (dense_index(p.dtype) < 0) continue;

@@ -122,10 +122,27 @@ static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0
     return hipErrorInvalidValue;
 }
 
+static bool aligned_to(const void* ptr, uintptr_t n) { return reinterpret_cast<uintptr_t>(ptr) % n == 0; }
+
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream) {
     if (p.family == TTX_FAMILY_EMPTY) return hipSuccess;
+    if (config_is_wide(c)) {
+        // dense tiles over whole units of the kept rows: one element per unit
+        Problem w;
+        if (!widen(p, &w)) return hipErrorInvalidValue;
+        const uintptr_t ub = uintptr_t(elem_bytes(w.dtype));
+        if (!aligned_to(A, ub) || !aligned_to(Bdst, ub) || (Bsrc && !aligned_to(Bsrc, ub)))
+            return launch_tiles(p, default_config_elementwise(p), beta0, A, Bsrc, Bdst, alpha, beta, stream);
+        ttx_config cw = c;
+        cw.flags &= ~TTX_CFG_WIDE;
+        switch (w.code) {
+            case kWideF32x4: return launch_tiled<f32x4, f32x4>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+            case kWideF64x2: return launch_tiled<f64x2, f64x2>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+            default: return launch_tiled<f32x2, f32x2>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+        }
+    }
     return with_types(p.code, [&](auto t, auto s) {
         using T = decltype(t);
         using S = decltype(s);
@@ -137,6 +154,17 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
 std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, const void* Bdst) {
     if (p.family == TTX_FAMILY_EMPTY) return "";
+    if (config_is_wide(c)) {
+        Problem w;
+        const uintptr_t ub = widen(p, &w) ? uintptr_t(elem_bytes(w.dtype)) : 0;
+        if (!ub || !aligned_to(A, ub) || !aligned_to(Bdst, ub) || (Bsrc && !aligned_to(Bsrc, ub)))
+            return kernel_name(p, default_config_elementwise(p), beta0, A, Bsrc, Bdst);
+        static const char* const kWideName[] = {"ttx::f32x4", "ttx::f64x2", "ttx::f32x2"};
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "k_dense<%s, %s, %d>", kWideName[w.dtype - kWideF32x4],
+                      beta0 ? "true" : "false", dense_cap(w.dtype));
+        return buf;
+    }
     static const char* const kTypeName[] = {"float", "double", "ttx::cf32", "ttx::cf64"};
     // the same-type kernels are k_<kind><T, ...>; mixed ones k_<kind>_x<T, S, ...>
     char ts[64];

@@ -1,5 +1,5 @@
 // Dense-tile kernel instantiations (the dense capacity of B's element type,
-// for every data-type code).
+// for every data-type code, and for the whole-unit types of kept rows).
 #include <mutex>
 #include <type_traits>
 
@@ -67,6 +67,15 @@ uint32_t dense_grid(int code, bool beta0) {
             return beta0 ? resident<cf64, cf32, true, TTX_DENSE_CAP_C64>(dev) : resident<cf64, cf32, false, TTX_DENSE_CAP_C64>(dev);
         case TTX_C64_C32:
             return beta0 ? resident<cf32, cf64, true, TTX_DENSE_CAP_C32>(dev) : resident<cf32, cf64, false, TTX_DENSE_CAP_C32>(dev);
+        case kWideF32x4:
+            return beta0 ? resident<f32x4, f32x4, true, TTX_DENSE_CAP_W16>(dev)
+                         : resident<f32x4, f32x4, false, TTX_DENSE_CAP_W16>(dev);
+        case kWideF64x2:
+            return beta0 ? resident<f64x2, f64x2, true, TTX_DENSE_CAP_W16>(dev)
+                         : resident<f64x2, f64x2, false, TTX_DENSE_CAP_W16>(dev);
+        case kWideF32x2:
+            return beta0 ? resident<f32x2, f32x2, true, TTX_DENSE_CAP_W8>(dev)
+                         : resident<f32x2, f32x2, false, TTX_DENSE_CAP_W8>(dev);
         default: return 0;
     }
 }
@@ -89,6 +98,15 @@ TileLaunchFn dense_launcher(int code, bool beta0) {
             return beta0 ? launch_dense<cf64, cf32, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, cf32, false, TTX_DENSE_CAP_C64>;
         case TTX_C64_C32:
             return beta0 ? launch_dense<cf32, cf64, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, cf64, false, TTX_DENSE_CAP_C32>;
+        case kWideF32x4:
+            return beta0 ? launch_dense<f32x4, f32x4, true, TTX_DENSE_CAP_W16>
+                         : launch_dense<f32x4, f32x4, false, TTX_DENSE_CAP_W16>;
+        case kWideF64x2:
+            return beta0 ? launch_dense<f64x2, f64x2, true, TTX_DENSE_CAP_W16>
+                         : launch_dense<f64x2, f64x2, false, TTX_DENSE_CAP_W16>;
+        case kWideF32x2:
+            return beta0 ? launch_dense<f32x2, f32x2, true, TTX_DENSE_CAP_W8>
+                         : launch_dense<f32x2, f32x2, false, TTX_DENSE_CAP_W8>;
         default: return nullptr;
     }
 }

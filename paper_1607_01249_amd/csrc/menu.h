@@ -67,6 +67,9 @@
 #define TTX_DENSE_CAP_F64 1024
 #define TTX_DENSE_CAP_C32 1024
 #define TTX_DENSE_CAP_C64 512
+// and for whole units of kept rows: 16-byte units (8 KiB), 8-byte units (8 KiB)
+#define TTX_DENSE_CAP_W16 512
+#define TTX_DENSE_CAP_W8 1024
 
 // Tile variants compiled into the persistent batched kernel, per dtype:
 // X(index, kind, p1, p2, p3).  For the moved, preserved and flat kinds

@@ -349,6 +349,35 @@ static int dense_z(const Problem& p, const Layout& L, const int* order, int n) {
 
 // ---------------------------------------------------------------------------------------
 // Config validation and the kernel-side grid
+bool widen(const Problem& p, Problem* w) {
+    if (p.family != TTX_FAMILY_PRESERVED || p.dtype != p.dtype_a) return false;
+    if (p.dtype != TTX_F32 && p.dtype != TTX_F64) return false;
+    if (p.dim[0].sa != 1 || p.dim[0].sb != 1) return false;
+    auto fits = [&](int64_t k) {
+        if (p.dim[0].size % k || p.dim[0].size / k < 2) return false;
+        for (int d = 1; d < p.n; ++d)
+            if (p.dim[d].sa % k || p.dim[d].sb % k) return false;
+        return true;
+    };
+    int k = 0, code = 0;
+    if (p.dtype == TTX_F32) {
+        if (fits(4)) k = 4, code = kWideF32x4;
+        else if (fits(2)) k = 2, code = kWideF32x2;
+    } else if (fits(2)) {
+        k = 2, code = kWideF64x2;
+    }
+    if (!k) return false;
+    *w = p;
+    w->dtype = w->dtype_a = w->code = code;
+    w->dim[0].size /= k;
+    for (int d = 1; d < p.n; ++d) {
+        w->dim[d].sa /= k;
+        w->dim[d].sb /= k;
+    }
+    w->elements /= k;
+    return true;
+}
+
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     auto bad = [&](const char* m) {
         if (why) *why = m;
@@ -356,7 +385,15 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     };
     if (c.family != p.family) return bad("config family does not match the problem");
     if (c.threads != kThreads) return bad("threads must be 256");
-    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE)) return bad("unknown flag");
+    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE)) return bad("unknown flag");
+    if (config_is_wide(c)) {
+        if (!config_is_dense(c)) return bad("whole-unit rows are for dense tiles only");
+        Problem w;
+        if (!widen(p, &w)) return bad("the rows cannot be moved in whole units");
+        ttx_config cw = c;
+        cw.flags &= ~TTX_CFG_WIDE;
+        return config_valid(w, cw, why);
+    }
     if (p.family == TTX_FAMILY_EMPTY) return true;
     if (c.n_order != p.n) return bad("order must list every merged index");
     bool seen[kMaxDims] = {};
@@ -408,6 +445,14 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
 }
 
 void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
+    if (config_is_wide(c)) {   // the grid of the problem over whole units
+        Problem w;
+        widen(p, &w);
+        ttx_config cw = c;
+        cw.flags &= ~TTX_CFG_WIDE;
+        build_grid(w, cw, h);
+        return;
+    }
     Layout L;
     make_layout(p, c.group_a, c.group_b, &L);
     TileGrid* g = &h->g;
@@ -556,8 +601,11 @@ static constexpr double kResident = 2048.0;
 // except for 16-byte elements (double complex), which are whole vectors.
 static constexpr double kScalarPenalty = 1.15;
 static double scalar_penalty(const Problem& p) { return elem_bytes(p.dtype) >= 16 ? 1.0 : kScalarPenalty; }
-// Dense tiles also decode every element's coordinates at run time.
+// Dense tiles also decode every element's coordinates at run time; over
+// whole units of kept rows (8 or 16 bytes each) that work is shared by
+// several elements.
 static constexpr double kDensePenalty = 1.3;
+static constexpr double kWideDensePenalty = 1.1;
 
 static double lines(double bytes) { return std::ceil(bytes / kLine) * kLine; }
 
@@ -651,7 +699,8 @@ static double dense_cost(const Problem& p, const Layout& L, int tx, int ty, int 
                 work += cnt * elems;
             }
     if (useful == 0) return 1e30;
-    return kDensePenalty * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
+    const double pen = p.dtype >= kWideF32x4 ? kWideDensePenalty : kDensePenalty;
+    return pen * traffic / useful * (1.0 + 0.25 * (slots / work - 1.0));
 }
 
 // Planes per dense tile worth trying along index z (1 = one plane).
@@ -908,19 +957,31 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
                               make_config(p, shapes[s].ta, shapes[s].tb, o, f, ga, gb));
                 }
             }
-            if (!dense_layout(p, L)) continue;
-            for (const TileShape& d : dense_shapes(p, L)) {
-                ttx_config probe = make_config(p, d.ta, d.tb, orders[0], TTX_CFG_DENSE, ga, gb);
-                if (!config_valid(p, probe, nullptr)) continue;
-                for (const auto& o : orders) {
-                    const int z = dense_z(p, L, o.data(), p.n);
-                    double oc = order_cost(p, L, d.ta, d.tb, o.data(), p.n);
-                    for (int tz : dense_planes(p, L, d.ta, d.tb, z)) {
-                        const double bc = dense_cost(p, L, d.ta, d.tb, tz, z);
-                        for (int f : flag_sets) {
-                            ttx_config c = make_config(p, d.ta, d.tb, o, f | TTX_CFG_DENSE, ga, gb);
-                            c.tile_c = tz;
-                            offer(bc * (1.0 + oc) + flag_cost(f), c);
+        }
+        // dense tiles, over elements and (when the rows allow it) over whole units of the rows
+        Problem w;
+        const bool wide = widen(p, &w);
+        for (int pass = 0; pass < (wide ? 2 : 1); ++pass) {
+            const Problem& q = pass ? w : p;
+            const int extra = pass ? TTX_CFG_WIDE : 0;
+            for (auto [ga, gb] : group_options(q)) {
+                Layout L;
+                make_layout(q, ga, gb, &L);
+                if (!dense_layout(q, L)) continue;
+                auto orders = loop_orders(q, L);
+                for (const TileShape& d : dense_shapes(q, L)) {
+                    ttx_config probe = make_config(q, d.ta, d.tb, orders[0], TTX_CFG_DENSE, ga, gb);
+                    if (!config_valid(q, probe, nullptr)) continue;
+                    for (const auto& o : orders) {
+                        const int z = dense_z(q, L, o.data(), q.n);
+                        double oc = order_cost(q, L, d.ta, d.tb, o.data(), q.n);
+                        for (int tz : dense_planes(q, L, d.ta, d.tb, z)) {
+                            const double bc = dense_cost(q, L, d.ta, d.tb, tz, z);
+                            for (int f : flag_sets) {
+                                ttx_config c = make_config(q, d.ta, d.tb, o, f | TTX_CFG_DENSE | extra, ga, gb);
+                                c.tile_c = tz;
+                                offer(bc * (1.0 + oc) + flag_cost(f), c);
+                            }
                         }
                     }
                 }
@@ -962,7 +1023,7 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
 }
 
 ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
-                               const TileShape* staged, int nstaged, bool dense) {
+                               const TileShape* staged, int nstaged, bool dense, bool wide) {
     ttx_config best;
     std::memset(&best, 0, sizeof(best));
     best.family = p.family;
@@ -1052,13 +1113,61 @@ ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns
             }
         }
     }
+    // dense tiles over whole units of the rows
+    Problem w;
+    if (dense && wide && widen(p, &w)) {
+        for (auto [ga, gb] : group_options(w)) {
+            Layout L;
+            make_layout(w, ga, gb, &L);
+            if (!dense_layout(w, L)) continue;
+            int gi[kMaxDims], ng = 0, tail[kMaxDims], nt = 0;
+            double span[kMaxDims] = {};
+            for (int d = 0; d < w.n; ++d) {
+                if (L.member[d]) {
+                    tail[nt++] = d;
+                    continue;
+                }
+                gi[ng++] = d;
+                double cnt, sA, sB;
+                grid_step(w, L, d, 1, 1, &cnt, &sA, &sB);
+                span[d] = sA + sB;
+            }
+            std::vector<int> o;
+            for (const TileShape& d : dense_shapes(w, L)) {
+                double sp[kMaxDims];
+                for (int k = 0; k < ng; ++k) sp[gi[k]] = span[gi[k]] * (gi[k] == L.a ? d.ta : gi[k] == L.b ? d.tb : 1);
+                o.assign(gi, gi + ng);
+                std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return sp[x] < sp[y]; });
+                o.insert(o.end(), tail, tail + nt);
+                const int z = dense_z(w, L, o.data(), w.n);
+                for (int tz : dense_planes(w, L, d.ta, d.tb, z)) {
+                    const double dc = dense_cost(w, L, d.ta, d.tb, tz, z);
+                    if (dc >= bestc) continue;
+                    ttx_config c = make_config(w, d.ta, d.tb, o, TTX_CFG_DENSE | TTX_CFG_WIDE, ga, gb);
+                    c.tile_c = tz;
+                    if (!config_valid(p, c, nullptr)) continue;
+                    const double cost = dc * (1.0 + order_cost(w, L, d.ta, d.tb, o.data(), w.n));
+                    if (cost < bestc) {
+                        bestc = cost;
+                        best = c;
+                    }
+                }
+            }
+        }
+    }
     return best;
 }
 
 ttx_config default_config(const Problem& p) {
     const TileShape* shapes;
     int ns = tile_menu(p.dtype, p.family, &shapes);
-    return default_config_from(p, shapes, ns, nullptr, -1, true);
+    return default_config_from(p, shapes, ns, nullptr, -1, true, true);
+}
+
+ttx_config default_config_elementwise(const Problem& p) {
+    const TileShape* shapes;
+    int ns = tile_menu(p.dtype, p.family, &shapes);
+    return default_config_from(p, shapes, ns, nullptr, -1, true, false);
 }
 
 }  // namespace ttx

@@ -78,6 +78,18 @@ template <>
 struct RawOf<cf64, 1> {
     using type = double __attribute__((ext_vector_type(2)));
 };
+template <>
+struct RawOf<f32x4, 1> {
+    using type = float __attribute__((ext_vector_type(4)));
+};
+template <>
+struct RawOf<f64x2, 1> {
+    using type = double __attribute__((ext_vector_type(2)));
+};
+template <>
+struct RawOf<f32x2, 1> {
+    using type = float __attribute__((ext_vector_type(2)));
+};
 
 template <typename T>
 constexpr int kVec = 16 / int(sizeof(T));
@@ -127,7 +139,22 @@ __device__ __forceinline__ C cmul(const C& s, const C& x) {
 template <typename T, int N, bool BETA0>
 __device__ __forceinline__ vec_t<T, N> epilogue(const vec_t<T, N>& a, const vec_t<T, N>& b,
                                                 T alpha, T beta) {
-    if constexpr (IsComplex<T>::value) {
+    if constexpr (WideOf<T>::lanes > 0) {
+        // a unit of a kept row: Eqn. 1 on each of its elements
+        static_assert(N == 1, "units are whole vectors");
+        T r;
+#pragma unroll
+        for (int i = 0; i < WideOf<T>::lanes; ++i) {
+            if constexpr (BETA0) {
+                r.v[i] = alpha.v[i] * a.v[i];
+            } else {
+                const auto pa = alpha.v[i] * a.v[i];
+                const auto pb = beta.v[i] * b.v[i];
+                r.v[i] = pa + pb;
+            }
+        }
+        return r;
+    } else if constexpr (IsComplex<T>::value) {
         vec_t<T, N> r;
 #pragma unroll
         for (int j = 0; j < N; ++j) {

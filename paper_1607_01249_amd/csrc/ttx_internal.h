@@ -23,20 +23,60 @@ struct alignas(16) cf64 {
     double re, im;
 };
 
+// Units of a kept row (the internal wide element types).
+struct alignas(16) f32x4 {
+    float v[4];
+};
+struct alignas(16) f64x2 {
+    double v[2];
+};
+struct alignas(8) f32x2 {
+    float v[2];
+};
+template <typename T>
+struct WideOf {
+    static constexpr int lanes = 0;
+};
+template <>
+struct WideOf<f32x4> {
+    static constexpr int lanes = 4;
+    using lane_t = float;
+};
+template <>
+struct WideOf<f64x2> {
+    static constexpr int lanes = 2;
+    using lane_t = double;
+};
+template <>
+struct WideOf<f32x2> {
+    static constexpr int lanes = 2;
+    using lane_t = float;
+};
+
 // A data-type code (ttx_dtype) names the element types of A and B; they
 // differ for the mixed-precision codes.
 inline bool dtype_valid(int code) { return code >= TTX_F32 && code <= TTX_C64_C32; }
+// Internal element types (never accepted from callers): whole units of a
+// kept stride-1 row, moved as one element each (configs with TTX_CFG_WIDE).
+enum : int {
+    kWideF32x4 = 8,   // four FP32 elements (16 bytes)
+    kWideF64x2 = 9,   // two FP64 elements (16 bytes)
+    kWideF32x2 = 10,  // two FP32 elements (8 bytes)
+};
 inline int dtype_b_of(int code) {
-    static const int b[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F64, TTX_F32, TTX_C64, TTX_C32};
+    static const int b[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F64, TTX_F32, TTX_C64, TTX_C32,
+                            kWideF32x4, kWideF64x2, kWideF32x2};
     return b[code];
 }
 inline int dtype_a_of(int code) {
-    static const int a[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F32, TTX_F64, TTX_C32, TTX_C64};
+    static const int a[] = {TTX_F32, TTX_F64, TTX_C32, TTX_C64, TTX_F32, TTX_F64, TTX_C32, TTX_C64,
+                            kWideF32x4, kWideF64x2, kWideF32x2};
     return a[code];
 }
 inline bool dtype_complex(int dtype) { return dtype == TTX_C32 || dtype == TTX_C64; }
 inline int elem_bytes(int dtype) {
-    return dtype == TTX_F32 ? 4 : dtype == TTX_F64 ? 8 : dtype == TTX_C32 ? 8 : 16;
+    static const int e[] = {4, 8, 8, 16, 0, 0, 0, 0, 16, 16, 8};
+    return e[dtype];
 }
 inline const char* dtype_name(int dtype) {
     return dtype == TTX_F32 ? "f32" : dtype == TTX_F64 ? "f64" : dtype == TTX_C32 ? "c32" : "c64";
@@ -54,12 +94,17 @@ struct Scalar {
 // The scalar rounded to the element type's scalar.
 template <typename T>
 inline T scalar_as(const Scalar& s) {
-    if constexpr (std::is_same<T, cf32>::value)
+    if constexpr (std::is_same<T, cf32>::value) {
         return T{float(s.re), float(s.im)};
-    else if constexpr (std::is_same<T, cf64>::value)
+    } else if constexpr (std::is_same<T, cf64>::value) {
         return T{s.re, s.im};
-    else
+    } else if constexpr (WideOf<T>::lanes > 0) {
+        T t;
+        for (int i = 0; i < WideOf<T>::lanes; ++i) t.v[i] = typename WideOf<T>::lane_t(s.re);
+        return t;
+    } else {
         return T(s.re);
+    }
 }
 
 // Division by a run-time invariant 32-bit divisor with a multiply and a
@@ -230,12 +275,15 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why);
 // The heuristic default config (best-ranked candidate).
 ttx_config default_config(const Problem& p);
+// The same without whole-unit rows (for pointers not aligned to the unit).
+ttx_config default_config_elementwise(const Problem& p);
 // The same greedy choice restricted to the given tile shapes; staged tiles
 // (preserved family, short rows) come from `staged` entries packed as
 // {lanes * 65536 + tile_x, tile_y}, or from the whole staged menu when
-// nstaged < 0; dense tiles are considered when `dense` is set.
+// nstaged < 0; dense tiles are considered when `dense` is set, and dense
+// tiles over whole units of the rows (TTX_CFG_WIDE) also when `wide` is.
 ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
-                               const TileShape* staged, int nstaged, bool dense);
+                               const TileShape* staged, int nstaged, bool dense, bool wide = false);
 // Candidate enumeration with estimated costs (sorted ascending).
 int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, double* cost, int cap);
 // Builds the kernel-side grid, strides and index groups for a config.
@@ -259,9 +307,16 @@ inline bool config_is_staged(const ttx_config& c) {
 }
 // Elements per dense tile.
 inline int dense_cap(int dtype) {
-    return dtype == TTX_F32 ? TTX_DENSE_CAP_F32 : dtype == TTX_F64 ? TTX_DENSE_CAP_F64
-           : dtype == TTX_C32 ? TTX_DENSE_CAP_C32 : TTX_DENSE_CAP_C64;
+    static const int cap[] = {TTX_DENSE_CAP_F32, TTX_DENSE_CAP_F64, TTX_DENSE_CAP_C32, TTX_DENSE_CAP_C64,
+                              0, 0, 0, 0, TTX_DENSE_CAP_W16, TTX_DENSE_CAP_W16, TTX_DENSE_CAP_W8};
+    return cap[dtype];
 }
+inline bool config_is_wide(const ttx_config& c) { return (c.flags & TTX_CFG_WIDE) != 0; }
+// The problem over whole units of the kept stride-1 rows (TTX_CFG_WIDE):
+// FP32/FP64 one-type preserved problems whose row length and other strides
+// are multiples of the unit and whose rows hold at least two units.  Fills
+// *w and returns true when there is one.
+bool widen(const Problem& p, Problem* w);
 constexpr int kThreads = 256;
 
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.

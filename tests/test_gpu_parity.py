@@ -324,3 +324,40 @@ def test_dense_tiles(perm, size, oa, ob, dtype):
         for i, c in enumerate(pick):
             got, ref, exact = _case(perm, size, dtype, alpha, beta, oa, ob, seed=40 + i % 3, plan_config=c)
             assert_parity(got, ref, exact=exact, what=str(c.as_dict()))
+
+
+# -- dense tiles over whole units of kept rows (TTX_CFG_WIDE) ----------------------------------
+WIDE_CASES = [
+    ((0, 3, 1, 2), (20, 16, 7, 9), None, None),          # rows of 5 (FP32) / 10 (FP64) units
+    ((0, 5, 1, 4, 2, 3), (24, 5, 4, 3, 7, 3), None, None),
+    ((0, 2, 1, 3), (6, 40, 30, 3), None, None),           # FP32: 8-byte units
+    ((0, 2, 1), (8, 50, 40), (8, 52, 41), (8, 41, 51)),   # outer sizes on both sides
+    ((0, 2, 1, 3), (12, 33, 7, 5), (12, 34, 8, 5), None),
+]
+
+
+@pytest.mark.parametrize("perm,size,oa,ob", WIDE_CASES)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_wide_unit_dense_tiles(perm, size, oa, ob, dtype):
+    code = ttx.F32 if dtype == F32 else ttx.F64
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, outer_a=oa, outer_b=ob, max_candidates=-1,
+                                       cap=200000)
+    wide = [c for c in cands if c.flags & ttx.CFG_WIDE]
+    assert wide, "no whole-unit candidate"
+    seen, pick = set(), []
+    for c in wide:
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c)
+        if key not in seen:
+            seen.add(key)
+            pick.append(c)
+    pick = pick[:24] + wide[::max(1, len(wide) // 6)]
+    _say("wide %s %s %s: %d configs" % (perm, size, dtype, len(pick)))
+    for alpha, beta in ((1.0, 0.0), (-0.5, 1.0), (1.3, 0.7)):
+        for i, c in enumerate(pick):
+            got, ref, exact = _case(perm, size, dtype, alpha, beta, oa, ob, seed=50 + i % 3, plan_config=c)
+            assert_parity(got, ref, exact=exact, what=str(c.as_dict()))
+    # pointers aligned to the element but not to the unit run an element-wise config
+    for pad_a, pad_b in ((1, 0), (0, 1), (2, 2)):
+        got, ref, exact = _case(perm, size, dtype, 1.25, 0.5, oa, ob, seed=60, pad_a=pad_a, pad_b=pad_b,
+                                plan_config=pick[0])
+        assert_parity(got, ref, exact, (pad_a, pad_b))
