@@ -35,10 +35,12 @@ CLIENTS = 4
 # device slots (micro-batches in flight) of the served runs
 SLOTS = 8
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
-KERNEL_SOURCES = ["tile_kernels.h", "menu.h", "registry.h", "kernels_moved_f32_beta.hip",
-                  "kernels_moved_f32_beta0.hip", "kernels_moved_f64_beta.hip",
-                  "kernels_moved_f64_beta0.hip", "kernels_preserved.hip", "kernels_staged.hip",
-                  "kernels_dense.hip", "dispatch.hip"]
+# the per-call kernels' sources (their code, without comments, keys the counter traffic)
+KERNEL_SOURCES = (["tile_kernels.h", "menu.h", "registry.h", "moved_launch.h", "staged_launch.h",
+                   "dispatch.hip"] +
+                  sorted(os.path.basename(f) for f in glob.glob(os.path.join(
+                      os.path.dirname(os.path.abspath(__file__)), "paper_1607_01249_amd", "csrc",
+                      "kernels_*.hip"))))
 METRIC = "achieved HBM GB/s (% of D2D-copy peak) per perm; batched p50/p99 latency vs per-call"
 
 

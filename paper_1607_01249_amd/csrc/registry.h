@@ -52,7 +52,27 @@ struct StagedRow {
     int n0_max, tx, ty;
     TileLaunchFn fn;
 };
-int staged_rows(int code, bool beta0, const StagedRow** out);
+int staged_rows_f32(bool beta0, const StagedRow** out);
+int staged_rows_f64(bool beta0, const StagedRow** out);
+int staged_rows_c32(bool beta0, const StagedRow** out);
+int staged_rows_c64(bool beta0, const StagedRow** out);
+int staged_rows_sd(bool beta0, const StagedRow** out);
+int staged_rows_ds(bool beta0, const StagedRow** out);
+int staged_rows_cz(bool beta0, const StagedRow** out);
+int staged_rows_zc(bool beta0, const StagedRow** out);
+inline int staged_rows(int code, bool beta0, const StagedRow** out) {
+    switch (code) {
+        case TTX_F32: return staged_rows_f32(beta0, out);
+        case TTX_F64: return staged_rows_f64(beta0, out);
+        case TTX_C32: return staged_rows_c32(beta0, out);
+        case TTX_C64: return staged_rows_c64(beta0, out);
+        case TTX_F32_F64: return staged_rows_sd(beta0, out);
+        case TTX_F64_F32: return staged_rows_ds(beta0, out);
+        case TTX_C32_C64: return staged_rows_cz(beta0, out);
+        case TTX_C64_C32: return staged_rows_zc(beta0, out);
+        default: return 0;
+    }
+}
 
 // The dense-tile kernel for a data-type code and beta class, and the
 // workgroups that fill the device with it (its launches loop over the tiles).
