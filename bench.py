@@ -439,6 +439,53 @@ def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False
                 pct_of_d2d_median=round(100 * float(np.median(g)) / d2d, 1))
 
 
+PACK_CASES = [  # name, dtype code of (A, panels), kind, rows, cols, ld, panel
+    ("A_f32_8192x8192_mr16", "F32", "PACK_ROWS", 8192, 8192, 8192, 16),
+    ("B_f32_8192x8192_nr16", "F32", "PACK_COLS", 8192, 8192, 8192, 16),
+    ("A_f64_6000x5000_mr8_ld6016", "F64", "PACK_ROWS", 6000, 5000, 6016, 8),
+    ("B_f64_5000x6000_nr6", "F64", "PACK_COLS", 5000, 6000, 5000, 6),
+    ("A_sd_8192x4096_mr16", "F32_F64", "PACK_ROWS", 8192, 4096, 8192, 16),
+    ("A_c64_4096x4096_mr4", "C64", "PACK_ROWS", 4096, 4096, 4096, 4),
+]
+
+
+def bench_packing(torch, ttx, d2d, stream, tune_candidates, reps=10):
+    """GEMM operand packing (read A, write the panels), one case resident at a
+    time, three buffer pairs in rotation as in bench_types."""
+    out = []
+    tdt = {ttx.F32: torch.float32, ttx.F64: torch.float64, ttx.C32: torch.complex64,
+           ttx.C64: torch.complex128}
+    for name, code_name, kind_name, rows, cols, ld, panel in PACK_CASES:
+        code, kind = getattr(ttx, code_name), getattr(ttx, kind_name)
+        ta, tb = ttx.TYPES_OF[code]
+        packed, cfgs = ttx.ttx_pack_describe(code, kind, rows, cols, ld, panel)
+        ttx.ttx_pack_tune(code, kind, rows, cols, ld, panel, max_candidates=tune_candidates, reps=3)
+        real = lambda t: torch.view_as_real(t) if t.is_complex() else t
+        pairs = []
+        for k in range(3):
+            A = torch.empty(ld * cols, dtype=tdt[ta], device="cuda")
+            P = torch.empty(packed, dtype=tdt[tb], device="cuda")
+            fill_uniform(torch, real(A), 40 + k)
+            pairs.append((A, P))
+        state = {"i": 0}
+
+        def run():
+            state["i"] = (state["i"] + 1) % len(pairs)
+            A, P = pairs[state["i"]]
+            ttx.ttx_pack(code, kind, rows, cols, ld, panel, 1.0, A.data_ptr(), P.data_ptr(), stream)
+
+        for _ in range(3):
+            run()
+        _, tmed = time_events(torch, run, reps)
+        nbytes = rows * cols * ttx.ELEM_BYTES[ta] + packed * ttx.ELEM_BYTES[tb]
+        gbps = nbytes / tmed / 1e9
+        out.append(dict(case=name, GBps=round(gbps, 1), pct_of_d2d=round(100 * gbps / d2d, 1),
+                        us=round(tmed * 1e6, 1), transpositions=len(cfgs)))
+        del pairs
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_served(torch, ttx, seconds, rate):
     """Open-loop Poisson trace through the server vs the same trace run one
     synchronised per-call request at a time; a sample of requests is re-run
@@ -708,10 +755,12 @@ def main():
     if not args.no_served:
         served = bench_served(torch, ttx, args.serve_seconds, args.serve_rate)
 
-    cplx = None
+    cplx = packing = None
     if not args.no_types and not args.profile_run:
         log("complex and mixed-precision cases")
         cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates)
+        log("GEMM operand packing")
+        packing = bench_packing(torch, ttx, d2d, stream, args.tune_candidates)
         if args.save_table:
             ttx.ttx_tune_table_save(args.save_table)
 
@@ -734,6 +783,7 @@ def main():
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
         roofline=roofline, cpu_baseline=cpu, batched=batched, served=served, other_types=cplx,
+        packing=packing,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,

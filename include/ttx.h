@@ -250,6 +250,40 @@ ttx_status ttx_tune_table_load(const char *path);
 ttx_status ttx_tune_table_clear(void);
 int ttx_tune_table_size(void);
 
+/* -- GEMM operand packing (Sec. 2.1, Fig. 3) -----------------------------------------
+ * Packing for a GEMM kernel is a transposition of the matrix viewed as a 3D
+ * tensor: the index cut into panels becomes two indices (position inside the
+ * panel, panel number), and the panel number moves outermost.  A is a
+ * column-major rows x cols matrix with leading dimension ld (>= rows),
+ * elements of A's type of dtype; P receives the panels, elements of B's
+ * type (mixed-precision codes pack into another precision), every element
+ * scaled by alpha = (alpha[0], alpha[1]) as in ttx_transpose_c with beta = 0:
+ *   TTX_PACK_ROWS (the left operand): panels of `panel` = mr rows; panel p
+ *     is an mr x cols column-major block, P[i + c*mr + p*mr*cols] =
+ *     alpha * A[(p*mr + i) + c*ld] (the view (mr, rows/mr, cols) with perm
+ *     (0,2,1), Fig. 3);
+ *   TTX_PACK_COLS (the right operand): panels of `panel` = nr columns;
+ *     panel p holds rows of nr contiguous elements,
+ *     P[j + r*nr + p*nr*rows] = alpha * A[r + (p*nr + j)*ld] (the view
+ *     (rows, nr, cols/nr) with perm (1,0,2)).
+ * A ragged last panel is padded with zeros; P holds ceil(extent/panel) *
+ * panel * other elements.  A and P are device pointers aligned to their
+ * element sizes whose byte ranges must not overlap (TTX_EOVERLAP).  Plans
+ * are cached per (dtype, kind, rows, cols, ld, panel); the transpositions
+ * use the tune table (ttx_pack_tune fills it).  Asynchronous on `stream`. */
+typedef enum ttx_pack_kind { TTX_PACK_ROWS = 0, TTX_PACK_COLS = 1 } ttx_pack_kind;
+
+ttx_status ttx_pack(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64_t ld, int64_t panel,
+                    const double *alpha, const void *A, void *P, hipStream_t stream);
+/* Tunes the transpositions a packing runs (as ttx_tune does; blocks). */
+ttx_status ttx_pack_tune(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64_t ld,
+                         int64_t panel, int max_candidates, int reps);
+/* Host only: the packed element count, the number of transpositions (1 or 2;
+ * 0 when empty) and their configs (configs[0..1], may be NULL). */
+ttx_status ttx_pack_describe(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64_t ld,
+                             int64_t panel, int64_t *packed_elements, int *transpositions,
+                             ttx_config *configs);
+
 /* -- batched execution ----------------------------------------------------------
  * Many independent transpositions, each Eqn. 1 with its own dtype, shape,
  * permutation, leading dimensions, scalars and tensors, run by ONE

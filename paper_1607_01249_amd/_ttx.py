@@ -30,6 +30,7 @@ OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = rang
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
 CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE, CFG_WIDE = 1, 2, 4, 8
+PACK_ROWS, PACK_COLS = 0, 1
 DENSE_CAP = {F32: 1024, F64: 1024, C32: 1024, C64: 512}
 DENSE_CAP.update({code: DENSE_CAP[b] for code, (a, b) in TYPES_OF.items() if a != b})
 
@@ -206,6 +207,9 @@ def _declare(L):
         "ttx_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], S),
         "ttx_server_destroy": ([vp], S),
         "ttx_replay_sequential": ([i64, vp, i64p, vp, i64, vp, ctypes.POINTER(ctypes.c_double)], S),
+        "ttx_pack": ([S, S, i64, i64, i64, i64, dp, vp, vp, vp], S),
+        "ttx_pack_tune": ([S, S, i64, i64, i64, i64, S, S], S),
+        "ttx_pack_describe": ([S, S, i64, i64, i64, i64, i64p, ip, ctypes.POINTER(Config)], S),
         "ttx_copy_kernel": ([vp, vp, i64, vp], S),
         "ttx_axpby_kernel": ([S, i64, ctypes.c_double, vp, ctypes.c_double, vp, vp], S),
     }
@@ -477,6 +481,26 @@ def ttx_server_destroy(server):
 
 def ttx_copy_kernel(src, dst, nbytes, stream=0):
     return _check(lib().ttx_copy_kernel(src, dst, int(nbytes), stream))
+
+
+def ttx_pack(dtype, kind, rows, cols, ld, panel, alpha, A, P, stream=0):
+    return _check(lib().ttx_pack(dtype, kind, int(rows), int(cols), int(ld), int(panel),
+                                 _complex2(alpha), A, P, stream))
+
+
+def ttx_pack_tune(dtype, kind, rows, cols, ld, panel, max_candidates=0, reps=3):
+    return _check(lib().ttx_pack_tune(dtype, kind, int(rows), int(cols), int(ld), int(panel),
+                                      int(max_candidates), int(reps)))
+
+
+def ttx_pack_describe(dtype, kind, rows, cols, ld, panel):
+    """(packed element count, [configs of the transpositions run])."""
+    n = i64(0)
+    parts = ctypes.c_int(0)
+    cfg = (Config * 2)()
+    _check(lib().ttx_pack_describe(dtype, kind, int(rows), int(cols), int(ld), int(panel),
+                                   ctypes.byref(n), ctypes.byref(parts), cfg))
+    return n.value, [cfg[i] for i in range(parts.value)]
 
 
 def ttx_axpby_kernel(dtype, n, alpha, x, beta, y, stream=0):

@@ -196,6 +196,28 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
     return buf;
 }
 
+// Zero fill of a strided region (the padding of a ragged packed panel), in
+// 4-byte words: word w of row r is at dst + r*pitch + 4*w.
+__global__ __launch_bounds__(kThreads) void k_fill_zero(uint32_t* __restrict__ dst, int64_t words,
+                                                        int64_t height, int64_t pitch_words) {
+    const int64_t total = words * height;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += int64_t(gridDim.x) * kThreads) {
+        const int64_t r = i / words, w = i - r * words;
+        dst[r * pitch_words + w] = 0u;
+    }
+}
+
+hipError_t launch_fill_zero(void* dst, int64_t width, int64_t height, int64_t pitch, hipStream_t stream) {
+    const int64_t words = width / 4, total = words * height;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + kThreads - 1) / kThreads;
+    const int64_t cap = int64_t(device_cus()) * 8;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_fill_zero, dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, static_cast<uint32_t*>(dst),
+                       words, height, pitch / 4);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------
 // Ceiling kernels: a 16-byte-vector copy and an unfused axpby (the SAXPY
 // peak of Sec. 3).  Grid-stride loops with 4 vectors in flight per thread.

@@ -113,7 +113,11 @@ ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
         if (__builtin_mul_overflow(prod, o, &prod)) return fail(TTX_EINVAL, "outer_b overflows");
     }
     for (int k = 0; k < n; ++k) sb[perm[k]] = sbpos[k];
+    return make_problem_strided(dtype, n, perm, size, sa, sb, out);
+}
 
+ttx_status make_problem_strided(int dtype, int n, const int* perm, const int64_t* size,
+                                const int64_t* sa, const int64_t* sb, Problem* out) {
     Problem p;
     p.code = dtype;
     p.dtype = dtype_b_of(dtype);

@@ -271,6 +271,11 @@ ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* si
 // Planner (host only).
 ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
                         const int64_t* outer_a, const int64_t* outer_b, Problem* out);
+// The same from element strides (sa[m], sb[m]: A's and B's stride of A index m)
+// that the caller has already checked (n, perm, sizes valid; B's addressed
+// elements distinct).
+ttx_status make_problem_strided(int dtype, int n, const int* perm, const int64_t* size,
+                                const int64_t* sa, const int64_t* sb, Problem* out);
 // Validates a config against a problem; fills *why on rejection.
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why);
 // The heuristic default config (best-ranked candidate).
@@ -328,12 +333,18 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
 std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, const void* Bdst);
 
+// Zero bytes [0, width) of `height` rows that start `pitch` bytes apart
+// (dispatch.hip; width and pitch multiples of 4, dst 4-byte aligned).
+hipError_t launch_fill_zero(void* dst, int64_t width, int64_t height, int64_t pitch, hipStream_t stream);
+
 // Ceiling kernels (dispatch.hip).
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t stream);
 hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, double beta, void* y,
                         hipStream_t stream);
 
 // Tune table (tune.cpp).
+ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
+                        int* n_timed);
 bool table_lookup(const Problem& p, bool beta0, ttx_config* out);
 void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec);
 uint64_t table_generation();

@@ -164,6 +164,35 @@ ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
     return TTX_OK;
 }
 
+// Ranks the candidates of p, times the best max_candidates of them and
+// stores the fastest in the tune table (ttx_tune for a built problem).
+ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
+                        int* n_timed) {
+    if (n_timed) *n_timed = 0;
+    if (p.family == TTX_FAMILY_EMPTY) {
+        *best = default_config(p);
+        return TTX_OK;
+    }
+    const int keep = max_candidates == 0 ? 200 : max_candidates;
+    std::vector<ttx_config> cands(keep < 0 ? 1 << 17 : keep);
+    int nc = rank_candidates(p, max_candidates, cands.data(), nullptr, int(cands.size()));
+    if (nc <= 0) return fail(TTX_EUNSUPPORTED, "no candidate for this problem");
+    cands.resize(nc);
+    int best_i = -1;
+    double best_us = 0;
+    ttx_status st = time_candidates(
+        p, beta0, int(cands.size()), reps,
+        [&](int i, const void* A, void* B, hipStream_t s) {
+            return launch_tiles(p, cands[i], beta0, A, B, B, 1.0, beta0 ? 0.0 : 1.0, s);
+        },
+        &best_i, &best_us);
+    if (st != TTX_OK) return st;
+    *best = cands[best_i];
+    if (n_timed) *n_timed = nc;
+    table_store(p, beta0, *best, best_us);
+    return TTX_OK;
+}
+
 }  // namespace ttx
 
 using namespace ttx;
@@ -188,31 +217,8 @@ ttx_status ttx_tune(ttx_dtype dtype, int n, const int* perm, const int64_t* size
     Problem p;
     ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
     if (st != TTX_OK) return st;
-    if (n_timed) *n_timed = 0;
-    if (p.family == TTX_FAMILY_EMPTY) {
-        *best = default_config(p);
-        return TTX_OK;
-    }
-    const int keep = max_candidates == 0 ? 200 : max_candidates;
-    std::vector<ttx_config> cands(keep < 0 ? 1 << 17 : keep);
-    int nc = rank_candidates(p, max_candidates, cands.data(), nullptr, int(cands.size()));
-    if (nc <= 0) return fail(TTX_EUNSUPPORTED, "no candidate for this problem");
-    cands.resize(nc);
-    const bool beta0 = beta_is_zero != 0;
-    int best_i = -1;
-    double best_us = 0;
-    st = time_candidates(p, beta0, int(cands.size()), reps,
-                         [&](int i, const void* A, void* B, hipStream_t s) {
-                             return launch_tiles(p, cands[i], beta0, A, B, B, 1.0, beta0 ? 0.0 : 1.0, s);
-                         },
-                         &best_i, &best_us);
-    if (st != TTX_OK) return st;
-    *best = cands[best_i];
-    if (n_timed) *n_timed = nc;
-    table_store(p, beta0, *best, best_us);
-    return TTX_OK;
+    return tune_problem(p, beta_is_zero != 0, max_candidates, reps, best, n_timed);
 }
-
 ttx_status ttx_tune_table_save(const char* path) {
     if (!path) return fail(TTX_EINVAL, "NULL path");
     std::ofstream f(path);

@@ -492,3 +492,34 @@ def test_batch_takes_real_one_type_problems_only(code):
     with pytest.raises(ttx.TTXError) as e:
         ttx.ttx_batch_plan([q])
     assert e.value.status == ttx.EUNSUPPORTED
+
+
+# -- GEMM operand packing (host planning) ------------------------------------------------------
+def test_pack_describe_splits_whole_and_ragged_panels():
+    n, cfgs = ttx.ttx_pack_describe(ttx.F32, ttx.PACK_ROWS, 37, 19, 40, 8)
+    assert n == 5 * 8 * 19 and len(cfgs) == 2
+    assert cfgs[0].family == ttx.FAMILY_PRESERVED       # panel rows stay contiguous
+    n, cfgs = ttx.ttx_pack_describe(ttx.F32, ttx.PACK_ROWS, 32, 19, 40, 8)
+    assert n == 32 * 19 and len(cfgs) == 1
+    n, cfgs = ttx.ttx_pack_describe(ttx.F64, ttx.PACK_COLS, 19, 37, 20, 8)
+    assert n == 19 * 5 * 8 and len(cfgs) == 2
+    assert cfgs[0].family == ttx.FAMILY_MOVED
+    n, cfgs = ttx.ttx_pack_describe(ttx.C32_C64, ttx.PACK_COLS, 0, 37, 20, 8)
+    assert n == 0 and cfgs == []
+
+
+def test_pack_argument_errors_need_no_gpu():
+    big = 1 << 40
+    for args, status in [((ttx.F32, 2, 4, 4, 4, 2), ttx.EINVAL),       # unknown kind
+                         ((ttx.F32, 0, 4, 4, 3, 2), ttx.EINVAL),       # ld < rows
+                         ((ttx.F32, 0, 4, 4, 4, 0), ttx.EINVAL),       # panel < 1
+                         ((8, 0, 4, 4, 4, 2), ttx.EINVAL)]:            # unknown dtype
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_pack(*args, 1.0, big, big + (1 << 20))
+        assert e.value.status == status, args
+    with pytest.raises(ttx.TTXError) as e:   # A spans 4*4*4 = 64 bytes, P 64 bytes
+        ttx.ttx_pack(ttx.F32, 0, 4, 4, 4, 2, 1.0, big, big + 60)
+    assert e.value.status == ttx.EOVERLAP
+    with pytest.raises(ttx.TTXError) as e:   # complex scale for real panels
+        ttx.ttx_pack(ttx.F32, 0, 4, 4, 4, 2, 1j, big, big + 4096)
+    assert e.value.status == ttx.EINVAL

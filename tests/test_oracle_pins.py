@@ -680,3 +680,93 @@ def test_sampled_oracle_matches_full_oracle():
             idx = rng.integers(0, _elems(size), size=50)
             vals, off = oracle.sample(perm, size, alpha, A, beta, B0, idx, oa, ob)
             assert _same_bits(vals, full[off])
+
+
+# ---------------------------------------------------------------------------------------
+# GEMM operand packing (Sec. 2.1, Fig. 3): oracle/pack.py.
+from oracle import pack as pack_oracle   # noqa: E402
+
+
+def test_pack_oracle_tiny_example_by_hand():
+    """A = [[1, 4], [2, 5], [3, 6]] (column-major 1..6), panels of 2 rows:
+    panel 0 holds rows 0-1 as a 2x2 column-major block, panel 1 row 2 and a
+    zero row; panels of 1 column are the columns themselves."""
+    A = np.arange(1, 7, dtype=np.float64)
+    P = pack_oracle.pack(pack_oracle.ROWS, A, 3, 2, 3, 2)
+    assert P.tolist() == [1, 2, 4, 5, 3, 0, 6, 0]
+    Q = pack_oracle.pack(pack_oracle.COLS, A, 3, 2, 3, 1)
+    assert Q.tolist() == [1, 2, 3, 4, 5, 6]
+    R = pack_oracle.pack(pack_oracle.COLS, A, 3, 2, 3, 2)   # one panel: rows of 2 contiguous
+    assert R.tolist() == [1, 4, 2, 5, 3, 6]
+
+
+def _int_matrix(rng, n, dtype):
+    return rng.integers(-8, 9, size=n).astype(dtype)
+
+
+def test_pack_oracle_gemm_identity():
+    """Panels feed a GEMM: for rows packing of A (m x k) every panel times X
+    gives its rows of A @ X; for columns packing of Y (k x n), W times every
+    panel gives its columns of W @ Y (integer-valued, so the products are
+    exact)."""
+    rng = np.random.default_rng(71)
+    for m, k, n, mr, lda in [(37, 19, 5, 8, 40), (16, 7, 3, 4, 16), (5, 3, 2, 8, 9)]:
+        A = _int_matrix(rng, lda * k, np.float64)
+        Am = A.reshape(k, lda).T[:m]           # column-major view with ld
+        X = _int_matrix(rng, k * n, np.float64).reshape(k, n)
+        P = pack_oracle.pack(pack_oracle.ROWS, A, m, k, lda, mr)
+        npan = -(-m // mr)
+        panels = P.reshape(npan, k, mr)        # [p][c][i]
+        C = Am @ X
+        for p in range(npan):
+            rows = slice(p * mr, min(m, (p + 1) * mr))
+            got = panels[p].T @ X              # mr x n, padded rows give zeros
+            nrow = rows.stop - rows.start
+            assert np.array_equal(got[:nrow], C[rows])
+            assert not got[nrow:].any()
+    for k, n, w, nr, ldy in [(19, 37, 5, 8, 21), (7, 16, 3, 4, 7)]:
+        Y = _int_matrix(rng, ldy * n, np.float64)
+        Ym = Y.reshape(n, ldy).T[:k]
+        W = _int_matrix(rng, w * k, np.float64).reshape(w, k)
+        P = pack_oracle.pack(pack_oracle.COLS, Y, k, n, ldy, nr)
+        npan = -(-n // nr)
+        panels = P.reshape(npan, k, nr)        # [p][r][j]
+        C = W @ Ym
+        for p in range(npan):
+            cols = slice(p * nr, min(n, (p + 1) * nr))
+            got = W @ panels[p]
+            ncol = cols.stop - cols.start
+            assert np.array_equal(got[:, :ncol], C[:, cols])
+            assert not got[:, ncol:].any()
+
+
+def test_pack_oracle_is_the_fig3_transposition():
+    """With whole panels and ld a multiple of the panel, rows packing is the
+    transposition of the view (mr, m/mr, k) with perm (0, 2, 1), and columns
+    packing that of (k, nr, n/nr) with perm (1, 0, 2) (the pinned oracle)."""
+    rng = np.random.default_rng(72)
+    for dtype in (F32, F64, C32, C64):
+        m, k, mr, lda = 24, 7, 8, 32
+        A = _rand(lda * k, dtype, rng)
+        P = pack_oracle.pack(pack_oracle.ROWS, A, m, k, lda, mr, alpha=0.5)
+        T = np.zeros(m * k, dtype=dtype)
+        _run(oracle.lib(), (0, 2, 1), (mr, m // mr, k), 0.5, A, 0.0, T, (mr, lda // mr, k))
+        assert _same_bits(P, T)
+        kk, n, nr, ldy = 9, 12, 4, 10
+        Y = _rand(ldy * n, dtype, rng)
+        P = pack_oracle.pack(pack_oracle.COLS, Y, kk, n, ldy, nr, alpha=-1.5)
+        T = np.zeros(kk * n, dtype=dtype)
+        _run(oracle.lib(), (1, 0, 2), (kk, nr, n // nr), -1.5, Y, 0.0, T, (ldy, nr, n // nr))
+        assert _same_bits(P, T)
+
+
+def test_pack_oracle_complex_and_mixed_scalars_match_the_transposition_oracle():
+    rng = np.random.default_rng(73)
+    for da, db in ((C32, C64), (C64, C32), (F32, F64), (F64, F32), (C64, C64)):
+        m, k, mr = 16, 5, 4
+        A = _rand(m * k, da, rng)
+        alpha = complex(0.75, -1.25) if db in (C32, C64) else 1.3
+        P = pack_oracle.pack(pack_oracle.ROWS, A, m, k, m, mr, alpha=alpha, out_dtype=db)
+        T = np.zeros(m * k, dtype=db)
+        _run(oracle.lib(), (0, 2, 1), (mr, m // mr, k), alpha, A, 0.0, T)
+        assert _same_bits(P, T), (da, db)
