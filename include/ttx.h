@@ -249,6 +249,15 @@ ttx_status ttx_tune_table_save(const char *path);
 ttx_status ttx_tune_table_load(const char *path);
 ttx_status ttx_tune_table_clear(void);
 int ttx_tune_table_size(void);
+/* A table file as a solution database shared across processes (Sec. 2.1:
+ * the database is consulted before any search and keeps every solution):
+ * its entries are merged into the table, keeping the lowest time per key
+ * (the file is created when missing), and from then on every tuning result
+ * is also appended to it as one line under an exclusive file lock.  The
+ * environment variable TTX_TUNE_DB attaches a file before the table is
+ * first used.  Detach stops the appending (the table keeps its entries). */
+ttx_status ttx_tune_db_attach(const char *path);
+ttx_status ttx_tune_db_detach(void);
 
 /* -- GEMM operand packing (Sec. 2.1, Fig. 3) -----------------------------------------
  * Packing for a GEMM kernel is a transposition of the matrix viewed as a 3D

@@ -186,6 +186,8 @@ def _declare(L):
         "ttx_tune_table_load": ([ctypes.c_char_p], S),
         "ttx_tune_table_clear": ([], S),
         "ttx_tune_table_size": ([], S),
+        "ttx_tune_db_attach": ([ctypes.c_char_p], S),
+        "ttx_tune_db_detach": ([], S),
         "ttx_batch_create": ([ctypes.POINTER(vp), S, ctypes.POINTER(Problem)], S),
         "ttx_batch_tune": ([vp, S, S], S),
         "ttx_batch_execute": ([vp, vp], S),
@@ -336,6 +338,14 @@ def ttx_tune_table_clear():
 
 def ttx_tune_table_size():
     return lib().ttx_tune_table_size()
+
+
+def ttx_tune_db_attach(path):
+    return _check(lib().ttx_tune_db_attach(path.encode()))
+
+
+def ttx_tune_db_detach():
+    return _check(lib().ttx_tune_db_detach())
 
 
 def _problem_array(problems):

@@ -7,7 +7,13 @@
 // menu, loop order, XCD swizzle, streaming stores), so stage 4 (compile)
 // disappears and stage 5 times each candidate directly on the GPU.  The
 // database is an in-process table keyed by the merged problem, with a
-// one-line-per-entry text format for saving and loading.
+// one-line-per-entry text format for saving and loading.  A table file can
+// also be attached as a database shared across processes: its entries are
+// merged in (lowest time per key) and every new tuning result is appended
+// to it under an exclusive file lock (TTX_TUNE_DB names one at start-up).
+#include <sys/file.h>
+#include <unistd.h>
+
 #include <atomic>
 #include <cstdlib>
 #include <cstdio>
@@ -31,8 +37,26 @@ struct TableEntry {
 static std::mutex g_table_mu;
 static std::map<std::string, TableEntry> g_table;
 static std::atomic<uint64_t> g_table_gen{1};
+static std::string g_db_path;   // attached database file ("" when none); under g_table_mu
+static const char* const kTableHeader =
+    "# ttx tune table v3: key | family tile_a tile_b threads flags group_a group_b n_order order... "
+    "[c<tile_c>] | usec\n";
 
-uint64_t table_generation() { return g_table_gen.load(); }
+static ttx_status attach_db(const char* path);
+
+// The database named by TTX_TUNE_DB, attached once before the table is first used.
+static void attach_env_db() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char* path = std::getenv("TTX_TUNE_DB");
+        if (path && *path) (void)attach_db(path);
+    });
+}
+
+uint64_t table_generation() {
+    attach_env_db();
+    return g_table_gen.load();
+}
 
 // Key: dtype, beta == 0, and the merged problem (extents, permutation and
 // both stride vectors), so that every call that plans to the same merged
@@ -51,6 +75,7 @@ static std::string table_key(const Problem& p, bool beta0) {
 }
 
 bool table_lookup(const Problem& p, bool beta0, ttx_config* out) {
+    attach_env_db();
     std::lock_guard<std::mutex> lock(g_table_mu);
     auto it = g_table.find(table_key(p, beta0));
     if (it == g_table.end() || !config_valid(p, it->second.cfg, nullptr)) return false;
@@ -58,10 +83,36 @@ bool table_lookup(const Problem& p, bool beta0, ttx_config* out) {
     return true;
 }
 
+static std::string config_text(const ttx_config& c);
+
+// Appends one entry to the attached database under an exclusive lock, so
+// that processes sharing the file never interleave partial lines.
+static void db_append(const std::string& path, const std::string& line) {
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    if (flock(fileno(f), LOCK_EX) == 0) {
+        std::fputs(line.c_str(), f);
+        std::fflush(f);
+        (void)flock(fileno(f), LOCK_UN);
+    }
+    std::fclose(f);
+}
+
 void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec) {
-    std::lock_guard<std::mutex> lock(g_table_mu);
-    g_table[table_key(p, beta0)] = TableEntry{c, usec};
-    g_table_gen.fetch_add(1);
+    attach_env_db();
+    const std::string key = table_key(p, beta0);
+    std::string db;
+    {
+        std::lock_guard<std::mutex> lock(g_table_mu);
+        g_table[key] = TableEntry{c, usec};
+        g_table_gen.fetch_add(1);
+        db = g_db_path;
+    }
+    if (!db.empty()) {
+        std::ostringstream os;
+        os << key << " | " << config_text(c) << " | " << usec << "\n";
+        db_append(db, os.str());
+    }
 }
 
 static std::string config_text(const ttx_config& c) {
@@ -193,6 +244,51 @@ ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int re
     return TTX_OK;
 }
 
+// Reads a table file; a key listed more than once keeps its lowest time
+// (a database file collects appended results).
+static ttx_status read_table(const char* path, std::map<std::string, TableEntry>* out) {
+    std::ifstream f(path);
+    if (!f) return fail(TTX_ENOTFOUND, "cannot open tune table");
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        size_t a = line.find(" | "), b = line.rfind(" | ");
+        if (a == std::string::npos || b == a) return fail(TTX_EINVAL, "malformed tune table line");
+        TableEntry e;
+        std::istringstream cs(line.substr(a + 3, b - a - 3));
+        if (!parse_config(cs, &e.cfg)) return fail(TTX_EINVAL, "malformed config in tune table");
+        e.usec = std::atof(line.substr(b + 3).c_str());
+        const std::string key = line.substr(0, a);
+        auto it = out->find(key);
+        if (it == out->end() || e.usec < it->second.usec) (*out)[key] = e;
+    }
+    return TTX_OK;
+}
+
+static ttx_status attach_db(const char* path) {
+    std::map<std::string, TableEntry> loaded;
+    ttx_status st = read_table(path, &loaded);
+    if (st == TTX_ENOTFOUND) {   // a new database: create it with the header line
+        FILE* f = std::fopen(path, "a");
+        if (!f) return fail(TTX_EINVAL, "cannot create the tune database");
+        if (flock(fileno(f), LOCK_EX) == 0) {
+            if (std::ftell(f) == 0) std::fputs(kTableHeader, f);
+            (void)flock(fileno(f), LOCK_UN);
+        }
+        std::fclose(f);
+        st = TTX_OK;
+    }
+    if (st != TTX_OK) return st;
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    for (auto& kv : loaded) {
+        auto it = g_table.find(kv.first);
+        if (it == g_table.end() || kv.second.usec < it->second.usec) g_table[kv.first] = kv.second;
+    }
+    g_db_path = path;
+    g_table_gen.fetch_add(1);
+    return TTX_OK;
+}
+
 }  // namespace ttx
 
 using namespace ttx;
@@ -224,7 +320,7 @@ ttx_status ttx_tune_table_save(const char* path) {
     std::ofstream f(path);
     if (!f) return fail(TTX_EINVAL, "cannot open tune table for writing");
     std::lock_guard<std::mutex> lock(g_table_mu);
-    f << "# ttx tune table v3: key | family tile_a tile_b threads flags group_a group_b n_order order... [c<tile_c>] | usec\n";
+    f << kTableHeader;
     for (const auto& kv : g_table)
         f << kv.first << " | " << config_text(kv.second.cfg) << " | " << kv.second.usec << "\n";
     return f ? TTX_OK : fail(TTX_EINVAL, "write failed");
@@ -232,23 +328,25 @@ ttx_status ttx_tune_table_save(const char* path) {
 
 ttx_status ttx_tune_table_load(const char* path) {
     if (!path) return fail(TTX_EINVAL, "NULL path");
-    std::ifstream f(path);
-    if (!f) return fail(TTX_ENOTFOUND, "cannot open tune table");
+    attach_env_db();
     std::map<std::string, TableEntry> loaded;
-    std::string line;
-    while (std::getline(f, line)) {
-        if (line.empty() || line[0] == '#') continue;
-        size_t a = line.find(" | "), b = line.rfind(" | ");
-        if (a == std::string::npos || b == a) return fail(TTX_EINVAL, "malformed tune table line");
-        TableEntry e;
-        std::istringstream cs(line.substr(a + 3, b - a - 3));
-        if (!parse_config(cs, &e.cfg)) return fail(TTX_EINVAL, "malformed config in tune table");
-        e.usec = std::atof(line.substr(b + 3).c_str());
-        loaded[line.substr(0, a)] = e;
-    }
+    ttx_status st = read_table(path, &loaded);
+    if (st != TTX_OK) return st;
     std::lock_guard<std::mutex> lock(g_table_mu);
     for (auto& kv : loaded) g_table[kv.first] = kv.second;
     g_table_gen.fetch_add(1);
+    return TTX_OK;
+}
+
+ttx_status ttx_tune_db_attach(const char* path) {
+    if (!path || !*path) return fail(TTX_EINVAL, "NULL or empty path");
+    attach_env_db();
+    return attach_db(path);
+}
+
+ttx_status ttx_tune_db_detach(void) {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    g_db_path.clear();
     return TTX_OK;
 }
 

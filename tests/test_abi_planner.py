@@ -523,3 +523,46 @@ def test_pack_argument_errors_need_no_gpu():
     with pytest.raises(ttx.TTXError) as e:   # complex scale for real panels
         ttx.ttx_pack(ttx.F32, 0, 4, 4, 4, 2, 1j, big, big + 4096)
     assert e.value.status == ttx.EINVAL
+
+
+# -- the tune table as a database shared across processes ------------------------------------
+KEY_PLAIN = "d0:b1:n3:s96,128,80:p2,1,0:a1,96,12288:o10240,80,1"
+
+
+def test_tune_db_keeps_lowest_time_and_creates_missing_files(tmp_path):
+    ttx.ttx_tune_table_clear()
+    db = str(tmp_path / "db.txt")
+    with open(db, "w") as f:
+        f.write(KEY_PLAIN + " | 3 32 16 256 1 1 1 3 0 2 1 | 12.5\n")
+        f.write(KEY_PLAIN + " | 3 64 32 256 0 1 1 3 2 0 1 | 9.0\n")    # faster, appended later
+        f.write(KEY_PLAIN + " | 3 16 16 256 0 1 1 3 1 0 2 | 30.0\n")
+    try:
+        ttx.ttx_tune_db_attach(db)
+        d = _describe(0, (2, 1, 0), (96, 128, 80))
+        assert d["config_from_table"] == [0, 1]
+        assert d["config"][1]["tile_a"] == 64 and d["config"][1]["order"] == [2, 0, 1]
+    finally:
+        ttx.ttx_tune_db_detach()
+        ttx.ttx_tune_table_clear()
+    fresh = str(tmp_path / "new_db.txt")
+    try:
+        ttx.ttx_tune_db_attach(fresh)
+        assert open(fresh).read().startswith("# ttx tune table")
+    finally:
+        ttx.ttx_tune_db_detach()
+
+
+def test_tune_db_from_the_environment_in_a_new_process(tmp_path):
+    import subprocess
+    import sys
+    db = str(tmp_path / "env_db.txt")
+    with open(db, "w") as f:
+        f.write(KEY_PLAIN + " | 3 32 16 256 1 1 1 3 0 2 1 | 12.5\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r); import paper_1607_01249_amd as t; "
+            "p = t.ttx_plan_create(0, (2, 1, 0), (96, 128, 80)); d = t.ttx_plan_describe(p); "
+            "print(d['config_from_table'][1], d['config'][1]['tile_a'])" % root)
+    env = dict(os.environ, TTX_TUNE_DB=db)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["1", "32"]

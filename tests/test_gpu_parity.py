@@ -361,3 +361,28 @@ def test_wide_unit_dense_tiles(perm, size, oa, ob, dtype):
         got, ref, exact = _case(perm, size, dtype, 1.25, 0.5, oa, ob, seed=60, pad_a=pad_a, pad_b=pad_b,
                                 plan_config=pick[0])
         assert_parity(got, ref, exact, (pad_a, pad_b))
+
+
+def test_tune_db_appends_each_result(tmp_path):
+    """A tuning result is appended to the attached database and is found by
+    a new process that attaches the same file."""
+    import os
+    import subprocess
+    db = str(tmp_path / "db.txt")
+    ttx.ttx_tune_table_clear()
+    ttx.ttx_tune_db_attach(db)
+    try:
+        best, n = ttx.ttx_tune(ttx.F32, (2, 0, 1), (64, 48, 40), max_candidates=8, reps=2)
+        assert n == 8
+        lines = [l for l in open(db) if not l.startswith("#")]
+        assert len(lines) == 1 and lines[0].startswith("d0:b0:")
+    finally:
+        ttx.ttx_tune_db_detach()
+        ttx.ttx_tune_table_clear()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r); import paper_1607_01249_amd as t; "
+            "p = t.ttx_plan_create(0, (2, 0, 1), (64, 48, 40)); "
+            "print(t.ttx_plan_describe(p)['config_from_table'][0])" % root)
+    r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, TTX_TUNE_DB=db),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.split() == ["1"], r.stderr
