@@ -302,8 +302,11 @@ ttx_status ttx_pack_describe(ttx_dtype dtype, int kind, int64_t rows, int64_t co
  * captured once into a HIP graph and replayed by ttx_batch_execute.  Each
  * problem's tile variant comes from a small menu compiled into that kernel:
  * the per-shape tune table when ttx_batch_tune has timed it, otherwise the
- * heuristics of Sec. 2.3.  Results are bitwise the same as per-call
- * execution (the same tile code and operation order). */
+ * heuristics of Sec. 2.3.  Problems of the complex and mixed-precision
+ * types are not in that kernel: each runs its per-call kernel (per-call
+ * tune table, else heuristics), launched after the persistent kernel in the
+ * same graph.  Results are bitwise the same as per-call execution (the same
+ * tile code and operation order). */
 typedef struct ttx_problem {
     ttx_dtype dtype;
     int n;
@@ -318,6 +321,8 @@ typedef struct ttx_problem {
     const void *A;
     const void *B_in;                /* beta*B is read from here; NULL means B */
     void *B;                         /* result */
+    double alpha_im;                 /* imaginary parts of alpha and beta (complex types; */
+    double beta_im;                  /* zero for the real ones) */
 } ttx_problem;
 
 typedef struct ttx_batch_info {
@@ -329,6 +334,8 @@ typedef struct ttx_batch_info {
     int64_t algorithmic_bytes;       /* sum of 2S (beta == 0) or 3S bytes */
     int64_t chunks;                  /* units of work claimed by the workgroups: runs of up to
                                         a fixed number of consecutive tiles of one problem */
+    int per_call;                    /* problems launched with their per-call kernels (complex
+                                        and mixed-precision types) */
 } ttx_batch_info;
 
 typedef struct ttx_batch ttx_batch;
@@ -356,7 +363,8 @@ ttx_status ttx_batch_get_info(const ttx_batch *batch, ttx_batch_info *info);
 ttx_status ttx_batch_config(const ttx_batch *batch, int index, ttx_config *config);
 ttx_status ttx_batch_destroy(ttx_batch *batch);
 /* Host-only planning of `count` problems as ttx_batch_create would plan them
- * (no HIP call, no device memory): the config and tile count of each. */
+ * (no HIP call, no device memory): the config and tile count of each (the
+ * tile count is 0 for problems launched with their per-call kernels). */
 ttx_status ttx_batch_plan(int count, const ttx_problem *problems, ttx_config *configs,
                           int64_t *tiles);
 
@@ -371,8 +379,8 @@ ttx_status ttx_batch_plan(int count, const ttx_problem *problems, ttx_config *co
  * `slots` device slots (each a stream plus a descriptor ring entry in device
  * memory) is free, so work that arrives while earlier micro-batches run
  * overlaps with them on the device.  A request of at least 32 MiB of
- * algorithmic traffic fills the device alone and takes a slot by itself,
- * launched with the per-call kernels (whole tile menu, tune table).  Results are bitwise those of
+ * algorithmic traffic, or of a complex or mixed-precision type, takes a slot
+ * by itself, launched with the per-call kernels (whole tile menu, tune table).  Results are bitwise those of
  * ttx_transpose on the same inputs.  Latency = completion (observed by the
  * dispatcher) minus arrival. */
 typedef struct ttx_server_opts {

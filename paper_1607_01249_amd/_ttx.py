@@ -71,12 +71,14 @@ class Problem(ctypes.Structure):
                 ("size", i64 * MAX_DIMS), ("outer_a", i64 * MAX_DIMS), ("outer_b", i64 * MAX_DIMS),
                 ("has_outer_a", ctypes.c_int), ("has_outer_b", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("A", vp), ("B_in", vp), ("B", vp)]
+                ("A", vp), ("B_in", vp), ("B", vp),
+                ("alpha_im", ctypes.c_double), ("beta_im", ctypes.c_double)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int), ("grid", ctypes.c_int), ("variants_used", ctypes.c_int),
-                ("tuned", ctypes.c_int), ("total_tiles", i64), ("algorithmic_bytes", i64), ("chunks", i64)]
+                ("tuned", ctypes.c_int), ("total_tiles", i64), ("algorithmic_bytes", i64), ("chunks", i64),
+                ("per_call", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -137,7 +139,9 @@ def make_problem(dtype, perm, size, alpha, A, beta, B, outer_a=None, outer_b=Non
         q.has_outer_b = 1
         for k, v in enumerate(outer_b):
             q.outer_b[k] = int(v)
-    q.alpha, q.beta = float(alpha), float(beta)
+    alpha, beta = complex(alpha), complex(beta)
+    q.alpha, q.beta = alpha.real, beta.real
+    q.alpha_im, q.beta_im = alpha.imag, beta.imag
     q.A, q.B, q.B_in = A, B, B_in
     return q
 
@@ -382,7 +386,7 @@ def ttx_batch_get_info(batch):
     _check(lib().ttx_batch_get_info(batch, ctypes.byref(info)))
     return dict(count=info.count, grid=info.grid, variants_used=info.variants_used,
                 tuned=info.tuned, total_tiles=info.total_tiles,
-                algorithmic_bytes=info.algorithmic_bytes, chunks=info.chunks)
+                algorithmic_bytes=info.algorithmic_bytes, chunks=info.chunks, per_call=info.per_call)
 
 
 def ttx_batch_config(batch, index):

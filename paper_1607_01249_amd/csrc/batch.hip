@@ -24,9 +24,11 @@ struct ttx_batch {
     std::vector<ttx_problem> src;
     std::vector<ttx_config> cfg;
     std::vector<int> forced;
-    std::vector<ttx::BatchDesc> desc;    // in work order
+    std::vector<int> per_call;           // problems launched with their per-call kernels
+    std::vector<ttx::BatchDesc> desc;    // kernel problems, in work order
     std::vector<uint32_t> chunk_prefix;  // over the work order
     std::vector<int> order;              // work position -> problem index
+    int nk = 0;                          // problems in the persistent kernel
     unsigned char* d_work = nullptr;     // descriptors, chunk prefix, claim counter
     size_t work_bytes = 0;
     uint64_t total = 0;                  // tiles
@@ -458,8 +460,20 @@ static std::map<std::string, ttx_config> g_btab;
 using namespace ttx;
 
 static ttx_status problem_from(const ttx_problem& q, Problem* p) {
-    return make_problem(q.dtype, q.n, q.perm, q.size, q.has_outer_a ? q.outer_a : nullptr,
-                        q.has_outer_b ? q.outer_b : nullptr, p);
+    ttx_status st = make_problem(q.dtype, q.n, q.perm, q.size, q.has_outer_a ? q.outer_a : nullptr,
+                                 q.has_outer_b ? q.outer_b : nullptr, p);
+    if (st == TTX_OK && !dtype_complex(p->dtype) && (q.alpha_im != 0.0 || q.beta_im != 0.0))
+        return fail(TTX_EINVAL, "complex alpha or beta for a real element type");
+    return st;
+}
+
+static Scalar alpha_of(const ttx_problem& q) { return Scalar(q.alpha, q.alpha_im); }
+static Scalar beta_of(const ttx_problem& q) { return Scalar(q.beta, q.beta_im); }
+
+// Complex and mixed-precision problems run their per-call kernels (the
+// persistent kernel's variants are FP32 and FP64 only).
+static bool runs_per_call(const Problem& p) {
+    return p.family != TTX_FAMILY_EMPTY && (dtype_complex(p.dtype) || p.dtype_a != p.dtype);
 }
 
 // Device work block of a batch: descriptors, chunk prefix, claim counter.
@@ -470,21 +484,29 @@ static size_t work_bytes(int count) { return counter_offset(count) + 2 * sizeof(
 
 static const BatchDesc* work_desc(const ttx_batch* b) { return reinterpret_cast<const BatchDesc*>(b->d_work); }
 static const uint32_t* work_prefix(const ttx_batch* b) {
-    return reinterpret_cast<const uint32_t*>(b->d_work + prefix_offset(int(b->prob.size())));
+    return reinterpret_cast<const uint32_t*>(b->d_work + prefix_offset(b->nk));
 }
 static uint32_t* work_counter(const ttx_batch* b) {
-    return reinterpret_cast<uint32_t*>(b->d_work + counter_offset(int(b->prob.size())));
+    return reinterpret_cast<uint32_t*>(b->d_work + counter_offset(b->nk));
 }
 
 static ttx_status describe_all(ttx_batch* b) {
     const int count = int(b->prob.size());
     std::vector<BatchDesc> desc(count);
+    std::vector<int> kernel;
     uint64_t total = 0;
     b->bytes = 0;
+    b->per_call.clear();
     for (int i = 0; i < count; ++i) {
         const ttx_problem& q = b->src[i];
         const Problem& p = b->prob[i];
-        const bool beta0 = beta_is_zero(p.dtype, q.beta);
+        const bool beta0 = beta_is_zero(p.dtype, beta_of(q));
+        b->bytes += p.elements * (elem_bytes(p.dtype_a) + elem_bytes(p.dtype) * (beta0 ? 1 : 2));
+        if (runs_per_call(p)) {
+            if (!b->forced[i] && !table_lookup(p, beta0, &b->cfg[i])) b->cfg[i] = default_config(p);
+            b->per_call.push_back(i);
+            continue;
+        }
         const void* Bin = q.B_in ? q.B_in : q.B;
         ttx_config used;
         ttx_status st = batch_describe(p, b->forced[i] ? &b->cfg[i] : nullptr, beta0, q.A, Bin, q.B,
@@ -493,26 +515,40 @@ static ttx_status describe_all(ttx_batch* b) {
         b->cfg[i] = used;
         total += desc[i].tiles;
         if (total >= (uint64_t(1) << 32)) return fail(TTX_EUNSUPPORTED, "batch has too many tiles");
-        b->bytes += p.elements * elem_bytes(p.dtype) * (beta0 ? 2 : 3);
+        kernel.push_back(i);
     }
     // largest problems first, so that the chunks claimed last are short ones
-    b->order.resize(count);
-    for (int i = 0; i < count; ++i) b->order[i] = i;
+    b->order = kernel;
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         return b->prob[x].elements * elem_bytes(b->prob[x].dtype) >
                b->prob[y].elements * elem_bytes(b->prob[y].dtype);
     });
-    b->desc.resize(count);
-    for (int i = 0; i < count; ++i) b->desc[i] = desc[b->order[i]];
-    b->chunk_prefix.assign(count + 1, 0);
+    b->nk = int(kernel.size());
+    b->desc.resize(b->nk);
+    for (int i = 0; i < b->nk; ++i) b->desc[i] = desc[b->order[i]];
+    b->chunk_prefix.assign(b->nk + 1, 0);
     b->total = total;
-    b->chunks = count ? batch_layout(b->desc.data(), count, b->chunk_prefix.data(), &b->grid) : 0;
-    if (!count) b->grid = 0;
+    b->chunks = b->nk ? batch_layout(b->desc.data(), b->nk, b->chunk_prefix.data(), &b->grid) : 0;
+    if (!b->nk) b->grid = 0;
     return TTX_OK;
 }
 
+// The per-call launches of a batch's complex and mixed-precision problems.
+static hipError_t launch_per_call(const ttx_batch* b, hipStream_t stream) {
+    for (int i : b->per_call) {
+        const ttx_problem& q = b->src[i];
+        const Problem& p = b->prob[i];
+        const bool beta0 = beta_is_zero(p.dtype, beta_of(q));
+        const void* Bin = q.B_in ? q.B_in : q.B;
+        hipError_t e = launch_tiles(p, b->cfg[i], beta0, q.A, beta0 ? nullptr : Bin, q.B, alpha_of(q), beta_of(q),
+                                    stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 static ttx_status upload(ttx_batch* b, hipStream_t stream) {
-    const int count = int(b->prob.size());
+    const int count = b->nk;
     const size_t need = work_bytes(count);
     if (!b->d_work) {
         if (hipMalloc(reinterpret_cast<void**>(&b->d_work), need) != hipSuccess)
@@ -552,10 +588,10 @@ ttx_status ttx_batch_create(ttx_batch** out, int count, const ttx_problem* probl
     for (int i = 0; i < count; ++i) {
         ttx_status st = problem_from(problems[i], &b->prob[i]);
         if (st == TTX_OK) {
-            const bool beta0 = beta_is_zero(problems[i].dtype, problems[i].beta);
+            const bool beta0 = beta_is_zero(b->prob[i].dtype, beta_of(problems[i]));
             const void* Bin = problems[i].B_in ? problems[i].B_in : problems[i].B;
             st = check_pointers(b->prob[i], problems[i].A, Bin, problems[i].B, beta0);
-            if (st == TTX_OK && b->prob[i].family != TTX_FAMILY_EMPTY) {
+            if (st == TTX_OK && b->prob[i].family != TTX_FAMILY_EMPTY && !runs_per_call(b->prob[i])) {
                 std::lock_guard<std::mutex> lock(g_btab_mu);
                 auto it = g_btab.find(batch_key(b->prob[i], beta0,
                                                 vector_ok(b->prob[i], problems[i].A, beta0 ? nullptr : Bin,
@@ -588,12 +624,12 @@ ttx_status ttx_batch_update(ttx_batch* b, int count, const ttx_problem* problems
         ttx_status st = problem_from(problems[i], &p);
         if (st != TTX_OK) return st;
         const Problem& o = b->prob[i];
-        bool same = p.dtype == o.dtype && p.n == o.n && p.family == o.family && p.elements == o.elements;
+        bool same = p.code == o.code && p.n == o.n && p.family == o.family && p.elements == o.elements;
         for (int d = 0; same && d < p.n; ++d)
             same = p.perm[d] == o.perm[d] && p.dim[d].size == o.dim[d].size &&
                    p.dim[d].sa == o.dim[d].sa && p.dim[d].sb == o.dim[d].sb;
         if (!same) return fail(TTX_EINVAL, "problem " + std::to_string(i) + " changed shape");
-        const bool beta0 = beta_is_zero(p.dtype, problems[i].beta);
+        const bool beta0 = beta_is_zero(p.dtype, beta_of(problems[i]));
         const void* Bin = problems[i].B_in ? problems[i].B_in : problems[i].B;
         st = check_pointers(p, problems[i].A, Bin, problems[i].B, beta0);
         if (st != TTX_OK) return st;
@@ -604,7 +640,8 @@ ttx_status ttx_batch_update(ttx_batch* b, int count, const ttx_problem* problems
     for (int i = 0; i < count; ++i) b->forced[i] = b->prob[i].family != TTX_FAMILY_EMPTY;
     ttx_status st = describe_all(b);
     if (st != TTX_OK) return st;
-    if (b->chunks != old_chunks || b->grid != old_grid) drop_graph(b);
+    // per-call launches carry their pointers in the graph: capture again
+    if (b->chunks != old_chunks || b->grid != old_grid || !b->per_call.empty()) drop_graph(b);
     return upload(b, stream);
 }
 
@@ -629,7 +666,16 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
         const Problem& p = b->prob[i];
         if (p.family == TTX_FAMILY_EMPTY) continue;
         const ttx_problem& q = b->src[i];
-        const bool beta0 = beta_is_zero(p.dtype, q.beta);
+        const bool beta0 = beta_is_zero(p.dtype, beta_of(q));
+        if (runs_per_call(p)) {   // the per-call tuner and tune table
+            ttx_config best;
+            result = tune_problem(p, beta0, max_candidates, reps, &best, nullptr);
+            if (result == TTX_OK) {
+                b->cfg[i] = best;
+                b->forced[i] = 1;
+            }
+            continue;
+        }
         const void* Bin = q.B_in ? q.B_in : q.B;
         const int vec = vector_ok(p, q.A, beta0 ? nullptr : Bin, q.B);
         const std::string key = batch_key(p, beta0, vec);
@@ -686,22 +732,26 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
 
 ttx_status ttx_batch_execute_direct(ttx_batch* b, hipStream_t stream) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
-    hipError_t e = launch_batch(work_desc(b), work_prefix(b), int(b->prob.size()), b->chunks, b->grid,
-                                work_counter(b), stream);
+    hipError_t e = b->chunks ? launch_batch(work_desc(b), work_prefix(b), b->nk, b->chunks, b->grid,
+                                            work_counter(b), stream)
+                             : hipSuccess;
+    if (e == hipSuccess) e = launch_per_call(b, stream);
     return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
 }
 
 ttx_status ttx_batch_execute(ttx_batch* b, hipStream_t stream) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
-    if (b->chunks == 0) return TTX_OK;
+    if (b->chunks == 0 && b->per_call.empty()) return TTX_OK;
     if (!b->captured) {
         drop_graph(b);
         if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(TTX_EHIP, "capture stream creation failed");
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(TTX_EHIP, "stream capture failed to start");
-        hipError_t e = launch_batch(work_desc(b), work_prefix(b), int(b->prob.size()), b->chunks, b->grid,
-                                    work_counter(b), b->cap_stream);
+        hipError_t e = b->chunks ? launch_batch(work_desc(b), work_prefix(b), b->nk, b->chunks, b->grid,
+                                                work_counter(b), b->cap_stream)
+                                 : hipSuccess;
+        if (e == hipSuccess) e = launch_per_call(b, b->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -736,6 +786,7 @@ ttx_status ttx_batch_get_info(const ttx_batch* b, ttx_batch_info* info) {
     int tuned = 0;
     for (int f : b->forced) tuned += f;
     info->tuned = tuned;
+    info->per_call = int(b->per_call.size());
     return TTX_OK;
 }
 
@@ -751,10 +802,15 @@ ttx_status ttx_batch_plan(int count, const ttx_problem* problems, ttx_config* co
         Problem p;
         ttx_status st = problem_from(problems[i], &p);
         if (st != TTX_OK) return st;
-        const bool beta0 = beta_is_zero(p.dtype, problems[i].beta);
+        const bool beta0 = beta_is_zero(p.dtype, beta_of(problems[i]));
         const void* Bin = problems[i].B_in ? problems[i].B_in : problems[i].B;
         st = check_pointers(p, problems[i].A, Bin, problems[i].B, beta0);
         if (st != TTX_OK) return st;
+        if (runs_per_call(p)) {
+            if (!table_lookup(p, beta0, &configs[i])) configs[i] = default_config(p);
+            tiles[i] = 0;
+            continue;
+        }
         BatchDesc d;
         ttx_config used;
         st = batch_describe(p, nullptr, beta0, problems[i].A, Bin, problems[i].B, problems[i].alpha,

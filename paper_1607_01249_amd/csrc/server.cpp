@@ -89,9 +89,9 @@ struct Request {
     ttx_config cfg;          // batched-menu config, chosen at submission
     ttx_config direct;       // per-call config, for requests large enough to run alone
     BatchDesc desc;          // described at submission; an arena output is filled in at launch
-    bool large = false;
+    bool large = false;      // runs alone with the per-call kernels (large, complex or mixed)
     bool beta0;
-    double alpha, beta;
+    Scalar alpha, beta;
     const void* A;
     const void* Bin;
     void* Bout;
@@ -341,9 +341,11 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
     ttx_status st = make_problem(q.dtype, q.n, q.perm, q.size, q.has_outer_a ? q.outer_a : nullptr,
                                  q.has_outer_b ? q.outer_b : nullptr, &r.p);
     if (st != TTX_OK) return st;
-    r.alpha = q.alpha;
-    r.beta = q.beta;
-    r.beta0 = beta_is_zero(r.p.dtype, q.beta);
+    if (!dtype_complex(r.p.dtype) && (q.alpha_im != 0.0 || q.beta_im != 0.0))
+        return fail(TTX_EINVAL, "complex alpha or beta for a real element type");
+    r.alpha = Scalar(q.alpha, q.alpha_im);
+    r.beta = Scalar(q.beta, q.beta_im);
+    r.beta0 = beta_is_zero(r.p.dtype, r.beta);
     r.A = q.A;
     r.arena_out = q.B == nullptr;
     r.Bout = q.B;
@@ -366,12 +368,16 @@ static ttx_status submit_one(ttx_server* s, const ttx_request* rq, uint64_t* tic
         // plan outside the lock; arena outputs are 256-byte aligned, like the
         // probe pointer used here for the vector decision
         const void* out_probe = r.arena_out ? reinterpret_cast<void*>(uintptr_t(1) << 44) : r.Bout;
-        st = batch_describe(r.p, nullptr, r.beta0, r.A, r.Bin, const_cast<void*>(out_probe), r.alpha,
-                            r.beta, &r.desc, &r.cfg);
-        if (st != TTX_OK) return st;
         // a large request fills the device by itself: it runs alone with the
-        // per-call kernels (whole tile menu, tuned configs)
-        r.large = r.bytes >= kDirectBytes;
+        // per-call kernels (whole tile menu, tuned configs); so do complex and
+        // mixed-precision requests, which the persistent kernel does not take
+        const bool per_call_type = dtype_complex(r.p.dtype) || r.p.dtype_a != r.p.dtype;
+        if (!per_call_type) {
+            st = batch_describe(r.p, nullptr, r.beta0, r.A, r.Bin, const_cast<void*>(out_probe), r.alpha.re,
+                                r.beta.re, &r.desc, &r.cfg);
+            if (st != TTX_OK) return st;
+        }
+        r.large = r.bytes >= kDirectBytes || per_call_type;
         if (r.large && !table_lookup(r.p, r.beta0, &r.direct)) r.direct = default_config(r.p);
     }
     r.t_arrival = rq->arrival_ns > 0 ? rq->arrival_ns : now_ns();
@@ -627,11 +633,11 @@ ttx_status ttx_replay_sequential(int64_t count, const ttx_request* requests, con
         if (st != TTX_OK) return st;
         void* out = q.B ? q.B : scratch;   // (planning here is repeated by the cached path: cheap)
         if (!q.B && p.extent_b > scratch_bytes) return fail(TTX_EINVAL, "scratch too small");
-        const bool beta0 = beta_is_zero(p.dtype, q.beta);
+        const bool beta0 = beta_is_zero(p.dtype, Scalar(q.beta, q.beta_im));
         const void* Bin = q.B_in ? q.B_in : out;
         st = transpose_cached(q.dtype, q.n, q.perm, q.size, q.has_outer_a ? q.outer_a : nullptr,
-                              q.has_outer_b ? q.outer_b : nullptr, q.alpha, q.A, q.beta,
-                              beta0 ? nullptr : Bin, out, stream);
+                              q.has_outer_b ? q.outer_b : nullptr, Scalar(q.alpha, q.alpha_im), q.A,
+                              Scalar(q.beta, q.beta_im), beta0 ? nullptr : Bin, out, stream);
         if (st != TTX_OK) return st;
         if (hipStreamSynchronize(stream) != hipSuccess) return fail(TTX_EHIP, "sync failed");
         latencies_us[i] = (now_ns() - due) * 1e-3;

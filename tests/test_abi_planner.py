@@ -487,11 +487,27 @@ def test_mixed_argument_errors_need_no_gpu():
 
 
 @pytest.mark.parametrize("code", [ttx.C32, ttx.C64, ttx.F32_F64, ttx.C64_C32])
-def test_batch_takes_real_one_type_problems_only(code):
-    q = ttx.make_problem(code, (1, 0), (4, 5), 1.0, 1 << 40, 0.0, 1 << 41)
+def test_batch_plans_complex_and_mixed_problems_per_call(code):
+    """The persistent kernel takes FP32/FP64 problems; complex and mixed ones
+    get their per-call configs (and no tiles of the persistent kernel)."""
+    alpha = 0.5 - 1j if code in (ttx.C32, ttx.C64, ttx.C64_C32) else 1.0
+    q = ttx.make_problem(code, (1, 0), (40, 50), alpha, 1 << 40, 0.0, 1 << 41)
+    r = ttx.make_problem(ttx.F32, (1, 0), (40, 50), 1.0, 1 << 42, 0.0, 1 << 43)
+    cfgs, tiles = ttx.ttx_batch_plan([q, r])
+    assert tiles[0] == 0 and tiles[1] > 0
+    plan = ttx.ttx_plan_create(code, (1, 0), (40, 50))
+    try:
+        want = ttx.ttx_plan_describe(plan)["config"][1]
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    assert cfgs[0].as_dict() == want
+
+
+def test_batch_rejects_complex_scalars_for_real_problems():
+    q = ttx.make_problem(ttx.F64, (1, 0), (40, 50), 1j, 1 << 40, 0.0, 1 << 41)
     with pytest.raises(ttx.TTXError) as e:
         ttx.ttx_batch_plan([q])
-    assert e.value.status == ttx.EUNSUPPORTED
+    assert e.value.status == ttx.EINVAL
 
 
 # -- GEMM operand packing (host planning) ------------------------------------------------------

@@ -244,3 +244,25 @@ def test_server_replay_from_several_clients():
             ttx.ttx_server_replay_clients(s, reqs[:4], np.zeros(4, dtype=np.int64), 0)
         finally:
             ttx.ttx_server_destroy(s)
+
+
+def test_server_runs_complex_and_mixed_requests_alone():
+    """Complex and mixed-precision requests take the per-call path (a slot of
+    their own), whatever their size; real scalars only for real types."""
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=1 << 34, slots=2)
+    try:
+        tickets = []
+        for code, alpha in ((ttx.C64, 0.5 - 2j), (ttx.F32_F64, 1.5), (ttx.C32_C64, 1j)):
+            q = ttx.make_problem(code, (1, 0), (64, 64), alpha, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
+            tickets.append(ttx.ttx_server_submit(s, ttx.make_request(q, 0, False)))
+            tickets.append(ttx.ttx_server_submit(s, _req(size=(64, 64))))
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["completed"] == 6 and st["batches"] >= 4
+        assert all(ttx.ttx_server_poll(s, t) for t in tickets)
+        bad = ttx.make_problem(ttx.F64, (1, 0), (64, 64), 1j, FAKE_BASE, 0.0, FAKE_BASE + (1 << 20))
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_server_submit(s, ttx.make_request(bad, 0, False))
+        assert e.value.status == ttx.EINVAL
+    finally:
+        ttx.ttx_server_destroy(s)

@@ -250,3 +250,125 @@ def test_served_results_equal_alone_and_oracle():
         assert ttx.ttx_server_get_stats(s)["in_use_bytes"] == 0
     finally:
         ttx.ttx_server_destroy(s)
+
+
+# -- complex and mixed-precision problems in batches and in the server ----------------------
+def _typed_problems():
+    """(code, A dtype, B dtype, perm, size, alpha, beta) for a mixed list."""
+    from gpu_util import C32, C64, F64
+    return [
+        (ttx.F32, F32, F32, (1, 0), (300, 200), 1.3, 0.7),
+        (ttx.C32, C32, C32, (2, 0, 1), (40, 30, 20), 0.5 - 1.25j, 0.25 + 0.5j),
+        (ttx.F32_F64, F32, F64, (0, 2, 1), (24, 40, 30), -1.5, 0.0),
+        (ttx.C64_C32, C64, C32, (1, 0, 2), (33, 17, 9), 1j, 0j),
+        (ttx.F64, F64, F64, (2, 1, 0), (50, 60, 70), 2.0, -1.0),
+        (ttx.C64, C64, C64, (0, 1), (1000, 3), 1.0 + 0j, 1.0 + 0j),
+        (ttx.F64_F32, F64, F32, (1, 0), (129, 257), 0.75, 0.5),
+    ]
+
+
+class TypedBatch:
+    def __init__(self, seed):
+        import torch
+        from gpu_util import to_device
+        self.items = _typed_problems()
+        self.A, self.B0, self.dA, self.dB, self.pa, self.pb = [], [], [], [], [], []
+        for i, (code, da, db, perm, size, alpha, beta) in enumerate(self.items):
+            n = workloads.elements(size)
+            a = workloads.uniform(n, da, seed + 2 * i)
+            b = workloads.uniform(n, db, seed + 2 * i + 1)
+            ta, pa = to_device(a)
+            tb, pb = to_device(b)
+            self.A.append(a)
+            self.B0.append(b)
+            self.dA.append(ta)
+            self.dB.append(tb)
+            self.pa.append(pa)
+            self.pb.append(pb)
+        torch.cuda.synchronize()
+
+    def problems(self):
+        return [ttx.make_problem(code, perm, size, alpha, pa, beta, pb)
+                for (code, _, _, perm, size, alpha, beta), pa, pb in zip(self.items, self.pa, self.pb)]
+
+    def reset_b(self):
+        import torch
+        for d, b in zip(self.dB, self.B0):
+            d.copy_(torch.from_numpy(b))
+        torch.cuda.synchronize()
+
+    def results(self):
+        import torch
+        torch.cuda.synchronize()
+        return [d.cpu().numpy() for d in self.dB]
+
+    def oracle(self):
+        out = []
+        for (code, _, _, perm, size, alpha, beta), a, b in zip(self.items, self.A, self.B0):
+            r = b.copy()
+            assert oracle.transpose(perm, size, alpha, a, beta, r) == 0
+            out.append(r)
+        return out
+
+
+def test_batch_with_complex_and_mixed_problems():
+    import torch
+    tb = TypedBatch(seed=300)
+    ref = tb.oracle()
+    h = ttx.ttx_batch_create(tb.problems())
+    try:
+        info = ttx.ttx_batch_get_info(h)
+        assert info["count"] == 7 and info["per_call"] == 5   # all but the FP32 and FP64 ones
+        stream = ttx.current_stream()
+        ttx.ttx_batch_execute(h, stream)
+        got = tb.results()
+        for g, r, it in zip(got, ref, tb.items):
+            assert_parity(g, r, exact=False, what=str(it))
+        for rep in range(2):   # graph replays with eager work in between
+            tb.reset_b()
+            x = torch.ones(1 << 16, device="cuda") * rep
+            torch.cuda.synchronize()
+            ttx.ttx_batch_execute(h, stream)
+            assert _same(tb.results(), got), "replay %d" % rep
+            assert float(x.sum()) == float(rep * (1 << 16))
+        tb.reset_b()
+        ttx.ttx_batch_execute_direct(h, stream)
+        assert _same(tb.results(), got)
+        # the per-call path gives the same bits
+        tb.reset_b()
+        for (code, _, _, perm, size, alpha, beta), pa, pb in zip(tb.items, tb.pa, tb.pb):
+            ttx.ttx_transpose_c(code, len(perm), perm, size, None, None, alpha, pa, beta, pb, stream)
+        assert _same(tb.results(), got)
+        # new pointers: the graph is captured again
+        tb2 = TypedBatch(seed=700)
+        ttx.ttx_batch_update(h, tb2.problems(), stream)
+        ttx.ttx_batch_execute(h, stream)
+        for g, r in zip(tb2.results(), tb2.oracle()):
+            assert_parity(g, r, exact=False)
+        ttx.ttx_batch_tune(h, 4, 2)
+        tb2.reset_b()
+        ttx.ttx_batch_execute(h, stream)
+        for g, r in zip(tb2.results(), tb2.oracle()):
+            assert_parity(g, r, exact=False)
+    finally:
+        ttx.ttx_batch_destroy(h)
+
+
+def test_server_complex_and_mixed_requests_equal_alone():
+    tb = TypedBatch(seed=900)
+    ref = tb.oracle()
+    s = ttx.ttx_server_create(slots=2)
+    try:
+        tickets = [ttx.ttx_server_submit(s, ttx.make_request(q, 0, False)) for q in tb.problems()]
+        ttx.ttx_server_drain(s)
+        assert all(ttx.ttx_server_poll(s, t) for t in tickets)
+        got = tb.results()
+    finally:
+        ttx.ttx_server_destroy(s)
+    for g, r, it in zip(got, ref, tb.items):
+        assert_parity(g, r, exact=False, what=str(it))
+    tb.reset_b()
+    stream = ttx.current_stream()
+    for (code, _, _, perm, size, alpha, beta), pa, pb in zip(tb.items, tb.pa, tb.pb):
+        ttx.ttx_transpose_c(code, len(perm), perm, size, None, None, alpha, pa, beta, pb, stream)
+    assert _same(tb.results(), got)
