@@ -255,7 +255,9 @@ int ttx_tune_table_size(void);
  * (the file is created when missing), and from then on every tuning result
  * is also appended to it as one line under an exclusive file lock.  The
  * environment variable TTX_TUNE_DB attaches a file before the table is
- * first used.  Detach stops the appending (the table keeps its entries). */
+ * first used, and TTX_TUNE_TABLE names a table file that is only read then
+ * (the shipped per-architecture table, for instance).  Detach stops the
+ * appending (the table keeps its entries). */
 ttx_status ttx_tune_db_attach(const char *path);
 ttx_status ttx_tune_db_detach(void);
 

@@ -43,11 +43,16 @@ static const char* const kTableHeader =
     "[c<tile_c>] | usec\n";
 
 static ttx_status attach_db(const char* path);
+static ttx_status merge_file(const char* path);
 
-// The database named by TTX_TUNE_DB, attached once before the table is first used.
+// Before the table is first used: the table named by TTX_TUNE_TABLE is
+// loaded (read only; e.g. the shipped per-architecture table) and the
+// database named by TTX_TUNE_DB attached.
 static void attach_env_db() {
     static std::once_flag once;
     std::call_once(once, [] {
+        const char* table = std::getenv("TTX_TUNE_TABLE");
+        if (table && *table) (void)merge_file(table);
         const char* path = std::getenv("TTX_TUNE_DB");
         if (path && *path) (void)attach_db(path);
     });
@@ -265,6 +270,20 @@ static ttx_status read_table(const char* path, std::map<std::string, TableEntry>
     return TTX_OK;
 }
 
+// Merges a table file into the table, keeping the lowest time per key.
+static ttx_status merge_file(const char* path) {
+    std::map<std::string, TableEntry> loaded;
+    ttx_status st = read_table(path, &loaded);
+    if (st != TTX_OK) return st;
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    for (auto& kv : loaded) {
+        auto it = g_table.find(kv.first);
+        if (it == g_table.end() || kv.second.usec < it->second.usec) g_table[kv.first] = kv.second;
+    }
+    g_table_gen.fetch_add(1);
+    return TTX_OK;
+}
+
 static ttx_status attach_db(const char* path) {
     std::map<std::string, TableEntry> loaded;
     ttx_status st = read_table(path, &loaded);
@@ -319,6 +338,7 @@ ttx_status ttx_tune_table_save(const char* path) {
     if (!path) return fail(TTX_EINVAL, "NULL path");
     std::ofstream f(path);
     if (!f) return fail(TTX_EINVAL, "cannot open tune table for writing");
+    attach_env_db();
     std::lock_guard<std::mutex> lock(g_table_mu);
     f << kTableHeader;
     for (const auto& kv : g_table)
@@ -351,6 +371,7 @@ ttx_status ttx_tune_db_detach(void) {
 }
 
 ttx_status ttx_tune_table_clear(void) {
+    attach_env_db();
     std::lock_guard<std::mutex> lock(g_table_mu);
     g_table.clear();
     g_table_gen.fetch_add(1);
@@ -358,6 +379,7 @@ ttx_status ttx_tune_table_clear(void) {
 }
 
 int ttx_tune_table_size(void) {
+    attach_env_db();
     std::lock_guard<std::mutex> lock(g_table_mu);
     return int(g_table.size());
 }

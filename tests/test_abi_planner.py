@@ -582,3 +582,21 @@ def test_tune_db_from_the_environment_in_a_new_process(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert r.stdout.split() == ["1", "32"]
+
+
+def test_tune_table_from_the_environment_is_read_only(tmp_path):
+    import subprocess
+    import sys
+    table = str(tmp_path / "shipped.txt")
+    with open(table, "w") as f:
+        f.write(KEY_PLAIN + " | 3 32 16 256 1 1 1 3 0 2 1 | 12.5\n")
+    before = open(table).read()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r); import paper_1607_01249_amd as t; "
+            "print(t.ttx_tune_table_size()); p = t.ttx_plan_create(0, (2, 1, 0), (96, 128, 80)); "
+            "print(t.ttx_plan_describe(p)['config_from_table'][1])" % root)
+    r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, TTX_TUNE_TABLE=table),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["1", "1"]
+    assert open(table).read() == before
