@@ -555,27 +555,15 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
     Layout L;
     if (!make_layout(p, c.group_a, c.group_b, &L)) return f;
     if (L.staged) return f;   // staged tiles move single elements
-    bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
-    for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
-    for (int k = 0; k < L.gb; ++k) inB[L.memB[k]] = true;
+    // Menu tiles take 16-byte vectors wherever the tile's run is contiguous:
+    // the vectors need only element alignment (runs may start anywhere) and
+    // a run's last, partial vector is moved element by element.
     if (p.family == TTX_FAMILY_PRESERVED) {
-        inA[0] = inB[0] = true;
-        bool ok = p.dim[0].sa == 1 && p.dim[0].sb == 1 && c.tile_a % V == 0 && p.dim[0].size % V == 0 &&
-                  aligned16(A) && bptrs;
-        for (int d = 1; d < p.n && ok; ++d) ok = p.dim[d].sa % V == 0 && p.dim[d].sb % V == 0;
-        if (ok) f |= KF_VEC_A | KF_VEC_B;
+        if (p.dim[0].sa == 1 && p.dim[0].sb == 1 && c.tile_a % V == 0) f |= KF_VEC_A | KF_VEC_B;
         return f;
     }
-    // A side: runs along the A-side super index, every other A stride a
-    // multiple of the vector width; B side likewise
-    bool okA = p.dim[L.a].sa == 1 && c.tile_a % VA == 0 && L.SA % VA == 0 && aligned16(A);
-    for (int d = 0; d < p.n && okA; ++d)
-        if (!inA[d]) okA = p.dim[d].sa % VA == 0;
-    bool okB = p.dim[L.b].sb == 1 && c.tile_b % VB == 0 && L.SB % VB == 0 && bptrs;
-    for (int d = 0; d < p.n && okB; ++d)
-        if (!inB[d]) okB = p.dim[d].sb % VB == 0;
-    if (okA) f |= KF_VEC_A;
-    if (okB) f |= KF_VEC_B;
+    if (p.dim[L.a].sa == 1 && c.tile_a % VA == 0) f |= KF_VEC_A;
+    if (p.dim[L.b].sb == 1 && c.tile_b % VB == 0) f |= KF_VEC_B;
     return f;
 }
 
@@ -640,21 +628,8 @@ static bool vector_shape(const Problem& p, const Layout& L, int ta, int tb) {
     const int VA = 16 / elem_bytes(p.dtype_a), VB = 16 / elem_bytes(p.dtype);
     const int V = VA < VB ? VA : VB;
     if (L.staged) return false;
-    bool inA[kMaxDims] = {}, inB[kMaxDims] = {};
-    for (int k = 0; k < L.ga; ++k) inA[L.memA[k]] = true;
-    for (int k = 0; k < L.gb; ++k) inB[L.memB[k]] = true;
-    if (p.family == TTX_FAMILY_PRESERVED) {
-        bool ok = p.dim[0].sa == 1 && p.dim[0].sb == 1 && ta % V == 0 && p.dim[0].size % V == 0;
-        for (int d = 1; d < p.n && ok; ++d) ok = p.dim[d].sa % V == 0 && p.dim[d].sb % V == 0;
-        return ok;
-    }
-    bool ok = p.dim[L.a].sa == 1 && ta % VA == 0 && L.SA % VA == 0 && p.dim[L.b].sb == 1 && tb % VB == 0 &&
-              L.SB % VB == 0;
-    for (int d = 0; d < p.n && ok; ++d) {
-        if (!inA[d]) ok = p.dim[d].sa % VA == 0;
-        if (ok && !inB[d]) ok = p.dim[d].sb % VB == 0;
-    }
-    return ok;
+    if (p.family == TTX_FAMILY_PRESERVED) return p.dim[0].sa == 1 && p.dim[0].sb == 1 && ta % V == 0;
+    return p.dim[L.a].sa == 1 && ta % VA == 0 && p.dim[L.b].sb == 1 && tb % VB == 0;
 }
 
 // Dense tiles: rows of n0, tx x ty rows per plane, tz planes (along index z,

@@ -126,6 +126,69 @@ __device__ __forceinline__ void st(T* p, const vec_t<T, N>& v, bool nt) {
         *reinterpret_cast<R*>(p) = r;
 }
 
+// The same bytes with only the element's alignment: a 16-byte vector that
+// starts at any element boundary (global memory takes dword-aligned
+// multi-dword accesses, so these are still single 16-byte instructions).
+template <typename T, int N>
+struct RawU {
+    using type = typename RawOf<T, N>::type;
+};
+template <>
+struct RawU<float, 4> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct RawU<float, 2> {
+    typedef float type __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <>
+struct RawU<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <>
+struct RawU<cf32, 2> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(8)));
+};
+
+// Up to N elements at p (element-aligned): the whole vector when n >= N,
+// else elements 0..n-1 one by one (the rest of v is left as it was), so that
+// a run whose length is not a multiple of N never reads or writes past it.
+template <typename T, int N>
+__device__ __forceinline__ void ld_part(vec_t<T, N>& v, const T* p, int n) {
+    if constexpr (N == 1) {
+        v = ld<T, 1>(p);
+    } else {
+        using R = typename RawU<T, N>::type;
+        if (n >= N) {
+            v = __builtin_bit_cast(vec_t<T, N>, *reinterpret_cast<const R*>(p));
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (j < n) set_lane<T, N>(v, j, p[j]);
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void st_part(T* p, const vec_t<T, N>& v, int n, bool nt) {
+    if constexpr (N == 1) {
+        st<T, 1>(p, v, nt);
+    } else {
+        using R = typename RawU<T, N>::type;
+        if (n >= N) {
+            const R r = __builtin_bit_cast(R, v);
+            if (nt)
+                __builtin_nontemporal_store(r, reinterpret_cast<R*>(p));
+            else
+                *reinterpret_cast<R*>(p) = r;
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (j < n) p[j] = lane<T, N>(v, j);
+        }
+    }
+}
+
 // Complex product s*x: re = s.re*x.re - s.im*x.im, im = s.re*x.im + s.im*x.re,
 // every product and sum rounded on its own (contraction is off in this file).
 template <typename C>
@@ -263,8 +326,9 @@ constexpr int pow2_ceil(int x) {
 // indices, contiguous in B): element (x0 + x, y0 + y) for x < ea, y < eb is
 // A[oa + x*sAa + gB.offset(y0 + y)] -> B[ob + y*sBb + gA.offset(x0 + x)].
 // VA / VB are the vector widths along x in A and along y in B (VA > 1
-// implies sAa == 1, VB > 1 implies sBb == 1).  The LDS tile has TB rows of
-// TA + 1 elements.
+// implies sAa == 1, VB > 1 implies sBb == 1); vectors need only element
+// alignment, and a vector that would run past the end of the super index is
+// moved element by element.  The LDS tile has TB rows of TA + 1 elements.
 template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T>
 struct MovedTile {
     static constexpr bool kUsesLds = true;
@@ -291,7 +355,7 @@ struct MovedTile {
         const S* pa = a.A + c.oa + int64_t(xa) * a.sAa;
 #pragma unroll
         for (int i = 0; i < NA; ++i)
-            if (live_a && ya + i * RA < c.eb) ra[i] = ld<S, VA>(pa + a.gB.offset(c.y0 + ya + i * RA));
+            if (live_a && ya + i * RA < c.eb) ld_part<S, VA>(ra[i], pa + a.gB.offset(c.y0 + ya + i * RA), c.ea - xa);
         if constexpr (!BETA0) {
             const int yb = (tid % PB) * VB, xb = tid / PB;
             const bool live_b = (tid % PB) < LB && yb < c.eb;
@@ -299,7 +363,7 @@ struct MovedTile {
 #pragma unroll
             for (int i = 0; i < NB; ++i)
                 if (live_b && xb + i * RB < c.ea)
-                    rb[i] = ld<T, VB>(a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB));
+                    ld_part<T, VB>(rb[i], a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB), c.eb - yb);
         }
     }
 
@@ -343,7 +407,7 @@ struct MovedTile {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int x = xb + i * RB;
-            if (live_b && x < c.ea) st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], nt);
+            if (live_b && x < c.ea) st_part<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], c.eb - yb, nt);
         }
     }
 
@@ -362,8 +426,8 @@ struct MovedTile {
                 vec_t<T, VB> v;
 #pragma unroll
                 for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
-                st<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
-                          nt);
+                st_part<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
+                               c.eb - yb, nt);
             }
         }
     }
@@ -397,8 +461,8 @@ struct PreservedTile {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             if (live && y0 + i * R < c.eb) {
-                ra[i] = ld<S, V>(a.A + off_a + i * int64_t(R) * a.sAb);
-                if constexpr (!BETA0) rb[i] = ld<T, V>(a.Bsrc + off_b + i * int64_t(R) * a.sBb);
+                ld_part<S, V>(ra[i], a.A + off_a + i * int64_t(R) * a.sAb, c.ea - x);
+                if constexpr (!BETA0) ld_part<T, V>(rb[i], a.Bsrc + off_b + i * int64_t(R) * a.sBb, c.ea - x);
             }
         }
     }
@@ -416,7 +480,7 @@ struct PreservedTile {
         const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (live && y0 + i * R < c.eb) st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], nt);
+            if (live && y0 + i * R < c.eb) st_part<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], c.ea - x, nt);
     }
 
     // finish and store in one pass
@@ -429,8 +493,8 @@ struct PreservedTile {
 #pragma unroll
         for (int i = 0; i < N; ++i)
             if (live && y0 + i * R < c.eb)
-                st<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
-                         epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta), nt);
+                st_part<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
+                              epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta), c.ea - x, nt);
     }
 };
 
