@@ -75,6 +75,8 @@ def parse_args():
     ap.add_argument("--literal", action="store_true",
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
+    ap.add_argument("--no-specialised", action="store_true",
+                    help="skip the comparison with size-specialised (run-time compiled) kernels")
     ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
     ap.add_argument("--no-types", action="store_true",
                     help="skip the complex (c, z) and mixed-precision (sd, ds, cz, zc) cases")
@@ -378,6 +380,56 @@ def bench_batched(torch, ttx, reps=20, tune=True):
                              variants=info["variants_used"], tuned=info["tuned"],
                              tune_seconds=round(tune_s, 1), launch="1 persistent kernel per hipGraph replay"),
                 speedup=round(pc_med / b_med, 2))
+
+
+def bench_specialised(torch, ttx, cases, d2d, stream, reps=10):
+    """The step's cases through plans, each with its generic kernel and with
+    its size-specialised kernel (compiled at run time, sizes as constants):
+    median of `reps` launches each, alternating, and the compile time."""
+    out, t_gen, t_spec, step_bytes, compile_s = [], 0.0, 0.0, 0, 0.0
+    for c in cases:
+        plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
+        spec = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
+        try:
+            z = c["beta"] == 0
+            t0 = time.perf_counter()
+            ttx.ttx_plan_specialise(spec, z)
+            compile_s += time.perf_counter() - t0
+            A, B = c["A"].data_ptr(), c["B"].data_ptr()
+
+            def gen():
+                ttx.ttx_plan_execute(plan, c["alpha"], A, c["beta"], B, stream)
+
+            def sp():
+                ttx.ttx_plan_execute(spec, c["alpha"], A, c["beta"], B, stream)
+
+            for f in (gen, sp):   # warm-up
+                f()
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+            for k in range(reps):
+                ev[k][0].record()
+                gen()
+                ev[k][1].record()
+                ev[k][2].record()
+                sp()
+                ev[k][3].record()
+            torch.cuda.synchronize()
+            g = float(np.median([e[0].elapsed_time(e[1]) for e in ev])) * 1e-3
+            s = float(np.median([e[2].elapsed_time(e[3]) for e in ev])) * 1e-3
+        finally:
+            ttx.ttx_plan_destroy(plan)
+            ttx.ttx_plan_destroy(spec)
+        t_gen += g
+        t_spec += s
+        step_bytes += c["bytes"]
+        out.append(dict(case=c["name"], generic_us=round(g * 1e6, 1), specialised_us=round(s * 1e6, 1),
+                        speedup=round(g / s, 3), specialised_pct_of_d2d=round(100 * c["bytes"] / s / 1e9 / d2d, 1)))
+    sp_all = [o["speedup"] for o in out]
+    return dict(step_GBps_generic=round(step_bytes / t_gen / 1e9, 1),
+                step_GBps_specialised=round(step_bytes / t_spec / 1e9, 1),
+                speedup_min=min(sp_all), speedup_median=float(np.median(sp_all)), speedup_max=max(sp_all),
+                compile_seconds=round(compile_s, 2), note="sum of per-launch medians (events around each launch)",
+                per_case=out)
 
 
 def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False):
@@ -743,6 +795,11 @@ def main():
             json.dump(dict(kernel=dom_name, bytes_per_launch=bytes_per_launch,
                            avg_launch_us=roofline["avg_launch_us"]), f)
 
+    specialised = None
+    if not args.no_specialised and not args.profile_run:
+        log("size-specialised kernels")
+        specialised = bench_specialised(torch, ttx, cases, d2d, stream)
+
     for c in cases:   # the large cases' buffers are not needed any more
         c.pop("A", None)
         c.pop("B", None)
@@ -782,7 +839,8 @@ def main():
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
-        roofline=roofline, cpu_baseline=cpu, batched=batched, served=served, other_types=cplx,
+        roofline=roofline, cpu_baseline=cpu, specialised=specialised, batched=batched, served=served,
+        other_types=cplx,
         packing=packing,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),

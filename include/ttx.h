@@ -166,6 +166,7 @@ typedef struct ttx_plan_info {
     int64_t extent_b_bytes;
     ttx_config config[2];               /* [0]: beta != 0, [1]: beta == 0 */
     int config_from_table[2];           /* 1 when the config came from the tune table */
+    int specialised[2];                 /* 1 when a size-specialised kernel is attached */
 } ttx_plan_info;
 
 /* -- errors --------------------------------------------------------------- */
@@ -224,6 +225,32 @@ ttx_status ttx_plan_destroy(ttx_plan *plan);
  * NUL-terminated into buf (len bytes).  Host only. */
 ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A, const void *B,
                                 char *buf, int len);
+
+/* -- size-specialised kernels (Sec. 2.1) -------------------------------------
+ * A solution generated by the paper's compiler carries the sizes of its
+ * transposition as compile-time constants (known trip counts); the
+ * pre-instantiated kernels here take them as run-time arguments instead.
+ * ttx_plan_specialise compiles, at run time with hipRTC, the plan's kernel
+ * for one beta class (beta_is_zero = 1: beta == 0) with every extent,
+ * stride, tile count and index divisor of the plan's problem and config as
+ * a constant, and loads it on the current device.  Later executions of the
+ * plan in that beta class, on that device, launch it when the tensors are
+ * aligned as for the plan's vector paths (16 bytes suffices; hipMalloc'd
+ * tensors are); other executions use the generic kernel.  Both compute the
+ * same bits.  Moved- and preserved-family problems only: for empty and
+ * single-index problems nothing is attached (TTX_OK).  ttx_plan_set_config
+ * drops the kernel of that beta class.  Kernels stay loaded until the
+ * process ends and are shared by plans of the same problem; when the
+ * environment variable TTX_JIT_CACHE names a directory, code objects are
+ * also kept there (created if missing) and reused by later processes.
+ * Needs a GPU; blocks the caller while compiling (about a second).
+ * Errors: TTX_EINVAL (NULL plan), TTX_EHIP (compilation or loading failed;
+ * ttx_last_error starts with the compiler log). */
+ttx_status ttx_plan_specialise(ttx_plan *plan, int beta_is_zero);
+/* The translation unit ttx_plan_specialise compiles for the plan (host
+ * only), NUL-terminated into buf (len bytes).  TTX_EINVAL when buf is too
+ * small (about 8 KB suffices) or the problem has nothing to specialise. */
+ttx_status ttx_plan_specialised_source(const ttx_plan *plan, int beta_is_zero, char *buf, int len);
 
 /* -- autotuner (Sec. 2.1 stages 2-6, Sec. 2.3) --------------------------------
  * Enumerates every candidate (tile shape from the kernel menu x loop order

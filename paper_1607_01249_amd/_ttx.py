@@ -63,7 +63,8 @@ class PlanInfo(ctypes.Structure):
                 ("perm", ctypes.c_int * MAX_DIMS), ("size", i64 * MAX_DIMS),
                 ("stride_a", i64 * MAX_DIMS), ("stride_b", i64 * MAX_DIMS),
                 ("elements", i64), ("extent_a_bytes", i64), ("extent_b_bytes", i64),
-                ("config", Config * 2), ("config_from_table", ctypes.c_int * 2)]
+                ("config", Config * 2), ("config_from_table", ctypes.c_int * 2),
+                ("specialised", ctypes.c_int * 2)]
 
 
 class Problem(ctypes.Structure):
@@ -183,6 +184,8 @@ def _declare(L):
         "ttx_plan_set_config": ([vp, S, ctypes.POINTER(Config)], S),
         "ttx_plan_destroy": ([vp], S),
         "ttx_plan_kernel_name": ([vp, ctypes.c_double, vp, vp, ctypes.c_char_p, S], S),
+        "ttx_plan_specialise": ([vp, S], S),
+        "ttx_plan_specialised_source": ([vp, S, ctypes.c_char_p, S], S),
         "ttx_tune": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_candidates": ([S, S, ip, i64p, i64p, i64p, S, ctypes.POINTER(Config),
                                  ctypes.POINTER(ctypes.c_double), S, ip], S),
@@ -291,7 +294,8 @@ def ttx_plan_describe(plan):
                 extent_b_bytes=info.extent_b_bytes,
                 config=[info.config[0].as_dict(), info.config[1].as_dict()],
                 config_raw=[info.config[0], info.config[1]],
-                config_from_table=list(info.config_from_table))
+                config_from_table=list(info.config_from_table),
+                specialised=list(info.specialised))
 
 
 def ttx_plan_set_config(plan, beta_is_zero, config):
@@ -301,6 +305,16 @@ def ttx_plan_set_config(plan, beta_is_zero, config):
 def ttx_plan_kernel_name(plan, beta, A, B):
     buf = ctypes.create_string_buffer(256)
     _check(lib().ttx_plan_kernel_name(plan, float(beta), A, B, buf, 256))
+    return buf.value.decode()
+
+
+def ttx_plan_specialise(plan, beta_is_zero):
+    return _check(lib().ttx_plan_specialise(plan, int(bool(beta_is_zero))))
+
+
+def ttx_plan_specialised_source(plan, beta_is_zero):
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().ttx_plan_specialised_source(plan, int(bool(beta_is_zero)), buf, 1 << 16))
     return buf.value.decode()
 
 

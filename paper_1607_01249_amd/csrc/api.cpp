@@ -13,6 +13,7 @@ struct ttx_plan {
     int from_table[2];
     bool user_set[2];
     uint64_t table_gen;
+    const ttx::JitKernel* jit[2];   // size-specialised kernels ([beta_is_zero]; owned by the JIT cache)
 };
 
 namespace ttx {
@@ -89,8 +90,16 @@ static ttx_status execute(const ttx_plan* plan, const Scalar& alpha, const void*
     const bool beta0 = beta_is_zero(p.dtype, beta);
     ttx_status st = check_pointers(p, A, Bin, Bout, beta0);
     if (st != TTX_OK) return st;
-    hipError_t e = launch_tiles(p, plan->cfg[beta0 ? 1 : 0], beta0, A, beta0 ? nullptr : Bin, Bout,
-                                alpha, beta, stream);
+    const int z = beta0 ? 1 : 0;
+    if (plan->jit[z]) {
+        TiledLaunch L;
+        if (prepare_tiled(p, plan->cfg[z], beta0, A, Bin, Bout, alpha, beta, &L) && jit_matches(*plan->jit[z], L)) {
+            const hipError_t e = jit_launch(*plan->jit[z], L, stream);
+            if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            return TTX_OK;
+        }
+    }
+    hipError_t e = launch_tiles(p, plan->cfg[z], beta0, A, beta0 ? nullptr : Bin, Bout, alpha, beta, stream);
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return TTX_OK;
 }
@@ -212,6 +221,7 @@ ttx_status ttx_plan_describe(const ttx_plan* plan, ttx_plan_info* info) {
     for (int z = 0; z < 2; ++z) {
         info->config[z] = plan->cfg[z];
         info->config_from_table[z] = plan->from_table[z];
+        info->specialised[z] = plan->jit[z] != nullptr;
     }
     return TTX_OK;
 }
@@ -224,6 +234,48 @@ ttx_status ttx_plan_set_config(ttx_plan* plan, int beta_is_zero, const ttx_confi
     plan->cfg[z] = *config;
     plan->user_set[z] = true;
     plan->from_table[z] = 0;
+    plan->jit[z] = nullptr;
+    return TTX_OK;
+}
+
+// Stand-in pointers for specialisation: aligned for every vector path (the
+// kernel flags depend only on alignment), never dereferenced.
+static void* fake_ptr(uintptr_t at) { return reinterpret_cast<void*>(at); }
+
+static ttx_status specialised_launch(const ttx_plan* plan, int beta_is_zero, TiledLaunch* L) {
+    const Problem& p = plan->prob;
+    const bool beta0 = beta_is_zero != 0;
+    if (!prepare_tiled(p, plan->cfg[beta0 ? 1 : 0], beta0, fake_ptr(1u << 20), beta0 ? nullptr : fake_ptr(2u << 20),
+                       fake_ptr(3u << 20), Scalar(1.0), Scalar(beta0 ? 0.0 : 1.0), L))
+        return fail(TTX_EINVAL, "nothing to specialise (empty or single-index problem)");
+    return TTX_OK;
+}
+
+ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero) {
+    if (!plan) return fail(TTX_EINVAL, "NULL argument");
+    const int z = beta_is_zero ? 1 : 0;
+    if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) {
+        plan->jit[z] = nullptr;
+        return TTX_OK;
+    }
+    TiledLaunch L;
+    ttx_status st = specialised_launch(plan, z, &L);
+    if (st != TTX_OK) return st;
+    const JitKernel* k = nullptr;
+    st = jit_kernel(L, &k);
+    if (st != TTX_OK) return st;
+    plan->jit[z] = k;
+    return TTX_OK;
+}
+
+ttx_status ttx_plan_specialised_source(const ttx_plan* plan, int beta_is_zero, char* buf, int len) {
+    if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
+    TiledLaunch L;
+    ttx_status st = specialised_launch(plan, beta_is_zero, &L);
+    if (st != TTX_OK) return st;
+    const std::string src = jit_source(L);
+    if (int64_t(src.size()) >= int64_t(len)) return fail(TTX_EINVAL, "buffer too small");
+    std::memcpy(buf, src.c_str(), src.size() + 1);
     return TTX_OK;
 }
 

@@ -18,6 +18,7 @@
 
 #include "menu.h"
 #include "tile_kernels.h"
+#include "ttx_internal.h"
 
 struct ttx_batch {
     std::vector<ttx::Problem> prob;

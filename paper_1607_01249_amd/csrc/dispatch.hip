@@ -2,6 +2,7 @@
 // bandwidth-ceiling kernels used for measurement.
 #include <cstdio>
 #include <mutex>
+#include <new>
 #include <type_traits>
 
 #include "registry.h"
@@ -76,122 +77,167 @@ static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0,
     return hipGetLastError();
 }
 
+// Calls f with values of B's and A's element types for any element code,
+// the internal wide units included.
+template <typename F>
+static bool with_all_types(int code, F&& f) {
+    switch (code) {
+        case kWideF32x4: f(f32x4{}, f32x4{}); return true;
+        case kWideF64x2: f(f64x2{}, f64x2{}); return true;
+        case kWideF32x2: f(f32x2{}, f32x2{}); return true;
+        default: return with_types(code, [&](auto t, auto s) { f(t, s); return hipSuccess; }) == hipSuccess;
+    }
+}
+
 template <typename T, typename S>
-static hipError_t launch_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A,
-                               const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
-                               hipStream_t stream) {
-    TileArgs<T, S> a;
-    build_grid(p, c, &a);
-    a.A = static_cast<const S*>(A);
-    a.Bsrc = static_cast<const T*>(Bsrc);
-    a.Bdst = static_cast<T*>(Bdst);
-    a.alpha = scalar_as<T>(alpha);
-    a.beta = scalar_as<T>(beta);
-    a.flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
-    if (config_is_dense(c)) {
-        const uint32_t full = dense_grid(p.code, beta0);
-        const uint32_t grid = a.g.ntiles < full ? a.g.ntiles : full;
-        return dense_launcher(p.code, beta0)(&a, grid, stream);
-    }
-    if (config_is_staged(c)) {
-        const StagedRow* rows;
-        const int nr = staged_rows(p.code, beta0, &rows);
-        const int lanes = staged_lanes(p.dim[0].size);
-        for (int i = 0; i < nr; ++i) {
-            if (rows[i].n0_max == lanes && rows[i].tx == c.tile_a && rows[i].ty == c.tile_b) {
-                uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
-                return rows[i].fn(&a, grid, stream);
-            }
-        }
-        return hipErrorInvalidValue;
-    }
-    const LauncherRow* table;
-    int n;
-    if (p.family == TTX_FAMILY_MOVED) {
-        n = moved_rows(p.code, beta0, &table);
-    } else {
-        n = preserved_rows(p.code, beta0, &table);
-    }
-    const int variant = a.flags & (KF_VEC_A | KF_VEC_B);
-    for (int i = 0; i < n; ++i) {
-        if (table[i].ta == c.tile_a && table[i].tb == c.tile_b) {
-            uint32_t grid = a.g.ntiles < kMaxGrid ? a.g.ntiles : kMaxGrid;
-            return table[i].fn[variant](&a, grid, stream);
-        }
-    }
-    return hipErrorInvalidValue;
+static void fill_args(const Problem& p, const ttx_config& c, bool beta0, const void* A, const void* Bsrc,
+                      void* Bdst, const Scalar& alpha, const Scalar& beta, TiledLaunch* L) {
+    static_assert(sizeof(TileArgs<T, S>) <= sizeof(L->args), "argument block too small");
+    TileArgs<T, S>* a = new (L->args) TileArgs<T, S>();
+    build_grid(p, c, a);
+    a->A = static_cast<const S*>(A);
+    a->Bsrc = static_cast<const T*>(Bsrc);
+    a->Bdst = static_cast<T*>(Bdst);
+    a->alpha = scalar_as<T>(alpha);
+    a->beta = scalar_as<T>(beta);
+    a->flags = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+    L->args_bytes = sizeof(TileArgs<T, S>);
+    L->flags = a->flags;
+    L->ntiles = a->g.ntiles;
 }
 
 static bool aligned_to(const void* ptr, uintptr_t n) { return reinterpret_cast<uintptr_t>(ptr) % n == 0; }
+
+bool prepare_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A, const void* Bsrc,
+                   void* Bdst, const Scalar& alpha, const Scalar& beta, TiledLaunch* L) {
+    if (p.family != TTX_FAMILY_MOVED && p.family != TTX_FAMILY_PRESERVED) return false;
+    if (beta0) Bsrc = nullptr;
+    if (config_is_wide(c)) {
+        // dense tiles over whole units of the kept rows: one element per unit
+        Problem w;
+        if (!widen(p, &w)) return false;
+        const uintptr_t ub = uintptr_t(elem_bytes(w.dtype));
+        if (!aligned_to(A, ub) || !aligned_to(Bdst, ub) || (Bsrc && !aligned_to(Bsrc, ub)))
+            return prepare_tiled(p, default_config_elementwise(p), beta0, A, Bsrc, Bdst, alpha, beta, L);
+        L->p = w;
+        L->c = c;
+        L->c.flags &= ~TTX_CFG_WIDE;
+    } else {
+        L->p = p;
+        L->c = c;
+    }
+    L->beta0 = beta0;
+    const Problem& q = L->p;
+    const ttx_config& k = L->c;
+    if (!with_all_types(q.code, [&](auto t, auto s) {
+            fill_args<decltype(t), decltype(s)>(q, k, beta0, A, Bsrc, Bdst, alpha, beta, L);
+        }))
+        return false;
+    const int VA = 16 / elem_bytes(q.dtype_a), VB = 16 / elem_bytes(q.dtype);
+    L->va = L->vb = 1;
+    L->n0 = 0;
+    L->cap = 0;
+    uint32_t limit = kMaxGrid;
+    if (config_is_dense(k)) {
+        L->kind = kTileDense;
+        L->cap = dense_cap(q.dtype);
+        limit = dense_grid(q.code, beta0);
+    } else if (config_is_staged(k)) {
+        L->kind = kTileStaged;
+        L->n0 = staged_lanes(q.dim[0].size);
+    } else if (q.family == TTX_FAMILY_MOVED) {
+        L->kind = kTileMoved;
+        if ((L->flags & KF_VEC_A) && VA > 1 && k.tile_a % VA == 0) L->va = VA;
+        if ((L->flags & KF_VEC_B) && VB > 1 && k.tile_b % VB == 0) L->vb = VB;
+    } else {
+        L->kind = kTilePreserved;
+        const int V = VA < VB ? VA : VB;
+        if ((L->flags & KF_VEC_A) && (L->flags & KF_VEC_B) && V > 1 && k.tile_a % V == 0) L->va = L->vb = V;
+    }
+    L->grid = L->ntiles < limit ? L->ntiles : limit;
+    return true;
+}
+
+// The generic (pre-instantiated) kernel for a prepared launch.
+static hipError_t launch_prepared(const TiledLaunch& L, hipStream_t stream) {
+    const ttx_config& c = L.c;
+    if (L.kind == kTileDense) return dense_launcher(L.p.code, L.beta0)(L.args, L.grid, stream);
+    if (L.kind == kTileStaged) {
+        const StagedRow* rows;
+        const int nr = staged_rows(L.p.code, L.beta0, &rows);
+        for (int i = 0; i < nr; ++i)
+            if (rows[i].n0_max == L.n0 && rows[i].tx == c.tile_a && rows[i].ty == c.tile_b)
+                return rows[i].fn(L.args, L.grid, stream);
+        return hipErrorInvalidValue;
+    }
+    const LauncherRow* table;
+    const int n = L.kind == kTileMoved ? moved_rows(L.p.code, L.beta0, &table) : preserved_rows(L.p.code, L.beta0, &table);
+    const int variant = L.flags & (KF_VEC_A | KF_VEC_B);
+    for (int i = 0; i < n; ++i)
+        if (table[i].ta == c.tile_a && table[i].tb == c.tile_b) return table[i].fn[variant](L.args, L.grid, stream);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream) {
     if (p.family == TTX_FAMILY_EMPTY) return hipSuccess;
-    if (config_is_wide(c)) {
-        // dense tiles over whole units of the kept rows: one element per unit
-        Problem w;
-        if (!widen(p, &w)) return hipErrorInvalidValue;
-        const uintptr_t ub = uintptr_t(elem_bytes(w.dtype));
-        if (!aligned_to(A, ub) || !aligned_to(Bdst, ub) || (Bsrc && !aligned_to(Bsrc, ub)))
-            return launch_tiles(p, default_config_elementwise(p), beta0, A, Bsrc, Bdst, alpha, beta, stream);
-        ttx_config cw = c;
-        cw.flags &= ~TTX_CFG_WIDE;
-        switch (w.code) {
-            case kWideF32x4: return launch_tiled<f32x4, f32x4>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-            case kWideF64x2: return launch_tiled<f64x2, f64x2>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-            default: return launch_tiled<f32x2, f32x2>(w, cw, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-        }
+    if (p.family == TTX_FAMILY_FLAT) {
+        return with_types(p.code, [&](auto t, auto s) {
+            return launch_flat<decltype(t), decltype(s)>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
+        });
     }
-    return with_types(p.code, [&](auto t, auto s) {
-        using T = decltype(t);
-        using S = decltype(s);
-        if (p.family == TTX_FAMILY_FLAT) return launch_flat<T, S>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-        return launch_tiled<T, S>(p, c, beta0, A, Bsrc, Bdst, alpha, beta, stream);
-    });
+    TiledLaunch L;
+    if (!prepare_tiled(p, c, beta0, A, Bsrc, Bdst, alpha, beta, &L)) return hipErrorInvalidValue;
+    return launch_prepared(L, stream);
+}
+
+const char* element_type_name(int dtype) {
+    switch (dtype) {
+        case TTX_F32: return "float";
+        case TTX_F64: return "double";
+        case TTX_C32: return "ttx::cf32";
+        case TTX_C64: return "ttx::cf64";
+        case kWideF32x4: return "ttx::f32x4";
+        case kWideF64x2: return "ttx::f64x2";
+        case kWideF32x2: return "ttx::f32x2";
+        default: return "?";
+    }
 }
 
 std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, const void* Bdst) {
     if (p.family == TTX_FAMILY_EMPTY) return "";
-    if (config_is_wide(c)) {
-        Problem w;
-        const uintptr_t ub = widen(p, &w) ? uintptr_t(elem_bytes(w.dtype)) : 0;
-        if (!ub || !aligned_to(A, ub) || !aligned_to(Bdst, ub) || (Bsrc && !aligned_to(Bsrc, ub)))
-            return kernel_name(p, default_config_elementwise(p), beta0, A, Bsrc, Bdst);
-        static const char* const kWideName[] = {"ttx::f32x4", "ttx::f64x2", "ttx::f32x2"};
-        char buf[96];
-        std::snprintf(buf, sizeof(buf), "k_dense<%s, %s, %d>", kWideName[w.dtype - kWideF32x4],
-                      beta0 ? "true" : "false", dense_cap(w.dtype));
-        return buf;
-    }
-    static const char* const kTypeName[] = {"float", "double", "ttx::cf32", "ttx::cf64"};
     // the same-type kernels are k_<kind><T, ...>; mixed ones k_<kind>_x<T, S, ...>
-    char ts[64];
-    const bool mixed = p.dtype_a != p.dtype;
-    if (mixed)
-        std::snprintf(ts, sizeof(ts), "_x<%s, %s", kTypeName[p.dtype], kTypeName[p.dtype_a]);
-    else
-        std::snprintf(ts, sizeof(ts), "<%s", kTypeName[p.dtype]);
+    auto types = [](const Problem& q) {
+        std::string ts = q.dtype_a != q.dtype ? "_x<" : "<";
+        ts += element_type_name(q.dtype);
+        if (q.dtype_a != q.dtype) ts += std::string(", ") + element_type_name(q.dtype_a);
+        return ts;
+    };
     const char* z = beta0 ? "true" : "false";
-    const int VA = 16 / elem_bytes(p.dtype_a), VB = 16 / elem_bytes(p.dtype);
-    const int V = VA < VB ? VA : VB;
-    const int f = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
     char buf[160];
     if (p.family == TTX_FAMILY_FLAT) {
-        std::snprintf(buf, sizeof(buf), "k_flat%s, %s>", ts, z);
-    } else if (config_is_dense(c)) {
-        std::snprintf(buf, sizeof(buf), "k_dense%s, %s, %d>", ts, z, dense_cap(p.dtype));
-    } else if (p.family == TTX_FAMILY_MOVED) {
-        const int va = (f & KF_VEC_A) && VA > 1 && c.tile_a % VA == 0 ? VA : 1;
-        const int vb = (f & KF_VEC_B) && VB > 1 && c.tile_b % VB == 0 ? VB : 1;
-        std::snprintf(buf, sizeof(buf), "k_moved%s, %s, %d, %d, %d, %d>", ts, z, c.tile_a, c.tile_b, va, vb);
-    } else if (config_is_staged(c)) {
-        std::snprintf(buf, sizeof(buf), "k_staged%s, %s, %d, %d, %d>", ts, z, staged_lanes(p.dim[0].size),
-                      c.tile_a, c.tile_b);
-    } else {
-        const int v = (f & KF_VEC_A) && V > 1 && c.tile_a % V == 0 ? V : 1;
-        std::snprintf(buf, sizeof(buf), "k_preserved%s, %s, %d, %d, %d>", ts, z, c.tile_a, c.tile_b, v);
+        std::snprintf(buf, sizeof(buf), "k_flat%s, %s>", types(p).c_str(), z);
+        return buf;
+    }
+    TiledLaunch L;
+    if (!prepare_tiled(p, c, beta0, A, Bsrc, const_cast<void*>(Bdst), Scalar(1.0), Scalar(0.0), &L)) return "";
+    const std::string ts = types(L.p);
+    switch (L.kind) {
+        case kTileDense:
+            std::snprintf(buf, sizeof(buf), "k_dense%s, %s, %d>", ts.c_str(), z, L.cap);
+            break;
+        case kTileMoved:
+            std::snprintf(buf, sizeof(buf), "k_moved%s, %s, %d, %d, %d, %d>", ts.c_str(), z, L.c.tile_a, L.c.tile_b,
+                          L.va, L.vb);
+            break;
+        case kTileStaged:
+            std::snprintf(buf, sizeof(buf), "k_staged%s, %s, %d, %d, %d>", ts.c_str(), z, L.n0, L.c.tile_a, L.c.tile_b);
+            break;
+        default:
+            std::snprintf(buf, sizeof(buf), "k_preserved%s, %s, %d, %d, %d>", ts.c_str(), z, L.c.tile_a, L.c.tile_b,
+                          L.va);
     }
     return buf;
 }

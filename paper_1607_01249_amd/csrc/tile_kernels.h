@@ -22,11 +22,12 @@
 // alpha*a + beta*b with both products and the sum rounded separately.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
-
+#endif
 #include <type_traits>
 
-#include "ttx_internal.h"
+#include "device_types.h"
 
 #pragma clang fp contract(off)
 
@@ -334,10 +335,14 @@ struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
     static constexpr int NT = kThreads, LDR = TA + 1;
-    __device__ static int ext_a(const TileArgs<T, S>&) { return TA; }
-    __device__ static int ext_b(const TileArgs<T, S>&) { return TB; }
-    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
+    template <typename Args>
+    __device__ static int ext_a(const Args&) { return TA; }
+    template <typename Args>
+    __device__ static int ext_b(const Args&) { return TB; }
+    template <typename Args>
+    __device__ static int ext_c(const Args&) { return 1; }
+    template <typename Args>
+    __device__ __forceinline__ void init(const Args&) {}
     // A side: columns (fixed y) of TA elements along x
     static constexpr int LA = TA / VA, PA = pow2_ceil(LA), RA = NT / PA, NA = (TB + RA - 1) / RA;
     // B side: rows (fixed x) of TB elements along y
@@ -348,7 +353,8 @@ struct MovedTile {
     vec_t<T, VB> rb[NB];
     vec_t<T, VB> out[NB];
 
-    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int xa = (tid % PA) * VA, ya = tid / PA;
         const bool live_a = (tid % PA) < LA && xa < c.ea;
@@ -367,7 +373,8 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const Args&, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int xa = (tid % PA) * VA, ya = tid / PA;
         if ((tid % PA) >= LA) return;
@@ -381,7 +388,8 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const Args& a,
                                              const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
@@ -398,7 +406,8 @@ struct MovedTile {
         }
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
@@ -412,7 +421,8 @@ struct MovedTile {
     }
 
     // from_lds and store in one pass (no tile held in registers in between)
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
@@ -441,10 +451,14 @@ struct PreservedTile {
     static constexpr bool kUsesLds = false;
     static constexpr int kTA = TA, kTB = TR;
     static constexpr int NT = kThreads;
-    __device__ static int ext_a(const TileArgs<T, S>&) { return TA; }
-    __device__ static int ext_b(const TileArgs<T, S>&) { return TR; }
-    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
+    template <typename Args>
+    __device__ static int ext_a(const Args&) { return TA; }
+    template <typename Args>
+    __device__ static int ext_b(const Args&) { return TR; }
+    template <typename Args>
+    __device__ static int ext_c(const Args&) { return 1; }
+    template <typename Args>
+    __device__ __forceinline__ void init(const Args&) {}
     static constexpr int L = TA / V, P = pow2_ceil(L), R = NT / P, N = (TR + R - 1) / R;
     static_assert(P <= NT, "row too long for the workgroup");
 
@@ -452,7 +466,8 @@ struct PreservedTile {
     vec_t<T, V> rb[N];
     vec_t<T, V> out[N];
 
-    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -467,12 +482,14 @@ struct PreservedTile {
         }
     }
 
-    __device__ __forceinline__ void finish(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void finish(const Args& a, const TileCoord& c) {
 #pragma unroll
         for (int i = 0; i < N; ++i) out[i] = epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta);
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -484,7 +501,8 @@ struct PreservedTile {
     }
 
     // finish and store in one pass
-    __device__ __forceinline__ void finish_store(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void finish_store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
@@ -511,10 +529,14 @@ struct StagedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TX, kTB = TY;
     static constexpr int NT = kThreads, LDR = TX * N0 + 1;
-    __device__ static int ext_a(const TileArgs<T, S>&) { return TX; }
-    __device__ static int ext_b(const TileArgs<T, S>&) { return TY; }
-    __device__ static int ext_c(const TileArgs<T, S>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T, S>&) {}
+    template <typename Args>
+    __device__ static int ext_a(const Args&) { return TX; }
+    template <typename Args>
+    __device__ static int ext_b(const Args&) { return TY; }
+    template <typename Args>
+    __device__ static int ext_c(const Args&) { return 1; }
+    template <typename Args>
+    __device__ __forceinline__ void init(const Args&) {}
     // padded runs: N0 lanes per row, TX rows per A run, TY rows per B run
     static constexpr int PA = N0 * TX, PB = N0 * TY;
     static constexpr int NA = PA * TY / NT, NB = PB * TX / NT;
@@ -526,7 +548,8 @@ struct StagedTile {
     T out[NB];
     int n0_ = 0;
 
-    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         n0_ = n0;
         const S* A0 = a.A + c.oa;
@@ -548,7 +571,8 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const Args&, const TileCoord& c) {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
@@ -558,7 +582,8 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const Args& a,
                                              const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
 #pragma unroll
@@ -570,7 +595,8 @@ struct StagedTile {
         }
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
@@ -584,7 +610,8 @@ struct StagedTile {
     }
 
     // from_lds and store in one pass
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
         const bool nt = a.flags & KF_NT_STORE;
@@ -618,9 +645,12 @@ struct DenseTile {
     static constexpr bool kUsesLds = true;
     static constexpr int NT = kThreads, NS = CAP / NT;
     static_assert(CAP % NT == 0 && CAP <= 1024, "whole passes; slot coordinates packed in 11+11+10 bits");
-    __device__ static int ext_a(const TileArgs<T, S>& a) { return a.tx; }
-    __device__ static int ext_b(const TileArgs<T, S>& a) { return a.ty; }
-    __device__ static int ext_c(const TileArgs<T, S>& a) { return a.tz; }
+    template <typename Args>
+    __device__ static int ext_a(const Args& a) { return a.tx; }
+    template <typename Args>
+    __device__ static int ext_b(const Args& a) { return a.ty; }
+    template <typename Args>
+    __device__ static int ext_c(const Args& a) { return a.tz; }
 
     S ra[NS];
     T rb[NS];
@@ -633,7 +663,8 @@ struct DenseTile {
     uint32_t la[NS], lb[NS];
     uint32_t pa[NS], pb[NS];
 
-    __device__ __forceinline__ void init(const TileArgs<T, S>& a) {
+    template <typename Args>
+    __device__ __forceinline__ void init(const Args& a) {
         const uint32_t tid = threadIdx.x;
         const uint32_t count = a.planeA * uint32_t(a.tz);
         const int64_t ya = a.gB.ng == 1 ? a.gB.stride[0] : 0;   // A stride of y when linear
@@ -668,16 +699,19 @@ struct DenseTile {
         return (p & 2047u) < uint32_t(c.ea) && ((p >> 11) & 2047u) < uint32_t(c.eb) && (p >> 22) < uint32_t(c.ez);
     }
     // A and B addresses of slot s in tile c
-    __device__ __forceinline__ const S* a_ptr(const TileArgs<T, S>& a, const TileCoord& c, int s) const {
+    template <typename Args>
+    __device__ __forceinline__ const S* a_ptr(const Args& a, const TileCoord& c, int s) const {
         if (a.gB.ng == 1) return a.A + (c.oa + c.y0 * a.gB.stride[0]) + relA[s];
         return a.A + c.oa + relA[s] + a.gB.offset(c.y0 + ((pa[s] >> 11) & 2047u));
     }
-    __device__ __forceinline__ int64_t b_off(const TileArgs<T, S>& a, const TileCoord& c, int s) const {
+    template <typename Args>
+    __device__ __forceinline__ int64_t b_off(const Args& a, const TileCoord& c, int s) const {
         if (a.gA.ng == 1) return c.ob + c.x0 * a.gA.stride[0] + relB[s];
         return c.ob + relB[s] + a.gA.offset(c.x0 + (pb[s] & 2047u));
     }
 
-    __device__ __forceinline__ void load(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pa[s])) ra[s] = *a_ptr(a, c, s);
@@ -688,27 +722,31 @@ struct DenseTile {
         }
     }
 
-    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const TileArgs<T, S>&, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void to_lds(T* __restrict__ lds, const Args&, const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pa[s])) lds[la[s]] = conv<T, S>(ra[s]);
     }
 
-    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const Args& a,
                                              const TileCoord& c) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pb[s])) out[s] = epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta);
     }
 
-    __device__ __forceinline__ void store(const TileArgs<T, S>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pb[s])) st<T, 1>(a.Bdst + b_off(a, c, s), out[s], nt);
     }
 
-    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const TileArgs<T, S>& a,
+    template <typename Args>
+    __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
@@ -729,16 +767,21 @@ template <typename T, bool BETA0, int V, int U>
 struct FlatTile {
     static constexpr bool kUsesLds = false;
     static constexpr int NT = kThreads, TF = NT * V * U;
-    __device__ static int ext_a(const TileArgs<T>&) { return TF; }
-    __device__ static int ext_b(const TileArgs<T>&) { return 1; }
-    __device__ static int ext_c(const TileArgs<T>&) { return 1; }
-    __device__ __forceinline__ void init(const TileArgs<T>&) {}
+    template <typename Args>
+    __device__ static int ext_a(const Args&) { return TF; }
+    template <typename Args>
+    __device__ static int ext_b(const Args&) { return 1; }
+    template <typename Args>
+    __device__ static int ext_c(const Args&) { return 1; }
+    template <typename Args>
+    __device__ __forceinline__ void init(const Args&) {}
 
     vec_t<T, V> ra[U];
     vec_t<T, V> rb[U];
     vec_t<T, V> out[U];
 
-    __device__ __forceinline__ void load(const TileArgs<T>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -749,11 +792,13 @@ struct FlatTile {
             }
         }
     }
-    __device__ __forceinline__ void finish(const TileArgs<T>& a, const TileCoord&) {
+    template <typename Args>
+    __device__ __forceinline__ void finish(const Args& a, const TileCoord&) {
 #pragma unroll
         for (int u = 0; u < U; ++u) out[u] = epilogue<T, V, BETA0>(ra[u], rb[u], a.alpha, a.beta);
     }
-    __device__ __forceinline__ void store(const TileArgs<T>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
         const bool nt = a.flags & KF_NT_STORE;
 #pragma unroll
@@ -762,7 +807,8 @@ struct FlatTile {
             if (k < c.ea) st<T, V>(a.Bdst + c.ob + int64_t(k) * a.sBa, out[u], nt);
         }
     }
-    __device__ __forceinline__ void finish_store(const TileArgs<T>& a, const TileCoord& c) {
+    template <typename Args>
+    __device__ __forceinline__ void finish_store(const Args& a, const TileCoord& c) {
         finish(a, c);
         store(a, c);
     }
@@ -818,6 +864,53 @@ __device__ __forceinline__ void tile_loop(T* __restrict__ lds, const Args& a, ui
     }
 }
 
+// The kernel body shared by the generic kernels and the size-specialised
+// ones: workgroup b takes tiles b, b + G, ... (G workgroups; ids permuted
+// XCD-aware when KF_SWIZZLE is set).
+template <typename Tile, bool PIPE, typename T, typename Args>
+__device__ __forceinline__ void run_grid(T* lds, const Args& a) {
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
+    if (first < a.g.ntiles) tile_loop<Tile, PIPE>(lds, a, first, a.g.ntiles, G);
+}
+
+// Arguments of a size-specialised kernel (compiled at run time for one
+// problem): the problem-dependent part is the compile-time constant H, so
+// every extent, stride, tile count and divisor that the tile code reads
+// folds into the instructions, and loops over merged indices and group
+// members unroll; the pointers and scalars are run-time values.  The
+// members mirror TileArgs (a member added to TileArgsHost is added here).
+template <const TileArgsHost& H, typename T, typename S, int FLAGS>
+struct ConstArgs {
+    static constexpr const TileGrid& g = H.g;
+    static constexpr int64_t sAa = H.sAa, sAb = H.sAb, sBa = H.sBa, sBb = H.sBb;
+    static constexpr const Group& gA = H.gA;
+    static constexpr const Group& gB = H.gB;
+    static constexpr int64_t s0A = H.s0A, s0B = H.s0B;
+    static constexpr int n0 = H.n0, dn0 = H.dn0, tx = H.tx, ty = H.ty, ldr = H.ldr;
+    static constexpr uint32_t runA = H.runA, runB = H.runB;
+    static constexpr const FastDiv& dv0 = H.dv0;
+    static constexpr const FastDiv& dvA = H.dvA;
+    static constexpr const FastDiv& dvB = H.dvB;
+    static constexpr int tz = H.tz;
+    static constexpr int64_t sAz = H.sAz, sBz = H.sBz;
+    static constexpr uint32_t planeA = H.planeA, planeB = H.planeB;
+    static constexpr const FastDiv& dvPA = H.dvPA;
+    static constexpr const FastDiv& dvPB = H.dvPB;
+    static constexpr int flags = FLAGS;
+    const S* A;
+    const T* Bsrc;
+    T* Bdst;
+    T alpha, beta;
+};
+
+// Body of a size-specialised kernel: the generic body over ConstArgs.
+template <typename Tile, bool PIPE, const TileArgsHost& H, int FLAGS, typename T, typename S>
+__device__ __forceinline__ void run_specialised(T* lds, const TileArgs<T, S>& in) {
+    const ConstArgs<H, T, S, FLAGS> a{in.A, in.Bsrc, in.Bdst, in.alpha, in.beta};
+    run_grid<Tile, PIPE>(lds, a);
+}
+
 // Vector widths are template parameters so that each variant gets its own
 // register allocation: the scalar fallbacks need many more address
 // registers than the 16-byte paths and would otherwise lower the occupancy
@@ -827,19 +920,14 @@ __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
 void k_moved(TileArgs<T> a) {
     __shared__ T lds[TB * (TA + 1)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<MovedTile<T, BETA0, TA, TB, VA, VB>, false>(lds, a, first, a.g.ntiles, G);
+    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB>, false>(lds, a);
 }
 
 template <typename T, bool BETA0, int TA, int TR, int V>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
 void k_preserved(TileArgs<T> a) {
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles)
-        tile_loop<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
+    run_grid<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a);
 }
 
 // Launched with about one wave of workgroups, each looping over tiles
@@ -847,18 +935,14 @@ void k_preserved(TileArgs<T> a) {
 template <typename T, bool BETA0, int CAP>
 __global__ __launch_bounds__(kThreads) void k_dense(TileArgs<T> a) {
     __shared__ T lds[dense_lds_elems(CAP)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP>, true>(lds, a, first, a.g.ntiles, G);
+    run_grid<DenseTile<T, BETA0, CAP>, true>(lds, a);
 }
 
 template <typename T, bool BETA0, int N0, int TX, int TY>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_staged(TileArgs<T> a) {
     __shared__ T lds[TY * (TX * N0 + 1)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<StagedTile<T, BETA0, N0, TX, TY>, false>(lds, a, first, a.g.ntiles, G);
+    run_grid<StagedTile<T, BETA0, N0, TX, TY>, false>(lds, a);
 }
 
 // Mixed precision (A of type S, B of type T): the same tiles, converting
@@ -868,37 +952,27 @@ __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
 void k_moved_x(TileArgs<T, S> a) {
     __shared__ T lds[TB * (TA + 1)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles)
-        tile_loop<MovedTile<T, BETA0, TA, TB, VA, VB, S>, false>(lds, a, first, a.g.ntiles, G);
+    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB, S>, false>(lds, a);
 }
 
 template <typename T, typename S, bool BETA0, int TA, int TR, int V>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
 void k_preserved_x(TileArgs<T, S> a) {
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles)
-        tile_loop<PreservedTile<T, BETA0, TA, TR, V, S>, false>(static_cast<T*>(nullptr), a, first, a.g.ntiles, G);
+    run_grid<PreservedTile<T, BETA0, TA, TR, V, S>, false>(static_cast<T*>(nullptr), a);
 }
 
 template <typename T, typename S, bool BETA0, int CAP>
 __global__ __launch_bounds__(kThreads) void k_dense_x(TileArgs<T, S> a) {
     __shared__ T lds[dense_lds_elems(CAP)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<DenseTile<T, BETA0, CAP, S>, true>(lds, a, first, a.g.ntiles, G);
+    run_grid<DenseTile<T, BETA0, CAP, S>, true>(lds, a);
 }
 
 template <typename T, typename S, bool BETA0, int N0, int TX, int TY>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_staged_x(TileArgs<T, S> a) {
     __shared__ T lds[TY * (TX * N0 + 1)];
-    const uint32_t G = gridDim.x;
-    const uint32_t first = (a.flags & KF_SWIZZLE) ? swizzle_id(blockIdx.x, G) : blockIdx.x;
-    if (first < a.g.ntiles) tile_loop<StagedTile<T, BETA0, N0, TX, TY, S>, false>(lds, a, first, a.g.ntiles, G);
+    run_grid<StagedTile<T, BETA0, N0, TX, TY, S>, false>(lds, a);
 }
 
 // Flat: one index of n elements with strides sa, sb.  The vector path

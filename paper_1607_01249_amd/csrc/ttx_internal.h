@@ -8,50 +8,12 @@
 #include <type_traits>
 
 #include "../../include/ttx.h"
+#include "device_types.h"
 #include "menu.h"
 
 namespace ttx {
 
-constexpr int kMaxDims = TTX_MAX_DIMS;
-
-// Complex elements: interleaved (re, im) pairs, aligned to their size so
-// that one element is one 8- or 16-byte access.
-struct alignas(8) cf32 {
-    float re, im;
-};
-struct alignas(16) cf64 {
-    double re, im;
-};
-
-// Units of a kept row (the internal wide element types).
-struct alignas(16) f32x4 {
-    float v[4];
-};
-struct alignas(16) f64x2 {
-    double v[2];
-};
-struct alignas(8) f32x2 {
-    float v[2];
-};
-template <typename T>
-struct WideOf {
-    static constexpr int lanes = 0;
-};
-template <>
-struct WideOf<f32x4> {
-    static constexpr int lanes = 4;
-    using lane_t = float;
-};
-template <>
-struct WideOf<f64x2> {
-    static constexpr int lanes = 2;
-    using lane_t = double;
-};
-template <>
-struct WideOf<f32x2> {
-    static constexpr int lanes = 2;
-    using lane_t = float;
-};
+static_assert(kMaxDims == TTX_MAX_DIMS, "rank limit of the C ABI");
 
 // A data-type code (ttx_dtype) names the element types of A and B; they
 // differ for the mixed-precision codes.
@@ -107,125 +69,6 @@ inline T scalar_as(const Scalar& s) {
     }
 }
 
-// Division by a run-time invariant 32-bit divisor with a multiply and a
-// shift (Granlund and Montgomery, "Division by invariant integers using
-// multiplication", PLDI 1994): for d >= 1, l = ceil(log2 d) and
-// m = floor(2^32 (2^l - d) / d) + 1 give n / d = (mulhi(n, m) + n) >> l for
-// every 32-bit n (the sum is formed in 64 bits).
-struct FastDiv {
-    uint32_t d;
-    uint32_t m;
-    uint32_t l;
-
-    FastDiv() : d(1), m(1), l(0) {}
-    explicit FastDiv(uint32_t divisor) { init(divisor); }
-
-    void init(uint32_t divisor) {
-        d = divisor ? divisor : 1;
-        l = 0;
-        while ((uint64_t(1) << l) < d) ++l;
-        m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
-    }
-
-    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
-        uint64_t hi = (uint64_t(n) * m) >> 32;
-        return uint32_t((hi + n) >> l);
-    }
-};
-
-// Description of the tiled iteration space shared by the tile kernels.
-// Tile ids enumerate the merged indices in `order` (fastest first); position
-// p has count[p] steps, and one step moves the tile origin by stepA[p] /
-// stepB[p] elements.  Positions pa and pb hold the two tile indices; their
-// full extents bound the edge tiles.
-struct TileGrid {
-    int nd;
-    int pa, pb;
-    int pz;                        // dense tiles: position of the third tiled index (-1: none)
-    uint32_t ntiles;
-    int64_t ext_a, ext_b;          // extents along the two tile indices
-    int64_t ext_z;                 // and along the third (dense tiles)
-    uint32_t count[kMaxDims];
-    FastDiv div[kMaxDims];
-    int64_t stepA[kMaxDims];
-    int64_t stepB[kMaxDims];
-};
-
-// Kernel-side flags (separate from TTX_CFG_*, which describe a config).
-enum : int {
-    KF_VEC_A = 1,      // 16-byte vector accesses along the tile index of A
-    KF_VEC_B = 2,      // 16-byte vector accesses along the tile index of B
-    KF_NT_STORE = 4,   // non-temporal stores to B
-    KF_SWIZZLE = 8,    // XCD-aware tile id mapping
-};
-
-// A super index: ng consecutive merged indices tiled as one.  The offset of
-// position y in the other tensor is sum_k digit_k(y) * stride[k] with
-// digit_k = (y / prod_{j<k} size_j) % size_k (index 0 fastest).  With several
-// members the extent is below 2^31 and digits come from 32-bit divisions.
-constexpr int kMaxGroup = 4;
-struct Group {
-    int ng;
-    FastDiv div[kMaxGroup - 1];   // sizes of all members but the last
-    int64_t stride[kMaxGroup];
-
-    __host__ __device__ __forceinline__ int64_t offset(int64_t y) const {
-        if (ng == 1) return y * stride[0];
-        uint32_t rem = uint32_t(y);
-        int64_t off = 0;
-        for (int k = 0; k + 1 < ng; ++k) {
-            const uint32_t q = div[k].div(rem);
-            off += int64_t(rem - q * div[k].d) * stride[k];
-            rem = q;
-        }
-        return off + int64_t(rem) * stride[ng - 1];
-    }
-};
-
-// The dtype-independent part of a tile kernel's arguments (built by the planner).
-struct TileArgsHost {
-    TileGrid g;
-    int64_t sAa, sAb;   // A strides of the two tile (leader) indices
-    int64_t sBa, sBb;   // B strides of the two tile (leader) indices
-    Group gA;           // B offsets of the A-side super index (moved and staged tiles)
-    Group gB;           // A offsets of the B-side super index (moved and staged tiles)
-    int64_t s0A, s0B;   // staged tiles: strides of the shared row index in A and B
-    int n0;             // staged tiles: row length
-    // dense tiles: rows of dn0 elements (1 for the moved family), tx x ty rows
-    // per tile; an A run holds runA = dn0*tx elements, a B run runB = dn0*ty;
-    // the LDS tile has ty rows of ldr >= runA elements
-    int dn0, tx, ty, ldr;
-    uint32_t runA, runB;
-    FastDiv dv0, dvA, dvB;
-    // and tz planes along a third index (strides sAz, sBz); a plane holds
-    // planeA = runA*ty (A order) or planeB = runB*tx (B order) elements
-    int tz;
-    int64_t sAz, sBz;
-    uint32_t planeA, planeB;
-    FastDiv dvPA, dvPB;
-};
-
-// T: B's element type (the arithmetic and LDS type); S: A's (converted to T
-// on load when the precisions differ).
-template <typename T, typename S = T>
-struct TileArgs : TileArgsHost {
-    const S* A;
-    const T* Bsrc;      // read when beta != 0
-    T* Bdst;
-    T alpha, beta;
-    int flags;
-};
-
-template <typename T, typename S = T>
-struct FlatArgs {
-    const S* A;
-    const T* Bsrc;
-    T* Bdst;
-    T alpha, beta;
-    int64_t n;          // element count
-    int64_t sa, sb;     // strides of the single index
-    int flags;
-};
 
 // A merged problem (planner output), A order.
 struct Dim {
@@ -322,12 +165,48 @@ inline bool config_is_wide(const ttx_config& c) { return (c.flags & TTX_CFG_WIDE
 // are multiples of the unit and whose rows hold at least two units.  Fills
 // *w and returns true when there is one.
 bool widen(const Problem& p, Problem* w);
-constexpr int kThreads = 256;
 
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,
                         hipStream_t stream);
+
+// What launch_tiles runs for a tiled (moved or preserved family) problem,
+// resolved for a set of pointers: the problem and config the tile kernel
+// runs on (over whole units of the kept rows for wide configs, or the
+// element-wise fallback when the pointers are not aligned to the unit), the
+// tile kind with its vector widths, row lanes or slot count, the grid, and
+// the kernel's argument block (a TileArgs<T, S>).
+enum : int { kTileMoved = 0, kTilePreserved = 1, kTileStaged = 2, kTileDense = 3 };
+struct TiledLaunch {
+    Problem p;
+    ttx_config c;
+    bool beta0;
+    int kind;
+    int va, vb;          // vector widths (moved: A and B sides; preserved: both the same)
+    int n0;              // staged tiles: row lanes
+    int cap;             // dense tiles: slots
+    int flags;           // kernel flags (KF_*)
+    uint32_t ntiles, grid;
+    size_t args_bytes;
+    alignas(16) unsigned char args[sizeof(TileArgs<cf64, cf64>)];
+};
+// Fills *L; false for empty and flat problems (nothing tiled) and for
+// element codes without tile kernels.
+bool prepare_tiled(const Problem& p, const ttx_config& c, bool beta0, const void* A, const void* Bsrc,
+                   void* Bdst, const Scalar& alpha, const Scalar& beta, TiledLaunch* L);
+// Size-specialised kernels (jit.cpp): the kernel a prepared launch runs,
+// compiled at run time with the problem's arguments as constants.
+struct JitKernel;
+// Finds or compiles (hipRTC) and loads the kernel for L on the current device.
+ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out);
+// The translation unit jit_kernel compiles for L.
+std::string jit_source(const TiledLaunch& L);
+// True when k runs what L launches (same device, kernel, flags and arguments).
+bool jit_matches(const JitKernel& k, const TiledLaunch& L);
+hipError_t jit_launch(const JitKernel& k, const TiledLaunch& L, hipStream_t stream);
+// C++ spelling of an element type ("float", "ttx::cf32", "ttx::f32x4", ...).
+const char* element_type_name(int dtype);
 
 // The kernel launch_tiles would use, spelled as profilers print it.
 std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const void* A,

@@ -40,14 +40,15 @@ def from_device(t, pad_elems=0):
 
 
 def gpu_transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, pad_a=0, pad_b=0,
-                  plan_config=None):
+                  plan_config=None, specialise=False):
     """Runs Eqn. 1 on the GPU through ttx_transpose (or a plan with a forced
-    config) and returns B as a host array."""
+    config, or a plan with its size-specialised kernel) and returns B as a
+    host array."""
     dA, pa = to_device(A, pad_a)
     dB, pb = to_device(B, pad_b)
     stream = ttx.current_stream()
     cx = isinstance(alpha, complex) or isinstance(beta, complex)
-    if plan_config is None:
+    if plan_config is None and not specialise:
         run = ttx.ttx_transpose_c if cx else ttx.ttx_transpose
         run(dtype_code(A.dtype, B.dtype), len(perm), perm, size, outer_a, outer_b, alpha, pa, beta, pb,
             stream)
@@ -55,7 +56,12 @@ def gpu_transpose(perm, size, alpha, A, beta, B, outer_a=None, outer_b=None, pad
         plan = ttx.ttx_plan_create(dtype_code(A.dtype, B.dtype), perm, size, outer_a, outer_b)
         try:
             beta0 = B.dtype.type(beta) == 0
-            ttx.ttx_plan_set_config(plan, beta0, plan_config)
+            if plan_config is not None:
+                ttx.ttx_plan_set_config(plan, beta0, plan_config)
+            if specialise:
+                ttx.ttx_plan_specialise(plan, beta0)
+                info = ttx.ttx_plan_describe(plan)
+                assert info["specialised"][int(beta0)] == int(info["family"] in ("moved", "preserved"))
             if cx:
                 ttx.ttx_plan_execute_c(plan, alpha, pa, beta, pb, pb, stream)
             else:

@@ -1,0 +1,163 @@
+"""GPU parity for size-specialised kernels (compiled at run time with hipRTC,
+the problem's sizes and strides as constants; Sec. 2.1), through the C ABI:
+bit-identical with the generic kernels and with the CPU oracle to the same
+bar (bit-exact for alpha = 1, beta = 0; at most 1 ulp otherwise)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1607_01249_amd as ttx
+import workloads
+from gpu_util import C32, C64, F32, F64, assert_parity, dtype_code, gpu_transpose
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _scalars(db, beta_zero):
+    if db in (C32, C64):
+        return complex(0.75, -1.25), (0j if beta_zero else complex(-0.5, 0.375))
+    return 1.3, (0.0 if beta_zero else 0.7)
+
+
+def _inputs(perm, size, da, db, seed, outer_a=None, outer_b=None):
+    size_b = [size[p] for p in perm]
+    A = workloads.uniform(workloads.elements(outer_a or size), da, seed=9000 + seed) * 3
+    B = workloads.uniform(workloads.elements(outer_b or size_b), db, seed=9500 + seed)
+    return A, B
+
+
+def _check(perm, size, da, db, beta_zero, seed=0, outer_a=None, outer_b=None, plan_config=None, pad_a=0,
+           pad_b=0):
+    alpha, beta = _scalars(db, beta_zero)
+    A, B = _inputs(perm, size, da, db, seed, outer_a, outer_b)
+    ref = B.copy()
+    assert oracle.transpose(perm, size, alpha, A, beta, ref, outer_a, outer_b) == 0
+    got = gpu_transpose(perm, size, alpha, A, beta, B, outer_a, outer_b, pad_a, pad_b, plan_config,
+                        specialise=True)
+    generic = gpu_transpose(perm, size, alpha, A, beta, B, outer_a, outer_b, pad_a, pad_b, plan_config)
+    assert np.array_equal(got.view(np.uint8), generic.view(np.uint8)), (perm, size, "differs from generic")
+    assert_parity(got, ref, alpha == 1 and beta == 0, (perm, size))
+
+
+TYPES = [(F32, F32), (F64, F64), (C32, C32), (C64, C64), (F32, F64), (F64, F32), (C32, C64), (C64, C32)]
+TYPE_IDS = ["s", "d", "c", "z", "sd", "ds", "cz", "zc"]
+SHAPES = [((2, 0, 3, 1), (37, 70, 19, 23)), ((2, 1, 0), (33, 40, 27)), ((0, 2, 1), (64, 9, 48)),
+          ((0, 5, 1, 4, 2, 3), (5, 7, 6, 4, 3, 5)), ((0, 2, 1, 3), (40, 9, 11, 13)), ((1, 0, 2), (3, 4, 700)),
+          ((4, 3, 2, 1, 0), (13, 17, 11, 9, 7))]
+
+
+@pytest.mark.parametrize("beta_zero", [False, True], ids=["beta", "beta0"])
+@pytest.mark.parametrize("types", TYPES, ids=TYPE_IDS)
+def test_specialised_matches_generic_and_oracle(types, beta_zero):
+    da, db = types
+    for i, (perm, size) in enumerate(SHAPES):
+        _check(perm, size, da, db, beta_zero, seed=i)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64, C64])
+@pytest.mark.parametrize("perm,size", [((2, 0, 3, 1), (37, 70, 19, 23)), ((0, 2, 1, 3), (40, 9, 11, 13)),
+                                       ((0, 2, 1), (5, 40, 33)), ((1, 0, 2), (3, 4, 700)),
+                                       ((0, 5, 1, 4, 2, 3), (24, 7, 4, 3, 5, 6))])
+def test_every_tile_kind_specialised(perm, size, dtype):
+    """One config per distinct tile (menu, staged, dense, whole-unit dense),
+    each specialised: the same bits as its generic kernel."""
+    cands, _ = ttx.ttx_tune_candidates(dtype_code(dtype), perm, size, max_candidates=-1, cap=200000)
+    seen, pick = set(), []
+    for c in cands:
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c, c.flags & (ttx.CFG_DENSE | ttx.CFG_WIDE))
+        if key not in seen:
+            seen.add(key)
+            pick.append(c)
+    _say("specialised candidates %s %s %s: %d configs" % (perm, size, np.dtype(dtype).name, len(pick)))
+    for bz in (False, True):
+        for c in pick:
+            _check(perm, size, dtype, dtype, bz, seed=3, plan_config=c)
+
+
+EDGE = [((1, 0), (1, 1), None, None), ((3, 2, 1, 0), (5, 3, 7, 9), (6, 3, 8, 9), (10, 7, 3, 5)),
+        ((0, 2, 1), (6, 50, 40), (8, 52, 41), (7, 41, 51)), ((1, 0, 2), (3, 4, 700), (4, 5, 700), (5, 3, 701)),
+        ((5, 4, 3, 2, 1, 0), (7, 5, 3, 6, 5, 3), None, None), ((2, 0, 1), (3, 1, 200), None, None)]
+
+
+@pytest.mark.parametrize("perm,size,oa,ob", EDGE)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_edge_and_leading_dimension_shapes(perm, size, oa, ob, dtype):
+    for bz in (False, True):
+        _check(perm, size, dtype, dtype, bz, seed=5, outer_a=oa, outer_b=ob)
+
+
+@pytest.mark.parametrize("pad_a,pad_b", [(1, 0), (0, 1), (1, 3)])
+def test_misaligned_pointers_fall_back(pad_a, pad_b):
+    """Pointers outside the vector alignment the kernel was compiled for run
+    the generic kernel (whole-unit dense tiles need unit-aligned rows)."""
+    for perm, size in [((0, 5, 1, 4, 2, 3), (24, 7, 4, 3, 5, 6)), ((2, 1, 0), (64, 9, 48)),
+                       ((0, 2, 1), (64, 9, 48))]:
+        _check(perm, size, F32, F32, False, seed=8, pad_a=pad_a, pad_b=pad_b)
+
+
+def test_flat_and_empty_attach_nothing():
+    for perm, size in [((0, 1), (64, 9)), ((0,), (1000,)), ((1, 0), (1, 0))]:
+        plan = ttx.ttx_plan_create(ttx.F32, perm, size)
+        try:
+            ttx.ttx_plan_specialise(plan, True)
+            assert ttx.ttx_plan_describe(plan)["specialised"] == [0, 0]
+        finally:
+            ttx.ttx_plan_destroy(plan)
+
+
+def test_set_config_drops_the_specialised_kernel():
+    perm, size = (2, 0, 1), (40, 30, 20)
+    plan = ttx.ttx_plan_create(ttx.F64, perm, size)
+    try:
+        ttx.ttx_plan_specialise(plan, False)
+        ttx.ttx_plan_specialise(plan, True)
+        assert ttx.ttx_plan_describe(plan)["specialised"] == [1, 1]
+        cfg = ttx.ttx_plan_describe(plan)["config_raw"][0]
+        ttx.ttx_plan_set_config(plan, False, cfg)
+        assert ttx.ttx_plan_describe(plan)["specialised"] == [0, 1]
+    finally:
+        ttx.ttx_plan_destroy(plan)
+
+
+def test_disk_cache_written_and_reused(tmp_path):
+    """With TTX_JIT_CACHE set, the code object lands in the directory; a
+    second process finds it there and leaves it untouched."""
+    import subprocess
+    d = tmp_path / "jit"
+    perm, size = (2, 0, 3, 1), (29, 31, 7, 5)   # not compiled elsewhere in this process
+    os.environ["TTX_JIT_CACHE"] = str(d)
+    try:
+        _check(perm, size, F32, F32, False, seed=11)
+    finally:
+        del os.environ["TTX_JIT_CACHE"]
+    files = sorted(os.listdir(d))
+    assert len(files) == 1 and files[0].endswith(".co"), files
+    mtime = os.stat(d / files[0]).st_mtime_ns
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r); import paper_1607_01249_amd as ttx\n"
+            "p = ttx.ttx_plan_create(ttx.F32, %r, %r); ttx.ttx_plan_specialise(p, False)\n"
+            "assert ttx.ttx_plan_describe(p)['specialised'][0] == 1; print('reused')" % (root, perm, size))
+    env = dict(os.environ, TTX_JIT_CACHE=str(d))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert sorted(os.listdir(d)) == files and os.stat(d / files[0]).st_mtime_ns == mtime
+
+
+# -- full sizes (about 200 MiB per tensor): the cases the throughput figures time ------------
+@pytest.mark.parametrize("dtype,perm,beta_zero", [(F64, (2, 0, 3, 1), False), (F32, (3, 2, 1, 0), True),
+                                                   (F32, (0, 5, 1, 4, 2, 3), True),
+                                                   (F64, (0, 5, 1, 4, 2, 3), False),
+                                                   (F64, (1, 3, 0, 4, 2), True)])
+def test_full_size_specialised(dtype, perm, beta_zero):
+    rank = "%dd" % len(perm)
+    size = workloads.LARGE_SHAPES[(rank, dtype)]
+    _say("full-size specialised %s %s %s beta0=%s" % (np.dtype(dtype).name, perm, size, beta_zero))
+    _check(perm, size, dtype, dtype, beta_zero, seed=30)

@@ -1,0 +1,133 @@
+"""Host-side checks of the size-specialised kernels (Sec. 2.1): the source the
+library generates names the tile of the generic kernel it replaces, and it
+compiles with hipRTC for gfx950 without a GPU, with no scratch memory."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+import paper_1607_01249_amd as ttx
+
+CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1607_01249_amd", "csrc")
+HEADERS = ["device_types.h", "tile_kernels.h"]
+OPTIONS = ["-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "--offload-arch=gfx950"]
+
+CASES = [  # dtype, perm, size, beta_is_zero
+    (ttx.F64, (2, 0, 3, 1), (160, 160, 32, 32), False),
+    (ttx.F32, (3, 2, 1, 0), (160, 160, 64, 32), True),
+    (ttx.F32, (0, 5, 1, 4, 2, 3), (24, 21, 20, 18, 17, 17), True),
+    (ttx.F64, (0, 5, 1, 4, 2, 3), (20, 16, 16, 20, 16, 16), False),
+    (ttx.F64, (0, 3, 2, 4, 1), (44, 32, 24, 32, 24), False),
+    (ttx.C32, (2, 0, 1), (40, 30, 20), False),
+    (ttx.C64, (0, 2, 1), (5, 40, 33), True),
+    (ttx.F32_F64, (1, 0, 2), (3, 4, 700), False),
+    (ttx.C64_C32, (4, 3, 2, 1, 0), (13, 17, 11, 9, 7), True),
+]
+IDS = ["d_moved", "s_moved", "s_6d", "d_6d", "d_preserved", "c", "z", "sd", "zc"]
+
+
+def _source(dtype, perm, size, bz):
+    plan = ttx.ttx_plan_create(dtype, perm, size)
+    try:
+        src = ttx.ttx_plan_specialised_source(plan, bz)
+        name = ttx.ttx_plan_kernel_name(plan, 0.0 if bz else 1.0, 1 << 20, 3 << 20)
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    return src, name
+
+
+def _expected_tile(name):
+    """The tile type a generic kernel name runs: k_moved<T, B0, TA, TB, VA, VB>
+    runs MovedTile<T, B0, TA, TB, VA, VB, S> (k_<kind>_x<T, S, ...> when the
+    types differ), and likewise for the other kinds."""
+    m = re.fullmatch(r"k_(moved|preserved|staged|dense)(_x)?<(.*)>", name)
+    assert m, name
+    args = [a.strip() for a in m.group(3).split(",")]
+    t = args[0]
+    s, rest = (args[1], args[2:]) if m.group(2) else (t, args[1:])
+    tile = {"moved": "MovedTile", "preserved": "PreservedTile", "staged": "StagedTile", "dense": "DenseTile"}
+    return "ttx::%s<%s, %s, %s>" % (tile[m.group(1)], t, ", ".join(rest), s)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_source_runs_the_generic_kernels_tile(case):
+    src, name = _source(*case)
+    assert _expected_tile(name) in src, (name, src[-400:])
+    assert 'extern "C" __global__' in src and "ttx_specialised(" in src
+    assert "__builtin_bit_cast(ttx::TileArgsHost, kImage)" in src
+
+
+def test_nothing_to_specialise_for_flat_and_empty():
+    for perm, size in [((0, 1), (64, 9)), ((0,), (1000,)), ((1, 0), (1, 0))]:
+        plan = ttx.ttx_plan_create(ttx.F32, perm, size)
+        try:
+            with pytest.raises(ttx.TTXError):
+                ttx.ttx_plan_specialised_source(plan, False)
+            ttx.ttx_plan_specialise(plan, False)   # no GPU call: nothing to compile
+            assert ttx.ttx_plan_describe(plan)["specialised"] == [0, 0]
+        finally:
+            ttx.ttx_plan_destroy(plan)
+
+
+def test_specialised_source_null_and_small_buffer():
+    plan = ttx.ttx_plan_create(ttx.F64, (2, 0, 1), (40, 30, 20))
+    try:
+        buf = ctypes.create_string_buffer(64)
+        assert ttx.lib().ttx_plan_specialised_source(plan, 0, buf, 64) == ttx.EINVAL
+        assert ttx.lib().ttx_plan_specialised_source(None, 0, buf, 64) == ttx.EINVAL
+        assert ttx.lib().ttx_plan_specialise(None, 0) == ttx.EINVAL
+    finally:
+        ttx.ttx_plan_destroy(plan)
+
+
+def _hiprtc():
+    for path in ("/opt/rocm/lib/libhiprtc.so", "libhiprtc.so"):
+        try:
+            return ctypes.CDLL(path)
+        except OSError:
+            continue
+    pytest.skip("hipRTC not installed")
+
+
+def _compile(src):
+    rtc = _hiprtc()
+    names = [h.encode() for h in HEADERS]
+    texts = [open(os.path.join(CSRC, h), "rb").read() for h in HEADERS]
+    prog = ctypes.c_void_p()
+    arr = ctypes.c_char_p * len(HEADERS)
+    assert rtc.hiprtcCreateProgram(ctypes.byref(prog), src.encode(), b"t.hip", len(HEADERS), arr(*texts),
+                                   arr(*names)) == 0
+    opts = (ctypes.c_char_p * len(OPTIONS))(*[o.encode() for o in OPTIONS])
+    r = rtc.hiprtcCompileProgram(prog, len(OPTIONS), opts)
+    n = ctypes.c_size_t()
+    rtc.hiprtcGetProgramLogSize(prog, ctypes.byref(n))
+    log = ctypes.create_string_buffer(n.value + 1)
+    rtc.hiprtcGetProgramLog(prog, log)
+    code = b""
+    if r == 0:
+        rtc.hiprtcGetCodeSize(prog, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        rtc.hiprtcGetCode(prog, buf)
+        code = buf.raw
+    rtc.hiprtcDestroyProgram(ctypes.byref(prog))
+    return r, log.value.decode(errors="replace"), code
+
+
+@pytest.mark.parametrize("case", [CASES[i] for i in (0, 2, 3, 4, 8)], ids=[IDS[i] for i in (0, 2, 3, 4, 8)])
+def test_source_compiles_without_scratch(case, tmp_path):
+    src, _ = _source(*case)
+    r, log, code = _compile(src)
+    assert r == 0 and code, log[:3000]
+    readobj = shutil.which("llvm-readobj") or "/opt/rocm/llvm/bin/llvm-readobj"
+    if not os.path.exists(readobj):
+        pytest.skip("llvm-readobj not installed")
+    co = tmp_path / "k.co"
+    co.write_bytes(code)
+    notes = subprocess.run([readobj, "--notes", str(co)], capture_output=True, text=True, check=True).stdout
+    assert ".name:           ttx_specialised" in notes
+    # every index constant folded: no private (scratch) memory
+    assert re.search(r"\.private_segment_fixed_size:\s+0\b", notes), notes
