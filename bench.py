@@ -382,53 +382,61 @@ def bench_batched(torch, ttx, reps=20, tune=True):
                 speedup=round(pc_med / b_med, 2))
 
 
-def bench_specialised(torch, ttx, cases, d2d, stream, reps=10):
-    """The step's cases through plans, each with its generic kernel and with
-    its size-specialised kernel (compiled at run time, sizes as constants):
-    median of `reps` launches each, alternating, and the compile time."""
-    out, t_gen, t_spec, step_bytes, compile_s = [], 0.0, 0.0, 0, 0.0
+def bench_specialised(torch, ttx, cases, d2d, stream, steps=10, reps=5):
+    """The step's cases through plans with their generic kernels, with
+    size-specialised kernels (compiled at run time with the sizes as
+    constants) for every case, and with specialised kernels where timing
+    chose them (ttx_plan_specialise with reps > 0): alternating whole steps
+    (every launch sees the same cache state as in the headline step), events
+    around each launch, medians over the steps; and the compile time."""
+    n = len(cases)
+    plans = {"generic": [], "specialised": [], "tuned": []}
+    compile_s, kept = 0.0, 0
     for c in cases:
-        plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
-        spec = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
-        try:
-            z = c["beta"] == 0
-            t0 = time.perf_counter()
-            ttx.ttx_plan_specialise(spec, z)
-            compile_s += time.perf_counter() - t0
-            A, B = c["A"].data_ptr(), c["B"].data_ptr()
+        z = c["beta"] == 0
+        for k in plans:
+            plans[k].append(ttx.ttx_plan_create(c["code"], c["perm"], c["size"]))
+        t0 = time.perf_counter()
+        ttx.ttx_plan_specialise(plans["specialised"][-1], z)
+        compile_s += time.perf_counter() - t0
+        kept += ttx.ttx_plan_specialise(plans["tuned"][-1], z, reps=reps)
+    try:
+        def run(ps, ev=None):
+            for i, c in enumerate(cases):
+                if ev is not None:
+                    ev[i].record()
+                ttx.ttx_plan_execute(ps[i], c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
+            if ev is not None:
+                ev[n].record()
 
-            def gen():
-                ttx.ttx_plan_execute(plan, c["alpha"], A, c["beta"], B, stream)
-
-            def sp():
-                ttx.ttx_plan_execute(spec, c["alpha"], A, c["beta"], B, stream)
-
-            for f in (gen, sp):   # warm-up
-                f()
-            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
-            for k in range(reps):
-                ev[k][0].record()
-                gen()
-                ev[k][1].record()
-                ev[k][2].record()
-                sp()
-                ev[k][3].record()
-            torch.cuda.synchronize()
-            g = float(np.median([e[0].elapsed_time(e[1]) for e in ev])) * 1e-3
-            s = float(np.median([e[2].elapsed_time(e[3]) for e in ev])) * 1e-3
-        finally:
-            ttx.ttx_plan_destroy(plan)
-            ttx.ttx_plan_destroy(spec)
-        t_gen += g
-        t_spec += s
-        step_bytes += c["bytes"]
+        for ps in plans.values():
+            run(ps)
+        ev = {k: [[torch.cuda.Event(enable_timing=True) for _ in range(n + 1)] for _ in range(steps)]
+              for k in plans}
+        for s in range(steps):
+            for k, ps in plans.items():
+                run(ps, ev[k][s])
+        torch.cuda.synchronize()
+        chosen = [ttx.ttx_plan_describe(p)["specialised"][int(c["beta"] == 0)] for p, c in zip(plans["tuned"], cases)]
+    finally:
+        for ps in plans.values():
+            for p in ps:
+                ttx.ttx_plan_destroy(p)
+    med = {k: [float(np.median([e[s][i].elapsed_time(e[s][i + 1]) for s in range(steps)])) * 1e-3
+               for i in range(n)] for k, e in ev.items()}
+    step = {k: float(np.median([e[s][0].elapsed_time(e[s][n]) for s in range(steps)])) * 1e-3
+            for k, e in ev.items()}
+    step_bytes = sum(c["bytes"] for c in cases)
+    out = []
+    for i, c in enumerate(cases):
+        g, s, t = med["generic"][i], med["specialised"][i], med["tuned"][i]
         out.append(dict(case=c["name"], generic_us=round(g * 1e6, 1), specialised_us=round(s * 1e6, 1),
-                        speedup=round(g / s, 3), specialised_pct_of_d2d=round(100 * c["bytes"] / s / 1e9 / d2d, 1)))
+                        speedup=round(g / s, 3), chosen=bool(chosen[i]), tuned_us=round(t * 1e6, 1)))
     sp_all = [o["speedup"] for o in out]
-    return dict(step_GBps_generic=round(step_bytes / t_gen / 1e9, 1),
-                step_GBps_specialised=round(step_bytes / t_spec / 1e9, 1),
+    return dict({"step_GBps_" + k: round(step_bytes / v / 1e9, 1) for k, v in step.items()},
                 speedup_min=min(sp_all), speedup_median=float(np.median(sp_all)), speedup_max=max(sp_all),
-                compile_seconds=round(compile_s, 2), note="sum of per-launch medians (events around each launch)",
+                kept_by_timing=kept, compile_seconds=round(compile_s, 2), steps=steps, timing_reps=reps,
+                note="alternating whole steps through plans; step = events from the first launch to the last",
                 per_case=out)
 
 

@@ -233,20 +233,29 @@ ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A
  * ttx_plan_specialise compiles, at run time with hipRTC, the plan's kernel
  * for one beta class (beta_is_zero = 1: beta == 0) with every extent,
  * stride, tile count and index divisor of the plan's problem and config as
- * a constant, and loads it on the current device.  Later executions of the
- * plan in that beta class, on that device, launch it when the tensors are
- * aligned as for the plan's vector paths (16 bytes suffices; hipMalloc'd
- * tensors are); other executions use the generic kernel.  Both compute the
- * same bits.  Moved- and preserved-family problems only: for empty and
- * single-index problems nothing is attached (TTX_OK).  ttx_plan_set_config
- * drops the kernel of that beta class.  Kernels stay loaded until the
- * process ends and are shared by plans of the same problem; when the
- * environment variable TTX_JIT_CACHE names a directory, code objects are
- * also kept there (created if missing) and reused by later processes.
- * Needs a GPU; blocks the caller while compiling (about a second).
- * Errors: TTX_EINVAL (NULL plan), TTX_EHIP (compilation or loading failed;
- * ttx_last_error starts with the compiler log). */
-ttx_status ttx_plan_specialise(ttx_plan *plan, int beta_is_zero);
+ * a constant, and loads it on the current device.
+ *   reps == 0: the kernel is attached to the plan;
+ *   reps > 0:  the generic and the specialised kernel are timed on scratch
+ *              tensors the call allocates (minimum of `reps` runs each,
+ *              caches flushed before each run, as ttx_tune does), and the
+ *              specialised kernel is attached only when it is more than 1%
+ *              faster (stage 5 of Sec. 2.1 over the two variants).
+ * *kept (may be NULL) receives 1 when a kernel was attached.  Later
+ * executions of the plan in that beta class, on that device, launch it
+ * when the tensors are aligned as for the plan's vector paths (16 bytes
+ * suffices; hipMalloc'd tensors are); other executions use the generic
+ * kernel.  Both compute the same bits.  Moved- and preserved-family
+ * problems only: for empty and single-index problems nothing is attached
+ * (TTX_OK, no GPU call).  A call replaces the plan's earlier specialised
+ * kernel of that beta class; ttx_plan_set_config drops it.  Kernels stay
+ * loaded until the process ends and are shared by plans of the same
+ * problem; when the environment variable TTX_JIT_CACHE names a directory,
+ * code objects are also kept there (created if missing) and reused by
+ * later processes.  Needs a GPU; blocks the caller (about half a second to
+ * compile).  Errors: TTX_EINVAL (NULL plan), TTX_EHIP (compilation or
+ * loading failed; ttx_last_error starts with the compiler log), TTX_ENOMEM
+ * (timing scratch). */
+ttx_status ttx_plan_specialise(ttx_plan *plan, int beta_is_zero, int reps, int *kept);
 /* The translation unit ttx_plan_specialise compiles for the plan (host
  * only), NUL-terminated into buf (len bytes).  TTX_EINVAL when buf is too
  * small (about 8 KB suffices) or the problem has nothing to specialise. */

@@ -184,7 +184,7 @@ def _declare(L):
         "ttx_plan_set_config": ([vp, S, ctypes.POINTER(Config)], S),
         "ttx_plan_destroy": ([vp], S),
         "ttx_plan_kernel_name": ([vp, ctypes.c_double, vp, vp, ctypes.c_char_p, S], S),
-        "ttx_plan_specialise": ([vp, S], S),
+        "ttx_plan_specialise": ([vp, S, S, ip], S),
         "ttx_plan_specialised_source": ([vp, S, ctypes.c_char_p, S], S),
         "ttx_tune": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_candidates": ([S, S, ip, i64p, i64p, i64p, S, ctypes.POINTER(Config),
@@ -308,8 +308,13 @@ def ttx_plan_kernel_name(plan, beta, A, B):
     return buf.value.decode()
 
 
-def ttx_plan_specialise(plan, beta_is_zero):
-    return _check(lib().ttx_plan_specialise(plan, int(bool(beta_is_zero))))
+def ttx_plan_specialise(plan, beta_is_zero, reps=0):
+    """Compiles and attaches the plan's size-specialised kernel; with reps > 0
+    only when it times faster than the generic kernel.  Returns True when a
+    kernel was attached."""
+    kept = ctypes.c_int(0)
+    _check(lib().ttx_plan_specialise(plan, int(bool(beta_is_zero)), int(reps), ctypes.byref(kept)))
+    return bool(kept.value)
 
 
 def ttx_plan_specialised_source(plan, beta_is_zero):

@@ -251,20 +251,45 @@ static ttx_status specialised_launch(const ttx_plan* plan, int beta_is_zero, Til
     return TTX_OK;
 }
 
-ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero) {
+// A specialised kernel is kept by a timed specialisation only when it beats
+// the generic one by more than this fraction (timing noise).
+static constexpr double kSpecialiseMargin = 0.01;
+
+ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero, int reps, int* kept) {
+    if (kept) *kept = 0;
     if (!plan) return fail(TTX_EINVAL, "NULL argument");
     const int z = beta_is_zero ? 1 : 0;
-    if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) {
-        plan->jit[z] = nullptr;
-        return TTX_OK;
-    }
+    plan->jit[z] = nullptr;
+    if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) return TTX_OK;
     TiledLaunch L;
     ttx_status st = specialised_launch(plan, z, &L);
     if (st != TTX_OK) return st;
     const JitKernel* k = nullptr;
     st = jit_kernel(L, &k);
     if (st != TTX_OK) return st;
+    if (reps > 0) {
+        // candidate 0: the generic kernel, 1: the specialised one, on the
+        // tuner's scratch tensors (hipMalloc'd, so in the compiled alignment class)
+        const Problem& p = plan->prob;
+        const ttx_config& c = plan->cfg[z];
+        const bool beta0 = z == 1;
+        const Scalar alpha(1.25), beta(beta0 ? 0.0 : 0.75);
+        auto launch = [&](int i, const void* A, void* B, hipStream_t stream) -> hipError_t {
+            const void* Bsrc = beta0 ? nullptr : B;
+            if (i == 0) return launch_tiles(p, c, beta0, A, Bsrc, B, alpha, beta, stream);
+            TiledLaunch T;
+            if (!prepare_tiled(p, c, beta0, A, Bsrc, B, alpha, beta, &T) || !jit_matches(*k, T))
+                return hipErrorInvalidValue;
+            return jit_launch(*k, T, stream);
+        };
+        int best = 0;
+        double best_us = 0, us[2] = {0, 0};
+        st = time_candidates(p, beta0, 2, reps, launch, &best, &best_us, us);
+        if (st != TTX_OK) return st;
+        if (!(us[1] < us[0] * (1.0 - kSpecialiseMargin))) return TTX_OK;
+    }
     plan->jit[z] = k;
+    if (kept) *kept = 1;
     return TTX_OK;
 }
 

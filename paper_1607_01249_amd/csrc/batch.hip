@@ -95,7 +95,9 @@ constexpr int batch_lds_bytes() {
 constexpr int kBatchLds = batch_lds_bytes();
 
 // Tiles [t0, t1) of one problem with the variant's tile body, pipelined
-// across the tiles.  Thread 0 also claims the workgroup's next chunk: the
+// across the tiles, with plain (not nontemporal) stores: a second store kind
+// would double every variant's code in the persistent kernel, so its
+// candidates do not offer TTX_CFG_NT_STORE.  Thread 0 also claims the workgroup's next chunk: the
 // claim is issued first, so that its round trip overlaps the chunk, and its
 // result is left in *next (LDS) for the caller's barrier to publish.
 //
@@ -122,18 +124,18 @@ __device__ __noinline__ void batch_body(unsigned char* lds, const TileArgs<T>& a
     if (threadIdx.x == 0) claim = atomicAdd(counter, 1u);
     T* l = reinterpret_cast<T*>(lds);
     if constexpr (KIND == TTX_BATCH_STAGED) {
-        tile_loop<StagedTile<T, B0, P1, P2, P3>, true>(l, a, t0, t1, 1);
+        tile_loop<StagedTile<T, B0, P1, P2, P3, T, 0>, true>(l, a, t0, t1, 1);
     } else if constexpr (KIND == TTX_BATCH_DENSE) {
-        tile_loop<DenseTile<T, B0, P1>, false>(l, a, t0, t1, 1);
+        tile_loop<DenseTile<T, B0, P1, T, 0>, false>(l, a, t0, t1, 1);
     } else if constexpr (KIND == TTX_FAMILY_FLAT) {
         constexpr int V = P3 ? kVec<T> : 1;
-        tile_loop<FlatTile<T, B0, V, P1 / (kThreads * V)>, true>(l, a, t0, t1, 1);
+        tile_loop<FlatTile<T, B0, V, P1 / (kThreads * V), 0>, true>(l, a, t0, t1, 1);
     } else {
         constexpr int V = P3 ? kVec<T> : 1;
         if constexpr (KIND == TTX_FAMILY_MOVED)
-            tile_loop<MovedTile<T, B0, P1, P2, V, V>, true>(l, a, t0, t1, 1);
+            tile_loop<MovedTile<T, B0, P1, P2, V, V, T, 0>, true>(l, a, t0, t1, 1);
         else
-            tile_loop<PreservedTile<T, B0, P1, P2, V>, true>(l, a, t0, t1, 1);
+            tile_loop<PreservedTile<T, B0, P1, P2, V, T, 0>, true>(l, a, t0, t1, 1);
     }
     if (threadIdx.x == 0) *next = claim;
 }
@@ -360,7 +362,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
         a.Bdst = static_cast<float*>(Bdst);
         a.alpha = float(alpha);
         a.beta = float(beta);
-        a.flags = (c.flags & TTX_CFG_NT_STORE) ? KF_NT_STORE : 0;
+        a.flags = 0;   // plain stores (the tile bodies below fix the store kind)
         d->tiles = a.g.ntiles;
         std::memcpy(d->args, &a, sizeof(a));
     } else {
@@ -371,7 +373,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
         a.Bdst = static_cast<double*>(Bdst);
         a.alpha = alpha;
         a.beta = beta;
-        a.flags = (c.flags & TTX_CFG_NT_STORE) ? KF_NT_STORE : 0;
+        a.flags = 0;   // plain stores (the tile bodies below fix the store kind)
         d->tiles = a.g.ntiles;
         std::memcpy(d->args, &a, sizeof(a));
     }
@@ -393,14 +395,11 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     int n = 0;
     if (max_candidates == 0) max_candidates = 200;
     const int limit = max_candidates < 0 ? cap : (max_candidates < cap ? max_candidates : cap);
-    if (p.family == TTX_FAMILY_FLAT) {
-        for (int f : {0, TTX_CFG_NT_STORE}) {
-            if (n >= limit) break;
-            out[n] = default_config(p);
-            out[n].flags = f;
-            ++n;
-        }
-        return n;
+    if (p.family == TTX_FAMILY_FLAT) {   // one candidate: the persistent kernel stores plainly
+        if (limit < 1) return 0;
+        out[0] = default_config(p);
+        out[0].flags = 0;
+        return 1;
     }
     std::vector<ttx_config> all(1 << 17);
     int na = rank_candidates(p, -1, all.data(), nullptr, int(all.size()));
@@ -409,7 +408,7 @@ int batch_candidates(const Problem& p, int max_candidates, ttx_config* out, int 
     std::vector<int> eligible, kind;
     for (int i = 0; i < na; ++i) {
         const ttx_config& c = all[i];
-        if (c.flags & (TTX_CFG_XCD_SWIZZLE | TTX_CFG_WIDE)) continue;
+        if (c.flags & (TTX_CFG_XCD_SWIZZLE | TTX_CFG_WIDE | TTX_CFG_NT_STORE)) continue;
         int k = 0;
         if (config_is_dense(c)) {
             if (dense_index(p.dtype) < 0) continue;

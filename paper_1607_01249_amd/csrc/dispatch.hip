@@ -63,16 +63,18 @@ static hipError_t launch_flat(const Problem& p, const ttx_config& c, bool beta0,
     const int64_t cap = int64_t(device_cus()) * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
+    const dim3 g(static_cast<uint32_t>(blocks)), b(kThreads);
+    const bool nt = (a.flags & KF_NT_STORE) != 0;
     if constexpr (std::is_same<T, S>::value) {
-        if (beta0)
-            hipLaunchKernelGGL((k_flat<T, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_flat<T, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+        if (beta0 && nt) hipLaunchKernelGGL((k_flat<T, true, true>), g, b, 0, stream, a);
+        else if (beta0) hipLaunchKernelGGL((k_flat<T, true, false>), g, b, 0, stream, a);
+        else if (nt) hipLaunchKernelGGL((k_flat<T, false, true>), g, b, 0, stream, a);
+        else hipLaunchKernelGGL((k_flat<T, false, false>), g, b, 0, stream, a);
     } else {
-        if (beta0)
-            hipLaunchKernelGGL((k_flat_x<T, S, true>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_flat_x<T, S, false>), dim3(uint32_t(blocks)), dim3(kThreads), 0, stream, a);
+        if (beta0 && nt) hipLaunchKernelGGL((k_flat_x<T, S, true, true>), g, b, 0, stream, a);
+        else if (beta0) hipLaunchKernelGGL((k_flat_x<T, S, true, false>), g, b, 0, stream, a);
+        else if (nt) hipLaunchKernelGGL((k_flat_x<T, S, false, true>), g, b, 0, stream, a);
+        else hipLaunchKernelGGL((k_flat_x<T, S, false, false>), g, b, 0, stream, a);
     }
     return hipGetLastError();
 }
@@ -161,18 +163,19 @@ bool prepare_tiled(const Problem& p, const ttx_config& c, bool beta0, const void
 // The generic (pre-instantiated) kernel for a prepared launch.
 static hipError_t launch_prepared(const TiledLaunch& L, hipStream_t stream) {
     const ttx_config& c = L.c;
-    if (L.kind == kTileDense) return dense_launcher(L.p.code, L.beta0)(L.args, L.grid, stream);
+    const bool nt = (L.flags & KF_NT_STORE) != 0;
+    if (L.kind == kTileDense) return dense_launcher(L.p.code, L.beta0, nt)(L.args, L.grid, stream);
     if (L.kind == kTileStaged) {
         const StagedRow* rows;
         const int nr = staged_rows(L.p.code, L.beta0, &rows);
         for (int i = 0; i < nr; ++i)
             if (rows[i].n0_max == L.n0 && rows[i].tx == c.tile_a && rows[i].ty == c.tile_b)
-                return rows[i].fn(L.args, L.grid, stream);
+                return rows[i].fn[nt ? 1 : 0](L.args, L.grid, stream);
         return hipErrorInvalidValue;
     }
     const LauncherRow* table;
     const int n = L.kind == kTileMoved ? moved_rows(L.p.code, L.beta0, &table) : preserved_rows(L.p.code, L.beta0, &table);
-    const int variant = L.flags & (KF_VEC_A | KF_VEC_B);
+    const int variant = (L.flags & (KF_VEC_A | KF_VEC_B)) | (nt ? 4 : 0);
     for (int i = 0; i < n; ++i)
         if (table[i].ta == c.tile_a && table[i].tb == c.tile_b) return table[i].fn[variant](L.args, L.grid, stream);
     return hipErrorInvalidValue;
@@ -218,26 +221,30 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
     const char* z = beta0 ? "true" : "false";
     char buf[160];
     if (p.family == TTX_FAMILY_FLAT) {
-        std::snprintf(buf, sizeof(buf), "k_flat%s, %s>", types(p).c_str(), z);
+        const int f = kernel_flags(p, c, A, beta0 ? nullptr : Bsrc, Bdst);
+        std::snprintf(buf, sizeof(buf), "k_flat%s, %s, %s>", types(p).c_str(), z,
+                      (f & KF_NT_STORE) ? "true" : "false");
         return buf;
     }
     TiledLaunch L;
     if (!prepare_tiled(p, c, beta0, A, Bsrc, const_cast<void*>(Bdst), Scalar(1.0), Scalar(0.0), &L)) return "";
     const std::string ts = types(L.p);
+    const char* nt = (L.flags & KF_NT_STORE) ? "true" : "false";
     switch (L.kind) {
         case kTileDense:
-            std::snprintf(buf, sizeof(buf), "k_dense%s, %s, %d>", ts.c_str(), z, L.cap);
+            std::snprintf(buf, sizeof(buf), "k_dense%s, %s, %d, %s>", ts.c_str(), z, L.cap, nt);
             break;
         case kTileMoved:
-            std::snprintf(buf, sizeof(buf), "k_moved%s, %s, %d, %d, %d, %d>", ts.c_str(), z, L.c.tile_a, L.c.tile_b,
-                          L.va, L.vb);
+            std::snprintf(buf, sizeof(buf), "k_moved%s, %s, %d, %d, %d, %d, %s>", ts.c_str(), z, L.c.tile_a,
+                          L.c.tile_b, L.va, L.vb, nt);
             break;
         case kTileStaged:
-            std::snprintf(buf, sizeof(buf), "k_staged%s, %s, %d, %d, %d>", ts.c_str(), z, L.n0, L.c.tile_a, L.c.tile_b);
+            std::snprintf(buf, sizeof(buf), "k_staged%s, %s, %d, %d, %d, %s>", ts.c_str(), z, L.n0, L.c.tile_a,
+                          L.c.tile_b, nt);
             break;
         default:
-            std::snprintf(buf, sizeof(buf), "k_preserved%s, %s, %d, %d, %d>", ts.c_str(), z, L.c.tile_a, L.c.tile_b,
-                          L.va);
+            std::snprintf(buf, sizeof(buf), "k_preserved%s, %s, %d, %d, %d, %s>", ts.c_str(), z, L.c.tile_a,
+                          L.c.tile_b, L.va, nt);
     }
     return buf;
 }
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_axpby(const T* __restrict__ x, T* 
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (base + u * G < nv)
-                st<T, V>(y + (base + u * G) * V, epilogue<T, V, false>(a[u], b[u], alpha, beta), false);
+                st<T, V, false>(y + (base + u * G) * V, epilogue<T, V, false>(a[u], b[u], alpha, beta));
     }
     const int64_t i = nv * V + gid;
     if (i < n) y[i] = epilogue<T, 1, false>(x[i], y[i], alpha, beta);

@@ -44,7 +44,15 @@ struct JitKernel {
 static const char* const kJitOptions[] = {"-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
                                           "-Xclang", "-packed-fp32-ops"};
 static constexpr int kJitOptionCount = int(sizeof(kJitOptions) / sizeof(kJitOptions[0]));
-static const char* const kJitEntry = "ttx_specialised";
+
+static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
 
 // What a specialised kernel is compiled for: the tile kind and template
 // parameters, the element types, the beta class, the kernel flags and the
@@ -54,6 +62,24 @@ static std::string jit_key(const TiledLaunch& L) {
     std::string k(reinterpret_cast<const char*>(head), sizeof(head));
     k.append(reinterpret_cast<const char*>(L.args), sizeof(TileArgsHost));
     return k;
+}
+
+// The kernel's name: kind, element types, beta class, tile shape, and a
+// hash of the problem, so that profiles tell specialised kernels apart.
+static std::string entry_name(const TiledLaunch& L) {
+    static const char* const kKind[] = {"moved", "preserved", "staged", "dense"};
+    auto type = [](int dtype) {
+        std::string t = element_type_name(dtype);
+        return t.rfind("ttx::", 0) == 0 ? t.substr(5) : t;
+    };
+    std::string n = std::string("ttx_jit_") + kKind[L.kind] + "_" + type(L.p.dtype);
+    if (L.p.dtype_a != L.p.dtype) n += "_" + type(L.p.dtype_a);
+    n += L.beta0 ? "_b0_" : "_b_";
+    n += std::to_string(L.c.tile_a) + "x" + std::to_string(L.c.tile_b);
+    const std::string key = jit_key(L);
+    char h[16];
+    std::snprintf(h, sizeof(h), "_%08x", unsigned(fnv1a(key.data(), key.size()) & 0xffffffffu));
+    return n + h;
 }
 
 std::string jit_source(const TiledLaunch& L) {
@@ -100,7 +126,7 @@ std::string jit_source(const TiledLaunch& L) {
     s += "constexpr ttx::TileArgsHost kHost = __builtin_bit_cast(ttx::TileArgsHost, kImage);\n}  // namespace\n\n";
     s += "extern \"C\" __global__ __launch_bounds__(ttx::kThreads)";
     if (waves) s += " __attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + ")))";
-    s += "\nvoid " + std::string(kJitEntry) + "(ttx::TileArgs<" + T + ", " + S + "> a) {\n";
+    s += "\nvoid " + entry_name(L) + "(ttx::TileArgs<" + T + ", " + S + "> a) {\n";
     if (lds)
         s += "    __shared__ " + T + " lds[" + std::to_string(lds) + "];\n";
     else
@@ -110,14 +136,6 @@ std::string jit_source(const TiledLaunch& L) {
     return s;
 }
 
-static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
-    const unsigned char* p = static_cast<const unsigned char*>(data);
-    for (size_t i = 0; i < n; ++i) {
-        h ^= p[i];
-        h *= 1099511628211ull;
-    }
-    return h;
-}
 
 static std::string device_arch(int dev) {
     hipDeviceProp_t prop;
@@ -164,7 +182,7 @@ static void write_file_atomic(const std::string& path, const std::string& data) 
 // Compiles src for arch with hipRTC; *code receives the code object.
 static ttx_status compile(const std::string& src, const std::string& arch, std::string* code) {
     hiprtcProgram prog;
-    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "ttx_specialised.hip", kJitHeaderCount,
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "ttx_jit.hip", kJitHeaderCount,
                                          kJitHeaderSources, kJitHeaderNames);
     if (r != HIPRTC_SUCCESS) return fail(TTX_EHIP, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
     std::vector<const char*> opts(kJitOptions, kJitOptions + kJitOptionCount);
@@ -226,7 +244,7 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     k->key = key;
     e = hipModuleLoadData(&k->module, code.data());
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
-    e = hipModuleGetFunction(&k->fn, k->module, kJitEntry);
+    e = hipModuleGetFunction(&k->fn, k->module, entry_name(L).c_str());
     if (e != hipSuccess) {
         hipModuleUnload(k->module);
         return fail(TTX_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));

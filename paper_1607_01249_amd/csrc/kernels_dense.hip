@@ -9,22 +9,23 @@
 
 namespace ttx {
 
-template <typename T, typename S, bool B0, int CAP>
+template <typename T, typename S, bool B0, int CAP, bool NT>
 static hipError_t launch_dense(const void* args, uint32_t grid, hipStream_t stream) {
     const TileArgs<T, S>& a = *static_cast<const TileArgs<T, S>*>(args);
     if constexpr (std::is_same<T, S>::value)
-        hipLaunchKernelGGL((k_dense<T, B0, CAP>), dim3(grid), dim3(kThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_dense<T, B0, CAP, NT>), dim3(grid), dim3(kThreads), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_dense_x<T, S, B0, CAP>), dim3(grid), dim3(kThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_dense_x<T, S, B0, CAP, NT>), dim3(grid), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 
+// (both store kinds of a dense kernel use the same resources)
 template <typename T, typename S, bool B0, int CAP>
 static hipError_t dense_occupancy(int* nb) {
     if constexpr (std::is_same<T, S>::value)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense<T, B0, CAP>, kThreads, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense<T, B0, CAP, false>, kThreads, 0);
     else
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense_x<T, S, B0, CAP>, kThreads, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_dense_x<T, S, B0, CAP, false>, kThreads, 0);
 }
 
 // Workgroups of a full wave of the dense kernel on the current device: the
@@ -80,33 +81,25 @@ uint32_t dense_grid(int code, bool beta0) {
     }
 }
 
-TileLaunchFn dense_launcher(int code, bool beta0) {
+template <typename T, typename S, int CAP>
+static TileLaunchFn pick_dense(bool beta0, bool nt) {
+    if (beta0) return nt ? launch_dense<T, S, true, CAP, true> : launch_dense<T, S, true, CAP, false>;
+    return nt ? launch_dense<T, S, false, CAP, true> : launch_dense<T, S, false, CAP, false>;
+}
+
+TileLaunchFn dense_launcher(int code, bool beta0, bool nt) {
     switch (code) {
-        case TTX_F32:
-            return beta0 ? launch_dense<float, float, true, TTX_DENSE_CAP_F32> : launch_dense<float, float, false, TTX_DENSE_CAP_F32>;
-        case TTX_F64:
-            return beta0 ? launch_dense<double, double, true, TTX_DENSE_CAP_F64> : launch_dense<double, double, false, TTX_DENSE_CAP_F64>;
-        case TTX_C32:
-            return beta0 ? launch_dense<cf32, cf32, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, cf32, false, TTX_DENSE_CAP_C32>;
-        case TTX_C64:
-            return beta0 ? launch_dense<cf64, cf64, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, cf64, false, TTX_DENSE_CAP_C64>;
-        case TTX_F32_F64:
-            return beta0 ? launch_dense<double, float, true, TTX_DENSE_CAP_F64> : launch_dense<double, float, false, TTX_DENSE_CAP_F64>;
-        case TTX_F64_F32:
-            return beta0 ? launch_dense<float, double, true, TTX_DENSE_CAP_F32> : launch_dense<float, double, false, TTX_DENSE_CAP_F32>;
-        case TTX_C32_C64:
-            return beta0 ? launch_dense<cf64, cf32, true, TTX_DENSE_CAP_C64> : launch_dense<cf64, cf32, false, TTX_DENSE_CAP_C64>;
-        case TTX_C64_C32:
-            return beta0 ? launch_dense<cf32, cf64, true, TTX_DENSE_CAP_C32> : launch_dense<cf32, cf64, false, TTX_DENSE_CAP_C32>;
-        case kWideF32x4:
-            return beta0 ? launch_dense<f32x4, f32x4, true, TTX_DENSE_CAP_W16>
-                         : launch_dense<f32x4, f32x4, false, TTX_DENSE_CAP_W16>;
-        case kWideF64x2:
-            return beta0 ? launch_dense<f64x2, f64x2, true, TTX_DENSE_CAP_W16>
-                         : launch_dense<f64x2, f64x2, false, TTX_DENSE_CAP_W16>;
-        case kWideF32x2:
-            return beta0 ? launch_dense<f32x2, f32x2, true, TTX_DENSE_CAP_W8>
-                         : launch_dense<f32x2, f32x2, false, TTX_DENSE_CAP_W8>;
+        case TTX_F32: return pick_dense<float, float, TTX_DENSE_CAP_F32>(beta0, nt);
+        case TTX_F64: return pick_dense<double, double, TTX_DENSE_CAP_F64>(beta0, nt);
+        case TTX_C32: return pick_dense<cf32, cf32, TTX_DENSE_CAP_C32>(beta0, nt);
+        case TTX_C64: return pick_dense<cf64, cf64, TTX_DENSE_CAP_C64>(beta0, nt);
+        case TTX_F32_F64: return pick_dense<double, float, TTX_DENSE_CAP_F64>(beta0, nt);
+        case TTX_F64_F32: return pick_dense<float, double, TTX_DENSE_CAP_F32>(beta0, nt);
+        case TTX_C32_C64: return pick_dense<cf64, cf32, TTX_DENSE_CAP_C64>(beta0, nt);
+        case TTX_C64_C32: return pick_dense<cf32, cf64, TTX_DENSE_CAP_C32>(beta0, nt);
+        case kWideF32x4: return pick_dense<f32x4, f32x4, TTX_DENSE_CAP_W16>(beta0, nt);
+        case kWideF64x2: return pick_dense<f64x2, f64x2, TTX_DENSE_CAP_W16>(beta0, nt);
+        case kWideF32x2: return pick_dense<f32x2, f32x2, TTX_DENSE_CAP_W8>(beta0, nt);
         default: return nullptr;
     }
 }

@@ -9,21 +9,23 @@
 namespace ttx {
 
 // V counts elements of both A and B: the smaller of their 16-byte widths.
-template <typename T, typename S, bool B0, int TA, int TR, int VEC>
+template <typename T, typename S, bool B0, int TA, int TR, int VEC, bool NT>
 static hipError_t launch(const void* args, uint32_t grid, hipStream_t stream) {
     constexpr int W = kVec<T> < kVec<S> ? kVec<T> : kVec<S>;
     constexpr int V = (VEC == 3 && W > 1 && TA % W == 0) ? W : 1;
     const TileArgs<T, S>& a = *static_cast<const TileArgs<T, S>*>(args);
     if constexpr (std::is_same<T, S>::value)
-        hipLaunchKernelGGL((k_preserved<T, B0, TA, TR, V>), dim3(grid), dim3(kThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_preserved<T, B0, TA, TR, V, NT>), dim3(grid), dim3(kThreads), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_preserved_x<T, S, B0, TA, TR, V>), dim3(grid), dim3(kThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_preserved_x<T, S, B0, TA, TR, V, NT>), dim3(grid), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 
 #define TTX_ROW(T, S, B0, ta, tr) \
-    {ta, tr, {launch<T, S, B0, ta, tr, 0>, launch<T, S, B0, ta, tr, 0>, launch<T, S, B0, ta, tr, 0>, \
-              launch<T, S, B0, ta, tr, 3>}},
+    {ta, tr, {launch<T, S, B0, ta, tr, 0, false>, launch<T, S, B0, ta, tr, 0, false>,             \
+              launch<T, S, B0, ta, tr, 0, false>, launch<T, S, B0, ta, tr, 3, false>,             \
+              launch<T, S, B0, ta, tr, 0, true>, launch<T, S, B0, ta, tr, 0, true>,               \
+              launch<T, S, B0, ta, tr, 0, true>, launch<T, S, B0, ta, tr, 3, true>}},
 #define TTX_F32_B(ta, tr) TTX_ROW(float, float, false, ta, tr)
 #define TTX_F32_Z(ta, tr) TTX_ROW(float, float, true, ta, tr)
 #define TTX_F64_B(ta, tr) TTX_ROW(double, double, false, ta, tr)

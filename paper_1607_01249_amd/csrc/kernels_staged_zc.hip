@@ -1,6 +1,6 @@
 // Staged preserved-family kernel instantiations: A double complex, B single complex.
 #include "staged_launch.h"
 
-#define TTX_ENTRY_B(n0, tx, ty) {n0, tx, ty, launch_staged<cf32, cf64, false, n0, tx, ty>},
-#define TTX_ENTRY_Z(n0, tx, ty) {n0, tx, ty, launch_staged<cf32, cf64, true, n0, tx, ty>},
+#define TTX_ENTRY_B(n0, tx, ty) TTX_STAGED_ENTRY(cf32, cf64, false, n0, tx, ty)
+#define TTX_ENTRY_Z(n0, tx, ty) TTX_STAGED_ENTRY(cf32, cf64, true, n0, tx, ty)
 TTX_STAGED_TABLE(staged_rows_zc, cf32, cf64, TTX_STAGED_MENU_F64)

@@ -8,12 +8,13 @@ namespace ttx {
 using TileLaunchFn = hipError_t (*)(const void* args, uint32_t grid, hipStream_t stream);
 
 // fn[v]: v = vector variant, bit 0 = 16-byte accesses along A's tile index,
-// bit 1 = along B's tile index (the preserved family uses 0 and 3 only).
+// bit 1 = along B's tile index (the preserved family uses 0 and 3 only),
+// bit 2 = nontemporal stores to B.
 // A variant a shape cannot use (its tile edge is not a multiple of the
 // vector width) is instantiated with scalar accesses on that side.
 struct LauncherRow {
     int ta, tb;
-    TileLaunchFn fn[4];
+    TileLaunchFn fn[8];
 };
 
 int moved_rows_f32_beta(const LauncherRow** out);
@@ -50,7 +51,7 @@ int preserved_rows(int code, bool beta0, const LauncherRow** out);
 
 struct StagedRow {
     int n0_max, tx, ty;
-    TileLaunchFn fn;
+    TileLaunchFn fn[2];   // [nontemporal stores]
 };
 int staged_rows_f32(bool beta0, const StagedRow** out);
 int staged_rows_f64(bool beta0, const StagedRow** out);
@@ -76,7 +77,7 @@ inline int staged_rows(int code, bool beta0, const StagedRow** out) {
 
 // The dense-tile kernel for a data-type code and beta class, and the
 // workgroups that fill the device with it (its launches loop over the tiles).
-TileLaunchFn dense_launcher(int code, bool beta0);
+TileLaunchFn dense_launcher(int code, bool beta0, bool nt);
 uint32_t dense_grid(int code, bool beta0);
 
 }  // namespace ttx

@@ -117,11 +117,14 @@ __device__ __forceinline__ vec_t<T, N> ld(const T* p) {
     return __builtin_bit_cast(vec_t<T, N>, *reinterpret_cast<const R*>(p));
 }
 
-template <typename T, int N>
-__device__ __forceinline__ void st(T* p, const vec_t<T, N>& v, bool nt) {
+// NT: nontemporal store.  The store kind is a template parameter: a run-time
+// choice between the two stores, which differ only in their cache hint, is
+// merged by the compiler into one plain store.
+template <typename T, int N, bool NT>
+__device__ __forceinline__ void st(T* p, const vec_t<T, N>& v) {
     using R = typename RawOf<T, N>::type;
     const R r = __builtin_bit_cast(R, v);
-    if (nt)
+    if constexpr (NT)
         __builtin_nontemporal_store(r, reinterpret_cast<R*>(p));
     else
         *reinterpret_cast<R*>(p) = r;
@@ -170,15 +173,15 @@ __device__ __forceinline__ void ld_part(vec_t<T, N>& v, const T* p, int n) {
     }
 }
 
-template <typename T, int N>
-__device__ __forceinline__ void st_part(T* p, const vec_t<T, N>& v, int n, bool nt) {
+template <typename T, int N, bool NT>
+__device__ __forceinline__ void st_part(T* p, const vec_t<T, N>& v, int n) {
     if constexpr (N == 1) {
-        st<T, 1>(p, v, nt);
+        st<T, 1, NT>(p, v);
     } else {
         using R = typename RawU<T, N>::type;
         if (n >= N) {
             const R r = __builtin_bit_cast(R, v);
-            if (nt)
+            if constexpr (NT)
                 __builtin_nontemporal_store(r, reinterpret_cast<R*>(p));
             else
                 *reinterpret_cast<R*>(p) = r;
@@ -322,6 +325,19 @@ constexpr int pow2_ceil(int x) {
 // operations retire in order), and the stores drain while the next tile is
 // transposed.  `tile_loop` runs tiles t, t + step, ... < end that way.
 
+// Whether a tile stores to B nontemporally: fixed by the tile's NTS (0 or 1;
+// the generic kernels are instantiated once per store kind and the host
+// picks the instance from KF_NT_STORE), or, with NTS < 0, the KF_NT_STORE
+// bit of an argument block whose flags are a compile-time constant (the
+// size-specialised kernels).
+template <int NTS, typename Args>
+constexpr bool nt_of() {
+    if constexpr (NTS >= 0)
+        return NTS == 1;
+    else
+        return (Args::flags & KF_NT_STORE) != 0;
+}
+
 // One moved-family tile over the A-side super index x (A's first group_a
 // indices, contiguous in A) and the B-side super index y (B's first group_b
 // indices, contiguous in B): element (x0 + x, y0 + y) for x < ea, y < eb is
@@ -330,7 +346,7 @@ constexpr int pow2_ceil(int x) {
 // implies sAa == 1, VB > 1 implies sBb == 1); vectors need only element
 // alignment, and a vector that would run past the end of the super index is
 // moved element by element.  The LDS tile has TB rows of TA + 1 elements.
-template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T>
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T, int NTS = -1>
 struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
@@ -411,12 +427,12 @@ struct MovedTile {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
         const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int x = xb + i * RB;
-            if (live_b && x < c.ea) st_part<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], c.eb - yb, nt);
+            if (live_b && x < c.ea) st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], c.eb - yb);
         }
     }
 
@@ -427,7 +443,7 @@ struct MovedTile {
         const int tid = threadIdx.x;
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
         const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -436,8 +452,8 @@ struct MovedTile {
                 vec_t<T, VB> v;
 #pragma unroll
                 for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
-                st_part<T, VB>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
-                               c.eb - yb, nt);
+                st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
+                               c.eb - yb);
             }
         }
     }
@@ -446,7 +462,7 @@ struct MovedTile {
 // One preserved-family tile: rows of ea elements contiguous in A and B.
 // Row y < eb starts at A[oa + y*sAb] and B[ob + y*sBb]; element x of a row is
 // at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).  No LDS.
-template <typename T, bool BETA0, int TA, int TR, int V, typename S = T>
+template <typename T, bool BETA0, int TA, int TR, int V, typename S = T, int NTS = -1>
 struct PreservedTile {
     static constexpr bool kUsesLds = false;
     static constexpr int kTA = TA, kTB = TR;
@@ -493,11 +509,11 @@ struct PreservedTile {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
         const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (live && y0 + i * R < c.eb) st_part<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], c.ea - x, nt);
+            if (live && y0 + i * R < c.eb) st_part<T, V, nt>(a.Bdst + off_b + i * int64_t(R) * a.sBb, out[i], c.ea - x);
     }
 
     // finish and store in one pass
@@ -506,13 +522,13 @@ struct PreservedTile {
         const int tid = threadIdx.x;
         const int x = (tid % P) * V, y0 = tid / P;
         const bool live = (tid % P) < L && x < c.ea;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
         const int64_t off_b = c.ob + int64_t(x) * a.sBa + int64_t(y0) * a.sBb;
 #pragma unroll
         for (int i = 0; i < N; ++i)
             if (live && y0 + i * R < c.eb)
-                st_part<T, V>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
-                              epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta), c.ea - x, nt);
+                st_part<T, V, nt>(a.Bdst + off_b + i * int64_t(R) * a.sBb,
+                              epilogue<T, V, BETA0>(conv_vec<T, S, V>(ra[i]), rb[i], a.alpha, a.beta), c.ea - x);
     }
 };
 
@@ -524,7 +540,7 @@ struct PreservedTile {
 //   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
 // A is read in runs of n0*TX elements and B written in runs of n0*TY; the
 // tile passes through LDS as [y][x][i] (row length TX*N0 + 1).
-template <typename T, bool BETA0, int N0, int TX, int TY, typename S = T>
+template <typename T, bool BETA0, int N0, int TX, int TY, typename S = T, int NTS = -1>
 struct StagedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TX, kTB = TY;
@@ -598,14 +614,14 @@ struct StagedTile {
     template <typename Args>
     __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * NT, r = e % PB, x = e / PB;
             const int iv = r % N0, y = r / N0;
             if (iv < n0 && y < c.eb && x < c.ea)
-                st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
-                         out[i], nt);
+                st<T, 1, nt>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
+                         out[i]);
         }
     }
 
@@ -614,15 +630,15 @@ struct StagedTile {
     __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x, n0 = a.n0;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * NT, r = e % PB, x = e / PB;
             const int iv = r % N0, y = r / N0;
             if (iv < n0 && y < c.eb && x < c.ea) {
                 const T v = lds[y * LDR + x * N0 + iv];
-                st<T, 1>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
-                         epilogue<T, 1, BETA0>(v, rb[i], a.alpha, a.beta), nt);
+                st<T, 1, nt>(a.Bdst + c.ob + int64_t(iv) * a.s0B + int64_t(y) * a.sBb + a.gA.offset(c.x0 + x),
+                         epilogue<T, 1, BETA0>(v, rb[i], a.alpha, a.beta));
             }
         }
     }
@@ -640,7 +656,7 @@ struct StagedTile {
 // order (i, y, x, z: runs of runB), so that both sides run along their
 // contiguous index without padding lanes to a power of two.  The tile passes
 // through LDS as [z][y][x][i], rows of ldr >= runA elements (odd when possible).
-template <typename T, bool BETA0, int CAP, typename S = T>
+template <typename T, bool BETA0, int CAP, typename S = T, int NTS = -1>
 struct DenseTile {
     static constexpr bool kUsesLds = true;
     static constexpr int NT = kThreads, NS = CAP / NT;
@@ -739,20 +755,20 @@ struct DenseTile {
 
     template <typename Args>
     __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (inside(c, pb[s])) st<T, 1>(a.Bdst + b_off(a, c, s), out[s], nt);
+            if (inside(c, pb[s])) st<T, 1, nt>(a.Bdst + b_off(a, c, s), out[s]);
     }
 
     template <typename Args>
     __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (inside(c, pb[s]))
-                st<T, 1>(a.Bdst + b_off(a, c, s), epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta), nt);
+                st<T, 1, nt>(a.Bdst + b_off(a, c, s), epilogue<T, 1, BETA0>(lds[lb[s]], rb[s], a.alpha, a.beta));
     }
 };
 
@@ -763,7 +779,7 @@ constexpr int dense_lds_elems(int cap) { return 2 * cap; }
 // One flat tile (everything merged into one index): TF consecutive elements,
 // V-element vectors (V > 1 needs unit strides and an element count that is
 // a multiple of V), U vectors per thread.  No LDS.
-template <typename T, bool BETA0, int V, int U>
+template <typename T, bool BETA0, int V, int U, int NTS = -1>
 struct FlatTile {
     static constexpr bool kUsesLds = false;
     static constexpr int NT = kThreads, TF = NT * V * U;
@@ -800,11 +816,11 @@ struct FlatTile {
     template <typename Args>
     __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
-        const bool nt = a.flags & KF_NT_STORE;
+        constexpr bool nt = nt_of<NTS, Args>();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = (tid + u * NT) * V;
-            if (k < c.ea) st<T, V>(a.Bdst + c.ob + int64_t(k) * a.sBa, out[u], nt);
+            if (k < c.ea) st<T, V, nt>(a.Bdst + c.ob + int64_t(k) * a.sBa, out[u]);
         }
     }
     template <typename Args>
@@ -915,75 +931,75 @@ __device__ __forceinline__ void run_specialised(T* lds, const TileArgs<T, S>& in
 // register allocation: the scalar fallbacks need many more address
 // registers than the 16-byte paths and would otherwise lower the occupancy
 // of every variant.  Scalar variants ask for at least 4 waves per SIMD.
-template <typename T, bool BETA0, int TA, int TB, int VA, int VB>
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB, bool NT>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
 void k_moved(TileArgs<T> a) {
     __shared__ T lds[TB * (TA + 1)];
-    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB>, false>(lds, a);
+    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB, T, NT>, false>(lds, a);
 }
 
-template <typename T, bool BETA0, int TA, int TR, int V>
+template <typename T, bool BETA0, int TA, int TR, int V, bool NT>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
 void k_preserved(TileArgs<T> a) {
-    run_grid<PreservedTile<T, BETA0, TA, TR, V>, false>(static_cast<T*>(nullptr), a);
+    run_grid<PreservedTile<T, BETA0, TA, TR, V, T, NT>, false>(static_cast<T*>(nullptr), a);
 }
 
 // Launched with about one wave of workgroups, each looping over tiles
 // (pipelined): the per-slot offsets are computed once per workgroup.
-template <typename T, bool BETA0, int CAP>
+template <typename T, bool BETA0, int CAP, bool NT>
 __global__ __launch_bounds__(kThreads) void k_dense(TileArgs<T> a) {
     __shared__ T lds[dense_lds_elems(CAP)];
-    run_grid<DenseTile<T, BETA0, CAP>, true>(lds, a);
+    run_grid<DenseTile<T, BETA0, CAP, T, NT>, true>(lds, a);
 }
 
-template <typename T, bool BETA0, int N0, int TX, int TY>
+template <typename T, bool BETA0, int N0, int TX, int TY, bool NT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_staged(TileArgs<T> a) {
     __shared__ T lds[TY * (TX * N0 + 1)];
-    run_grid<StagedTile<T, BETA0, N0, TX, TY>, false>(lds, a);
+    run_grid<StagedTile<T, BETA0, N0, TX, TY, T, NT>, false>(lds, a);
 }
 
 // Mixed precision (A of type S, B of type T): the same tiles, converting
 // A's elements to T as they are loaded.
-template <typename T, typename S, bool BETA0, int TA, int TB, int VA, int VB>
+template <typename T, typename S, bool BETA0, int TA, int TB, int VA, int VB, bool NT>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(VA == 1 || VB == 1 ? 4 : 1)))
 void k_moved_x(TileArgs<T, S> a) {
     __shared__ T lds[TB * (TA + 1)];
-    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB, S>, false>(lds, a);
+    run_grid<MovedTile<T, BETA0, TA, TB, VA, VB, S, NT>, false>(lds, a);
 }
 
-template <typename T, typename S, bool BETA0, int TA, int TR, int V>
+template <typename T, typename S, bool BETA0, int TA, int TR, int V, bool NT>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 1)))
 void k_preserved_x(TileArgs<T, S> a) {
-    run_grid<PreservedTile<T, BETA0, TA, TR, V, S>, false>(static_cast<T*>(nullptr), a);
+    run_grid<PreservedTile<T, BETA0, TA, TR, V, S, NT>, false>(static_cast<T*>(nullptr), a);
 }
 
-template <typename T, typename S, bool BETA0, int CAP>
+template <typename T, typename S, bool BETA0, int CAP, bool NT>
 __global__ __launch_bounds__(kThreads) void k_dense_x(TileArgs<T, S> a) {
     __shared__ T lds[dense_lds_elems(CAP)];
-    run_grid<DenseTile<T, BETA0, CAP, S>, true>(lds, a);
+    run_grid<DenseTile<T, BETA0, CAP, S, NT>, true>(lds, a);
 }
 
-template <typename T, typename S, bool BETA0, int N0, int TX, int TY>
+template <typename T, typename S, bool BETA0, int N0, int TX, int TY, bool NT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_staged_x(TileArgs<T, S> a) {
     __shared__ T lds[TY * (TX * N0 + 1)];
-    run_grid<StagedTile<T, BETA0, N0, TX, TY, S>, false>(lds, a);
+    run_grid<StagedTile<T, BETA0, N0, TX, TY, S, NT>, false>(lds, a);
 }
 
 // Flat: one index of n elements with strides sa, sb.  The vector path
 // (contiguous, aligned) moves 4 vectors per thread per iteration; the
 // remaining n % V elements are handled one per thread.  V counts elements
 // of both A and B (the smaller of their 16-byte widths).
-template <typename T, typename S, bool BETA0>
+template <typename T, typename S, bool BETA0, bool NT>
 __device__ __forceinline__ void flat_body(const FlatArgs<T, S>& a) {
     constexpr int V = kVec<T> < kVec<S> ? kVec<T> : kVec<S>;
     constexpr int U = 4;
-    const bool nt = a.flags & KF_NT_STORE;
+    constexpr bool nt = NT;
     const int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     const int64_t G = int64_t(gridDim.x) * kThreads;
     if (a.flags & KF_VEC_A) {
@@ -1003,8 +1019,7 @@ __device__ __forceinline__ void flat_body(const FlatArgs<T, S>& a) {
             for (int u = 0; u < U; ++u) {
                 const int64_t i = base + u * G;
                 if (i < nv)
-                    st<T, V>(a.Bdst + i * V, epilogue<T, V, BETA0>(conv_vec<T, S, V>(va[u]), vb[u], a.alpha, a.beta),
-                             nt);
+                    st<T, V, nt>(a.Bdst + i * V, epilogue<T, V, BETA0>(conv_vec<T, S, V>(va[u]), vb[u], a.alpha, a.beta));
             }
         }
         const int64_t i = nv * V + gid;
@@ -1022,14 +1037,14 @@ __device__ __forceinline__ void flat_body(const FlatArgs<T, S>& a) {
     }
 }
 
-template <typename T, bool BETA0>
+template <typename T, bool BETA0, bool NT>
 __global__ __launch_bounds__(kThreads) void k_flat(FlatArgs<T> a) {
-    flat_body<T, T, BETA0>(a);
+    flat_body<T, T, BETA0, NT>(a);
 }
 
-template <typename T, typename S, bool BETA0>
+template <typename T, typename S, bool BETA0, bool NT>
 __global__ __launch_bounds__(kThreads) void k_flat_x(FlatArgs<T, S> a) {
-    flat_body<T, S, BETA0>(a);
+    flat_body<T, S, BETA0, NT>(a);
 }
 
 }  // namespace ttx

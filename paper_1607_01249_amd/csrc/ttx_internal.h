@@ -229,10 +229,11 @@ void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec)
 uint64_t table_generation();
 // Times `count` candidates on tuner-owned scratch buffers sized for p (minimum
 // of `reps` runs, the 1 GiB flush area cleared before each) and returns the
-// fastest; launch(i, A, B, stream) runs candidate i.
+// fastest; launch(i, A, B, stream) runs candidate i.  all_us (may be NULL)
+// receives every candidate's time.
 ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
                            const std::function<hipError_t(int, const void*, void*, hipStream_t)>& launch,
-                           int* best_i, double* best_us);
+                           int* best_i, double* best_us, double* all_us = nullptr);
 
 // -- batched execution (batch.hip) ------------------------------------------
 // One entry of the device descriptor table read by the persistent kernel:

@@ -179,7 +179,7 @@ struct TuneScratch {
 
 ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
                            const std::function<hipError_t(int, const void*, void*, hipStream_t)>& launch,
-                           int* best_i, double* best_us) {
+                           int* best_i, double* best_us, double* all_us) {
     if (reps <= 0) reps = 3;
     TuneScratch s;
     s.flush = flush_area();
@@ -211,6 +211,7 @@ ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
             (void)hipEventElapsedTime(&ms, s.e0, s.e1);
             if (ms * 1e3 < t_min) t_min = ms * 1e3;
         }
+        if (all_us) all_us[i] = t_min;
         if (t_min < *best_us) {   // ties keep the earlier (better-ranked) candidate
             *best_us = t_min;
             *best_i = i;

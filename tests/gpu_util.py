@@ -8,6 +8,9 @@ F32, F64 = np.dtype(np.float32), np.dtype(np.float64)
 C32, C64 = np.dtype(np.complex64), np.dtype(np.complex128)
 REAL_OF = {C32: F32, C64: F64}
 _CODES = {F32: ttx.F32, F64: ttx.F64, C32: ttx.C32, C64: ttx.C64}
+_DTYPES = {v: k for k, v in _CODES.items()}
+# data-type code -> (A's numpy dtype, B's numpy dtype)
+TYPES_OF_CODE = {code: (_DTYPES[a], _DTYPES[b]) for (a, b), code in ttx.CODE_OF.items()}
 
 
 def dtype_code(dtype, dtype_b=None):

@@ -127,6 +127,21 @@ def test_set_config_drops_the_specialised_kernel():
         ttx.ttx_plan_destroy(plan)
 
 
+def test_timed_specialisation_keeps_the_faster_kernel():
+    """reps > 0 times both kernels and attaches the specialised one only when
+    it wins; either way the plan computes the same bits."""
+    for perm, size, bz in [((0, 5, 1, 4, 2, 3), (20, 16, 16, 20, 16, 16), False),
+                           ((2, 0, 3, 1), (160, 160, 32, 32), True), ((0, 2, 1), (64, 90, 48), False)]:
+        plan = ttx.ttx_plan_create(ttx.F64, perm, size)
+        try:
+            kept = ttx.ttx_plan_specialise(plan, bz, reps=3)
+            assert ttx.ttx_plan_describe(plan)["specialised"][int(bz)] == int(kept)
+            _say("timed specialisation %s %s beta0=%s: kept=%s" % (perm, size, bz, kept))
+        finally:
+            ttx.ttx_plan_destroy(plan)
+        _check(perm, size, F64, F64, bz, seed=12)
+
+
 def test_disk_cache_written_and_reused(tmp_path):
     """With TTX_JIT_CACHE set, the code object lands in the directory; a
     second process finds it there and leaves it untouched."""

@@ -282,6 +282,39 @@ def test_every_candidate_bit_identical(perm, size, dtype):
             assert_parity(got, ref, exact=True, what=str(cands[i].as_dict()))
 
 
+# -- nontemporal and plain stores (separate kernel instances) compute the same bits ---------
+@pytest.mark.parametrize("code,perm,size", [
+    (ttx.F32, (2, 0, 3, 1), (37, 70, 19, 23)), (ttx.F64, (0, 2, 1, 3), (40, 9, 11, 13)),
+    (ttx.F64, (0, 5, 1, 4, 2, 3), (20, 7, 4, 3, 5, 6)), (ttx.F32, (0, 5, 1, 4, 2, 3), (24, 7, 4, 3, 5, 6)),
+    (ttx.F32, (1, 0, 2), (3, 4, 700)), (ttx.F64, (0, 1), (64, 9)), (ttx.C64, (2, 1, 0), (33, 40, 27)),
+    (ttx.F64_F32, (3, 2, 1, 0), (5, 3, 70, 9))])
+def test_store_kinds_bit_identical(code, perm, size):
+    """Every tile kind of a problem with TTX_CFG_NT_STORE on and off: the
+    generic kernels exist once per store kind and must agree bit for bit."""
+    from gpu_util import TYPES_OF_CODE
+    da, db = TYPES_OF_CODE[code]
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    seen, pick = set(), []
+    for c in cands:
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c, c.flags & (ttx.CFG_DENSE | ttx.CFG_WIDE))
+        if key not in seen:
+            seen.add(key)
+            pick.append(c)
+    n = _elems(size)
+    A = workloads.uniform(n, da, 16)
+    B = workloads.uniform(n, db, 17)
+    cx = db in (np.complex64, np.complex128)
+    for beta in ((0.5 - 0.25j, 0j) if cx else (0.7, 0.0)):
+        alpha = (1.25 + 0.5j) if cx else 1.3
+        ref = B.copy()
+        oracle.transpose(perm, size, alpha, A, beta, ref)
+        for c in pick:
+            for nt in (0, ttx.CFG_NT_STORE):
+                c.flags = (c.flags & ~ttx.CFG_NT_STORE) | nt
+                got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c)
+                assert_parity(got, ref, exact=True, what=str(c.as_dict()))
+
+
 # -- dense tiles (run-time extents, rows packed without padding) ----------------------------
 DENSE_CASES = [
     ((0, 2, 1), (2, 17835, 2), None, None),            # kept stride-1 index, rows of 2

@@ -41,14 +41,15 @@ def _source(dtype, perm, size, bz):
 
 
 def _expected_tile(name):
-    """The tile type a generic kernel name runs: k_moved<T, B0, TA, TB, VA, VB>
+    """The tile type a generic kernel name runs: k_moved<T, B0, TA, TB, VA, VB, NT>
     runs MovedTile<T, B0, TA, TB, VA, VB, S> (k_<kind>_x<T, S, ...> when the
-    types differ), and likewise for the other kinds."""
+    types differ; the specialised kernel takes the store kind NT from its
+    constant flags), and likewise for the other kinds."""
     m = re.fullmatch(r"k_(moved|preserved|staged|dense)(_x)?<(.*)>", name)
     assert m, name
     args = [a.strip() for a in m.group(3).split(",")]
     t = args[0]
-    s, rest = (args[1], args[2:]) if m.group(2) else (t, args[1:])
+    s, rest = (args[1], args[2:-1]) if m.group(2) else (t, args[1:-1])
     tile = {"moved": "MovedTile", "preserved": "PreservedTile", "staged": "StagedTile", "dense": "DenseTile"}
     return "ttx::%s<%s, %s, %s>" % (tile[m.group(1)], t, ", ".join(rest), s)
 
@@ -57,7 +58,7 @@ def _expected_tile(name):
 def test_source_runs_the_generic_kernels_tile(case):
     src, name = _source(*case)
     assert _expected_tile(name) in src, (name, src[-400:])
-    assert 'extern "C" __global__' in src and "ttx_specialised(" in src
+    assert 'extern "C" __global__' in src and re.search(r"void ttx_jit_\w+_[0-9a-f]{8}\(", src)
     assert "__builtin_bit_cast(ttx::TileArgsHost, kImage)" in src
 
 
@@ -67,7 +68,8 @@ def test_nothing_to_specialise_for_flat_and_empty():
         try:
             with pytest.raises(ttx.TTXError):
                 ttx.ttx_plan_specialised_source(plan, False)
-            ttx.ttx_plan_specialise(plan, False)   # no GPU call: nothing to compile
+            assert not ttx.ttx_plan_specialise(plan, False)   # no GPU call: nothing to compile
+            assert not ttx.ttx_plan_specialise(plan, True, reps=3)
             assert ttx.ttx_plan_describe(plan)["specialised"] == [0, 0]
         finally:
             ttx.ttx_plan_destroy(plan)
@@ -79,7 +81,7 @@ def test_specialised_source_null_and_small_buffer():
         buf = ctypes.create_string_buffer(64)
         assert ttx.lib().ttx_plan_specialised_source(plan, 0, buf, 64) == ttx.EINVAL
         assert ttx.lib().ttx_plan_specialised_source(None, 0, buf, 64) == ttx.EINVAL
-        assert ttx.lib().ttx_plan_specialise(None, 0) == ttx.EINVAL
+        assert ttx.lib().ttx_plan_specialise(None, 0, 0, None) == ttx.EINVAL
     finally:
         ttx.ttx_plan_destroy(plan)
 
@@ -128,6 +130,6 @@ def test_source_compiles_without_scratch(case, tmp_path):
     co = tmp_path / "k.co"
     co.write_bytes(code)
     notes = subprocess.run([readobj, "--notes", str(co)], capture_output=True, text=True, check=True).stdout
-    assert ".name:           ttx_specialised" in notes
+    assert re.search(r"\.name:\s+ttx_jit_\w+", notes), notes
     # every index constant folded: no private (scratch) memory
     assert re.search(r"\.private_segment_fixed_size:\s+0\b", notes), notes
