@@ -103,7 +103,8 @@ typedef enum ttx_family {
 
 /* Config flags. */
 #define TTX_CFG_XCD_SWIZZLE 1  /* map consecutive tile ids onto one XCD */
-#define TTX_CFG_NT_STORE 2     /* non-temporal (streaming) stores to B */
+#define TTX_CFG_NT_STORE 2     /* non-temporal (streaming) stores to B (per-call kernels;
+                                  the persistent batched kernel always stores plainly) */
 #define TTX_CFG_DENSE 4        /* dense tiles (MOVED, or PRESERVED with index groups): tile_a x
                                   tile_b are run-time extents, rows of the shared stride-1 index
                                   (PRESERVED) are packed without padding, at most 1024 elements
