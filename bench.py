@@ -36,8 +36,8 @@ CLIENTS = 4
 SLOTS = 8
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 # the per-call kernels' sources (their code, without comments, keys the counter traffic)
-KERNEL_SOURCES = (["tile_kernels.h", "menu.h", "registry.h", "moved_launch.h", "staged_launch.h",
-                   "dispatch.hip"] +
+KERNEL_SOURCES = (["device_types.h", "tile_kernels.h", "menu.h", "registry.h", "moved_launch.h",
+                   "staged_launch.h", "dispatch.hip"] +
                   sorted(os.path.basename(f) for f in glob.glob(os.path.join(
                       os.path.dirname(os.path.abspath(__file__)), "paper_1607_01249_amd", "csrc",
                       "kernels_*.hip"))))
