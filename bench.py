@@ -37,7 +37,7 @@ SLOTS = 8
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 # the per-call kernels' sources (their code, without comments, keys the counter traffic)
 KERNEL_SOURCES = (["device_types.h", "tile_kernels.h", "menu.h", "registry.h", "moved_launch.h",
-                   "staged_launch.h", "dispatch.hip"] +
+                   "staged_launch.h", "dispatch.hip", "jit.cpp"] +
                   sorted(os.path.basename(f) for f in glob.glob(os.path.join(
                       os.path.dirname(os.path.abspath(__file__)), "paper_1607_01249_amd", "csrc",
                       "kernels_*.hip"))))
@@ -75,6 +75,8 @@ def parse_args():
     ap.add_argument("--literal", action="store_true",
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
+    ap.add_argument("--generic", action="store_true",
+                    help="time the step through ttx_transpose with the generic kernels (no run-time compilation)")
     ap.add_argument("--no-specialised", action="store_true",
                     help="skip the comparison with size-specialised (run-time compiled) kernels")
     ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
@@ -271,7 +273,7 @@ def traffic_from(fetch_path, write_path, out_path=None):
         scale = (1 << 30) / (float(np.median(copy)) * 1024.0)
         res[counter] = dict(scale=scale, copy_kib=float(np.median(copy)),
                             kernels={k: dict(kib=float(np.mean(v)), dispatches=len(v))
-                                     for k, v in per.items() if k.startswith("k_")})
+                                     for k, v in per.items() if k.startswith(("k_", "ttx_jit_"))})
     table = {}
     for k, f in res["FETCH_SIZE"]["kernels"].items():
         w = res["WRITE_SIZE"]["kernels"].get(k)
@@ -735,22 +737,35 @@ def main():
     tune_s = time.time() - tune_t0
     if args.save_table:
         ttx.ttx_tune_table_save(args.save_table)
+    # The step runs each case's plan with its size-specialised kernel (Sec. 2.1:
+    # a solution per transposition, sizes as constants), compiled here, before
+    # the timed region; a case whose compilation fails keeps its generic kernel.
+    spec_t0 = time.time()
+    n_spec = 0
     for c in cases:
-        plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
-        c["kernel"] = ttx.ttx_plan_kernel_name(plan, c["beta"], c["A"].data_ptr(), c["B"].data_ptr())
-        c["config"] = ttx.ttx_plan_describe(plan)["config"][1 if c["beta"] == 0 else 0]
-        ttx.ttx_plan_destroy(plan)
+        c["plan"] = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
+        if not args.generic:
+            try:
+                n_spec += ttx.ttx_plan_specialise(c["plan"], c["beta"] == 0)
+            except ttx.TTXError as e:
+                log("specialisation failed for %s (%s): generic kernel" % (c["name"], e))
+        c["kernel"] = ttx.ttx_plan_kernel_name(c["plan"], c["beta"], c["A"].data_ptr(), c["B"].data_ptr())
+        c["config"] = ttx.ttx_plan_describe(c["plan"])["config"][1 if c["beta"] == 0 else 0]
+    spec_s = time.time() - spec_t0
 
     log("measuring ceilings")
     ceil = measure_ceilings(torch, ttx)
     d2d = ceil["hipMemcpy_d2d"]["GBps"]
 
-    def step(events=None):
+    def step(events=None, generic=args.generic):
         for i, c in enumerate(cases):
             if events is not None:
                 events[i].record()
-            ttx.ttx_transpose(c["code"], len(c["perm"]), c["perm"], c["size"], None, None,
-                              c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
+            if generic:
+                ttx.ttx_transpose(c["code"], len(c["perm"]), c["perm"], c["size"], None, None,
+                                  c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
+            else:
+                ttx.ttx_plan_execute(c["plan"], c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
         if events is not None:
             events[len(cases)].record()
 
@@ -770,6 +785,17 @@ def main():
 
     step_bytes = sum(c["bytes"] for c in cases)
     value = step_bytes * args.steps / wall / 1e9
+    per_call_generic = None
+    if not args.generic and not args.profile_run:
+        # the same step through the per-call entry point with the generic kernels
+        step(generic=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(generic=True)
+        torch.cuda.synchronize()
+        v = step_bytes * args.steps / (time.perf_counter() - t0) / 1e9
+        per_call_generic = dict(value=round(v, 1), pct_of_d2d=round(100 * v / d2d, 1), entry_point="ttx_transpose")
     per_case, by_kernel = [], {}
     for i, c in enumerate(cases):
         durs = [events[k][i].elapsed_time(events[k][i + 1]) * 1e-3 for k in range(args.steps)]
@@ -808,9 +834,10 @@ def main():
         log("size-specialised kernels")
         specialised = bench_specialised(torch, ttx, cases, d2d, stream)
 
-    for c in cases:   # the large cases' buffers are not needed any more
+    for c in cases:   # the large cases' buffers and plans are not needed any more
         c.pop("A", None)
         c.pop("B", None)
+        ttx.ttx_plan_destroy(c.pop("plan"))
     torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
@@ -843,7 +870,11 @@ def main():
                              "(beta=0.7, beta=0), alpha=1.3, %d cases per step%s" %
                              (len(cases), " + literal 160^4" if args.literal else ""),
                     cases=len(cases), bytes_per_step=step_bytes, layout="column-major",
-                    entry_point="ttx_transpose (per call)", parallelism="single GPU"),
+                    entry_point="ttx_transpose (per call, generic kernels)" if args.generic else
+                    "ttx_plan_execute, one plan per case with its size-specialised kernel (ttx_plan_specialise, "
+                    "%d of %d compiled in %.1f s before timing)" % (n_spec, len(cases), spec_s),
+                    parallelism="single GPU"),
+        per_call_generic=per_call_generic,
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
         per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),

@@ -222,8 +222,10 @@ ttx_status ttx_plan_set_config(ttx_plan *plan, int beta_is_zero, const ttx_confi
 ttx_status ttx_plan_destroy(ttx_plan *plan);
 /* Name of the kernel ttx_plan_execute would launch for these pointers (the
  * vector variant depends on their alignment), e.g.
- * "k_moved<float, false, 64, 64, 4, 4>", as profilers print it; written
- * NUL-terminated into buf (len bytes).  Host only. */
+ * "k_moved<float, false, 64, 64, 4, 4, false>" (the last argument: nontemporal
+ * stores), or the name of the plan's size-specialised kernel when that one
+ * would run ("ttx_jit_moved_float_b_64x64_1a2b3c4d"), as profilers print it;
+ * written NUL-terminated into buf (len bytes).  Host only. */
 ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A, const void *B,
                                 char *buf, int len);
 

@@ -309,7 +309,15 @@ ttx_status ttx_plan_kernel_name(const ttx_plan* plan, double beta, const void* A
     if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
     const Problem& p = plan->prob;
     const bool beta0 = beta_is_zero(p.dtype, beta);
-    const std::string name = kernel_name(p, plan->cfg[beta0 ? 1 : 0], beta0, A, B, B);
+    const int z = beta0 ? 1 : 0;
+    std::string name;
+    TiledLaunch L;
+    if (plan->jit[z] && prepare_tiled(p, plan->cfg[z], beta0, A, B, const_cast<void*>(B), Scalar(1.0), Scalar(beta),
+                                      &L) &&
+        jit_matches(*plan->jit[z], L))
+        name = jit_name(*plan->jit[z]);
+    else
+        name = kernel_name(p, plan->cfg[z], beta0, A, B, B);
     if (int(name.size()) >= len) return fail(TTX_EINVAL, "buffer too small");
     std::memcpy(buf, name.c_str(), name.size() + 1);
     return TTX_OK;

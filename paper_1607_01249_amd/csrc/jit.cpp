@@ -36,6 +36,7 @@ namespace ttx {
 struct JitKernel {
     int device;
     std::string key;
+    std::string name;
     hipModule_t module;
     hipFunction_t fn;
     uint32_t dense_grid;   // dense tiles: workgroups that fill the device with this kernel
@@ -242,9 +243,10 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     std::unique_ptr<JitKernel> k(new JitKernel());
     k->device = dev;
     k->key = key;
+    k->name = entry_name(L);
     e = hipModuleLoadData(&k->module, code.data());
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
-    e = hipModuleGetFunction(&k->fn, k->module, entry_name(L).c_str());
+    e = hipModuleGetFunction(&k->fn, k->module, k->name.c_str());
     if (e != hipSuccess) {
         hipModuleUnload(k->module);
         return fail(TTX_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
@@ -262,6 +264,8 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     g_jit[{dev, key}] = std::move(k);
     return TTX_OK;
 }
+
+const std::string& jit_name(const JitKernel& k) { return k.name; }
 
 bool jit_matches(const JitKernel& k, const TiledLaunch& L) {
     int dev = 0;

@@ -204,6 +204,8 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out);
 std::string jit_source(const TiledLaunch& L);
 // True when k runs what L launches (same device, kernel, flags and arguments).
 bool jit_matches(const JitKernel& k, const TiledLaunch& L);
+// The kernel's name as profilers print it.
+const std::string& jit_name(const JitKernel& k);
 hipError_t jit_launch(const JitKernel& k, const TiledLaunch& L, hipStream_t stream);
 // C++ spelling of an element type ("float", "ttx::cf32", "ttx::f32x4", ...).
 const char* element_type_name(int dtype);

@@ -142,6 +142,20 @@ def test_timed_specialisation_keeps_the_faster_kernel():
         _check(perm, size, F64, F64, bz, seed=12)
 
 
+def test_kernel_name_names_the_specialised_kernel():
+    import torch
+    plan = ttx.ttx_plan_create(ttx.F32, (2, 0, 3, 1), (37, 70, 19, 23))
+    try:
+        generic = ttx.ttx_plan_kernel_name(plan, 0.7, 1 << 20, 3 << 20)
+        assert generic.startswith("k_moved<float, false")
+        ttx.ttx_plan_specialise(plan, False)
+        name = ttx.ttx_plan_kernel_name(plan, 0.7, 1 << 20, 3 << 20)
+        assert name.startswith("ttx_jit_moved_float_b_"), name
+        assert ttx.ttx_plan_kernel_name(plan, 0.0, 1 << 20, 3 << 20).startswith("k_moved<float, true")
+    finally:
+        ttx.ttx_plan_destroy(plan)
+
+
 def test_disk_cache_written_and_reused(tmp_path):
     """With TTX_JIT_CACHE set, the code object lands in the directory; a
     second process finds it there and leaves it untouched."""
