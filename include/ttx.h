@@ -276,6 +276,19 @@ ttx_status ttx_plan_specialised_source(const ttx_plan *plan, int beta_is_zero, c
 ttx_status ttx_tune(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
                     const int64_t *outer_a, const int64_t *outer_b, int beta_is_zero,
                     int max_candidates, int reps, ttx_config *best, int *n_timed);
+/* ttx_tune with every kept candidate compiled at run time as a
+ * size-specialised kernel (see ttx_plan_specialise) and timed in that form,
+ * as the paper's compiler compiles and times each candidate (Sec. 2.1
+ * stages 4 and 5): max_candidates defaults to 24 when 0 is passed (each
+ * candidate costs a compilation of about half a second; -1 keeps all).
+ * The fastest config goes into the tune table as with ttx_tune; plans made
+ * afterwards take it, and ttx_plan_specialise attaches its specialised
+ * kernel.  Empty and single-index problems take the generic search.  Needs
+ * a GPU; blocks the caller.  Errors as ttx_tune, and TTX_EHIP when a
+ * compilation fails. */
+ttx_status ttx_tune_specialised(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
+                                const int64_t *outer_a, const int64_t *outer_b, int beta_is_zero,
+                                int max_candidates, int reps, ttx_config *best, int *n_timed);
 /* The ranked candidate list (host only, no GPU): up to `cap` configs in
  * increasing estimated cost, with their estimated costs in cost[] (may be
  * NULL).  *count receives how many were written. */

@@ -187,6 +187,7 @@ def _declare(L):
         "ttx_plan_specialise": ([vp, S, S, ip], S),
         "ttx_plan_specialised_source": ([vp, S, ctypes.c_char_p, S], S),
         "ttx_tune": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
+        "ttx_tune_specialised": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_candidates": ([S, S, ip, i64p, i64p, i64p, S, ctypes.POINTER(Config),
                                  ctypes.POINTER(ctypes.c_double), S, ip], S),
         "ttx_tune_table_save": ([ctypes.c_char_p], S),
@@ -334,6 +335,16 @@ def ttx_tune(dtype, perm, size, outer_a=None, outer_b=None, beta_is_zero=False,
     _check(lib().ttx_tune(dtype, len(perm), _ints(perm), _i64s(size), _i64s(outer_a),
                           _i64s(outer_b), int(beta_is_zero), int(max_candidates), int(reps),
                           ctypes.byref(best), ctypes.byref(timed)))
+    return best, timed.value
+
+
+def ttx_tune_specialised(dtype, perm, size, outer_a=None, outer_b=None, beta_is_zero=False,
+                         max_candidates=0, reps=3):
+    best = Config()
+    timed = ctypes.c_int(0)
+    _check(lib().ttx_tune_specialised(dtype, len(perm), _ints(perm), _i64s(size), _i64s(outer_a),
+                                      _i64s(outer_b), int(beta_is_zero), int(max_candidates), int(reps),
+                                      ctypes.byref(best), ctypes.byref(timed)))
     return best, timed.value
 
 

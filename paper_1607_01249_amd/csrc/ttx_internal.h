@@ -226,6 +226,10 @@ hipError_t launch_axpby(int dtype, int64_t n, double alpha, const void* x, doubl
 // Tune table (tune.cpp).
 ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
                         int* n_timed);
+// The same with every candidate compiled as a size-specialised kernel and
+// timed in that form (default 24 candidates).
+ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
+                                    int* n_timed);
 bool table_lookup(const Problem& p, bool beta0, ttx_config* out);
 void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec);
 uint64_t table_generation();

@@ -250,6 +250,52 @@ ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int re
     return TTX_OK;
 }
 
+// Stages 4 and 5 of Sec. 2.1 as the paper's compiler runs them: every kept
+// candidate is compiled (here at run time, as a size-specialised kernel) and
+// timed, and the fastest goes into the table.  Problems without tiles take
+// the generic search.
+ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
+                                    int* n_timed) {
+    if (n_timed) *n_timed = 0;
+    if (p.family != TTX_FAMILY_MOVED && p.family != TTX_FAMILY_PRESERVED)
+        return tune_problem(p, beta0, max_candidates, reps, best, n_timed);
+    const int keep = max_candidates == 0 ? 24 : max_candidates;
+    std::vector<ttx_config> cands(keep < 0 ? 1 << 17 : keep);
+    int nc = rank_candidates(p, keep, cands.data(), nullptr, int(cands.size()));
+    if (nc <= 0) return fail(TTX_EUNSUPPORTED, "no candidate for this problem");
+    cands.resize(nc);
+    // compile every candidate for aligned tensors (the tuner's scratch
+    // tensors are hipMalloc'd, so each launch finds its specialised kernel)
+    const Scalar alpha(1.25), beta(beta0 ? 0.0 : 0.75);
+    std::vector<const JitKernel*> ks(nc, nullptr);
+    for (int i = 0; i < nc; ++i) {
+        TiledLaunch L;
+        void* a = reinterpret_cast<void*>(uintptr_t(1) << 20);
+        void* b = reinterpret_cast<void*>(uintptr_t(3) << 20);
+        if (!prepare_tiled(p, cands[i], beta0, a, beta0 ? nullptr : b, b, alpha, beta, &L))
+            return fail(TTX_EUNSUPPORTED, "candidate without a tile kernel");
+        ttx_status st = jit_kernel(L, &ks[i]);
+        if (st != TTX_OK) return st;
+    }
+    int best_i = -1;
+    double best_us = 0;
+    ttx_status st = time_candidates(
+        p, beta0, nc, reps,
+        [&](int i, const void* A, void* B, hipStream_t s) {
+            const void* Bsrc = beta0 ? nullptr : B;
+            TiledLaunch L;
+            if (!prepare_tiled(p, cands[i], beta0, A, Bsrc, B, alpha, beta, &L)) return hipErrorInvalidValue;
+            if (jit_matches(*ks[i], L)) return jit_launch(*ks[i], L, s);
+            return launch_tiles(p, cands[i], beta0, A, Bsrc, B, alpha, beta, s);
+        },
+        &best_i, &best_us);
+    if (st != TTX_OK) return st;
+    *best = cands[best_i];
+    if (n_timed) *n_timed = nc;
+    table_store(p, beta0, *best, best_us);
+    return TTX_OK;
+}
+
 // Reads a table file; a key listed more than once keeps its lowest time
 // (a database file collects appended results).
 static ttx_status read_table(const char* path, std::map<std::string, TableEntry>* out) {
@@ -334,6 +380,15 @@ ttx_status ttx_tune(ttx_dtype dtype, int n, const int* perm, const int64_t* size
     ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
     if (st != TTX_OK) return st;
     return tune_problem(p, beta_is_zero != 0, max_candidates, reps, best, n_timed);
+}
+ttx_status ttx_tune_specialised(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                                const int64_t* outer_a, const int64_t* outer_b, int beta_is_zero,
+                                int max_candidates, int reps, ttx_config* best, int* n_timed) {
+    if (!best) return fail(TTX_EINVAL, "best must not be NULL");
+    Problem p;
+    ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    if (st != TTX_OK) return st;
+    return tune_problem_specialised(p, beta_is_zero != 0, max_candidates, reps, best, n_timed);
 }
 ttx_status ttx_tune_table_save(const char* path) {
     if (!path) return fail(TTX_EINVAL, "NULL path");

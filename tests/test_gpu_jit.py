@@ -156,6 +156,25 @@ def test_kernel_name_names_the_specialised_kernel():
         ttx.ttx_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("dtype,perm,size,bz", [(F64, (2, 0, 1), (40, 30, 20), False),
+                                              (F32, (0, 5, 1, 4, 2, 3), (24, 7, 4, 3, 5, 6), True),
+                                              (F32, (0, 1), (64, 9), False)])
+def test_tune_specialised_stores_a_config(dtype, perm, size, bz):
+    """Candidates compiled and timed as specialised kernels: the winner lands
+    in the tune table, and the plan that takes it computes the oracle's bits."""
+    code = dtype_code(dtype)
+    best, timed = ttx.ttx_tune_specialised(code, perm, size, beta_is_zero=bz, max_candidates=6, reps=2)
+    assert timed >= 1
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        info = ttx.ttx_plan_describe(plan)
+        assert info["config_from_table"][int(bz)] == 1
+        assert info["config"][int(bz)] == best.as_dict()
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    _check(perm, size, dtype, dtype, bz, seed=13)
+
+
 def test_disk_cache_written_and_reused(tmp_path):
     """With TTX_JIT_CACHE set, the code object lands in the directory; a
     second process finds it there and leaves it untouched."""
