@@ -232,7 +232,8 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     const std::string src = jit_source(L);
     const std::string path = cache_file(arch, src);
     std::string code;
-    if (path.empty() || !read_file(path, &code)) {
+    const bool from_disk = !path.empty() && read_file(path, &code);
+    if (!from_disk) {
         ttx_status st = compile(src, arch, &code);
         if (st != TTX_OK) return st;
         if (!path.empty()) {
@@ -245,6 +246,12 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     k->key = key;
     k->name = entry_name(L);
     e = hipModuleLoadData(&k->module, code.data());
+    if (e != hipSuccess && from_disk) {   // a damaged cache file: compile again
+        ttx_status st = compile(src, arch, &code);
+        if (st != TTX_OK) return st;
+        write_file_atomic(path, code);
+        e = hipModuleLoadData(&k->module, code.data());
+    }
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
     e = hipModuleGetFunction(&k->fn, k->module, k->name.c_str());
     if (e != hipSuccess) {

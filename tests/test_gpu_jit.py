@@ -197,6 +197,11 @@ def test_disk_cache_written_and_reused(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert sorted(os.listdir(d)) == files and os.stat(d / files[0]).st_mtime_ns == mtime
+    # a damaged file (not an ELF image: the host loader rejects it) is compiled again and replaced
+    (d / files[0]).write_bytes(b"damaged code object")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert sorted(os.listdir(d)) == files and (d / files[0]).read_bytes()[:4] == b"\x7fELF"
 
 
 # -- full sizes (about 200 MiB per tensor): the cases the throughput figures time ------------
