@@ -259,6 +259,19 @@ ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A
  * loading failed; ttx_last_error starts with the compiler log), TTX_ENOMEM
  * (timing scratch). */
 ttx_status ttx_plan_specialise(ttx_plan *plan, int beta_is_zero, int reps, int *kept);
+/* Automatic specialisation for the per-call entry points (ttx_transpose,
+ * ttx_transpose_c): a shape's size-specialised kernel is compiled at its
+ * `calls`-th call in a beta class (the hottest shapes get one; a failed
+ * compilation leaves the shape on its generic kernel), 0 turns it off (the
+ * default, or the value of the environment variable TTX_AUTO_SPECIALISE at
+ * the first call).  The compiling call blocks for about half a second; a
+ * call running concurrently on the same shape may still take the generic
+ * kernel.  TTX_EINVAL for calls < 0. */
+ttx_status ttx_set_auto_specialise(int calls);
+/* The per-call entry points' plan cache: *plans (may be NULL) receives the
+ * number of cached shapes, *specialised (may be NULL) how many of them have a
+ * size-specialised kernel.  Host only. */
+ttx_status ttx_transpose_cache_info(int *plans, int *specialised);
 /* The translation unit ttx_plan_specialise compiles for the plan (host
  * only), NUL-terminated into buf (len bytes).  TTX_EINVAL when buf is too
  * small (about 8 KB suffices) or the problem has nothing to specialise. */

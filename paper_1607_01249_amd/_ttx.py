@@ -185,6 +185,8 @@ def _declare(L):
         "ttx_plan_destroy": ([vp], S),
         "ttx_plan_kernel_name": ([vp, ctypes.c_double, vp, vp, ctypes.c_char_p, S], S),
         "ttx_plan_specialise": ([vp, S, S, ip], S),
+        "ttx_set_auto_specialise": ([S], S),
+        "ttx_transpose_cache_info": ([ip, ip], S),
         "ttx_plan_specialised_source": ([vp, S, ctypes.c_char_p, S], S),
         "ttx_tune": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_specialised": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
@@ -316,6 +318,16 @@ def ttx_plan_specialise(plan, beta_is_zero, reps=0):
     kept = ctypes.c_int(0)
     _check(lib().ttx_plan_specialise(plan, int(bool(beta_is_zero)), int(reps), ctypes.byref(kept)))
     return bool(kept.value)
+
+
+def ttx_set_auto_specialise(calls):
+    return _check(lib().ttx_set_auto_specialise(int(calls)))
+
+
+def ttx_transpose_cache_info():
+    plans, spec = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().ttx_transpose_cache_info(ctypes.byref(plans), ctypes.byref(spec)))
+    return plans.value, spec.value
 
 
 def ttx_plan_specialised_source(plan, beta_is_zero):

@@ -1,4 +1,6 @@
 // C ABI: errors, plans, the per-call entry point and the ceiling kernels.
+#include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -14,6 +16,8 @@ struct ttx_plan {
     bool user_set[2];
     uint64_t table_gen;
     const ttx::JitKernel* jit[2];   // size-specialised kernels ([beta_is_zero]; owned by the JIT cache)
+    uint32_t calls[2];              // per-call entry points: calls so far (automatic specialisation)
+    bool jit_tried[2];              // automatic specialisation attempted
 };
 
 namespace ttx {
@@ -126,6 +130,37 @@ static std::string cache_key(int dtype, int n, const int* perm, const int64_t* s
     return k;
 }
 
+// Automatic specialisation of the per-call entry points' plans: a shape's
+// size-specialised kernel is compiled at its n-th call in a beta class
+// (0: never).  The default comes from TTX_AUTO_SPECIALISE.
+static std::mutex g_auto_mu;
+static std::atomic<int> g_auto_calls{-1};
+static int g_auto_specialised = 0;
+
+static int auto_calls() {
+    int n = g_auto_calls.load(std::memory_order_relaxed);
+    if (n >= 0) return n;
+    const char* env = std::getenv("TTX_AUTO_SPECIALISE");
+    const int v = env ? std::atoi(env) : 0;
+    int expected = -1;
+    g_auto_calls.compare_exchange_strong(expected, v < 0 ? 0 : v);
+    return g_auto_calls.load(std::memory_order_relaxed);
+}
+
+static void maybe_specialise(ttx_plan* plan, const Scalar& beta, int hot) {
+    const int z = beta_is_zero(plan->prob.dtype, beta) ? 1 : 0;
+    std::lock_guard<std::mutex> lock(g_auto_mu);
+    if (plan->jit_tried[z] || ++plan->calls[z] < uint32_t(hot)) return;
+    plan->jit_tried[z] = true;
+    if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) return;
+    const std::string saved = g_last_error;
+    int kept = 0;
+    if (ttx_plan_specialise(plan, z, 0, &kept) != TTX_OK)
+        g_last_error = saved;   // the shape keeps its generic kernel
+    else if (kept)
+        ++g_auto_specialised;
+}
+
 ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
                             const int64_t* outer_a, const int64_t* outer_b, const Scalar& alpha,
                             const void* A, const Scalar& beta, const void* Bin, void* Bout,
@@ -150,7 +185,17 @@ ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* si
         if (g_cache.size() >= kCacheCap) g_cache.clear();
         g_cache[key] = plan;
     }
+    const int hot = auto_calls();
+    if (hot > 0) maybe_specialise(plan.get(), beta, hot);
     return execute(plan.get(), alpha, A, beta, Bin, Bout, stream);
+}
+
+static void cache_info(int* plans, int* specialised) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    int s = 0;
+    for (const auto& kv : g_cache) s += (kv.second->jit[0] || kv.second->jit[1]) ? 1 : 0;
+    if (plans) *plans = int(g_cache.size());
+    if (specialised) *specialised = s;
 }
 
 }  // namespace ttx
@@ -340,6 +385,17 @@ ttx_status ttx_transpose_c(ttx_dtype dtype, int n, const int* perm, const int64_
     if (!alpha || !beta) return fail(TTX_EINVAL, "alpha and beta must not be NULL");
     return transpose_cached(dtype, n, perm, size, outer_a, outer_b, Scalar(alpha[0], alpha[1]), A,
                             Scalar(beta[0], beta[1]), B, B, stream);
+}
+
+ttx_status ttx_set_auto_specialise(int calls) {
+    if (calls < 0) return fail(TTX_EINVAL, "calls must be >= 0");
+    g_auto_calls.store(calls, std::memory_order_relaxed);
+    return TTX_OK;
+}
+
+ttx_status ttx_transpose_cache_info(int* plans, int* specialised) {
+    cache_info(plans, specialised);
+    return TTX_OK;
 }
 
 ttx_status ttx_copy_kernel(const void* src, void* dst, int64_t bytes, hipStream_t stream) {

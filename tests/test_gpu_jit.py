@@ -175,6 +175,25 @@ def test_tune_specialised_stores_a_config(dtype, perm, size, bz):
     _check(perm, size, dtype, dtype, bz, seed=13)
 
 
+def test_auto_specialise_hot_shapes():
+    """With automatic specialisation at the 3rd call, a shape called through
+    ttx_transpose gets its specialised kernel then, and every call computes
+    the oracle's bits."""
+    perm, size = (3, 1, 0, 2), (23, 29, 6, 7)   # a shape no other test calls
+    A, B = _inputs(perm, size, F32, F32, 21)
+    ref = B.copy()
+    oracle.transpose(perm, size, 1.3, A, 0.7, ref)
+    ttx.ttx_set_auto_specialise(3)
+    try:
+        before = ttx.ttx_transpose_cache_info()[1]
+        for k in range(4):
+            got = gpu_transpose(perm, size, 1.3, A, 0.7, B)
+            assert_parity(got, ref, False, k)
+            assert ttx.ttx_transpose_cache_info()[1] == before + (1 if k >= 2 else 0), k
+    finally:
+        ttx.ttx_set_auto_specialise(0)
+
+
 def test_disk_cache_written_and_reused(tmp_path):
     """With TTX_JIT_CACHE set, the code object lands in the directory; a
     second process finds it there and leaves it untouched."""

@@ -82,6 +82,8 @@ def test_specialised_source_null_and_small_buffer():
         assert ttx.lib().ttx_plan_specialised_source(plan, 0, buf, 64) == ttx.EINVAL
         assert ttx.lib().ttx_plan_specialised_source(None, 0, buf, 64) == ttx.EINVAL
         assert ttx.lib().ttx_plan_specialise(None, 0, 0, None) == ttx.EINVAL
+        assert ttx.lib().ttx_set_auto_specialise(-1) == ttx.EINVAL
+        assert ttx.lib().ttx_transpose_cache_info(None, None) == ttx.OK
         perm = (ctypes.c_int * 3)(2, 0, 1)
         size = (ctypes.c_int64 * 3)(40, 30, 20)
         assert ttx.lib().ttx_tune_specialised(ttx.F64, 3, perm, size, None, None, 0, 4, 1, None, None) == ttx.EINVAL
