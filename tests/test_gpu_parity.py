@@ -419,3 +419,23 @@ def test_tune_db_appends_each_result(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, TTX_TUNE_DB=db),
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.split() == ["1"], r.stderr
+
+
+# -- the bandwidth-ceiling kernels (one pass over the array) ---------------------------------
+@pytest.mark.parametrize("n", [1, 7, 4096, 1000003])
+def test_ceiling_kernels(n):
+    import torch
+    src = torch.arange(n * 4, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    ttx.ttx_copy_kernel(src.data_ptr(), dst.data_ptr(), n * 16, ttx.current_stream())
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    for dtype, code in ((F32, ttx.F32), (F64, ttx.F64)):
+        x = workloads.uniform(n, dtype, 31)
+        y = workloads.uniform(n, dtype, 32)
+        # unfused: both products and the sum rounded separately
+        want = (dtype.type(1.25) * x) + (dtype.type(-0.5) * y)
+        dx, dy = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+        ttx.ttx_axpby_kernel(code, n, 1.25, dx.data_ptr(), -0.5, dy.data_ptr(), ttx.current_stream())
+        torch.cuda.synchronize()
+        assert np.array_equal(dy.cpu().numpy().view(np.uint8), want.view(np.uint8)), (n, dtype)
