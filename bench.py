@@ -71,6 +71,8 @@ def parse_args():
     ap.add_argument("--retune", action="store_true", help="ignore the shipped tune table")
     ap.add_argument("--save-table", default=None, help="write the tune table here")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dominant-out", default=None,
+                    help="also write the dominant kernel's name and launch figures to this JSON file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--literal", action="store_true",
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
@@ -682,7 +684,7 @@ def main():
         summarize_trace(args.summarize_trace)
         return 0
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
     if args.profile_run:
@@ -823,9 +825,8 @@ def main():
                     kernel=dom_name, launches=dom["launches"],
                     avg_launch_us=round(dom["time"] / dom["launches"] * 1e6, 2),
                     algorithmic_bytes_per_launch=int(bytes_per_launch))
-    dom_path = os.path.join(ROOT, "gpurun_out", "dominant_kernel.json")
-    if os.path.isdir(os.path.dirname(dom_path)) and not args.profile_run:
-        with open(dom_path, "w") as f:
+    if args.dominant_out and not args.profile_run:
+        with open(args.dominant_out, "w") as f:
             json.dump(dict(kernel=dom_name, bytes_per_launch=bytes_per_launch,
                            avg_launch_us=roofline["avg_launch_us"]), f)
 
