@@ -117,6 +117,9 @@ typedef enum ttx_family {
                                   tile_c and the capacity count rows of units (512 units of 16
                                   bytes, 1024 of 8).  Pointers not aligned to the unit run an
                                   element-wise configuration instead. */
+#define TTX_CFG_GROUPED 16     /* tile ids walk groups of 8 steps of the fastest grid index
+                                  across the whole second one (in each plane of the two), so
+                                  the tiles in flight together are neighbours along both */
 
 /* One implementation candidate (Sec. 2.2: blocking and loop order).
  *   tile_a  : tile extent along A's stride-1 index (merged index 0);

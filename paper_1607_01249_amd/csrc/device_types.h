@@ -98,6 +98,24 @@ struct TileGrid {
     FastDiv div[kMaxDims];
     int64_t stepA[kMaxDims];
     int64_t stepB[kMaxDims];
+    // Grouped order (gk > 0): within each plane of the first two positions,
+    // ids walk groups of gk steps of position 0 across all of position 1, so
+    // the tiles in flight together are neighbours along both.  dvg divides by
+    // gk * count[1], dvp by count[0] * count[1].
+    uint32_t gk;
+    FastDiv dvg, dvp;
+
+    // The plane-major id of the tile that grouped id t names (a bijection on
+    // [0, ntiles)).
+    __host__ __device__ __forceinline__ uint32_t grouped(uint32_t t) const {
+        const uint32_t c0 = count[0], c1 = count[1];
+        const uint32_t q = dvp.div(t), r = t - q * (c0 * c1);
+        const uint32_t g = dvg.div(r), first0 = g * gk;
+        const uint32_t gsz = c0 - first0 < gk ? c0 - first0 : gk;
+        const uint32_t rr = r - g * gk * c1;
+        const uint32_t p1 = rr / gsz, p0 = first0 + (rr - p1 * gsz);
+        return q * (c0 * c1) + p0 + p1 * c0;
+    }
 };
 
 // Kernel-side flags (separate from TTX_CFG_*, which describe a config).

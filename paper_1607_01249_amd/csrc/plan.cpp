@@ -389,7 +389,8 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     };
     if (c.family != p.family) return bad("config family does not match the problem");
     if (c.threads != kThreads) return bad("threads must be 256");
-    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE)) return bad("unknown flag");
+    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE | TTX_CFG_GROUPED))
+        return bad("unknown flag");
     if (config_is_wide(c)) {
         if (!config_is_dense(c)) return bad("whole-unit rows are for dense tiles only");
         Problem w;
@@ -500,6 +501,14 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
     }
     g->nd = q;
     g->ntiles = uint32_t(tiles);
+    g->gk = 0;
+    if ((c.flags & TTX_CFG_GROUPED) && q >= 2 && g->count[0] > 1 && g->count[1] > 1 &&
+        uint64_t(kGroupedSteps) * g->count[1] < (uint64_t(1) << 31) &&
+        uint64_t(g->count[0]) * g->count[1] < (uint64_t(1) << 31)) {
+        g->gk = kGroupedSteps;
+        g->dvg.init(kGroupedSteps * g->count[1]);
+        g->dvp.init(g->count[0] * g->count[1]);
+    }
     g->ext_a = L.SA;
     g->ext_b = L.SB;
     h->sAa = p.dim[L.a].sa;

@@ -288,6 +288,7 @@ struct TileCoord {
 // tile; TC is the tile extent along the third index of dense tiles.
 __device__ __forceinline__ TileCoord decode_tile(const TileGrid& g, uint32_t t, int TA, int TB, int TC = 1) {
     TileCoord c{0, 0, 0, 0, TA, TB, TC};
+    if (g.gk) t = g.grouped(t);
     uint32_t rem = t;
     for (int q = 0; q < g.nd; ++q) {
         const uint32_t next = g.div[q].div(rem);

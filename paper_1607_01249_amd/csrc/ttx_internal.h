@@ -160,6 +160,8 @@ inline int dense_cap(int dtype) {
     return cap[dtype];
 }
 inline bool config_is_wide(const ttx_config& c) { return (c.flags & TTX_CFG_WIDE) != 0; }
+// Steps of the first grid position per group of the grouped tile order.
+constexpr uint32_t kGroupedSteps = 8;
 // The problem over whole units of the kept stride-1 rows (TTX_CFG_WIDE):
 // FP32/FP64 one-type preserved problems whose row length and other strides
 // are multiples of the unit and whose rows hold at least two units.  Fills

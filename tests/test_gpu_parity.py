@@ -439,3 +439,34 @@ def test_ceiling_kernels(n):
         ttx.ttx_axpby_kernel(code, n, 1.25, dx.data_ptr(), -0.5, dy.data_ptr(), ttx.current_stream())
         torch.cuda.synchronize()
         assert np.array_equal(dy.cpu().numpy().view(np.uint8), want.view(np.uint8)), (n, dtype)
+
+
+# -- grouped tile order (TTX_CFG_GROUPED): a permutation of the tile ids, the same bits ------
+@pytest.mark.parametrize("code,perm,size", [
+    (ttx.F32, (2, 0, 3, 1), (37, 70, 19, 23)), (ttx.F64, (1, 0), (300, 517)), (ttx.F32, (3, 2, 1, 0), (70, 9, 33, 21)),
+    (ttx.F64, (0, 2, 1, 3), (40, 9, 11, 13)), (ttx.F64, (0, 5, 1, 4, 2, 3), (20, 7, 4, 3, 5, 6)),
+    (ttx.F32, (0, 5, 1, 4, 2, 3), (24, 7, 4, 3, 5, 6)), (ttx.C64, (2, 1, 0), (33, 40, 27))])
+def test_grouped_order_bit_identical(code, perm, size):
+    from gpu_util import TYPES_OF_CODE
+    da, db = TYPES_OF_CODE[code]
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    seen, pick = set(), []
+    for c in cands:
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b, c.tile_c, c.flags & (ttx.CFG_DENSE | ttx.CFG_WIDE))
+        if key not in seen:
+            seen.add(key)
+            pick.append(c)
+    n = _elems(size)
+    A = workloads.uniform(n, da, 18)
+    B = workloads.uniform(n, db, 19)
+    cx = db in (np.complex64, np.complex128)
+    for beta in ((0.5 - 0.25j, 0j) if cx else (0.7, 0.0)):
+        alpha = (1.25 + 0.5j) if cx else 1.3
+        ref = B.copy()
+        oracle.transpose(perm, size, alpha, A, beta, ref)
+        for c in pick:
+            c.flags |= ttx.CFG_GROUPED
+            got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c)
+            assert_parity(got, ref, exact=True, what=str(c.as_dict()))
+            got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c, specialise=True)
+            assert_parity(got, ref, exact=True, what="specialised " + str(c.as_dict()))
