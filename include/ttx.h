@@ -239,7 +239,10 @@ ttx_status ttx_plan_kernel_name(const ttx_plan *plan, double beta, const void *A
  * ttx_plan_specialise compiles, at run time with hipRTC, the plan's kernel
  * for one beta class (beta_is_zero = 1: beta == 0) with every extent,
  * stride, tile count and index divisor of the plan's problem and config as
- * a constant, and loads it on the current device.
+ * a constant, and loads it on the current device.  When the tune table
+ * holds a configuration tuned for specialised execution of the problem
+ * (ttx_tune_specialised) and no config was set on the plan, the plan takes
+ * it for that beta class first.
  *   reps == 0: the kernel is attached to the plan;
  *   reps > 0:  the generic and the specialised kernel are timed on scratch
  *              tensors the call allocates (minimum of `reps` runs each,
@@ -297,9 +300,9 @@ ttx_status ttx_tune(ttx_dtype dtype, int n, const int *perm, const int64_t *size
  * as the paper's compiler compiles and times each candidate (Sec. 2.1
  * stages 4 and 5): max_candidates defaults to 24 when 0 is passed (each
  * candidate costs a compilation of about half a second; -1 keeps all).
- * The fastest config goes into the tune table as with ttx_tune; plans made
- * afterwards take it, and ttx_plan_specialise attaches its specialised
- * kernel.  Empty and single-index problems take the generic search.  Needs
+ * The fastest config goes into the tune table's entries for specialised
+ * execution (the generic entry is left alone): ttx_plan_specialise takes
+ * it.  Empty and single-index problems take the generic search.  Needs
  * a GPU; blocks the caller.  Errors as ttx_tune, and TTX_EHIP when a
  * compilation fails. */
 ttx_status ttx_tune_specialised(ttx_dtype dtype, int n, const int *perm, const int64_t *size,

@@ -306,6 +306,13 @@ ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero, int reps, int* 
     const int z = beta_is_zero ? 1 : 0;
     plan->jit[z] = nullptr;
     if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) return TTX_OK;
+    // a configuration tuned for specialised execution, when the table has one
+    // and the caller has not set the config
+    ttx_config cs;
+    if (!plan->user_set[z] && table_lookup(plan->prob, z == 1, &cs, true)) {
+        plan->cfg[z] = cs;
+        plan->from_table[z] = 1;
+    }
     TiledLaunch L;
     ttx_status st = specialised_launch(plan, z, &L);
     if (st != TTX_OK) return st;

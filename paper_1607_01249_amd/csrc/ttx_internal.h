@@ -232,8 +232,9 @@ ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int re
 // timed in that form (default 24 candidates).
 ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
                                     int* n_timed);
-bool table_lookup(const Problem& p, bool beta0, ttx_config* out);
-void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec);
+// specialised: the entries for size-specialised execution (ttx_tune_specialised).
+bool table_lookup(const Problem& p, bool beta0, ttx_config* out, bool specialised = false);
+void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec, bool specialised = false);
 uint64_t table_generation();
 // Times `count` candidates on tuner-owned scratch buffers sized for p (minimum
 // of `reps` runs, the 1 GiB flush area cleared before each) and returns the

@@ -66,8 +66,11 @@ uint64_t table_generation() {
 // Key: dtype, beta == 0, and the merged problem (extents, permutation and
 // both stride vectors), so that every call that plans to the same merged
 // problem shares a solution (Sec. 2.1: lookup happens after merging).
-static std::string table_key(const Problem& p, bool beta0) {
+// Entries for size-specialised execution carry the prefix "j:" (their best
+// configuration can differ from the generic kernels').
+static std::string table_key(const Problem& p, bool beta0, bool specialised = false) {
     std::ostringstream os;
+    if (specialised) os << "j:";
     os << "d" << p.code << ":b" << (beta0 ? 1 : 0) << ":n" << p.n << ":s";
     for (int i = 0; i < p.n; ++i) os << (i ? "," : "") << p.dim[i].size;
     os << ":p";
@@ -79,10 +82,10 @@ static std::string table_key(const Problem& p, bool beta0) {
     return os.str();
 }
 
-bool table_lookup(const Problem& p, bool beta0, ttx_config* out) {
+bool table_lookup(const Problem& p, bool beta0, ttx_config* out, bool specialised) {
     attach_env_db();
     std::lock_guard<std::mutex> lock(g_table_mu);
-    auto it = g_table.find(table_key(p, beta0));
+    auto it = g_table.find(table_key(p, beta0, specialised));
     if (it == g_table.end() || !config_valid(p, it->second.cfg, nullptr)) return false;
     *out = it->second.cfg;
     return true;
@@ -103,9 +106,9 @@ static void db_append(const std::string& path, const std::string& line) {
     std::fclose(f);
 }
 
-void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec) {
+void table_store(const Problem& p, bool beta0, const ttx_config& c, double usec, bool specialised) {
     attach_env_db();
-    const std::string key = table_key(p, beta0);
+    const std::string key = table_key(p, beta0, specialised);
     std::string db;
     {
         std::lock_guard<std::mutex> lock(g_table_mu);
@@ -292,7 +295,7 @@ ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candid
     if (st != TTX_OK) return st;
     *best = cands[best_i];
     if (n_timed) *n_timed = nc;
-    table_store(p, beta0, *best, best_us);
+    table_store(p, beta0, *best, best_us, true);
     return TTX_OK;
 }
 
