@@ -600,3 +600,46 @@ def test_tune_table_from_the_environment_is_read_only(tmp_path):
     assert r.returncode == 0, r.stderr
     assert r.stdout.split() == ["1", "1"]
     assert open(table).read() == before
+
+
+def test_shipped_table_covers_the_large_cases():
+    """Every line of the shipped tune table parses and names a config the
+    planner accepts: each large case's plan takes its generic entry, and the
+    entries for specialised execution (prefix j:) name valid configs too."""
+    import os
+    import workloads
+    table = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_1607_01249_amd", "tune", "gfx950.txt")
+    ttx.ttx_tune_table_clear()
+    try:
+        ttx.ttx_tune_table_load(table)
+        lines = [l for l in open(table) if l.strip() and not l.startswith("#")]
+        assert ttx.ttx_tune_table_size() == len(lines)
+        spec_keys = {l.split("|")[0].strip()[2:] for l in lines if l.startswith("j:")}
+        for c in workloads.large_cases():
+            code = ttx.F32 if c["dtype"] == workloads.F32 else ttx.F64
+            plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
+            try:
+                info = ttx.ttx_plan_describe(plan)
+                z = 1 if c["beta"] == 0 else 0
+                assert info["config_from_table"][z] == 1, c["name"]
+                key = "d%d:b%d:n%d:s%s:p%s:a%s:o%s" % (
+                    info["dtype"], z, info["n"], ",".join(map(str, info["size"])), ",".join(map(str, info["perm"])),
+                    ",".join(map(str, info["stride_a"])), ",".join(map(str, info["stride_b"])))
+                if key in spec_keys:   # the specialised entry's config must be valid for the plan
+                    line = [l for l in lines if l.startswith("j:" + key + " |")][0]
+                    f = line.split("|")[1].split()
+                    cfg = ttx.Config()
+                    cfg.family, cfg.tile_a, cfg.tile_b, cfg.threads, cfg.flags = map(int, f[:5])
+                    cfg.group_a, cfg.group_b, cfg.n_order = map(int, f[5:8])
+                    for i in range(cfg.n_order):
+                        cfg.order[i] = int(f[8 + i])
+                    extra = f[8 + cfg.n_order:]
+                    cfg.tile_c = int(extra[0][1:]) if extra else 0
+                    ttx.ttx_plan_set_config(plan, z, cfg)
+                    spec_keys.discard(key)
+            finally:
+                ttx.ttx_plan_destroy(plan)
+        assert not spec_keys, spec_keys
+    finally:
+        ttx.ttx_tune_table_clear()
