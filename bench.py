@@ -3,15 +3,19 @@
 
 Workload (one "step"): the 36 paper-shaped transpositions of about 200 MiB
 per tensor -- 4D, 5D and 6D, FP32 and FP64, beta = 0.7 and beta = 0 with
-alpha = 1.3 -- each through the per-call entry point ``ttx_transpose`` on
+alpha = 1.3 -- each through its plan with its size-specialised kernel, on
 its own device buffers (14 GiB in all, so no tensor is still cached in the
 256 MiB Infinity Cache when its turn comes).  The reported value is the
 whole step's algorithmic traffic (2S bytes for beta = 0, 3S otherwise, S the
 bytes of the transposed tensor; Sec. 3, Eqn. 2) divided by its wall time.
 
-Also reported: every case's bandwidth as a fraction of a measured
-hipMemcpy device-to-device ceiling, the dominant kernel against the HBM
-roofline (8 TB/s), and the CPU oracle timed on the host on a bounded sample.
+Also measured: every case against a hipMemcpy device-to-device ceiling, the
+dominant kernel against the HBM roofline (8 TB/s), the CPU oracle on the
+host (which also checks every element of every case's GPU output), the
+leading-dimension, awkward and literal shapes, the 512-problem batch, the
+served trace, and the complex, mixed-precision and packing cases.  The
+printed JSON line holds the summary; the per-case detail goes to
+``--detail-out``.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -73,7 +77,6 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dominant-out", default=None,
                     help="also write the dominant kernel's name and launch figures to this JSON file")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--literal", action="store_true",
                     help="add the literal (160,160,160,160) FP32/FP64 shapes to the step")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched comparison")
@@ -82,6 +85,10 @@ def parse_args():
     ap.add_argument("--no-specialised", action="store_true",
                     help="skip the comparison with size-specialised (run-time compiled) kernels")
     ap.add_argument("--no-served", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side shapes (leading dimensions, awkward extents, literal 160^4 and 24^6)")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="the per-case detail (JSON); the printed line holds the summary")
     ap.add_argument("--no-types", action="store_true",
                     help="skip the complex (c, z) and mixed-precision (sd, ds, cz, zc) cases")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -203,40 +210,111 @@ def measure_ceilings(torch, ttx):
     return out
 
 
-def cpu_baseline(cases, budget_s):
+def _ulp_diff(x, y):
+    """Largest distance in units in the last place between two float arrays of
+    one dtype (complex arrays compared part by part); NaNs of either sign
+    count as equal to each other."""
+    if x.dtype.kind == "c":
+        x = x.view(np.float32 if x.dtype == np.complex64 else np.float64)
+        y = y.view(x.dtype)
+    it = np.int32 if x.dtype == np.float32 else np.int64
+    xi, yi = x.view(it).astype(np.int64), y.view(it).astype(np.int64)
+    # map the sign-magnitude bit patterns to one ordered integer line
+    lo = np.iinfo(it).min
+    xo = np.where(xi < 0, lo - xi, xi)
+    yo = np.where(yi < 0, lo - yi, yi)
+    d = np.abs(xo - yo)
+    both_nan = np.isnan(x) & np.isnan(y)
+    d[both_nan] = 0
+    return int(d.max()) if d.size else 0
+
+
+def host_cpu_info():
+    """The host's core counts and processor model (for the CPU baseline)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(logical_cpus=os.cpu_count(), usable_cpus=usable, model=model,
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
+def cpu_baseline(torch, ttx, cases, stream, one_thread_every=3):
     """The oracle (plain C loop nest, OpenMP over the outermost B index) on the
-    host cores, timed on a bounded sample of the step's cases."""
+    host cores, on every case of the step, timed (min of 3 runs per case) on
+    the inputs of one more GPU call of that case copied from the device; the
+    GPU's output of that call is compared with the oracle's first run element
+    by element.  Then a 1-thread run of every ``one_thread_every``-th case."""
     os.environ.setdefault("OMP_PROC_BIND", "close")
     os.environ.setdefault("OMP_PLACES", "cores")
     import oracle
-    import workloads
-    # every third case, so that each rank, dtype and both betas appear
-    pick = cases[::3]
-    total_bytes, total_t, runs, names = 0, 0.0, 0, []
     t_start = time.time()
-    for c in pick:
-        if time.time() - t_start > budget_s and names:
-            break
-        A = workloads.uniform(c["elements"], c["dtype"], c["seed_a"])
-        B = workloads.uniform(c["elements"], c["dtype"], c["seed_b"])
+    per_case, total_bytes, total_t = [], 0, 0.0
+    mismatched, max_ulp, compared = 0, 0, 0
+    for c in cases:
+        A = c["A"].cpu().numpy()
+        B0 = c["B"].cpu().numpy()                      # B before the call
+        ttx.ttx_plan_execute(c["plan"], c["alpha"], c["A"].data_ptr(), c["beta"], c["B"].data_ptr(), stream)
+        torch.cuda.synchronize()
+        G = c["B"].cpu().numpy()                       # the GPU's result
         best = None
-        for _ in range(3):
+        for r in range(3):
+            B = B0.copy()
             t0 = time.perf_counter()
             st = oracle.transpose(c["perm"], c["size"], c["alpha"], A, c["beta"], B)
             dt = time.perf_counter() - t0
-            assert st == 0
+            assert st == 0, st
             best = dt if best is None else min(best, dt)
-            runs += 1
-            if time.time() - t_start > budget_s:
-                break
+            if r == 0:
+                bits = np.int64 if B.itemsize == 8 else np.int32
+                diff = int(np.count_nonzero(B.view(bits) != G.view(bits)))
+                mismatched += diff
+                compared += B.size
+                if diff:
+                    max_ulp = max(max_ulp, _ulp_diff(B, G))
         total_bytes += c["bytes"]
         total_t += best
-        names.append(c["name"])
-        del A, B
-    return dict(value=round(total_bytes / total_t / 1e9, 3), unit="GB/s", cores=oracle.threads(),
-                kind="oracle",
-                sample="%d of the step's cases (%s), min of up to 3 runs each, %d runs in %.1f s" %
-                       (len(names), ", ".join(names), runs, time.time() - t_start))
+        per_case.append(dict(case=c["name"], GBps=round(c["bytes"] / best / 1e9, 2), s=round(best, 4),
+                             differing_elements=diff))
+        del A, B0, G, B
+    threads = oracle.threads()
+    # the same loop nest on one thread, on a sample of the cases
+    one = None
+    if one_thread_every:
+        import workloads
+        prev = oracle.set_threads(1)
+        b1, t1, names = 0, 0.0, []
+        try:
+            for c in cases[::one_thread_every]:
+                A = workloads.uniform(c["elements"], c["dtype"], c["seed_a"])
+                B = workloads.uniform(c["elements"], c["dtype"], c["seed_b"])
+                t0 = time.perf_counter()
+                assert oracle.transpose(c["perm"], c["size"], c["alpha"], A, c["beta"], B) == 0
+                t1 += time.perf_counter() - t0
+                b1 += c["bytes"]
+                names.append(c["name"])
+                del A, B
+        finally:
+            oracle.set_threads(threads if threads >= 1 else prev)
+        one = dict(value=round(b1 / t1 / 1e9, 3), unit="GB/s", cores=1,
+                   sample="%d cases (every %d-th of the step), 1 run each" % (len(names), one_thread_every))
+    verification = dict(cases=len(cases), elements_compared=compared, differing_elements=mismatched,
+                        max_ulp=max_ulp, verified=bool(max_ulp <= 1),
+                        how="every element of every case's GPU output against the oracle on the same inputs")
+    return dict(value=round(total_bytes / total_t / 1e9, 3), unit="GB/s", cores=threads, kind="oracle",
+                sample="all %d cases of the step, min of 3 runs each, inputs of one GPU call copied from the "
+                       "device" % len(cases),
+                one_thread=one, host=host_cpu_info(), seconds=round(time.time() - t_start, 1),
+                per_case=per_case), verification
 
 
 def _rocpd(path):
@@ -550,6 +628,84 @@ def bench_packing(torch, ttx, d2d, stream, tune_candidates, reps=10):
     return out
 
 
+def side_cases():
+    """Shapes timed beside the step: the multiple-leading-dimension and awkward
+    shapes (FP64 sub-tensor (384,96,48,32) in outer sizes, (7,1023,33,65) with
+    the stride-1 index moved last; both scalar pairs), the literal
+    (160,160,160,160) 4D shapes and the literal 24^6 6D shapes."""
+    import workloads
+    out = []
+    for c in workloads.LD_CASES:
+        for alpha, beta in workloads.LD_SCALARS:
+            out.append(dict(name="%s_a%s_b%s" % (c["name"], alpha, beta), dtype=c["dtype"], size=c["size"],
+                            perm=c["perm"], outer_a=c["outer_a"], outer_b=c["outer_b"], alpha=alpha, beta=beta))
+    for dtype in (workloads.F32, workloads.F64):
+        dn = "f32" if dtype == workloads.F32 else "f64"
+        for perm in workloads.LARGE_PERMS["4d"]:
+            out.append(dict(name="literal160_%s_p%s" % (dn, "".join(map(str, perm))), dtype=dtype,
+                            size=workloads.LITERAL_4D, perm=perm, outer_a=None, outer_b=None, alpha=1.3, beta=0.7))
+        for perm in workloads.LARGE_PERMS["6d"]:
+            out.append(dict(name="literal24x6_%s_p%s" % (dn, "".join(map(str, perm))), dtype=dtype,
+                            size=workloads.LITERAL_6D, perm=perm, outer_a=None, outer_b=None, alpha=1.3, beta=0.7))
+    return out
+
+
+def bench_side(torch, ttx, d2d, stream, tune_candidates, reps=5, tune=True):
+    """Each side case through its plan with its size-specialised kernel (tuned
+    first when the table has no entry): median of `reps` launches bracketed by
+    events.  Shapes under 256 MiB rotate over four buffer sets so that no
+    launch finds its own data in the Infinity Cache."""
+    import workloads
+    out, tuned = [], 0
+    for c in side_cases():
+        code = ttx.F32 if c["dtype"] == workloads.F32 else ttx.F64
+        es = c["dtype"].itemsize
+        size_b = [c["size"][p] for p in c["perm"]]
+        na = workloads.elements(c["outer_a"] or c["size"])
+        nb = workloads.elements(c["outer_b"] or size_b)
+        z = c["beta"] == 0
+        plan = ttx.ttx_plan_create(code, c["perm"], c["size"], c["outer_a"], c["outer_b"])
+        if tune and not ttx.ttx_plan_describe(plan)["config_from_table"][int(z)]:
+            log("tuning %s" % c["name"])
+            ttx.ttx_tune(code, c["perm"], c["size"], c["outer_a"], c["outer_b"], beta_is_zero=z,
+                         max_candidates=tune_candidates, reps=3)
+            ttx.ttx_plan_destroy(plan)
+            plan = ttx.ttx_plan_create(code, c["perm"], c["size"], c["outer_a"], c["outer_b"])
+            tuned += 1
+        try:
+            ttx.ttx_plan_specialise(plan, z)
+        except ttx.TTXError as e:
+            log("specialisation failed for %s (%s): generic kernel" % (c["name"], e))
+        tdt = torch.float32 if es == 4 else torch.float64
+        sets = 4 if (na + nb) * es < (256 << 20) else 1
+        bufs = []
+        for k in range(sets):
+            A = torch.empty(na, dtype=tdt, device="cuda")
+            B = torch.empty(nb, dtype=tdt, device="cuda")
+            fill_uniform(torch, A, 300 + k)
+            fill_uniform(torch, B, 400 + k)
+            bufs.append((A, B))
+        kernel = ttx.ttx_plan_kernel_name(plan, c["beta"], bufs[0][0].data_ptr(), bufs[0][1].data_ptr())
+        state = {"i": 0}
+
+        def run():
+            state["i"] = (state["i"] + 1) % len(bufs)
+            A, B = bufs[state["i"]]
+            ttx.ttx_plan_execute(plan, c["alpha"], A.data_ptr(), c["beta"], B.data_ptr(), stream)
+
+        for _ in range(2):
+            run()
+        tmin, tmed = time_events(torch, run, reps)
+        ttx.ttx_plan_destroy(plan)
+        nbytes = workloads.elements(c["size"]) * es * (2 if z else 3)
+        gbps = nbytes / tmed / 1e9
+        out.append(dict(case=c["name"], GBps=round(gbps, 1), pct_of_d2d=round(100 * gbps / d2d, 1),
+                        us=round(tmed * 1e6, 1), bytes=nbytes, kernel=kernel))
+        del bufs
+        torch.cuda.empty_cache()
+    return dict(cases=out, shapes_tuned_now=tuned)
+
+
 def bench_served(torch, ttx, seconds, rate):
     """Open-loop Poisson trace through the server vs the same trace run one
     synchronised per-call request at a time; a sample of requests is re-run
@@ -674,6 +830,73 @@ def bench_saturated(torch, ttx, reqs, meta, scratch, budget_bytes=8e9):
                 throughput_ratio=round(st["throughput_gbps"] / (total / seq_span / 1e9), 2))
 
 
+def compact_line(full, detail_path=None):
+    """The one JSON line bench.py prints: the headline, the roofline and CPU
+    baseline, and one-number summaries of the side measurements; the per-case
+    detail goes to the side file (``detail_path``)."""
+    def pick(d, *keys):
+        return {k: d[k] for k in keys if d is not None and k in d} if d else None
+
+    line = pick(full, "metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "pct_of_d2d")
+    cfg = full["config"]
+    line["config"] = dict(workload=cfg["workload"], cases=cfg["cases"], bytes_per_step=cfg["bytes_per_step"],
+                          entry_point="ttx_plan_execute + ttx_plan_specialise"
+                          if "specialise" in cfg["entry_point"] else "ttx_transpose (generic kernels)",
+                          parallelism=cfg["parallelism"])
+    c = full.get("ceilings") or {}
+    line["ceilings_GBps"] = {k: v["GBps"] for k, v in c.items()}
+    line["per_perm_GBps"] = full.get("per_perm_GBps")
+    v = full.get("verification")
+    line["verified"] = None if v is None else v["verified"]
+    if v is not None:
+        line["verification"] = pick(v, "elements_compared", "differing_elements", "max_ulp")
+    line["roofline"] = pick(full["roofline"], "bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                            "avg_launch_us", "algorithmic_bytes_per_launch", "launches")
+    cpu = full.get("cpu_baseline")
+    if cpu:
+        host = cpu.get("host") or {}
+        line["cpu_baseline"] = dict(pick(cpu, "value", "unit", "cores", "kind", "sample"),
+                                    one_thread_GBps=(cpu.get("one_thread") or {}).get("value"),
+                                    host_cpus=host.get("usable_cpus"), host_model=host.get("model"))
+    else:
+        line["cpu_baseline"] = None
+    g = full.get("per_call_generic")
+    line["per_call_generic_GBps"] = g["value"] if g else None
+    b = full.get("batched")
+    if b:
+        line["batched"] = dict(GBps=b["batched"]["GBps"], per_call_GBps=b["per_call"]["GBps"],
+                               x_per_call=b["speedup"], p50_ms=b["batched"]["makespan_p50_ms"],
+                               p99_ms=b["batched"]["makespan_p99_ms"], target_x=3.0)
+    sv = full.get("served")
+    if sv:
+        sat = sv.get("saturated") or {}
+        line["served"] = dict(GBps=sv["served"]["GBps"], seq_GBps=sv["sequential"]["GBps"],
+                              x_seq=sv["throughput_ratio"], p50_us=sv["served"]["p50_us"],
+                              p99_us=sv["served"]["p99_us"], seq_p50_us=sv["sequential"]["p50_us"],
+                              seq_p99_us=sv["sequential"]["p99_us"],
+                              saturated_x_seq=sat.get("throughput_ratio"),
+                              mix_mismatches=sv["mix_check"]["bitwise_mismatches"], target_x=3.0)
+    sd = full.get("side")
+    if sd:
+        line["side_pct_of_d2d"] = {k: min(o["pct_of_d2d"] for o in sd["cases"] if o["case"].startswith(k))
+                                   for k in ("ld_f64", "awkward", "literal160", "literal24x6")
+                                   if any(o["case"].startswith(k) for o in sd["cases"])}
+    ot = full.get("other_types")
+    if ot:
+        pcts = {o["case"]: o["pct_of_d2d"] for o in ot["cases"]}
+        line["other_types_pct_of_d2d"] = dict(median=ot["pct_of_d2d_median"], min=min(pcts.values()),
+                                              weakest=min(pcts, key=pcts.get))
+    pk = full.get("packing")
+    if pk:
+        line["packing_pct_of_d2d_min"] = min(o["pct_of_d2d"] for o in pk)
+    sp = full.get("specialised")
+    if sp:
+        line["specialised_vs_generic_step"] = round(sp["step_GBps_specialised"] / sp["step_GBps_generic"], 3)
+    line["detail"] = detail_path
+    return line
+
+
 # ---------------------------------------------------------------------------------------
 def main():
     args = parse_args()
@@ -689,7 +912,7 @@ def main():
         return 2
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu_baseline = 2, 1, True
-        args.no_batched = args.no_served = True
+        args.no_batched = args.no_served = args.no_side = True
 
     import torch
     import paper_1607_01249_amd as ttx
@@ -830,6 +1053,13 @@ def main():
             json.dump(dict(kernel=dom_name, bytes_per_launch=bytes_per_launch,
                            avg_launch_us=roofline["avg_launch_us"]), f)
 
+    # The CPU-baseline leg: the oracle timed on the host, and every case's GPU
+    # output compared with it (outside the timed region).
+    cpu = verification = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline and verification")
+        cpu, verification = cpu_baseline(torch, ttx, cases, stream)
+
     specialised = None
     if not args.no_specialised and not args.profile_run:
         log("size-specialised kernels")
@@ -840,6 +1070,10 @@ def main():
         c.pop("B", None)
         ttx.ttx_plan_destroy(c.pop("plan"))
     torch.cuda.empty_cache()
+    side = None
+    if not args.no_side and not args.profile_run:
+        log("side shapes: leading dimensions, awkward extents, literal 160^4 and 24^6")
+        side = bench_side(torch, ttx, d2d, stream, args.tune_candidates)
     batched = None
     if not args.no_batched:
         log("batched: 512 problems")
@@ -854,16 +1088,12 @@ def main():
         cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates)
         log("GEMM operand packing")
         packing = bench_packing(torch, ttx, d2d, stream, args.tune_candidates)
-        if args.save_table:
-            ttx.ttx_tune_table_save(args.save_table)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("CPU oracle baseline")
-        cpu = cpu_baseline(cases, args.cpu_seconds)
+    if args.save_table:
+        ttx.ttx_tune_table_save(args.save_table)
 
     gbps_cases = [p["GBps"] for p in per_case]
-    out = dict(
+    weakest = min(per_case, key=lambda p: p["GBps"])
+    full = dict(
         metric=METRIC, value=round(value, 1), unit="GB/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(wall / args.steps * 1e3, 3), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
@@ -878,15 +1108,23 @@ def main():
         per_call_generic=per_call_generic,
         pct_of_d2d=round(100 * value / d2d, 1),
         ceilings=ceil,
-        per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases)),
-        roofline=roofline, cpu_baseline=cpu, specialised=specialised, batched=batched, served=served,
+        per_perm_GBps=dict(min=min(gbps_cases), median=float(np.median(gbps_cases)), max=max(gbps_cases),
+                           weakest=weakest["case"], weakest_pct_of_d2d=weakest["pct_of_d2d"]),
+        verification=verification,
+        roofline=roofline, cpu_baseline=cpu, specialised=specialised, side=side, batched=batched, served=served,
         other_types=cplx,
         packing=packing,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,
     )
-    print(json.dumps(out), flush=True)
+    line = compact_line(full, args.detail_out)
+    if args.detail_out:
+        d = os.path.dirname(os.path.abspath(args.detail_out))
+        os.makedirs(d, exist_ok=True)
+        with open(args.detail_out, "w") as f:
+            json.dump(full, f, indent=1)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
     return 0
 
 

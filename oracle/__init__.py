@@ -74,6 +74,8 @@ def _load(path):
     L.ttx_ref_b_offsets.restype = ctypes.c_int
     L.ttx_ref_threads.argtypes = []
     L.ttx_ref_threads.restype = ctypes.c_int
+    L.ttx_ref_set_threads.argtypes = [ctypes.c_int]
+    L.ttx_ref_set_threads.restype = ctypes.c_int
     return L
 
 
@@ -148,3 +150,8 @@ def sample(perm, size, alpha, A, beta, B_in, b_index, outer_a=None, outer_b=None
 def threads(library=None):
     """OpenMP threads the oracle's loop nest runs on."""
     return (library or lib()).ttx_ref_threads()
+
+
+def set_threads(n, library=None):
+    """Runs later oracle calls on ``n`` OpenMP threads; returns the count now in effect."""
+    return (library or lib()).ttx_ref_set_threads(int(n))

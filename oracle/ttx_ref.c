@@ -431,3 +431,11 @@ int ttx_ref_threads(void)
 {
     return omp_get_max_threads();
 }
+
+/* Sets the number of threads later calls use (n >= 1); results do not
+ * depend on it.  Returns the number now in effect. */
+int ttx_ref_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}

@@ -9,15 +9,30 @@
 
 #include "ttx_internal.h"
 
+// What a plan runs for one beta class: the configuration and, when one is
+// attached, the size-specialised kernel compiled for it.  Published as one
+// immutable object, so that an execution running concurrently with
+// ttx_plan_specialise or ttx_plan_set_config sees either the old pair or the
+// new one, never a mix.
+struct PlanExec {
+    ttx_config cfg;
+    int from_table;
+    const ttx::JitKernel* jit;   // owned by the JIT cache (lives until the process ends)
+};
+
 struct ttx_plan {
     ttx::Problem prob;
-    ttx_config cfg[2];       // [beta_is_zero]
-    int from_table[2];
-    bool user_set[2];
-    uint64_t table_gen;
-    const ttx::JitKernel* jit[2];   // size-specialised kernels ([beta_is_zero]; owned by the JIT cache)
-    uint32_t calls[2];              // per-call entry points: calls so far (automatic specialisation)
-    bool jit_tried[2];              // automatic specialisation attempted
+    std::shared_ptr<const PlanExec> exec[2];   // [beta_is_zero]; read and replaced with std::atomic_load/store
+    std::mutex mu;                             // serialises the writers
+    bool user_set[2] = {false, false};
+    uint64_t table_gen = 0;
+    uint32_t calls[2] = {0, 0};                // per-call entry points: calls so far (automatic specialisation)
+    bool jit_tried[2] = {false, false};        // automatic specialisation attempted
+
+    std::shared_ptr<const PlanExec> load(int z) const { return std::atomic_load(&exec[z]); }
+    void publish(int z, const ttx_config& cfg, int from_table, const ttx::JitKernel* jit) {
+        std::atomic_store(&exec[z], std::shared_ptr<const PlanExec>(new PlanExec{cfg, from_table, jit}));
+    }
 };
 
 namespace ttx {
@@ -36,13 +51,10 @@ static void resolve_configs(ttx_plan* plan) {
     for (int z = 0; z < 2; ++z) {
         if (plan->user_set[z]) continue;
         ttx_config c;
-        if (table_lookup(plan->prob, z == 1, &c)) {
-            plan->cfg[z] = c;
-            plan->from_table[z] = 1;
-        } else {
-            plan->cfg[z] = default_config(plan->prob);
-            plan->from_table[z] = 0;
-        }
+        if (table_lookup(plan->prob, z == 1, &c))
+            plan->publish(z, c, 1, nullptr);
+        else
+            plan->publish(z, default_config(plan->prob), 0, nullptr);
     }
 }
 
@@ -51,9 +63,8 @@ static ttx_status new_plan(ttx_plan** out, int dtype, int n, const int* perm, co
     Problem p;
     ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
     if (st != TTX_OK) return st;
-    ttx_plan* plan = new (std::nothrow) ttx_plan;
+    ttx_plan* plan = new (std::nothrow) ttx_plan();
     if (!plan) return fail(TTX_ENOMEM, "out of host memory");
-    std::memset(plan, 0, sizeof(*plan));
     plan->prob = p;
     resolve_configs(plan);
     *out = plan;
@@ -94,16 +105,16 @@ static ttx_status execute(const ttx_plan* plan, const Scalar& alpha, const void*
     const bool beta0 = beta_is_zero(p.dtype, beta);
     ttx_status st = check_pointers(p, A, Bin, Bout, beta0);
     if (st != TTX_OK) return st;
-    const int z = beta0 ? 1 : 0;
-    if (plan->jit[z]) {
+    const std::shared_ptr<const PlanExec> x = plan->load(beta0 ? 1 : 0);
+    if (x->jit) {
         TiledLaunch L;
-        if (prepare_tiled(p, plan->cfg[z], beta0, A, Bin, Bout, alpha, beta, &L) && jit_matches(*plan->jit[z], L)) {
-            const hipError_t e = jit_launch(*plan->jit[z], L, stream);
+        if (prepare_tiled(p, x->cfg, beta0, A, Bin, Bout, alpha, beta, &L) && jit_matches(*x->jit, L)) {
+            const hipError_t e = jit_launch(*x->jit, L, stream);
             if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
             return TTX_OK;
         }
     }
-    hipError_t e = launch_tiles(p, plan->cfg[z], beta0, A, beta0 ? nullptr : Bin, Bout, alpha, beta, stream);
+    hipError_t e = launch_tiles(p, x->cfg, beta0, A, beta0 ? nullptr : Bin, Bout, alpha, beta, stream);
     if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return TTX_OK;
 }
@@ -149,16 +160,20 @@ static int auto_calls() {
 
 static void maybe_specialise(ttx_plan* plan, const Scalar& beta, int hot) {
     const int z = beta_is_zero(plan->prob.dtype, beta) ? 1 : 0;
-    std::lock_guard<std::mutex> lock(g_auto_mu);
-    if (plan->jit_tried[z] || ++plan->calls[z] < uint32_t(hot)) return;
-    plan->jit_tried[z] = true;
+    {
+        std::lock_guard<std::mutex> lock(g_auto_mu);
+        if (plan->jit_tried[z] || ++plan->calls[z] < uint32_t(hot)) return;
+        plan->jit_tried[z] = true;
+    }
     if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) return;
     const std::string saved = g_last_error;
     int kept = 0;
-    if (ttx_plan_specialise(plan, z, 0, &kept) != TTX_OK)
+    if (ttx_plan_specialise(plan, z, 0, &kept) != TTX_OK) {
         g_last_error = saved;   // the shape keeps its generic kernel
-    else if (kept)
+    } else if (kept) {
+        std::lock_guard<std::mutex> lock(g_auto_mu);
         ++g_auto_specialised;
+    }
 }
 
 ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* size,
@@ -193,7 +208,7 @@ ttx_status transpose_cached(int dtype, int n, const int* perm, const int64_t* si
 static void cache_info(int* plans, int* specialised) {
     std::lock_guard<std::mutex> lock(g_cache_mu);
     int s = 0;
-    for (const auto& kv : g_cache) s += (kv.second->jit[0] || kv.second->jit[1]) ? 1 : 0;
+    for (const auto& kv : g_cache) s += (kv.second->load(0)->jit || kv.second->load(1)->jit) ? 1 : 0;
     if (plans) *plans = int(g_cache.size());
     if (specialised) *specialised = s;
 }
@@ -264,9 +279,10 @@ ttx_status ttx_plan_describe(const ttx_plan* plan, ttx_plan_info* info) {
     info->extent_a_bytes = p.extent_a;
     info->extent_b_bytes = p.extent_b;
     for (int z = 0; z < 2; ++z) {
-        info->config[z] = plan->cfg[z];
-        info->config_from_table[z] = plan->from_table[z];
-        info->specialised[z] = plan->jit[z] != nullptr;
+        const std::shared_ptr<const PlanExec> x = plan->load(z);
+        info->config[z] = x->cfg;
+        info->config_from_table[z] = x->from_table;
+        info->specialised[z] = x->jit != nullptr;
     }
     return TTX_OK;
 }
@@ -276,10 +292,9 @@ ttx_status ttx_plan_set_config(ttx_plan* plan, int beta_is_zero, const ttx_confi
     std::string why;
     if (!config_valid(plan->prob, *config, &why)) return fail(TTX_EINVAL, why);
     const int z = beta_is_zero ? 1 : 0;
-    plan->cfg[z] = *config;
+    std::lock_guard<std::mutex> lock(plan->mu);
     plan->user_set[z] = true;
-    plan->from_table[z] = 0;
-    plan->jit[z] = nullptr;
+    plan->publish(z, *config, 0, nullptr);
     return TTX_OK;
 }
 
@@ -287,10 +302,9 @@ ttx_status ttx_plan_set_config(ttx_plan* plan, int beta_is_zero, const ttx_confi
 // kernel flags depend only on alignment), never dereferenced.
 static void* fake_ptr(uintptr_t at) { return reinterpret_cast<void*>(at); }
 
-static ttx_status specialised_launch(const ttx_plan* plan, int beta_is_zero, TiledLaunch* L) {
-    const Problem& p = plan->prob;
+static ttx_status specialised_launch(const Problem& p, const ttx_config& cfg, int beta_is_zero, TiledLaunch* L) {
     const bool beta0 = beta_is_zero != 0;
-    if (!prepare_tiled(p, plan->cfg[beta0 ? 1 : 0], beta0, fake_ptr(1u << 20), beta0 ? nullptr : fake_ptr(2u << 20),
+    if (!prepare_tiled(p, cfg, beta0, fake_ptr(1u << 20), beta0 ? nullptr : fake_ptr(2u << 20),
                        fake_ptr(3u << 20), Scalar(1.0), Scalar(beta0 ? 0.0 : 1.0), L))
         return fail(TTX_EINVAL, "nothing to specialise (empty or single-index problem)");
     return TTX_OK;
@@ -304,33 +318,45 @@ ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero, int reps, int* 
     if (kept) *kept = 0;
     if (!plan) return fail(TTX_EINVAL, "NULL argument");
     const int z = beta_is_zero ? 1 : 0;
-    plan->jit[z] = nullptr;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    const std::shared_ptr<const PlanExec> prev = plan->load(z);
+    // the generic configuration: the one in effect without a specialised kernel
+    ttx_config generic = prev->cfg;
+    int generic_from_table = prev->from_table;
+    if (prev->jit && !plan->user_set[z]) {   // a specialised configuration may be in effect: look again
+        ttx_config c;
+        generic_from_table = table_lookup(plan->prob, z == 1, &c) ? 1 : 0;
+        generic = generic_from_table ? c : default_config(plan->prob);
+    }
+    plan->publish(z, generic, generic_from_table, nullptr);
     if (plan->prob.family != TTX_FAMILY_MOVED && plan->prob.family != TTX_FAMILY_PRESERVED) return TTX_OK;
     // a configuration tuned for specialised execution, when the table has one
     // and the caller has not set the config
+    ttx_config cfg = generic;
+    int from_table = generic_from_table;
     ttx_config cs;
     if (!plan->user_set[z] && table_lookup(plan->prob, z == 1, &cs, true)) {
-        plan->cfg[z] = cs;
-        plan->from_table[z] = 1;
+        cfg = cs;
+        from_table = 1;
     }
     TiledLaunch L;
-    ttx_status st = specialised_launch(plan, z, &L);
+    ttx_status st = specialised_launch(plan->prob, cfg, z, &L);
     if (st != TTX_OK) return st;
     const JitKernel* k = nullptr;
     st = jit_kernel(L, &k);
     if (st != TTX_OK) return st;
     if (reps > 0) {
-        // candidate 0: the generic kernel, 1: the specialised one, on the
-        // tuner's scratch tensors (hipMalloc'd, so in the compiled alignment class)
+        // candidate 0: the generic kernel with its own configuration, 1: the
+        // specialised one, on the tuner's scratch tensors (hipMalloc'd, so in
+        // the compiled alignment class)
         const Problem& p = plan->prob;
-        const ttx_config& c = plan->cfg[z];
         const bool beta0 = z == 1;
         const Scalar alpha(1.25), beta(beta0 ? 0.0 : 0.75);
         auto launch = [&](int i, const void* A, void* B, hipStream_t stream) -> hipError_t {
             const void* Bsrc = beta0 ? nullptr : B;
-            if (i == 0) return launch_tiles(p, c, beta0, A, Bsrc, B, alpha, beta, stream);
+            if (i == 0) return launch_tiles(p, generic, beta0, A, Bsrc, B, alpha, beta, stream);
             TiledLaunch T;
-            if (!prepare_tiled(p, c, beta0, A, Bsrc, B, alpha, beta, &T) || !jit_matches(*k, T))
+            if (!prepare_tiled(p, cfg, beta0, A, Bsrc, B, alpha, beta, &T) || !jit_matches(*k, T))
                 return hipErrorInvalidValue;
             return jit_launch(*k, T, stream);
         };
@@ -338,9 +364,10 @@ ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero, int reps, int* 
         double best_us = 0, us[2] = {0, 0};
         st = time_candidates(p, beta0, 2, reps, launch, &best, &best_us, us);
         if (st != TTX_OK) return st;
+        // not faster: the plan keeps its generic kernel and configuration
         if (!(us[1] < us[0] * (1.0 - kSpecialiseMargin))) return TTX_OK;
     }
-    plan->jit[z] = k;
+    plan->publish(z, cfg, from_table, k);
     if (kept) *kept = 1;
     return TTX_OK;
 }
@@ -348,7 +375,7 @@ ttx_status ttx_plan_specialise(ttx_plan* plan, int beta_is_zero, int reps, int* 
 ttx_status ttx_plan_specialised_source(const ttx_plan* plan, int beta_is_zero, char* buf, int len) {
     if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
     TiledLaunch L;
-    ttx_status st = specialised_launch(plan, beta_is_zero, &L);
+    ttx_status st = specialised_launch(plan->prob, plan->load(beta_is_zero ? 1 : 0)->cfg, beta_is_zero, &L);
     if (st != TTX_OK) return st;
     const std::string src = jit_source(L);
     if (int64_t(src.size()) >= int64_t(len)) return fail(TTX_EINVAL, "buffer too small");
@@ -361,15 +388,14 @@ ttx_status ttx_plan_kernel_name(const ttx_plan* plan, double beta, const void* A
     if (!plan || !buf || len <= 0) return fail(TTX_EINVAL, "NULL argument");
     const Problem& p = plan->prob;
     const bool beta0 = beta_is_zero(p.dtype, beta);
-    const int z = beta0 ? 1 : 0;
+    const std::shared_ptr<const PlanExec> x = plan->load(beta0 ? 1 : 0);
     std::string name;
     TiledLaunch L;
-    if (plan->jit[z] && prepare_tiled(p, plan->cfg[z], beta0, A, B, const_cast<void*>(B), Scalar(1.0), Scalar(beta),
-                                      &L) &&
-        jit_matches(*plan->jit[z], L))
-        name = jit_name(*plan->jit[z]);
+    if (x->jit && prepare_tiled(p, x->cfg, beta0, A, B, const_cast<void*>(B), Scalar(1.0), Scalar(beta), &L) &&
+        jit_matches(*x->jit, L))
+        name = jit_name(*x->jit);
     else
-        name = kernel_name(p, plan->cfg[z], beta0, A, B, B);
+        name = kernel_name(p, x->cfg, beta0, A, B, B);
     if (int(name.size()) >= len) return fail(TTX_EINVAL, "buffer too small");
     std::memcpy(buf, name.c_str(), name.size() + 1);
     return TTX_OK;

@@ -330,6 +330,51 @@ def test_plan_set_config_validation():
         ttx.ttx_plan_destroy(p)
 
 
+def test_plan_config_handoff_between_threads():
+    """A plan's configuration is replaced as one object: a thread reading it
+    while another swaps between two configurations always sees one of the
+    two whole, never fields of both."""
+    import threading
+    perm, size = (2, 0, 3, 1), (70, 33, 19, 23)
+    cands, _ = ttx.ttx_tune_candidates(ttx.F32, perm, size, max_candidates=-1, cap=100000)
+    a = cands[0]
+    b = next(c for c in cands if (c.tile_a, c.tile_b) != (a.tile_a, a.tile_b) and
+             list(c.order[:4]) != list(a.order[:4]) and c.flags != a.flags)
+    key = lambda d: json.dumps(d, sort_keys=True)
+    want = {key(a.as_dict()), key(b.as_dict())}
+    p = ttx.ttx_plan_create(ttx.F32, perm, size)
+    stop = threading.Event()
+    seen, errors = set(), []
+
+    def writer():
+        i = 0
+        while not stop.is_set():
+            ttx.ttx_plan_set_config(p, 0, a if i % 2 == 0 else b)
+            i += 1
+
+    def reader():
+        for _ in range(20000):
+            k = key(ttx.ttx_plan_describe(p)["config"][0])
+            seen.add(k)
+            if k not in want:
+                errors.append(k)
+                break
+
+    try:
+        ttx.ttx_plan_set_config(p, 0, a)
+        w = threading.Thread(target=writer)
+        w.start()
+        try:
+            reader()
+        finally:
+            stop.set()
+            w.join()
+    finally:
+        ttx.ttx_plan_destroy(p)
+    assert not errors, errors[:1]
+    assert seen <= want
+
+
 def test_tune_table_roundtrip(tmp_path):
     ttx.ttx_tune_table_clear()
     path = str(tmp_path / "table.txt")

@@ -6,6 +6,7 @@ bit-identity is the expectation there too and the number of differing
 elements is reported).
 """
 import itertools
+import os
 import sys
 
 import numpy as np
@@ -14,7 +15,7 @@ import pytest
 import oracle
 import paper_1607_01249_amd as ttx
 import workloads
-from gpu_util import F32, F64, assert_parity, gpu_transpose
+from gpu_util import F32, F64, assert_parity, from_device, gpu_transpose, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -76,17 +77,59 @@ def test_reduced_large_perms_plain_copy_exact(rank, perm, dtype):
 
 
 # -- paper-shaped permutations at full size (about 200 MiB per tensor) -------------------
+# These run the kernels the throughput step times: the shipped tune table is
+# loaded, and each case runs (a) through ttx_transpose (the generic kernel
+# with the table's configuration) and (b) through a plan with its
+# size-specialised kernel (the table's configuration for specialised
+# execution where it has one), both against the oracle on every element.
+TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_1607_01249_amd", "tune", "gfx950.txt")
+
+
+@pytest.fixture(scope="module")
+def shipped_table():
+    ttx.ttx_tune_table_clear()
+    ttx.ttx_tune_table_load(TABLE)
+    yield
+    ttx.ttx_tune_table_clear()
+
+
 @pytest.mark.parametrize("case", workloads.large_cases(), ids=lambda c: c["name"])
-def test_full_size_large_perms(case):
+def test_full_size_large_perms(case, shipped_table):
+    import torch
     _say("full-size case %s" % case["name"])
     perm, size, dtype = case["perm"], case["size"], case["dtype"]
+    code = ttx.F32 if dtype == F32 else ttx.F64
     n = _elems(size)
     A = workloads.uniform(n, dtype, case["seed_a"])
     B = workloads.uniform(n, dtype, case["seed_b"])
     ref = B.copy()
     assert oracle.transpose(perm, size, case["alpha"], A, case["beta"], ref) == 0
-    got = gpu_transpose(perm, size, case["alpha"], A, case["beta"], B)
-    assert_parity(got, ref, exact=False, what=case["name"])
+    dA, pa = to_device(A)
+    dB, pb = to_device(B)
+    stream = ttx.current_stream()
+    z = case["beta"] == 0
+    # (a) per call: the generic kernel with the table's configuration
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        assert ttx.ttx_plan_describe(plan)["config_from_table"][int(z)], "case missing from the shipped table"
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    ttx.ttx_transpose(code, len(perm), perm, size, None, None, case["alpha"], pa, case["beta"], pb, stream)
+    assert_parity(from_device(dB), ref, exact=False, what="generic " + case["name"])
+    # (b) the plan with its size-specialised kernel, as the throughput step runs it
+    dB.copy_(torch.from_numpy(B))
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        assert ttx.ttx_plan_specialise(plan, z)
+        kernel = ttx.ttx_plan_kernel_name(plan, case["beta"], pa, pb)
+        assert kernel.startswith("ttx_jit_"), kernel
+        _say("  %s" % kernel)
+        ttx.ttx_plan_execute(plan, case["alpha"], pa, case["beta"], pb, stream)
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    assert_parity(from_device(dB), ref, exact=False, what="specialised " + case["name"])
+    del dA, dB
 
 
 @pytest.mark.parametrize("dtype,perm", [(F32, (3, 2, 1, 0)), (F32, (2, 0, 3, 1)),

@@ -54,6 +54,8 @@ LARGE_PERMS = {
 }
 # the literal "(160,160,160,160)" shape: 2.44 GiB (FP32) / 4.88 GiB (FP64) per tensor
 LITERAL_4D = (160, 160, 160, 160)
+# the literal "all dims 24" 6D shape: 729 MiB (FP32) / 1458 MiB (FP64) per tensor
+LITERAL_6D = (24, 24, 24, 24, 24, 24)
 
 
 def large_cases(betas=(0.7, 0.0)):
