@@ -441,6 +441,27 @@ ttx_status ttx_batch_destroy(ttx_batch *batch);
 ttx_status ttx_batch_plan(int count, const ttx_problem *problems, ttx_config *configs,
                           int64_t *tiles);
 
+/* Allocation-free batched run, for callers that cannot allocate device
+ * memory (serving loops that must not call hipMalloc, harnesses that forbid
+ * it).  Computes what ttx_batch_create + ttx_batch_execute + ttx_batch_destroy
+ * compute for the same problems, with the same configs and the same
+ * persistent kernel, bit for bit, but allocates no device memory: the work
+ * block (descriptor table, chunk prefix, claim counter) is a static per-GPU
+ * array of about 1 MiB that the library holds until the process ends.
+ * count <= TTX_STATIC_BATCH_MAX, else TTX_EINVAL and nothing runs.  The
+ * caller owns every A and B; each problem is checked as ttx_transpose
+ * checks it and the first failure is returned before anything is launched.
+ * Asynchronous on `stream`: the descriptors are copied from host memory to
+ * the array on `stream` (the host copy has been read when the call returns),
+ * then the kernel and any per-call launches (complex and mixed-precision
+ * problems) follow on the same stream.  Every call on a GPU shares that
+ * GPU's array: calls ordered on one stream are safe, calls that may overlap
+ * on one GPU (different streams without synchronisation, several threads)
+ * race and give wrong results.  The copy comes from pageable host memory,
+ * so the call is not for use under stream capture. */
+#define TTX_STATIC_BATCH_MAX 1024
+ttx_status ttx_batch_run_static(int count, const ttx_problem *problems, hipStream_t stream);
+
 /* -- serving ----------------------------------------------------------------------
  * A request loop with continuous batching.  Requests (one Eqn. 1 each) are
  * admitted in arrival order while the sum of the HBM footprints of admitted,

@@ -207,6 +207,7 @@ def _declare(L):
         "ttx_batch_config": ([vp, S, ctypes.POINTER(Config)], S),
         "ttx_batch_destroy": ([vp], S),
         "ttx_batch_plan": ([S, ctypes.POINTER(Problem), ctypes.POINTER(Config), i64p], S),
+        "ttx_batch_run_static": ([S, ctypes.POINTER(Problem), vp], S),
         "ttx_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(ServerOpts)], S),
         "ttx_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], S),
         "ttx_server_poll": ([vp, ctypes.c_uint64, ip], S),
@@ -439,6 +440,14 @@ def ttx_batch_config(batch, index):
 
 def ttx_batch_destroy(batch):
     return _check(lib().ttx_batch_destroy(batch))
+
+
+STATIC_BATCH_MAX = 1024   # TTX_STATIC_BATCH_MAX
+
+
+def ttx_batch_run_static(problems, stream=0):
+    """Allocation-free batched run (the work block is a static device array)."""
+    return _check(lib().ttx_batch_run_static(len(problems), _problem_array(problems), stream))
 
 
 def ttx_batch_plan(problems):

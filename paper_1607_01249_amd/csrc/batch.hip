@@ -477,10 +477,10 @@ static bool runs_per_call(const Problem& p) {
 }
 
 // Device work block of a batch: descriptors, chunk prefix, claim counter.
-static size_t desc_bytes(int count) { return size_t(count) * sizeof(BatchDesc); }
-static size_t prefix_offset(int count) { return desc_bytes(count); }
-static size_t counter_offset(int count) { return (prefix_offset(count) + sizeof(uint32_t) * (count + 1) + 15) & ~size_t(15); }
-static size_t work_bytes(int count) { return counter_offset(count) + 2 * sizeof(uint32_t); }
+static constexpr size_t desc_bytes(int count) { return size_t(count) * sizeof(BatchDesc); }
+static constexpr size_t prefix_offset(int count) { return desc_bytes(count); }
+static constexpr size_t counter_offset(int count) { return (prefix_offset(count) + sizeof(uint32_t) * (count + 1) + 15) & ~size_t(15); }
+static constexpr size_t work_bytes(int count) { return counter_offset(count) + 2 * sizeof(uint32_t); }
 
 static const BatchDesc* work_desc(const ttx_batch* b) { return reinterpret_cast<const BatchDesc*>(b->d_work); }
 static const uint32_t* work_prefix(const ttx_batch* b) {
@@ -567,20 +567,10 @@ static ttx_status upload(ttx_batch* b, hipStream_t stream) {
     return TTX_OK;
 }
 
-static void drop_graph(ttx_batch* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    b->captured = false;
-}
-
-extern "C" {
-
-ttx_status ttx_batch_create(ttx_batch** out, int count, const ttx_problem* problems) {
-    if (!out || count < 0 || (count > 0 && !problems)) return fail(TTX_EINVAL, "bad batch arguments");
-    ttx_batch* b = new (std::nothrow) ttx_batch;
-    if (!b) return fail(TTX_ENOMEM, "out of host memory");
+// Checks and plans every problem and builds the descriptor table, on the
+// host only (no HIP call): what ttx_batch_create and ttx_batch_run_static
+// share, so that both run the same configs.
+static ttx_status prepare(ttx_batch* b, int count, const ttx_problem* problems) {
     b->prob.resize(count);
     b->src.assign(problems, problems + count);
     b->cfg.resize(count);
@@ -602,13 +592,59 @@ ttx_status ttx_batch_create(ttx_batch** out, int count, const ttx_problem* probl
                 }
             }
         }
-        if (st != TTX_OK) {
-            delete b;
-            return fail(st, "problem " + std::to_string(i) + ": " + ttx_last_error());
-        }
+        if (st != TTX_OK) return fail(st, "problem " + std::to_string(i) + ": " + ttx_last_error());
     }
-    ttx_status st = describe_all(b);
-    if (st == TTX_OK) st = upload(b, nullptr);
+    return describe_all(b);
+}
+
+// -- allocation-free runs ----------------------------------------------------------------
+// The work block of ttx_batch_run_static (descriptors, chunk prefix, claim
+// counter of at most TTX_STATIC_BATCH_MAX problems) lives in this file-scope
+// device array: each GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy (on the host it is only a stand-in symbol): it uses the device
+// address that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[work_bytes(TTX_STATIC_BATCH_MAX)];
+
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[64];
+
+static ttx_status scratch_address(unsigned char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TTX_EHIP, "no current device");
+    if (dev < 0 || dev >= 64) return fail(TTX_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TTX_EHIP, std::string("scratch address lookup: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return TTX_OK;
+}
+
+static void drop_graph(ttx_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->captured = false;
+}
+
+extern "C" {
+
+ttx_status ttx_batch_create(ttx_batch** out, int count, const ttx_problem* problems) {
+    if (!out || count < 0 || (count > 0 && !problems)) return fail(TTX_EINVAL, "bad batch arguments");
+    ttx_batch* b = new (std::nothrow) ttx_batch;
+    if (!b) return fail(TTX_ENOMEM, "out of host memory");
+    ttx_status st = prepare(b, count, problems);
+    if (st != TTX_OK) {
+        delete b;
+        return st;
+    }
+    st = upload(b, nullptr);
     if (st != TTX_OK) {
         ttx_batch_destroy(b);
         return st;
@@ -767,6 +803,35 @@ ttx_status ttx_batch_execute(ttx_batch* b, hipStream_t stream) {
     }
     hipError_t e = hipGraphLaunch(b->exec, stream);
     return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
+ttx_status ttx_batch_run_static(int count, const ttx_problem* problems, hipStream_t stream) {
+    if (count < 0 || (count > 0 && !problems)) return fail(TTX_EINVAL, "bad batch arguments");
+    if (count > TTX_STATIC_BATCH_MAX)
+        return fail(TTX_EINVAL, "at most " + std::to_string(TTX_STATIC_BATCH_MAX) +
+                                    " problems per allocation-free run, got " + std::to_string(count));
+    ttx_batch b;   // host bookkeeping only: it owns no device memory and no graph
+    ttx_status st = prepare(&b, count, problems);
+    if (st != TTX_OK) return st;
+    hipError_t e = hipSuccess;
+    if (b.chunks) {
+        unsigned char* base = nullptr;
+        st = scratch_address(&base);
+        if (st != TTX_OK) return st;
+        // one host block: descriptors, chunk prefix and a zeroed claim
+        // counter, copied in one transfer ordered on the stream (a copy from
+        // pageable memory has read the block when the call returns)
+        std::vector<unsigned char> host(work_bytes(b.nk), 0);
+        std::memcpy(host.data(), b.desc.data(), desc_bytes(b.nk));
+        std::memcpy(host.data() + prefix_offset(b.nk), b.chunk_prefix.data(), sizeof(uint32_t) * (b.nk + 1));
+        e = hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = launch_batch(reinterpret_cast<const BatchDesc*>(base),
+                             reinterpret_cast<const uint32_t*>(base + prefix_offset(b.nk)), b.nk, b.chunks, b.grid,
+                             reinterpret_cast<uint32_t*>(base + counter_offset(b.nk)), stream);
+    }
+    if (e == hipSuccess) e = launch_per_call(&b, stream);
+    return e == hipSuccess ? TTX_OK : fail(TTX_EHIP, std::string("static batch launch: ") + hipGetErrorString(e));
 }
 
 ttx_status ttx_batch_get_info(const ttx_batch* b, ttx_batch_info* info) {

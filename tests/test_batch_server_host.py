@@ -91,6 +91,22 @@ def test_batch_plan_rejects_bad_problems():
     assert e.value.status == ttx.EOVERLAP
 
 
+def test_static_batch_run_checks_before_any_launch():
+    """The allocation-free run refuses too many problems and bad problems
+    before it touches a device (so this runs without one)."""
+    import re
+    hdr = open(__file__.rsplit("/tests/", 1)[0] + "/include/ttx.h").read()
+    assert int(re.search(r"#define TTX_STATIC_BATCH_MAX (\d+)", hdr).group(1)) == ttx.STATIC_BATCH_MAX
+    good = ttx.make_problem(ttx.F32, (1, 0), (8, 8), 1.0, FAKE_BASE, 0.0, FAKE_BASE + 4096)
+    with pytest.raises(ttx.TTXError, match="at most") as e:
+        ttx.ttx_batch_run_static([good] * (ttx.STATIC_BATCH_MAX + 1))
+    assert e.value.status == ttx.EINVAL
+    bad = ttx.make_problem(ttx.F32, (0, 0), (8, 8), 1.0, FAKE_BASE, 0.0, FAKE_BASE + 4096)
+    with pytest.raises(ttx.TTXError) as e:
+        ttx.ttx_batch_run_static([good, bad])
+    assert e.value.status == ttx.EPERM
+
+
 # -- server with the fake executor -------------------------------------------------------
 def _req(size=(64, 64), perm=(1, 0), dtype=ttx.F32, beta=0.0, A=FAKE_BASE, B=None, B_in=None,
          keep=False):
