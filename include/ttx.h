@@ -126,7 +126,7 @@ typedef enum ttx_family {
  *   tile_b  : MOVED: tile extent along B's stride-1 index;
  *             PRESERVED: rows per tile along B's second index;
  *             FLAT: elements per workgroup iteration (informational);
- *   threads : threads per workgroup;
+ *   threads : threads per workgroup: 64, 128, 256 or 512 (flat problems: 256);
  *   order   : the merged indices in the order tile ids enumerate them,
  *             fastest first (the "loop order" of Sec. 2.2); n_order entries;
  *   flags   : TTX_CFG_* bits;
@@ -141,7 +141,16 @@ typedef enum ttx_family {
  *   length for PRESERVED, 1 for MOVED);
  *   tile_c  : dense tiles only -- extent along a third index, the first index
  *             of `order` that is neither a tile index nor a group member, so
- *             that one tile holds several small planes (0 or 1: one plane). */
+ *             that one tile holds several small planes (0 or 1: one plane);
+ *   lds_pad : elements appended to each row of an LDS-staged tile (MOVED menu
+ *             tiles and PRESERVED tiles with groups): 0..TTX_MAX_LDS_PAD; the
+ *             row of a moved tile holds tile_a + lds_pad elements.  Ignored by
+ *             tiles that do not pass through LDS with fixed rows (direct
+ *             PRESERVED rows, dense tiles, FLAT).
+ * The library holds pre-compiled kernels for threads = 256 and lds_pad = 1;
+ * a configuration with other values runs a size-specialised kernel compiled
+ * at run time (hipRTC) on first use, with the same arithmetic. */
+#define TTX_MAX_LDS_PAD 4
 typedef struct ttx_config {
     int family;
     int tile_a;
@@ -153,6 +162,7 @@ typedef struct ttx_config {
     int group_a;   /* index groups, see above (1 = the single index) */
     int group_b;
     int tile_c;    /* dense tiles: planes per tile along the third index (0 or 1: one) */
+    int lds_pad;   /* LDS row padding of staged tiles, in elements (see above) */
 } ttx_config;
 
 /* What the planner made of a problem (Sec. 2.1 stage 1 and the family split
@@ -290,8 +300,13 @@ ttx_status ttx_plan_specialised_source(const ttx_plan *plan, int beta_is_zero, c
  * as --maxImplementations=-1), times each on scratch buffers the tuner
  * allocates (minimum of `reps` runs, caches flushed before each run) and
  * stores the fastest in the in-process tune table, which later plans for
- * the same merged problem use.  *best receives the winner; *n_timed (may be
- * NULL) the number of candidates timed.  Needs a GPU; blocks the caller. */
+ * the same merged problem use.  A second stage then times the workgroup
+ * variants (ttx_tune_variants: threads per workgroup, LDS row padding) of
+ * the TTX_TUNE_VARIANT_BASES fastest blockings of the first, each compiled
+ * at run time when it is not a pre-compiled kernel.  *best receives the
+ * winner; *n_timed (may be NULL) the number of candidates timed in both
+ * stages.  Needs a GPU; blocks the caller. */
+#define TTX_TUNE_VARIANT_BASES 2
 ttx_status ttx_tune(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
                     const int64_t *outer_a, const int64_t *outer_b, int beta_is_zero,
                     int max_candidates, int reps, ttx_config *best, int *n_timed);
@@ -315,6 +330,19 @@ ttx_status ttx_tune_candidates(ttx_dtype dtype, int n, const int *perm, const in
                                const int64_t *outer_a, const int64_t *outer_b,
                                int max_candidates, ttx_config *out, double *cost, int cap,
                                int *count);
+/* The workgroup variants of one config (host only, no GPU): the same
+ * blocking, loop order and flags with each valid threads-per-workgroup value
+ * (64, 128, 256, 512) and, for LDS-staged tiles, each LDS row padding
+ * 0..TTX_MAX_LDS_PAD, every combination once, the given config first.  A
+ * variant is valid when the tile's rows and vectors fit the workgroup and
+ * each thread holds at most 32 vectors per side.  These are the second
+ * search stage of ttx_tune and ttx_tune_specialised, around the measured
+ * best blockings (Sec. 2.2: blockings and loop orders, extended here by the
+ * workgroup shape and the shared-memory layout of Sec. 2.3).  Up to `cap`
+ * configs are written; *count receives how many. */
+ttx_status ttx_tune_variants(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
+                             const int64_t *outer_a, const int64_t *outer_b, const ttx_config *base,
+                             ttx_config *out, int cap, int *count);
 /* Tune table persistence (one text line per entry) and reset. */
 ttx_status ttx_tune_table_save(const char *path);
 ttx_status ttx_tune_table_load(const char *path);

@@ -50,12 +50,19 @@ class Config(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("tile_a", ctypes.c_int), ("tile_b", ctypes.c_int),
                 ("threads", ctypes.c_int), ("n_order", ctypes.c_int),
                 ("order", ctypes.c_int * MAX_DIMS), ("flags", ctypes.c_int),
-                ("group_a", ctypes.c_int), ("group_b", ctypes.c_int), ("tile_c", ctypes.c_int)]
+                ("group_a", ctypes.c_int), ("group_b", ctypes.c_int), ("tile_c", ctypes.c_int),
+                ("lds_pad", ctypes.c_int)]
+
+    def __init__(self, *args, **kw):
+        # the pre-compiled kernels' workgroup shape unless given
+        kw.setdefault("threads", 256)
+        kw.setdefault("lds_pad", 1)
+        super().__init__(*args, **kw)
 
     def as_dict(self):
         return dict(family=FAMILY_NAMES[self.family], tile_a=self.tile_a, tile_b=self.tile_b,
                     threads=self.threads, order=list(self.order[:self.n_order]), flags=self.flags,
-                    group_a=self.group_a, group_b=self.group_b, tile_c=self.tile_c)
+                    group_a=self.group_a, group_b=self.group_b, tile_c=self.tile_c, lds_pad=self.lds_pad)
 
 
 class PlanInfo(ctypes.Structure):
@@ -192,6 +199,8 @@ def _declare(L):
         "ttx_tune_specialised": ([S, S, ip, i64p, i64p, i64p, S, S, S, ctypes.POINTER(Config), ip], S),
         "ttx_tune_candidates": ([S, S, ip, i64p, i64p, i64p, S, ctypes.POINTER(Config),
                                  ctypes.POINTER(ctypes.c_double), S, ip], S),
+        "ttx_tune_variants": ([S, S, ip, i64p, i64p, i64p, ctypes.POINTER(Config), ctypes.POINTER(Config),
+                               S, ip], S),
         "ttx_tune_table_save": ([ctypes.c_char_p], S),
         "ttx_tune_table_load": ([ctypes.c_char_p], S),
         "ttx_tune_table_clear": ([], S),
@@ -369,6 +378,15 @@ def ttx_tune_candidates(dtype, perm, size, outer_a=None, outer_b=None, max_candi
                                      _i64s(outer_b), int(max_candidates), out, cost, cap,
                                      ctypes.byref(count)))
     return [out[i] for i in range(count.value)], [cost[i] for i in range(count.value)]
+
+
+def ttx_tune_variants(dtype, perm, size, base, outer_a=None, outer_b=None, cap=64):
+    """Workgroup variants (threads per workgroup x LDS row padding) of one config, itself first."""
+    out = (Config * cap)()
+    count = ctypes.c_int(0)
+    _check(lib().ttx_tune_variants(dtype, len(perm), _ints(perm), _i64s(size), _i64s(outer_a), _i64s(outer_b),
+                                   ctypes.byref(base), out, cap, ctypes.byref(count)))
+    return [out[i] for i in range(count.value)]
 
 
 def ttx_tune_table_save(path):

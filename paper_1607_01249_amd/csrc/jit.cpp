@@ -59,15 +59,18 @@ static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 14695981039346656
 // parameters, the element types, the beta class, the kernel flags and the
 // bytes of the problem-dependent arguments.
 static std::string jit_key(const TiledLaunch& L) {
-    const int head[] = {L.p.code, L.kind, L.va, L.vb, L.n0, L.cap, L.flags, L.beta0 ? 1 : 0, L.c.tile_a, L.c.tile_b};
+    const int head[] = {L.p.code, L.kind, L.va,       L.vb,       L.n0,        L.cap,
+                        L.flags,  L.beta0 ? 1 : 0, L.c.tile_a, L.c.tile_b, L.c.threads, config_pad(L.c)};
     std::string k(reinterpret_cast<const char*>(head), sizeof(head));
     k.append(reinterpret_cast<const char*>(L.args), sizeof(TileArgsHost));
     return k;
 }
 
-// The kernel's name: kind, element types, beta class, tile shape, and a
-// hash of the problem, so that profiles tell specialised kernels apart.
-static std::string entry_name(const TiledLaunch& L) {
+// The kernel's name: kind, element types, beta class, tile shape, the
+// workgroup size and LDS padding when they differ from the pre-compiled
+// kernels' (256, 1), and a hash of the problem, so that profiles tell
+// specialised kernels apart.
+std::string jit_entry_name(const TiledLaunch& L) {
     static const char* const kKind[] = {"moved", "preserved", "staged", "dense"};
     auto type = [](int dtype) {
         std::string t = element_type_name(dtype);
@@ -77,6 +80,8 @@ static std::string entry_name(const TiledLaunch& L) {
     if (L.p.dtype_a != L.p.dtype) n += "_" + type(L.p.dtype_a);
     n += L.beta0 ? "_b0_" : "_b_";
     n += std::to_string(L.c.tile_a) + "x" + std::to_string(L.c.tile_b);
+    if (L.c.threads != kThreads) n += "_t" + std::to_string(L.c.threads);
+    if (config_pad(L.c) != 1) n += "_p" + std::to_string(config_pad(L.c));
     const std::string key = jit_key(L);
     char h[16];
     std::snprintf(h, sizeof(h), "_%08x", unsigned(fnv1a(key.data(), key.size()) & 0xffffffffu));
@@ -86,29 +91,34 @@ static std::string entry_name(const TiledLaunch& L) {
 std::string jit_source(const TiledLaunch& L) {
     const std::string T = element_type_name(L.p.dtype), S = element_type_name(L.p.dtype_a);
     const char* b0 = L.beta0 ? "true" : "false";
-    char tile[192];
+    char tile[224];
     int lds = 0, waves = 0;
     bool pipe = false;
-    switch (L.kind) {   // the tiles, shared memory and occupancy hints of the generic kernels
+    const int nt = L.c.threads, pad = config_pad(L.c);
+    // the tiles, shared memory and occupancy hints of the generic kernels,
+    // with the config's workgroup size and LDS row padding (store kind -1:
+    // taken from the constant kernel flags)
+    switch (L.kind) {
         case kTileMoved:
-            std::snprintf(tile, sizeof(tile), "ttx::MovedTile<%s, %s, %d, %d, %d, %d, %s>", T.c_str(), b0, L.c.tile_a,
-                          L.c.tile_b, L.va, L.vb, S.c_str());
-            lds = L.c.tile_b * (L.c.tile_a + 1);
+            std::snprintf(tile, sizeof(tile), "ttx::MovedTile<%s, %s, %d, %d, %d, %d, %s, -1, %d, %d>", T.c_str(), b0,
+                          L.c.tile_a, L.c.tile_b, L.va, L.vb, S.c_str(), nt, pad);
+            lds = L.c.tile_b * (L.c.tile_a + pad);
             waves = (L.va == 1 || L.vb == 1) ? 4 : 1;
             break;
         case kTilePreserved:
-            std::snprintf(tile, sizeof(tile), "ttx::PreservedTile<%s, %s, %d, %d, %d, %s>", T.c_str(), b0, L.c.tile_a,
-                          L.c.tile_b, L.va, S.c_str());
+            std::snprintf(tile, sizeof(tile), "ttx::PreservedTile<%s, %s, %d, %d, %d, %s, -1, %d>", T.c_str(), b0,
+                          L.c.tile_a, L.c.tile_b, L.va, S.c_str(), nt);
             waves = L.va == 1 ? 4 : 1;
             break;
         case kTileStaged:
-            std::snprintf(tile, sizeof(tile), "ttx::StagedTile<%s, %s, %d, %d, %d, %s>", T.c_str(), b0, L.n0,
-                          L.c.tile_a, L.c.tile_b, S.c_str());
-            lds = L.c.tile_b * (L.c.tile_a * L.n0 + 1);
+            std::snprintf(tile, sizeof(tile), "ttx::StagedTile<%s, %s, %d, %d, %d, %s, -1, %d, %d>", T.c_str(), b0,
+                          L.n0, L.c.tile_a, L.c.tile_b, S.c_str(), nt, pad);
+            lds = L.c.tile_b * (L.c.tile_a * L.n0 + pad);
             waves = 4;
             break;
         default:
-            std::snprintf(tile, sizeof(tile), "ttx::DenseTile<%s, %s, %d, %s>", T.c_str(), b0, L.cap, S.c_str());
+            std::snprintf(tile, sizeof(tile), "ttx::DenseTile<%s, %s, %d, %s, -1, %d>", T.c_str(), b0, L.cap,
+                          S.c_str(), nt);
             lds = 2 * L.cap;
             pipe = true;
     }
@@ -125,9 +135,9 @@ std::string jit_source(const TiledLaunch& L) {
     }
     s += "\n}};\nstatic_assert(sizeof(Image) == sizeof(ttx::TileArgsHost), \"argument layout\");\n";
     s += "constexpr ttx::TileArgsHost kHost = __builtin_bit_cast(ttx::TileArgsHost, kImage);\n}  // namespace\n\n";
-    s += "extern \"C\" __global__ __launch_bounds__(ttx::kThreads)";
+    s += "extern \"C\" __global__ __launch_bounds__(" + std::to_string(nt) + ")";
     if (waves) s += " __attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + ")))";
-    s += "\nvoid " + entry_name(L) + "(ttx::TileArgs<" + T + ", " + S + "> a) {\n";
+    s += "\nvoid " + jit_entry_name(L) + "(ttx::TileArgs<" + T + ", " + S + "> a) {\n";
     if (lds)
         s += "    __shared__ " + T + " lds[" + std::to_string(lds) + "];\n";
     else
@@ -244,7 +254,7 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     std::unique_ptr<JitKernel> k(new JitKernel());
     k->device = dev;
     k->key = key;
-    k->name = entry_name(L);
+    k->name = jit_entry_name(L);
     e = hipModuleLoadData(&k->module, code.data());
     if (e != hipSuccess && from_disk) {   // a damaged cache file: compile again
         ttx_status st = compile(src, arch, &code);
@@ -261,7 +271,7 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
     k->dense_grid = 0;
     if (L.kind == kTileDense) {
         int nb = 0, cus = 0;
-        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, kThreads, 0) != hipSuccess || nb <= 0)
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, L.c.threads, 0) != hipSuccess || nb <= 0)
             nb = 4;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
@@ -284,7 +294,7 @@ hipError_t jit_launch(const JitKernel& k, const TiledLaunch& L, hipStream_t stre
     uint32_t grid = L.grid;
     if (L.kind == kTileDense) grid = L.ntiles < k.dense_grid ? L.ntiles : k.dense_grid;
     void* params[] = {const_cast<unsigned char*>(L.args)};
-    return hipModuleLaunchKernel(k.fn, grid, 1, 1, kThreads, 1, 1, 0, stream, params, nullptr);
+    return hipModuleLaunchKernel(k.fn, grid, 1, 1, uint32_t(L.c.threads), 1, 1, 0, stream, params, nullptr);
 }
 
 }  // namespace ttx

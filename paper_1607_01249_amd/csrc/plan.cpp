@@ -382,13 +382,70 @@ bool widen(const Problem& p, Problem* w) {
     return true;
 }
 
+// Whether a tile of config c (shape already validated) can run with
+// c.threads threads and c.lds_pad padding: the tile's rows (in vectors)
+// must fit the workgroup, each thread may hold at most kMaxVectors vectors
+// per side (register budget), staged and dense tiles must split into whole
+// passes, and the LDS tile must fit a workgroup's 64 KiB.  The vector widths
+// are the ones the launch will use (kernel_flags: they depend on strides
+// and the tile shape only).  The pre-compiled configurations (256 threads,
+// padding 1) all pass.
+static constexpr int kMaxVectors = 32;
+
+static int per_thread(int run, int rows, int nt) {   // vectors per thread: runs of `run` over `rows`
+    int lanes = 1;
+    while (lanes < run) lanes <<= 1;
+    if (lanes > nt) return -1;
+    const int per_pass = nt / lanes;
+    return (rows + per_pass - 1) / per_pass;
+}
+
+static bool workgroup_fits(const Problem& p, const Layout& L, const ttx_config& c, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return false;
+    };
+    const int nt = c.threads;
+    const int es = elem_bytes(p.dtype);
+    if (config_is_dense(c)) {
+        const int cap = dense_cap(p.dtype);
+        if (cap % nt || cap / nt > 16) return bad("dense tile slots do not split over this many threads");
+        return true;
+    }
+    if (L.staged) {
+        const int n0 = staged_lanes(p.dim[0].size);
+        const int slots = n0 * c.tile_a * c.tile_b;
+        if (slots % nt || slots / nt > kMaxVectors) return bad("staged tile does not split over this many threads");
+        if (int64_t(c.tile_b) * (int64_t(c.tile_a) * n0 + c.lds_pad) * es > 65536)
+            return bad("staged LDS tile larger than 64 KiB");
+        return true;
+    }
+    const int VAe = 16 / elem_bytes(p.dtype_a), VBe = 16 / es;
+    if (p.family == TTX_FAMILY_PRESERVED) {
+        const int V = VAe < VBe ? VAe : VBe;
+        const int v = (p.dim[0].sa == 1 && p.dim[0].sb == 1 && c.tile_a % V == 0) ? V : 1;
+        const int k = per_thread(c.tile_a / v, c.tile_b, nt);
+        if (k < 0 || k > kMaxVectors) return bad("preserved tile rows do not fit this many threads");
+        return true;
+    }
+    const int va = (p.dim[L.a].sa == 1 && c.tile_a % VAe == 0) ? VAe : 1;
+    const int vb = (p.dim[L.b].sb == 1 && c.tile_b % VBe == 0) ? VBe : 1;
+    const int ka = per_thread(c.tile_a / va, c.tile_b, nt), kb = per_thread(c.tile_b / vb, c.tile_a, nt);
+    if (ka < 0 || kb < 0 || ka > kMaxVectors || kb > kMaxVectors)
+        return bad("moved tile runs do not fit this many threads");
+    if (int64_t(c.tile_b) * (c.tile_a + c.lds_pad) * es > 65536) return bad("LDS tile larger than 64 KiB");
+    return true;
+}
+
 bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     auto bad = [&](const char* m) {
         if (why) *why = m;
         return false;
     };
     if (c.family != p.family) return bad("config family does not match the problem");
-    if (c.threads != kThreads) return bad("threads must be 256");
+    if (c.threads != 64 && c.threads != 128 && c.threads != 256 && c.threads != 512)
+        return bad("threads must be 64, 128, 256 or 512");
+    if (c.lds_pad < 0 || c.lds_pad > TTX_MAX_LDS_PAD) return bad("lds_pad out of range");
     if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE | TTX_CFG_GROUPED))
         return bad("unknown flag");
     if (config_is_wide(c)) {
@@ -411,6 +468,7 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     if (!make_layout(p, c.group_a, c.group_b, &L)) return bad("invalid index groups for this problem");
     if (p.family == TTX_FAMILY_FLAT) {
         if (config_is_dense(c)) return bad("dense tiles need a moved or preserved problem");
+        if (c.threads != kThreads) return bad("flat problems run 256 threads per workgroup");
         return true;
     }
     const int64_t tc = c.tile_c > 1 ? c.tile_c : 1;
@@ -446,7 +504,7 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
         if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
     }
     if (tiles >= (uint64_t(1) << 32)) return bad("too many tiles for this tile shape");
-    return true;
+    return workgroup_fits(p, L, c, why);
 }
 
 void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
@@ -866,6 +924,7 @@ static ttx_config make_config(const Problem& p, int ta, int tb, const std::vecto
     c.tile_a = ta;
     c.tile_b = tb;
     c.threads = kThreads;
+    c.lds_pad = 1;
     c.n_order = int(order.size());
     for (size_t i = 0; i < order.size(); ++i) c.order[i] = order[i];
     c.flags = flags;
@@ -1010,12 +1069,32 @@ int rank_candidates(const Problem& p, int max_candidates, ttx_config* out, doubl
     return n;
 }
 
+int workgroup_variants(const Problem& p, const ttx_config& base, ttx_config* out, int cap) {
+    int n = 0;
+    if (cap <= 0) return 0;
+    out[n++] = base;
+    if (p.family != TTX_FAMILY_MOVED && p.family != TTX_FAMILY_PRESERVED) return n;
+    static const int kThreadMenu[] = {64, 128, 256, 512};
+    const bool padded = config_uses_pad(base);
+    for (int t : kThreadMenu)
+        for (int pad = 0; pad <= (padded ? TTX_MAX_LDS_PAD : 0); ++pad) {
+            ttx_config c = base;
+            c.threads = t;
+            if (padded) c.lds_pad = pad;
+            if (c.threads == base.threads && config_pad(c) == config_pad(base)) continue;   // the base itself
+            if (!config_valid(p, c, nullptr)) continue;
+            if (n < cap) out[n++] = c;
+        }
+    return n;
+}
+
 ttx_config default_config_from(const Problem& p, const TileShape* shapes, int ns,
                                const TileShape* staged, int nstaged, bool dense, bool wide) {
     ttx_config best;
     std::memset(&best, 0, sizeof(best));
     best.family = p.family;
     best.threads = kThreads;
+    best.lds_pad = 1;
     best.group_a = best.group_b = 1;
     if (p.family == TTX_FAMILY_EMPTY) return best;
     if (p.family == TTX_FAMILY_FLAT) {

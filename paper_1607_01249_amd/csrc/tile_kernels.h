@@ -2,13 +2,15 @@
 //
 // Sec. 2.2 splits an N-D transposition into independent 2D transpositions
 // ("macro-tiles") that run in parallel, one per thread block on GPUs, each
-// staged through on-chip memory.  Here one 256-thread workgroup handles one
+// staged through on-chip memory.  Here one workgroup (256 threads in the
+// pre-compiled kernels; 64 to 512 in size-specialised ones) handles one
 // tile at a time:
 //   - moved family (A's stride-1 index moves): the tile is TA elements along
 //     A's stride-1 index times TB elements along B's stride-1 index.  A is
 //     read along its stride-1 index with 16-byte vector loads, the tile is
-//     transposed through LDS (rows padded by one element so that the
-//     column-wise reads of the store phase fall in distinct banks), and B
+//     transposed through LDS (rows padded, by one element in the
+//     pre-compiled kernels, so that the column-wise reads of the store
+//     phase spread over the banks), and B
 //     is written along its stride-1 index with 16-byte vector stores;
 //   - preserved family (the stride-1 index stays in place, Sec. 3.2): rows
 //     are contiguous in both tensors, so they are copied directly with
@@ -346,12 +348,15 @@ constexpr bool nt_of() {
 // VA / VB are the vector widths along x in A and along y in B (VA > 1
 // implies sAa == 1, VB > 1 implies sBb == 1); vectors need only element
 // alignment, and a vector that would run past the end of the super index is
-// moved element by element.  The LDS tile has TB rows of TA + 1 elements.
-template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T, int NTS = -1>
+// moved element by element.  The LDS tile has TB rows of TA + PAD elements
+// (the pre-compiled kernels pad by one, so that the column-wise reads of the
+// store phase fall in distinct banks); NTH threads share the tile.
+template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T, int NTS = -1,
+          int NTH = kThreads, int PAD = 1>
 struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
-    static constexpr int NT = kThreads, LDR = TA + 1;
+    static constexpr int NT = NTH, LDR = TA + PAD;
     template <typename Args>
     __device__ static int ext_a(const Args&) { return TA; }
     template <typename Args>
@@ -462,12 +467,12 @@ struct MovedTile {
 
 // One preserved-family tile: rows of ea elements contiguous in A and B.
 // Row y < eb starts at A[oa + y*sAb] and B[ob + y*sBb]; element x of a row is
-// at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).  No LDS.
-template <typename T, bool BETA0, int TA, int TR, int V, typename S = T, int NTS = -1>
+// at x*sAa / x*sBa (V > 1 implies sAa == sBa == 1).  No LDS.  NTH threads.
+template <typename T, bool BETA0, int TA, int TR, int V, typename S = T, int NTS = -1, int NTH = kThreads>
 struct PreservedTile {
     static constexpr bool kUsesLds = false;
     static constexpr int kTA = TA, kTB = TR;
-    static constexpr int NT = kThreads;
+    static constexpr int NT = NTH;
     template <typename Args>
     __device__ static int ext_a(const Args&) { return TA; }
     template <typename Args>
@@ -540,12 +545,13 @@ struct PreservedTile {
 // index, contiguous in B).  Element (i, x0 + x, y0 + y) is
 //   A[oa + i*s0A + x*sAa + gB.offset(y0 + y)] -> B[ob + i*s0B + y*sBb + gA.offset(x0 + x)].
 // A is read in runs of n0*TX elements and B written in runs of n0*TY; the
-// tile passes through LDS as [y][x][i] (row length TX*N0 + 1).
-template <typename T, bool BETA0, int N0, int TX, int TY, typename S = T, int NTS = -1>
+// tile passes through LDS as [y][x][i] (row length TX*N0 + PAD).  NTH threads.
+template <typename T, bool BETA0, int N0, int TX, int TY, typename S = T, int NTS = -1, int NTH = kThreads,
+          int PAD = 1>
 struct StagedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TX, kTB = TY;
-    static constexpr int NT = kThreads, LDR = TX * N0 + 1;
+    static constexpr int NT = NTH, LDR = TX * N0 + PAD;
     template <typename Args>
     __device__ static int ext_a(const Args&) { return TX; }
     template <typename Args>
@@ -657,10 +663,11 @@ struct StagedTile {
 // order (i, y, x, z: runs of runB), so that both sides run along their
 // contiguous index without padding lanes to a power of two.  The tile passes
 // through LDS as [z][y][x][i], rows of ldr >= runA elements (odd when possible).
-template <typename T, bool BETA0, int CAP, typename S = T, int NTS = -1>
+// NTH threads, CAP / NTH slots each.
+template <typename T, bool BETA0, int CAP, typename S = T, int NTS = -1, int NTH = kThreads>
 struct DenseTile {
     static constexpr bool kUsesLds = true;
-    static constexpr int NT = kThreads, NS = CAP / NT;
+    static constexpr int NT = NTH, NS = CAP / NT;
     static_assert(CAP % NT == 0 && CAP <= 1024, "whole passes; slot coordinates packed in 11+11+10 bits");
     template <typename Args>
     __device__ static int ext_a(const Args& a) { return a.tx; }

@@ -160,6 +160,20 @@ inline int dense_cap(int dtype) {
     return cap[dtype];
 }
 inline bool config_is_wide(const ttx_config& c) { return (c.flags & TTX_CFG_WIDE) != 0; }
+// Whether the config's tile passes through LDS in rows of a fixed length
+// (moved menu tiles and staged tiles): the tiles that lds_pad pads.
+inline bool config_uses_pad(const ttx_config& c) {
+    return !config_is_dense(c) && (c.family == TTX_FAMILY_MOVED || config_is_staged(c));
+}
+// The LDS row padding in effect (1, the pre-compiled kernels', where none applies).
+inline int config_pad(const ttx_config& c) { return config_uses_pad(c) ? c.lds_pad : 1; }
+// Whether the config runs outside the pre-compiled kernels (another
+// workgroup size or LDS padding): then it always runs a size-specialised
+// kernel, compiled on first use.
+inline bool config_needs_jit(const ttx_config& c) { return c.threads != kThreads || config_pad(c) != 1; }
+// Workgroup variants of a valid config (threads per workgroup x LDS row
+// padding), the config itself first; returns how many were written.
+int workgroup_variants(const Problem& p, const ttx_config& base, ttx_config* out, int cap);
 // Steps of the first grid position per group of the grouped tile order.
 constexpr uint32_t kGroupedSteps = 8;
 // The problem over whole units of the kept stride-1 rows (TTX_CFG_WIDE):
@@ -202,8 +216,9 @@ bool prepare_tiled(const Problem& p, const ttx_config& c, bool beta0, const void
 struct JitKernel;
 // Finds or compiles (hipRTC) and loads the kernel for L on the current device.
 ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out);
-// The translation unit jit_kernel compiles for L.
+// The translation unit jit_kernel compiles for L, and its kernel's name.
 std::string jit_source(const TiledLaunch& L);
+std::string jit_entry_name(const TiledLaunch& L);
 // True when k runs what L launches (same device, kernel, flags and arguments).
 bool jit_matches(const JitKernel& k, const TiledLaunch& L);
 // The kernel's name as profilers print it.

@@ -40,7 +40,7 @@ static std::atomic<uint64_t> g_table_gen{1};
 static std::string g_db_path;   // attached database file ("" when none); under g_table_mu
 static const char* const kTableHeader =
     "# ttx tune table v3: key | family tile_a tile_b threads flags group_a group_b n_order order... "
-    "[c<tile_c>] | usec\n";
+    "[c<tile_c>] [l<lds_pad>] | usec\n";
 
 static ttx_status attach_db(const char* path);
 static ttx_status merge_file(const char* path);
@@ -129,6 +129,7 @@ static std::string config_text(const ttx_config& c) {
        << c.group_a << " " << c.group_b << " " << c.n_order;
     for (int i = 0; i < c.n_order; ++i) os << " " << c.order[i];
     if (c.tile_c > 1) os << " c" << c.tile_c;
+    if (c.lds_pad != 1) os << " l" << c.lds_pad;
     return os.str();
 }
 
@@ -140,11 +141,21 @@ static bool parse_config(std::istringstream& is, ttx_config* c) {
     if (c->n_order < 0 || c->n_order > kMaxDims) return false;
     for (int i = 0; i < c->n_order; ++i)
         if (!(is >> c->order[i])) return false;
-    std::string extra;   // optional "c<planes>" (dense tiles)
-    if (is >> extra) {
-        if (extra.size() < 2 || extra[0] != 'c') return false;
-        c->tile_c = std::atoi(extra.c_str() + 1);
-        if (c->tile_c < 1) return false;
+    // optional "c<planes>" (dense tiles) and "l<padding>" (LDS rows; 1 when absent)
+    c->lds_pad = 1;
+    std::string extra;
+    while (is >> extra) {
+        if (extra.size() < 2 || (extra[0] != 'c' && extra[0] != 'l')) return false;
+        char* end = nullptr;
+        const long v = std::strtol(extra.c_str() + 1, &end, 10);
+        if (*end != '\0') return false;
+        if (extra[0] == 'c') {
+            if (v < 1) return false;
+            c->tile_c = int(v);
+        } else {
+            if (v < 0 || v > TTX_MAX_LDS_PAD) return false;
+            c->lds_pad = int(v);
+        }
     }
     return true;
 }
@@ -224,6 +235,71 @@ ttx_status time_candidates(const Problem& p, bool beta0, int count, int reps,
     return TTX_OK;
 }
 
+// Second search stage: the workgroup variants (threads per workgroup x LDS
+// row padding) of the TTX_TUNE_VARIANT_BASES fastest distinct candidates of
+// the first stage (times in us[]), each compiled as a size-specialised
+// kernel before it is timed (a variant whose compilation fails is skipped;
+// the pre-compiled configurations among them run their generic kernels
+// unless `specialised`).  *best and *best_us are replaced by a faster
+// variant; *timed grows by the variants timed.
+static ttx_status tune_variants(const Problem& p, bool beta0, const std::vector<ttx_config>& cands,
+                                const std::vector<double>& us, int reps, bool specialised, ttx_config* best,
+                                double* best_us, int* timed) {
+    if (p.family != TTX_FAMILY_MOVED && p.family != TTX_FAMILY_PRESERVED) return TTX_OK;
+    std::vector<int> order(cands.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return us[x] < us[y]; });
+    const Scalar alpha(1.25), beta(beta0 ? 0.0 : 0.75);
+    std::vector<ttx_config> vars;
+    std::vector<const JitKernel*> ks;
+    ttx_config buf[4 * (TTX_MAX_LDS_PAD + 1)];
+    for (int b = 0, taken = 0; b < int(order.size()) && taken < TTX_TUNE_VARIANT_BASES; ++b) {
+        const int nv = workgroup_variants(p, cands[order[b]], buf, int(sizeof(buf) / sizeof(buf[0])));
+        ++taken;
+        for (int v = 1; v < nv; ++v) {   // buf[0] is the base, timed in the first stage
+            bool dup = false;
+            for (const ttx_config& c : vars) dup |= std::memcmp(&c, &buf[v], sizeof(c)) == 0;
+            if (dup) continue;
+            const JitKernel* k = nullptr;
+            if (specialised || config_needs_jit(buf[v])) {
+                TiledLaunch L;
+                void* a = reinterpret_cast<void*>(uintptr_t(1) << 20);
+                void* bb = reinterpret_cast<void*>(uintptr_t(3) << 20);
+                if (!prepare_tiled(p, buf[v], beta0, a, beta0 ? nullptr : bb, bb, alpha, beta, &L)) continue;
+                const std::string saved = ttx_last_error();
+                if (jit_kernel(L, &k) != TTX_OK) {   // no kernel for this variant: leave it out
+                    fail(TTX_OK, saved);
+                    continue;
+                }
+            }
+            vars.push_back(buf[v]);
+            ks.push_back(k);
+        }
+    }
+    if (vars.empty()) return TTX_OK;
+    int vi = -1;
+    double vus = 0;
+    ttx_status st = time_candidates(
+        p, beta0, int(vars.size()), reps,
+        [&](int i, const void* A, void* B, hipStream_t s) {
+            const void* Bsrc = beta0 ? nullptr : B;
+            if (ks[i]) {
+                TiledLaunch L;
+                if (!prepare_tiled(p, vars[i], beta0, A, Bsrc, B, alpha, beta, &L)) return hipErrorInvalidValue;
+                if (jit_matches(*ks[i], L)) return jit_launch(*ks[i], L, s);
+            }
+            return launch_tiles(p, vars[i], beta0, A, Bsrc, B, alpha, beta, s);
+        },
+        &vi, &vus);
+    if (st != TTX_OK) return st;
+    *timed += int(vars.size());
+    if (vi >= 0 && vus < *best_us) {
+        *best = vars[vi];
+        *best_us = vus;
+    }
+    return TTX_OK;
+}
+
 // Ranks the candidates of p, times the best max_candidates of them and
 // stores the fastest in the tune table (ttx_tune for a built problem).
 ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int reps, ttx_config* best,
@@ -240,15 +316,19 @@ ttx_status tune_problem(const Problem& p, bool beta0, int max_candidates, int re
     cands.resize(nc);
     int best_i = -1;
     double best_us = 0;
+    std::vector<double> us(nc, 0.0);
     ttx_status st = time_candidates(
         p, beta0, int(cands.size()), reps,
         [&](int i, const void* A, void* B, hipStream_t s) {
             return launch_tiles(p, cands[i], beta0, A, B, B, 1.0, beta0 ? 0.0 : 1.0, s);
         },
-        &best_i, &best_us);
+        &best_i, &best_us, us.data());
     if (st != TTX_OK) return st;
     *best = cands[best_i];
-    if (n_timed) *n_timed = nc;
+    int timed = nc;
+    st = tune_variants(p, beta0, cands, us, reps, false, best, &best_us, &timed);
+    if (st != TTX_OK) return st;
+    if (n_timed) *n_timed = timed;
     table_store(p, beta0, *best, best_us);
     return TTX_OK;
 }
@@ -282,6 +362,7 @@ ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candid
     }
     int best_i = -1;
     double best_us = 0;
+    std::vector<double> us(nc, 0.0);
     ttx_status st = time_candidates(
         p, beta0, nc, reps,
         [&](int i, const void* A, void* B, hipStream_t s) {
@@ -291,10 +372,13 @@ ttx_status tune_problem_specialised(const Problem& p, bool beta0, int max_candid
             if (jit_matches(*ks[i], L)) return jit_launch(*ks[i], L, s);
             return launch_tiles(p, cands[i], beta0, A, Bsrc, B, alpha, beta, s);
         },
-        &best_i, &best_us);
+        &best_i, &best_us, us.data());
     if (st != TTX_OK) return st;
     *best = cands[best_i];
-    if (n_timed) *n_timed = nc;
+    int timed = nc;
+    st = tune_variants(p, beta0, cands, us, reps, true, best, &best_us, &timed);
+    if (st != TTX_OK) return st;
+    if (n_timed) *n_timed = timed;
     table_store(p, beta0, *best, best_us, true);
     return TTX_OK;
 }
@@ -372,6 +456,19 @@ ttx_status ttx_tune_candidates(ttx_dtype dtype, int n, const int* perm, const in
     ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
     if (st != TTX_OK) return st;
     *count = rank_candidates(p, max_candidates, out, cost, cap);
+    return TTX_OK;
+}
+
+ttx_status ttx_tune_variants(ttx_dtype dtype, int n, const int* perm, const int64_t* size,
+                             const int64_t* outer_a, const int64_t* outer_b, const ttx_config* base,
+                             ttx_config* out, int cap, int* count) {
+    if (!base || !out || !count || cap < 0) return fail(TTX_EINVAL, "NULL argument or negative cap");
+    Problem p;
+    ttx_status st = make_problem(dtype, n, perm, size, outer_a, outer_b, &p);
+    if (st != TTX_OK) return st;
+    std::string why;
+    if (!config_valid(p, *base, &why)) return fail(TTX_EINVAL, why);
+    *count = workgroup_variants(p, *base, out, cap);
     return TTX_OK;
 }
 

@@ -394,6 +394,31 @@ def test_tune_table_roundtrip(tmp_path):
     assert d["config_from_table"] == [0, 0]
 
 
+def test_tune_table_keeps_workgroup_shape(tmp_path):
+    """Entries with another workgroup size and LDS padding (l<pad>) load,
+    reach the plan, and are written back the same way; an out-of-range
+    padding is a malformed line."""
+    ttx.ttx_tune_table_clear()
+    path = str(tmp_path / "table.txt")
+    line = "d0:b1:n3:s96,128,80:p2,1,0:a1,96,12288:o10240,80,1 | 3 32 16 128 1 1 1 3 0 2 1 l3 | 12.5\n"
+    with open(path, "w") as f:
+        f.write(line)
+    try:
+        ttx.ttx_tune_table_load(path)
+        d = _describe(0, (2, 1, 0), (96, 128, 80))
+        assert d["config_from_table"] == [0, 1]
+        assert d["config"][1]["threads"] == 128 and d["config"][1]["lds_pad"] == 3
+        out = str(tmp_path / "saved.txt")
+        ttx.ttx_tune_table_save(out)
+        assert " 128 1 1 1 3 0 2 1 l3 | " in open(out).read()
+        with open(path, "w") as f:
+            f.write(line.replace(" l3 ", " l9 "))
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_tune_table_load(path)
+    finally:
+        ttx.ttx_tune_table_clear()
+
+
 def test_fastdiv_host_exhaustive_sample(tmp_path):
     src = tmp_path / "fd.cpp"
     src.write_text(r'''
@@ -679,8 +704,11 @@ def test_shipped_table_covers_the_large_cases():
                     cfg.group_a, cfg.group_b, cfg.n_order = map(int, f[5:8])
                     for i in range(cfg.n_order):
                         cfg.order[i] = int(f[8 + i])
-                    extra = f[8 + cfg.n_order:]
-                    cfg.tile_c = int(extra[0][1:]) if extra else 0
+                    for tok in f[8 + cfg.n_order:]:   # optional c<planes> and l<padding>
+                        if tok[0] == "c":
+                            cfg.tile_c = int(tok[1:])
+                        elif tok[0] == "l":
+                            cfg.lds_pad = int(tok[1:])
                     ttx.ttx_plan_set_config(plan, z, cfg)
                     spec_keys.discard(key)
             finally:

@@ -51,7 +51,10 @@ def _expected_tile(name):
     t = args[0]
     s, rest = (args[1], args[2:-1]) if m.group(2) else (t, args[1:-1])
     tile = {"moved": "MovedTile", "preserved": "PreservedTile", "staged": "StagedTile", "dense": "DenseTile"}
-    return "ttx::%s<%s, %s, %s>" % (tile[m.group(1)], t, ", ".join(rest), s)
+    # then the store kind (-1: from the constant flags), the workgroup size
+    # and, for tiles staged through LDS rows, the row padding
+    wg = {"moved": "256, 1", "staged": "256, 1", "preserved": "256", "dense": "256"}[m.group(1)]
+    return "ttx::%s<%s, %s, %s, -1, %s>" % (tile[m.group(1)], t, ", ".join(rest), s, wg)
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -138,3 +141,85 @@ def test_source_compiles_without_scratch(case, tmp_path):
     assert re.search(r"\.name:\s+ttx_jit_\w+", notes), notes
     # every index constant folded: no private (scratch) memory
     assert re.search(r"\.private_segment_fixed_size:\s+0\b", notes), notes
+
+
+# -- workgroup variants: threads per workgroup and LDS row padding -----------------------
+def _variants(dtype, perm, size, bz):
+    plan = ttx.ttx_plan_create(dtype, perm, size)
+    try:
+        base = ttx.ttx_plan_describe(plan)["config_raw"][1 if bz else 0]
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    return base, ttx.ttx_tune_variants(dtype, perm, size, base)
+
+
+def test_variants_of_a_moved_tile_span_threads_and_padding():
+    base, vs = _variants(ttx.F32, (3, 2, 1, 0), (160, 160, 64, 32), True)
+    assert vs[0].as_dict() == base.as_dict()
+    seen = {(v.threads, v.lds_pad) for v in vs}
+    assert len(seen) == len(vs), "each combination once"
+    assert {t for t, _ in seen} <= {64, 128, 256, 512} and {p for _, p in seen} <= set(range(5))
+    # the pre-compiled shape and at least one other size and padding are there
+    assert (256, 1) in seen and len({t for t, _ in seen}) >= 3 and len({p for _, p in seen}) == 5
+    for v in vs:   # nothing but the workgroup shape changes
+        d, b = v.as_dict(), base.as_dict()
+        for k in ("threads", "lds_pad"):
+            d.pop(k), b.pop(k)
+        assert d == b
+
+
+def test_variants_of_unpadded_tiles_change_threads_only():
+    # direct preserved rows do not pass through LDS: padding is not a dimension
+    base, vs = _variants(ttx.F64, (0, 2, 1, 3), (160, 160, 32, 32), False)
+    assert base.family == ttx.FAMILY_PRESERVED and (base.group_a, base.group_b) == (1, 1)
+    assert len({v.lds_pad for v in vs}) == 1 and len(vs) == len({v.threads for v in vs}) >= 2
+    # flat problems run the fixed flat kernel
+    base, vs = _variants(ttx.F32, (0, 1), (64, 9), False)
+    assert len(vs) == 1
+
+
+def test_variant_configs_are_checked():
+    plan = ttx.ttx_plan_create(ttx.F32, (1, 0), (256, 256))
+    try:
+        c = ttx.ttx_plan_describe(plan)["config_raw"][0]
+        for threads, pad in [(100, 1), (256, 5), (256, -1), (1024, 1)]:
+            bad = ttx.Config.from_buffer_copy(c)
+            bad.threads, bad.lds_pad = threads, pad
+            with pytest.raises(ttx.TTXError):
+                ttx.ttx_plan_set_config(plan, False, bad)
+        ok = ttx.Config.from_buffer_copy(c)
+        ok.threads, ok.lds_pad = 128, 3
+        ttx.ttx_plan_set_config(plan, False, ok)
+        name = ttx.ttx_plan_kernel_name(plan, 1.0, 1 << 20, 3 << 20)
+        assert name.startswith("ttx_jit_moved_float_b_") and "_t128_p3_" in name, name
+        src = ttx.ttx_plan_specialised_source(plan, False)
+        assert "__launch_bounds__(128)" in src and ", -1, 128, 3>" in src
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    flat = ttx.ttx_plan_create(ttx.F32, (0, 1), (64, 9))
+    try:
+        c = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(flat)["config_raw"][0])
+        c.threads = 128
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(flat, False, c)
+    finally:
+        ttx.ttx_plan_destroy(flat)
+
+
+@pytest.mark.parametrize("threads,pad", [(64, 0), (128, 2), (512, 4)])
+def test_variant_sources_compile_without_scratch(threads, pad):
+    for dtype, perm, size in [(ttx.F64, (2, 0, 3, 1), (160, 160, 32, 32)),
+                              (ttx.F32, (0, 5, 1, 4, 2, 3), (24, 21, 20, 18, 17, 17))]:
+        base, vs = _variants(dtype, perm, size, False)
+        pick = [v for v in vs if v.threads == threads and (v.lds_pad == pad or base.family != ttx.FAMILY_MOVED)]
+        if not pick:
+            continue
+        plan = ttx.ttx_plan_create(dtype, perm, size)
+        try:
+            ttx.ttx_plan_set_config(plan, False, pick[0])
+            src = ttx.ttx_plan_specialised_source(plan, False)
+        finally:
+            ttx.ttx_plan_destroy(plan)
+        assert "__launch_bounds__(%d)" % threads in src
+        r, log, code = _compile(src)
+        assert r == 0 and code, log[:3000]
