@@ -522,11 +522,13 @@ def bench_specialised(torch, ttx, cases, d2d, stream, steps=10, reps=5):
                 per_case=out)
 
 
-def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False):
-    """Per-call transpositions of the other element types: complex (c and z,
-    complex alpha and beta) about 200 MiB per tensor, and mixed precision
-    (sd, ds, cz, zc), beta != 0, one case resident at a time: the median
-    time of `reps` launches per case (bytes: read A, read and write B).
+def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False, specialise=True):
+    """Transpositions of the other element types through plans with their
+    size-specialised kernels (as the main step runs its cases; generic
+    kernels with specialise=False): complex (c and z, complex alpha and beta)
+    about 200 MiB per tensor, and mixed precision (sd, ds, cz, zc), beta != 0,
+    one case resident at a time: the median time of `reps` launches per case
+    (bytes: read A, read and write B).
     Launches rotate over three (A, B) pairs so that each one starts with the
     data of the two before it in the 256 MiB Infinity Cache, not its own."""
     import workloads
@@ -549,6 +551,11 @@ def bench_types(torch, ttx, d2d, stream, tune_candidates, reps=10, profile=False
             ttx.ttx_plan_destroy(plan)
             plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
             tuned += 1
+        if specialise:
+            try:
+                ttx.ttx_plan_specialise(plan, False)
+            except ttx.TTXError as e:
+                log("specialisation failed for %s (%s): generic kernel" % (c["name"], e))
         pairs = []
         real = lambda t: torch.view_as_real(t) if t.is_complex() else t
         for k in range(3):
@@ -1085,7 +1092,7 @@ def main():
     cplx = packing = None
     if not args.no_types and not args.profile_run:
         log("complex and mixed-precision cases")
-        cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates)
+        cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates, specialise=not args.generic)
         log("GEMM operand packing")
         packing = bench_packing(torch, ttx, d2d, stream, args.tune_candidates)
     if args.save_table:

@@ -1,0 +1,156 @@
+"""Refines a tune table's entries for size-specialised execution with the
+workgroup dimensions (threads per workgroup, LDS row padding).
+
+For each problem given, the plan's configuration for specialised execution
+(the table's `j:` entry, else its generic entry) is the base; every workgroup
+variant of it (ttx_tune_variants) is compiled as a size-specialised kernel
+and timed the way a throughput loop runs it: back-to-back launches on warm
+data, median of the launch times, in several rounds with the base re-timed
+in each.  A variant replaces the base only when its median is lower by at
+least `--margin` in every round.  The result is written as `j:` entries of
+a new table file (the generic entries are copied unchanged).
+
+    python paper_1607_01249_amd/tune/refine_workgroups.py IN OUT [--cases large|complex|mixed|all]
+
+Needs a GPU.  Blocks for a few seconds per problem.
+"""
+import argparse
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def table_key(info, z):
+    """The tune table key of a plan (the format ttx writes: dtype, beta == 0, merged problem)."""
+    j = lambda xs: ",".join(map(str, xs))
+    return "d%d:b%d:n%d:s%s:p%s:a%s:o%s" % (info["dtype"], z, info["n"], j(info["size"]), j(info["perm"]),
+                                          j(info["stride_a"]), j(info["stride_b"]))
+
+
+def config_text(c):
+    """A config as a table line's middle field."""
+    f = [c.family, c.tile_a, c.tile_b, c.threads, c.flags, c.group_a, c.group_b, c.n_order]
+    f += list(c.order[:c.n_order])
+    s = " ".join(map(str, f))
+    if c.tile_c > 1:
+        s += " c%d" % c.tile_c
+    if c.lds_pad != 1:
+        s += " l%d" % c.lds_pad
+    return s
+
+
+def _timed(ttx, torch, plan, case, A, B, stream, launches=13):
+    for _ in range(3):
+        ttx.ttx_plan_execute_c(plan, case["alpha"], A, case["beta"], B, B, stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
+    for r in range(launches):
+        ev[r].record()
+        ttx.ttx_plan_execute_c(plan, case["alpha"], A, case["beta"], B, B, stream)
+    ev[launches].record()
+    torch.cuda.synchronize()
+    return statistics.median(ev[r].elapsed_time(ev[r + 1]) * 1e3 for r in range(launches))
+
+
+def refine(cases, rounds=2, margin=0.02, log=print):
+    """{key: (config, usec)} of the variants that beat their base."""
+    import torch
+    import paper_1607_01249_amd as ttx
+    stream = ttx.current_stream()
+    out = {}
+    for case in cases:
+        code, perm, size = case["code"], case["perm"], case["size"]
+        z = 1 if case["beta"] == 0 else 0
+        plan = ttx.ttx_plan_create(code, perm, size)
+        try:
+            ttx.ttx_plan_specialise(plan, z)
+            info = ttx.ttx_plan_describe(plan)
+            base = ttx.Config.from_buffer_copy(info["config_raw"][z])
+        finally:
+            ttx.ttx_plan_destroy(plan)
+        if info["family"] not in ("moved", "preserved"):
+            continue
+        variants = ttx.ttx_tune_variants(code, perm, size, base)
+        A = torch.empty(max(1, info["extent_a_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1)
+        B = torch.empty(max(1, info["extent_b_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1)
+        plans = []
+        for v in variants:
+            p = ttx.ttx_plan_create(code, perm, size)
+            ttx.ttx_plan_set_config(p, z, v)
+            ttx.ttx_plan_specialise(p, z)
+            plans.append(p)
+        times = [[] for _ in variants]
+        for _ in range(rounds):
+            for i, p in enumerate(plans):
+                times[i].append(_timed(ttx, torch, p, case, A.data_ptr(), B.data_ptr(), stream))
+        for p in plans:
+            ttx.ttx_plan_destroy(p)
+        best = min(range(len(variants)), key=lambda i: max(times[i]))
+        gain = [1 - times[best][r] / times[0][r] for r in range(rounds)]
+        kept = best != 0 and min(gain) >= margin
+        log("%s: base t%d p%d %.1f us, best t%d p%d %.1f us (%+.1f%%)%s" % (
+            case["name"], base.threads, base.lds_pad, max(times[0]), variants[best].threads,
+            variants[best].lds_pad, max(times[best]), -100 * min(gain), " -> kept" if kept else ""))
+        if kept:
+            out[table_key(info, z)] = (variants[best], max(times[best]))
+        del A, B
+        torch.cuda.empty_cache()
+    return out
+
+
+def write_table(src, dst, entries):
+    """Copies src to dst with `j:` entries for `entries` (replacing any there)."""
+    lines = open(src).read().splitlines()
+    keep = [l for l in lines if not any(l.startswith("j:" + k + " |") for k in entries)]
+    for k, (c, us) in sorted(entries.items()):
+        keep.append("j:%s | %s | %.3f" % (k, config_text(c), us))
+    with open(dst, "w") as f:
+        f.write("\n".join(keep) + "\n")
+
+
+def bench_cases(which):
+    """The throughput problems, as dicts with code, perm, size, alpha, beta (complex scalars)."""
+    import paper_1607_01249_amd as ttx
+    import workloads
+    import numpy as np
+    tcode = {np.dtype(np.float32): ttx.F32, np.dtype(np.float64): ttx.F64,
+             np.dtype(np.complex64): ttx.C32, np.dtype(np.complex128): ttx.C64}
+    out = []
+    if which in ("large", "all"):
+        for c in workloads.large_cases():
+            out.append(dict(name=c["name"], code=tcode[np.dtype(c["dtype"])], perm=c["perm"], size=c["size"],
+                            alpha=complex(c["alpha"]), beta=complex(c["beta"])))
+    for kind, gen in (("complex", workloads.complex_cases), ("mixed", workloads.mixed_cases)):
+        if which in (kind, "all"):
+            for c in gen():
+                code = ttx.CODE_OF[(tcode[np.dtype(c["dtype_a"])], tcode[np.dtype(c["dtype"])])]
+                out.append(dict(name=c["name"], code=code, perm=c["perm"], size=c["size"],
+                                alpha=complex(c["alpha"]), beta=complex(c["beta"])))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("table_in")
+    ap.add_argument("table_out")
+    ap.add_argument("--cases", default="large", choices=["large", "complex", "mixed", "all"])
+    ap.add_argument("--only", nargs="*", default=None, help="case names")
+    ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--margin", type=float, default=0.02)
+    args = ap.parse_args()
+    import paper_1607_01249_amd as ttx
+    ttx.ttx_tune_table_clear()
+    ttx.ttx_tune_table_load(args.table_in)
+    cases = bench_cases(args.cases)
+    if args.only:
+        cases = [c for c in cases if c["name"] in args.only]
+    entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True))
+    write_table(args.table_in, args.table_out, entries)
+    print("%d of %d entries refined -> %s" % (len(entries), len(cases), args.table_out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

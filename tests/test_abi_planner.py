@@ -674,10 +674,17 @@ def test_tune_table_from_the_environment_is_read_only(tmp_path):
 
 def test_shipped_table_covers_the_large_cases():
     """Every line of the shipped tune table parses and names a config the
-    planner accepts: each large case's plan takes its generic entry, and the
-    entries for specialised execution (prefix j:) name valid configs too."""
+    planner accepts: each throughput case's plan (large, complex, mixed)
+    takes its generic entry, and the entries for specialised execution
+    (prefix j:) name valid configs too."""
     import os
+    import numpy as np
     import workloads
+    tcode = {np.dtype(np.float32): ttx.F32, np.dtype(np.float64): ttx.F64,
+             np.dtype(np.complex64): ttx.C32, np.dtype(np.complex128): ttx.C64}
+    cases = [dict(c, code=tcode[np.dtype(c["dtype"])]) for c in workloads.large_cases()]
+    cases += [dict(c, code=ttx.CODE_OF[(tcode[np.dtype(c["dtype_a"])], tcode[np.dtype(c["dtype"])])])
+              for c in workloads.complex_cases() + workloads.mixed_cases()]
     table = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                          "paper_1607_01249_amd", "tune", "gfx950.txt")
     ttx.ttx_tune_table_clear()
@@ -686,9 +693,8 @@ def test_shipped_table_covers_the_large_cases():
         lines = [l for l in open(table) if l.strip() and not l.startswith("#")]
         assert ttx.ttx_tune_table_size() == len(lines)
         spec_keys = {l.split("|")[0].strip()[2:] for l in lines if l.startswith("j:")}
-        for c in workloads.large_cases():
-            code = ttx.F32 if c["dtype"] == workloads.F32 else ttx.F64
-            plan = ttx.ttx_plan_create(code, c["perm"], c["size"])
+        for c in cases:
+            plan = ttx.ttx_plan_create(c["code"], c["perm"], c["size"])
             try:
                 info = ttx.ttx_plan_describe(plan)
                 z = 1 if c["beta"] == 0 else 0
