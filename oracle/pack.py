@@ -18,6 +18,23 @@ exact, narrowing to nearest) and multiplied by alpha rounded to P's type,
 one rounding per product; complex products follow the textbook order,
 re = ar*xr - ai*xi and im = ar*xi + ai*xr, each product and sum rounded on
 its own (Eqn. 1 with beta = 0, as in ttx_ref.c).
+
+Matrix-core operand panels (pack_mfma) are the layout a 64-lane matrix
+fused multiply-add instruction of an AMD CDNA GPU reads its operands in:
+for a panel of `panel` rows (left operand; columns for the right operand)
+and kb = 64 / panel values of the reduction index k per instruction, lane
+l of the wave holds element (l mod panel, l div panel) of the
+panel x kb block of one instruction; successive instructions take
+successive blocks of kb values of k.  A panel is therefore stored as its
+blocks one after another, each block as 64 consecutive elements in lane
+order, and the k extent is padded with zeros to a whole block:
+
+* left operand (m x k matrix A, panels of `panel` rows):
+  P[l + 64*b + p*panel*K] = alpha * A[(p*panel + l mod panel) + (b*kb + l div panel)*ld]
+  with K = kb * ceil(k / kb), zero where the row is >= m or the k index >= k;
+* right operand (k x n matrix A, panels of `panel` columns):
+  P[l + 64*b + p*panel*K] = alpha * A[(b*kb + l div panel) + (p*panel + l mod panel)*ld]
+  with the same K, zero where the column is >= n or the k index >= k.
 """
 import numpy as np
 
@@ -62,5 +79,34 @@ def pack(kind, A, rows, cols, ld, panel, alpha=1.0, out_dtype=None):
         dst = j + r * panel + p * panel * rows
         src = r + col * ld
         keep = col < cols
+    P[dst[keep]] = _scale(A[src[keep]], alpha, out_dtype)
+    return P
+
+
+LANES = 64   # lanes of a wave: one operand element each per matrix instruction
+
+
+def pack_mfma(kind, A, rows, cols, ld, panel, alpha=1.0, out_dtype=None):
+    """Matrix-core operand panels of the column-major rows x cols matrix in
+    the flat array A (leading dimension ld): kind ROWS packs the left
+    operand (rows x k, k = cols), COLS the right one (k x cols, k = rows);
+    panel must divide 64.  Returns a flat array of
+    ceil(extent/panel) * panel * K elements of out_dtype."""
+    if LANES % panel:
+        raise ValueError("panel must divide 64")
+    out_dtype = np.dtype(out_dtype or A.dtype)
+    kb = LANES // panel                         # k values per instruction
+    split, k = (rows, cols) if kind == ROWS else (cols, rows)
+    npanels = -(-split // panel)
+    K = kb * -(-k // kb)                        # k padded to whole blocks
+    P = np.zeros(npanels * panel * K, dtype=out_dtype)
+    if split == 0 or k == 0:
+        return P
+    lane, blk, p = np.meshgrid(np.arange(LANES), np.arange(K // kb), np.arange(npanels), indexing="ij")
+    inner = p * panel + lane % panel            # the row (ROWS) or column (COLS) of A
+    kk = blk * kb + lane // panel               # the reduction index
+    dst = lane + LANES * blk + p * panel * K
+    src = inner + kk * ld if kind == ROWS else kk + inner * ld
+    keep = (inner < split) & (kk < k)
     P[dst[keep]] = _scale(A[src[keep]], alpha, out_dtype)
     return P

@@ -770,3 +770,118 @@ def test_pack_oracle_complex_and_mixed_scalars_match_the_transposition_oracle():
         T = np.zeros(m * k, dtype=db)
         _run(oracle.lib(), (0, 2, 1), (mr, m // mr, k), alpha, A, 0.0, T)
         assert _same_bits(P, T), (da, db)
+
+
+# -- matrix-core operand panels (oracle/pack.py pack_mfma) ----------------------------------
+def test_pack_mfma_tiny_example_by_hand():
+    """A 2 x 5 left operand in one 16-row panel: four k values per block, so
+    K = 8; block 0 holds columns 0..3 at lanes i + 16*c, block 1 column 4 at
+    lanes 64 + i, everything else is zero."""
+    A = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 10], dtype=np.float32)   # 2 x 5, ld = 2
+    P = pack_oracle.pack_mfma(pack_oracle.ROWS, A, 2, 5, 2, 16)
+    want = np.zeros(16 * 8, dtype=np.float32)
+    for (i, c), pos in {(0, 0): 0, (1, 0): 1, (0, 1): 16, (1, 1): 17, (0, 2): 32, (1, 2): 33,
+                        (0, 3): 48, (1, 3): 49, (0, 4): 64, (1, 4): 65}.items():
+        want[pos] = A[i + 2 * c]
+    assert np.array_equal(P, want)
+    # the same matrix as a right operand (k = 2 rows, n = 5 columns) in 32-column
+    # panels: two k values per block, lane j + 32*r holds row r of column j
+    Q = pack_oracle.pack_mfma(pack_oracle.COLS, A, 2, 5, 2, 32)
+    want = np.zeros(32 * 2, dtype=np.float32)
+    for j in range(5):
+        for r in range(2):
+            want[j + 32 * r] = A[r + 2 * j]
+    assert np.array_equal(Q, want)
+
+
+def _pad_columns(A, rows, cols, ld, cols_to):
+    """The column-major matrix with zero columns appended up to cols_to (ld kept)."""
+    M = np.zeros(ld * cols_to, dtype=A.dtype)
+    M[:ld * (cols - 1) + rows] = A[:ld * (cols - 1) + rows]
+    return M
+
+
+def _pad_rows(A, rows, cols, ld, rows_to):
+    """The column-major matrix with zero rows appended up to rows_to (new ld = rows_to)."""
+    M = np.zeros(rows_to * cols, dtype=A.dtype)
+    for c in range(cols):
+        M[c * rows_to:c * rows_to + rows] = A[c * ld:c * ld + rows]
+    return M
+
+
+@pytest.mark.parametrize("panel", [16, 32, 64, 8])
+def test_pack_mfma_is_rows_and_columns_packing_of_the_k_padded_matrix(panel):
+    """The matrix-core layout is the Fig. 3 packing (pinned above) of the
+    matrix with k padded by zeros to whole blocks of 64/panel values."""
+    rng = np.random.default_rng(41)
+    kb = 64 // panel
+    for m, k, ld in [(37, 13, 40), (16, 8, 16), (5, 1, 7), (64, 30, 64), (1, 3, 1)]:
+        K = kb * -(-k // kb)
+        A = rng.standard_normal(ld * k).astype(np.float64)
+        P = pack_oracle.pack_mfma(pack_oracle.ROWS, A, m, k, ld, panel, alpha=1.5)
+        want = pack_oracle.pack(pack_oracle.ROWS, _pad_columns(A, m, k, ld, K), m, K, ld, panel, alpha=1.5)
+        assert np.array_equal(P, want), (m, k, ld)
+        # right operand: k rows, n columns
+        n, ldb = m, max(ld, k)
+        Y = rng.standard_normal(ldb * n).astype(np.float32)
+        Q = pack_oracle.pack_mfma(pack_oracle.COLS, Y, k, n, ldb, panel, alpha=-0.5)
+        want = pack_oracle.pack(pack_oracle.COLS, _pad_rows(Y, k, n, ldb, K), K, n, K, panel, alpha=-0.5)
+        assert np.array_equal(Q, want), (k, n, ldb)
+
+
+def _mfma_emulated(Pa, Pb, m, n, K, panel):
+    """C = A @ B from left and right operand panels, consumed as a 64-lane
+    matrix instruction reads them (the documented operand order of the
+    M x N x kb FP32/FP64 instructions with M = N = panel, kb = 64/panel:
+    lane l supplies A[l mod M][l div M] and B[l div N][l mod N] of the
+    instruction's block).  Written from that description, not from the
+    packing formula."""
+    kb = 64 // panel
+    mp, nq = -(-m // panel), -(-n // panel)
+    C = np.zeros((mp * panel, nq * panel), dtype=np.float64)
+    for p in range(mp):
+        for q in range(nq):
+            acc = np.zeros((panel, panel))
+            for b in range(K // kb):
+                a_regs = Pa[p * panel * K + 64 * b:p * panel * K + 64 * b + 64]
+                b_regs = Pb[q * panel * K + 64 * b:q * panel * K + 64 * b + 64]
+                Ablk = np.zeros((panel, kb))
+                Bblk = np.zeros((kb, panel))
+                for lane in range(64):
+                    Ablk[lane % panel, lane // panel] = a_regs[lane]
+                    Bblk[lane // panel, lane % panel] = b_regs[lane]
+                acc += Ablk @ Bblk
+            C[p * panel:(p + 1) * panel, q * panel:(q + 1) * panel] = acc
+    return C[:m, :n]
+
+
+@pytest.mark.parametrize("panel", [16, 32])
+def test_pack_mfma_feeds_the_matrix_instruction(panel):
+    """Integer matrices: the panels read in the instruction's lane order give
+    A @ B exactly, with ragged panels and a k that is not a whole block."""
+    rng = np.random.default_rng(43)
+    for m, n, k, lda, ldb in [(37, 21, 13, 40, 15), (16, 16, 4, 16, 4), (50, 3, 7, 50, 9)]:
+        A = rng.integers(-8, 9, size=lda * k).astype(np.float64)
+        B = rng.integers(-8, 9, size=ldb * n).astype(np.float64)
+        kb = 64 // panel
+        K = kb * -(-k // kb)
+        Pa = pack_oracle.pack_mfma(pack_oracle.ROWS, A, m, k, lda, panel)
+        Pb = pack_oracle.pack_mfma(pack_oracle.COLS, B, k, n, ldb, panel)
+        Am = A.reshape(k, lda).T[:m, :k]
+        Bm = B.reshape(n, ldb).T[:k, :n]
+        assert np.array_equal(_mfma_emulated(Pa, Pb, m, n, K, panel), Am @ Bm), (m, n, k)
+        # a transposed operand order (lane l holding element (l div kb, l mod kb))
+        # would not: check that the emulator tells the two apart
+        if m >= panel and k >= kb and (m, k) != (kb, panel):
+            bad = Pa.copy()
+            blk = bad[:64].reshape(panel, kb).T.reshape(-1)   # swap the roles of lane bits
+            bad[:64] = blk
+            assert not np.array_equal(_mfma_emulated(bad, Pb, m, n, K, panel), Am @ Bm)
+
+
+def test_pack_mfma_empty_and_argument_errors():
+    A = np.zeros(4, dtype=np.float32)
+    assert pack_oracle.pack_mfma(pack_oracle.ROWS, A, 0, 4, 1, 16).size == 0
+    assert pack_oracle.pack_mfma(pack_oracle.COLS, A, 0, 3, 1, 16).size == 0
+    with pytest.raises(ValueError):
+        pack_oracle.pack_mfma(pack_oracle.ROWS, A, 2, 2, 2, 12)
