@@ -376,12 +376,22 @@ ttx_status ttx_tune_db_detach(void);
  *     panel p holds rows of nr contiguous elements,
  *     P[j + r*nr + p*nr*rows] = alpha * A[r + (p*nr + j)*ld] (the view
  *     (rows, nr, cols/nr) with perm (1,0,2)).
+ *   TTX_PACK_MFMA_A / TTX_PACK_MFMA_B: matrix-core operand panels, the two
+ *     layouts above with the k extent of every panel (cols for _A, rows for
+ *     _B) padded with zeros to K = a multiple of kb = 64 / panel (panel must
+ *     divide 64): P[l + 64*b + p*panel*K] holds element (l mod panel, b*kb +
+ *     l div panel) of panel p -- the operand of the b-th 64-lane matrix
+ *     instruction of shape panel x panel x kb, lane l's register (16 x 16 x 4
+ *     for FP32 and FP64, 32 x 32 x 2 for FP32; ttx_gemm_panels reads them).
  * A ragged last panel is padded with zeros; P holds ceil(extent/panel) *
- * panel * other elements.  A and P are device pointers aligned to their
+ * panel * other elements (other rounded up to K for the matrix-core kinds).
+ * A and P are device pointers aligned to their
  * element sizes whose byte ranges must not overlap (TTX_EOVERLAP).  Plans
  * are cached per (dtype, kind, rows, cols, ld, panel); the transpositions
  * use the tune table (ttx_pack_tune fills it).  Asynchronous on `stream`. */
-typedef enum ttx_pack_kind { TTX_PACK_ROWS = 0, TTX_PACK_COLS = 1 } ttx_pack_kind;
+typedef enum ttx_pack_kind {
+    TTX_PACK_ROWS = 0, TTX_PACK_COLS = 1, TTX_PACK_MFMA_A = 2, TTX_PACK_MFMA_B = 3
+} ttx_pack_kind;
 
 ttx_status ttx_pack(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64_t ld, int64_t panel,
                     const double *alpha, const void *A, void *P, hipStream_t stream);
@@ -393,6 +403,23 @@ ttx_status ttx_pack_tune(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, 
 ttx_status ttx_pack_describe(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64_t ld,
                              int64_t panel, int64_t *packed_elements, int *transpositions,
                              ttx_config *configs);
+/* C = A * B from matrix-core operand panels: Pa holds the m x k left operand
+ * packed with TTX_PACK_MFMA_A, Pb the k x n right operand packed with
+ * TTX_PACK_MFMA_B, both with the same `panel`; C is a column-major m x n
+ * matrix with leading dimension ldc >= m, overwritten.  The consumer of the
+ * packed operands that Sec. 2.1 (Fig. 3) prepares, and the contraction step
+ * of a transpose-transpose-GEMM-transpose tensor contraction (Sec. 4): each
+ * wave computes a panel x panel block with the gfx950 matrix instructions
+ * (16 x 16 x 4 FP32 or FP64 for panel 16, 32 x 32 x 2 FP32 for panel 32),
+ * reading each instruction's operands as 64 consecutive panel elements.
+ * dtype TTX_F32 (panel 16 or 32) or TTX_F64 (panel 16), else
+ * TTX_EUNSUPPORTED.  The products are summed by the matrix cores in the
+ * element type (the summation order is the hardware's: results equal a
+ * reference GEMM exactly only where no rounding occurs, e.g. small
+ * integers).  Device pointers aligned to the element size; asynchronous on
+ * `stream`. */
+ttx_status ttx_gemm_panels(ttx_dtype dtype, int panel, int64_t m, int64_t n, int64_t k, const void *Pa,
+                           const void *Pb, void *C, int64_t ldc, hipStream_t stream);
 
 /* -- batched execution ----------------------------------------------------------
  * Many independent transpositions, each Eqn. 1 with its own dtype, shape,
@@ -445,9 +472,11 @@ typedef struct ttx_batch ttx_batch;
  * device memory; the caller owns every A and B).  Every problem is checked
  * as ttx_transpose would check it; the first failure is returned. */
 ttx_status ttx_batch_create(ttx_batch **batch, int count, const ttx_problem *problems);
-/* Times up to max_candidates batched-menu configs per distinct shape (0:
- * 16) inside the persistent kernel on scratch buffers, keeps the fastest in
- * a process-wide per-shape table and rebuilds the descriptors.  Blocks. */
+/* Times the current config and up to max_candidates batched-menu configs
+ * per distinct shape (0: 16) inside the persistent kernel on scratch
+ * buffers, one problem at a time; another config replaces the current one
+ * only when it is at least 5% faster.  Winners go into a process-wide
+ * per-shape table; the descriptors are rebuilt.  Blocks. */
 ttx_status ttx_batch_tune(ttx_batch *batch, int max_candidates, int reps);
 /* One graph launch of the persistent kernel on `stream` (captured on first use).
  * Launches of one batch must not overlap each other (they share the batch's

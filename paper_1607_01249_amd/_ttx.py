@@ -30,7 +30,7 @@ OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = rang
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
 CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE, CFG_WIDE, CFG_GROUPED = 1, 2, 4, 8, 16
-PACK_ROWS, PACK_COLS = 0, 1
+PACK_ROWS, PACK_COLS, PACK_MFMA_A, PACK_MFMA_B = 0, 1, 2, 3
 DENSE_CAP = {F32: 1024, F64: 1024, C32: 1024, C64: 512}
 DENSE_CAP.update({code: DENSE_CAP[b] for code, (a, b) in TYPES_OF.items() if a != b})
 
@@ -230,6 +230,7 @@ def _declare(L):
         "ttx_server_destroy": ([vp], S),
         "ttx_replay_sequential": ([i64, vp, i64p, vp, i64, vp, ctypes.POINTER(ctypes.c_double)], S),
         "ttx_pack": ([S, S, i64, i64, i64, i64, dp, vp, vp, vp], S),
+        "ttx_gemm_panels": ([S, S, i64, i64, i64, vp, vp, vp, i64, vp], S),
         "ttx_pack_tune": ([S, S, i64, i64, i64, i64, S, S], S),
         "ttx_pack_describe": ([S, S, i64, i64, i64, i64, i64p, ip, ctypes.POINTER(Config)], S),
         "ttx_copy_kernel": ([vp, vp, i64, vp], S),
@@ -564,6 +565,11 @@ def ttx_server_destroy(server):
 
 def ttx_copy_kernel(src, dst, nbytes, stream=0):
     return _check(lib().ttx_copy_kernel(src, dst, int(nbytes), stream))
+
+
+def ttx_gemm_panels(dtype, panel, m, n, k, Pa, Pb, C, ldc, stream=0):
+    """C (m x n, column-major, ldc) = A * B from matrix-core operand panels."""
+    return _check(lib().ttx_gemm_panels(dtype, int(panel), int(m), int(n), int(k), Pa, Pb, C, int(ldc), stream))
 
 
 def ttx_pack(dtype, kind, rows, cols, ld, panel, alpha, A, P, stream=0):

@@ -683,6 +683,10 @@ ttx_status ttx_batch_update(ttx_batch* b, int count, const ttx_problem* problems
     return upload(b, stream);
 }
 
+// A tuned batched configuration replaces the current one only when it is
+// faster by at least this fraction.
+static constexpr double kBatchTuneMargin = 0.05;
+
 ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
     if (max_candidates == 0) max_candidates = 16;
@@ -726,14 +730,19 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
                 continue;
             }
         }
-        int nc = batch_candidates(p, max_candidates, cands.data(), int(cands.size()));
+        // candidate 0: the configuration the batch runs now (the heuristic
+        // choice), then the ranked batched-menu candidates
+        cands[0] = b->cfg[i];
+        int nc = batch_candidates(p, max_candidates, cands.data() + 1, int(cands.size()) - 1);
         if (nc <= 0) continue;
+        ++nc;
         // scratch pointers keep the real pointers' offsets modulo 16 bytes, so
         // that each candidate runs the same vector variant it will run for real
         const uintptr_t offa = reinterpret_cast<uintptr_t>(q.A) & 15;
         const uintptr_t offb = reinterpret_cast<uintptr_t>(q.B) & 15;
         int best_i = -1;
         double best_us = 0;
+        std::vector<double> us(nc, 0.0);
         result = time_candidates(p, beta0, nc, reps,
             [&](int c, const void* A, void* B, hipStream_t s) -> hipError_t {
                 BatchDesc one;
@@ -750,8 +759,11 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
                 if (e != hipSuccess) return e;
                 return launch_batch(d_one, d_pre, 1, chunks, grid, d_cnt, s);
             },
-            &best_i, &best_us);
-        if (result == TTX_OK && best_i >= 0) {
+            &best_i, &best_us, us.data());
+        // another configuration only when it is clearly faster than the
+        // current one (timing one problem alone ranks close candidates
+        // differently from the full batch)
+        if (result == TTX_OK && best_i > 0 && best_us < us[0] * (1.0 - kBatchTuneMargin)) {
             b->cfg[i] = cands[best_i];
             b->forced[i] = 1;
             std::lock_guard<std::mutex> lock(g_btab_mu);

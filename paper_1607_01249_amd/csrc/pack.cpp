@@ -15,6 +15,15 @@
 //
 // The whole panels are one transposition; a ragged last panel is a second,
 // two-index one, and the rest of that panel is set to zero.
+//
+// Matrix-core operand panels (TTX_PACK_MFMA_A / _B) are the same two
+// layouts with the k extent of every panel padded with zeros to a multiple
+// of kb = 64 / panel: a 64-lane matrix instruction with M (or N) = panel
+// takes kb values of k per instruction, lane l holding element
+// (l mod panel, l div panel) of the block, so with the panel stride
+// panel*K (K = k rounded up to kb) each instruction's operand is 64
+// consecutive elements in lane order.  The k padding is one more zero
+// region: the last (K - k) * panel elements of every panel.
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -33,6 +42,8 @@ struct PackPlan {
     int64_t p_off[2] = {0, 0};
     int64_t pad_off = 0;          // zero region of the last panel (elements of P)
     int64_t pad_width = 0, pad_height = 0, pad_pitch = 0;
+    int64_t kpad_off = 0;         // matrix-core panels: the k padding of every panel
+    int64_t kpad_width = 0, kpad_height = 0, kpad_pitch = 0;
     int64_t a_extent = 0, p_extent = 0;   // bytes
     int elem_p = 0;
     uint64_t table_gen = 0;
@@ -41,21 +52,34 @@ struct PackPlan {
 static ttx_status make_pack_plan(int dtype, int kind, int64_t rows, int64_t cols, int64_t ld, int64_t panel,
                                  PackPlan* pl) {
     if (!dtype_valid(dtype)) return fail(TTX_EINVAL, "unknown dtype");
-    if (kind != TTX_PACK_ROWS && kind != TTX_PACK_COLS) return fail(TTX_EINVAL, "unknown packing kind");
+    if (kind != TTX_PACK_ROWS && kind != TTX_PACK_COLS && kind != TTX_PACK_MFMA_A && kind != TTX_PACK_MFMA_B)
+        return fail(TTX_EINVAL, "unknown packing kind");
     if (rows < 0 || cols < 0 || panel < 1) return fail(TTX_EINVAL, "negative extent or panel < 1");
     if (ld < rows || ld < 1) return fail(TTX_EINVAL, "ld smaller than the row count");
+    const bool mfma = kind == TTX_PACK_MFMA_A || kind == TTX_PACK_MFMA_B;
+    if (mfma && (panel > 64 || 64 % panel)) return fail(TTX_EINVAL, "matrix-core panels must divide 64");
+    if (kind == TTX_PACK_MFMA_A) kind = TTX_PACK_ROWS;   // the same layouts, k padded below
+    if (kind == TTX_PACK_MFMA_B) kind = TTX_PACK_COLS;
     *pl = PackPlan();
     pl->elem_p = elem_bytes(dtype_b_of(dtype));
     const int64_t ea = elem_bytes(dtype_a_of(dtype));
     const int64_t split = kind == TTX_PACK_ROWS ? rows : cols;   // the extent cut into panels
-    const int64_t other = kind == TTX_PACK_ROWS ? cols : rows;
+    const int64_t other = kind == TTX_PACK_ROWS ? cols : rows;   // k
     if (split == 0 || other == 0) return TTX_OK;
     const int64_t np = (split + panel - 1) / panel, full = split / panel, tail = split % panel;
+    const int64_t kb = mfma ? 64 / panel : 1;
+    const int64_t K = (other + kb - 1) / kb * kb;   // k of a stored panel
     int64_t tmp;
-    if (__builtin_mul_overflow(np * panel, other, &tmp) || __builtin_mul_overflow(ld, cols, &tmp))
+    if (__builtin_mul_overflow(np * panel, K, &tmp) || __builtin_mul_overflow(ld, cols, &tmp))
         return fail(TTX_EINVAL, "sizes overflow");
     pl->a_extent = ((cols - 1) * ld + rows) * ea;
-    pl->p_extent = np * panel * other * pl->elem_p;
+    pl->p_extent = np * panel * K * pl->elem_p;
+    if (K > other) {   // the k padding of every panel: its last (K - k) * panel elements
+        pl->kpad_off = other * panel;
+        pl->kpad_width = (K - other) * panel;
+        pl->kpad_height = np;
+        pl->kpad_pitch = panel * K;
+    }
     auto add = [&](int n, const int* perm, const int64_t* size, const int64_t* sa, const int64_t* sb,
                    int64_t a_off, int64_t p_off) -> ttx_status {
         Problem& p = pl->prob[pl->parts];
@@ -70,16 +94,16 @@ static ttx_status make_pack_plan(int dtype, int kind, int64_t rows, int64_t cols
         const int64_t k = cols, mr = panel;
         if (full > 0) {
             const int perm[3] = {0, 2, 1};
-            const int64_t size[3] = {mr, full, k}, sa[3] = {1, mr, ld}, sb[3] = {1, mr * k, mr};
+            const int64_t size[3] = {mr, full, k}, sa[3] = {1, mr, ld}, sb[3] = {1, mr * K, mr};
             ttx_status st = add(3, perm, size, sa, sb, 0, 0);
             if (st != TTX_OK) return st;
         }
         if (tail > 0) {
             const int perm[2] = {0, 1};
             const int64_t size[2] = {tail, k}, sa[2] = {1, ld}, sb[2] = {1, mr};
-            ttx_status st = add(2, perm, size, sa, sb, full * mr, full * mr * k);
+            ttx_status st = add(2, perm, size, sa, sb, full * mr, full * mr * K);
             if (st != TTX_OK) return st;
-            pl->pad_off = full * mr * k + tail;
+            pl->pad_off = full * mr * K + tail;
             pl->pad_width = mr - tail;
             pl->pad_height = k;
             pl->pad_pitch = mr;
@@ -88,16 +112,16 @@ static ttx_status make_pack_plan(int dtype, int kind, int64_t rows, int64_t cols
         const int64_t k = rows, nr = panel;
         if (full > 0) {
             const int perm[3] = {1, 0, 2};
-            const int64_t size[3] = {k, nr, full}, sa[3] = {1, ld, ld * nr}, sb[3] = {nr, 1, nr * k};
+            const int64_t size[3] = {k, nr, full}, sa[3] = {1, ld, ld * nr}, sb[3] = {nr, 1, nr * K};
             ttx_status st = add(3, perm, size, sa, sb, 0, 0);
             if (st != TTX_OK) return st;
         }
         if (tail > 0) {
             const int perm[2] = {1, 0};
             const int64_t size[2] = {k, tail}, sa[2] = {1, ld}, sb[2] = {nr, 1};
-            ttx_status st = add(2, perm, size, sa, sb, full * nr * ld, full * nr * k);
+            ttx_status st = add(2, perm, size, sa, sb, full * nr * ld, full * nr * K);
             if (st != TTX_OK) return st;
-            pl->pad_off = full * nr * k + tail;
+            pl->pad_off = full * nr * K + tail;
             pl->pad_width = nr - tail;
             pl->pad_height = k;
             pl->pad_pitch = nr;
@@ -166,6 +190,12 @@ ttx_status ttx_pack(ttx_dtype dtype, int kind, int64_t rows, int64_t cols, int64
         hipError_t e = launch_fill_zero(static_cast<char*>(P) + pl->pad_off * pl->elem_p,
                                         pl->pad_width * pl->elem_p, pl->pad_height,
                                         pl->pad_pitch * pl->elem_p, stream);
+        if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    if (pl->kpad_width > 0) {
+        hipError_t e = launch_fill_zero(static_cast<char*>(P) + pl->kpad_off * pl->elem_p,
+                                        pl->kpad_width * pl->elem_p, pl->kpad_height,
+                                        pl->kpad_pitch * pl->elem_p, stream);
         if (e != hipSuccess) return fail(TTX_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     }
     return TTX_OK;

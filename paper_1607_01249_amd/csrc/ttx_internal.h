@@ -182,6 +182,10 @@ constexpr uint32_t kGroupedSteps = 8;
 // *w and returns true when there is one.
 bool widen(const Problem& p, Problem* w);
 
+// The matrix-core GEMM over packed panels (gemm.hip).
+hipError_t launch_gemm_panels(int dtype, int panel, int64_t m, int64_t n, int64_t k, const void* Pa,
+                              const void* Pb, void* C, int64_t ldc, hipStream_t stream);
+
 // Launchers (kernels.hip).  They return hipSuccess or the launch error.
 hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const void* A,
                         const void* Bsrc, void* Bdst, const Scalar& alpha, const Scalar& beta,

@@ -596,7 +596,9 @@ def test_pack_describe_splits_whole_and_ragged_panels():
 
 def test_pack_argument_errors_need_no_gpu():
     big = 1 << 40
-    for args, status in [((ttx.F32, 2, 4, 4, 4, 2), ttx.EINVAL),       # unknown kind
+    for args, status in [((ttx.F32, 4, 4, 4, 4, 2), ttx.EINVAL),       # unknown kind
+                         ((ttx.F32, ttx.PACK_MFMA_A, 4, 4, 4, 12), ttx.EINVAL),   # panel not dividing 64
+                         ((ttx.F32, ttx.PACK_MFMA_B, 4, 4, 4, 128), ttx.EINVAL),
                          ((ttx.F32, 0, 4, 4, 3, 2), ttx.EINVAL),       # ld < rows
                          ((ttx.F32, 0, 4, 4, 4, 0), ttx.EINVAL),       # panel < 1
                          ((8, 0, 4, 4, 4, 2), ttx.EINVAL)]:            # unknown dtype
@@ -609,6 +611,26 @@ def test_pack_argument_errors_need_no_gpu():
     with pytest.raises(ttx.TTXError) as e:   # complex scale for real panels
         ttx.ttx_pack(ttx.F32, 0, 4, 4, 4, 2, 1j, big, big + 4096)
     assert e.value.status == ttx.EINVAL
+
+
+def test_mfma_pack_describe_and_gemm_argument_errors_need_no_gpu():
+    """Matrix-core panels hold ceil(extent/panel)*panel*K elements, K = k
+    rounded up to whole blocks of 64/panel; the GEMM refuses unsupported
+    (dtype, panel) pairs and bad extents before any launch."""
+    for kind, rows, cols, panel, want in [(ttx.PACK_MFMA_A, 37, 13, 16, 48 * 16), (ttx.PACK_MFMA_B, 13, 37, 16, 48 * 16),
+                                          (ttx.PACK_MFMA_A, 100, 7, 32, 128 * 8), (ttx.PACK_MFMA_A, 64, 8, 16, 64 * 8),
+                                          (ttx.PACK_ROWS, 37, 13, 16, 48 * 13)]:
+        n, parts = ttx.ttx_pack_describe(ttx.F32, kind, rows, cols, rows, panel)
+        assert n == want, (kind, rows, cols, panel)
+    big = 1 << 40
+    for args in [(ttx.F64, 32, 4, 4, 4), (ttx.C32, 16, 4, 4, 4), (ttx.F32, 8, 4, 4, 4)]:
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_gemm_panels(*args, big, big + 4096, big + 8192, 4)
+        assert e.value.status == ttx.EUNSUPPORTED, args
+    for args in [(ttx.F32, 16, -1, 4, 4, 4), (ttx.F32, 16, 8, 4, 4, 4), (ttx.F32, 16, 4, 4, -2, 4)]:
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_gemm_panels(*args[:5], big, big + 4096, big + 8192, args[5])
+        assert e.value.status == ttx.EINVAL, args
 
 
 # -- the tune table as a database shared across processes ------------------------------------

@@ -129,7 +129,10 @@ def test_batched_tuned_is_bitwise_the_same(batch512):
     try:
         ttx.ttx_batch_tune(h, 4, 2)
         info = ttx.ttx_batch_get_info(h)
-        assert info["tuned"] > 0
+        # problems whose config the tuner replaced (only where a candidate
+        # was clearly faster); every problem must compute the same bits
+        _say("batch tuning replaced %d of 48 configs" % info["tuned"])
+        assert 0 <= info["tuned"] <= 48
         sub.reset_b()
         ttx.ttx_batch_execute(h, ttx.current_stream())
         got = sub.results()

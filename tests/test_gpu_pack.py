@@ -83,3 +83,67 @@ def test_pack_tune_then_pack():
     want = pack_oracle.pack(ttx.PACK_ROWS, A, 1000, 64, 1000, 16)
     got = _gpu_pack(ttx.PACK_ROWS, A, 1000, 64, 1000, 16, 1.0, F32)
     assert_parity(got, want, exact=True)
+
+
+# -- matrix-core operand panels and the GEMM that reads them ------------------------------
+def _gpu_pack_mfma(kind, A, rows, cols, ld, panel, alpha, out_dtype):
+    split, k = (rows, cols) if kind == ttx.PACK_MFMA_A else (cols, rows)
+    kb = 64 // panel
+    n_out = -(-split // panel) * panel * (kb * -(-k // kb))
+    dA, pa = to_device(A)
+    dP, pp = to_device(np.full(n_out, np.nan, dtype=out_dtype))
+    ttx.ttx_pack(dtype_code(A.dtype, out_dtype), kind, rows, cols, ld, panel, alpha, pa, pp, ttx.current_stream())
+    out = from_device(dP)
+    del dA, dP
+    return out
+
+
+MFMA_SHAPES = [  # rows, cols, ld, panel: ragged panels, k not a whole block, ld > rows
+    (37, 13, 40, 16), (64, 32, 64, 16), (5, 3, 9, 16), (100, 7, 101, 32), (33, 66, 33, 32), (16, 1, 16, 64),
+    (3, 300, 3, 8)]
+
+
+@pytest.mark.parametrize("kind", [ttx.PACK_MFMA_A, ttx.PACK_MFMA_B], ids=["left", "right"])
+@pytest.mark.parametrize("types", [(F32, F32), (F64, F64), (F32, F64), (C64, C64)], ids=["s", "d", "sd", "z"])
+def test_mfma_panels_match_oracle(kind, types):
+    """The matrix-core layout (k padded with zeros to whole blocks) element
+    by element against the pinned oracle, with every padding position
+    overwritten (the output starts as NaN)."""
+    da, db = types
+    okind = pack_oracle.ROWS if kind == ttx.PACK_MFMA_A else pack_oracle.COLS
+    alpha = complex(0.75, -1.25) if db in (C32, C64) else 1.3
+    for rows, cols, ld, panel in MFMA_SHAPES:
+        A = workloads.uniform(ld * cols, da, seed=rows + 7 * cols)
+        want = pack_oracle.pack_mfma(okind, A, rows, cols, ld, panel, alpha=alpha, out_dtype=db)
+        got = _gpu_pack_mfma(kind, A, rows, cols, ld, panel, alpha, db)
+        assert_parity(got, want, exact=False, what=(rows, cols, ld, panel))
+        want1 = pack_oracle.pack_mfma(okind, A, rows, cols, ld, panel, out_dtype=db)
+        assert_parity(_gpu_pack_mfma(kind, A, rows, cols, ld, panel, 1.0, db), want1, exact=True)
+
+
+@pytest.mark.parametrize("dtype,panel", [(F32, 16), (F32, 32), (F64, 16)])
+def test_gemm_reads_mfma_panels_directly(dtype, panel):
+    """Packed panels go to the matrix-core GEMM as they are (no transposition
+    in between): integer-valued A and B give C = A @ B exactly, with ragged
+    panels, a k that is not a whole block and ldc > m; C outside m x n is
+    not touched."""
+    import torch
+    rng = np.random.default_rng(17 + panel)
+    for m, n, k, lda, ldb, ldc in [(200, 72, 96, 203, 100, 210), (37, 21, 13, 40, 15, 37), (1, 1, 1, 1, 1, 1),
+                                   (64, 96, 130, 64, 131, 70)]:
+        A = rng.integers(-8, 9, size=lda * k).astype(dtype)
+        B = rng.integers(-8, 9, size=ldb * n).astype(dtype)
+        Am = A.reshape(k, lda).T[:m].astype(np.float64)
+        Bm = B.reshape(n, ldb).T[:k].astype(np.float64)
+        PA = _gpu_pack_mfma(ttx.PACK_MFMA_A, A, m, k, lda, panel, 1.0, dtype)
+        PB = _gpu_pack_mfma(ttx.PACK_MFMA_B, B, k, n, ldb, panel, 1.0, dtype)
+        dA = torch.from_numpy(PA).cuda()
+        dB = torch.from_numpy(PB).cuda()
+        dC = torch.full((ldc * n,), 7.0, dtype=dA.dtype, device="cuda")
+        ttx.ttx_gemm_panels(dtype_code(dtype), panel, m, n, k, dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), ldc,
+                            ttx.current_stream())
+        torch.cuda.synchronize()
+        C = dC.cpu().numpy().reshape(n, ldc).T
+        assert np.array_equal(C[:m].astype(np.float64), Am @ Bm), (m, n, k)
+        assert (C[m:] == 7.0).all()
+
