@@ -255,6 +255,103 @@ def test_served_results_equal_alone_and_oracle():
         ttx.ttx_server_destroy(s)
 
 
+def test_served_large_multid_requests_equal_alone_and_oracle():
+    """The served workload's large requests at their real size (64..256 MiB,
+    N in 3..6, multi-dimensional shapes as drawn) among small ones, replayed
+    at 20K requests/s: every large result and every 17th small one is
+    compared bitwise with the same request run alone through ttx_transpose,
+    and the alone result with the oracle (the first mismatch fails)."""
+    import torch
+    from gpu_util import dev_copy
+    times, shapes = workloads.served_trace(rate=20000.0, duration=0.02, seed_arrivals=31, seed_shapes=32,
+                                           large_frac=0.02, large_bytes=(64 << 20, 256 << 20))
+    large = [i for i, r in enumerate(shapes) if r["large"]]
+    assert len(large) >= 4, "trace holds %d large requests" % len(large)
+    large = large[:6]
+    small = [i for i, r in enumerate(shapes) if not r["large"]][:120]
+    keep = sorted(large + small)
+    rng = np.random.default_rng(33)
+    pool_bytes = 64 << 20
+    host_pool = workloads.uniform(pool_bytes // 4, F32, 34)
+    pool = torch.from_numpy(host_pool).cuda()
+    raw = host_pool.view(np.uint8)
+    half = pool_bytes // 2
+    n = len(keep)
+    reqs = ttx._ttx.request_array(n)
+    meta, owned = [], []
+    for slot, i in enumerate(keep):
+        r = shapes[i]
+        es = r["dtype"].itemsize
+        ne = workloads.elements(r["size"])
+        nbytes = ne * es
+        if r["large"]:   # inputs of their own, kept on the host for the checks
+            a_host = workloads.uniform(ne, r["dtype"], 1000 + i)
+            b_host = workloads.uniform(ne, r["dtype"], 2000 + i)
+            dA = torch.from_numpy(a_host).cuda()
+            dB = torch.from_numpy(b_host).cuda()
+            owned.append((dA, dB))
+            ptr_a, ptr_b = dA.data_ptr(), dB.data_ptr()
+        else:
+            if nbytes > half // 2:
+                r = dict(r, size=(half // 2 // es,), perm=(0,))
+                ne = workloads.elements(r["size"])
+                nbytes = ne * es
+            off_a = int(rng.integers(0, (half - nbytes) // 256 + 1)) * 256
+            off_b = half + int(rng.integers(0, (half - nbytes) // 256 + 1)) * 256
+            a_host = raw[off_a:off_a + nbytes].view(r["dtype"]).copy()
+            b_host = raw[off_b:off_b + nbytes].view(r["dtype"]).copy()
+            ptr_a, ptr_b = pool.data_ptr() + off_a, pool.data_ptr() + off_b
+        k = len(r["perm"])
+        reqs[slot]["dtype"] = ttx.F32 if es == 4 else ttx.F64
+        reqs[slot]["n"] = k
+        reqs[slot]["perm"][:k] = r["perm"]
+        reqs[slot]["size"][:k] = r["size"]
+        reqs[slot]["alpha"] = r["alpha"]
+        reqs[slot]["beta"] = r["beta"]
+        reqs[slot]["A"] = ptr_a
+        reqs[slot]["B_in"] = ptr_b
+        check = r["large"] or slot % 17 == 0
+        reqs[slot]["keep_result"] = 1 if check else 0
+        meta.append((r, ptr_a, ptr_b, nbytes, a_host if check else None, b_host if check else None))
+    torch.cuda.synchronize()
+    _say("served with large requests: %d requests, large %s" %
+         (n, [(shapes[i]["size"], shapes[i]["perm"], shapes[i]["dtype"].name) for i in large]))
+    offsets = (np.asarray([times[i] for i in keep]) * 1e9).astype(np.int64)
+    s = ttx.ttx_server_create(slots=4)
+    try:
+        tickets = ttx.ttx_server_replay(s, reqs, offsets)
+        ttx.ttx_server_drain(s)
+        st = ttx.ttx_server_get_stats(s)
+        assert st["completed"] == n and st["rejected"] == 0
+        stream = ttx.current_stream()
+        checked_large = 0
+        for slot in range(n):
+            if not reqs[slot]["keep_result"]:
+                continue
+            r, ptr_a, ptr_b, nbytes, a_host, b_host = meta[slot]
+            ptr, lat = ttx.ttx_server_result(s, int(tickets[slot]))
+            ne = workloads.elements(r["size"])
+            served = torch.empty(ne, dtype=_tdt(r["dtype"]), device="cuda")
+            dev_copy(served.data_ptr(), ptr, nbytes)
+            alone = torch.from_numpy(b_host).cuda()
+            ttx.ttx_transpose(ttx.F32 if r["dtype"].itemsize == 4 else ttx.F64, len(r["perm"]), r["perm"],
+                              r["size"], None, None, r["alpha"], ptr_a, r["beta"], alone.data_ptr(), stream)
+            torch.cuda.synchronize()
+            got_alone = alone.cpu().numpy()
+            assert np.array_equal(served.cpu().numpy().view(np.uint8), got_alone.view(np.uint8)), \
+                ("served differs from alone", slot, r["size"], r["perm"])
+            ref = b_host.copy()
+            assert oracle.transpose(r["perm"], r["size"], r["alpha"], a_host, r["beta"], ref) == 0
+            assert_parity(got_alone, ref, exact=False, what=(slot, r["size"], r["perm"]))
+            ttx.ttx_server_release(s, int(tickets[slot]))
+            checked_large += int(r["large"])
+            del served, alone
+        assert checked_large == len(large)
+        assert ttx.ttx_server_get_stats(s)["in_use_bytes"] == 0
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
 # -- complex and mixed-precision problems in batches and in the server ----------------------
 def _typed_problems():
     """(code, A dtype, B dtype, perm, size, alpha, beta) for a mixed list."""
