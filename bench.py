@@ -102,6 +102,10 @@ def parse_args():
                          "script into profiles/traffic_counters.json and exit")
     ap.add_argument("--traffic-out", default=None,
                     help="where --traffic-from writes (default profiles/traffic_counters.json)")
+    ap.add_argument("--summarize-counters", metavar="DB",
+                    help="print a markdown table of the SQ counters (waves, LDS instructions, LDS bank "
+                         "conflict cycles) and the register, LDS and scratch budgets of each ttx kernel "
+                         "in a rocprofv3 --pmc database, and exit")
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="print the kernel statistics of a rocprofv3 --kernel-trace --stats run")
     return ap.parse_args()
@@ -371,6 +375,36 @@ def traffic_from(fetch_path, write_path, out_path=None):
     with open(out_path or TRAFFIC, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     print(json.dumps(out, sort_keys=True))
+
+
+def summarize_counters(path):
+    """Per ttx kernel of a rocprofv3 --pmc database: the mean of each SQ counter
+    per dispatch, LDS bank-conflict cycles per LDS instruction, and the
+    kernel's VGPRs, LDS bytes and scratch bytes per lane with the waves per
+    SIMD they allow (512 VGPRs per SIMD lane, 160 KiB of LDS per CU, 4 SIMDs
+    and at most 8 waves each)."""
+    counters, budget = {}, {}
+    for db in _rocpd(path):
+        for name, cname, val in db.execute("select name, counter_name, counter_value from pmc_events"):
+            k = _short_kernel(name) if "ttx::" in name else name
+            if k.startswith(("ttx_jit_", "k_")):
+                counters.setdefault(k, {}).setdefault(cname, []).append(float(val))
+        for name, vgpr, lds, priv in db.execute(
+                "select kernel_name, arch_vgpr_count, group_segment_size, private_segment_size from kernel_symbols"):
+            name = name[:-3] if name.endswith(".kd") else name   # the kernel descriptor's symbol
+            k = _short_kernel(name) if "ttx::" in name else name
+            budget[k] = (int(vgpr), int(lds), int(priv))
+    names = sorted({c for v in counters.values() for c in v})
+    lines = ["| kernel | " + " | ".join(names) + " | conflict cycles / LDS instr | VGPRs | LDS B | scratch B/lane |"
+             " waves/SIMD (VGPR) |", "|---|" + "---|" * (len(names) + 5)]
+    for k in sorted(counters):
+        mean = {c: float(np.mean(v)) for c, v in counters[k].items()}
+        ratio = (mean.get("SQ_LDS_BANK_CONFLICT", 0.0) / mean["SQ_INSTS_LDS"]) if mean.get("SQ_INSTS_LDS") else 0.0
+        vgpr, lds, priv = budget.get(k, (0, 0, 0))
+        waves = min(8, 512 // max(8, -(-vgpr // 8) * 8)) if vgpr else 0
+        lines.append("| %s | %s | %.2f | %d | %d | %d | %d |" % (
+            k, " | ".join("%.0f" % mean.get(c, float("nan")) for c in names), ratio, vgpr, lds, priv, waves))
+    print("\n".join(lines))
 
 
 def summarize_trace(path, top=25):
@@ -910,6 +944,9 @@ def main():
     if args.traffic_from:
         traffic_from(*args.traffic_from, out_path=args.traffic_out)
         return 0
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
         return 0
