@@ -120,6 +120,12 @@ typedef enum ttx_family {
 #define TTX_CFG_GROUPED 16     /* tile ids walk groups of 8 steps of the fastest grid index
                                   across the whole second one (in each plane of the two), so
                                   the tiles in flight together are neighbours along both */
+#define TTX_CFG_ALIGN_A 32     /* MOVED menu tiles over a contiguous A run (stride 1): each
+                                  tile's range along A's stride-1 index starts on a 128-byte
+                                  line of A in the row of its first B-side index (one more
+                                  tile along that index covers the shift), so runs whose
+                                  length is not a multiple of the line cost whole lines;
+                                  runs as a size-specialised kernel */
 
 /* One implementation candidate (Sec. 2.2: blocking and loop order).
  *   tile_a  : tile extent along A's stride-1 index (merged index 0);
@@ -332,8 +338,10 @@ ttx_status ttx_tune_candidates(ttx_dtype dtype, int n, const int *perm, const in
                                int *count);
 /* The workgroup variants of one config (host only, no GPU): the same
  * blocking, loop order and flags with each valid threads-per-workgroup value
- * (64, 128, 256, 512) and, for LDS-staged tiles, each LDS row padding
- * 0..TTX_MAX_LDS_PAD, every combination once, the given config first.  A
+ * (64, 128, 256, 512), for LDS-staged tiles each LDS row padding
+ * 0..TTX_MAX_LDS_PAD, and for moved menu tiles over a contiguous A run
+ * TTX_CFG_ALIGN_A both set and clear, every combination once, the given
+ * config first.  A
  * variant is valid when the tile's rows and vectors fit the workgroup and
  * each thread holds at most 32 vectors per side.  These are the second
  * search stage of ttx_tune and ttx_tune_specialised, around the measured

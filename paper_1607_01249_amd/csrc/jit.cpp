@@ -59,8 +59,9 @@ static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 14695981039346656
 // parameters, the element types, the beta class, the kernel flags and the
 // bytes of the problem-dependent arguments.
 static std::string jit_key(const TiledLaunch& L) {
-    const int head[] = {L.p.code, L.kind, L.va,       L.vb,       L.n0,        L.cap,
-                        L.flags,  L.beta0 ? 1 : 0, L.c.tile_a, L.c.tile_b, L.c.threads, config_pad(L.c)};
+    const int head[] = {L.p.code,   L.kind,     L.va,        L.vb,           L.n0,
+                        L.cap,      L.flags,    L.beta0 ? 1 : 0, L.c.tile_a, L.c.tile_b,
+                        L.c.threads, config_pad(L.c), L.c.flags & TTX_CFG_ALIGN_A};
     std::string k(reinterpret_cast<const char*>(head), sizeof(head));
     k.append(reinterpret_cast<const char*>(L.args), sizeof(TileArgsHost));
     return k;
@@ -82,6 +83,7 @@ std::string jit_entry_name(const TiledLaunch& L) {
     n += std::to_string(L.c.tile_a) + "x" + std::to_string(L.c.tile_b);
     if (L.c.threads != kThreads) n += "_t" + std::to_string(L.c.threads);
     if (config_pad(L.c) != 1) n += "_p" + std::to_string(config_pad(L.c));
+    if (L.c.flags & TTX_CFG_ALIGN_A) n += "_al";
     const std::string key = jit_key(L);
     char h[16];
     std::snprintf(h, sizeof(h), "_%08x", unsigned(fnv1a(key.data(), key.size()) & 0xffffffffu));
@@ -100,8 +102,9 @@ std::string jit_source(const TiledLaunch& L) {
     // taken from the constant kernel flags)
     switch (L.kind) {
         case kTileMoved:
-            std::snprintf(tile, sizeof(tile), "ttx::MovedTile<%s, %s, %d, %d, %d, %d, %s, -1, %d, %d>", T.c_str(), b0,
-                          L.c.tile_a, L.c.tile_b, L.va, L.vb, S.c_str(), nt, pad);
+            std::snprintf(tile, sizeof(tile), "ttx::MovedTile<%s, %s, %d, %d, %d, %d, %s, -1, %d, %d, %d>", T.c_str(),
+                          b0, L.c.tile_a, L.c.tile_b, L.va, L.vb, S.c_str(), nt, pad,
+                          config_align_elems(L.c, elem_bytes(L.p.dtype_a)));
             lds = L.c.tile_b * (L.c.tile_a + pad);
             waves = (L.va == 1 || L.vb == 1) ? 4 : 1;
             break;

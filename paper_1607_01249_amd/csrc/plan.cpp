@@ -446,7 +446,8 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     if (c.threads != 64 && c.threads != 128 && c.threads != 256 && c.threads != 512)
         return bad("threads must be 64, 128, 256 or 512");
     if (c.lds_pad < 0 || c.lds_pad > TTX_MAX_LDS_PAD) return bad("lds_pad out of range");
-    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE | TTX_CFG_GROUPED))
+    if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE | TTX_CFG_GROUPED |
+                    TTX_CFG_ALIGN_A))
         return bad("unknown flag");
     if (config_is_wide(c)) {
         if (!config_is_dense(c)) return bad("whole-unit rows are for dense tiles only");
@@ -496,8 +497,13 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     } else if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b)) {
         return bad("tile shape not in menu");
     }
-    // the tile id space must fit 32 bits
-    uint64_t tiles = uint64_t((L.SA + c.tile_a - 1) / c.tile_a) * uint64_t((L.SB + c.tile_b - 1) / c.tile_b);
+    const int aln = config_align_elems(c, elem_bytes(p.dtype_a));
+    if (aln && (p.family != TTX_FAMILY_MOVED || config_is_dense(c) || L.staged || p.dim[L.a].sa != 1 ||
+                128 % elem_bytes(p.dtype_a)))
+        return bad("line-aligned A runs need a moved menu tile over a contiguous A run");
+    // the tile id space must fit 32 bits (line-aligned runs add one tile along A's run)
+    uint64_t tiles = uint64_t((L.SA + (aln ? aln - 1 : 0) + c.tile_a - 1) / c.tile_a) *
+                     uint64_t((L.SB + c.tile_b - 1) / c.tile_b);
     for (int d = 0; d < p.n; ++d) {
         if (d == L.a || d == L.b || L.member[d]) continue;
         tiles *= d == z ? uint64_t((p.dim[d].size + tc - 1) / tc) : uint64_t(p.dim[d].size);
@@ -533,7 +539,10 @@ void build_grid(const Problem& p, const ttx_config& c, TileArgsHost* h) {
         int64_t stepA, stepB;
         if (d == L.a) {
             ext = c.tile_a;
-            extent = L.SA;
+            // line-aligned A runs shift each tile down by up to a line less
+            // one element: one more tile covers the end of the run
+            const int aln = config_align_elems(c, elem_bytes(p.dtype_a));
+            extent = L.SA + (aln ? aln - 1 : 0);
         } else if (d == L.b) {
             ext = c.tile_b;
             extent = L.SB;
@@ -1076,15 +1085,21 @@ int workgroup_variants(const Problem& p, const ttx_config& base, ttx_config* out
     if (p.family != TTX_FAMILY_MOVED && p.family != TTX_FAMILY_PRESERVED) return n;
     static const int kThreadMenu[] = {64, 128, 256, 512};
     const bool padded = config_uses_pad(base);
-    for (int t : kThreadMenu)
-        for (int pad = 0; pad <= (padded ? TTX_MAX_LDS_PAD : 0); ++pad) {
-            ttx_config c = base;
-            c.threads = t;
-            if (padded) c.lds_pad = pad;
-            if (c.threads == base.threads && config_pad(c) == config_pad(base)) continue;   // the base itself
-            if (!config_valid(p, c, nullptr)) continue;
-            if (n < cap) out[n++] = c;
-        }
+    // line-aligned A runs, both ways, where the tile allows them
+    ttx_config toggled = base;
+    toggled.flags ^= TTX_CFG_ALIGN_A;
+    const bool align_dim = config_valid(p, toggled, nullptr);
+    for (int al = 0; al < (align_dim ? 2 : 1); ++al)
+        for (int t : kThreadMenu)
+            for (int pad = 0; pad <= (padded ? TTX_MAX_LDS_PAD : 0); ++pad) {
+                ttx_config c = al ? toggled : base;
+                c.threads = t;
+                if (padded) c.lds_pad = pad;
+                if (c.threads == base.threads && config_pad(c) == config_pad(base) && c.flags == base.flags)
+                    continue;   // the base itself
+                if (!config_valid(p, c, nullptr)) continue;
+                if (n < cap) out[n++] = c;
+            }
     return n;
 }
 

@@ -351,12 +351,45 @@ constexpr bool nt_of() {
 // moved element by element.  The LDS tile has TB rows of TA + PAD elements
 // (the pre-compiled kernels pad by one, so that the column-wise reads of the
 // store phase fall in distinct banks); NTH threads share the tile.
+//
+// Line-aligned A runs (ALN > 0, the elements of one 128-byte line of A;
+// A's super index contiguous, sAa == 1): the tile's x range is shifted down
+// so that it starts on a line boundary (of device addresses) in the A row
+// of its first y,
+// [x0 - s, x0 - s + TA) with s = that row's element offset modulo ALN, and
+// clipped to [0, ext_a); the grid holds one more x tile to cover the shift.
+// Rows whose length is not a multiple of the line then cost whole lines
+// only, instead of sharing the lines at each tile boundary with the
+// neighbouring tile.  With ALN == 0 the tile is [x0, x0 + TA).
 template <typename T, bool BETA0, int TA, int TB, int VA, int VB, typename S = T, int NTS = -1,
-          int NTH = kThreads, int PAD = 1>
+          int NTH = kThreads, int PAD = 1, int ALN = 0>
 struct MovedTile {
     static constexpr bool kUsesLds = true;
     static constexpr int kTA = TA, kTB = TB;
     static constexpr int NT = NTH, LDR = TA + PAD;
+    static_assert(ALN == 0 || (ALN & (ALN - 1)) == 0, "line length in elements is a power of two");
+
+    // The tile's x range: origin x0 (the tile covers x0 .. x0 + TA - 1), the
+    // A offset of element x0 of its first row, and the valid positions
+    // lo <= x < hi relative to x0.
+    struct Span {
+        int64_t x0, oa;
+        int lo, hi;
+    };
+    template <typename Args>
+    __device__ __forceinline__ static Span span(const Args& a, const TileCoord& c) {
+        if constexpr (ALN == 0) {
+            return Span{c.x0, c.oa, 0, c.ea};
+        } else {
+            // A element index (from address 0) of (x = 0, y0): the tile's
+            // origin offset without its x term, plus A's base in elements
+            const int64_t row = c.oa - c.x0 + a.gB.offset(c.y0) +
+                                int64_t(reinterpret_cast<uintptr_t>(a.A) / sizeof(S));
+            const int s = int(row & (ALN - 1));
+            const int64_t x0 = c.x0 - s, rem = a.g.ext_a - x0;
+            return Span{x0, c.oa - s, x0 < 0 ? int(-x0) : 0, int(rem < TA ? (rem < 0 ? 0 : rem) : TA)};
+        }
+    }
     template <typename Args>
     __device__ static int ext_a(const Args&) { return TA; }
     template <typename Args>
@@ -378,20 +411,34 @@ struct MovedTile {
     template <typename Args>
     __device__ __forceinline__ void load(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
+        const Span sp = span(a, c);
         const int xa = (tid % PA) * VA, ya = tid / PA;
-        const bool live_a = (tid % PA) < LA && xa < c.ea;
-        const S* pa = a.A + c.oa + int64_t(xa) * a.sAa;
+        const bool live_a = (tid % PA) < LA && xa < sp.hi && xa + VA > sp.lo;
+        const S* pa = a.A + sp.oa + int64_t(xa) * a.sAa;
 #pragma unroll
         for (int i = 0; i < NA; ++i)
-            if (live_a && ya + i * RA < c.eb) ld_part<S, VA>(ra[i], pa + a.gB.offset(c.y0 + ya + i * RA), c.ea - xa);
+            if (live_a && ya + i * RA < c.eb) {
+                const S* p = pa + a.gB.offset(c.y0 + ya + i * RA);
+                if constexpr (ALN == 0) {
+                    ld_part<S, VA>(ra[i], p, sp.hi - xa);
+                } else if (xa >= sp.lo) {
+                    ld_part<S, VA>(ra[i], p, sp.hi - xa);
+                } else {   // a vector that starts before x = 0: its elements from x = 0 on
+#pragma unroll
+                    for (int j = 0; j < VA; ++j)
+                        if (xa + j >= sp.lo && xa + j < sp.hi) set_lane<S, VA>(ra[i], j, p[j]);
+                }
+            }
         if constexpr (!BETA0) {
             const int yb = (tid % PB) * VB, xb = tid / PB;
             const bool live_b = (tid % PB) < LB && yb < c.eb;
             const int64_t off_b = c.ob + int64_t(yb) * a.sBb;
 #pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (live_b && xb + i * RB < c.ea)
-                    ld_part<T, VB>(rb[i], a.Bsrc + off_b + a.gA.offset(c.x0 + xb + i * RB), c.eb - yb);
+            for (int i = 0; i < NB; ++i) {
+                const int x = xb + i * RB;
+                if (live_b && x >= sp.lo && x < sp.hi)
+                    ld_part<T, VB>(rb[i], a.Bsrc + off_b + a.gA.offset(sp.x0 + x), c.eb - yb);
+            }
         }
     }
 
@@ -414,12 +461,13 @@ struct MovedTile {
     __device__ __forceinline__ void from_lds(const T* __restrict__ lds, const Args& a,
                                              const TileCoord& c) {
         const int tid = threadIdx.x;
+        const Span sp = span(a, c);
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int x = xb + i * RB;
-            if (live_b && x < c.ea) {
+            if (live_b && x >= sp.lo && x < sp.hi) {
                 vec_t<T, VB> v;
 #pragma unroll
                 for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
@@ -431,6 +479,7 @@ struct MovedTile {
     template <typename Args>
     __device__ __forceinline__ void store(const Args& a, const TileCoord& c) {
         const int tid = threadIdx.x;
+        const Span sp = span(a, c);
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
         constexpr bool nt = nt_of<NTS, Args>();
@@ -438,7 +487,8 @@ struct MovedTile {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int x = xb + i * RB;
-            if (live_b && x < c.ea) st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(c.x0 + x), out[i], c.eb - yb);
+            if (live_b && x >= sp.lo && x < sp.hi)
+                st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(sp.x0 + x), out[i], c.eb - yb);
         }
     }
 
@@ -447,6 +497,7 @@ struct MovedTile {
     __device__ __forceinline__ void read_store(const T* __restrict__ lds, const Args& a,
                                                const TileCoord& c) {
         const int tid = threadIdx.x;
+        const Span sp = span(a, c);
         const int yb = (tid % PB) * VB, xb = tid / PB;
         const bool live_b = (tid % PB) < LB && yb < c.eb;
         constexpr bool nt = nt_of<NTS, Args>();
@@ -454,11 +505,11 @@ struct MovedTile {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int x = xb + i * RB;
-            if (live_b && x < c.ea) {
+            if (live_b && x >= sp.lo && x < sp.hi) {
                 vec_t<T, VB> v;
 #pragma unroll
                 for (int j = 0; j < VB; ++j) set_lane<T, VB>(v, j, lds[(yb + j) * LDR + x]);
-                st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(c.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
+                st_part<T, VB, nt>(a.Bdst + off_b + a.gA.offset(sp.x0 + x), epilogue<T, VB, BETA0>(v, rb[i], a.alpha, a.beta),
                                c.eb - yb);
             }
         }

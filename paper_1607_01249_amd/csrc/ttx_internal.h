@@ -170,7 +170,13 @@ inline int config_pad(const ttx_config& c) { return config_uses_pad(c) ? c.lds_p
 // Whether the config runs outside the pre-compiled kernels (another
 // workgroup size or LDS padding): then it always runs a size-specialised
 // kernel, compiled on first use.
-inline bool config_needs_jit(const ttx_config& c) { return c.threads != kThreads || config_pad(c) != 1; }
+inline bool config_needs_jit(const ttx_config& c) {
+    return c.threads != kThreads || config_pad(c) != 1 || (c.flags & TTX_CFG_ALIGN_A);
+}
+// Elements of A per 128-byte line for line-aligned A runs (TTX_CFG_ALIGN_A; 0 when off).
+inline int config_align_elems(const ttx_config& c, int elem_bytes_a) {
+    return (c.flags & TTX_CFG_ALIGN_A) ? 128 / elem_bytes_a : 0;
+}
 // Workgroup variants of a valid config (threads per workgroup x LDS row
 // padding), the config itself first; returns how many were written.
 int workgroup_variants(const Problem& p, const ttx_config& base, ttx_config* out, int cap);

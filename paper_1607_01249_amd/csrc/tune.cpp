@@ -252,7 +252,7 @@ static ttx_status tune_variants(const Problem& p, bool beta0, const std::vector<
     const Scalar alpha(1.25), beta(beta0 ? 0.0 : 0.75);
     std::vector<ttx_config> vars;
     std::vector<const JitKernel*> ks;
-    ttx_config buf[4 * (TTX_MAX_LDS_PAD + 1)];
+    ttx_config buf[2 * 4 * (TTX_MAX_LDS_PAD + 1)];
     for (int b = 0, taken = 0; b < int(order.size()) && taken < TTX_TUNE_VARIANT_BASES; ++b) {
         const int nv = workgroup_variants(p, cands[order[b]], buf, int(sizeof(buf) / sizeof(buf[0])));
         ++taken;

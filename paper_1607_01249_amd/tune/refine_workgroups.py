@@ -1,5 +1,6 @@
 """Refines a tune table's entries for size-specialised execution with the
-workgroup dimensions (threads per workgroup, LDS row padding).
+workgroup dimensions (threads per workgroup, LDS row padding, line-aligned
+A runs).
 
 For each problem given, the plan's configuration for specialised execution
 (the table's `j:` entry, else its generic entry) is the base; every workgroup
@@ -91,9 +92,11 @@ def refine(cases, rounds=2, margin=0.02, log=print):
         best = min(range(len(variants)), key=lambda i: max(times[i]))
         gain = [1 - times[best][r] / times[0][r] for r in range(rounds)]
         kept = best != 0 and min(gain) >= margin
-        log("%s: base t%d p%d %.1f us, best t%d p%d %.1f us (%+.1f%%)%s" % (
-            case["name"], base.threads, base.lds_pad, max(times[0]), variants[best].threads,
-            variants[best].lds_pad, max(times[best]), -100 * min(gain), " -> kept" if kept else ""))
+        al = lambda c: "a" if c.flags & ttx.CFG_ALIGN_A else ""
+        log("%s: base t%d p%d%s %.1f us, best t%d p%d%s %.1f us (%+.1f%%)%s" % (
+            case["name"], base.threads, base.lds_pad, al(base), max(times[0]), variants[best].threads,
+            variants[best].lds_pad, al(variants[best]), max(times[best]), -100 * min(gain),
+            " -> kept" if kept else ""))
         if kept:
             out[table_key(info, z)] = (variants[best], max(times[best]))
         del A, B

@@ -370,6 +370,50 @@ def test_every_workgroup_variant_bit_identical(code, perm, size):
     assert ran >= 4
 
 
+@pytest.mark.parametrize("code,perm,size", [
+    (ttx.F32, (5, 4, 3, 2, 1, 0), (7, 9, 5, 4, 3, 5)), (ttx.F64, (5, 4, 3, 2, 1, 0), (7, 9, 5, 4, 3, 5)),
+    (ttx.F32, (2, 0, 3, 1), (37, 70, 19, 23)), (ttx.F32, (1, 0), (7, 3000)), (ttx.F64, (1, 0), (300, 5)),
+    (ttx.F32, (1, 0, 2), (1001, 33, 3)), (ttx.C64, (2, 1, 0), (33, 40, 27)), (ttx.F64_F32, (3, 2, 1, 0), (5, 3, 70, 9)),
+    (ttx.F32_F64, (1, 2, 0), (129, 17, 31))])
+def test_line_aligned_a_runs_bit_identical(code, perm, size):
+    """TTX_CFG_ALIGN_A (tile ranges along A's run start on 128-byte lines):
+    every moved menu candidate over a contiguous A run, and its 64- and
+    512-thread variants, with the flag set gives the oracle's bits at both
+    beta classes, also with misaligned pointers."""
+    from gpu_util import TYPES_OF_CODE
+    da, db = TYPES_OF_CODE[code]
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    seen, picks = set(), []
+    for c in cands:
+        if c.family != ttx.FAMILY_MOVED or c.flags & ttx.CFG_DENSE:
+            continue
+        key = (c.tile_a, c.tile_b, c.group_a, c.group_b)
+        if key in seen:
+            continue
+        seen.add(key)
+        al = ttx.Config.from_buffer_copy(c)
+        al.flags |= ttx.CFG_ALIGN_A
+        try:
+            variants = ttx.ttx_tune_variants(code, perm, size, al)
+        except ttx.TTXError:
+            continue   # A's run is not contiguous for these groups
+        picks += [v for v in variants if v.threads in (64, 256, 512) and v.lds_pad == 1]
+        if len(seen) >= 8:   # the 8 best-ranked moved tile shapes (each config is compiled)
+            break
+    assert picks, "no candidate takes line-aligned A runs"
+    n = _elems(size)
+    A = workloads.uniform(n, da, 26)
+    B = workloads.uniform(n, db, 27)
+    for beta in (0.7, 0.0):
+        ref = B.copy()
+        assert oracle.transpose(perm, size, 1.3, A, beta, ref) == 0
+        for k, v in enumerate(picks):
+            pad = (k % 3, (k + 1) % 2)   # element offsets of A and B in their buffers
+            _say("  aligned %s beta=%g pad=%s" % (v.as_dict(), beta, pad))
+            got = gpu_transpose(perm, size, 1.3, A, beta, B, pad_a=pad[0], pad_b=pad[1], plan_config=v)
+            assert_parity(got, ref, exact=True, what="%s beta=%g pad=%s" % (v.as_dict(), beta, pad))
+
+
 def test_tuner_second_stage_times_workgroup_variants():
     """ttx_tune times the workgroup variants of its fastest candidates after
     the ranked list; whatever wins, the plan that takes it computes the

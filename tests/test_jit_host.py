@@ -53,7 +53,7 @@ def _expected_tile(name):
     tile = {"moved": "MovedTile", "preserved": "PreservedTile", "staged": "StagedTile", "dense": "DenseTile"}
     # then the store kind (-1: from the constant flags), the workgroup size
     # and, for tiles staged through LDS rows, the row padding
-    wg = {"moved": "256, 1", "staged": "256, 1", "preserved": "256", "dense": "256"}[m.group(1)]
+    wg = {"moved": "256, 1, 0", "staged": "256, 1", "preserved": "256", "dense": "256"}[m.group(1)]
     return "ttx::%s<%s, %s, %s, -1, %s>" % (tile[m.group(1)], t, ", ".join(rest), s, wg)
 
 
@@ -156,15 +156,19 @@ def _variants(dtype, perm, size, bz):
 def test_variants_of_a_moved_tile_span_threads_and_padding():
     base, vs = _variants(ttx.F32, (3, 2, 1, 0), (160, 160, 64, 32), True)
     assert vs[0].as_dict() == base.as_dict()
-    seen = {(v.threads, v.lds_pad) for v in vs}
+    seen = {(v.threads, v.lds_pad, v.flags & ttx.CFG_ALIGN_A) for v in vs}
     assert len(seen) == len(vs), "each combination once"
-    assert {t for t, _ in seen} <= {64, 128, 256, 512} and {p for _, p in seen} <= set(range(5))
-    # the pre-compiled shape and at least one other size and padding are there
-    assert (256, 1) in seen and len({t for t, _ in seen}) >= 3 and len({p for _, p in seen}) == 5
-    for v in vs:   # nothing but the workgroup shape changes
+    assert {t for t, _, _ in seen} <= {64, 128, 256, 512} and {p for _, p, _ in seen} <= set(range(5))
+    # the pre-compiled shape and at least one other size and padding are there,
+    # with line-aligned A runs both ways (A's run is contiguous here)
+    assert (256, 1, 0) in seen and len({t for t, _, _ in seen}) >= 3 and len({p for _, p, _ in seen}) == 5
+    assert {a for _, _, a in seen} == {0, ttx.CFG_ALIGN_A}
+    for v in vs:   # nothing but the workgroup shape and the alignment flag changes
         d, b = v.as_dict(), base.as_dict()
         for k in ("threads", "lds_pad"):
             d.pop(k), b.pop(k)
+        d["flags"] &= ~ttx.CFG_ALIGN_A
+        b["flags"] &= ~ttx.CFG_ALIGN_A
         assert d == b
 
 
@@ -193,7 +197,7 @@ def test_variant_configs_are_checked():
         name = ttx.ttx_plan_kernel_name(plan, 1.0, 1 << 20, 3 << 20)
         assert name.startswith("ttx_jit_moved_float_b_") and "_t128_p3_" in name, name
         src = ttx.ttx_plan_specialised_source(plan, False)
-        assert "__launch_bounds__(128)" in src and ", -1, 128, 3>" in src
+        assert "__launch_bounds__(128)" in src and ", -1, 128, 3, 0>" in src
     finally:
         ttx.ttx_plan_destroy(plan)
     flat = ttx.ttx_plan_create(ttx.F32, (0, 1), (64, 9))
