@@ -5,13 +5,15 @@ A runs).
 For each problem given, the plan's configuration for specialised execution
 (the table's `j:` entry, else its generic entry) is the base; every workgroup
 variant of it (ttx_tune_variants) is compiled as a size-specialised kernel
-and timed the way a throughput loop runs it: back-to-back launches on warm
-data, median of the launch times, in several rounds with the base re-timed
-in each.  A variant replaces the base only when its median is lower by at
+and timed the way a throughput loop runs it: back-to-back launches that
+rotate over three buffer pairs (so that each launch finds the data of the
+two before it in the 256 MiB Infinity Cache, not its own), median of the
+launch times, in several rounds with the base re-timed in each.  A variant replaces the base only when its median is lower by at
 least `--margin` in every round.  The result is written as `j:` entries of
 a new table file (the generic entries are copied unchanged).
 
     python paper_1607_01249_amd/tune/refine_workgroups.py IN OUT [--cases large|complex|mixed|all]
+           [--only NAME ...] [--shapes]
 
 Needs a GPU.  Blocks for a few seconds per problem.
 """
@@ -44,11 +46,14 @@ def config_text(c):
     return s
 
 
-def _timed(ttx, torch, plan, case, A, B, stream, launches=13):
-    for _ in range(3):
+def _timed(ttx, torch, plan, case, pairs, stream, launches=13):
+    """Median launch time (us), launches rotating over the (A, B) pointer pairs."""
+    for k in range(3):
+        A, B = pairs[k % len(pairs)]
         ttx.ttx_plan_execute_c(plan, case["alpha"], A, case["beta"], B, B, stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
     for r in range(launches):
+        A, B = pairs[r % len(pairs)]
         ev[r].record()
         ttx.ttx_plan_execute_c(plan, case["alpha"], A, case["beta"], B, B, stream)
     ev[launches].record()
@@ -56,8 +61,33 @@ def _timed(ttx, torch, plan, case, A, B, stream, launches=13):
     return statistics.median(ev[r].elapsed_time(ev[r + 1]) * 1e3 for r in range(launches))
 
 
-def refine(cases, rounds=2, margin=0.02, log=print):
-    """{key: (config, usec)} of the variants that beat their base."""
+def shape_variants(ttx, code, perm, size, base):
+    """Moved-family configs with the base's index groups, loop order and
+    flags and every other tile shape of the menu that fits this layout,
+    each at 256 and 512 threads per workgroup, with line-aligned A runs on
+    and off where they apply (the first search stage ranks shapes at 256
+    threads only)."""
+    if base.family != ttx.FAMILY_MOVED or base.flags & ttx.CFG_DENSE:
+        return []
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    shapes = sorted({(c.tile_a, c.tile_b) for c in cands
+                     if c.family == ttx.FAMILY_MOVED and not c.flags & ttx.CFG_DENSE and
+                     (c.group_a, c.group_b) == (base.group_a, base.group_b)})
+    out = []
+    for ta, tb in shapes:
+        for threads in (256, 512):
+            for align in (0, ttx.CFG_ALIGN_A):
+                v = ttx.Config.from_buffer_copy(base)
+                v.tile_a, v.tile_b, v.threads, v.lds_pad = ta, tb, threads, 1
+                v.flags = (v.flags & ~ttx.CFG_ALIGN_A) | align
+                if (ta, tb, threads, v.flags) != (base.tile_a, base.tile_b, base.threads, base.flags):
+                    out.append(v)
+    return out
+
+
+def refine(cases, rounds=2, margin=0.02, log=print, shapes=False):
+    """{key: (config, usec)} of the variants that beat their base (with
+    shapes, also the other menu tile shapes of moved-family bases)."""
     import torch
     import paper_1607_01249_amd as ttx
     stream = ttx.current_stream()
@@ -75,31 +105,41 @@ def refine(cases, rounds=2, margin=0.02, log=print):
         if info["family"] not in ("moved", "preserved"):
             continue
         variants = ttx.ttx_tune_variants(code, perm, size, base)
-        A = torch.empty(max(1, info["extent_a_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1)
-        B = torch.empty(max(1, info["extent_b_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1)
-        plans = []
+        if shapes:
+            variants += shape_variants(ttx, code, perm, size, base)
+        bufs = [(torch.empty(max(1, info["extent_a_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1),
+                 torch.empty(max(1, info["extent_b_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1))
+                for _ in range(3)]
+        pairs = [(a.data_ptr(), b.data_ptr()) for a, b in bufs]
+        plans, kept_v = [], []
         for v in variants:
             p = ttx.ttx_plan_create(code, perm, size)
-            ttx.ttx_plan_set_config(p, z, v)
+            try:
+                ttx.ttx_plan_set_config(p, z, v)
+            except ttx.TTXError:   # a shape whose tile does not fit this workgroup
+                ttx.ttx_plan_destroy(p)
+                continue
             ttx.ttx_plan_specialise(p, z)
             plans.append(p)
+            kept_v.append(v)
+        variants = kept_v
         times = [[] for _ in variants]
         for _ in range(rounds):
             for i, p in enumerate(plans):
-                times[i].append(_timed(ttx, torch, p, case, A.data_ptr(), B.data_ptr(), stream))
+                times[i].append(_timed(ttx, torch, p, case, pairs, stream))
         for p in plans:
             ttx.ttx_plan_destroy(p)
         best = min(range(len(variants)), key=lambda i: max(times[i]))
         gain = [1 - times[best][r] / times[0][r] for r in range(rounds)]
         kept = best != 0 and min(gain) >= margin
         al = lambda c: "a" if c.flags & ttx.CFG_ALIGN_A else ""
-        log("%s: base t%d p%d%s %.1f us, best t%d p%d%s %.1f us (%+.1f%%)%s" % (
-            case["name"], base.threads, base.lds_pad, al(base), max(times[0]), variants[best].threads,
-            variants[best].lds_pad, al(variants[best]), max(times[best]), -100 * min(gain),
-            " -> kept" if kept else ""))
+        log("%s: base %dx%d t%d p%d%s %.1f us, best %dx%d t%d p%d%s %.1f us (%+.1f%%)%s" % (
+            case["name"], base.tile_a, base.tile_b, base.threads, base.lds_pad, al(base), max(times[0]),
+            variants[best].tile_a, variants[best].tile_b, variants[best].threads, variants[best].lds_pad,
+            al(variants[best]), max(times[best]), -100 * min(gain), " -> kept" if kept else ""))
         if kept:
             out[table_key(info, z)] = (variants[best], max(times[best]))
-        del A, B
+        del bufs
         torch.cuda.empty_cache()
     return out
 
@@ -143,6 +183,9 @@ def main():
     ap.add_argument("--only", nargs="*", default=None, help="case names")
     ap.add_argument("--rounds", type=int, default=2)
     ap.add_argument("--margin", type=float, default=0.02)
+    ap.add_argument("--shapes", action="store_true",
+                    help="also try the other menu tile shapes of moved-family bases (256/512 threads, "
+                         "line-aligned A runs on and off)")
     args = ap.parse_args()
     import paper_1607_01249_amd as ttx
     ttx.ttx_tune_table_clear()
@@ -150,7 +193,7 @@ def main():
     cases = bench_cases(args.cases)
     if args.only:
         cases = [c for c in cases if c["name"] in args.only]
-    entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True))
+    entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True), shapes=args.shapes)
     write_table(args.table_in, args.table_out, entries)
     print("%d of %d entries refined -> %s" % (len(entries), len(cases), args.table_out), flush=True)
 
