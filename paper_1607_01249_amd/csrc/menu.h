@@ -77,7 +77,9 @@
 // both sides (flat tiles: p1 consecutive elements, four per thread, in
 // vectors or single elements); for TTX_BATCH_STAGED p1 is the row-lane count and p2 x p3 the
 // staged tile; for TTX_BATCH_DENSE p1 is the dense capacity.  Kept small: every variant adds code to the one kernel and
-// its register and LDS needs set the kernel's occupancy.
+// its register and LDS needs set the kernel's occupancy (the dense variant sets the
+// registers; the large vector tiles, 16-17 KB of LDS like it, cost no occupancy and carry
+// most of the batch's bytes: its largest problems run 2-3% faster with them).
 #define TTX_BATCH_STAGED 4
 #define TTX_BATCH_DENSE 5
 
@@ -89,7 +91,8 @@
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 4096, 1, 1)               \
     X(10, TTX_FAMILY_FLAT, 1024, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                  \
     X(12, TTX_BATCH_STAGED, 32, 8, 8) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
-    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F32, 0, 0)
+    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F32, 0, 0) X(15, TTX_FAMILY_MOVED, 64, 64, 1)     \
+    X(16, TTX_FAMILY_MOVED, 128, 32, 1) X(17, TTX_FAMILY_MOVED, 32, 128, 1)
 
 #define TTX_BATCH_MENU_F64(X)                                                             \
     X(0, TTX_FAMILY_MOVED, 32, 32, 1) X(1, TTX_FAMILY_MOVED, 32, 16, 1)                   \
@@ -99,6 +102,7 @@
     X(8, TTX_FAMILY_PRESERVED, 16, 64, 0) X(9, TTX_FAMILY_FLAT, 2048, 1, 1)               \
     X(10, TTX_FAMILY_FLAT, 1024, 1, 0) X(11, TTX_BATCH_STAGED, 16, 8, 8)                  \
     X(12, TTX_BATCH_STAGED, 32, 4, 4) X(13, TTX_BATCH_STAGED, 64, 4, 4)                   \
-    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F64, 0, 0)
+    X(14, TTX_BATCH_DENSE, TTX_DENSE_CAP_F64, 0, 0) X(15, TTX_FAMILY_MOVED, 64, 32, 1)     \
+    X(16, TTX_FAMILY_MOVED, 32, 64, 1) X(17, TTX_FAMILY_MOVED, 16, 128, 1)
 
-#define TTX_BATCH_MENU_SIZE 15
+#define TTX_BATCH_MENU_SIZE 18

@@ -29,8 +29,8 @@ def _fake_problems(probs, gap=256):
 
 
 BATCH_SHAPES = {
-    (ttx.F32, ttx.FAMILY_MOVED): {(64, 32), (32, 32), (32, 64), (8, 128), (128, 8)},
-    (ttx.F64, ttx.FAMILY_MOVED): {(32, 32), (32, 16), (16, 32), (4, 128), (128, 4)},
+    (ttx.F32, ttx.FAMILY_MOVED): {(64, 32), (32, 32), (32, 64), (8, 128), (128, 8), (64, 64), (128, 32), (32, 128)},
+    (ttx.F64, ttx.FAMILY_MOVED): {(32, 32), (32, 16), (16, 32), (4, 128), (128, 4), (64, 32), (32, 64), (16, 128)},
     # direct preserved tiles, and staged (tile_x, tile_y) for short rows
     (ttx.F32, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
     (ttx.F64, ttx.FAMILY_PRESERVED): {(64, 16), (16, 64), (8, 8), (4, 4)},
