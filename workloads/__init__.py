@@ -192,3 +192,44 @@ def served_trace(rate=20000.0, duration=10.0, seed_arrivals=5, seed_shapes=6,
         reqs.append(dict(dtype=dtype, size=size, perm=perm, alpha=alpha, beta=beta,
                          large=bool(large)))
     return times, reqs
+
+
+# -- tensor contractions cast as transpose-transpose-GEMM-transpose ------------------------
+# Binary contractions with integer mode labels (column-major tensors, labels in
+# storage order); a label in A and B only is summed over.  The three measured
+# ones span the two regimes of the approach: the matrix product dominates (all
+# extents 40, m = n = k = 1600), or the transpositions do (small contracted
+# extents, large free extents, where the operands' memory traffic is most of the
+# work).  The parity cases add ragged panels, operands already in matrix order
+# (no transposition), K-major operands, a scalar result and empty extents.
+CONTRACTIONS = [
+    dict(name="ttgt_gemm_bound_f32", dtype=F32, labels_a=(2, 4, 0, 5), labels_b=(5, 3, 4, 1),
+         labels_c=(0, 1, 2, 3), extent={0: 40, 1: 40, 2: 40, 3: 40, 4: 40, 5: 40}, alpha=1.0, beta=0.0),
+    dict(name="ttgt_small_k_f32", dtype=F32, labels_a=(2, 6, 0, 4), labels_b=(5, 3, 6, 1),
+         labels_c=(0, 1, 2, 3, 4, 5), extent={0: 24, 1: 24, 2: 24, 3: 24, 4: 24, 5: 24, 6: 16}, alpha=1.0,
+         beta=0.5),
+    dict(name="ttgt_small_k_f64", dtype=F64, labels_a=(1, 3, 0), labels_b=(3, 2), labels_c=(0, 1, 2),
+         extent={0: 96, 1: 64, 2: 512, 3: 8}, alpha=-1.5, beta=1.0),
+]
+
+CONTRACTION_PARITY = [  # small: the oracle contracts them whole in well under a second
+    dict(name="matrix_product", labels_a=(0, 2), labels_b=(2, 1), labels_c=(0, 1), extent={0: 70, 1: 45, 2: 33}),
+    dict(name="k_major_operands", labels_a=(2, 0), labels_b=(1, 2), labels_c=(0, 1), extent={0: 37, 1: 50, 2: 65}),
+    dict(name="4d_reordered", labels_a=(2, 4, 0, 5), labels_b=(5, 3, 4, 1), labels_c=(0, 1, 2, 3),
+         extent={0: 9, 1: 7, 2: 5, 3: 6, 4: 4, 5: 11}),
+    dict(name="6d_result", labels_a=(2, 6, 0, 4), labels_b=(5, 3, 6, 1), labels_c=(0, 1, 2, 3, 4, 5),
+         extent={0: 5, 1: 4, 2: 3, 3: 6, 4: 2, 5: 7, 6: 9}),
+    dict(name="k_order_differs", labels_a=(0, 3, 4, 1), labels_b=(4, 2, 3), labels_c=(1, 2, 0),
+         extent={0: 17, 1: 3, 2: 40, 3: 5, 4: 6}),
+    dict(name="outer_product", labels_a=(1, 0), labels_b=(2,), labels_c=(0, 2, 1), extent={0: 33, 1: 3, 2: 20}),
+    dict(name="inner_product", labels_a=(0, 1), labels_b=(1, 0), labels_c=(), extent={0: 31, 1: 29}),
+    dict(name="matrix_vector", labels_a=(1, 0), labels_b=(1,), labels_c=(0,), extent={0: 100, 1: 77}),
+    dict(name="empty_contracted", labels_a=(0, 2), labels_b=(2, 1), labels_c=(0, 1), extent={0: 8, 1: 9, 2: 0}),
+    dict(name="empty_free", labels_a=(0, 2), labels_b=(2, 1), labels_c=(0, 1), extent={0: 0, 1: 9, 2: 5}),
+]
+
+
+def contraction_sizes(case):
+    """(size_a, size_b, size_c): the extents of each tensor's modes."""
+    e = case["extent"]
+    return tuple(tuple(e[l] for l in case[k]) for k in ("labels_a", "labels_b", "labels_c"))
