@@ -429,6 +429,61 @@ ttx_status ttx_pack_describe(ttx_dtype dtype, int kind, int64_t rows, int64_t co
 ttx_status ttx_gemm_panels(ttx_dtype dtype, int panel, int64_t m, int64_t n, int64_t k, const void *Pa,
                            const void *Pb, void *C, int64_t ldc, hipStream_t stream);
 
+/* -- tensor contraction: transpose-transpose-GEMM-transpose (Sec. 1, Sec. 4) -----------
+ * A contraction cast as a matrix product by transpositions, the use Sec. 1
+ * gives for a fast transposition and the compiler Sec. 4 builds on it:
+ *   C[c] <- alpha * sum over the contracted labels of A[a] * B[b] + beta * C[c]
+ * A, B and C are column-major tensors (first mode fastest, contiguous) whose
+ * modes carry integer labels: a label carried by A and B only is contracted
+ * (its extents multiply to k); every label of C is carried by exactly one
+ * operand (A's make m, B's make n).  Labels carried by all three tensors
+ * (batch labels), twice by one tensor, or by one tensor only are
+ * TTX_EINVAL, and so are extents that differ for one label.  na, nb, nc
+ * are in 0..TTX_MAX_DIMS (0: a scalar).
+ *
+ * Execution: each operand that is not already a matrix (its free modes and
+ * its contracted modes in two contiguous blocks, in either order, with the
+ * contracted modes in the order the other operand uses) is transposed into
+ * one (ttx_plan_execute); both are packed into matrix-core panels
+ * (ttx_pack, TTX_PACK_MFMA_A or _B, whichever reads the matrix in its
+ * storage order); ttx_gemm_panels forms the m x n product; and one
+ * transposition writes alpha * product + beta * C into C's mode order
+ * (Eqn. 1, so beta == 0 never reads C).  The product is summed in the
+ * element type by the matrix cores (see ttx_gemm_panels); alpha and beta
+ * are applied once, in the last step.  dtype TTX_F32 or TTX_F64 (else
+ * TTX_EUNSUPPORTED).
+ *
+ * The plan holds host memory only (no HIP call at creation).  Execution
+ * needs a device workspace of ttx_contraction_describe's workspace_bytes
+ * (at most (2*m*k + 2*k*n + m*n) elements plus panel padding), passed by
+ * the caller: the library allocates nothing.  A, B, C and the workspace
+ * are device pointers aligned to the element size; C's byte range must not
+ * overlap A's or B's, and the workspace's must overlap none of them
+ * (TTX_EOVERLAP).  Asynchronous on `stream`; calls that share a workspace
+ * must not overlap in time. */
+typedef struct ttx_contraction ttx_contraction;
+typedef struct ttx_contraction_info {
+    int64_t m, n, k;            /* the matrix product's extents */
+    int panel;                  /* matrix-core panel (16 or 32) */
+    int transposed_a;           /* 1: A is transposed into matrix order before packing */
+    int transposed_b;
+    int pack_kind_a;            /* TTX_PACK_MFMA_A or TTX_PACK_MFMA_B (A stored contracted-major) */
+    int pack_kind_b;            /* TTX_PACK_MFMA_B, or TTX_PACK_MFMA_A (B stored free-major) */
+    int n_m, n_n, n_k;          /* label counts of the three index groups */
+    int order_m[TTX_MAX_DIMS];  /* labels of the product's rows, fastest first */
+    int order_n[TTX_MAX_DIMS];  /* labels of its columns */
+    int order_k[TTX_MAX_DIMS];  /* contracted labels in the order both packed operands use */
+    int64_t workspace_bytes;
+} ttx_contraction_info;
+
+ttx_status ttx_contraction_create(ttx_contraction **plan, ttx_dtype dtype, int na, const int *labels_a,
+                                  const int64_t *size_a, int nb, const int *labels_b, const int64_t *size_b,
+                                  int nc, const int *labels_c, const int64_t *size_c);
+ttx_status ttx_contraction_describe(const ttx_contraction *plan, ttx_contraction_info *info);
+ttx_status ttx_contraction_execute(const ttx_contraction *plan, double alpha, const void *A, const void *B,
+                                   double beta, void *C, void *workspace, hipStream_t stream);
+ttx_status ttx_contraction_destroy(ttx_contraction *plan);
+
 /* -- batched execution ----------------------------------------------------------
  * Many independent transpositions, each Eqn. 1 with its own dtype, shape,
  * permutation, leading dimensions, scalars and tensors, run by ONE

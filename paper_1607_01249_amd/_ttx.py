@@ -89,6 +89,14 @@ class BatchInfo(ctypes.Structure):
                 ("per_call", ctypes.c_int)]
 
 
+class ContractionInfo(ctypes.Structure):
+    _fields_ = [("m", i64), ("n", i64), ("k", i64), ("panel", ctypes.c_int), ("transposed_a", ctypes.c_int),
+                ("transposed_b", ctypes.c_int), ("pack_kind_a", ctypes.c_int), ("pack_kind_b", ctypes.c_int),
+                ("n_m", ctypes.c_int), ("n_n", ctypes.c_int), ("n_k", ctypes.c_int),
+                ("order_m", ctypes.c_int * MAX_DIMS), ("order_n", ctypes.c_int * MAX_DIMS),
+                ("order_k", ctypes.c_int * MAX_DIMS), ("workspace_bytes", i64)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("problem", Problem), ("arrival_ns", i64), ("keep_result", ctypes.c_int)]
 
@@ -233,6 +241,10 @@ def _declare(L):
         "ttx_gemm_panels": ([S, S, i64, i64, i64, vp, vp, vp, i64, vp], S),
         "ttx_pack_tune": ([S, S, i64, i64, i64, i64, S, S], S),
         "ttx_pack_describe": ([S, S, i64, i64, i64, i64, i64p, ip, ctypes.POINTER(Config)], S),
+        "ttx_contraction_create": ([ctypes.POINTER(vp), S, S, ip, i64p, S, ip, i64p, S, ip, i64p], S),
+        "ttx_contraction_describe": ([vp, ctypes.POINTER(ContractionInfo)], S),
+        "ttx_contraction_execute": ([vp, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, vp], S),
+        "ttx_contraction_destroy": ([vp], S),
         "ttx_copy_kernel": ([vp, vp, i64, vp], S),
         "ttx_axpby_kernel": ([S, i64, ctypes.c_double, vp, ctypes.c_double, vp, vp], S),
     }
@@ -570,6 +582,32 @@ def ttx_copy_kernel(src, dst, nbytes, stream=0):
 def ttx_gemm_panels(dtype, panel, m, n, k, Pa, Pb, C, ldc, stream=0):
     """C (m x n, column-major, ldc) = A * B from matrix-core operand panels."""
     return _check(lib().ttx_gemm_panels(dtype, int(panel), int(m), int(n), int(k), Pa, Pb, C, int(ldc), stream))
+
+
+def ttx_contraction_create(dtype, labels_a, size_a, labels_b, size_b, labels_c, size_c):
+    """A transpose-transpose-GEMM-transpose contraction plan (host only)."""
+    h = vp()
+    _check(lib().ttx_contraction_create(ctypes.byref(h), dtype, len(labels_a), _ints(labels_a), _i64s(size_a),
+                                        len(labels_b), _ints(labels_b), _i64s(size_b),
+                                        len(labels_c), _ints(labels_c), _i64s(size_c)))
+    return h
+
+
+def ttx_contraction_describe(plan):
+    info = ContractionInfo()
+    _check(lib().ttx_contraction_describe(plan, ctypes.byref(info)))
+    return dict(m=info.m, n=info.n, k=info.k, panel=info.panel, transposed_a=bool(info.transposed_a),
+                transposed_b=bool(info.transposed_b), pack_kind_a=info.pack_kind_a, pack_kind_b=info.pack_kind_b,
+                order_m=list(info.order_m[:info.n_m]), order_n=list(info.order_n[:info.n_n]),
+                order_k=list(info.order_k[:info.n_k]), workspace_bytes=info.workspace_bytes)
+
+
+def ttx_contraction_execute(plan, alpha, A, B, beta, C, workspace, stream=0):
+    return _check(lib().ttx_contraction_execute(plan, float(alpha), A, B, float(beta), C, workspace, stream))
+
+
+def ttx_contraction_destroy(plan):
+    return _check(lib().ttx_contraction_destroy(plan))
 
 
 def ttx_pack(dtype, kind, rows, cols, ld, panel, alpha, A, P, stream=0):
