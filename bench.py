@@ -91,6 +91,10 @@ def parse_args():
                     help="the per-case detail (JSON); the printed line holds the summary")
     ap.add_argument("--no-types", action="store_true",
                     help="skip the complex (c, z) and mixed-precision (sd, ds, cz, zc) cases")
+    ap.add_argument("--no-contraction", action="store_true",
+                    help="skip the transpose-transpose-GEMM-transpose contractions")
+    ap.add_argument("--only-contraction", action="store_true",
+                    help="for rocprofv3: only the contractions (after the ceilings), then exit")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="Poisson arrival rate (req/s)")
     ap.add_argument("--profile-run", action="store_true",
@@ -669,6 +673,89 @@ def bench_packing(torch, ttx, d2d, stream, tune_candidates, reps=10):
     return out
 
 
+def bench_contraction(torch, ttx, d2d, stream, reps=10):
+    """Transpose-transpose-GEMM-transpose contractions (the workloads'
+    CONTRACTIONS), operands resident: the whole ttx_contraction_execute, its
+    panel GEMM alone (ttx_gemm_panels on panels of the same extents), the
+    rest (transpositions and packing) as the difference, and torch's
+    tensordot on the same tensors as a point of comparison."""
+    import workloads
+    out = []
+    for case in workloads.CONTRACTIONS:
+        dt = np.dtype(case["dtype"])
+        code, tdt = (ttx.F32, torch.float32) if dt == np.float32 else (ttx.F64, torch.float64)
+        es = dt.itemsize
+        sa, sb, sc = workloads.contraction_sizes(case)
+        la, lb, lc = case["labels_a"], case["labels_b"], case["labels_c"]
+        plan = ttx.ttx_contraction_create(code, la, sa, lb, sb, lc, sc)
+        try:
+            info = ttx.ttx_contraction_describe(plan)
+            m, n, k, panel = info["m"], info["n"], info["k"], info["panel"]
+            T = [torch.empty(int(np.prod(s, dtype=np.int64)), dtype=tdt, device="cuda") for s in (sa, sb, sc)]
+            for i, t in enumerate(T):
+                fill_uniform(torch, t, 60 + i)
+            ws = torch.empty(max(1, info["workspace_bytes"]), dtype=torch.uint8, device="cuda")
+
+            def run():
+                ttx.ttx_contraction_execute(plan, case["alpha"], T[0].data_ptr(), T[1].data_ptr(), case["beta"],
+                                            T[2].data_ptr(), ws.data_ptr(), stream)
+
+            for _ in range(2):
+                run()
+            _, t_all = time_events(torch, run, reps)
+        finally:
+            ttx.ttx_contraction_destroy(plan)
+        kb = 64 // panel
+        K = -(-k // kb) * kb
+        Pa = torch.empty(-(-m // panel) * panel * K, dtype=tdt, device="cuda")
+        Pb = torch.empty(-(-n // panel) * panel * K, dtype=tdt, device="cuda")
+        fill_uniform(torch, Pa, 70)
+        fill_uniform(torch, Pb, 71)
+        Cm = torch.empty(m * n, dtype=tdt, device="cuda")
+
+        def gemm():
+            ttx.ttx_gemm_panels(code, panel, m, n, k, Pa.data_ptr(), Pb.data_ptr(), Cm.data_ptr(), m, stream)
+
+        gemm()
+        _, t_gemm = time_events(torch, gemm, reps)
+        del Pa, Pb, Cm
+        # torch: column-major tensors are row-major ones with the modes reversed
+        ta = T[0].view(*reversed(sa)) if sa else T[0].view(())
+        tb = T[1].view(*reversed(sb)) if sb else T[1].view(())
+        con = [l for l in la if l in lb]
+        dims = ([len(la) - 1 - la.index(l) for l in con], [len(lb) - 1 - lb.index(l) for l in con])
+        free = [l for l in reversed(la) if l not in con] + [l for l in reversed(lb) if l not in con]
+        want = list(reversed(lc))
+        perm = [free.index(l) for l in want]
+
+        def torch_ttgt():
+            r = torch.tensordot(ta, tb, dims=dims).permute(*perm)
+            return T[2].view(*[case["extent"][l] for l in want]).mul_(case["beta"]).add_(r, alpha=case["alpha"])
+
+        torch_ttgt()
+        _, t_torch = time_events(torch, torch_ttgt, reps)
+        flops = 2.0 * m * n * k
+        rest_bytes = es * ((2 * m * k if info["transposed_a"] else 0) + (2 * k * n if info["transposed_b"] else 0)
+                           + m * k + -(-m // panel) * panel * K + k * n + -(-n // panel) * panel * K
+                           + m * n * (3 if case["beta"] != 0 else 2))
+        t_rest = max(t_all - t_gemm, 1e-9)
+        peak = 157.3 if code == ttx.F32 else 78.6
+        out.append(dict(case=case["name"], m=m, n=n, k=k, panel=panel, transposed_a=info["transposed_a"],
+                        transposed_b=info["transposed_b"], ms=round(t_all * 1e3, 3),
+                        TFLOPs=round(flops / t_all / 1e12, 2), gemm_ms=round(t_gemm * 1e3, 3),
+                        gemm_TFLOPs=round(flops / t_gemm / 1e12, 2), gemm_frac_of_peak=round(flops / t_gemm / 1e12 / peak, 3),
+                        rest_ms=round(t_rest * 1e3, 3), rest_bytes=rest_bytes,
+                        rest_GBps=round(rest_bytes / t_rest / 1e9, 1),
+                        rest_pct_of_d2d=round(100 * rest_bytes / t_rest / 1e9 / d2d, 1) if d2d else None,
+                        torch_tensordot_ms=round(t_torch * 1e3, 3),
+                        x_torch=round(t_torch / t_all, 2)))
+        log("  %s: %.3f ms (GEMM %.3f ms = %.1f TFLOP/s; rest %.3f ms) vs torch %.3f ms" % (
+            case["name"], t_all * 1e3, t_gemm * 1e3, flops / t_gemm / 1e12, t_rest * 1e3, t_torch * 1e3))
+        del T, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def side_cases():
     """Shapes timed beside the step: the multiple-leading-dimension and awkward
     shapes (FP64 sub-tensor (384,96,48,32) in outer sizes, (7,1023,33,65) with
@@ -931,6 +1018,10 @@ def compact_line(full, detail_path=None):
     pk = full.get("packing")
     if pk:
         line["packing_pct_of_d2d_min"] = min(o["pct_of_d2d"] for o in pk)
+    ct = full.get("contraction")
+    if ct:
+        line["contraction"] = {o["case"]: dict(ms=o["ms"], TFLOPs=o["TFLOPs"], gemm_frac_of_peak=o["gemm_frac_of_peak"],
+                                               x_torch=o["x_torch"]) for o in ct}
     sp = full.get("specialised")
     if sp:
         line["specialised_vs_generic_step"] = round(sp["step_GBps_specialised"] / sp["step_GBps_generic"], 3)
@@ -974,6 +1065,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print(json.dumps(bench_batched(torch, ttx, reps=5, tune=False)))
+        return 0
+    if args.only_contraction:
+        print(json.dumps(bench_contraction(torch, ttx, None, stream, reps=5)))
         return 0
     cases = make_cases(args.literal)
     log("allocating %d cases (%.1f GiB)" % (len(cases), sum(2 * c["elements"] * c["dtype"].itemsize for c in cases) / 2 ** 30))
@@ -1132,6 +1226,10 @@ def main():
         cplx = bench_types(torch, ttx, d2d, stream, args.tune_candidates, specialise=not args.generic)
         log("GEMM operand packing")
         packing = bench_packing(torch, ttx, d2d, stream, args.tune_candidates)
+    contraction = None
+    if not args.no_contraction and not args.profile_run:
+        log("tensor contractions (transpose-transpose-GEMM-transpose)")
+        contraction = bench_contraction(torch, ttx, d2d, stream)
     if args.save_table:
         ttx.ttx_tune_table_save(args.save_table)
 
@@ -1158,6 +1256,7 @@ def main():
         roofline=roofline, cpu_baseline=cpu, specialised=specialised, side=side, batched=batched, served=served,
         other_types=cplx,
         packing=packing,
+        contraction=contraction,
         tuning=dict(table=os.path.relpath(TABLE, ROOT) if os.path.exists(TABLE) else None,
                     shapes_tuned_now=tuned, seconds=round(tune_s, 1)),
         per_perm=per_case,

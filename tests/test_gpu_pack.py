@@ -147,3 +147,30 @@ def test_gemm_reads_mfma_panels_directly(dtype, panel):
         assert np.array_equal(C[:m].astype(np.float64), Am @ Bm), (m, n, k)
         assert (C[m:] == 7.0).all()
 
+
+
+@pytest.mark.parametrize("dtype,panel,mnk", [(F32, 16, (2053, 2050, 37)), (F32, 32, (4100, 4097, 9)),
+                                             (F64, 16, (2053, 2049, 21)), (F32, 32, (1600, 1600, 1600))],
+                         ids=["s16-2x2", "s32-2x2", "d16-2x2", "s32-1x1-deep"])
+def test_gemm_large_grids(dtype, panel, mnk):
+    """Grids large enough for 2 x 2 blocks per wave (with ragged edges in
+    both directions and a k that is not a whole chunk of blocks), and a deep
+    k with one block per wave: integer-valued operands, C compared exactly."""
+    import torch
+    m, n, k = mnk
+    rng = np.random.default_rng(m + n + k)
+    A = rng.integers(-3, 4, size=m * k).astype(dtype)
+    B = rng.integers(-3, 4, size=k * n).astype(dtype)
+    PA = _gpu_pack_mfma(ttx.PACK_MFMA_A, A, m, k, m, panel, 1.0, dtype)
+    PB = _gpu_pack_mfma(ttx.PACK_MFMA_B, B, k, n, k, panel, 1.0, dtype)
+    dA = torch.from_numpy(PA).cuda()
+    dB = torch.from_numpy(PB).cuda()
+    ldc = m + 3
+    dC = torch.full((ldc * n,), 7.0, dtype=dA.dtype, device="cuda")
+    ttx.ttx_gemm_panels(dtype_code(dtype), panel, m, n, k, dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), ldc,
+                        ttx.current_stream())
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().reshape(n, ldc).T
+    want = A.reshape(k, m).T.astype(np.float64) @ B.reshape(n, k).T.astype(np.float64)
+    assert np.array_equal(C[:m].astype(np.float64), want)
+    assert (C[m:] == 7.0).all()
