@@ -538,8 +538,15 @@ ttx_status ttx_batch_create(ttx_batch **batch, int count, const ttx_problem *pro
 /* Times the current config and up to max_candidates batched-menu configs
  * per distinct shape (0: 16) inside the persistent kernel on scratch
  * buffers, one problem at a time; another config replaces the current one
- * only when it is at least 5% faster.  Winners go into a process-wide
- * per-shape table; the descriptors are rebuilt.  Blocks. */
+ * only when it is at least 5% faster.  The tuned set is then checked in
+ * context: the whole persistent launch is timed with it and with the
+ * configs it replaced, alternately, on scratch buffers the size of the
+ * batch's footprint (the caller's tensors are not touched), and the kernel
+ * problems keep the tuned set only when it is at least 1% faster (else they
+ * return to their previous configs and this call's table entries are
+ * withdrawn; without the scratch memory the check is skipped).  Winners go
+ * into a process-wide per-shape table; the descriptors are rebuilt.
+ * Blocks. */
 ttx_status ttx_batch_tune(ttx_batch *batch, int max_candidates, int reps);
 /* One graph launch of the persistent kernel on `stream` (captured on first use).
  * Launches of one batch must not overlap each other (they share the batch's

@@ -10,6 +10,7 @@
 // prefix sums, and runs that problem's tile body over the chunk -- the same
 // tile code as the per-call kernels, pipelined across the chunk's tiles.  The
 // launch is captured once into a HIP graph and replayed.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -686,6 +687,84 @@ ttx_status ttx_batch_update(ttx_batch* b, int count, const ttx_problem* problems
 // A tuned batched configuration replaces the current one only when it is
 // faster by at least this fraction.
 static constexpr double kBatchTuneMargin = 0.05;
+// The tuned set must also win in context, by this much.
+static constexpr double kBatchContextMargin = 0.01;
+
+// Median time (ms) of `reps` persistent launches of the batch as described now.
+static double time_launches(ttx_batch* b, hipStream_t s, int reps, hipEvent_t* ev) {
+    std::vector<float> ms;
+    for (int r = -1; r < reps; ++r) {   // r = -1: warm-up
+        if (hipEventRecord(ev[0], s) != hipSuccess) return -1;
+        if (launch_batch(work_desc(b), work_prefix(b), b->nk, b->chunks, b->grid, work_counter(b), s) != hipSuccess)
+            return -1;
+        if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) return -1;
+        float t = 0;
+        if (hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess) return -1;
+        if (r >= 0) ms.push_back(t);
+    }
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+}
+
+// Whether the configs now in `b` (the tuned set) run the whole persistent
+// launch faster than `old_cfg` / `old_forced` (the set they replaced): both
+// are timed in alternation on scratch copies of the batch's footprint (the
+// kernel problems' A and B extents, each at its pointer's offset modulo 16
+// bytes, so that every problem runs the same vector variant), never on the
+// caller's tensors.  When the scratch cannot be allocated the tuned set is
+// kept.  Leaves `b` described with the tuned set and the real pointers.
+static bool tuned_set_wins(ttx_batch* b, const std::vector<ttx_config>& old_cfg, const std::vector<int>& old_forced,
+                           int reps) {
+    const std::vector<ttx_config> new_cfg = b->cfg;
+    const std::vector<int> new_forced = b->forced;
+    const std::vector<ttx_problem> real = b->src;
+    std::vector<int64_t> off_a(b->prob.size(), -1), off_b(b->prob.size(), -1);
+    int64_t total = 0;
+    for (size_t i = 0; i < b->prob.size(); ++i) {
+        const Problem& p = b->prob[i];
+        if (p.family == TTX_FAMILY_EMPTY || runs_per_call(p)) continue;
+        off_a[i] = total + int64_t(reinterpret_cast<uintptr_t>(real[i].A) & 15);
+        total += (p.extent_a + 16 + 255) / 256 * 256;
+        off_b[i] = total + int64_t(reinterpret_cast<uintptr_t>(real[i].B) & 15);
+        total += (p.extent_b + 16 + 255) / 256 * 256;
+    }
+    unsigned char* scratch = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ok = total > 0 && hipMalloc(reinterpret_cast<void**>(&scratch), size_t(total)) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    ok = ok && hipMemsetAsync(scratch, 0, size_t(total), s) == hipSuccess;
+    double t_new = 0, t_old = 0;
+    if (ok) {
+        for (size_t i = 0; i < b->prob.size(); ++i) {
+            if (off_a[i] < 0) continue;
+            b->src[i].A = scratch + off_a[i];
+            b->src[i].B = scratch + off_b[i];
+            b->src[i].B_in = nullptr;
+        }
+        for (int round = 0; round < 2 && ok; ++round) {
+            for (int set = 0; set < 2 && ok; ++set) {
+                b->cfg = set == 0 ? new_cfg : old_cfg;
+                b->forced = set == 0 ? new_forced : old_forced;
+                ok = describe_all(b) == TTX_OK && upload(b, s) == TTX_OK;
+                const double t = ok ? time_launches(b, s, reps, ev) : -1;
+                ok = ok && t > 0;
+                (set == 0 ? t_new : t_old) += t;
+            }
+        }
+    }
+    if (!ok) (void)hipGetLastError();   // no in-context check: the tuned set stays
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    if (s) (void)hipStreamDestroy(s);
+    if (scratch) (void)hipFree(scratch);
+    b->src = real;
+    b->cfg = new_cfg;
+    b->forced = new_forced;
+    clear_error();
+    return !ok || t_new < t_old * (1.0 - kBatchContextMargin);
+}
 
 ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
@@ -704,6 +783,10 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
     uint32_t* d_cnt = reinterpret_cast<uint32_t*>(d_blk + counter_offset(1));
     ttx_status result = TTX_OK;
     std::vector<ttx_config> cands(4096);
+    const std::vector<ttx_config> old_cfg = b->cfg;
+    const std::vector<int> old_forced = b->forced;
+    std::vector<std::string> added;   // per-shape table keys this call adds
+    bool changed = false;             // a kernel problem's config differs from the one it started with
     for (size_t i = 0; i < b->prob.size() && result == TTX_OK; ++i) {
         const Problem& p = b->prob[i];
         if (p.family == TTX_FAMILY_EMPTY) continue;
@@ -725,6 +808,7 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
             std::lock_guard<std::mutex> lock(g_btab_mu);
             auto it = g_btab.find(key);
             if (it != g_btab.end()) {
+                changed = changed || std::memcmp(&b->cfg[i], &it->second, sizeof(ttx_config)) != 0;
                 b->cfg[i] = it->second;
                 b->forced[i] = 1;
                 continue;
@@ -766,17 +850,30 @@ ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
         if (result == TTX_OK && best_i > 0 && best_us < us[0] * (1.0 - kBatchTuneMargin)) {
             b->cfg[i] = cands[best_i];
             b->forced[i] = 1;
+            changed = true;
             std::lock_guard<std::mutex> lock(g_btab_mu);
             g_btab[key] = cands[best_i];
+            added.push_back(key);
         }
     }
     (void)hipFree(d_blk);
     if (result != TTX_OK) return result;
-    const uint32_t old_chunks = b->chunks;
-    const int old_grid = b->grid;
+    // Timing one problem alone ranks close candidates differently from the
+    // full batch, so the tuned set must also win in context; otherwise the
+    // kernel problems go back to the configs they started with (per-call
+    // problems keep their tuned configs: they run alone in any case).
+    if (changed && b->nk > 0 && !tuned_set_wins(b, old_cfg, old_forced, std::max(reps, 5))) {
+        for (size_t i = 0; i < b->prob.size(); ++i)
+            if (!runs_per_call(b->prob[i])) {
+                b->cfg[i] = old_cfg[i];
+                b->forced[i] = old_forced[i];
+            }
+        std::lock_guard<std::mutex> lock(g_btab_mu);
+        for (const std::string& k : added) g_btab.erase(k);
+    }
     ttx_status st = describe_all(b);
     if (st != TTX_OK) return st;
-    if (b->chunks != old_chunks || b->grid != old_grid) drop_graph(b);
+    drop_graph(b);   // descriptors, chunk count or grid may have changed
     return upload(b, nullptr);
 }
 

@@ -340,10 +340,12 @@ def _kind(c):
     (ttx.F32, (1, 0), (7, 3000)), (ttx.C64, (2, 1, 0), (33, 40, 27))])
 def test_every_workgroup_variant_bit_identical(code, perm, size):
     """The best-ranked candidate of each tile kind (menu, staged, dense) in
-    every workgroup variant (ttx_tune_variants: 64..512 threads, LDS row
-    padding 0..4), each run as a size-specialised kernel compiled for it,
-    gives the oracle's bits at beta = 0.7; the 64- and 512-thread variants
-    also at beta = 0."""
+    its workgroup variants (ttx_tune_variants) along each knob: every thread
+    count (64..512) at LDS row padding 1, and every padding (0..4) at 256
+    threads, each run as a size-specialised kernel compiled for it, gives
+    the oracle's bits at beta = 0.7; the 64- and 512-thread variants also at
+    beta = 0.  (The knobs are independent template constants of one tile
+    code; their cross product is left to the tuner's own runs.)"""
     from gpu_util import TYPES_OF_CODE
     da, db = TYPES_OF_CODE[code]
     cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
@@ -361,6 +363,7 @@ def test_every_workgroup_variant_bit_identical(code, perm, size):
     for kind, base in sorted(bases.items()):
         variants = ttx.ttx_tune_variants(code, perm, size, base)
         assert len(variants) >= 2 or base.family == ttx.FAMILY_FLAT, kind
+        variants = [v for v in variants if v.lds_pad == 1 or v.threads == 256]
         print("%s: %d variants of %s" % (kind, len(variants), base.as_dict()), flush=True)
         for v in variants:
             for beta in ((0.7, 0.0) if v.threads in (64, 512) else (0.7,)):
@@ -377,7 +380,7 @@ def test_every_workgroup_variant_bit_identical(code, perm, size):
     (ttx.F32_F64, (1, 2, 0), (129, 17, 31))])
 def test_line_aligned_a_runs_bit_identical(code, perm, size):
     """TTX_CFG_ALIGN_A (tile ranges along A's run start on 128-byte lines):
-    every moved menu candidate over a contiguous A run, and its 64- and
+    the four best-ranked moved tile shapes over a contiguous A run, and its 64- and
     512-thread variants, with the flag set gives the oracle's bits at both
     beta classes, also with misaligned pointers."""
     from gpu_util import TYPES_OF_CODE
@@ -398,7 +401,7 @@ def test_line_aligned_a_runs_bit_identical(code, perm, size):
         except ttx.TTXError:
             continue   # A's run is not contiguous for these groups
         picks += [v for v in variants if v.threads in (64, 256, 512) and v.lds_pad == 1]
-        if len(seen) >= 8:   # the 8 best-ranked moved tile shapes (each config is compiled)
+        if len(seen) >= 4:   # the 4 best-ranked moved tile shapes (each config is compiled)
             break
     assert picks, "no candidate takes line-aligned A runs"
     n = _elems(size)
@@ -621,9 +624,13 @@ def test_grouped_order_bit_identical(code, perm, size):
         alpha = (1.25 + 0.5j) if cx else 1.3
         ref = B.copy()
         oracle.transpose(perm, size, alpha, A, beta, ref)
+        specialised = {}
         for c in pick:
             c.flags |= ttx.CFG_GROUPED
             got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c)
             assert_parity(got, ref, exact=True, what=str(c.as_dict()))
-            got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c, specialise=True)
-            assert_parity(got, ref, exact=True, what="specialised " + str(c.as_dict()))
+            # size-specialised too for the two best-ranked tiles of each kind (each one is compiled)
+            if specialised.get(_kind(c), 0) < 2:
+                specialised[_kind(c)] = specialised.get(_kind(c), 0) + 1
+                got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c, specialise=True)
+                assert_parity(got, ref, exact=True, what="specialised " + str(c.as_dict()))
