@@ -351,6 +351,16 @@ ttx_status ttx_tune_candidates(ttx_dtype dtype, int n, const int *perm, const in
 ttx_status ttx_tune_variants(ttx_dtype dtype, int n, const int *perm, const int64_t *size,
                              const int64_t *outer_a, const int64_t *outer_b, const ttx_config *base,
                              ttx_config *out, int cap, int *count);
+/* The tile shapes of a kernel family (TTX_FAMILY_MOVED or
+ * TTX_FAMILY_PRESERVED) for a dtype (B's type of a mixed code): with
+ * run_time_only = 0 the pre-compiled menu (Sec. 2.2 blockings); with
+ * run_time_only = 1 the larger moved-family tiles that exist only as
+ * size-specialised kernels compiled at run time (256- to 512-byte runs on
+ * both sides; valid in any config of a moved problem, which then always
+ * runs its run-time compiled kernel).  Up to `cap` shapes go to tile_a[],
+ * tile_b[]; *count receives how many there are. */
+ttx_status ttx_tile_shapes(ttx_dtype dtype, int family, int run_time_only, int *tile_a, int *tile_b, int cap,
+                           int *count);
 /* Tune table persistence (one text line per entry) and reset. */
 ttx_status ttx_tune_table_save(const char *path);
 ttx_status ttx_tune_table_load(const char *path);

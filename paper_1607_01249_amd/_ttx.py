@@ -209,6 +209,7 @@ def _declare(L):
                                  ctypes.POINTER(ctypes.c_double), S, ip], S),
         "ttx_tune_variants": ([S, S, ip, i64p, i64p, i64p, ctypes.POINTER(Config), ctypes.POINTER(Config),
                                S, ip], S),
+        "ttx_tile_shapes": ([S, S, S, ip, ip, S, ip], S),
         "ttx_tune_table_save": ([ctypes.c_char_p], S),
         "ttx_tune_table_load": ([ctypes.c_char_p], S),
         "ttx_tune_table_clear": ([], S),
@@ -582,6 +583,16 @@ def ttx_copy_kernel(src, dst, nbytes, stream=0):
 def ttx_gemm_panels(dtype, panel, m, n, k, Pa, Pb, C, ldc, stream=0):
     """C (m x n, column-major, ldc) = A * B from matrix-core operand panels."""
     return _check(lib().ttx_gemm_panels(dtype, int(panel), int(m), int(n), int(k), Pa, Pb, C, int(ldc), stream))
+
+
+def ttx_tile_shapes(dtype, family, run_time_only=False):
+    """[(tile_a, tile_b)] of a family's pre-compiled menu, or of its run-time-only large tiles."""
+    count = ctypes.c_int()
+    _check(lib().ttx_tile_shapes(dtype, family, int(bool(run_time_only)), None, None, 0, ctypes.byref(count)))
+    ta = (ctypes.c_int * max(1, count.value))()
+    tb = (ctypes.c_int * max(1, count.value))()
+    _check(lib().ttx_tile_shapes(dtype, family, int(bool(run_time_only)), ta, tb, count.value, ctypes.byref(count)))
+    return [(ta[i], tb[i]) for i in range(count.value)]
 
 
 def ttx_contraction_create(dtype, labels_a, size_a, labels_b, size_b, labels_c, size_c):

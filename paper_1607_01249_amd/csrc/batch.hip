@@ -330,7 +330,7 @@ ttx_status batch_describe(const Problem& p, const ttx_config* forced, bool beta0
     const bool vec = vector_ok(p, A, beta0 ? nullptr : Bsrc, Bdst);
     // the persistent kernel's variants run 256 threads with one element of
     // LDS padding: a config for another workgroup shape takes the heuristic
-    ttx_config c = forced && !config_needs_jit(*forced) ? *forced : batch_default(p, vec);
+    ttx_config c = forced && !config_needs_jit(p, *forced) ? *forced : batch_default(p, vec);
     if (c.family != p.family) return fail(TTX_EINVAL, "config family does not match the problem");
     if (config_is_wide(c)) return fail(TTX_EINVAL, "whole-unit rows are for per-call launches only");
     c.flags &= ~TTX_CFG_XCD_SWIZZLE;  // tile ids are global in the persistent launch

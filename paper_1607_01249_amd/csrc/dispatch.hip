@@ -192,7 +192,7 @@ hipError_t launch_tiles(const Problem& p, const ttx_config& c, bool beta0, const
     }
     TiledLaunch L;
     if (!prepare_tiled(p, c, beta0, A, Bsrc, Bdst, alpha, beta, &L)) return hipErrorInvalidValue;
-    if (config_needs_jit(L.c)) {
+    if (config_needs_jit(L.p, L.c)) {
         // no pre-compiled kernel for this workgroup size or LDS padding: the
         // size-specialised one (compiled on first use, then cached)
         const JitKernel* k = nullptr;
@@ -235,7 +235,7 @@ std::string kernel_name(const Problem& p, const ttx_config& c, bool beta0, const
     }
     TiledLaunch L;
     if (!prepare_tiled(p, c, beta0, A, Bsrc, const_cast<void*>(Bdst), Scalar(1.0), Scalar(0.0), &L)) return "";
-    if (config_needs_jit(L.c)) return jit_entry_name(L);
+    if (config_needs_jit(L.p, L.c)) return jit_entry_name(L);
     const std::string ts = types(L.p);
     const char* nt = (L.flags & KF_NT_STORE) ? "true" : "false";
     switch (L.kind) {

@@ -32,6 +32,13 @@
     X(24, 8) X(24, 16) X(24, 24) X(24, 32) X(32, 8) X(32, 16) X(32, 24) X(32, 32)          \
     X(2, 128) X(4, 64) X(128, 2) X(64, 4) X(64, 16) X(16, 64)
 
+// Larger moved-family tiles, compiled only at run time as size-specialised
+// kernels (no pre-compiled instance): runs of 256 to 512 bytes on both sides,
+// for the shape search around the tuner's fastest blockings.  X(tile_a, tile_b)
+#define TTX_MOVED_LARGE_F32(X) X(64, 128) X(128, 64) X(96, 128) X(128, 96)
+#define TTX_MOVED_LARGE_F64(X) X(32, 128) X(128, 32) X(64, 96) X(96, 64)
+#define TTX_MOVED_LARGE_C64(X) X(32, 64) X(64, 32) X(48, 64) X(64, 48)
+
 // X(tile_a, rows)
 #define TTX_PRESERVED_MENU_F32(X)                                                         \
     X(16, 64) X(16, 256) X(32, 32) X(32, 128) X(64, 16) X(64, 64) X(128, 8) X(128, 32)    \

@@ -79,6 +79,26 @@ bool tile_in_menu(int dtype, int family, int ta, int tb) {
     return false;
 }
 
+#define TTX_SHAPE(a, b) {a, b},
+static const TileShape kLargeF32[] = {TTX_MOVED_LARGE_F32(TTX_SHAPE)};
+static const TileShape kLargeF64[] = {TTX_MOVED_LARGE_F64(TTX_SHAPE)};
+static const TileShape kLargeC64[] = {TTX_MOVED_LARGE_C64(TTX_SHAPE)};
+#undef TTX_SHAPE
+
+int large_tile_menu(int dtype, const TileShape** shapes) {
+    if (dtype == TTX_F32) return *shapes = kLargeF32, TTX_COUNT(kLargeF32);
+    if (dtype == TTX_C64) return *shapes = kLargeC64, TTX_COUNT(kLargeC64);
+    return *shapes = kLargeF64, TTX_COUNT(kLargeF64);
+}
+
+bool tile_in_large_menu(int dtype, int ta, int tb) {
+    const TileShape* s;
+    const int n = large_tile_menu(dtype, &s);
+    for (int i = 0; i < n; ++i)
+        if (s[i].ta == ta && s[i].tb == tb) return true;
+    return false;
+}
+
 // ---------------------------------------------------------------------------------------
 // Problem construction
 ttx_status make_problem(int dtype, int n, const int* perm, const int64_t* size,
@@ -494,7 +514,8 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     } else if (L.staged) {
         if (!staged_in_menu(p.dtype, staged_lanes(p.dim[0].size), c.tile_a, c.tile_b))
             return bad("staged tile shape not in menu");
-    } else if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b)) {
+    } else if (!tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b) &&
+               !(p.family == TTX_FAMILY_MOVED && tile_in_large_menu(p.dtype, c.tile_a, c.tile_b))) {
         return bad("tile shape not in menu");
     }
     const int aln = config_align_elems(c, elem_bytes(p.dtype_a));

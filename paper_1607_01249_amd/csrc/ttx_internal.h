@@ -143,6 +143,9 @@ int kernel_flags(const Problem& p, const ttx_config& c, const void* A, const voi
 // Kernel menu (tile shapes the library instantiates), per dtype and family.
 int tile_menu(int dtype, int family, const TileShape** shapes);
 bool tile_in_menu(int dtype, int family, int ta, int tb);
+// The larger moved-family tiles that exist only as run-time compiled kernels.
+int large_tile_menu(int dtype, const TileShape** shapes);
+bool tile_in_large_menu(int dtype, int ta, int tb);
 // Staged preserved tiles: row-lane count for a row length (16, 32 or 64; 0 if
 // the rows are too long to stage) and whether (n0_max, tx, ty) is instantiated.
 int staged_lanes(int64_t n0);
@@ -168,10 +171,16 @@ inline bool config_uses_pad(const ttx_config& c) {
 // The LDS row padding in effect (1, the pre-compiled kernels', where none applies).
 inline int config_pad(const ttx_config& c) { return config_uses_pad(c) ? c.lds_pad : 1; }
 // Whether the config runs outside the pre-compiled kernels (another
-// workgroup size or LDS padding): then it always runs a size-specialised
-// kernel, compiled on first use.
+// workgroup size or LDS padding, line-aligned A runs): then it always runs a
+// size-specialised kernel, compiled on first use.
 inline bool config_needs_jit(const ttx_config& c) {
     return c.threads != kThreads || config_pad(c) != 1 || (c.flags & TTX_CFG_ALIGN_A);
+}
+// The same, also true for a moved tile of the run-time-only list (a shape
+// outside the pre-compiled menu).
+inline bool config_needs_jit(const Problem& p, const ttx_config& c) {
+    return config_needs_jit(c) || (p.family == TTX_FAMILY_MOVED && !config_is_dense(c) &&
+                                   !tile_in_menu(p.dtype, p.family, c.tile_a, c.tile_b));
 }
 // Elements of A per 128-byte line for line-aligned A runs (TTX_CFG_ALIGN_A; 0 when off).
 inline int config_align_elems(const ttx_config& c, int elem_bytes_a) {

@@ -261,7 +261,7 @@ static ttx_status tune_variants(const Problem& p, bool beta0, const std::vector<
             for (const ttx_config& c : vars) dup |= std::memcmp(&c, &buf[v], sizeof(c)) == 0;
             if (dup) continue;
             const JitKernel* k = nullptr;
-            if (specialised || config_needs_jit(buf[v])) {
+            if (specialised || config_needs_jit(p, buf[v])) {
                 TiledLaunch L;
                 void* a = reinterpret_cast<void*>(uintptr_t(1) << 20);
                 void* bb = reinterpret_cast<void*>(uintptr_t(3) << 20);
@@ -469,6 +469,26 @@ ttx_status ttx_tune_variants(ttx_dtype dtype, int n, const int* perm, const int6
     std::string why;
     if (!config_valid(p, *base, &why)) return fail(TTX_EINVAL, why);
     *count = workgroup_variants(p, *base, out, cap);
+    return TTX_OK;
+}
+
+ttx_status ttx_tile_shapes(ttx_dtype dtype, int family, int run_time_only, int* tile_a, int* tile_b, int cap,
+                           int* count) {
+    if (!count || cap < 0 || (cap > 0 && (!tile_a || !tile_b))) return fail(TTX_EINVAL, "NULL argument or negative cap");
+    if (!dtype_valid(dtype)) return fail(TTX_EINVAL, "unknown dtype");
+    if (family != TTX_FAMILY_MOVED && family != TTX_FAMILY_PRESERVED)
+        return fail(TTX_EINVAL, "tile shapes exist for the moved and preserved families");
+    const TileShape* s = nullptr;
+    int n = 0;
+    if (!run_time_only)
+        n = tile_menu(dtype_b_of(dtype), family, &s);
+    else if (family == TTX_FAMILY_MOVED)
+        n = large_tile_menu(dtype_b_of(dtype), &s);
+    for (int i = 0; i < n && i < cap; ++i) {
+        tile_a[i] = s[i].ta;
+        tile_b[i] = s[i].tb;
+    }
+    *count = n;
     return TTX_OK;
 }
 

@@ -13,7 +13,7 @@ least `--margin` in every round.  The result is written as `j:` entries of
 a new table file (the generic entries are copied unchanged).
 
     python paper_1607_01249_amd/tune/refine_workgroups.py IN OUT [--cases large|complex|mixed|all]
-           [--only NAME ...] [--shapes]
+           [--only NAME ...] [--shapes] [--large-only]
 
 Needs a GPU.  Blocks for a few seconds per problem.
 """
@@ -61,18 +61,37 @@ def _timed(ttx, torch, plan, case, pairs, stream, launches=13):
     return statistics.median(ev[r].elapsed_time(ev[r + 1]) * 1e3 for r in range(launches))
 
 
+def large_variants(ttx, code, perm, size, base):
+    """The base with each run-time-only large moved tile instead of its own,
+    at 256 and 512 threads, line-aligned A runs on and off (moved bases only)."""
+    if base.family != ttx.FAMILY_MOVED or base.flags & ttx.CFG_DENSE:
+        return []
+    out = []
+    for ta, tb in ttx.ttx_tile_shapes(code, ttx.FAMILY_MOVED, run_time_only=True):
+        for threads in (256, 512):
+            for align in (0, ttx.CFG_ALIGN_A):
+                v = ttx.Config.from_buffer_copy(base)
+                v.tile_a, v.tile_b, v.threads, v.lds_pad = ta, tb, threads, 1
+                v.flags = (v.flags & ~ttx.CFG_ALIGN_A) | align
+                out.append(v)
+    return out
+
+
 def shape_variants(ttx, code, perm, size, base):
     """Moved-family configs with the base's index groups, loop order and
-    flags and every other tile shape of the menu that fits this layout,
+    flags and every other tile shape of the menu that fits this layout (and
+    every run-time-only large tile),
     each at 256 and 512 threads per workgroup, with line-aligned A runs on
     and off where they apply (the first search stage ranks shapes at 256
     threads only)."""
     if base.family != ttx.FAMILY_MOVED or base.flags & ttx.CFG_DENSE:
         return []
     cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
-    shapes = sorted({(c.tile_a, c.tile_b) for c in cands
-                     if c.family == ttx.FAMILY_MOVED and not c.flags & ttx.CFG_DENSE and
-                     (c.group_a, c.group_b) == (base.group_a, base.group_b)})
+    shapes = {(c.tile_a, c.tile_b) for c in cands
+              if c.family == ttx.FAMILY_MOVED and not c.flags & ttx.CFG_DENSE and
+              (c.group_a, c.group_b) == (base.group_a, base.group_b)}
+    # and the larger tiles that exist only as run-time compiled kernels
+    shapes = sorted(shapes | set(ttx.ttx_tile_shapes(code, ttx.FAMILY_MOVED, run_time_only=True)))
     out = []
     for ta, tb in shapes:
         for threads in (256, 512):
@@ -85,9 +104,10 @@ def shape_variants(ttx, code, perm, size, base):
     return out
 
 
-def refine(cases, rounds=2, margin=0.02, log=print, shapes=False):
+def refine(cases, rounds=2, margin=0.02, log=print, shapes=False, large_only=False):
     """{key: (config, usec)} of the variants that beat their base (with
-    shapes, also the other menu tile shapes of moved-family bases)."""
+    shapes, also the other menu tile shapes of moved-family bases; with
+    large_only, the base against its large run-time-only tiles alone)."""
     import torch
     import paper_1607_01249_amd as ttx
     stream = ttx.current_stream()
@@ -104,9 +124,12 @@ def refine(cases, rounds=2, margin=0.02, log=print, shapes=False):
             ttx.ttx_plan_destroy(plan)
         if info["family"] not in ("moved", "preserved"):
             continue
-        variants = ttx.ttx_tune_variants(code, perm, size, base)
-        if shapes:
-            variants += shape_variants(ttx, code, perm, size, base)
+        if large_only:
+            variants = [base] + large_variants(ttx, code, perm, size, base)
+        else:
+            variants = ttx.ttx_tune_variants(code, perm, size, base)
+            if shapes:
+                variants += shape_variants(ttx, code, perm, size, base)
         bufs = [(torch.empty(max(1, info["extent_a_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1),
                  torch.empty(max(1, info["extent_b_bytes"] // 4 + 4), dtype=torch.float32, device="cuda").uniform_(-1, 1))
                 for _ in range(3)]
@@ -186,6 +209,8 @@ def main():
     ap.add_argument("--shapes", action="store_true",
                     help="also try the other menu tile shapes of moved-family bases (256/512 threads, "
                          "line-aligned A runs on and off)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="time each base against its run-time-only large moved tiles only")
     args = ap.parse_args()
     import paper_1607_01249_amd as ttx
     ttx.ttx_tune_table_clear()
@@ -193,7 +218,8 @@ def main():
     cases = bench_cases(args.cases)
     if args.only:
         cases = [c for c in cases if c["name"] in args.only]
-    entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True), shapes=args.shapes)
+    entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True), shapes=args.shapes,
+                     large_only=args.large_only)
     write_table(args.table_in, args.table_out, entries)
     print("%d of %d entries refined -> %s" % (len(entries), len(cases), args.table_out), flush=True)
 

@@ -245,3 +245,41 @@ def test_full_size_specialised(dtype, perm, beta_zero):
     size = workloads.LARGE_SHAPES[(rank, dtype)]
     _say("full-size specialised %s %s %s beta0=%s" % (np.dtype(dtype).name, perm, size, beta_zero))
     _check(perm, size, dtype, dtype, beta_zero, seed=30)
+
+
+@pytest.mark.parametrize("code,perm,size", [
+    (ttx.F32, (3, 2, 1, 0), (150, 7, 13, 140)), (ttx.F64, (2, 1, 0), (200, 9, 131)),
+    (ttx.C64, (1, 0, 2), (70, 66, 3)), (ttx.F32_F64, (4, 3, 2, 1, 0), (33, 5, 6, 7, 90))])
+def test_large_run_time_tiles_match_the_oracle(code, perm, size):
+    """Every run-time-only large moved tile (each compiled at run time), at
+    256 and 512 threads with line-aligned A runs on and off, ragged at both
+    tile edges: the oracle's bits at both beta classes."""
+    from gpu_util import TYPES_OF_CODE
+    da, db = TYPES_OF_CODE[code]
+    n = workloads.elements(size)
+    A = workloads.uniform(n, da, 40)
+    B = workloads.uniform(n, db, 41)
+    plan = ttx.ttx_plan_create(code, perm, size)
+    try:
+        base = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(plan)["config_raw"][0])
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    assert base.family == ttx.FAMILY_MOVED
+    cx = db in (C32, C64)
+    for k, shape in enumerate(ttx.ttx_tile_shapes(code, ttx.FAMILY_MOVED, run_time_only=True)):
+        c = ttx.Config.from_buffer_copy(base)
+        c.tile_a, c.tile_b, c.threads, c.lds_pad = shape[0], shape[1], (256, 512)[k % 2], 1
+        c.flags &= ~(ttx.CFG_DENSE | ttx.CFG_WIDE | ttx.CFG_ALIGN_A)
+        for beta in ((0.5 - 0.25j, 0j) if cx else (0.7, 0.0)):
+            alpha = (1.25 + 0.5j) if cx else 1.3
+            ref = B.copy()
+            assert oracle.transpose(perm, size, alpha, A, beta, ref) == 0
+            for align in (0, ttx.CFG_ALIGN_A):
+                c.flags = (c.flags & ~ttx.CFG_ALIGN_A) | align
+                _say("large %s align=%d beta=%s" % (shape, align, beta))
+                try:
+                    got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c)
+                except ttx.TTXError:
+                    assert align, "the large tile itself must be valid"
+                    continue   # line-aligned runs need a contiguous A run along the tile
+                assert_parity(got, ref, exact=True, what="%s %s" % (shape, c.as_dict()))

@@ -227,3 +227,56 @@ def test_variant_sources_compile_without_scratch(threads, pad):
         assert "__launch_bounds__(%d)" % threads in src
         r, log, code = _compile(src)
         assert r == 0 and code, log[:3000]
+
+
+# -- larger moved tiles that exist only as run-time compiled kernels ------------------------
+def test_large_tile_shapes_are_listed_apart_from_the_menu():
+    for code in (ttx.F32, ttx.F64, ttx.C32, ttx.C64, ttx.F32_F64):
+        menu = set(ttx.ttx_tile_shapes(code, ttx.FAMILY_MOVED))
+        large = ttx.ttx_tile_shapes(code, ttx.FAMILY_MOVED, run_time_only=True)
+        assert menu and large and not menu & set(large), code
+        assert ttx.ttx_tile_shapes(code, ttx.FAMILY_PRESERVED, run_time_only=True) == []
+    with pytest.raises(ttx.TTXError):
+        ttx.ttx_tile_shapes(ttx.F32, ttx.FAMILY_FLAT)
+
+
+def _large_config(dtype, perm, size, shape, threads=256, align=False):
+    plan = ttx.ttx_plan_create(dtype, perm, size)
+    c = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(plan)["config_raw"][0])
+    c.tile_a, c.tile_b, c.threads, c.lds_pad = shape[0], shape[1], threads, 1
+    c.flags = (c.flags & ~(ttx.CFG_DENSE | ttx.CFG_WIDE | ttx.CFG_ALIGN_A)) | (ttx.CFG_ALIGN_A if align else 0)
+    return plan, c
+
+
+@pytest.mark.parametrize("dtype,perm,size", [(ttx.F32, (3, 2, 1, 0), (160, 160, 64, 32)),
+                                             (ttx.F64, (1, 0, 2), (300, 200, 3)),
+                                             (ttx.C64, (2, 1, 0), (70, 9, 66))])
+def test_large_tiles_run_only_as_specialised_kernels(dtype, perm, size):
+    """Each large shape is a valid config of a moved problem; even at the
+    pre-compiled workgroup shape (256 threads, padding 1) its kernel is the
+    run-time compiled one, and its source compiles with no scratch memory."""
+    for k, shape in enumerate(ttx.ttx_tile_shapes(dtype, ttx.FAMILY_MOVED, run_time_only=True)):
+        plan, c = _large_config(dtype, perm, size, shape, threads=(256, 512)[k % 2], align=k % 2 == 1)
+        try:
+            ttx.ttx_plan_set_config(plan, False, c)
+            name = ttx.ttx_plan_kernel_name(plan, 1.0, 1 << 20, 3 << 20)
+            assert name.startswith("ttx_jit_moved_") and "_%dx%d" % shape in name, name
+            src = ttx.ttx_plan_specialised_source(plan, False)
+        finally:
+            ttx.ttx_plan_destroy(plan)
+        if k < 2:   # two compilations per type
+            r, log, code = _compile(src)
+            assert r == 0 and code, log[:3000]
+
+
+def test_large_tiles_rejected_outside_the_moved_family():
+    plan = ttx.ttx_plan_create(ttx.F64, (0, 2, 1, 3), (160, 160, 32, 32))   # preserved
+    try:
+        c = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(plan)["config_raw"][0])
+        pres = set(ttx.ttx_tile_shapes(ttx.F64, ttx.FAMILY_PRESERVED))
+        c.tile_a, c.tile_b = next(s for s in ttx.ttx_tile_shapes(ttx.F64, ttx.FAMILY_MOVED, run_time_only=True)
+                                  if s not in pres)
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(plan, False, c)
+    finally:
+        ttx.ttx_plan_destroy(plan)
