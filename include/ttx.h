@@ -126,6 +126,10 @@ typedef enum ttx_family {
                                   tile along that index covers the shift), so runs whose
                                   length is not a multiple of the line cost whole lines;
                                   runs as a size-specialised kernel */
+#define TTX_CFG_PIPELINED 64   /* MOVED or PRESERVED tiles, not dense: a persistent grid of as
+                                  many workgroups as the device holds at once, each looping
+                                  over its tiles and issuing the next tile's loads before the
+                                  current tile's stores; runs as a size-specialised kernel */
 
 /* One implementation candidate (Sec. 2.2: blocking and loop order).
  *   tile_a  : tile extent along A's stride-1 index (merged index 0);

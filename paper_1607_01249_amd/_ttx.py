@@ -29,7 +29,7 @@ CODE_OF = {v: k for k, v in TYPES_OF.items()}
 OK, EINVAL, EPERM, EOVERLAP, EUNSUPPORTED, ENOMEM, EHIP, EBUSY, ENOTFOUND = range(9)
 FAMILY_EMPTY, FAMILY_FLAT, FAMILY_PRESERVED, FAMILY_MOVED = range(4)
 FAMILY_NAMES = {0: "empty", 1: "flat", 2: "preserved", 3: "moved"}
-CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE, CFG_WIDE, CFG_GROUPED, CFG_ALIGN_A = 1, 2, 4, 8, 16, 32
+CFG_XCD_SWIZZLE, CFG_NT_STORE, CFG_DENSE, CFG_WIDE, CFG_GROUPED, CFG_ALIGN_A, CFG_PIPELINED = 1, 2, 4, 8, 16, 32, 64
 PACK_ROWS, PACK_COLS, PACK_MFMA_A, PACK_MFMA_B = 0, 1, 2, 3
 DENSE_CAP = {F32: 1024, F64: 1024, C32: 1024, C64: 512}
 DENSE_CAP.update({code: DENSE_CAP[b] for code, (a, b) in TYPES_OF.items() if a != b})

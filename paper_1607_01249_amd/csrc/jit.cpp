@@ -39,7 +39,7 @@ struct JitKernel {
     std::string name;
     hipModule_t module;
     hipFunction_t fn;
-    uint32_t dense_grid;   // dense tiles: workgroups that fill the device with this kernel
+    uint32_t dense_grid;   // dense tiles and pipelined grids: workgroups that fill the device with this kernel
 };
 
 static const char* const kJitOptions[] = {"-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
@@ -61,7 +61,7 @@ static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 14695981039346656
 static std::string jit_key(const TiledLaunch& L) {
     const int head[] = {L.p.code,   L.kind,     L.va,        L.vb,           L.n0,
                         L.cap,      L.flags,    L.beta0 ? 1 : 0, L.c.tile_a, L.c.tile_b,
-                        L.c.threads, config_pad(L.c), L.c.flags & TTX_CFG_ALIGN_A};
+                        L.c.threads, config_pad(L.c), L.c.flags & (TTX_CFG_ALIGN_A | TTX_CFG_PIPELINED)};
     std::string k(reinterpret_cast<const char*>(head), sizeof(head));
     k.append(reinterpret_cast<const char*>(L.args), sizeof(TileArgsHost));
     return k;
@@ -84,6 +84,7 @@ std::string jit_entry_name(const TiledLaunch& L) {
     if (L.c.threads != kThreads) n += "_t" + std::to_string(L.c.threads);
     if (config_pad(L.c) != 1) n += "_p" + std::to_string(config_pad(L.c));
     if (L.c.flags & TTX_CFG_ALIGN_A) n += "_al";
+    if (L.c.flags & TTX_CFG_PIPELINED) n += "_pl";
     const std::string key = jit_key(L);
     char h[16];
     std::snprintf(h, sizeof(h), "_%08x", unsigned(fnv1a(key.data(), key.size()) & 0xffffffffu));
@@ -125,6 +126,7 @@ std::string jit_source(const TiledLaunch& L) {
             lds = 2 * L.cap;
             pipe = true;
     }
+    if (L.c.flags & TTX_CFG_PIPELINED) pipe = true;   // a persistent grid: tiles overlap
     std::string s;
     s.reserve(8192);
     s += "// size-specialised transposition kernel\n#include \"tile_kernels.h\"\n\n";
@@ -272,7 +274,7 @@ ttx_status jit_kernel(const TiledLaunch& L, const JitKernel** out) {
         return fail(TTX_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
     }
     k->dense_grid = 0;
-    if (L.kind == kTileDense) {
+    if (L.kind == kTileDense || (L.c.flags & TTX_CFG_PIPELINED)) {
         int nb = 0, cus = 0;
         if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, L.c.threads, 0) != hipSuccess || nb <= 0)
             nb = 4;
@@ -295,7 +297,8 @@ bool jit_matches(const JitKernel& k, const TiledLaunch& L) {
 
 hipError_t jit_launch(const JitKernel& k, const TiledLaunch& L, hipStream_t stream) {
     uint32_t grid = L.grid;
-    if (L.kind == kTileDense) grid = L.ntiles < k.dense_grid ? L.ntiles : k.dense_grid;
+    if (L.kind == kTileDense || (L.c.flags & TTX_CFG_PIPELINED))
+        grid = L.ntiles < k.dense_grid ? L.ntiles : k.dense_grid;
     void* params[] = {const_cast<unsigned char*>(L.args)};
     return hipModuleLaunchKernel(k.fn, grid, 1, 1, uint32_t(L.c.threads), 1, 1, 0, stream, params, nullptr);
 }

@@ -467,7 +467,7 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
         return bad("threads must be 64, 128, 256 or 512");
     if (c.lds_pad < 0 || c.lds_pad > TTX_MAX_LDS_PAD) return bad("lds_pad out of range");
     if (c.flags & ~(TTX_CFG_XCD_SWIZZLE | TTX_CFG_NT_STORE | TTX_CFG_DENSE | TTX_CFG_WIDE | TTX_CFG_GROUPED |
-                    TTX_CFG_ALIGN_A))
+                    TTX_CFG_ALIGN_A | TTX_CFG_PIPELINED))
         return bad("unknown flag");
     if (config_is_wide(c)) {
         if (!config_is_dense(c)) return bad("whole-unit rows are for dense tiles only");
@@ -487,6 +487,8 @@ bool config_valid(const Problem& p, const ttx_config& c, std::string* why) {
     }
     Layout L;
     if (!make_layout(p, c.group_a, c.group_b, &L)) return bad("invalid index groups for this problem");
+    if ((c.flags & TTX_CFG_PIPELINED) && (p.family == TTX_FAMILY_FLAT || config_is_dense(c)))
+        return bad("pipelined grids are for moved and preserved tiles (dense tiles always pipeline)");
     if (p.family == TTX_FAMILY_FLAT) {
         if (config_is_dense(c)) return bad("dense tiles need a moved or preserved problem");
         if (c.threads != kThreads) return bad("flat problems run 256 threads per workgroup");

@@ -171,10 +171,10 @@ inline bool config_uses_pad(const ttx_config& c) {
 // The LDS row padding in effect (1, the pre-compiled kernels', where none applies).
 inline int config_pad(const ttx_config& c) { return config_uses_pad(c) ? c.lds_pad : 1; }
 // Whether the config runs outside the pre-compiled kernels (another
-// workgroup size or LDS padding, line-aligned A runs): then it always runs a
-// size-specialised kernel, compiled on first use.
+// workgroup size or LDS padding, line-aligned A runs, a pipelined persistent
+// grid): then it always runs a size-specialised kernel, compiled on first use.
 inline bool config_needs_jit(const ttx_config& c) {
-    return c.threads != kThreads || config_pad(c) != 1 || (c.flags & TTX_CFG_ALIGN_A);
+    return c.threads != kThreads || config_pad(c) != 1 || (c.flags & (TTX_CFG_ALIGN_A | TTX_CFG_PIPELINED));
 }
 // The same, also true for a moved tile of the run-time-only list (a shape
 // outside the pre-compiled menu).

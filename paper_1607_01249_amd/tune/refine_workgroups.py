@@ -13,7 +13,7 @@ least `--margin` in every round.  The result is written as `j:` entries of
 a new table file (the generic entries are copied unchanged).
 
     python paper_1607_01249_amd/tune/refine_workgroups.py IN OUT [--cases large|complex|mixed|all]
-           [--only NAME ...] [--shapes] [--large-only]
+           [--only NAME ...] [--shapes] [--large-only] [--pipelined-only]
 
 Needs a GPU.  Blocks for a few seconds per problem.
 """
@@ -77,6 +77,21 @@ def large_variants(ttx, code, perm, size, base):
     return out
 
 
+def pipelined_variants(ttx, code, perm, size, base):
+    """The base as a pipelined persistent grid (TTX_CFG_PIPELINED), at its
+    own workgroup size and at the other of 256 and 512 threads (moved and
+    preserved bases, not dense ones)."""
+    if base.family not in (ttx.FAMILY_MOVED, ttx.FAMILY_PRESERVED) or base.flags & ttx.CFG_DENSE:
+        return []
+    out = []
+    for threads in sorted({base.threads, 512 if base.threads == 256 else 256}):
+        v = ttx.Config.from_buffer_copy(base)
+        v.flags |= ttx.CFG_PIPELINED
+        v.threads = threads
+        out.append(v)
+    return out
+
+
 def shape_variants(ttx, code, perm, size, base):
     """Moved-family configs with the base's index groups, loop order and
     flags and every other tile shape of the menu that fits this layout (and
@@ -104,10 +119,11 @@ def shape_variants(ttx, code, perm, size, base):
     return out
 
 
-def refine(cases, rounds=2, margin=0.02, log=print, shapes=False, large_only=False):
+def refine(cases, rounds=2, margin=0.02, log=print, shapes=False, large_only=False, pipelined_only=False):
     """{key: (config, usec)} of the variants that beat their base (with
     shapes, also the other menu tile shapes of moved-family bases; with
-    large_only, the base against its large run-time-only tiles alone)."""
+    large_only, the base against its large run-time-only tiles alone; with
+    pipelined_only, against its pipelined persistent grids alone)."""
     import torch
     import paper_1607_01249_amd as ttx
     stream = ttx.current_stream()
@@ -126,6 +142,8 @@ def refine(cases, rounds=2, margin=0.02, log=print, shapes=False, large_only=Fal
             continue
         if large_only:
             variants = [base] + large_variants(ttx, code, perm, size, base)
+        elif pipelined_only:
+            variants = [base] + pipelined_variants(ttx, code, perm, size, base)
         else:
             variants = ttx.ttx_tune_variants(code, perm, size, base)
             if shapes:
@@ -155,11 +173,15 @@ def refine(cases, rounds=2, margin=0.02, log=print, shapes=False, large_only=Fal
         best = min(range(len(variants)), key=lambda i: max(times[i]))
         gain = [1 - times[best][r] / times[0][r] for r in range(rounds)]
         kept = best != 0 and min(gain) >= margin
-        al = lambda c: "a" if c.flags & ttx.CFG_ALIGN_A else ""
-        log("%s: base %dx%d t%d p%d%s %.1f us, best %dx%d t%d p%d%s %.1f us (%+.1f%%)%s" % (
-            case["name"], base.tile_a, base.tile_b, base.threads, base.lds_pad, al(base), max(times[0]),
-            variants[best].tile_a, variants[best].tile_b, variants[best].threads, variants[best].lds_pad,
-            al(variants[best]), max(times[best]), -100 * min(gain), " -> kept" if kept else ""))
+        al = lambda c: ("a" if c.flags & ttx.CFG_ALIGN_A else "") + ("P" if c.flags & ttx.CFG_PIPELINED else "")
+        other = min(range(1, len(variants)), key=lambda i: max(times[i])) if len(variants) > 1 else 0
+        log("%s: base %dx%d t%d p%d%s %.1f us, best %dx%d t%d p%d%s %.1f us (%+.1f%%)%s; best other %dx%d t%d p%d%s "
+            "%.1f us" % (
+                case["name"], base.tile_a, base.tile_b, base.threads, base.lds_pad, al(base), max(times[0]),
+                variants[best].tile_a, variants[best].tile_b, variants[best].threads, variants[best].lds_pad,
+                al(variants[best]), max(times[best]), -100 * min(gain), " -> kept" if kept else "",
+                variants[other].tile_a, variants[other].tile_b, variants[other].threads, variants[other].lds_pad,
+                al(variants[other]), max(times[other])))
         if kept:
             out[table_key(info, z)] = (variants[best], max(times[best]))
         del bufs
@@ -211,6 +233,8 @@ def main():
                          "line-aligned A runs on and off)")
     ap.add_argument("--large-only", action="store_true",
                     help="time each base against its run-time-only large moved tiles only")
+    ap.add_argument("--pipelined-only", action="store_true",
+                    help="time each base against its pipelined persistent grids (TTX_CFG_PIPELINED) only")
     args = ap.parse_args()
     import paper_1607_01249_amd as ttx
     ttx.ttx_tune_table_clear()
@@ -219,7 +243,7 @@ def main():
     if args.only:
         cases = [c for c in cases if c["name"] in args.only]
     entries = refine(cases, args.rounds, args.margin, log=lambda m: print(m, flush=True), shapes=args.shapes,
-                     large_only=args.large_only)
+                     large_only=args.large_only, pipelined_only=args.pipelined_only)
     write_table(args.table_in, args.table_out, entries)
     print("%d of %d entries refined -> %s" % (len(entries), len(cases), args.table_out), flush=True)
 

@@ -283,3 +283,48 @@ def test_large_run_time_tiles_match_the_oracle(code, perm, size):
                     assert align, "the large tile itself must be valid"
                     continue   # line-aligned runs need a contiguous A run along the tile
                 assert_parity(got, ref, exact=True, what="%s %s" % (shape, c.as_dict()))
+
+
+@pytest.mark.parametrize("code,perm,size", [
+    (ttx.F32, (1, 0, 2), (3000, 3001, 3)), (ttx.F64, (2, 1, 0), (301, 40, 2500)),
+    (ttx.F32, (0, 2, 1, 3), (40, 90, 70, 13)), (ttx.F64, (0, 5, 1, 4, 2, 3), (20, 7, 4, 3, 5, 6)),
+    (ttx.C64, (2, 1, 0), (33, 40, 27)), (ttx.F32_F64, (3, 2, 1, 0), (5, 3, 70, 9))])
+def test_pipelined_grids_match_the_oracle(code, perm, size):
+    """TTX_CFG_PIPELINED (a resident grid whose workgroups loop over tiles,
+    loading the next tile before storing the current one) on the two
+    best-ranked candidates of each tile kind but dense, at 256 and 512
+    threads (moved tiles also with line-aligned A runs): the oracle's bits
+    at both beta classes.  The first two problems have several tiles per
+    resident workgroup."""
+    from gpu_util import TYPES_OF_CODE
+    da, db = TYPES_OF_CODE[code]
+    cands, _ = ttx.ttx_tune_candidates(code, perm, size, max_candidates=-1, cap=200000)
+    per_kind, picks = {}, []
+    for c in cands:
+        if c.flags & ttx.CFG_DENSE:
+            continue
+        kind = (c.family, c.group_a > 1 or c.group_b > 1)
+        if per_kind.get(kind, 0) < 2:
+            per_kind[kind] = per_kind.get(kind, 0) + 1
+            picks.append(c)
+    n = workloads.elements(size)
+    A = workloads.uniform(n, da, 50)
+    B = workloads.uniform(n, db, 51)
+    cx = db in (C32, C64)
+    for beta in ((0.5 - 0.25j, 0j) if cx else (0.7, 0.0)):
+        alpha = (1.25 + 0.5j) if cx else 1.3
+        ref = B.copy()
+        assert oracle.transpose(perm, size, alpha, A, beta, ref) == 0
+        for k, base in enumerate(picks):
+            c = ttx.Config.from_buffer_copy(base)
+            c.flags |= ttx.CFG_PIPELINED
+            c.threads = (256, 512)[k % 2]
+            if c.family == ttx.FAMILY_MOVED and k % 2:
+                c.flags |= ttx.CFG_ALIGN_A
+            _say("pipelined %s beta=%s" % (c.as_dict(), beta))
+            try:
+                got = gpu_transpose(perm, size, alpha, A, beta, B, plan_config=c)
+            except ttx.TTXError:
+                assert c.threads != 256 or c.flags & ttx.CFG_ALIGN_A, "the base config must stay valid"
+                continue   # the tile does not fit 512 threads, or no contiguous A run to align
+            assert_parity(got, ref, exact=True, what=str(c.as_dict()))

@@ -280,3 +280,41 @@ def test_large_tiles_rejected_outside_the_moved_family():
             ttx.ttx_plan_set_config(plan, False, c)
     finally:
         ttx.ttx_plan_destroy(plan)
+
+
+# -- pipelined persistent grids (TTX_CFG_PIPELINED) -------------------------------------------
+@pytest.mark.parametrize("dtype,perm,size,kind", [(ttx.F32, (3, 2, 1, 0), (160, 160, 64, 32), "moved"),
+                                                  (ttx.F64, (0, 2, 1, 3), (160, 160, 32, 32), "preserved"),
+                                                  (ttx.F32, (0, 5, 1, 4, 2, 3), (24, 21, 20, 18, 17, 17),
+                                                   None)])
+def test_pipelined_configs_run_specialised_and_pipe(dtype, perm, size, kind):
+    plan = ttx.ttx_plan_create(dtype, perm, size)
+    try:
+        c = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(plan)["config_raw"][0])
+        if c.flags & ttx.CFG_DENSE:   # dense tiles always pipeline: the flag is refused
+            c.flags |= ttx.CFG_PIPELINED
+            with pytest.raises(ttx.TTXError):
+                ttx.ttx_plan_set_config(plan, False, c)
+            return
+        assert kind is None or ttx.FAMILY_NAMES[c.family] == kind
+        c.flags |= ttx.CFG_PIPELINED
+        ttx.ttx_plan_set_config(plan, False, c)
+        name = ttx.ttx_plan_kernel_name(plan, 1.0, 1 << 20, 3 << 20)
+        assert name.startswith("ttx_jit_") and "_pl_" in name, name
+        src = ttx.ttx_plan_specialised_source(plan, False)
+        assert ", true, kHost," in src, src[-400:]
+    finally:
+        ttx.ttx_plan_destroy(plan)
+    r, log, code = _compile(src)
+    assert r == 0 and code, log[:3000]
+
+
+def test_pipelined_flag_refused_for_flat_problems():
+    plan = ttx.ttx_plan_create(ttx.F32, (0, 1), (64, 9))
+    try:
+        c = ttx.Config.from_buffer_copy(ttx.ttx_plan_describe(plan)["config_raw"][0])
+        c.flags |= ttx.CFG_PIPELINED
+        with pytest.raises(ttx.TTXError):
+            ttx.ttx_plan_set_config(plan, False, c)
+    finally:
+        ttx.ttx_plan_destroy(plan)
