@@ -150,12 +150,15 @@ def test_gemm_reads_mfma_panels_directly(dtype, panel):
 
 
 @pytest.mark.parametrize("dtype,panel,mnk", [(F32, 16, (2053, 2050, 37)), (F32, 32, (4100, 4097, 9)),
-                                             (F64, 16, (2053, 2049, 21)), (F32, 32, (1600, 1600, 1600))],
-                         ids=["s16-2x2", "s32-2x2", "d16-2x2", "s32-1x1-deep"])
+                                             (F64, 16, (2053, 2049, 21)), (F32, 32, (1600, 1600, 1600)),
+                                             (F64, 16, (333, 301, 701)), (F32, 16, (100, 37, 1003)),
+                                             (F32, 32, (40, 70, 250))],
+                         ids=["s16-2x2", "s32-2x2", "d16-2x2", "s32-deep", "d16-deep", "s16-deep", "s32-deep-small"])
 def test_gemm_large_grids(dtype, panel, mnk):
     """Grids large enough for 2 x 2 blocks per wave (with ragged edges in
-    both directions and a k that is not a whole chunk of blocks), and a deep
-    k with one block per wave: integer-valued operands, C compared exactly."""
+    both directions and a k that is not a whole chunk of blocks), and deep k
+    on small grids with one block per wave (ragged panels, k not a whole
+    number of chunks): integer-valued operands, C compared exactly."""
     import torch
     m, n, k = mnk
     rng = np.random.default_rng(m + n + k)
