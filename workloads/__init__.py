@@ -226,6 +226,8 @@ CONTRACTION_PARITY = [  # small: the oracle contracts them whole in well under a
     dict(name="matrix_vector", labels_a=(1, 0), labels_b=(1,), labels_c=(0,), extent={0: 100, 1: 77}),
     dict(name="empty_contracted", labels_a=(0, 2), labels_b=(2, 1), labels_c=(0, 1), extent={0: 8, 1: 9, 2: 0}),
     dict(name="empty_free", labels_a=(0, 2), labels_b=(2, 1), labels_c=(0, 1), extent={0: 0, 1: 9, 2: 5}),
+    dict(name="scalars", labels_a=(), labels_b=(), labels_c=(), extent={}),
+    dict(name="scalar_operand", labels_a=(1, 0), labels_b=(), labels_c=(0, 1), extent={0: 37, 1: 5}),
 ]
 
 
