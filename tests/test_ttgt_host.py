@@ -134,3 +134,55 @@ def test_every_parity_case_plans():
             assert d["n"] == int(np.prod([e[l] for l in d["order_n"]], dtype=np.int64))
             assert d["k"] == int(np.prod([e[l] for l in d["order_k"]], dtype=np.int64))
             assert sorted(d["order_m"] + d["order_n"]) == sorted(case["labels_c"])
+
+
+def _random_contraction(rng):
+    """Random labels: up to 3 free labels per operand and 3 contracted, shuffled per tensor."""
+    nm, nn, nk = (int(x) for x in rng.integers(0, 4, 3))
+    labels = list(rng.permutation(20)[:nm + nn + nk])
+    M, N, K = labels[:nm], labels[nm:nm + nn], labels[nm + nn:]
+    ext = {l: int(rng.integers(1, 5)) for l in labels}
+    la = list(rng.permutation(M + K)) if rng.random() < 0.6 else M + K   # often already a matrix
+    lb = list(rng.permutation(K + N)) if rng.random() < 0.6 else (K + N if rng.random() < 0.5 else N + K)
+    lc = list(rng.permutation(M + N))
+    return [int(x) for x in la], [int(x) for x in lb], [int(x) for x in lc], ext
+
+
+def test_random_plans_are_consistent_and_replay_to_the_oracle():
+    """For 300 random contractions: the plan's index groups are A's free,
+    B's free and the contracted labels; an operand left untransposed is
+    stored as its two blocks in the order its pack kind reads; and replaying
+    the planned steps on the CPU (operands into the planned orders, matrix
+    product, product into C's order) gives the oracle's result."""
+    from oracle import tensor_contract as tc
+    rng = np.random.default_rng(77)
+    for _ in range(300):
+        la, lb, lc, ext = _random_contraction(rng)
+        sa, sb, sc = ([ext[l] for l in ls] for ls in (la, lb, lc))
+        p = ttx.ttx_contraction_create(ttx.F64, la, sa, lb, sb, lc, sc)
+        try:
+            d = ttx.ttx_contraction_describe(p)
+        finally:
+            ttx.ttx_contraction_destroy(p)
+        om, on, ok = d["order_m"], d["order_n"], d["order_k"]
+        assert sorted(om) == sorted(l for l in la if l in lc)
+        assert sorted(on) == sorted(l for l in lb if l in lc)
+        assert sorted(ok) == sorted(l for l in la if l in lb)
+        prod = lambda ls: int(np.prod([ext[l] for l in ls], dtype=np.int64))
+        assert (d["m"], d["n"], d["k"]) == (prod(om), prod(on), prod(ok))
+        if not d["transposed_a"]:
+            assert la == (om + ok if d["pack_kind_a"] == ttx.PACK_MFMA_A else ok + om), (la, d)
+        if not d["transposed_b"]:
+            assert lb == (ok + on if d["pack_kind_b"] == ttx.PACK_MFMA_B else on + ok), (lb, d)
+        A = rng.standard_normal(prod(la))
+        B = rng.standard_normal(prod(lb))
+        # replay: column-major tensors as numpy arrays indexed in label order
+        a = A.reshape([ext[l] for l in la], order="F") if la else A.reshape(())
+        b = B.reshape([ext[l] for l in lb], order="F") if lb else B.reshape(())
+        am = np.transpose(a, [la.index(l) for l in om + ok]).reshape((d["m"], d["k"]), order="F")
+        bm = np.transpose(b, [lb.index(l) for l in ok + on]).reshape((d["k"], d["n"]), order="F")
+        cm = (am @ bm).reshape([ext[l] for l in om + on] or [1], order="F")
+        got = np.transpose(cm.reshape([ext[l] for l in om + on]) if om + on else cm.reshape(()),
+                           [(om + on).index(l) for l in lc]).reshape(-1, order="F")
+        want = tc.contract(la, A, sa, lb, B, sb, lc, sc)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
