@@ -157,9 +157,11 @@ typedef enum ttx_family {
  *             row of a moved tile holds tile_a + lds_pad elements.  Ignored by
  *             tiles that do not pass through LDS with fixed rows (direct
  *             PRESERVED rows, dense tiles, FLAT).
- * The library holds pre-compiled kernels for threads = 256 and lds_pad = 1;
- * a configuration with other values runs a size-specialised kernel compiled
- * at run time (hipRTC) on first use, with the same arithmetic. */
+ * The library holds pre-compiled kernels for threads = 256 and lds_pad = 1
+ * over the menu tile shapes (ttx_tile_shapes); a configuration with other
+ * values, a run-time-only large tile, TTX_CFG_ALIGN_A or TTX_CFG_PIPELINED
+ * runs a size-specialised kernel compiled at run time (hipRTC) on first use,
+ * with the same arithmetic. */
 #define TTX_MAX_LDS_PAD 4
 typedef struct ttx_config {
     int family;
