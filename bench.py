@@ -13,9 +13,10 @@ Also measured: every case against a hipMemcpy device-to-device ceiling, the
 dominant kernel against the HBM roofline (8 TB/s), the CPU oracle on the
 host (which also checks every element of every case's GPU output), the
 leading-dimension, awkward and literal shapes, the 512-problem batch, the
-served trace, and the complex, mixed-precision and packing cases.  The
-printed JSON line holds the summary; the per-case detail goes to
-``--detail-out``.
+served trace, the complex, mixed-precision and packing cases, and three
+tensor contractions by transpose-transpose-GEMM-transpose (whole, panel
+GEMM alone, and torch's tensordot on the same tensors).  The printed JSON
+line holds the summary; the per-case detail goes to ``--detail-out``.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
