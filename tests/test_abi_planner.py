@@ -744,3 +744,54 @@ def test_shipped_table_covers_the_large_cases():
         assert not spec_keys, spec_keys
     finally:
         ttx.ttx_tune_table_clear()
+
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "ttx.h"
+/* A plain C (not C++) consumer of the boundary: host-only entry points. */
+int main(void) {
+    int perm[3] = {2, 1, 0};
+    int64_t size[3] = {96, 128, 80};
+    ttx_plan *p = NULL;
+    ttx_plan_info info;
+    ttx_contraction *c = NULL;
+    ttx_contraction_info ci;
+    int la[2] = {0, 2}, lb[2] = {2, 1}, lc[2] = {0, 1};
+    int64_t sa[2] = {70, 33}, sb[2] = {33, 45}, sc[2] = {70, 45};
+    int ta[64], tb[64], count = 0;
+    if (ttx_plan_create(&p, TTX_F32, 3, perm, size, NULL, NULL) != TTX_OK) return 1;
+    if (ttx_plan_describe(p, &info) != TTX_OK || info.family != TTX_FAMILY_MOVED) return 2;
+    ttx_plan_destroy(p);
+    perm[0] = 3;   /* not a permutation */
+    if (ttx_plan_create(&p, TTX_F32, 3, perm, size, NULL, NULL) != TTX_EPERM) return 3;
+    if (strlen(ttx_last_error()) == 0 || strlen(ttx_status_string(TTX_EPERM)) == 0) return 4;
+    if (ttx_contraction_create(&c, TTX_F64, 2, la, sa, 2, lb, sb, 2, lc, sc) != TTX_OK) return 5;
+    if (ttx_contraction_describe(c, &ci) != TTX_OK || ci.m != 70 || ci.n != 45 || ci.k != 33) return 6;
+    ttx_contraction_destroy(c);
+    if (ttx_tile_shapes(TTX_F32, TTX_FAMILY_MOVED, 0, ta, tb, 64, &count) != TTX_OK || count < 16) return 7;
+    printf("ok %s\n", ttx_version());
+    return 0;
+}
+"""
+
+
+def test_header_is_a_c_abi(tmp_path):
+    """include/ttx.h compiles as C99 with gcc (no C++ in the signatures), and
+    a C program linked against libttx.so runs its host-only entry points."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    rocm_inc = "/opt/rocm/include"
+    if not gcc or not os.path.isdir(rocm_inc):
+        pytest.skip("gcc or the ROCm headers are not installed")
+    src = tmp_path / "consumer.c"
+    src.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(ttx.lib()._name)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", rocm_inc, str(src), "-L", libdir, "-lttx", "-Wl,-rpath," + libdir, "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.startswith("ok "), (out.returncode, out.stdout, out.stderr)
