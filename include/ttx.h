@@ -562,7 +562,8 @@ ttx_status ttx_batch_create(ttx_batch **batch, int count, const ttx_problem *pro
  * return to their previous configs and this call's table entries are
  * withdrawn; without the scratch memory the check is skipped).  Winners go
  * into a process-wide per-shape table; the descriptors are rebuilt.
- * Blocks. */
+ * Blocks: waits for the device to be idle first (earlier launches of the
+ * batch may still be reading its descriptors). */
 ttx_status ttx_batch_tune(ttx_batch *batch, int max_candidates, int reps);
 /* One graph launch of the persistent kernel on `stream` (captured on first use).
  * Launches of one batch must not overlap each other (they share the batch's

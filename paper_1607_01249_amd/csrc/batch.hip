@@ -769,6 +769,9 @@ static bool tuned_set_wins(ttx_batch* b, const std::vector<ttx_config>& old_cfg,
 ttx_status ttx_batch_tune(ttx_batch* b, int max_candidates, int reps) {
     if (!b) return fail(TTX_EINVAL, "NULL batch");
     if (max_candidates == 0) max_candidates = 16;
+    // the batch's descriptors are rewritten below: no earlier launch of it may still read them
+    const hipError_t idle = hipDeviceSynchronize();
+    if (idle != hipSuccess) return fail(TTX_EHIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(idle));
     // a one-problem work block: descriptor, chunk prefix, claim counter
     const size_t need = work_bytes(1);
     unsigned char* d_blk = nullptr;
