@@ -663,6 +663,12 @@ ttx_status ttx_server_wait(ttx_server *server, uint64_t ticket);
 ttx_status ttx_server_result(ttx_server *server, uint64_t ticket, void **B, double *latency_us);
 /* Frees a kept result's arena region and budget. */
 ttx_status ttx_server_release(ttx_server *server, uint64_t ticket);
+/* Withdraws a request that has not been launched (queued, or admitted and
+ * waiting for a slot): its budget and arena region are returned and it never
+ * runs; later poll, wait, result and release calls on the ticket return
+ * TTX_ENOTFOUND.  A launched request cannot be recalled from the device
+ * (TTX_EBUSY); a finished one is released instead (TTX_EBUSY). */
+ttx_status ttx_server_cancel(ttx_server *server, uint64_t ticket);
 /* Waits until nothing is queued or running; TTX_EBUSY if admission is blocked
  * by results the caller still holds. */
 ttx_status ttx_server_drain(ttx_server *server);

@@ -233,6 +233,7 @@ def _declare(L):
         "ttx_server_result": ([vp, ctypes.c_uint64, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double)], S),
         "ttx_server_release": ([vp, ctypes.c_uint64], S),
         "ttx_server_drain": ([vp], S),
+        "ttx_server_cancel": ([vp, ctypes.c_uint64], S),
         "ttx_server_replay": ([vp, i64, vp, i64p, ctypes.POINTER(ctypes.c_uint64)], S),
         "ttx_server_replay_clients": ([vp, i64, vp, i64p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)], S),
         "ttx_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], S),
@@ -533,6 +534,11 @@ def ttx_server_release(server, ticket):
 
 def ttx_server_drain(server):
     return _check(lib().ttx_server_drain(server))
+
+
+def ttx_server_cancel(server, ticket):
+    """Withdraws a request that has not been launched."""
+    return _check(lib().ttx_server_cancel(server, ticket))
 
 
 def ttx_server_replay(server, requests, offsets_ns):

@@ -24,6 +24,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "ttx_internal.h"
@@ -141,6 +142,7 @@ struct ttx_server {
     std::deque<uint64_t> waiting;      // submitted, not admitted yet
     std::deque<uint64_t> ready;        // admitted, not launched yet
     std::unordered_map<uint64_t, Request> reqs;
+    std::unordered_set<uint64_t> cancelled;   // tickets withdrawn before launch
     uint64_t next_ticket = 1;
     int64_t running = 0;
     bool stop = false;
@@ -478,6 +480,7 @@ ttx_status ttx_server_poll(ttx_server* s, uint64_t ticket, int* done) {
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) {
         if (ticket == 0 || ticket >= s->next_ticket) return fail(TTX_ENOTFOUND, "unknown ticket");
+        if (s->cancelled.count(ticket)) return fail(TTX_ENOTFOUND, "request was cancelled");
         *done = 1;   // completed and already released
         return TTX_OK;
     }
@@ -489,6 +492,7 @@ ttx_status ttx_server_wait(ttx_server* s, uint64_t ticket) {
     if (!s) return fail(TTX_EINVAL, "NULL server");
     std::unique_lock<std::mutex> lock(s->mu);
     if (ticket == 0 || ticket >= s->next_ticket) return fail(TTX_ENOTFOUND, "unknown ticket");
+    if (s->cancelled.count(ticket)) return fail(TTX_ENOTFOUND, "request was cancelled");
     while (true) {
         if (!s->worker_error.empty()) return fail(TTX_EHIP, s->worker_error);
         auto it = s->reqs.find(ticket);
@@ -518,6 +522,25 @@ ttx_status ttx_server_release(ttx_server* s, uint64_t ticket) {
     s->reqs.erase(it);
     s->work_seq.fetch_add(1, std::memory_order_release);
     s->cv_work.notify_one();
+    return TTX_OK;
+}
+
+ttx_status ttx_server_cancel(ttx_server* s, uint64_t ticket) {
+    if (!s) return fail(TTX_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(TTX_ENOTFOUND, "unknown, released or cancelled ticket");
+    Request& r = it->second;
+    if (r.state == RUNNING) return fail(TTX_EBUSY, "request already launched");
+    if (r.state == DONE) return fail(TTX_EBUSY, "request finished: release it instead");
+    auto& q = r.state == WAITING ? s->waiting : s->ready;
+    q.erase(std::find(q.begin(), q.end(), ticket));
+    if (r.state == READY) release_locked(s, r);   // admitted: its arena region and budget
+    s->reqs.erase(it);
+    s->cancelled.insert(ticket);
+    s->work_seq.fetch_add(1, std::memory_order_release);   // freed budget may admit the next request
+    s->cv_work.notify_one();
+    s->cv_done.notify_all();
     return TTX_OK;
 }
 

@@ -282,3 +282,60 @@ def test_server_runs_complex_and_mixed_requests_alone():
         assert e.value.status == ttx.EINVAL
     finally:
         ttx.ttx_server_destroy(s)
+
+
+def test_server_cancel_withdraws_queued_requests_only():
+    """A request held back by admission is withdrawn and never runs; a
+    running or finished request cannot be cancelled; a cancelled ticket is
+    unknown afterwards; the budget and the rest of the queue are unaffected."""
+    # each request: 64 KiB in + 64 KiB out; budget 0.8 * 512 KiB -> 3 fit
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=512 << 10, max_queue=8)
+    try:
+        held = [ttx.ttx_server_submit(s, _req(size=(128, 128), keep=True)) for _ in range(3)]
+        for t in held:
+            ttx.ttx_server_wait(s, t)
+        queued = [ttx.ttx_server_submit(s, _req(size=(128, 128))) for _ in range(3)]
+        time.sleep(0.02)
+        ttx.ttx_server_cancel(s, queued[1])
+        for call in (lambda: ttx.ttx_server_poll(s, queued[1]), lambda: ttx.ttx_server_wait(s, queued[1]),
+                     lambda: ttx.ttx_server_result(s, queued[1]), lambda: ttx.ttx_server_release(s, queued[1]),
+                     lambda: ttx.ttx_server_cancel(s, queued[1]), lambda: ttx.ttx_server_cancel(s, 10 ** 6)):
+            with pytest.raises(ttx.TTXError) as e:
+                call()
+            assert e.value.status == ttx.ENOTFOUND
+        with pytest.raises(ttx.TTXError) as e:      # finished: released, not cancelled
+            ttx.ttx_server_cancel(s, held[0])
+        assert e.value.status == ttx.EBUSY
+        for t in held:
+            ttx.ttx_server_release(s, t)
+        ttx.ttx_server_drain(s)
+        assert ttx.ttx_server_poll(s, queued[0]) and ttx.ttx_server_poll(s, queued[2])
+        st = ttx.ttx_server_get_stats(s)
+        assert st["completed"] == 5 and st["queued"] == 0 and st["in_use_bytes"] == 0
+        ttx.ttx_server_drain(s)
+    finally:
+        ttx.ttx_server_destroy(s)
+
+
+def test_server_cancel_refuses_a_launched_request():
+    """The fake executor holds a request for bytes / 4 TB/s: an FP64
+    65536 x 65536 transposition (68.7 GB of traffic) runs for about 17 ms.
+    Once the server counts it as running (or finished), cancelling it is
+    refused."""
+    s = ttx.ttx_server_create(fake_device=True, fake_free_bytes=1 << 40)
+    try:
+        big = ttx.ttx_server_submit(s, _req(size=(65536, 65536), dtype=ttx.F64))
+        t0 = time.time()
+        while True:
+            st = ttx.ttx_server_get_stats(s)
+            if st["running"] or st["completed"]:
+                break
+            assert time.time() - t0 < 10, "the dispatcher never launched the request"
+            time.sleep(0.0002)
+        with pytest.raises(ttx.TTXError) as e:
+            ttx.ttx_server_cancel(s, big)
+        assert e.value.status == ttx.EBUSY
+        ttx.ttx_server_wait(s, big)
+        assert ttx.ttx_server_get_stats(s)["completed"] == 1
+    finally:
+        ttx.ttx_server_destroy(s)
