@@ -90,6 +90,10 @@ def _fake_full():
         other_types=dict(cases=[dict(case="6d_c32_p051423", GBps=3671.0, pct_of_d2d=71.5, us=1.0, kernel="k")] * 26,
                          pct_of_d2d_median=95.3, GBps_median=4892.0, GBps_min=3671.0, shapes_tuned_now=0),
         packing=[dict(case="A_f32", GBps=5000.0, pct_of_d2d=88.0, us=1.0, transpositions=1)] * 6,
+        contraction=[dict(case="ttgt_%d" % i, m=1600, n=1600, k=1600, panel=32, transposed_a=True,
+                          transposed_b=True, ms=0.16, TFLOPs=51.09, gemm_ms=0.122, gemm_TFLOPs=67.4,
+                          gemm_frac_of_peak=0.429, rest_ms=0.039, rest_bytes=102400000, rest_GBps=2635.0,
+                          rest_pct_of_d2d=50.3, torch_tensordot_ms=0.177, x_torch=1.1) for i in range(3)],
         tuning=dict(table="paper_1607_01249_amd/tune/gfx950.txt", shapes_tuned_now=0, seconds=0.0),
         per_perm=per_case)
 
@@ -99,7 +103,9 @@ def test_printed_line_is_compact_and_complete():
     the headline, the roofline and the CPU baseline (the detail goes to a file)."""
     line = bench.compact_line(_fake_full(), "gpurun_out/bench_detail.json")
     text = json.dumps(line, separators=(",", ":"))
-    assert len(text) < 2048, len(text)
+    assert len(text) < 3072, len(text)
+    assert set(line["contraction"]) == {"ttgt_0", "ttgt_1", "ttgt_2"}
+    assert line["contraction"]["ttgt_0"] == dict(ms=0.16, TFLOPs=51.09, gemm_frac_of_peak=0.429, x_torch=1.1)
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
               "scaling", "vs_baseline", "dtype", "data", "config", "pct_of_d2d", "roofline", "cpu_baseline",
               "verified", "batched", "served"):
